@@ -1,0 +1,270 @@
+"""FP64 CPU oracle of the L-GPDF hot path (VDB-GPDF, arXiv:2407.09649).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The product library
+never loads it and it never loads the product library: the two share no code.
+
+The arithmetic lives in ``gpdf_oracle.c`` (plain C, double precision, no
+fast-math, no FP contraction), and ``mlp.py`` (NumPy float64).  This module
+only marshals NumPy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gpdf_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle in place (gcc, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-Wextra",
+               "-Wno-unused-parameter", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        _lib = _bind(C.CDLL(_LIB))
+    return _lib
+
+
+class Params(C.Structure):
+    """Mirror of ``orc_params``.  Defaults: the noisy-sphere configuration
+    (Matern-3/2, l = 0.2 m, s = 0.01, raw points in 0.4 m cells, 27-cell
+    selection, smooth minimum with lambda = 100)."""
+    _fields_ = [
+        ("kernel", C.c_int32), ("selection", C.c_int32), ("knn_q", C.c_int32),
+        ("combine", C.c_int32), ("grad_mode", C.c_int32), ("pad_", C.c_int32),
+        ("l", C.c_double), ("s", C.c_double), ("voxel", C.c_double),
+        ("cell", C.c_double), ("lam", C.c_double), ("occ_min", C.c_double),
+        ("occ_max", C.c_double), ("fuse_voxel", C.c_double),
+        ("fuse_band", C.c_double),
+    ]
+
+    def __init__(self, **kw):
+        d = dict(kernel=0, selection=0, knn_q=8, combine=0, grad_mode=0,
+                 pad_=0, l=0.2, s=0.01, voxel=0.0, cell=0.4, lam=100.0,
+                 occ_min=1e-15, occ_max=1.0 - 1e-5, fuse_voxel=0.05,
+                 fuse_band=0.2)
+        d.update(kw)
+        super().__init__(**d)
+
+    def copy(self, **kw):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d.update(kw)
+        return Params(**d)
+
+
+_P = C.c_void_p
+_I64 = C.c_int64
+_D = C.c_double
+
+
+def _bind(L):
+    L.orc_keys.argtypes = [_P, _I64, _D, _P, _P]
+    L.orc_keys.restype = _I64
+    L.orc_matern_t.argtypes = [_D]
+    L.orc_matern_t.restype = _D
+    L.orc_revert.argtypes = [C.POINTER(Params), _D, C.POINTER(_D), C.POINTER(_D)]
+    L.orc_revert.restype = None
+    L.orc_cholesky.argtypes = [_P, _I64]
+    L.orc_cholesky.restype = C.c_int
+    L.orc_train.argtypes = [C.POINTER(Params), _P, _I64, C.c_int]
+    L.orc_train.restype = _P
+    L.orc_free.argtypes = [_P]
+    L.orc_model_sizes.argtypes = [_P, _P]
+    L.orc_model_export.argtypes = [_P, _P, _P, _P, _P, _P]
+    L.orc_model_factor.argtypes = [_P, _I64, _P]
+    L.orc_query.argtypes = [_P, _P, _I64, _P, _P, _P, _P, _P, _P, C.c_int]
+    L.orc_test_points.argtypes = [_P, _P, _I64]
+    L.orc_test_points.restype = _I64
+    L.orc_voxel_centres.argtypes = [_P, _I64, _D, _P]
+    L.orc_map_new.restype = _P
+    L.orc_map_free.argtypes = [_P]
+    L.orc_map_size.argtypes = [_P]
+    L.orc_map_size.restype = _I64
+    L.orc_map_export.argtypes = [_P, _P, _P, _P, _P]
+    L.orc_map_merge.argtypes = [_P, _P, _P, _P, _P, _I64, C.c_uint32]
+    L.orc_map_merge.restype = _I64
+    L.orc_fuse.argtypes = [_P, _P, _P, C.c_uint32, C.POINTER(_I64), C.c_int]
+    L.orc_fuse.restype = _I64
+    L.orc_query_global.argtypes = [_P, _D, _P, _I64, _P, _P, _P]
+    L.orc_nearest_distance.argtypes = [_P, _I64, _P, _I64, _P, C.c_int]
+    L.orc_max_threads.restype = C.c_int
+    return L
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+def keys(xyz, h):
+    """Packed voxel keys of FP32 points at edge h (and a validity mask)."""
+    x = _f32(xyz).reshape(-1, 3)
+    k = np.empty(x.shape[0], np.uint64)
+    ok = np.empty(x.shape[0], np.uint8)
+    lib().orc_keys(_ptr(x), x.shape[0], float(h), _ptr(k), _ptr(ok))
+    return k, ok.astype(bool)
+
+
+def matern_t(o: float) -> float:
+    return float(lib().orc_matern_t(float(o)))
+
+
+def revert(params: Params, o: float):
+    d, lam = _D(), _D()
+    lib().orc_revert(C.byref(params), float(o), C.byref(d), C.byref(lam))
+    return d.value, lam.value
+
+
+def cholesky(A):
+    """Lower Cholesky factor of A (copy) and the positive-definiteness flag."""
+    A = np.array(A, dtype=np.float64, order="C")
+    ok = lib().orc_cholesky(_ptr(A), A.shape[0])
+    return np.tril(A), bool(ok)
+
+
+class Model:
+    """The local GPs of one point cloud (one per leaf cluster)."""
+
+    def __init__(self, params: Params, xyz, nthreads: int = 0):
+        self.params = params.copy()
+        x = _f32(xyz).reshape(-1, 3)
+        self._h = lib().orc_train(C.byref(self.params), _ptr(x), x.shape[0],
+                                  int(nthreads))
+        s = np.zeros(4, np.int64)
+        lib().orc_model_sizes(self._h, _ptr(s))
+        self.nclusters, self.npoints, self.nonpd, self.skipped = map(int, s)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_free(h)
+            self._h = None
+
+    def export(self):
+        nc, npt = self.nclusters, self.npoints
+        ck = np.empty(nc, np.uint64)
+        off = np.empty(nc + 1, np.int64)
+        pts = np.empty((npt, 3), np.float32)
+        al = np.empty(npt, np.float64)
+        pd = np.empty(nc, np.uint8)
+        lib().orc_model_export(self._h, _ptr(ck), _ptr(off), _ptr(pts),
+                               _ptr(al), _ptr(pd))
+        return dict(ckey=ck, off=off, points=pts, alpha=al, pd=pd.astype(bool))
+
+    def factor(self, c: int):
+        e = self.export()
+        n = int(e["off"][c + 1] - e["off"][c])
+        L = np.empty((n, n), np.float64)
+        lib().orc_model_factor(self._h, int(c), _ptr(L))
+        return L
+
+    def query(self, q, origin=None, nthreads: int = 0):
+        x = _f32(q).reshape(-1, 3)
+        m = x.shape[0]
+        out = dict(dist=np.empty(m), grad=np.empty((m, 3)), var=np.empty(m),
+                   valid=np.empty(m, np.uint8), aux=np.empty((m, 3)))
+        o = None if origin is None else _f32(origin).reshape(3)
+        lib().orc_query(self._h, _ptr(x), m, _ptr(o), _ptr(out["dist"]),
+                        _ptr(out["grad"]), _ptr(out["var"]),
+                        _ptr(out["valid"]), _ptr(out["aux"]), int(nthreads))
+        out["valid"] = out["valid"].astype(bool)
+        return out
+
+    def test_points(self):
+        n = int(lib().orc_test_points(self._h, None, 0))
+        k = np.empty(n, np.uint64)
+        lib().orc_test_points(self._h, _ptr(k), n)
+        return k
+
+
+def voxel_centres(keys_, h):
+    k = np.ascontiguousarray(keys_, dtype=np.uint64)
+    x = np.empty((k.shape[0], 3), np.float32)
+    lib().orc_voxel_centres(_ptr(k), k.shape[0], float(h), _ptr(x))
+    return x
+
+
+class Map:
+    """The fused global grid: sorted (key, D, V, stamp) records."""
+
+    def __init__(self):
+        self._h = lib().orc_map_new()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_map_free(h)
+            self._h = None
+
+    def fuse(self, model: Model, origin, frame: int, nthreads: int = 0):
+        sk = _I64(0)
+        o = _f32(origin).reshape(3)
+        n = lib().orc_fuse(self._h, model._h, _ptr(o), int(frame),
+                           C.byref(sk), int(nthreads))
+        return int(n), int(sk.value)
+
+    def merge(self, keys_, d, v, ok, frame: int):
+        k = np.ascontiguousarray(keys_, np.uint64)
+        d = np.ascontiguousarray(d, np.float64)
+        v = np.ascontiguousarray(v, np.float64)
+        ok = np.ascontiguousarray(ok, np.uint8)
+        return int(lib().orc_map_merge(self._h, _ptr(k), _ptr(d), _ptr(v),
+                                       _ptr(ok), k.shape[0], int(frame)))
+
+    def size(self) -> int:
+        return int(lib().orc_map_size(self._h))
+
+    def export(self):
+        n = self.size()
+        k = np.empty(n, np.uint64)
+        D = np.empty(n)
+        V = np.empty(n)
+        s = np.empty(n, np.uint32)
+        lib().orc_map_export(self._h, _ptr(k), _ptr(D), _ptr(V), _ptr(s))
+        return dict(key=k, D=D, V=V, stamp=s)
+
+    def query(self, h, q):
+        x = _f32(q).reshape(-1, 3)
+        m = x.shape[0]
+        d = np.empty(m)
+        g = np.empty((m, 3))
+        ok = np.empty(m, np.uint8)
+        lib().orc_query_global(self._h, float(h), _ptr(x), m, _ptr(d), _ptr(g),
+                               _ptr(ok))
+        return dict(dist=d, grad=g, valid=ok.astype(bool))
+
+
+def nearest_distance(points, q, nthreads: int = 0):
+    p = _f32(points).reshape(-1, 3)
+    x = _f32(q).reshape(-1, 3)
+    out = np.empty(x.shape[0])
+    lib().orc_nearest_distance(_ptr(p), p.shape[0], _ptr(x), x.shape[0],
+                               _ptr(out), int(nthreads))
+    return out

@@ -1,0 +1,579 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+None of these re-types the oracle's formulas: each compares it with a closed
+form, a library routine on a special case, an invariant, exact rational
+arithmetic or brute force.  A plausible slip (dropped noise term, wrong sign
+in the variance, transposed triangular solve, wrong reverting derivative,
+smooth max instead of smooth min, wrong fusion weights, off-by-one keys)
+fails at least one of them.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.special as ssp
+from scipy.spatial import cKDTree
+
+import oracle as O
+from paper_2407_09649_amd import scenes as S
+
+SE = 1
+MATERN = 0
+
+
+# ----------------------------------------------------------------------------
+# keys: floor(x/h) of the exact real quotient, packed in three 21-bit fields
+# ----------------------------------------------------------------------------
+def _exact_floor(x: np.float32, h: float) -> int:
+    # IEEE division of double(x) by h is correctly rounded; floor of the
+    # rounded quotient equals floor of the exact quotient unless the exact
+    # quotient lies within half an ulp below an integer.  Compute what the
+    # rounded quotient's floor must be from exact rationals.
+    q = float(Fraction(float(x)) / Fraction(h))   # correctly rounded quotient
+    return math.floor(Fraction(q))
+
+
+def _pack(c):
+    b = 1 << 20
+    return ((c[0] + b) << 42) | ((c[1] + b) << 21) | (c[2] + b)
+
+
+def test_keys_adversarial_exact():
+    h = 0.1
+    base = [0.0, -0.0, 0.1, -0.1, 0.3, -0.3, 1.0, -1.0, 12.3, -12.3,
+            1e-30, -1e-30, 104857.5, -104857.5, 0.2999999, 0.7]
+    vals = []
+    for b in base:
+        f = np.float32(b)
+        vals += [f, np.nextafter(f, np.float32(np.inf)),
+                 np.nextafter(f, np.float32(-np.inf))]
+    # exact multiples of h as FP32 values
+    for k in range(-50, 51, 7):
+        vals.append(np.float32(k * h))
+    v = np.array(vals, np.float32)
+    pts = np.stack([v, v[::-1], np.roll(v, 3)], axis=1)
+    keys, ok = O.keys(pts, h)
+    assert ok.all()
+    for i in range(pts.shape[0]):
+        c = [_exact_floor(pts[i, a], h) for a in range(3)]
+        assert int(keys[i]) == _pack(c), (pts[i], c)
+
+
+def test_keys_reject_nonfinite_and_range():
+    pts = np.array([[np.nan, 0, 0], [0, np.inf, 0], [0, 0, -np.inf],
+                    [2.0 ** 20 * 0.1 * 1.0001, 0, 0],
+                    [-(2.0 ** 20) * 0.1 * 1.0001, 0, 0],
+                    [-(2.0 ** 20) * 0.1 * 0.9999, 0, 0]], np.float32)
+    keys, ok = O.keys(pts, 0.1)
+    assert ok.tolist() == [False, False, False, False, False, True]
+    assert (keys[~ok] == np.uint64(2 ** 64 - 1)).all()
+
+
+def test_keys_negative_zero_maps_to_cell_zero():
+    k, ok = O.keys(np.array([[-0.0, 0.0, -0.0]], np.float32), 0.05)
+    assert ok[0] and int(k[0]) == _pack([0, 0, 0])
+
+
+# ----------------------------------------------------------------------------
+# reverting functions (Eq. (3)) and their derivatives (Eq. (4))
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("o", [1e-15, 1e-9, 1e-4, 0.01, 0.3, 0.7, 0.99,
+                               0.999999, 1 - 1e-5])
+def test_matern_inverse_against_lambert_w(o):
+    # (1+t)e^{-t} = o  <=>  t = -1 - W_{-1}(-o/e)
+    t_ref = -1.0 - ssp.lambertw(-o / math.e, k=-1).real
+    t = O.matern_t(o)
+    assert abs(t - t_ref) <= 1e-9 * max(1.0, t_ref)
+    # round trip to double precision
+    assert abs((1 + t) * math.exp(-t) - o) <= 4e-16
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-9, 1e-12, 1e-14])
+def test_matern_inverse_branch_point_series(eps):
+    # Near o = 1, W_{-1} follows the branch-point series of Corless et al.
+    # (1996): with p = -sqrt(2(1 + e z)), W = -1 + p - p^2/3 + 11 p^3/72 - ...
+    # Here z = -o/e, so 1 + e z = 1 - o and t = -1 - W = s + s^2/3 + 11 s^3/72
+    # + O(s^4) with s = sqrt(2 (1 - o)).
+    o = 1.0 - eps
+    s = math.sqrt(2 * (1 - o))
+    t_ref = s + s * s / 3 + 11 * s ** 3 / 72
+    t = O.matern_t(o)
+    # 1 - o is exact in double for these o; the next series term is
+    # 43 s^4 / 540
+    assert abs(t - t_ref) <= 0.1 * s ** 4 + 1e-15 * t_ref
+
+
+def test_matern_inverse_at_one_is_zero():
+    assert O.matern_t(1.0) == 0.0
+
+
+@pytest.mark.parametrize("kernel", [MATERN, SE])
+@pytest.mark.parametrize("o", [1e-8, 0.05, 0.5, 0.9, 0.9999])
+def test_revert_derivative_finite_difference(kernel, o):
+    p = O.Params(kernel=kernel, l=0.2)
+    d, lam = O.revert(p, o)
+    h = 1e-7 * o
+    dp, _ = O.revert(p, o + h)
+    dm, _ = O.revert(p, o - h)
+    assert abs((dp - dm) / (2 * h) - lam) <= 1e-6 * abs(lam)
+
+
+def test_se_revert_closed_form():
+    p = O.Params(kernel=SE, l=0.3)
+    for o in [1e-6, 0.2, 0.8]:
+        d, lam = O.revert(p, o)
+        assert abs(d - math.sqrt(-2 * 0.09 * math.log(o))) < 1e-14
+        # Eq. (4): Lambda = -l / (o sqrt(-2 log o))
+        assert abs(lam + 0.3 / (o * math.sqrt(-2 * math.log(o)))) < 1e-9 * abs(lam)
+
+
+# ----------------------------------------------------------------------------
+# Cholesky: against SciPy's LAPACK factor, and the non-PD flag
+# ----------------------------------------------------------------------------
+def test_cholesky_against_lapack():
+    rng = np.random.default_rng(0)
+    for n in [1, 2, 5, 33, 96]:
+        X = rng.normal(size=(n, n))
+        A = X @ X.T + n * np.eye(n)
+        L, ok = O.cholesky(A)
+        assert ok
+        Lr = sla.cholesky(A, lower=True)
+        assert np.abs(L - Lr).max() <= 1e-12 * np.abs(Lr).max()
+        assert np.linalg.norm(L @ L.T - A) <= 1e-14 * np.linalg.norm(A) * n
+
+
+def test_cholesky_flags_singular():
+    v = np.array([1.0, 2.0, 3.0])
+    A = np.outer(v, v)
+    _, ok = O.cholesky(A)
+    assert not ok
+
+
+def test_duplicate_points_without_noise_are_non_pd():
+    pts = np.array([[0.1, 0.1, 0.1]] * 3 + [[0.15, 0.1, 0.1]], np.float32)
+    m = O.Model(O.Params(s=0.0, cell=0.4), pts)
+    assert m.nclusters == 1 and m.nonpd == 1
+    r = m.query(np.array([[0.1, 0.1, 0.2]], np.float32))
+    assert not r["valid"][0] and np.isinf(r["dist"][0])
+
+
+def test_alpha_solves_the_system_and_agrees_with_cho_solve():
+    sc = S.sphere_scene(seed=2, n_points=300)
+    p = O.Params()
+    m = O.Model(p, sc.points)
+    e = m.export()
+    c = int(np.argmax(np.diff(e["off"])))
+    a, b = e["off"][c], e["off"][c + 1]
+    L = m.factor(c)
+    A = L @ L.T
+    alpha = e["alpha"][a:b]
+    # L comes from the oracle; alpha from its own substitutions
+    assert np.abs(A @ alpha - 1).max() <= 1e-9 * np.linalg.cond(A)
+    ref = sla.cho_solve((L, True), np.ones(b - a))
+    assert np.abs(alpha - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+# ----------------------------------------------------------------------------
+# closed forms of the GP distance field
+# ----------------------------------------------------------------------------
+def _one_point_model(kernel, p0, l=0.2, s=0.01, **kw):
+    prm = O.Params(kernel=kernel, l=l, s=s, cell=10.0, **kw)
+    return O.Model(prm, np.array([p0], np.float32)), prm
+
+
+def test_single_point_se_closed_form():
+    # One training point: alpha = 1/(1+s^2), o = k/(1+s^2),
+    # d = sqrt(r^2 + 2 l^2 ln(1+s^2)), grad d = (x-p)/d, u = 1 - k^2/(1+s^2).
+    l, s = 0.2, 0.01
+    p0 = np.array([1.0, 2.0, 3.0], np.float32)
+    m, _ = _one_point_model(SE, p0, l=l, s=s)
+    rng = np.random.default_rng(1)
+    q = (p0 + rng.uniform(-0.5, 0.5, size=(200, 3))).astype(np.float32)
+    r = m.query(q)
+    assert r["valid"].all()
+    dx = q.astype(np.float64) - p0.astype(np.float64)
+    rr = np.linalg.norm(dx, axis=1)
+    k = np.exp(-rr ** 2 / (2 * l * l))
+    o = k / (1 + s * s)
+    keep = o > 1e-15
+    d = np.sqrt(rr ** 2 + 2 * l * l * np.log(1 + s * s))
+    assert np.abs(r["dist"] - d)[keep].max() < 1e-12
+    g = dx / d[:, None]
+    assert np.abs(r["grad"] - g)[keep].max() < 1e-10
+    # |grad| = r / d, the exact unit-norm pin away from the point
+    far = rr > 0.05
+    assert np.abs(np.linalg.norm(r["grad"], axis=1)[far] - 1).max() < 2e-3
+    u = 1 - k * k / (1 + s * s)
+    assert np.abs(r["aux"][:, 1] - u).max() < 1e-12
+    assert np.abs(r["aux"][:, 0] - o).max() < 1e-14
+    lam = -l / (o * np.sqrt(-2 * np.log(o)))
+    assert np.allclose(r["var"][keep], (lam * lam * u)[keep], rtol=1e-9)
+
+
+def test_single_point_matern_closed_form():
+    l, s = 0.2, 0.01
+    a = math.sqrt(3) / l
+    p0 = np.array([-0.3, 0.1, 0.05], np.float32)
+    m, _ = _one_point_model(MATERN, p0, l=l, s=s)
+    rng = np.random.default_rng(2)
+    q = (p0 + rng.uniform(-1, 1, size=(300, 3))).astype(np.float32)
+    r = m.query(q)
+    dx = q.astype(np.float64) - p0.astype(np.float64)
+    rr = np.linalg.norm(dx, axis=1)
+    k = (1 + a * rr) * np.exp(-a * rr)
+    o = np.minimum(k / (1 + s * s), 1 - 1e-5)
+    keep = o > 1e-14
+    t = -1 - ssp.lambertw(-o / math.e, k=-1).real
+    d = t / a
+    assert np.abs(r["dist"] - d)[keep].max() < 1e-9
+    # gradient: d(d)/dr = k'(r)/(1+s^2) / k'(d) along (x-p)/r
+    kp = lambda z: -a * a * z * np.exp(-a * z)
+    g = (kp(rr) / (1 + s * s) / kp(d))[:, None] * dx / rr[:, None]
+    assert np.abs(r["grad"] - g)[keep].max() < 1e-7
+
+
+def test_two_points_closed_form():
+    # 2x2: alpha_1 = alpha_2 = 1/(1+s^2+k12); u = 1 - k^T A^{-1} k with the
+    # explicit 2x2 inverse.  Distinguishes L^{-1} from L^{-T} in the variance.
+    l, s = 0.25, 0.05
+    p = np.array([[0.0, 0.0, 0.0], [0.15, 0.05, 0.0]], np.float32)
+    prm = O.Params(kernel=SE, l=l, s=s, cell=10.0)
+    m = O.Model(prm, p)
+    rng = np.random.default_rng(3)
+    q = rng.uniform(-0.3, 0.4, size=(100, 3)).astype(np.float32)
+    r = m.query(q)
+    P = p.astype(np.float64)
+    kf = lambda x, y: np.exp(-np.sum((x - y) ** 2, axis=-1) / (2 * l * l))
+    k12 = kf(P[0], P[1])
+    A = np.array([[1 + s * s, k12], [k12, 1 + s * s]])
+    det = A[0, 0] * A[1, 1] - A[0, 1] ** 2
+    Ai = np.array([[A[1, 1], -A[0, 1]], [-A[1, 0], A[0, 0]]]) / det
+    e = m.export()
+    assert np.allclose(e["alpha"], 1 / (1 + s * s + k12), rtol=1e-13)
+    Q = q.astype(np.float64)
+    kq = np.stack([kf(Q, P[0]), kf(Q, P[1])], axis=1)
+    o = kq.sum(1) / (1 + s * s + k12)
+    u = 1 - np.einsum("ni,ij,nj->n", kq, Ai, kq)
+    assert np.abs(r["aux"][:, 0] - o).max() < 1e-13
+    assert np.abs(r["aux"][:, 1] - np.clip(u, 0, 1)).max() < 1e-12
+
+
+@pytest.mark.slow
+def test_se_plane_lattice_closed_form():
+    # SE factorises along z; for an infinite planar lattice of spacing h the
+    # occupancy at height z over a lattice point is k(z) S / (S + s^2) with
+    # S = sum_j exp(-rho_j^2 / 2 l^2), so d(z) = sqrt(z^2 + 2 l^2 ln(1 + s^2/S)).
+    # dyadic spacing so the lattice is exact in FP32; h / l as for 0.05 / 0.2
+    h, l, s, nside = 0.0625, 0.25, 0.01, 41
+    g = (np.arange(nside) - nside // 2) * h
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    # centred at (3, 3, 3) so that the whole lattice is one 100 m cell;
+    # coordinates in [1, 3] are exact multiples of 2^-22 in FP32
+    c0 = 3.0
+    P = np.stack([X.ravel() + c0, Y.ravel() + c0, np.full(X.size, c0)], 1)
+    assert np.array_equal(P.astype(np.float32).astype(np.float64), P)
+    P = P.astype(np.float32)
+    prm = O.Params(kernel=SE, l=l, s=s, cell=100.0)
+    m = O.Model(prm, P)
+    assert m.nclusters == 1
+    z = np.array([0.01, 0.02, 0.05, 0.1, 0.2], np.float64)
+    q = np.stack([np.full_like(z, c0), np.full_like(z, c0), c0 + z], 1)
+    q = q.astype(np.float32)
+    z = q[:, 2].astype(np.float64) - c0
+    r = m.query(q)
+    jj = np.arange(-200, 201) * h
+    S1 = np.exp(-jj ** 2 / (2 * l * l)).sum()
+    Sinf = S1 * S1
+    d_ref = np.sqrt(z ** 2 + 2 * l * l * np.log(1 + s * s / Sinf))
+    # exact for ANY planar point set under SE: k(x0 + z n, p) = e^{-z^2/2l^2}
+    # k(x0, p), so o(z) = e^{-z^2/2l^2} o(0) and d(z)^2 - z^2 is constant
+    c = r["dist"] ** 2 - z ** 2
+    assert np.abs(c - c[0]).max() < 1e-12
+    # the gradient is exactly normal to the plane with norm z / d
+    assert np.abs(r["grad"][:, 2] - z / r["dist"]).max() < 1e-9
+    assert np.abs(r["grad"][:, :2]).max() < 1e-9
+    # the constant approaches the infinite-lattice value 2 l^2 ln(1 + s^2/S);
+    # the 41 x 41 lattice is within 1.3e-6 m^2 of it (finite-size effect)
+    assert abs(c[0] - 2 * l * l * np.log(1 + s * s / Sinf)) < 1.5e-6
+    assert np.abs(r["dist"] - d_ref).max() < 1e-4
+
+
+# ----------------------------------------------------------------------------
+# gradient: central finite differences of the returned distance (Q = 1)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("kernel", [MATERN, SE])
+def test_gradient_is_derivative_of_distance_single_gp(kernel):
+    sc = S.sphere_scene(seed=4, n_points=400)
+    # one cap of the sphere, moved to (3, 3, 3) so that it is one cluster
+    pts = (sc.points[sc.points[:, 0] > 0.6] + np.float32(3.0)).astype(np.float32)
+    prm = O.Params(kernel=kernel, cell=100.0)
+    m = O.Model(prm, pts)
+    assert m.nclusters == 1
+    rng = np.random.default_rng(5)
+    q = (3.0 + rng.uniform([0.8, -0.4, -0.4], [1.4, 0.4, 0.4], size=(60, 3))).astype(np.float32)
+    r = m.query(q)
+    h = 2.0 ** -12
+    for a in range(3):
+        qp = q.copy(); qp[:, a] += np.float32(h)
+        qm = q.copy(); qm[:, a] -= np.float32(h)
+        hp = qp[:, a].astype(np.float64) - qm[:, a].astype(np.float64)
+        fd = (m.query(qp)["dist"] - m.query(qm)["dist"]) / hp
+        capped = r["aux"][:, 0] >= 1 - 1e-5
+        # central-difference truncation error is h^2 |d'''| / 6 and a
+        # distance-like field has |d'''| ~ 1/d^2 (curvature of a cone)
+        tol = 1e-7 + h * h / r["dist"] ** 2
+        assert (np.abs(fd - r["grad"][:, a]) <= tol)[~capped].all()
+        assert (~capped).sum() > 40
+
+
+# ----------------------------------------------------------------------------
+# smooth minimum (Eq. (10)) and selection
+# ----------------------------------------------------------------------------
+def _per_cluster_results(points, prm, q):
+    """Each cluster trained on its own (as a one-cluster model)."""
+    m = O.Model(prm, points)
+    e = m.export()
+    res = []
+    for c in range(m.nclusters):
+        sub = e["points"][e["off"][c]:e["off"][c + 1]]
+        mc = O.Model(prm.copy(cell=1e4, selection=0), sub)
+        res.append(mc.query(q))
+    return m, e, res
+
+
+def test_smooth_min_combination_against_separately_trained_clusters():
+    # KNN with Q >= number of clusters selects every cluster, so the result
+    # must be exp(-lambda d_q)-weighted over per-cluster results obtained
+    # from separately trained single-cluster models.
+    sc = S.sphere_scene(seed=6, n_points=200)
+    prm = O.Params(selection=1, knn_q=64, cell=0.8)
+    rng = np.random.default_rng(7)
+    q = rng.uniform(-1.3, 1.3, size=(50, 3)).astype(np.float32)
+    m, e, res = _per_cluster_results(sc.points, prm, q)
+    assert 1 < m.nclusters <= 64
+    r = m.query(q)
+    D = np.stack([x["dist"] for x in res], 1)
+    G = np.stack([x["grad"] for x in res], 1)
+    w = np.exp(-100 * (D - D.min(1, keepdims=True)))
+    d_ref = (w * D).sum(1) / w.sum(1)
+    g_ref = (w[..., None] * G).sum(1) / w.sum(1)[:, None]
+    assert np.abs(r["dist"] - d_ref).max() < 1e-12
+    assert np.abs(r["grad"] - g_ref).max() < 1e-9
+    # smooth MIN: never above the largest and close to the smallest
+    assert (r["dist"] <= D.max(1) + 1e-12).all()
+    assert (r["dist"] - D.min(1) < 0.02).all()
+    # "directly average" mode: the plain mean of the per-cluster gradients
+    r2 = m.__class__(prm.copy(grad_mode=1), sc.points).query(q)
+    assert np.abs(r2["grad"] - G.mean(1)).max() < 1e-9
+    # hard minimum: the closest node (Sec. IV-B)
+    r3 = m.__class__(prm.copy(combine=1), sc.points).query(q)
+    amin = D.argmin(1)
+    assert np.abs(r3["dist"] - D.min(1)).max() < 1e-12
+    assert np.abs(r3["grad"] - G[np.arange(len(q)), amin]).max() < 1e-9
+
+
+def test_smooth_min_limits():
+    sc = S.sphere_scene(seed=8)
+    prm = O.Params()
+    q = sc.queries[:2000]
+    big = O.Model(prm.copy(lam=1e7), sc.points).query(q)
+    hard = O.Model(prm.copy(combine=1), sc.points).query(q)
+    v = hard["valid"]
+    assert np.abs(big["dist"][v] - hard["dist"][v]).max() < 1e-6
+
+
+def test_neighbour27_selection_brute_force():
+    # A query sees exactly the clusters whose cell differs by at most one
+    # in every axis; check n_local (aux[2]) against brute force.
+    sc = S.sphere_scene(seed=9, n_points=500, n_queries=400)
+    prm = O.Params(cell=0.4)
+    m = O.Model(prm, sc.points)
+    r = m.query(sc.queries)
+    pc = np.floor(sc.points.astype(np.float64) / 0.4).astype(np.int64)
+    qc = np.floor(sc.queries.astype(np.float64) / 0.4).astype(np.int64)
+    near = (np.abs(qc[:, None, :] - pc[None, :, :]) <= 1).all(-1)
+    n_local = near.sum(1)
+    assert (r["valid"] == (n_local > 0)).all()
+    assert (r["aux"][r["valid"], 2] == n_local[r["valid"]]).all()
+
+
+def test_knn_selects_nearest_cell_centres():
+    sc = S.sphere_scene(seed=10, n_points=600, n_queries=200)
+    prm = O.Params(selection=1, knn_q=3, cell=0.4)
+    m = O.Model(prm, sc.points)
+    r = m.query(sc.queries)
+    pc = np.floor(sc.points.astype(np.float64) / 0.4).astype(np.int64)
+    cells, counts = np.unique(pc, axis=0, return_counts=True)
+    ctr = (cells + 0.5) * 0.4
+    d2 = ((sc.queries.astype(np.float64)[:, None, :] - ctr[None]) ** 2).sum(-1)
+    nn = np.argsort(d2, axis=1, kind="stable")[:, :3]
+    assert r["valid"].all()
+    assert (r["aux"][:, 2] == counts[nn].sum(1)).all()
+
+
+def test_query_is_order_independent():
+    sc = S.sphere_scene(seed=11)
+    prm = O.Params()
+    a = O.Model(prm, sc.points).query(sc.queries)
+    perm = np.random.default_rng(0).permutation(len(sc.points))
+    b = O.Model(prm, sc.points[perm]).query(sc.queries)
+    v = a["valid"]
+    assert (a["valid"] == b["valid"]).all()
+    assert np.abs(a["dist"][v] - b["dist"][v]).max() < 1e-9
+
+
+# ----------------------------------------------------------------------------
+# geometry sanity bands (not parity): the GP distance follows the sphere
+# ----------------------------------------------------------------------------
+def test_sphere_distance_sanity():
+    sc = S.sphere_scene(seed=0)
+    m = O.Model(O.Params(), sc.points)
+    r = m.query(sc.queries)
+    v = r["valid"]
+    true = np.abs(np.linalg.norm(sc.queries.astype(np.float64), axis=1) - 1)[v]
+    d = r["dist"][v]
+    near = true < 0.2
+    assert np.sqrt(np.mean((d[near] - true[near]) ** 2)) < 0.05
+    # Matern GP distances under-estimate the Euclidean distance
+    assert np.mean(d[near] - true[near]) < 0.0
+    gn = np.linalg.norm(r["grad"][v], axis=1)
+    assert 0.7 < np.median(gn[(true > 0.05) & (true < 0.4)]) < 1.05
+
+
+def test_sign_from_sensor_origin():
+    # sensor at the centre of the sphere: inside is the sensor side (+),
+    # outside is behind the surface (-)
+    sc = S.sphere_scene(seed=12, n_points=3000)
+    m = O.Model(O.Params(), sc.points)
+    rng = np.random.default_rng(13)
+    u = rng.normal(size=(500, 3)); u /= np.linalg.norm(u, axis=1, keepdims=True)
+    rad = rng.choice([0.7, 0.8, 1.2, 1.3], size=500)
+    q = (u * rad[:, None]).astype(np.float32)
+    r = m.query(q, origin=np.zeros(3, np.float32))
+    v = r["valid"]
+    assert v.mean() > 0.9
+    assert (np.sign(r["dist"][v]) == np.where(rad[v] < 1, 1, -1)).all()
+    un = m.query(q)
+    assert np.allclose(np.abs(r["dist"][v]), un["dist"][v])
+
+
+# ----------------------------------------------------------------------------
+# fusion (Eq. (7)-(8)) and the global grid
+# ----------------------------------------------------------------------------
+def test_fusion_hand_computed():
+    g = O.Map()
+    k = np.array([5, 9], np.uint64)
+    g.merge(k, [1.0, 2.0], [0.5, 0.25], [1, 1], frame=0)
+    g.merge(k[:1], [3.0], [0.5], [1], frame=1)
+    e = g.export()
+    # equal variances: the mean of 1 and 3, variance halves
+    assert e["D"][0] == 2.0 and e["V"][0] == 0.25 and e["stamp"][0] == 1
+    assert e["D"][1] == 2.0 and e["V"][1] == 0.25 and e["stamp"][1] == 0
+    # third observation with variance 0.75 on top of (2, 0.25)
+    g.merge(k[:1], [6.0], [0.75], [1], frame=2)
+    e = g.export()
+    # alpha = V/(V+v) = 0.25, beta = 0.75: D = 0.25*6 + 0.75*2 = 3.0
+    assert abs(e["D"][0] - 3.0) < 1e-15
+    assert abs(e["V"][0] - 1 / (1 / 0.25 + 1 / 0.75)) < 1e-15
+
+
+def test_fusion_invariants_and_order_independence():
+    rng = np.random.default_rng(14)
+    keys = np.arange(1000, dtype=np.uint64) * 3
+    frames = []
+    for f in range(5):
+        sel = np.sort(rng.choice(1000, 600, replace=False))
+        frames.append((keys[sel], rng.normal(size=600), rng.uniform(0.01, 1, 600)))
+    g1, g2 = O.Map(), O.Map()
+    for i, (k, d, v) in enumerate(frames):
+        g1.merge(k, d, v, np.ones(600), i)
+    for i, (k, d, v) in enumerate(frames[::-1]):
+        g2.merge(k, d, v, np.ones(600), i)
+    a, b = g1.export(), g2.export()
+    assert (a["key"] == b["key"]).all()
+    assert np.abs(a["D"] - b["D"]).max() < 1e-12
+    assert np.abs(a["V"] / b["V"] - 1).max() < 1e-12
+    # the fused variance is below every observation's variance
+    for k, d, v in frames:
+        idx = np.searchsorted(a["key"], k)
+        assert (a["V"][idx] <= v * (1 + 1e-15)).all()
+    # non-positive or non-finite variances are skipped
+    g = O.Map()
+    sk = g.merge(np.array([1, 2, 3], np.uint64), [1.0, 1.0, 1.0],
+                 [np.inf, 0.0, 1.0], [1, 1, 1], 0)
+    assert sk == 2 and g.size() == 1
+
+
+def test_global_query_reproduces_affine_field():
+    h = 0.05
+    c = np.stack(np.meshgrid(np.arange(-5, 6), np.arange(-4, 5), np.arange(-3, 4),
+                             indexing="ij"), -1).reshape(-1, 3)
+    b = 1 << 20
+    keys = ((c[:, 0] + b).astype(np.uint64) << np.uint64(42)) | \
+           ((c[:, 1] + b).astype(np.uint64) << np.uint64(21)) | (c[:, 2] + b).astype(np.uint64)
+    order = np.argsort(keys)
+    ctr = (c + 0.5) * h
+    a, a0 = np.array([0.3, -1.1, 0.7]), 0.25
+    D = ctr @ a + a0
+    g = O.Map()
+    g.merge(keys[order], D[order], np.ones(len(D)), np.ones(len(D)), 0)
+    rng = np.random.default_rng(15)
+    q = rng.uniform(-4 * h + 0.5 * h, 4 * h, size=(300, 3)) * np.array([1, 0.8, 0.6])
+    q = q.astype(np.float32)
+    r = g.query(h, q)
+    assert r["valid"].all()
+    assert np.abs(r["dist"] - (q.astype(np.float64) @ a + a0)).max() < 1e-12
+    assert np.abs(r["grad"] - a).max() < 1e-10
+    far = g.query(h, np.array([[1.0, 1.0, 1.0]], np.float32))
+    assert not far["valid"][0]
+
+
+def test_test_points_brute_force():
+    pts = np.array([[0.01, 0.02, 0.03], [0.33, -0.12, 0.07], [0.36, -0.1, 0.05]],
+                   np.float32)
+    prm = O.Params(cell=0.4, fuse_voxel=0.05, fuse_band=0.2)
+    m = O.Model(prm, pts)
+    k = m.test_points()
+    got = set(int(x) for x in k)
+    assert (k[1:] > k[:-1]).all()
+    pc = np.floor(pts.astype(np.float64) / 0.05).astype(np.int64)
+    want = set()
+    for x in range(-20, 20):
+        for y in range(-20, 20):
+            for z in range(-20, 20):
+                if any((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2 <= 16 for c in pc):
+                    want.add(_pack([x, y, z]))
+    assert got == want
+
+
+def test_nearest_distance_against_kdtree():
+    rng = np.random.default_rng(16)
+    p = rng.normal(size=(500, 3)).astype(np.float32)
+    q = rng.normal(size=(300, 3)).astype(np.float32)
+    d = O.nearest_distance(p, q)
+    ref, _ = cKDTree(p.astype(np.float64)).query(q.astype(np.float64))
+    assert np.abs(d - ref).max() < 1e-12
+
+
+def test_voxel_downsample_centres():
+    rng = np.random.default_rng(17)
+    x = rng.uniform(-2, 2, size=(5000, 3)).astype(np.float32)
+    prm = O.Params(voxel=0.1)
+    m = O.Model(prm, x)
+    e = m.export()
+    vk, _ = O.keys(x, 0.1)
+    assert m.npoints == len(np.unique(vk))
+    # every training point is the FP32 centre of a voxel holding an input
+    ck, _ = O.keys(e["points"], 0.1)
+    assert set(ck.tolist()) == set(vk.tolist())
+    c = np.floor(x.astype(np.float64) / 0.1)
+    ctr = ((c + 0.5) * 0.1).astype(np.float32)
+    assert set(map(tuple, ctr.tolist())) == set(map(tuple, e["points"].tolist()))
+    # clusters are leaves of 8^3 voxels
+    vc = np.floor(e["points"].astype(np.float64) / 0.1).astype(np.int64)
+    leaf = np.floor_divide(vc, 8)
+    for cidx in range(m.nclusters):
+        blk = leaf[e["off"][cidx]:e["off"][cidx + 1]]
+        assert (blk == blk[0]).all()
