@@ -1,0 +1,254 @@
+/*
+ * vdbgpdf.h -- C ABI of the MI355X L-GPDF library (libvdbgpdf.so).
+ *
+ * The library implements the data-parallel hot path of VDB-GPDF (Wu,
+ * Le Gentil, Vidal-Calleja, "VDB-GPDF: Online Gaussian Process Distance
+ * Field with VDB Structure", arXiv:2407.09649): local Gaussian-process
+ * distance fields trained per leaf cluster of a voxelised point cloud
+ * (L-GPDF, Sec. IV-A), queried for distance, gradient and variance
+ * (Eq. (1)-(5), Eq. (10)), and fused by inverse-variance weighting into a
+ * device-resident hashed voxel grid standing in for the global VDB
+ * (Sec. IV-C, Eq. (7)-(8)).
+ *
+ * Conventions for every call:
+ *  - Pointers named d_* are DEVICE pointers owned by the caller (for example
+ *    torch tensor storage on the GPU).  Point arrays are row-major float[n][3]
+ *    in the world frame.  Outputs are written in input order.
+ *  - Pointers named h_* are HOST pointers owned by the caller.
+ *  - All calls enqueue work on the context's HIP stream and may return before
+ *    it finishes; the caller keeps device buffers alive until the stream is
+ *    synchronised.  gpdf_train_local_gps and gpdf_fuse_frame synchronise the
+ *    stream once internally to size their launches.
+ *  - The library owns its arenas.  They are sized at gpdf_create from the
+ *    capacities in gpdf_params and never grow: a call that would exceed one
+ *    returns GPDF_E_CAPACITY and leaves the previous state untouched.
+ *  - Return codes report host-detectable errors (null or non-finite
+ *    arguments, capacity, use before training, HIP failures).  Conditions
+ *    found on the device (non-finite inputs, non-positive-definite clusters,
+ *    refined queries, hash overflow) are counted and read with
+ *    gpdf_get_stats.
+ *  - An invalid query (no usable cluster around it, or a non-finite
+ *    coordinate) returns dist = +inf, grad = 0, var = +inf, valid = 0.
+ *  - No C++ exception crosses the ABI.  A context is used by one host thread
+ *    at a time.
+ */
+#ifndef VDBGPDF_H
+#define VDBGPDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPDF_ABI_VERSION 1u
+
+typedef struct gpdf_ctx gpdf_ctx;
+
+typedef enum {
+    GPDF_OK = 0,
+    GPDF_E_INVALID_ARG = 1,
+    GPDF_E_OOM = 2,
+    GPDF_E_HIP = 3,
+    GPDF_E_CAPACITY = 4,
+    GPDF_E_NOT_TRAINED = 5
+} gpdf_status;
+
+/* covariance function: Matern-3/2 k(r) = (1 + sqrt3 r/l) e^{-sqrt3 r/l}, or
+ * the squared exponential k(r) = e^{-r^2 / 2l^2} of Sec. III-A (k(0) = 1) */
+enum { GPDF_KERNEL_MATERN32 = 0, GPDF_KERNEL_SE = 1 };
+/* which local GPs a query uses: the 27 cells around its own, or the Q whose
+ * cell centres are nearest (the Q nearest nodes of Sec. IV-D) */
+enum { GPDF_SEL_NEIGHBOR27 = 0, GPDF_SEL_KNN = 1 };
+/* combination: smooth minimum of Eq. (10) read with exp(-lambda d), or the
+ * closest node only (the node with the smallest distance, Sec. IV-B) */
+enum { GPDF_COMB_SMOOTHMIN = 0, GPDF_COMB_HARDMIN = 1 };
+/* gradient combination: smooth-min weights, or the plain mean of the node
+ * gradients ("directly average", Sec. IV-D) */
+enum { GPDF_GRAD_WEIGHTED = 0, GPDF_GRAD_PAPER_MEAN = 1 };
+/* query arithmetic: FP32 with an FP64 re-evaluation of the queries whose FP32
+ * error bound exceeds the tolerance; everything in FP64; or FP32 kernel values
+ * with the variance product on BF16 MFMA */
+enum { GPDF_PREC_FP32 = 0, GPDF_PREC_BF16 = 1, GPDF_PREC_FP64 = 2 };
+
+typedef struct {
+    uint32_t abi_version;      /* must equal GPDF_ABI_VERSION */
+    int32_t kernel;            /* GPDF_KERNEL_* */
+    double length_scale;       /* l, metres */
+    double noise_sigma;        /* s: K + s^2 I (Eq. (1)) */
+    double voxel_size;         /* > 0: training points are the centres of the
+                                  occupied voxels and a cluster is a leaf of
+                                  8^3 voxels (Sec. III-B, IV-A);
+                                  0: raw points in cells of cluster_size */
+    double cluster_size;       /* raw-mode cluster edge, metres */
+    int32_t selection;         /* GPDF_SEL_* */
+    int32_t knn_q;             /* Q for GPDF_SEL_KNN, 1..16 */
+    int32_t combine;           /* GPDF_COMB_* */
+    int32_t grad_mode;         /* GPDF_GRAD_* */
+    double smooth_min_lambda;  /* 100 in Sec. IV-D */
+    double occ_min, occ_max;   /* caps on the latent occupancy (footnote 1) */
+    int32_t precision;         /* GPDF_PREC_* */
+    int32_t pad0;
+    double fuse_voxel_size;    /* global grid edge */
+    double fuse_band;          /* test-point band radius, metres */
+    double mlp_gate;           /* correction applied where variance <= gate */
+    int64_t max_points;        /* capacity: points per training call */
+    int64_t max_clusters;      /* capacity: clusters per training call */
+    int64_t max_cluster_points;/* capacity: points in one cluster (<= 1024) */
+    int64_t max_factor_elems;  /* capacity: sum over clusters of n(n+1)/2 */
+    int64_t max_queries;       /* capacity: queries per call (also test points) */
+    int64_t global_capacity;   /* capacity: voxels of the global grid */
+} gpdf_params;
+
+typedef struct {
+    int64_t clusters;          /* clusters of the last training */
+    int64_t points;            /* training points of the last training */
+    int64_t nonpd_clusters;    /* excluded: factor not positive definite */
+    int64_t skipped_points;    /* non-finite or out-of-range inputs */
+    int64_t queries;           /* queries of the last query call */
+    int64_t valid_queries;
+    int64_t refined_queries;   /* FP32 queries re-evaluated in FP64 */
+    int64_t test_points;       /* test points of the last fused frame */
+    int64_t fused;             /* observations fused in the last frame */
+    int64_t fuse_skipped;      /* invalid or non-finite observations */
+    int64_t global_voxels;     /* voxels in the global grid */
+    int64_t gated;             /* queries corrected by the MLP */
+    uint32_t status_bits;      /* GPDF_STATUS_* set since the last read */
+    uint32_t pad0;
+} gpdf_stats;
+
+enum {
+    GPDF_STATUS_HASH_FULL = 1u,       /* a probe sequence exhausted a table */
+    GPDF_STATUS_GLOBAL_FULL = 2u,     /* the global grid is full */
+    GPDF_STATUS_NONFINITE = 4u,       /* non-finite input points or queries */
+    GPDF_STATUS_NONPD = 8u            /* some cluster was not positive definite */
+};
+
+/* Fill *p with defaults: Matern-3/2, l = 0.2 m, s = 0.01, raw points in 0.4 m
+ * cells, 27-cell selection, smooth minimum with lambda = 100 (Sec. IV-D),
+ * occupancy caps [1e-15, 1 - 1e-5], FP32, global grid 0.05 m with a 0.2 m
+ * band, gate 0.05 m^2, and capacities for a few million points and queries. */
+gpdf_status gpdf_params_default(gpdf_params *p);
+
+/* Create a context bound to one HIP stream (hipStream_t passed as void*; NULL
+ * is the null stream) on the current device.  Allocates every arena.
+ * Errors: GPDF_E_INVALID_ARG (bad parameters or ABI version), GPDF_E_OOM. */
+gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_ctx **out);
+
+/* Release the context and its device memory (synchronises its stream). */
+void gpdf_destroy(gpdf_ctx *ctx);
+
+/* Replace the local GPs with ones trained on d_xyz [n][3] (the L-GPDF of the
+ * current frame, re-modelled every frame, Sec. IV-A): voxelise (voxel mode),
+ * group into leaf clusters, and for every cluster assemble K + s^2 I, factor
+ * it in FP64 and solve for alpha = (K + s^2 I)^{-1} 1 (Eq. (1)).  Non-finite
+ * points are skipped and counted.  n = 0 leaves an empty model.
+ * Errors: GPDF_E_CAPACITY (n, cluster count, cluster size or factor storage
+ * beyond the arenas), GPDF_E_INVALID_ARG. */
+gpdf_status gpdf_train_local_gps(gpdf_ctx *ctx, const float *d_xyz, int64_t n);
+
+/* Distance field at d_q [m][3] from the current local GPs: per selected
+ * cluster the latent occupancy (Eq. (1)), its variance (Eq. (2), posterior
+ * minus sign), reverting (Eq. (3)), distance variance (Eq. (4)) and gradient
+ * (Eq. (5) with the chain rule), combined over clusters (Eq. (10)).  With
+ * h_origin (host float[3]) the distance and gradient carry the sign of the
+ * sensor side (Sec. IV); NULL gives the unsigned field.
+ * Outputs (device, may be NULL except d_dist and d_valid): d_dist [m],
+ * d_grad [m][3], d_var [m], d_valid [m] (uint8), d_aux [m][3] = latent
+ * occupancy and latent variance of the closest cluster and the number of
+ * training points used.  correct != 0 applies the learned correction where
+ * the variance is at most mlp_gate (requires gpdf_mlp_* weights).
+ * Errors: GPDF_E_NOT_TRAINED, GPDF_E_CAPACITY (m > max_queries). */
+gpdf_status gpdf_query_distance(gpdf_ctx *ctx, const float *d_q, int64_t m,
+                                const float *h_origin, float *d_dist,
+                                float *d_grad, float *d_var, uint8_t *d_valid,
+                                float *d_aux, int32_t correct);
+
+/* One frame of fusion (Sec. IV-B, IV-C): train on d_xyz [n][3] (or, with
+ * d_xyz == NULL, reuse the current local GPs), generate the test voxels of
+ * the global grid within fuse_band of the training points, query them signed
+ * from h_origin, and fuse each valid result into the grid:
+ * D <- (V d + v D) / (V + v), V <- V v / (V + v) (Eq. (7)-(8)); absent voxels
+ * take (d, v).  Updated voxels are stamped with the frame counter.
+ * Errors: GPDF_E_CAPACITY (test points > max_queries, grid full),
+ * GPDF_E_NOT_TRAINED (d_xyz == NULL before any training). */
+gpdf_status gpdf_fuse_frame(gpdf_ctx *ctx, const float *d_xyz, int64_t n,
+                            const float *h_origin);
+
+/* Query the fused grid at d_q [m][3]: trilinear interpolation of D over the
+ * eight voxel centres around each point and its analytic gradient; valid only
+ * where all eight voxels exist (stand-in for the global field of Sec. IV-D).
+ * Outputs: d_dist [m], d_grad [m][3] (may be NULL), d_valid [m]. */
+gpdf_status gpdf_query_global(gpdf_ctx *ctx, const float *d_q, int64_t m,
+                              float *d_dist, float *d_grad, uint8_t *d_valid);
+
+/* Counters of the last calls (synchronises the stream). */
+gpdf_status gpdf_get_stats(gpdf_ctx *ctx, gpdf_stats *out);
+
+/* Message of the last error on this context (owned by the context). */
+const char *gpdf_last_error(const gpdf_ctx *ctx);
+
+/* Copy the current local GPs to host memory (synchronises): cluster keys
+ * (three 21-bit offset-binary cell coordinates), CSR offsets [clusters + 1],
+ * training points [points][3], alpha in FP64 [points], positive-definite
+ * flags [clusters].  Any pointer may be NULL.  Sizes come from gpdf_get_stats.
+ * Errors: GPDF_E_NOT_TRAINED. */
+gpdf_status gpdf_export_model(gpdf_ctx *ctx, uint64_t *h_ckey, int64_t *h_off,
+                              float *h_points, double *h_alpha, uint8_t *h_pd);
+
+/* Copy the global grid, sorted by key, to host memory (synchronises).  *count
+ * receives the number of voxels; nothing is written if it exceeds cap. */
+gpdf_status gpdf_export_global(gpdf_ctx *ctx, uint64_t *h_key, float *h_D,
+                               float *h_V, uint32_t *h_stamp, int64_t cap,
+                               int64_t *count);
+
+/* Copy the sorted unique test-voxel keys of the last fused frame. */
+gpdf_status gpdf_export_test_points(gpdf_ctx *ctx, uint64_t *h_key,
+                                    int64_t cap, int64_t *count);
+
+/* Write / read the global grid: a header (magic, version, voxel size, count,
+ * frame counter) and the key-sorted (key, D, V, stamp) records. */
+gpdf_status gpdf_save_global(gpdf_ctx *ctx, const char *path);
+gpdf_status gpdf_load_global(gpdf_ctx *ctx, const char *path);
+
+/* Brute-force distance from every d_q [m][3] to the nearest of d_pts [n][3]
+ * (FP32 differences, exact minimum) -- the truth used to generate training
+ * pairs for the learned correction. */
+gpdf_status gpdf_nearest_distance(gpdf_ctx *ctx, const float *d_pts, int64_t n,
+                                  const float *d_q, int64_t m, float *d_out);
+
+/* ---- learned correction (an extension; not in the paper) ----------------
+ * A 7-64-64-64-1 GELU network maps standardised features
+ * [d, log v, o, grad d (3), log(1 + n_local)] to a residual r.  Parameters
+ * are 8,897 FP32 master weights in the order W1[64x7], b1, W2[64x64], b2,
+ * W3[64x64], b3, W4[1x64], b4 (row-major W[out][in]); forward and backward
+ * run on BF16 MFMA with FP32 accumulation. */
+#define GPDF_MLP_NPARAM 8897
+gpdf_status gpdf_mlp_init(gpdf_ctx *ctx, uint64_t seed);
+gpdf_status gpdf_mlp_set_weights(gpdf_ctx *ctx, const float *h_w, int64_t n);
+gpdf_status gpdf_mlp_get_weights(gpdf_ctx *ctx, float *h_w, int64_t cap);
+/* feature standardisation: z = (f - mean) / std, h_mean and h_std float[7] */
+gpdf_status gpdf_mlp_set_norm(gpdf_ctx *ctx, const float *h_mean,
+                              const float *h_std);
+/* raw features [n][7] from query outputs (dist, var, aux, grad) */
+gpdf_status gpdf_mlp_features(gpdf_ctx *ctx, const float *d_dist,
+                              const float *d_var, const float *d_grad,
+                              const float *d_aux, int64_t n, float *d_feat);
+/* residual r [n] from raw features [n][7] */
+gpdf_status gpdf_mlp_forward(gpdf_ctx *ctx, const float *d_feat, int64_t n,
+                             float *d_r);
+/* mean squared error of r against d_target [n] and its gradient [8897] */
+gpdf_status gpdf_mlp_grad(gpdf_ctx *ctx, const float *d_feat,
+                          const float *d_target, int64_t n, float *d_grad,
+                          float *h_loss);
+/* epochs of shuffled mini-batch Adam (beta 0.9/0.999, eps 1e-8) on
+ * (feature, target) pairs; *h_loss receives the last epoch's mean loss */
+gpdf_status gpdf_mlp_train(gpdf_ctx *ctx, const float *d_feat,
+                           const float *d_target, int64_t n, int32_t epochs,
+                           int32_t batch, float lr, uint64_t seed,
+                           float *h_loss);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VDBGPDF_H */

@@ -1,0 +1,366 @@
+"""MI355X L-GPDF: local Gaussian-process distance fields (VDB-GPDF,
+arXiv:2407.09649) on hand-written HIP kernels behind a C ABI.
+
+This module only marshals arguments to ``libvdbgpdf.so`` (``include/vdbgpdf.h``):
+torch tensors supply device memory and the current HIP stream; every step of
+the computation runs in the library's kernels.  There is no CPU fallback: if
+the library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+__all__ = ["Params", "Stats", "Context", "load_library", "library_path",
+           "KERNEL_MATERN32", "KERNEL_SE", "SEL_NEIGHBOR27", "SEL_KNN",
+           "COMB_SMOOTHMIN", "COMB_HARDMIN", "GRAD_WEIGHTED", "GRAD_PAPER_MEAN",
+           "PREC_FP32", "PREC_BF16", "PREC_FP64", "MLP_NPARAM", "GpdfError"]
+
+ABI_VERSION = 1
+KERNEL_MATERN32, KERNEL_SE = 0, 1
+SEL_NEIGHBOR27, SEL_KNN = 0, 1
+COMB_SMOOTHMIN, COMB_HARDMIN = 0, 1
+GRAD_WEIGHTED, GRAD_PAPER_MEAN = 0, 1
+PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
+MLP_NPARAM = 8897
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "HIP", 4: "CAPACITY", 5: "NOT_TRAINED"}
+
+EXPORTS = [
+    "gpdf_params_default", "gpdf_create", "gpdf_destroy", "gpdf_train_local_gps",
+    "gpdf_query_distance", "gpdf_fuse_frame", "gpdf_query_global", "gpdf_get_stats",
+    "gpdf_last_error", "gpdf_export_model", "gpdf_export_global",
+    "gpdf_export_test_points", "gpdf_save_global", "gpdf_load_global",
+    "gpdf_nearest_distance", "gpdf_mlp_init", "gpdf_mlp_set_weights",
+    "gpdf_mlp_get_weights", "gpdf_mlp_set_norm", "gpdf_mlp_features",
+    "gpdf_mlp_forward", "gpdf_mlp_grad", "gpdf_mlp_train",
+]
+
+
+class GpdfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gpdf status {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    """Mirror of ``gpdf_params``; defaults from ``gpdf_params_default``."""
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("kernel", C.c_int32),
+        ("length_scale", C.c_double), ("noise_sigma", C.c_double),
+        ("voxel_size", C.c_double), ("cluster_size", C.c_double),
+        ("selection", C.c_int32), ("knn_q", C.c_int32),
+        ("combine", C.c_int32), ("grad_mode", C.c_int32),
+        ("smooth_min_lambda", C.c_double), ("occ_min", C.c_double),
+        ("occ_max", C.c_double), ("precision", C.c_int32), ("pad0", C.c_int32),
+        ("fuse_voxel_size", C.c_double), ("fuse_band", C.c_double),
+        ("mlp_gate", C.c_double),
+        ("max_points", C.c_int64), ("max_clusters", C.c_int64),
+        ("max_cluster_points", C.c_int64), ("max_factor_elems", C.c_int64),
+        ("max_queries", C.c_int64), ("global_capacity", C.c_int64),
+    ]
+
+    @classmethod
+    def default(cls, **kw) -> "Params":
+        p = cls()
+        _check(load_library().gpdf_params_default(C.byref(p)), None)
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise AttributeError(k)
+            setattr(p, k, v)
+        return p
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "clusters", "points", "nonpd_clusters", "skipped_points", "queries",
+        "valid_queries", "refined_queries", "test_points", "fused",
+        "fuse_skipped", "global_voxels", "gated")] + [
+        ("status_bits", C.c_uint32), ("pad0", C.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad0"}
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libvdbgpdf.so")
+
+
+def load_library():
+    """Load libvdbgpdf.so (built by ``paper_2407_09649_amd.build``)."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with "
+                               "python -m paper_2407_09649_amd.build")
+        _lib = _bind(C.CDLL(path))
+    return _lib
+
+
+def _bind(L):
+    P, I64, F, U64 = C.c_void_p, C.c_int64, C.c_float, C.c_uint64
+    sig = {
+        "gpdf_params_default": [P],
+        "gpdf_create": [P, P, P],
+        "gpdf_train_local_gps": [P, P, I64],
+        "gpdf_query_distance": [P, P, I64, P, P, P, P, P, P, C.c_int32],
+        "gpdf_fuse_frame": [P, P, I64, P],
+        "gpdf_query_global": [P, P, I64, P, P, P],
+        "gpdf_get_stats": [P, P],
+        "gpdf_export_model": [P, P, P, P, P, P],
+        "gpdf_export_global": [P, P, P, P, P, I64, P],
+        "gpdf_export_test_points": [P, P, I64, P],
+        "gpdf_save_global": [P, C.c_char_p],
+        "gpdf_load_global": [P, C.c_char_p],
+        "gpdf_nearest_distance": [P, P, I64, P, I64, P],
+        "gpdf_mlp_init": [P, U64],
+        "gpdf_mlp_set_weights": [P, P, I64],
+        "gpdf_mlp_get_weights": [P, P, I64],
+        "gpdf_mlp_set_norm": [P, P, P],
+        "gpdf_mlp_features": [P, P, P, P, P, I64, P],
+        "gpdf_mlp_forward": [P, P, I64, P],
+        "gpdf_mlp_grad": [P, P, P, I64, P, P],
+        "gpdf_mlp_train": [P, P, P, I64, C.c_int32, C.c_int32, F, U64, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.gpdf_destroy.argtypes = [P]
+    L.gpdf_destroy.restype = None
+    L.gpdf_last_error.argtypes = [P]
+    L.gpdf_last_error.restype = C.c_char_p
+    return L
+
+
+def _check(status, ctx):
+    if status != 0:
+        msg = ""
+        if ctx is not None:
+            m = load_library().gpdf_last_error(ctx)
+            msg = m.decode() if m else ""
+        raise GpdfError(status, msg)
+
+
+def _dptr(t, dtype=None, shape_last=None):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a tensor on the GPU")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if shape_last is not None and (t.dim() != 2 or t.shape[1] != shape_last):
+        raise ValueError(f"expected shape [n, {shape_last}]")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host3(v):
+    if v is None:
+        return None
+    a = (C.c_float * 3)(*[float(x) for x in v])
+    return a
+
+
+class Context:
+    """One library context bound to the current HIP stream of a device."""
+
+    def __init__(self, params: Params | None = None, device=None, stream=None, **kw):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self.params = params if params is not None else Params.default()
+        for k, v in kw.items():
+            setattr(self.params, k, v)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            h = C.c_void_p()
+            _check(self.lib.gpdf_create(C.byref(self.params),
+                                        C.c_void_p(self.stream.cuda_stream),
+                                        C.byref(h)), None)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.gpdf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- core calls ---------------------------------------------------------
+    def train(self, xyz):
+        torch = self._torch
+        n = 0 if xyz is None else xyz.shape[0]
+        _check(self.lib.gpdf_train_local_gps(self._h, _dptr(xyz, torch.float32, 3) if n else None, n),
+               self._h)
+
+    def query(self, q, origin=None, grad=True, var=True, aux=True, correct=False, out=None):
+        torch = self._torch
+        m = q.shape[0]
+        dev = self.device
+        o = out or {}
+        dist = o.get("dist", torch.empty(m, dtype=torch.float32, device=dev))
+        valid = o.get("valid", torch.empty(m, dtype=torch.uint8, device=dev))
+        g = o.get("grad", torch.empty((m, 3), dtype=torch.float32, device=dev)) if grad else None
+        v = o.get("var", torch.empty(m, dtype=torch.float32, device=dev)) if var else None
+        a = o.get("aux", torch.empty((m, 3), dtype=torch.float32, device=dev)) if aux else None
+        _check(self.lib.gpdf_query_distance(
+            self._h, _dptr(q, torch.float32, 3) if m else None, m, _host3(origin),
+            _dptr(dist), _dptr(g), _dptr(v), _dptr(valid), _dptr(a), int(bool(correct))), self._h)
+        r = {"dist": dist, "valid": valid}
+        if grad:
+            r["grad"] = g
+        if var:
+            r["var"] = v
+        if aux:
+            r["aux"] = a
+        return r
+
+    def fuse(self, xyz, origin):
+        torch = self._torch
+        n = 0 if xyz is None else xyz.shape[0]
+        _check(self.lib.gpdf_fuse_frame(
+            self._h, _dptr(xyz, torch.float32, 3) if xyz is not None and n else None, n,
+            _host3(origin)), self._h)
+
+    def query_global(self, q, grad=True):
+        torch = self._torch
+        m = q.shape[0]
+        dist = torch.empty(m, dtype=torch.float32, device=self.device)
+        valid = torch.empty(m, dtype=torch.uint8, device=self.device)
+        g = torch.empty((m, 3), dtype=torch.float32, device=self.device) if grad else None
+        _check(self.lib.gpdf_query_global(self._h, _dptr(q, torch.float32, 3) if m else None, m,
+                                          _dptr(dist), _dptr(g), _dptr(valid)), self._h)
+        r = {"dist": dist, "valid": valid}
+        if grad:
+            r["grad"] = g
+        return r
+
+    def nearest_distance(self, pts, q):
+        torch = self._torch
+        out = torch.empty(q.shape[0], dtype=torch.float32, device=self.device)
+        _check(self.lib.gpdf_nearest_distance(self._h, _dptr(pts, torch.float32, 3), pts.shape[0],
+                                              _dptr(q, torch.float32, 3), q.shape[0],
+                                              _dptr(out)), self._h)
+        return out
+
+    # -- inspection ------------------------------------------------------------
+    def stats(self) -> dict:
+        s = Stats()
+        _check(self.lib.gpdf_get_stats(self._h, C.byref(s)), self._h)
+        return s.as_dict()
+
+    def export_model(self):
+        import numpy as np
+        st = self.stats()
+        nc, npt = st["clusters"], st["points"]
+        ck = np.empty(nc, np.uint64)
+        off = np.empty(nc + 1, np.int64)
+        pts = np.empty((npt, 3), np.float32)
+        al = np.empty(npt, np.float64)
+        pd = np.empty(nc, np.uint8)
+        P = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check(self.lib.gpdf_export_model(self._h, P(ck), P(off), P(pts), P(al), P(pd)), self._h)
+        return dict(ckey=ck, off=off, points=pts, alpha=al, pd=pd.astype(bool))
+
+    def export_global(self):
+        import numpy as np
+        cnt = C.c_int64(0)
+        _check(self.lib.gpdf_export_global(self._h, None, None, None, None, 0, C.byref(cnt)), self._h)
+        n = cnt.value
+        k = np.empty(n, np.uint64)
+        D = np.empty(n, np.float32)
+        V = np.empty(n, np.float32)
+        s = np.empty(n, np.uint32)
+        P = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check(self.lib.gpdf_export_global(self._h, P(k), P(D), P(V), P(s), n, C.byref(cnt)), self._h)
+        return dict(key=k, D=D, V=V, stamp=s)
+
+    def export_test_points(self):
+        import numpy as np
+        cnt = C.c_int64(0)
+        _check(self.lib.gpdf_export_test_points(self._h, None, 0, C.byref(cnt)), self._h)
+        k = np.empty(cnt.value, np.uint64)
+        _check(self.lib.gpdf_export_test_points(self._h, k.ctypes.data_as(C.c_void_p), cnt.value,
+                                                C.byref(cnt)), self._h)
+        return k
+
+    def save_global(self, path):
+        _check(self.lib.gpdf_save_global(self._h, os.fsencode(path)), self._h)
+
+    def load_global(self, path):
+        _check(self.lib.gpdf_load_global(self._h, os.fsencode(path)), self._h)
+
+    # -- learned correction ---------------------------------------------------
+    def mlp_init(self, seed=0):
+        _check(self.lib.gpdf_mlp_init(self._h, int(seed)), self._h)
+
+    def mlp_set_weights(self, w):
+        import numpy as np
+        a = np.ascontiguousarray(w, np.float32)
+        _check(self.lib.gpdf_mlp_set_weights(self._h, a.ctypes.data_as(C.c_void_p), a.size), self._h)
+
+    def mlp_get_weights(self):
+        import numpy as np
+        a = np.empty(MLP_NPARAM, np.float32)
+        _check(self.lib.gpdf_mlp_get_weights(self._h, a.ctypes.data_as(C.c_void_p), a.size), self._h)
+        return a
+
+    def mlp_set_norm(self, mean, std):
+        import numpy as np
+        m = np.ascontiguousarray(mean, np.float32)
+        s = np.ascontiguousarray(std, np.float32)
+        _check(self.lib.gpdf_mlp_set_norm(self._h, m.ctypes.data_as(C.c_void_p),
+                                          s.ctypes.data_as(C.c_void_p)), self._h)
+
+    def mlp_features(self, res):
+        torch = self._torch
+        n = res["dist"].shape[0]
+        f = torch.empty((n, 7), dtype=torch.float32, device=self.device)
+        _check(self.lib.gpdf_mlp_features(self._h, _dptr(res["dist"]), _dptr(res["var"]),
+                                          _dptr(res["grad"]), _dptr(res["aux"]), n, _dptr(f)),
+               self._h)
+        return f
+
+    def mlp_forward(self, feat):
+        torch = self._torch
+        r = torch.empty(feat.shape[0], dtype=torch.float32, device=self.device)
+        _check(self.lib.gpdf_mlp_forward(self._h, _dptr(feat, torch.float32, 7), feat.shape[0],
+                                         _dptr(r)), self._h)
+        return r
+
+    def mlp_grad(self, feat, target):
+        torch = self._torch
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=self.device)
+        loss = C.c_float(0)
+        _check(self.lib.gpdf_mlp_grad(self._h, _dptr(feat, torch.float32, 7),
+                                      _dptr(target, torch.float32), feat.shape[0], _dptr(g),
+                                      C.byref(loss)), self._h)
+        return g, loss.value
+
+    def mlp_train(self, feat, target, epochs=1, batch=1024, lr=1e-3, seed=0):
+        torch = self._torch
+        loss = C.c_float(0)
+        _check(self.lib.gpdf_mlp_train(self._h, _dptr(feat, torch.float32, 7),
+                                       _dptr(target, torch.float32), feat.shape[0], int(epochs),
+                                       int(batch), float(lr), int(seed), C.byref(loss)), self._h)
+        return loss.value

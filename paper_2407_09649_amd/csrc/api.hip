@@ -1,0 +1,297 @@
+// api.hip -- the C ABI of libvdbgpdf.so: parameters, context and arenas,
+// argument checks, statistics and model export.  Every computational step
+// runs in the kernels of sort.hip, train.hip, query.hip, fuse.hip, mlp.hip.
+#include "gpdf_internal.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace gpdf {
+
+gpdf_status fail(gpdf_ctx *c, gpdf_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+gpdf_status hip_fail(gpdf_ctx *c, hipError_t e, const char *what) {
+    if (c) c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return GPDF_E_HIP;
+}
+
+}  // namespace gpdf
+
+using namespace gpdf;
+
+namespace {
+
+uint32_t pow2_mask(int64_t want) {
+    uint64_t cap = 1024;
+    while (int64_t(cap) < want) cap <<= 1;
+    return uint32_t(cap - 1);
+}
+
+void release(gpdf_ctx *c) {
+    void *ptrs[] = {c->d_key, c->d_key2, c->d_val, c->d_val2, c->d_flag, c->d_scan, c->d_hist,
+                    c->d_part, c->d_red, c->d_pts, c->d_alpha64, c->d_ckey, c->d_coff, c->d_pd,
+                    c->d_woff32, c->d_woff64, c->d_aoff, c->d_W32, c->d_W64, c->d_A, c->d_chash,
+                    c->d_chash_val, c->d_qhash, c->d_qhash_cnt, c->d_qhash_cell, c->d_qslot,
+                    c->d_qrank, c->d_order, c->d_cell_key, c->d_cell_cnt, c->d_cell_off,
+                    c->d_cell_chunks, c->d_chunk_off, c->d_cell_list, c->d_chunk, c->d_refine,
+                    c->d_tmp_dist, c->d_tmp_var, c->d_tmp_grad, c->d_tmp_valid, c->d_tset,
+                    c->d_tkeys, c->d_tpts, c->d_gkey, c->d_gD, c->d_gV, c->d_gstamp, c->d_offs,
+                    c->d_mlp_w, c->d_mlp_m, c->d_mlp_v, c->d_mlp_g, c->d_mlp_norm, c->d_mlp_feat,
+                    c->d_mlp_perm, c->d_mlp_loss, c->d_stat};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->h_stat) (void)hipHostFree(c->h_stat);
+}
+
+template <typename T>
+bool dalloc(T *&p, int64_t count, hipError_t &e) {
+    if (count < 1) count = 1;
+    e = hipMalloc((void **)&p, sizeof(T) * size_t(count));
+    return e == hipSuccess;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+extern "C" gpdf_status gpdf_params_default(gpdf_params *p) {
+    if (!p) return GPDF_E_INVALID_ARG;
+    std::memset(p, 0, sizeof *p);
+    p->abi_version = GPDF_ABI_VERSION;
+    p->kernel = GPDF_KERNEL_MATERN32;
+    p->length_scale = 0.2;
+    p->noise_sigma = 0.01;
+    p->voxel_size = 0.0;
+    p->cluster_size = 0.4;
+    p->selection = GPDF_SEL_NEIGHBOR27;
+    p->knn_q = 8;
+    p->combine = GPDF_COMB_SMOOTHMIN;
+    p->grad_mode = GPDF_GRAD_WEIGHTED;
+    p->smooth_min_lambda = 100.0;
+    p->occ_min = 1e-15;
+    p->occ_max = 1.0 - 1e-5;
+    p->precision = GPDF_PREC_FP32;
+    p->fuse_voxel_size = 0.05;
+    p->fuse_band = 0.2;
+    p->mlp_gate = 0.05;
+    p->max_points = int64_t(1) << 21;
+    p->max_clusters = int64_t(1) << 18;
+    p->max_cluster_points = 1024;
+    p->max_factor_elems = int64_t(1) << 24;
+    p->max_queries = int64_t(6) << 20;
+    p->global_capacity = int64_t(1) << 24;
+    return GPDF_OK;
+}
+
+extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_ctx **out) {
+    if (!p || !out) return GPDF_E_INVALID_ARG;
+    *out = nullptr;
+    if (p->abi_version != GPDF_ABI_VERSION) return GPDF_E_INVALID_ARG;
+    if (!finite_pos(p->length_scale) || !(std::isfinite(p->noise_sigma) && p->noise_sigma >= 0.0) ||
+        !(std::isfinite(p->voxel_size) && p->voxel_size >= 0.0) ||
+        (p->voxel_size == 0.0 && !finite_pos(p->cluster_size)) ||
+        !finite_pos(p->smooth_min_lambda) || !finite_pos(p->occ_min) ||
+        !(p->occ_max > p->occ_min && p->occ_max < 1.0) || !finite_pos(p->fuse_voxel_size) ||
+        !(std::isfinite(p->fuse_band) && p->fuse_band >= 0.0) ||
+        (p->kernel != GPDF_KERNEL_MATERN32 && p->kernel != GPDF_KERNEL_SE) ||
+        (p->selection != GPDF_SEL_NEIGHBOR27 && p->selection != GPDF_SEL_KNN) ||
+        (p->selection == GPDF_SEL_KNN && (p->knn_q < 1 || p->knn_q > 16)) ||
+        (p->combine != GPDF_COMB_SMOOTHMIN && p->combine != GPDF_COMB_HARDMIN) ||
+        (p->grad_mode != GPDF_GRAD_WEIGHTED && p->grad_mode != GPDF_GRAD_PAPER_MEAN) ||
+        (p->precision < GPDF_PREC_FP32 || p->precision > GPDF_PREC_FP64) || p->max_points < 1 ||
+        p->max_points > (int64_t(1) << 30) || p->max_clusters < 1 || p->max_cluster_points < 1 ||
+        p->max_cluster_points > 1024 || p->max_factor_elems < 1 || p->max_queries < 1 ||
+        p->max_queries > (int64_t(1) << 30) || p->global_capacity < 1 ||
+        p->global_capacity > (int64_t(1) << 30))
+        return GPDF_E_INVALID_ARG;
+    gpdf_ctx *c = new (std::nothrow) gpdf_ctx();
+    if (!c) return GPDF_E_OOM;
+    c->p = *p;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    (void)hipGetDevice(&c->device);
+    hipError_t e = hipSuccess;
+    const int64_t P = p->max_points, C = p->max_clusters, M = p->max_queries;
+    const int64_t nbP = (P + 4095) / 4096;
+    const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(P, M), 256 * nbP) + 1;
+    c->cap_w = p->max_factor_elems;
+    c->cap_a = 2 * p->max_factor_elems;
+    c->chash_mask = pow2_mask(2 * C);
+    c->qhash_mask = pow2_mask(2 * M);
+    c->tset_mask = pow2_mask(2 * M);
+    c->gmask = pow2_mask(2 * p->global_capacity);
+    c->offs_cap = 1 << 16;
+    const int64_t chunks = M + M / 64 + 2;
+    bool ok = dalloc(c->d_key, P + 1, e) && dalloc(c->d_key2, P + 1, e) && dalloc(c->d_val, P + 1, e) &&
+              dalloc(c->d_val2, P + 1, e) && dalloc(c->d_flag, P + 1, e) &&
+              dalloc(c->d_scan, scan_n, e) && dalloc(c->d_hist, 256 * nbP + 1, e) &&
+              dalloc(c->d_part, scan_n / 4096 + 64, e) && dalloc(c->d_red, 8, e) &&
+              dalloc(c->d_pts, P, e) && dalloc(c->d_alpha64, P, e) && dalloc(c->d_ckey, C + 1, e) &&
+              dalloc(c->d_coff, C + 1, e) && dalloc(c->d_pd, C + 1, e) && dalloc(c->d_woff32, C, e) &&
+              dalloc(c->d_woff64, C, e) && dalloc(c->d_aoff, C, e) && dalloc(c->d_W32, c->cap_w, e) &&
+              dalloc(c->d_W64, c->cap_w, e) && dalloc(c->d_A, c->cap_a, e) &&
+              dalloc(c->d_chash, int64_t(c->chash_mask) + 1, e) &&
+              dalloc(c->d_chash_val, int64_t(c->chash_mask) + 1, e) &&
+              dalloc(c->d_qhash, int64_t(c->qhash_mask) + 1, e) &&
+              dalloc(c->d_qhash_cnt, int64_t(c->qhash_mask) + 1, e) &&
+              dalloc(c->d_qhash_cell, int64_t(c->qhash_mask) + 1, e) && dalloc(c->d_qslot, M, e) &&
+              dalloc(c->d_qrank, M, e) && dalloc(c->d_order, M, e) && dalloc(c->d_cell_key, M + 1, e) &&
+              dalloc(c->d_cell_cnt, M + 1, e) && dalloc(c->d_cell_off, M + 1, e) &&
+              dalloc(c->d_cell_chunks, M + 1, e) && dalloc(c->d_chunk_off, M + 1, e) &&
+              dalloc(c->d_cell_list, (M + 1) * 28, e) && dalloc(c->d_chunk, chunks, e) &&
+              dalloc(c->d_refine, M, e) && dalloc(c->d_tmp_dist, M, e) && dalloc(c->d_tmp_var, M, e) &&
+              dalloc(c->d_tmp_grad, 3 * M, e) && dalloc(c->d_tmp_valid, M, e) &&
+              dalloc(c->d_tset, int64_t(c->tset_mask) + 1, e) && dalloc(c->d_tkeys, M, e) &&
+              dalloc(c->d_tpts, 3 * M, e) && dalloc(c->d_gkey, int64_t(c->gmask) + 1, e) &&
+              dalloc(c->d_gD, int64_t(c->gmask) + 1, e) && dalloc(c->d_gV, int64_t(c->gmask) + 1, e) &&
+              dalloc(c->d_gstamp, int64_t(c->gmask) + 1, e) && dalloc(c->d_offs, c->offs_cap, e) &&
+              dalloc(c->d_stat, ST_COUNT, e);
+    if (ok) {
+        e = hipHostMalloc((void **)&c->h_stat, sizeof(unsigned long long) * ST_COUNT, 0);
+        ok = e == hipSuccess;
+    }
+    if (!ok) {
+        release(c);
+        delete c;
+        return e == hipErrorOutOfMemory ? GPDF_E_OOM : GPDF_E_HIP;
+    }
+    fill_u64(c->d_stat, 0ull, ST_COUNT, c->stream);
+    fill_u64(c->d_gkey, (unsigned long long)kNoKey, int64_t(c->gmask) + 1, c->stream);
+    fill_u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1, c->stream);
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) {
+        release(c);
+        delete c;
+        return GPDF_E_HIP;
+    }
+    *out = c;
+    return GPDF_OK;
+}
+
+extern "C" void gpdf_destroy(gpdf_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+}
+
+extern "C" gpdf_status gpdf_train_local_gps(gpdf_ctx *c, const float *d_xyz, int64_t n) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    if (n < 0 || (n > 0 && !d_xyz)) return fail(c, GPDF_E_INVALID_ARG, "train: bad arguments");
+    try {
+        return train(c, d_xyz, n);
+    } catch (...) {
+        return fail(c, GPDF_E_OOM, "train: host allocation failed");
+    }
+}
+
+extern "C" gpdf_status gpdf_query_distance(gpdf_ctx *c, const float *d_q, int64_t m,
+                                           const float *h_origin, float *d_dist, float *d_grad,
+                                           float *d_var, uint8_t *d_valid, float *d_aux,
+                                           int32_t correct) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    try {
+        return query(c, d_q, m, h_origin, d_dist, d_grad, d_var, d_valid, d_aux, correct);
+    } catch (...) {
+        return fail(c, GPDF_E_OOM, "query: host allocation failed");
+    }
+}
+
+extern "C" gpdf_status gpdf_fuse_frame(gpdf_ctx *c, const float *d_xyz, int64_t n,
+                                       const float *h_origin) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    if (!h_origin || !(std::isfinite(h_origin[0]) && std::isfinite(h_origin[1]) &&
+                       std::isfinite(h_origin[2])))
+        return fail(c, GPDF_E_INVALID_ARG, "fuse: origin required");
+    try {
+        if (d_xyz) {
+            gpdf_status s = train(c, d_xyz, n);
+            if (s != GPDF_OK) return s;
+        }
+        return fuse(c, h_origin);
+    } catch (...) {
+        return fail(c, GPDF_E_OOM, "fuse: host allocation failed");
+    }
+}
+
+extern "C" gpdf_status gpdf_query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *d_dist,
+                                         float *d_grad, uint8_t *d_valid) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    return query_global(c, d_q, m, d_dist, d_grad, d_valid);
+}
+
+extern "C" gpdf_status gpdf_get_stats(gpdf_ctx *c, gpdf_stats *out) {
+    if (!c || !out) return GPDF_E_INVALID_ARG;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(c->h_stat, c->d_stat, sizeof(unsigned long long) * ST_COUNT,
+                            hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        return hip_fail(c, e, "get_stats");
+    const unsigned long long *h = c->h_stat;
+    std::memset(out, 0, sizeof *out);
+    out->clusters = c->model.nclusters;
+    out->points = c->model.npoints;
+    out->nonpd_clusters = int64_t(h[ST_NONPD]);
+    out->skipped_points = int64_t(h[ST_SKIPPED_POINTS]);
+    out->queries = c->last_queries;
+    out->valid_queries = int64_t(h[ST_VALID_Q]);
+    out->refined_queries = int64_t(h[ST_REFINE]);
+    out->test_points = c->last_test;
+    out->fused = int64_t(h[ST_FUSED]);
+    out->fuse_skipped = int64_t(h[ST_FUSE_SKIPPED]);
+    out->global_voxels = int64_t(h[ST_GLOBAL_COUNT]);
+    out->gated = int64_t(h[ST_GATED]);
+    uint32_t bits = 0;
+    if (h[ST_HASH_FULL]) bits |= GPDF_STATUS_HASH_FULL;
+    if (h[ST_GLOBAL_FULL]) bits |= GPDF_STATUS_GLOBAL_FULL;
+    if (h[ST_SKIPPED_POINTS] || h[ST_NONFINITE_Q]) bits |= GPDF_STATUS_NONFINITE;
+    if (h[ST_NONPD]) bits |= GPDF_STATUS_NONPD;
+    out->status_bits = bits;
+    // the status bits and training counters are read once; per-call counters
+    // are reset by the calls themselves
+    fill_u64(c->d_stat + ST_HASH_FULL, 0ull, 1, c->stream);
+    fill_u64(c->d_stat + ST_GLOBAL_FULL, 0ull, 1, c->stream);
+    return GPDF_OK;
+}
+
+extern "C" const char *gpdf_last_error(const gpdf_ctx *c) {
+    return c ? c->err.c_str() : "null context";
+}
+
+extern "C" gpdf_status gpdf_export_model(gpdf_ctx *c, uint64_t *h_ckey, int64_t *h_off,
+                                         float *h_points, double *h_alpha, uint8_t *h_pd) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    if (!c->model.trained) return fail(c, GPDF_E_NOT_TRAINED, "export before training");
+    const int64_t nc = c->model.nclusters, np = c->model.npoints;
+    hipError_t e;
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "export");
+    if (h_ckey && nc && (e = hipMemcpy(h_ckey, c->d_ckey, 8 * nc, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(c, e, "export keys");
+    if (h_off) {
+        std::vector<int32_t> o(nc + 1, 0);
+        if (nc && (e = hipMemcpy(o.data(), c->d_coff, 4 * (nc + 1), hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(c, e, "export offsets");
+        for (int64_t i = 0; i <= nc; ++i) h_off[i] = o[i];
+    }
+    if (h_points && np) {
+        std::vector<float4> p(np);
+        if ((e = hipMemcpy(p.data(), c->d_pts, 16 * np, hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(c, e, "export points");
+        for (int64_t i = 0; i < np; ++i) {
+            h_points[3 * i] = p[i].x; h_points[3 * i + 1] = p[i].y; h_points[3 * i + 2] = p[i].z;
+        }
+    }
+    if (h_alpha && np && (e = hipMemcpy(h_alpha, c->d_alpha64, 8 * np, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(c, e, "export alpha");
+    if (h_pd && nc && (e = hipMemcpy(h_pd, c->d_pd, nc, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(c, e, "export pd");
+    return GPDF_OK;
+}
+
+extern "C" gpdf_status gpdf_nearest_distance(gpdf_ctx *c, const float *d_pts, int64_t n,
+                                             const float *d_q, int64_t m, float *d_out) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    return nearest_distance(c, d_pts, n, d_q, m, d_out);
+}

@@ -1,0 +1,410 @@
+// fuse.hip -- test points, probabilistic fusion into the global grid, and the
+// global query (Sec. IV-B, IV-C, Eq. (7)-(8)).
+//
+// The global VDB is replaced by an open-addressing hash of voxel keys with
+// structure-of-arrays payload (D, V, stamp).  Test voxels are unique per
+// frame, so every voxel has at most one writer per fusion launch and the
+// update needs no floating-point atomics.
+#include "gpdf_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace gpdf {
+
+namespace {
+
+constexpr int kT = 256;
+
+inline unsigned blocks_for(int64_t n, int t = kT) {
+    int64_t g = (n + t - 1) / t;
+    return unsigned(g < 1 ? 1 : g);
+}
+
+// candidate test voxels: the global-grid cell of every training point plus
+// every integer offset inside the band ball
+__global__ void k_test_insert(const float4 *__restrict__ pts, int64_t npts, double hf,
+                              const int4 *__restrict__ offs, int noffs, HashView set,
+                              unsigned long long *__restrict__ stat) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= npts * noffs) return;
+    const int64_t i = t / noffs;
+    const int k = int(t - i * noffs);
+    const float4 p = pts[i];
+    int64_t c[3];
+    if (!(cell_coord(p.x, hf, c[0]) && cell_coord(p.y, hf, c[1]) && cell_coord(p.z, hf, c[2]))) return;
+    const int4 o = offs[k];
+    const int64_t v[3] = {c[0] + o.x, c[1] + o.y, c[2] + o.z};
+    for (int a = 0; a < 3; ++a)
+        if (v[a] < -kBias || v[a] >= kBias) return;
+    bool ins;
+    if (hash_insert(set, pack_key(v[0], v[1], v[2]), &ins) < 0) atomicAdd(&stat[ST_HASH_FULL], 1ull);
+}
+
+__global__ void k_test_compact(const unsigned long long *__restrict__ keys, int64_t cap,
+                               uint64_t *__restrict__ out, int64_t out_cap, double hf,
+                               float *__restrict__ xyz, unsigned long long *__restrict__ stat) {
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= cap) return;
+    const unsigned long long k = keys[s];
+    if (k == kNoKey) return;
+    const unsigned long long id = atomicAdd(&stat[ST_TESTPTS], 1ull);
+    if (int64_t(id) >= out_cap) return;
+    out[id] = k;
+    int64_t c[3];
+    unpack_key(k, c);
+    // voxel centre (c + 1/2) h formed in FP64, rounded once
+    xyz[3 * id] = float((double(c[0]) + 0.5) * hf);
+    xyz[3 * id + 1] = float((double(c[1]) + 0.5) * hf);
+    xyz[3 * id + 2] = float((double(c[2]) + 0.5) * hf);
+}
+
+// Eq. (7)-(8): D <- (V d + v D) / (V + v), V <- V v / (V + v); an absent voxel
+// takes (d, v) (the V = infinity limit)
+__global__ void k_fuse(const uint64_t *__restrict__ keys, const unsigned long long *__restrict__ nptr,
+                       const float *__restrict__ d, const float *__restrict__ v,
+                       const uint8_t *__restrict__ ok, HashView g, float *__restrict__ gD,
+                       float *__restrict__ gV, uint32_t *__restrict__ gstamp, uint32_t frame,
+                       unsigned long long *__restrict__ stat) {
+    const int64_t n = int64_t(*nptr);
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float di = d[i], vi = v[i];
+    if (!ok[i] || !isfinite(di) || !isfinite(vi) || !(vi > 0.f)) {
+        atomicAdd(&stat[ST_FUSE_SKIPPED], 1ull);
+        return;
+    }
+    bool ins;
+    const int64_t s = hash_insert(g, keys[i], &ins);
+    if (s < 0) {
+        atomicAdd(&stat[ST_GLOBAL_FULL], 1ull);
+        return;
+    }
+    if (ins) {
+        gD[s] = di;
+        gV[s] = vi;
+        atomicAdd(&stat[ST_GLOBAL_COUNT], 1ull);
+    } else {
+        const float Vp = gV[s], Dp = gD[s];
+        const float den = Vp + vi;
+        gD[s] = (Vp * di + vi * Dp) / den;
+        gV[s] = (Vp * vi) / den;
+    }
+    gstamp[s] = frame;
+    atomicAdd(&stat[ST_FUSED], 1ull);
+}
+
+// trilinear interpolation of D over the eight voxel centres around x
+__global__ void k_global_query(const float *__restrict__ q, int64_t m, double h,
+                               const unsigned long long *__restrict__ gkey, uint32_t gmask,
+                               const float *__restrict__ gD, float *__restrict__ dist,
+                               float *__restrict__ grad, uint8_t *__restrict__ valid) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double f[3];
+    int64_t i0[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        const float x = q[3 * j + a];
+        if (!isfinite(x)) { ok = false; break; }
+        const double u = double(x) / h - 0.5;
+        const double fl = floor(u);
+        if (fl < -double(kBias) || fl + 1.0 >= double(kBias)) { ok = false; break; }
+        i0[a] = int64_t(fl);
+        f[a] = u - fl;
+    }
+    double Dc[8];
+    for (int b = 0; b < 8 && ok; ++b) {
+        const int64_t s = hash_find(gkey, gmask,
+                                    pack_key(i0[0] + ((b >> 2) & 1), i0[1] + ((b >> 1) & 1),
+                                             i0[2] + (b & 1)));
+        if (s < 0) ok = false;
+        else Dc[b] = double(gD[s]);
+    }
+    if (!ok) {
+        dist[j] = INFINITY;
+        valid[j] = 0;
+        if (grad) { grad[3 * j] = 0.f; grad[3 * j + 1] = 0.f; grad[3 * j + 2] = 0.f; }
+        return;
+    }
+    double D = 0.0, G[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < 8; ++b) {
+        const int bx = (b >> 2) & 1, by = (b >> 1) & 1, bz = b & 1;
+        const double wx = bx ? f[0] : 1.0 - f[0], wy = by ? f[1] : 1.0 - f[1],
+                     wz = bz ? f[2] : 1.0 - f[2];
+        const double sx = bx ? 1.0 : -1.0, sy = by ? 1.0 : -1.0, sz = bz ? 1.0 : -1.0;
+        D += wx * wy * wz * Dc[b];
+        G[0] += sx * wy * wz * Dc[b];
+        G[1] += wx * sy * wz * Dc[b];
+        G[2] += wx * wy * sz * Dc[b];
+    }
+    dist[j] = float(D);
+    valid[j] = 1;
+    if (grad) {
+        grad[3 * j] = float(G[0] / h);
+        grad[3 * j + 1] = float(G[1] / h);
+        grad[3 * j + 2] = float(G[2] / h);
+    }
+}
+
+__global__ void k_global_load(const uint64_t *__restrict__ k, const float *__restrict__ D,
+                              const float *__restrict__ V, const uint32_t *__restrict__ st, int64_t n,
+                              HashView g, float *__restrict__ gD, float *__restrict__ gV,
+                              uint32_t *__restrict__ gs, unsigned long long *__restrict__ stat) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool ins;
+    const int64_t s = hash_insert(g, k[i], &ins);
+    if (s < 0) {
+        atomicAdd(&stat[ST_GLOBAL_FULL], 1ull);
+        return;
+    }
+    gD[s] = D[i];
+    gV[s] = V[i];
+    gs[s] = st[i];
+    if (ins) atomicAdd(&stat[ST_GLOBAL_COUNT], 1ull);
+}
+
+// brute-force nearest distance, FP32 differences, exact minimum
+__global__ void k_nearest(const float *__restrict__ pts, int64_t n, const float *__restrict__ q,
+                          int64_t m, float *__restrict__ out) {
+    __shared__ float sp[3][kT];
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool act = j < m;
+    const float qx = act ? q[3 * j] : 0.f, qy = act ? q[3 * j + 1] : 0.f, qz = act ? q[3 * j + 2] : 0.f;
+    float best = INFINITY;
+    for (int64_t b = 0; b < n; b += kT) {
+        __syncthreads();
+        const int64_t i = b + threadIdx.x;
+        if (i < n) { sp[0][threadIdx.x] = pts[3 * i]; sp[1][threadIdx.x] = pts[3 * i + 1]; sp[2][threadIdx.x] = pts[3 * i + 2]; }
+        __syncthreads();
+        const int cnt = int(min<int64_t>(kT, n - b));
+        for (int t = 0; t < cnt; ++t) {
+            const float dx = qx - sp[0][t], dy = qy - sp[1][t], dz = qz - sp[2][t];
+            best = fminf(best, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+        }
+    }
+    if (act) out[j] = sqrtf(best);
+}
+
+}  // namespace
+
+gpdf_status fuse(gpdf_ctx *c, const float *origin) {
+    hipStream_t s = c->stream;
+    const Model &M = c->model;
+    if (!M.trained) return fail(c, GPDF_E_NOT_TRAINED, "fuse before training");
+    hipError_t e;
+    fill_u64(c->d_stat + ST_TESTPTS, 0ull, 1, s);
+    fill_u64(c->d_stat + ST_FUSED, 0ull, 1, s);
+    fill_u64(c->d_stat + ST_FUSE_SKIPPED, 0ull, 1, s);
+    if (M.npoints == 0) {
+        c->last_test = 0;
+        c->frame++;
+        return GPDF_OK;
+    }
+    // band offsets
+    const double hf = c->p.fuse_voxel_size;
+    const int R = int(std::floor(c->p.fuse_band / hf + 1e-9));
+    std::vector<int4> &offs = c->h_offs;
+    offs.clear();
+    for (int a = -R; a <= R; ++a)
+        for (int b = -R; b <= R; ++b)
+            for (int d = -R; d <= R; ++d)
+                if (a * a + b * b + d * d <= R * R) offs.push_back(make_int4(a, b, d, 0));
+    if (int64_t(offs.size()) > c->offs_cap) return fail(c, GPDF_E_CAPACITY, "fuse: band too wide");
+    if ((e = hipMemcpyAsync(c->d_offs, offs.data(), sizeof(int4) * offs.size(), hipMemcpyHostToDevice,
+                            s)) != hipSuccess)
+        return hip_fail(c, e, "fuse: upload offsets");
+    const int64_t tcap = int64_t(c->tset_mask) + 1;
+    fill_u64(c->d_tset, (unsigned long long)kNoKey, tcap, s);
+    HashView set{c->d_tset, c->tset_mask};
+    const int64_t work = M.npoints * int64_t(offs.size());
+    hipLaunchKernelGGL(k_test_insert, dim3(blocks_for(work)), dim3(kT), 0, s, c->d_pts, M.npoints, hf,
+                       c->d_offs, int(offs.size()), set, c->d_stat);
+    hipLaunchKernelGGL(k_test_compact, dim3(blocks_for(tcap)), dim3(kT), 0, s, c->d_tset, tcap,
+                       c->d_tkeys, c->p.max_queries, hf, c->d_tpts, c->d_stat);
+    unsigned long long nt = 0;
+    if ((e = hipMemcpyAsync(&nt, c->d_stat + ST_TESTPTS, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(c, e, "fuse: read test count");
+    if (int64_t(nt) > c->p.max_queries) return fail(c, GPDF_E_CAPACITY, "fuse: test points exceed max_queries");
+    c->last_test = int64_t(nt);
+    gpdf_status st = query(c, c->d_tpts, int64_t(nt), origin, c->d_tmp_dist, nullptr, c->d_tmp_var,
+                           c->d_tmp_valid, nullptr, 0);
+    if (st != GPDF_OK) return st;
+    HashView g{c->d_gkey, c->gmask};
+    hipLaunchKernelGGL(k_fuse, dim3(blocks_for(int64_t(nt))), dim3(kT), 0, s, c->d_tkeys,
+                       c->d_stat + ST_TESTPTS, c->d_tmp_dist, c->d_tmp_var, c->d_tmp_valid, g, c->d_gD,
+                       c->d_gV, c->d_gstamp, c->frame, c->d_stat);
+    c->frame++;
+    return (e = hipGetLastError()) == hipSuccess ? GPDF_OK : hip_fail(c, e, "fuse launch");
+}
+
+gpdf_status query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *dist, float *grad,
+                         uint8_t *valid) {
+    if (m < 0) return fail(c, GPDF_E_INVALID_ARG, "query_global: m < 0");
+    if (m == 0) return GPDF_OK;
+    if (!d_q || !dist || !valid) return fail(c, GPDF_E_INVALID_ARG, "query_global: null buffer");
+    hipLaunchKernelGGL(k_global_query, dim3(blocks_for(m)), dim3(kT), 0, c->stream, d_q, m,
+                       c->p.fuse_voxel_size, c->d_gkey, c->gmask, c->d_gD, dist, grad, valid);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GPDF_OK : hip_fail(c, e, "query_global launch");
+}
+
+gpdf_status nearest_distance(gpdf_ctx *c, const float *pts, int64_t n, const float *q, int64_t m,
+                             float *out) {
+    if (n <= 0 || m < 0 || !pts || !out || (m > 0 && !q))
+        return fail(c, GPDF_E_INVALID_ARG, "nearest_distance: bad arguments");
+    if (m == 0) return GPDF_OK;
+    hipLaunchKernelGGL(k_nearest, dim3(blocks_for(m)), dim3(kT), 0, c->stream, pts, n, q, m, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GPDF_OK : hip_fail(c, e, "nearest launch");
+}
+
+}  // namespace gpdf
+
+using namespace gpdf;
+
+namespace {
+struct Rec {
+    uint64_t k;
+    float D, V;
+    uint32_t st;
+};
+
+gpdf_status read_global(gpdf_ctx *c, std::vector<Rec> &out) {
+    const int64_t cap = int64_t(c->gmask) + 1;
+    std::vector<unsigned long long> k(cap);
+    std::vector<float> D(cap), V(cap);
+    std::vector<uint32_t> st(cap);
+    hipError_t e;
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess ||
+        (e = hipMemcpy(k.data(), c->d_gkey, 8 * cap, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(D.data(), c->d_gD, 4 * cap, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(V.data(), c->d_gV, 4 * cap, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(st.data(), c->d_gstamp, 4 * cap, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(c, e, "read global grid");
+    out.clear();
+    for (int64_t i = 0; i < cap; ++i)
+        if (k[i] != kNoKey) out.push_back(Rec{k[i], D[i], V[i], st[i]});
+    std::sort(out.begin(), out.end(), [](const Rec &a, const Rec &b) { return a.k < b.k; });
+    return GPDF_OK;
+}
+}  // namespace
+
+extern "C" gpdf_status gpdf_export_global(gpdf_ctx *c, uint64_t *h_key, float *h_D, float *h_V,
+                                          uint32_t *h_stamp, int64_t cap, int64_t *count) {
+    if (!c || !count) return GPDF_E_INVALID_ARG;
+    std::vector<Rec> r;
+    gpdf_status s = read_global(c, r);
+    if (s != GPDF_OK) return s;
+    *count = int64_t(r.size());
+    if (int64_t(r.size()) > cap) return GPDF_OK;
+    for (size_t i = 0; i < r.size(); ++i) {
+        if (h_key) h_key[i] = r[i].k;
+        if (h_D) h_D[i] = r[i].D;
+        if (h_V) h_V[i] = r[i].V;
+        if (h_stamp) h_stamp[i] = r[i].st;
+    }
+    return GPDF_OK;
+}
+
+extern "C" gpdf_status gpdf_export_test_points(gpdf_ctx *c, uint64_t *h_key, int64_t cap,
+                                               int64_t *count) {
+    if (!c || !count) return GPDF_E_INVALID_ARG;
+    hipError_t e;
+    const int64_t n = c->last_test;
+    *count = n;
+    if (n > cap || n == 0) return GPDF_OK;
+    std::vector<uint64_t> k(n);
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess ||
+        (e = hipMemcpy(k.data(), c->d_tkeys, 8 * n, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(c, e, "export test points");
+    std::sort(k.begin(), k.end());
+    std::memcpy(h_key, k.data(), 8 * n);
+    return GPDF_OK;
+}
+
+namespace {
+constexpr uint64_t kMagic = 0x4650444742445631ull;  // "1VDBGDPF"
+struct FileHeader {
+    uint64_t magic;
+    uint32_t version, frame;
+    double voxel;
+    int64_t count;
+};
+}  // namespace
+
+extern "C" gpdf_status gpdf_save_global(gpdf_ctx *c, const char *path) {
+    if (!c || !path) return GPDF_E_INVALID_ARG;
+    std::vector<Rec> r;
+    gpdf_status s = read_global(c, r);
+    if (s != GPDF_OK) return s;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(c, GPDF_E_INVALID_ARG, "save_global: cannot open file");
+    FileHeader h{kMagic, 1u, c->frame, c->p.fuse_voxel_size, int64_t(r.size())};
+    bool ok = std::fwrite(&h, sizeof h, 1, f) == 1;
+    for (size_t i = 0; ok && i < r.size(); ++i) {
+        ok = std::fwrite(&r[i].k, 8, 1, f) == 1 && std::fwrite(&r[i].D, 4, 1, f) == 1 &&
+             std::fwrite(&r[i].V, 4, 1, f) == 1 && std::fwrite(&r[i].st, 4, 1, f) == 1;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? GPDF_OK : fail(c, GPDF_E_INVALID_ARG, "save_global: write failed");
+}
+
+extern "C" gpdf_status gpdf_load_global(gpdf_ctx *c, const char *path) {
+    if (!c || !path) return GPDF_E_INVALID_ARG;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(c, GPDF_E_INVALID_ARG, "load_global: cannot open file");
+    FileHeader h{};
+    if (std::fread(&h, sizeof h, 1, f) != 1 || h.magic != kMagic || h.version != 1u || h.count < 0 ||
+        h.voxel != c->p.fuse_voxel_size) {
+        std::fclose(f);
+        return fail(c, GPDF_E_INVALID_ARG, "load_global: bad header or voxel size");
+    }
+    if (h.count > c->p.global_capacity) {
+        std::fclose(f);
+        return fail(c, GPDF_E_CAPACITY, "load_global: file exceeds global_capacity");
+    }
+    std::vector<uint64_t> k(h.count);
+    std::vector<float> D(h.count), V(h.count);
+    std::vector<uint32_t> st(h.count);
+    bool ok = true;
+    for (int64_t i = 0; ok && i < h.count; ++i)
+        ok = std::fread(&k[i], 8, 1, f) == 1 && std::fread(&D[i], 4, 1, f) == 1 &&
+             std::fread(&V[i], 4, 1, f) == 1 && std::fread(&st[i], 4, 1, f) == 1;
+    std::fclose(f);
+    if (!ok) return fail(c, GPDF_E_INVALID_ARG, "load_global: truncated file");
+    hipStream_t s = c->stream;
+    hipError_t e;
+    const int64_t cap = int64_t(c->gmask) + 1;
+    fill_u64(c->d_gkey, (unsigned long long)kNoKey, cap, s);
+    fill_u64(c->d_stat + ST_GLOBAL_COUNT, 0ull, 1, s);
+    c->frame = h.frame;
+    if (h.count == 0) return GPDF_OK;
+    // stage the records through the test-point buffers (host to device)
+    uint64_t *dk = nullptr;
+    float *dD = nullptr, *dV = nullptr;
+    uint32_t *ds = nullptr;
+    if ((e = hipMallocAsync((void **)&dk, 8 * h.count, s)) != hipSuccess ||
+        (e = hipMallocAsync((void **)&dD, 4 * h.count, s)) != hipSuccess ||
+        (e = hipMallocAsync((void **)&dV, 4 * h.count, s)) != hipSuccess ||
+        (e = hipMallocAsync((void **)&ds, 4 * h.count, s)) != hipSuccess)
+        return hip_fail(c, e, "load_global: allocate staging");
+    if ((e = hipMemcpyAsync(dk, k.data(), 8 * h.count, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(dD, D.data(), 4 * h.count, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(dV, V.data(), 4 * h.count, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(ds, st.data(), 4 * h.count, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(c, e, "load_global: upload");
+    HashView g{c->d_gkey, c->gmask};
+    hipLaunchKernelGGL(k_global_load, dim3(unsigned((h.count + kT - 1) / kT)), dim3(kT), 0, s, dk, dD,
+                       dV, ds, h.count, g, c->d_gD, c->d_gV, c->d_gstamp, c->d_stat);
+    hipFreeAsync(dk, s);
+    hipFreeAsync(dD, s);
+    hipFreeAsync(dV, s);
+    hipFreeAsync(ds, s);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "load_global");
+    return GPDF_OK;
+}

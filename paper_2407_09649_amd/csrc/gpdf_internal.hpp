@@ -1,0 +1,248 @@
+// gpdf_internal.hpp -- internal declarations shared by the HIP sources of
+// libvdbgpdf.so.  Not installed; the public interface is include/vdbgpdf.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "vdbgpdf.h"
+
+namespace gpdf {
+
+// ---------------------------------------------------------------------------
+// keys: integer cell coordinates c = floor(x / h) taken in FP64, packed as
+// three 21-bit offset-binary fields (x high).  ~0 marks "no key".
+// ---------------------------------------------------------------------------
+constexpr int64_t kBias = int64_t(1) << 20;
+constexpr uint64_t kNoKey = ~uint64_t(0);
+
+__host__ __device__ inline uint64_t pack_key(int64_t cx, int64_t cy, int64_t cz) {
+    return (uint64_t(cx + kBias) << 42) | (uint64_t(cy + kBias) << 21) | uint64_t(cz + kBias);
+}
+__host__ __device__ inline void unpack_key(uint64_t k, int64_t c[3]) {
+    c[0] = int64_t((k >> 42) & 0x1FFFFF) - kBias;
+    c[1] = int64_t((k >> 21) & 0x1FFFFF) - kBias;
+    c[2] = int64_t(k & 0x1FFFFF) - kBias;
+}
+// floor(x / h) in FP64 with IEEE division; false for non-finite or out of range
+__device__ inline bool cell_coord(float x, double h, int64_t &c) {
+    if (!isfinite(x)) return false;
+    double f = floor(__ddiv_rn(double(x), h));
+    if (f < -double(kBias) || f >= double(kBias)) return false;
+    c = int64_t(f);
+    return true;
+}
+__host__ __device__ inline int64_t floor_div8(int64_t a) {  // arithmetic shift = floor
+    return a >> 3;
+}
+
+// 64-bit finaliser of MurmurHash3 (Appleby), a bijective mixer
+__host__ __device__ inline uint64_t mix64(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdULL;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ULL;
+    k ^= k >> 33;
+    return k;
+}
+
+// open-addressing table of 64-bit keys, linear probing, capacity 2^k
+struct HashView {
+    unsigned long long *keys;  // kNoKey = empty
+    uint32_t mask;             // capacity - 1
+};
+
+// find-or-insert; returns the slot or -1 if the probe sequence is exhausted
+__device__ inline int64_t hash_insert(HashView h, uint64_t key, bool *inserted) {
+    uint64_t s = mix64(key) & h.mask;
+    for (uint32_t p = 0; p <= h.mask; ++p) {
+        unsigned long long prev = atomicCAS(&h.keys[s], (unsigned long long)kNoKey,
+                                            (unsigned long long)key);
+        if (prev == kNoKey) { *inserted = true; return int64_t(s); }
+        if (prev == key) { *inserted = false; return int64_t(s); }
+        s = (s + 1) & h.mask;
+    }
+    *inserted = false;
+    return -1;
+}
+
+__device__ inline int64_t hash_find(const unsigned long long *__restrict__ keys, uint32_t mask,
+                                    uint64_t key) {
+    uint64_t s = mix64(key) & mask;
+    for (uint32_t p = 0; p <= mask; ++p) {
+        unsigned long long k = keys[s];
+        if (k == key) return int64_t(s);
+        if (k == kNoKey) return -1;
+        s = (s + 1) & mask;
+    }
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// device status block (uint64 counters)
+// ---------------------------------------------------------------------------
+enum Stat : int {
+    ST_SKIPPED_POINTS = 0,
+    ST_NONPD,
+    ST_NONFINITE_Q,
+    ST_VALID_Q,
+    ST_REFINE,       // number of refine records
+    ST_HASH_FULL,
+    ST_GLOBAL_FULL,
+    ST_FUSED,
+    ST_FUSE_SKIPPED,
+    ST_GLOBAL_COUNT, // voxels in the global grid
+    ST_CELLS,        // query cells of the last query call
+    ST_CHUNKS,       // query chunks of the last query call
+    ST_TESTPTS,      // unique test voxels of the last frame
+    ST_GATED,
+    ST_COUNT
+};
+
+// per-cluster FP32 factor layout: packed rows for n <= 64, 64-row panels
+// (column-major inside the panel) above that
+constexpr int kPanel = 64;
+__host__ __device__ inline int64_t w32_size(int64_t n) {
+    if (n <= kPanel) return n * (n + 1) / 2;
+    int64_t nb = (n + kPanel - 1) / kPanel, s = 0;
+    for (int64_t r = 0; r < nb; ++r) s += int64_t(kPanel) * ((r + 1) * kPanel < n ? (r + 1) * kPanel : n);
+    return s;
+}
+__host__ __device__ inline int64_t w32_panel_offset(int64_t n, int64_t r) {
+    int64_t s = 0;
+    for (int64_t q = 0; q < r; ++q) s += int64_t(kPanel) * ((q + 1) * kPanel < n ? (q + 1) * kPanel : n);
+    return s;
+}
+
+// query arithmetic knobs passed by value to the kernels
+struct QueryConsts {
+    float l, a;             // length scale and sqrt(3)/l (Matern) or 1/l (SE)
+    float c;                // l / sqrt(3) (Matern) or l (SE)
+    float lam;              // smooth-minimum lambda
+    float omin, omax;
+    float tau_d, tau_g, tau_v;  // FP32 error-estimate thresholds for FP64 refinement
+    float err_c;            // error-bound constant on sum |alpha k|
+    int kernel, combine, grad_mode, knn_q;
+    int signed_, has_origin_pad;
+    float ox, oy, oz;       // sensor origin (signed queries)
+    double ld, sd, hv, hc;  // FP64 copies: l, s, voxel, cell
+    double lamd, omind, omaxd;
+};
+
+struct Model {
+    int64_t nclusters = 0, npoints = 0, nonpd = 0, skipped = 0, max_n = 0;
+    bool trained = false;
+    std::vector<int32_t> h_n;  // cluster sizes (host copy)
+};
+
+}  // namespace gpdf
+
+struct gpdf_ctx {
+    gpdf_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    gpdf::Model model;
+
+    // ---- training arenas --------------------------------------------------
+    uint64_t *d_key = nullptr, *d_key2 = nullptr;  // sort keys  [max_points]
+    uint32_t *d_val = nullptr, *d_val2 = nullptr;  // sort values
+    uint32_t *d_flag = nullptr, *d_scan = nullptr; // [max_points + 1]
+    uint32_t *d_hist = nullptr;                    // radix histograms
+    uint32_t *d_part = nullptr;                    // scan partials
+    uint64_t *d_red = nullptr;                     // small reductions
+    float4 *d_pts = nullptr;                       // training points (x, y, z, alpha32)
+    double *d_alpha64 = nullptr;                   // alpha in FP64
+    uint64_t *d_ckey = nullptr;                    // cluster keys [max_clusters]
+    int32_t *d_coff = nullptr;                     // CSR offsets  [max_clusters + 1]
+    uint8_t *d_pd = nullptr;                       // positive definite
+    int64_t *d_woff32 = nullptr, *d_woff64 = nullptr, *d_aoff = nullptr;
+    float *d_W32 = nullptr;                        // FP32 inverse factors
+    double *d_W64 = nullptr;                       // FP64 inverse factors (packed columns)
+    double *d_A = nullptr;                         // FP64 workspace (K, then L)
+    int64_t cap_w = 0, cap_a = 0;
+    std::vector<int64_t> h_o32, h_o64, h_oa;       // factor offsets (host)
+    unsigned long long *d_chash = nullptr;         // cluster hash keys
+    int32_t *d_chash_val = nullptr;
+    uint32_t chash_mask = 0;
+
+    // ---- query arenas ------------------------------------------------------
+    unsigned long long *d_qhash = nullptr;         // cell table keys
+    uint32_t *d_qhash_cnt = nullptr;               // queries per slot
+    int32_t *d_qhash_cell = nullptr;               // slot -> cell id
+    uint32_t qhash_mask = 0;
+    int32_t *d_qslot = nullptr;                    // per query slot (-1 invalid)
+    uint32_t *d_qrank = nullptr;                   // rank inside the cell
+    uint32_t *d_order = nullptr;                   // queries in cell order
+    uint64_t *d_cell_key = nullptr;                // per cell
+    uint32_t *d_cell_cnt = nullptr, *d_cell_off = nullptr;
+    uint32_t *d_cell_chunks = nullptr, *d_chunk_off = nullptr;
+    int32_t *d_cell_list = nullptr;                // [cells][28]: count, ids
+    uint2 *d_chunk = nullptr;                      // (cell, start)
+    uint32_t *d_refine = nullptr;                  // query indices to redo in FP64
+    float *d_tmp_dist = nullptr, *d_tmp_var = nullptr, *d_tmp_grad = nullptr;
+    uint8_t *d_tmp_valid = nullptr;
+
+    // ---- fusion / global grid ---------------------------------------------
+    unsigned long long *d_tset = nullptr;          // test-voxel set keys
+    uint32_t tset_mask = 0;
+    uint64_t *d_tkeys = nullptr;                   // compacted test keys
+    float *d_tpts = nullptr;                       // test points [3]
+    unsigned long long *d_gkey = nullptr;          // global grid keys
+    float *d_gD = nullptr, *d_gV = nullptr;
+    uint32_t *d_gstamp = nullptr;
+    uint32_t gmask = 0;
+    uint32_t frame = 0;
+    std::vector<int4> h_offs;                      // band offsets (host)
+    int4 *d_offs = nullptr;
+    int64_t offs_cap = 0;
+    int64_t last_test = 0;
+
+    // ---- MLP ----------------------------------------------------------------
+    float *d_mlp_w = nullptr;       // FP32 master weights [8897]
+    float *d_mlp_m = nullptr, *d_mlp_v = nullptr;  // Adam moments
+    float *d_mlp_g = nullptr;       // gradient accumulator
+    float *d_mlp_norm = nullptr;    // mean[7], std[7]
+    float *d_mlp_feat = nullptr;    // scratch for features
+    uint32_t *d_mlp_perm = nullptr;
+    float *d_mlp_loss = nullptr;
+    int64_t mlp_cap = 0;
+    bool mlp_ready = false;
+    int64_t adam_t = 0;
+
+    // ---- counters ----------------------------------------------------------
+    unsigned long long *d_stat = nullptr;          // [ST_COUNT]
+    unsigned long long *h_stat = nullptr;          // pinned mirror
+    int64_t last_queries = 0;
+};
+
+namespace gpdf {
+// error helpers
+gpdf_status fail(gpdf_ctx *c, gpdf_status s, const std::string &msg);
+gpdf_status hip_fail(gpdf_ctx *c, hipError_t e, const char *what);
+
+// scans and sorting (sort.hip)
+void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
+                        hipStream_t s);
+void radix_sort_pairs(uint64_t *&keys, uint64_t *&keys_alt, uint32_t *&vals, uint32_t *&vals_alt,
+                      int64_t n, uint64_t varying_bits, uint32_t *hist, uint32_t *partials,
+                      hipStream_t s);
+void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
+void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+// stages (train.hip, query.hip, fuse.hip, mlp.hip)
+gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n);
+gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin, float *dist,
+                  float *grad, float *var, uint8_t *valid, float *aux, int32_t correct);
+gpdf_status fuse(gpdf_ctx *c, const float *origin);
+gpdf_status query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *dist, float *grad,
+                         uint8_t *valid);
+gpdf_status nearest_distance(gpdf_ctx *c, const float *pts, int64_t n, const float *q, int64_t m,
+                             float *out);
+gpdf_status mlp_apply(gpdf_ctx *c, const float *d_dist, const float *d_var, const float *d_grad,
+                      const float *d_aux, const uint8_t *valid, int64_t m, float *dist_out);
+QueryConsts make_consts(const gpdf_params &p, const float *origin);
+}  // namespace gpdf

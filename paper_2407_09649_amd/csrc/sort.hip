@@ -1,0 +1,229 @@
+// sort.hip -- device-wide exclusive scan, stable LSD radix sort of
+// (uint64 key, uint32 value) pairs, and fill kernels.
+//
+// The radix sort is what makes every result-bearing order deterministic:
+// clusters come out in ascending key order and members keep ascending voxel
+// key (voxel mode) or input index (raw mode), independent of hash-slot races.
+#include "gpdf_internal.hpp"
+
+namespace gpdf {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096 elements per block
+
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// block-wide exclusive scan of one value per thread; returns the block total
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds_wave, uint32_t &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == 63) lds_wave[wave] = inc;
+    __syncthreads();
+    uint32_t wave_off = 0, tot = 0;
+    for (int w = 0; w < nwaves; ++w) {
+        uint32_t s = lds_wave[w];
+        if (w < wave) wave_off += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return wave_off + inc - v;
+}
+
+__global__ void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
+                              uint32_t *__restrict__ partials) {
+    __shared__ uint32_t lds[kScanThreads / 64];
+    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t idx = base + int64_t(i) * kScanThreads + threadIdx.x;
+        if (idx < n) s += in[idx];
+    }
+    uint32_t tot;
+    block_exclusive_scan(s, lds, tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the block partials (any count)
+__global__ void k_scan_partials(uint32_t *__restrict__ partials, int64_t nb) {
+    __shared__ uint32_t lds[kScanThreads / 64];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += kScanThreads) {
+        int64_t idx = base + threadIdx.x;
+        uint32_t v = idx < nb ? partials[idx] : 0;
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan(v, lds, tot);
+        uint32_t c = carry;
+        if (idx < nb) partials[idx] = c + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+}
+
+// each thread owns kScanItems consecutive elements
+__global__ void k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                            int64_t n, const uint32_t *__restrict__ partials) {
+    __shared__ uint32_t lds[kScanThreads / 64];
+    const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t idx = base + i;
+        v[i] = idx < n ? in[idx] : 0;
+        s += v[i];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, lds, tot) + partials[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+    }
+    // the total lands one past the end: written by the thread whose range
+    // holds index n, or by the last thread when n fills the final tile
+    const bool last = blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1;
+    if ((base <= n && n < base + kScanItems) || (last && n == base + kScanItems)) out[n] = run;
+}
+
+// ---------------------------------------------------------------------------
+// radix sort, 8-bit digits
+// ---------------------------------------------------------------------------
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;
+
+__global__ void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                          uint32_t *__restrict__ hist, int64_t nblocks) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = int64_t(blockIdx.x) * kRsTile;
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        int64_t idx = base + int64_t(r) * kRsThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 0xFF], 1u);
+    }
+    __syncthreads();
+    hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                             uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
+                             int shift, const uint32_t *__restrict__ hist, int64_t nblocks) {
+    constexpr int W = kRsThreads / 64;
+    __shared__ uint32_t base_d[256];
+    __shared__ uint32_t wcnt[W][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    base_d[threadIdx.x] = hist[int64_t(threadIdx.x) * nblocks + blockIdx.x];
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    const int64_t tile = int64_t(blockIdx.x) * kRsTile;
+    for (int r = 0; r < kRsItems; ++r) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) wcnt[w][threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t idx = tile + int64_t(r) * kRsThreads + threadIdx.x;
+        const bool ok = idx < n;
+        uint64_t k = ok ? kin[idx] : 0;
+        uint32_t v = ok ? vin[idx] : 0;
+        uint32_t d = uint32_t(k >> shift) & 0xFF;
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t m = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? m : ~m;
+        }
+        const uint32_t below = __popcll(peers & lt);
+        if (ok && below == 0) wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (ok) {
+            uint32_t off = base_d[d] + below;
+            for (int w = 0; w < wave; ++w) off += wcnt[w][d];
+            kout[off] = k;
+            vout[off] = v;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) add += wcnt[w][threadIdx.x];
+        base_d[threadIdx.x] += add;
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+
+inline unsigned grid_for(int64_t n, int threads) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g > 65536) g = 65536;
+    return unsigned(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+// out[i] = sum_{j < i} in[j] for i <= n (out has n + 1 entries).
+// partials needs ceil(n / 4096) + 1 entries.
+void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
+                        hipStream_t s) {
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(unsigned(nb)), dim3(kScanThreads), 0, s, in, n, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s, partials, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3(unsigned(nb)), dim3(kScanThreads), 0, s, in, out, n,
+                       partials);
+}
+
+// Stable sort by key over the 8-bit digits that contain varying bits; the
+// result ends in (keys, vals) (pointers are swapped as needed).  hist needs
+// 256 * ceil(n / 4096) entries, partials ceil(256 * ceil(n / 4096) / 4096) + 1.
+void radix_sort_pairs(uint64_t *&keys, uint64_t *&keys_alt, uint32_t *&vals, uint32_t *&vals_alt,
+                      int64_t n, uint64_t varying_bits, uint32_t *hist, uint32_t *partials,
+                      hipStream_t s) {
+    if (n <= 1) return;
+    const int64_t nb = (n + kRsTile - 1) / kRsTile;
+    for (int shift = 0; shift < 64; shift += 8) {
+        if (((varying_bits >> shift) & 0xFF) == 0) continue;
+        hipLaunchKernelGGL(k_rs_hist, dim3(unsigned(nb)), dim3(kRsThreads), 0, s, keys, n, shift,
+                           hist, nb);
+        exclusive_scan_u32(hist, hist, 256 * nb, partials, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(unsigned(nb)), dim3(kRsThreads), 0, s, keys, vals,
+                           keys_alt, vals_alt, n, shift, hist, nb);
+        std::swap(keys, keys_alt);
+        std::swap(vals, vals_alt);
+    }
+}
+
+void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+}
+void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+}
+
+}  // namespace gpdf
