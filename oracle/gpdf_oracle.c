@@ -536,7 +536,12 @@ static void orc_eval_pair(const orc_model *m, int64_t c, const double x[3],
         orc_revert(p, oc, &d, &lam);                   /* Eq. (3) */
         r->d = d;
         r->v = lam * lam * r->u;                       /* Eq. (4) */
-        for (int a = 0; a < 3; ++a) r->g[a] = lam * go[a];  /* chain rule */
+        /* chain rule on the returned distance r(clamp(o)): below the lower
+         * cap that distance is the constant r(occ_min), so its gradient is
+         * zero; at the upper cap Lambda(occ_max) grad o keeps the direction
+         * of the surface normal (the cap only guards the singularity of r
+         * at o = 1) */
+        for (int a = 0; a < 3; ++a) r->g[a] = occ < p->occ_min ? 0.0 : lam * go[a];
     }
 }
 

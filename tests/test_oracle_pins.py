@@ -577,3 +577,18 @@ def test_voxel_downsample_centres():
     for cidx in range(m.nclusters):
         blk = leaf[e["off"][cidx]:e["off"][cidx + 1]]
         assert (blk == blk[0]).all()
+
+
+def test_lower_cap_saturates_distance_and_zeroes_gradient():
+    # beyond the point where k(r) / (1 + s^2) < occ_min the capped distance
+    # is r(occ_min) = l sqrt(-2 ln occ_min) (SE closed form), and constant
+    l = 0.2
+    p0 = np.array([2.0, 2.0, 2.0], np.float32)
+    m, prm = _one_point_model(SE, p0, l=l, s=0.01)
+    q = np.array([[2.0, 2.0, 3.9], [2.0, 3.95, 2.0], [2.0, 2.0, 2.5]], np.float32)
+    r = m.query(q)
+    dmax = l * math.sqrt(-2.0 * math.log(prm.occ_min))
+    assert abs(r["dist"][0] - dmax) < 1e-12 and abs(r["dist"][1] - dmax) < 1e-12
+    assert (r["grad"][:2] == 0.0).all()
+    # inside the cap range the gradient is the unit direction (single point)
+    assert abs(np.linalg.norm(r["grad"][2]) - 1.0) < 1e-3
