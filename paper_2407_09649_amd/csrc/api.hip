@@ -34,10 +34,12 @@ uint32_t pow2_mask(int64_t want) {
 void release(gpdf_ctx *c) {
     void *ptrs[] = {c->d_key, c->d_key2, c->d_val, c->d_val2, c->d_flag, c->d_scan, c->d_hist,
                     c->d_part, c->d_red, c->d_pts, c->d_alpha64, c->d_ckey, c->d_coff, c->d_pd,
-                    c->d_woff32, c->d_woff64, c->d_aoff, c->d_W32, c->d_W64, c->d_A, c->d_chash,
+                    c->d_woff, c->d_wtoff, c->d_aoff, c->d_W32, c->d_W64, c->d_Wt, c->d_A, c->d_chash,
                     c->d_chash_val, c->d_qhash, c->d_qhash_cnt, c->d_qhash_cell, c->d_qslot,
                     c->d_qrank, c->d_order, c->d_cell_key, c->d_cell_cnt, c->d_cell_off,
                     c->d_cell_chunks, c->d_chunk_off, c->d_cell_list, c->d_chunk, c->d_refine,
+                    c->d_rcnt, c->d_roff, c->d_rchunks, c->d_rchunk_off, c->d_rorder, c->d_rrank,
+                    c->d_rchunk,
                     c->d_tmp_dist, c->d_tmp_var, c->d_tmp_grad, c->d_tmp_valid, c->d_tset,
                     c->d_tkeys, c->d_tpts, c->d_gkey, c->d_gD, c->d_gV, c->d_gstamp, c->d_offs,
                     c->d_mlp_w, c->d_mlp_m, c->d_mlp_v, c->d_mlp_g, c->d_mlp_norm, c->d_mlp_feat,
@@ -130,9 +132,10 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
               dalloc(c->d_scan, scan_n, e) && dalloc(c->d_hist, 256 * nbP + 1, e) &&
               dalloc(c->d_part, scan_n / 4096 + 64, e) && dalloc(c->d_red, 8, e) &&
               dalloc(c->d_pts, P, e) && dalloc(c->d_alpha64, P, e) && dalloc(c->d_ckey, C + 1, e) &&
-              dalloc(c->d_coff, C + 1, e) && dalloc(c->d_pd, C + 1, e) && dalloc(c->d_woff32, C, e) &&
-              dalloc(c->d_woff64, C, e) && dalloc(c->d_aoff, C, e) && dalloc(c->d_W32, c->cap_w, e) &&
-              dalloc(c->d_W64, c->cap_w, e) && dalloc(c->d_A, c->cap_a, e) &&
+              dalloc(c->d_coff, C + 1, e) && dalloc(c->d_pd, C + 1, e) && dalloc(c->d_woff, C, e) &&
+              dalloc(c->d_wtoff, C, e) && dalloc(c->d_aoff, C, e) && dalloc(c->d_W32, c->cap_w, e) &&
+              dalloc(c->d_W64, c->cap_w, e) && dalloc(c->d_Wt, c->cap_w, e) &&
+              dalloc(c->d_A, c->cap_a, e) &&
               dalloc(c->d_chash, int64_t(c->chash_mask) + 1, e) &&
               dalloc(c->d_chash_val, int64_t(c->chash_mask) + 1, e) &&
               dalloc(c->d_qhash, int64_t(c->qhash_mask) + 1, e) &&
@@ -142,7 +145,9 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
               dalloc(c->d_cell_cnt, M + 1, e) && dalloc(c->d_cell_off, M + 1, e) &&
               dalloc(c->d_cell_chunks, M + 1, e) && dalloc(c->d_chunk_off, M + 1, e) &&
               dalloc(c->d_cell_list, (M + 1) * 28, e) && dalloc(c->d_chunk, chunks, e) &&
-              dalloc(c->d_refine, M, e) && dalloc(c->d_tmp_dist, M, e) && dalloc(c->d_tmp_var, M, e) &&
+              dalloc(c->d_refine, M, e) && dalloc(c->d_rcnt, M + 1, e) && dalloc(c->d_roff, M + 1, e) &&
+              dalloc(c->d_rchunks, M + 1, e) && dalloc(c->d_rchunk_off, M + 1, e) &&
+              dalloc(c->d_rorder, M, e) && dalloc(c->d_rrank, M, e) && dalloc(c->d_rchunk, chunks, e) && dalloc(c->d_tmp_dist, M, e) && dalloc(c->d_tmp_var, M, e) &&
               dalloc(c->d_tmp_grad, 3 * M, e) && dalloc(c->d_tmp_valid, M, e) &&
               dalloc(c->d_tset, int64_t(c->tset_mask) + 1, e) && dalloc(c->d_tkeys, M, e) &&
               dalloc(c->d_tpts, 3 * M, e) && dalloc(c->d_gkey, int64_t(c->gmask) + 1, e) &&

@@ -130,6 +130,7 @@ struct QueryConsts {
     float ox, oy, oz;       // sensor origin (signed queries)
     double ld, sd, hv, hc;  // FP64 copies: l, s, voxel, cell
     double lamd, omind, omaxd;
+    double ad, cd;          // FP64 copies of a and c
 };
 
 struct Model {
@@ -159,9 +160,11 @@ struct gpdf_ctx {
     uint64_t *d_ckey = nullptr;                    // cluster keys [max_clusters]
     int32_t *d_coff = nullptr;                     // CSR offsets  [max_clusters + 1]
     uint8_t *d_pd = nullptr;                       // positive definite
-    int64_t *d_woff32 = nullptr, *d_woff64 = nullptr, *d_aoff = nullptr;
-    float *d_W32 = nullptr;                        // FP32 inverse factors
-    double *d_W64 = nullptr;                       // FP64 inverse factors (packed columns)
+    int64_t *d_woff = nullptr;                     // factor offsets, query layout
+    int64_t *d_wtoff = nullptr, *d_aoff = nullptr; // workspace offsets
+    float *d_W32 = nullptr;                        // L^{-1} in FP32, query layout
+    double *d_W64 = nullptr;                       // L^{-1} in FP64, query layout
+    double *d_Wt = nullptr;                        // FP64 workspace: L^{-1} by packed columns
     double *d_A = nullptr;                         // FP64 workspace (K, then L)
     int64_t cap_w = 0, cap_a = 0;
     std::vector<int64_t> h_o32, h_o64, h_oa;       // factor offsets (host)
@@ -182,7 +185,11 @@ struct gpdf_ctx {
     uint32_t *d_cell_chunks = nullptr, *d_chunk_off = nullptr;
     int32_t *d_cell_list = nullptr;                // [cells][28]: count, ids
     uint2 *d_chunk = nullptr;                      // (cell, start)
-    uint32_t *d_refine = nullptr;                  // query indices to redo in FP64
+    uint2 *d_refine = nullptr;                     // (cell, query) records to redo in FP64
+    uint32_t *d_rcnt = nullptr, *d_roff = nullptr; // refine records per cell
+    uint32_t *d_rchunks = nullptr, *d_rchunk_off = nullptr;
+    uint32_t *d_rorder = nullptr, *d_rrank = nullptr;
+    uint2 *d_rchunk = nullptr;
     float *d_tmp_dist = nullptr, *d_tmp_var = nullptr, *d_tmp_grad = nullptr;
     uint8_t *d_tmp_valid = nullptr;
 

@@ -155,8 +155,9 @@ constexpr int kMaxClusterN = 1024;
 
 __global__ __launch_bounds__(kT) void k_train_clusters(
     float4 *__restrict__ pts, const int32_t *__restrict__ coff, const int64_t *__restrict__ aoff,
-    const int64_t *__restrict__ woff32, const int64_t *__restrict__ woff64, double *__restrict__ Aall,
-    double *__restrict__ W64all, float *__restrict__ W32all, double *__restrict__ alpha64,
+    const int64_t *__restrict__ woff, const int64_t *__restrict__ wtoff, double *__restrict__ Aall,
+    double *__restrict__ Wtall, double *__restrict__ W64all, float *__restrict__ W32all,
+    double *__restrict__ alpha64,
     uint8_t *__restrict__ pd, int kernel, double l, double s2, unsigned long long *__restrict__ stat) {
     __shared__ float sx[kMaxClusterN], sy[kMaxClusterN], sz[kMaxClusterN];
     __shared__ double sA[kMaxLdsN * kMaxLdsN];
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(kT) void k_train_clusters(
     const int n = coff[c + 1] - base;
     const int tid = threadIdx.x;
     double *A = (n <= kMaxLdsN) ? sA : Aall + aoff[c];
-    double *W = W64all + woff64[c];
+    double *W = Wtall + wtoff[c];
     for (int i = tid; i < n; i += kT) {
         float4 p = pts[base + i];
         sx[i] = p.x; sy[i] = p.y; sz[i] = p.z;
@@ -244,8 +245,10 @@ __global__ __launch_bounds__(kT) void k_train_clusters(
         alpha64[base + j] = s;
         pts[base + j].w = float(s);
     }
-    // FP32 copy of W in the query layout
-    float *W32 = W32all + woff32[c];
+    // W in the query layout, FP32 and FP64: packed rows for n <= 64, 64-row
+    // panels (column-major inside, zero above the diagonal) above that
+    float *W32 = W32all + woff[c];
+    double *W64 = W64all + woff[c];
     if (n <= kPanel) {
         for (int64_t idx = tid; idx < int64_t(n) * (n + 1) / 2; idx += kT) {
             // row i holds entries i (i + 1) / 2 .. i (i + 1) / 2 + i
@@ -253,19 +256,22 @@ __global__ __launch_bounds__(kT) void k_train_clusters(
             while (int64_t(i + 1) * (i + 2) / 2 <= idx) ++i;
             while (int64_t(i) * (i + 1) / 2 > idx) --i;
             const int j = int(idx - int64_t(i) * (i + 1) / 2);
-            W32[idx] = float(W[int64_t(j) * n - int64_t(j) * (j - 1) / 2 + (i - j)]);
+            const double w = W[int64_t(j) * n - int64_t(j) * (j - 1) / 2 + (i - j)];
+            W32[idx] = float(w);
+            W64[idx] = w;
         }
     } else {
         const int nb = (n + kPanel - 1) / kPanel;
         for (int r = 0; r < nb; ++r) {
-            float *P = W32 + w32_panel_offset(n, r);
+            const int64_t po = w32_panel_offset(n, r);
             const int ncol = std::min((r + 1) * kPanel, n);
             for (int idx = tid; idx < ncol * kPanel; idx += kT) {
                 const int j = idx / kPanel, rr = idx - j * kPanel;
                 const int i = r * kPanel + rr;
-                float v = 0.0f;
-                if (i < n && j <= i) v = float(W[int64_t(j) * n - int64_t(j) * (j - 1) / 2 + (i - j)]);
-                P[idx] = v;
+                double v = 0.0;
+                if (i < n && j <= i) v = W[int64_t(j) * n - int64_t(j) * (j - 1) / 2 + (i - j)];
+                W32[po + idx] = float(v);
+                W64[po + idx] = v;
             }
         }
     }
@@ -376,14 +382,14 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n) {
         M.trained = false;
         return fail(c, GPDF_E_CAPACITY, "train: factor storage exceeds max_factor_elems");
     }
-    if ((e = hipMemcpyAsync(c->d_woff32, o32.data(), 8 * ncl, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(c->d_woff64, o64.data(), 8 * ncl, hipMemcpyHostToDevice, s)) != hipSuccess ||
+    if ((e = hipMemcpyAsync(c->d_woff, o32.data(), 8 * ncl, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(c->d_wtoff, o64.data(), 8 * ncl, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(c->d_aoff, oa.data(), 8 * ncl, hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(c, e, "train: upload offsets");
     // 5. FP64 training
     const double l = c->p.length_scale, s2 = c->p.noise_sigma * c->p.noise_sigma;
     hipLaunchKernelGGL(k_train_clusters, dim3(ncl), dim3(kT), 0, s, c->d_pts, c->d_coff, c->d_aoff,
-                       c->d_woff32, c->d_woff64, c->d_A, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
+                       c->d_woff, c->d_wtoff, c->d_A, c->d_Wt, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
                        c->p.kernel, l, s2, c->d_stat);
     // 6. cluster hash
     fill_u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1, s);

@@ -1,0 +1,88 @@
+"""Shared helpers of the GPU parity tests: run the C-ABI library and the
+oracle on the same inputs and compare element by element.
+
+Tolerances (FP32 path against the FP64 oracle):
+  distance   |d - d_o| <= 1e-4 m
+  gradient   max_i |g_i - g_o,i| <= 1e-3
+  variance   |v / v_o - 1| <= 2e-3 (the FP32 path sends queries whose
+             estimated relative variance error exceeds 1e-3 to FP64; 2e-3
+             leaves a factor 2 for the estimate)
+  validity, sign, n_local: exact
+FP64 path: FP64-level agreement plus the final rounding of the FP32 outputs.
+"""
+import numpy as np
+import torch
+
+import oracle as O
+import paper_2407_09649_amd as P
+
+TOL_D, TOL_G, TOL_V = 1e-4, 1e-3, 2e-3
+
+
+def small_params(**kw):
+    base = dict(max_points=1 << 20, max_clusters=1 << 16, max_queries=1 << 20,
+                global_capacity=1 << 20, max_factor_elems=1 << 23)
+    base.update(kw)
+    return P.Params.default(**base)
+
+
+def oracle_params(p: P.Params) -> O.Params:
+    return O.Params(kernel=p.kernel, selection=p.selection, knn_q=p.knn_q,
+                    combine=p.combine, grad_mode=p.grad_mode, l=p.length_scale,
+                    s=p.noise_sigma, voxel=p.voxel_size, cell=p.cluster_size,
+                    lam=p.smooth_min_lambda, occ_min=p.occ_min, occ_max=p.occ_max,
+                    fuse_voxel=p.fuse_voxel_size, fuse_band=p.fuse_band)
+
+
+def gpu_query(ctx, q, origin=None):
+    dev = ctx.device
+    r = ctx.query(torch.from_numpy(np.ascontiguousarray(q, np.float32)).to(dev), origin=origin)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+def compare(g, o, fp64=False, check_aux=True, label=""):
+    """Element-wise comparison; returns a dict of maximum errors."""
+    vg = g["valid"].astype(bool)
+    vo = np.asarray(o["valid"]).astype(bool)
+    assert (vg == vo).all(), f"{label}: validity differs on {(vg != vo).sum()} queries"
+    v = vo
+    inval = ~v
+    assert np.isinf(g["dist"][inval]).all() and (g["grad"][inval] == 0).all()
+    out = dict(n=int(v.sum()))
+    if not v.any():
+        return out
+    d_err = np.abs(g["dist"][v] - o["dist"][v])
+    g_err = np.abs(g["grad"][v] - o["grad"][v]).max(1)
+    v_rel = np.abs(g["var"][v] / o["var"][v] - 1.0)
+    out.update(d=float(d_err.max()), g=float(g_err.max()), v=float(v_rel.max()))
+    if fp64:
+        # FP64 arithmetic, results stored as FP32: one rounding (2^-24
+        # relative) on top of FP64-level agreement
+        u = 2.0 ** -24
+        assert (d_err <= 1e-9 + 2 * u * np.abs(o["dist"][v])).all(), (label, d_err.max())
+        gmax = np.abs(o["grad"][v]).max(1)
+        assert (g_err <= 1e-8 + 2 * u * gmax).all(), (label, g_err.max())
+        assert (v_rel <= 1e-8 + 2 * u).all(), (label, v_rel.max())
+    else:
+        assert (d_err <= TOL_D).all(), (label, d_err.max())
+        assert (g_err <= TOL_G).all(), (label, g_err.max())
+        assert (v_rel <= TOL_V).all(), (label, v_rel.max())
+    # the sign is decided identically on both sides
+    assert (np.sign(g["dist"][v]) == np.sign(o["dist"][v])).all(), label
+    if check_aux:
+        assert (g["aux"][v, 2] == o["aux"][v, 2]).all(), f"{label}: n_local differs"
+    return out
+
+
+def export_equal(ctx, om, alpha_rtol=1e-9):
+    e = ctx.export_model()
+    eo = om.export()
+    assert np.array_equal(e["ckey"], eo["ckey"]), "cluster keys differ"
+    assert np.array_equal(e["off"], eo["off"]), "cluster offsets differ"
+    assert np.array_equal(e["points"].view(np.uint32), eo["points"].view(np.uint32)), \
+        "training points differ"
+    assert np.array_equal(e["pd"], eo["pd"])
+    scale = np.abs(eo["alpha"]).max() if eo["alpha"].size else 1.0
+    assert np.abs(e["alpha"] - eo["alpha"]).max(initial=0.0) <= alpha_rtol * scale
+    return e
