@@ -88,7 +88,8 @@ typedef struct {
     double smooth_min_lambda;  /* 100 in Sec. IV-D */
     double occ_min, occ_max;   /* caps on the latent occupancy (footnote 1) */
     int32_t precision;         /* GPDF_PREC_* */
-    int32_t pad0;
+    int32_t timing;            /* 1: time each stage with HIP events on the
+                                  context stream (gpdf_stats.ms) */
     double fuse_voxel_size;    /* global grid edge */
     double fuse_band;          /* test-point band radius, metres */
     double mlp_gate;           /* correction applied where variance <= gate */
@@ -113,9 +114,26 @@ typedef struct {
     int64_t fuse_skipped;      /* invalid or non-finite observations */
     int64_t global_voxels;     /* voxels in the global grid */
     int64_t gated;             /* queries corrected by the MLP */
+    int64_t eval_pairs;        /* last query, FP32 27-cell pass: (query, cluster) pairs */
+    int64_t eval_points;       /*   kernel evaluations, sum of n over the pairs */
+    int64_t eval_tri;          /*   variance multiply-adds, sum of n (n + 1) / 2 */
     uint32_t status_bits;      /* GPDF_STATUS_* set since the last read */
     uint32_t pad0;
+    float ms[8];               /* with timing = 1: GPU time of the last run of
+                                  each stage (GPDF_MS_*), milliseconds;
+                                  -1 when the stage has not run */
 } gpdf_stats;
+
+enum {
+    GPDF_MS_TRAIN = 0,   /* gpdf_train_local_gps, all kernels */
+    GPDF_MS_GROUP = 1,   /* query: grouping by cell and neighbour lists */
+    GPDF_MS_EVAL = 2,    /* query: the main evaluation kernel */
+    GPDF_MS_REFINE = 3,  /* query: regrouping and FP64 re-evaluation */
+    GPDF_MS_TESTPTS = 4, /* fuse: test-voxel generation */
+    GPDF_MS_FUSE = 5,    /* fuse: the update of the global grid */
+    GPDF_MS_GLOBAL = 6,  /* gpdf_query_global */
+    GPDF_MS_MLP = 7      /* learned correction (features, forward, gate) */
+};
 
 enum {
     GPDF_STATUS_HASH_FULL = 1u,       /* a probe sequence exhausted a table */

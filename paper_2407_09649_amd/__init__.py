@@ -53,7 +53,7 @@ class Params(C.Structure):
         ("selection", C.c_int32), ("knn_q", C.c_int32),
         ("combine", C.c_int32), ("grad_mode", C.c_int32),
         ("smooth_min_lambda", C.c_double), ("occ_min", C.c_double),
-        ("occ_max", C.c_double), ("precision", C.c_int32), ("pad0", C.c_int32),
+        ("occ_max", C.c_double), ("precision", C.c_int32), ("timing", C.c_int32),
         ("fuse_voxel_size", C.c_double), ("fuse_band", C.c_double),
         ("mlp_gate", C.c_double),
         ("max_points", C.c_int64), ("max_clusters", C.c_int64),
@@ -76,11 +76,16 @@ class Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "clusters", "points", "nonpd_clusters", "skipped_points", "queries",
         "valid_queries", "refined_queries", "test_points", "fused",
-        "fuse_skipped", "global_voxels", "gated")] + [
-        ("status_bits", C.c_uint32), ("pad0", C.c_uint32)]
+        "fuse_skipped", "global_voxels", "gated", "eval_pairs", "eval_points",
+        "eval_tri")] + [
+        ("status_bits", C.c_uint32), ("pad0", C.c_uint32), ("ms", C.c_float * 8)]
+
+    STAGES = ("train", "group", "eval", "refine", "testpts", "fuse", "global", "mlp")
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad0"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("pad0", "ms")}
+        d["ms"] = {k: float(self.ms[i]) for i, k in enumerate(self.STAGES)}
+        return d
 
 
 _lib = None

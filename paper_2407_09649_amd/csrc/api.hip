@@ -47,6 +47,8 @@ void release(gpdf_ctx *c) {
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
+    for (hipEvent_t &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
 }
 
 template <typename T>
@@ -77,6 +79,7 @@ extern "C" gpdf_status gpdf_params_default(gpdf_params *p) {
     p->occ_min = 1e-15;
     p->occ_max = 1.0 - 1e-5;
     p->precision = GPDF_PREC_FP32;
+    p->timing = 0;
     p->fuse_voxel_size = 0.05;
     p->fuse_band = 0.2;
     p->mlp_gate = 0.05;
@@ -104,7 +107,8 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
         (p->selection == GPDF_SEL_KNN && (p->knn_q < 1 || p->knn_q > 16)) ||
         (p->combine != GPDF_COMB_SMOOTHMIN && p->combine != GPDF_COMB_HARDMIN) ||
         (p->grad_mode != GPDF_GRAD_WEIGHTED && p->grad_mode != GPDF_GRAD_PAPER_MEAN) ||
-        (p->precision < GPDF_PREC_FP32 || p->precision > GPDF_PREC_FP64) || p->max_points < 1 ||
+        (p->precision < GPDF_PREC_FP32 || p->precision > GPDF_PREC_FP64) ||
+        (p->timing != 0 && p->timing != 1) || p->max_points < 1 ||
         p->max_points > (int64_t(1) << 30) || p->max_clusters < 1 || p->max_cluster_points < 1 ||
         p->max_cluster_points > 1024 || p->max_factor_elems < 1 || p->max_queries < 1 ||
         p->max_queries > (int64_t(1) << 30) || p->global_capacity < 1 ||
@@ -158,6 +162,10 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
         e = hipHostMalloc((void **)&c->h_stat, sizeof(unsigned long long) * ST_COUNT, 0);
         ok = e == hipSuccess;
     }
+    for (int i = 0; ok && p->timing && i < 16; ++i) {
+        e = hipEventCreate(&c->ev[i]);
+        ok = e == hipSuccess;
+    }
     if (!ok) {
         release(c);
         delete c;
@@ -186,7 +194,10 @@ extern "C" gpdf_status gpdf_train_local_gps(gpdf_ctx *c, const float *d_xyz, int
     if (!c) return GPDF_E_INVALID_ARG;
     if (n < 0 || (n > 0 && !d_xyz)) return fail(c, GPDF_E_INVALID_ARG, "train: bad arguments");
     try {
-        return train(c, d_xyz, n);
+        stage_begin(c, GPDF_MS_TRAIN);
+        gpdf_status s = train(c, d_xyz, n);
+        stage_end(c, GPDF_MS_TRAIN);
+        return s;
     } catch (...) {
         return fail(c, GPDF_E_OOM, "train: host allocation failed");
     }
@@ -212,7 +223,9 @@ extern "C" gpdf_status gpdf_fuse_frame(gpdf_ctx *c, const float *d_xyz, int64_t 
         return fail(c, GPDF_E_INVALID_ARG, "fuse: origin required");
     try {
         if (d_xyz) {
+            stage_begin(c, GPDF_MS_TRAIN);
             gpdf_status s = train(c, d_xyz, n);
+            stage_end(c, GPDF_MS_TRAIN);
             if (s != GPDF_OK) return s;
         }
         return fuse(c, h_origin);
@@ -224,7 +237,10 @@ extern "C" gpdf_status gpdf_fuse_frame(gpdf_ctx *c, const float *d_xyz, int64_t 
 extern "C" gpdf_status gpdf_query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *d_dist,
                                          float *d_grad, uint8_t *d_valid) {
     if (!c) return GPDF_E_INVALID_ARG;
-    return query_global(c, d_q, m, d_dist, d_grad, d_valid);
+    stage_begin(c, GPDF_MS_GLOBAL);
+    gpdf_status s = query_global(c, d_q, m, d_dist, d_grad, d_valid);
+    stage_end(c, GPDF_MS_GLOBAL);
+    return s;
 }
 
 extern "C" gpdf_status gpdf_get_stats(gpdf_ctx *c, gpdf_stats *out) {
@@ -248,12 +264,21 @@ extern "C" gpdf_status gpdf_get_stats(gpdf_ctx *c, gpdf_stats *out) {
     out->fuse_skipped = int64_t(h[ST_FUSE_SKIPPED]);
     out->global_voxels = int64_t(h[ST_GLOBAL_COUNT]);
     out->gated = int64_t(h[ST_GATED]);
+    out->eval_pairs = int64_t(h[ST_PAIRS]);
+    out->eval_points = int64_t(h[ST_POINTS]);
+    out->eval_tri = int64_t(h[ST_TRI]);
     uint32_t bits = 0;
     if (h[ST_HASH_FULL]) bits |= GPDF_STATUS_HASH_FULL;
     if (h[ST_GLOBAL_FULL]) bits |= GPDF_STATUS_GLOBAL_FULL;
     if (h[ST_SKIPPED_POINTS] || h[ST_NONFINITE_Q]) bits |= GPDF_STATUS_NONFINITE;
     if (h[ST_NONPD]) bits |= GPDF_STATUS_NONPD;
     out->status_bits = bits;
+    for (int k = 0; k < 8; ++k) {
+        float ms = -1.f;
+        if (c->ev_ok[k] && hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) != hipSuccess)
+            ms = -1.f;
+        out->ms[k] = ms;
+    }
     // the status bits and training counters are read once; per-call counters
     // are reset by the calls themselves
     fill_u64(c->d_stat + ST_HASH_FULL, 0ull, 1, c->stream);

@@ -47,11 +47,9 @@ __global__ void k_test_compact(const unsigned long long *__restrict__ keys, int6
                                uint64_t *__restrict__ out, int64_t out_cap, double hf,
                                float *__restrict__ xyz, unsigned long long *__restrict__ stat) {
     const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= cap) return;
-    const unsigned long long k = keys[s];
-    if (k == kNoKey) return;
-    const unsigned long long id = atomicAdd(&stat[ST_TESTPTS], 1ull);
-    if (int64_t(id) >= out_cap) return;
+    const unsigned long long k = s < cap ? keys[s] : kNoKey;
+    const unsigned long long id = wave_count(&stat[ST_TESTPTS], k != kNoKey);
+    if (k == kNoKey || int64_t(id) >= out_cap) return;
     out[id] = k;
     int64_t c[3];
     unpack_key(k, c);
@@ -70,22 +68,21 @@ __global__ void k_fuse(const uint64_t *__restrict__ keys, const unsigned long lo
                        unsigned long long *__restrict__ stat) {
     const int64_t n = int64_t(*nptr);
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float di = d[i], vi = v[i];
-    if (!ok[i] || !isfinite(di) || !isfinite(vi) || !(vi > 0.f)) {
-        atomicAdd(&stat[ST_FUSE_SKIPPED], 1ull);
-        return;
-    }
-    bool ins;
-    const int64_t s = hash_insert(g, keys[i], &ins);
-    if (s < 0) {
-        atomicAdd(&stat[ST_GLOBAL_FULL], 1ull);
-        return;
-    }
+    if (int64_t(blockIdx.x) * blockDim.x >= n) return;  // whole block past the end
+    const bool in = i < n;
+    const float di = in ? d[i] : 0.f, vi = in ? v[i] : 0.f;
+    const bool use = in && ok[i] && isfinite(di) && isfinite(vi) && vi > 0.f;
+    wave_count(&stat[ST_FUSE_SKIPPED], in && !use);
+    bool ins = false;
+    int64_t s = -1;
+    if (use) s = hash_insert(g, keys[i], &ins);
+    wave_count(&stat[ST_GLOBAL_FULL], use && s < 0);
+    wave_count(&stat[ST_GLOBAL_COUNT], s >= 0 && ins);
+    wave_count(&stat[ST_FUSED], s >= 0);
+    if (s < 0) return;
     if (ins) {
         gD[s] = di;
         gV[s] = vi;
-        atomicAdd(&stat[ST_GLOBAL_COUNT], 1ull);
     } else {
         const float Vp = gV[s], Dp = gD[s];
         const float den = Vp + vi;
@@ -93,7 +90,6 @@ __global__ void k_fuse(const uint64_t *__restrict__ keys, const unsigned long lo
         gV[s] = (Vp * vi) / den;
     }
     gstamp[s] = frame;
-    atomicAdd(&stat[ST_FUSED], 1ull);
 }
 
 // trilinear interpolation of D over the eight voxel centres around x
@@ -154,17 +150,15 @@ __global__ void k_global_load(const uint64_t *__restrict__ k, const float *__res
                               HashView g, float *__restrict__ gD, float *__restrict__ gV,
                               uint32_t *__restrict__ gs, unsigned long long *__restrict__ stat) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    bool ins;
-    const int64_t s = hash_insert(g, k[i], &ins);
-    if (s < 0) {
-        atomicAdd(&stat[ST_GLOBAL_FULL], 1ull);
-        return;
-    }
+    bool ins = false;
+    int64_t s = -1;
+    if (i < n) s = hash_insert(g, k[i], &ins);
+    wave_count(&stat[ST_GLOBAL_FULL], i < n && s < 0);
+    wave_count(&stat[ST_GLOBAL_COUNT], s >= 0 && ins);
+    if (s < 0) return;
     gD[s] = D[i];
     gV[s] = V[i];
     gs[s] = st[i];
-    if (ins) atomicAdd(&stat[ST_GLOBAL_COUNT], 1ull);
 }
 
 // brute-force nearest distance, FP32 differences, exact minimum
@@ -218,6 +212,7 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin) {
                             s)) != hipSuccess)
         return hip_fail(c, e, "fuse: upload offsets");
     const int64_t tcap = int64_t(c->tset_mask) + 1;
+    stage_begin(c, GPDF_MS_TESTPTS);
     fill_u64(c->d_tset, (unsigned long long)kNoKey, tcap, s);
     HashView set{c->d_tset, c->tset_mask};
     const int64_t work = M.npoints * int64_t(offs.size());
@@ -225,6 +220,7 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin) {
                        c->d_offs, int(offs.size()), set, c->d_stat);
     hipLaunchKernelGGL(k_test_compact, dim3(blocks_for(tcap)), dim3(kT), 0, s, c->d_tset, tcap,
                        c->d_tkeys, c->p.max_queries, hf, c->d_tpts, c->d_stat);
+    stage_end(c, GPDF_MS_TESTPTS);
     unsigned long long nt = 0;
     if ((e = hipMemcpyAsync(&nt, c->d_stat + ST_TESTPTS, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
@@ -235,9 +231,11 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin) {
                            c->d_tmp_valid, nullptr, 0);
     if (st != GPDF_OK) return st;
     HashView g{c->d_gkey, c->gmask};
+    stage_begin(c, GPDF_MS_FUSE);
     hipLaunchKernelGGL(k_fuse, dim3(blocks_for(int64_t(nt))), dim3(kT), 0, s, c->d_tkeys,
                        c->d_stat + ST_TESTPTS, c->d_tmp_dist, c->d_tmp_var, c->d_tmp_valid, g, c->d_gD,
                        c->d_gV, c->d_gstamp, c->frame, c->d_stat);
+    stage_end(c, GPDF_MS_FUSE);
     c->frame++;
     return (e = hipGetLastError()) == hipSuccess ? GPDF_OK : hip_fail(c, e, "fuse launch");
 }

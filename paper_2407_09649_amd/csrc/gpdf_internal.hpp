@@ -82,6 +82,44 @@ __device__ inline int64_t hash_find(const unsigned long long *__restrict__ keys,
 }
 
 // ---------------------------------------------------------------------------
+// wavefront-aggregated atomics: one atomic per wavefront (or per distinct
+// address in the wavefront) instead of one per lane
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t lanes_below() {
+    const int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// adds pred ? 1 : 0 per lane to *ctr; returns this lane's slot (valid when pred)
+__device__ inline unsigned long long wave_count(unsigned long long *ctr, bool pred) {
+    const uint64_t mb = __ballot(pred);
+    if (!mb) return 0;
+    const int leader = __ffsll((long long)mb) - 1;
+    unsigned long long base = 0;
+    if ((threadIdx.x & 63) == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(mb));
+    base = __shfl(base, leader, 64);
+    return base + __popcll(mb & lanes_below());
+}
+
+// per-lane increment of cnt[slot] returning the lane's rank, aggregated over
+// the lanes of the wavefront that share a slot (slot < 0: no increment)
+__device__ inline uint32_t wave_rank(uint32_t *cnt, int64_t slot) {
+    uint32_t rank = 0;
+    uint64_t todo = __ballot(slot >= 0);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int64_t s0 = __shfl(slot, leader, 64);
+        const uint64_t grp = __ballot(slot == s0) & todo;
+        uint32_t base = 0;
+        if ((threadIdx.x & 63) == leader) base = atomicAdd(&cnt[s0], uint32_t(__popcll(grp)));
+        base = __shfl(base, leader, 64);
+        if (slot == s0) rank = base + uint32_t(__popcll(grp & lanes_below()));
+        todo &= ~grp;
+    }
+    return rank;
+}
+
+// ---------------------------------------------------------------------------
 // device status block (uint64 counters)
 // ---------------------------------------------------------------------------
 enum Stat : int {
@@ -99,6 +137,9 @@ enum Stat : int {
     ST_CHUNKS,       // query chunks of the last query call
     ST_TESTPTS,      // unique test voxels of the last frame
     ST_GATED,
+    ST_PAIRS,        // (query, cluster) pairs of the last evaluation pass
+    ST_POINTS,       // kernel evaluations (sum of n over pairs)
+    ST_TRI,          // variance multiply-adds (sum of n (n + 1) / 2 over pairs)
     ST_COUNT
 };
 
@@ -220,6 +261,10 @@ struct gpdf_ctx {
     bool mlp_ready = false;
     int64_t adam_t = 0;
 
+    // ---- stage timers (GPDF_MS_*) -------------------------------------------
+    hipEvent_t ev[16] = {};
+    bool ev_ok[8] = {};
+
     // ---- counters ----------------------------------------------------------
     unsigned long long *d_stat = nullptr;          // [ST_COUNT]
     unsigned long long *h_stat = nullptr;          // pinned mirror
@@ -227,6 +272,16 @@ struct gpdf_ctx {
 };
 
 namespace gpdf {
+// stage timers: HIP events recorded on the context stream when p.timing is set
+inline void stage_begin(gpdf_ctx *c, int k) {
+    if (c->p.timing) (void)hipEventRecord(c->ev[2 * k], c->stream);
+}
+inline void stage_end(gpdf_ctx *c, int k) {
+    if (c->p.timing) {
+        (void)hipEventRecord(c->ev[2 * k + 1], c->stream);
+        c->ev_ok[k] = true;
+    }
+}
 // error helpers
 gpdf_status fail(gpdf_ctx *c, gpdf_status s, const std::string &msg);
 gpdf_status hip_fail(gpdf_ctx *c, hipError_t e, const char *what);

@@ -95,25 +95,26 @@ __global__ void k_qcells(const float *__restrict__ q, int64_t m, int voxel_mode,
                          HashView qh, uint32_t *__restrict__ cnt, int32_t *__restrict__ qslot,
                          uint32_t *__restrict__ qrank, float *dist, float *grad, float *var,
                          uint8_t *valid, float *aux, unsigned long long *__restrict__ stat) {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (int64_t(blockIdx.x) * blockDim.x >= m) return;  // whole block past the end
     int64_t c[3];
-    if (!query_cell(q + 3 * i, voxel_mode, hv, hc, c)) {
-        qslot[i] = -1;
-        write_invalid(uint32_t(i), dist, grad, var, valid, aux);
-        atomicAdd(&stat[ST_NONFINITE_Q], 1ull);
-        return;
-    }
+    const bool in = i < m;
+    const bool okc = in && query_cell(q + 3 * i, voxel_mode, hv, hc, c);
+    int64_t s = -1;
     bool ins;
-    int64_t s = hash_insert(qh, pack_key(c[0], c[1], c[2]), &ins);
+    if (okc) s = hash_insert(qh, pack_key(c[0], c[1], c[2]), &ins);
+    wave_count(&stat[ST_NONFINITE_Q], in && !okc);
+    wave_count(&stat[ST_HASH_FULL], okc && s < 0);
+    // queries of one wavefront mostly share a cell: one atomic per cell
+    const uint32_t rank = wave_rank(cnt, s);
+    if (!in) return;
     if (s < 0) {
         qslot[i] = -1;
         write_invalid(uint32_t(i), dist, grad, var, valid, aux);
-        atomicAdd(&stat[ST_HASH_FULL], 1ull);
         return;
     }
     qslot[i] = int32_t(s);
-    qrank[i] = atomicAdd(&cnt[s], 1u);
+    qrank[i] = rank;
 }
 
 __global__ void k_cells_compact(const unsigned long long *__restrict__ keys,
@@ -121,11 +122,10 @@ __global__ void k_cells_compact(const unsigned long long *__restrict__ keys,
                                 int32_t *__restrict__ cell_of_slot, uint64_t *__restrict__ cell_key,
                                 uint32_t *__restrict__ cell_cnt, uint32_t *__restrict__ cell_chunks,
                                 unsigned long long *__restrict__ stat) {
-    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= cap) return;
-    const unsigned long long k = keys[s];
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const unsigned long long k = s < cap ? keys[s] : kNoKey;
+    const uint32_t id = uint32_t(wave_count(&stat[ST_CELLS], k != kNoKey));
     if (k == kNoKey) return;
-    const uint32_t id = uint32_t(atomicAdd(&stat[ST_CELLS], 1ull));
     cell_of_slot[s] = int32_t(id);
     cell_key[id] = k;
     const uint32_t n = cnt[s];
@@ -185,8 +185,9 @@ __global__ void k_refine_count(const uint2 *__restrict__ rec, const unsigned lon
                                int64_t cap, uint32_t *__restrict__ rcnt, uint32_t *__restrict__ rrank) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t n = min(int64_t(*nrec), cap);
-    if (i >= n) return;
-    rrank[i] = atomicAdd(&rcnt[rec[i].x], 1u);
+    if (int64_t(blockIdx.x) * blockDim.x >= n) return;
+    const uint32_t r = wave_rank(rcnt, i < n ? int64_t(rec[i].x) : int64_t(-1));
+    if (i < n) rrank[i] = r;
 }
 
 __global__ void k_refine_chunks(int64_t ncells, const uint32_t *__restrict__ rcnt,
@@ -618,11 +619,21 @@ __global__ __launch_bounds__(kQT) void k_query_cells(const float *__restrict__ q
     const int nsel = int(uniform(uint32_t(L[0])));
     Acc<T> A;
     acc_init(A);
+    uint32_t sum_n = 0, sum_tri = 0;
     for (int s = 0; s < nsel; ++s) {
         const int32_t cid = int32_t(uniform(uint32_t(L[1 + s])));
         eval_cluster<T, KERN>(cid, Mo.pts, Mo.alpha64, Mo.coff, Mo.woff, Mo.W32, Mo.W64, Q, C, A);
+        const uint32_t n = uint32_t(Mo.coff[cid + 1] - Mo.coff[cid]);
+        sum_n += n;
+        sum_tri += n * (n + 1) / 2;
     }
     finish_query<T>(A, qi, cell, active, Q, Mo.pts, C, O);
+    // algorithmic work of this wavefront (active lanes), one atomic each
+    if (std::is_same<T, float>::value && lane == 0 && nsel > 0) {
+        atomicAdd(&O.stat[ST_PAIRS], (unsigned long long)nsel * cnt);
+        atomicAdd(&O.stat[ST_POINTS], (unsigned long long)sum_n * cnt);
+        atomicAdd(&O.stat[ST_TRI], (unsigned long long)sum_tri * cnt);
+    }
 }
 
 // squared FP64 distance from x to the centre of cell key k, no contraction,
@@ -784,6 +795,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     fill_u64(c->d_stat + ST_VALID_Q, 0ull, 1, s);
     fill_u64(c->d_stat + ST_REFINE, 0ull, 1, s);
     fill_u64(c->d_stat + ST_CELLS, 0ull, 1, s);
+    fill_u64(c->d_stat + ST_PAIRS, 0ull, 3, s);
     if (m == 0) return GPDF_OK;
     hipError_t e;
     if (M.nclusters == 0) {
@@ -800,6 +812,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     const ModelView Mo{c->d_pts, c->d_alpha64, c->d_coff, c->d_woff, c->d_W32, c->d_W64,
                        c->d_ckey, c->d_pd, M.nclusters, edge};
     // 1. group by cell
+    stage_begin(c, GPDF_MS_GROUP);
     const int64_t qcap = int64_t(c->qhash_mask) + 1;
     fill_u64(c->d_qhash, (unsigned long long)kNoKey, qcap, s);
     fill_u32(c->d_qhash_cnt, 0u, qcap, s);
@@ -826,17 +839,23 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
                            c->d_cell_list);
     hipLaunchKernelGGL(k_scatter_order, dim3(blocks_for(m)), dim3(kQT), 0, s, c->d_qslot, c->d_qrank, m,
                        c->d_qhash_cell, c->d_cell_off, c->d_order);
+    stage_end(c, GPDF_MS_GROUP);
     // 2. evaluation; the chunk count stays on the device (grid is an upper bound)
     const int64_t max_chunks = nc + (m + 63) / 64;
     const unsigned grid = blocks_for(max_chunks * 64);
     const Grouping G{c->d_chunk, c->d_chunk_off + nc, c->d_cell_cnt, c->d_cell_off, c->d_order};
     Outputs O{dist, grad, var, aux, valid, c->d_refine, c->d_stat};
     if (c->p.precision == GPDF_PREC_FP64) {
+        stage_begin(c, GPDF_MS_EVAL);
         launch_query_k<double>(kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O);
+        stage_end(c, GPDF_MS_EVAL);
     } else {
+        stage_begin(c, GPDF_MS_EVAL);
         launch_query_k<float>(kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O);
+        stage_end(c, GPDF_MS_EVAL);
         // 3. queries whose FP32 estimate is too large: regroup by cell
         //    (counting sort of the records) and redo them in FP64
+        stage_begin(c, GPDF_MS_REFINE);
         fill_u32(c->d_rcnt, 0u, nc, s);
         const unsigned rgrid = blocks_for(m);
         hipLaunchKernelGGL(k_refine_count, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
@@ -853,6 +872,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         Outputs O64 = O;
         O64.refine = nullptr;
         launch_query_k<double>(kern, knn, grid, s, d_q, R, c->d_cell_list, Mo, C, O64);
+        stage_end(c, GPDF_MS_REFINE);
     }
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "query launch");
     if (correct) return mlp_apply(c, dist, var, grad, aux, valid, m, dist);

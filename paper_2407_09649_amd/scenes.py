@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "SphereScene", "sphere_scene", "lidar_scene", "LidarScene", "lidar_frame",
     "lidar_band_queries", "planar_patches", "PatchScene", "sensor_path",
-    "sphere_eval_queries", "shuffle_rows",
+    "sphere_eval_queries", "shuffle_rows", "jitter_points",
 ]
 
 
@@ -240,6 +240,15 @@ def planar_patches(seed: int = 3, n_patches: int = 8192, n_lo: int = 8,
                       sizes=sizes.astype(np.int64),
                       queries=np.concatenate(qs).astype(np.float32),
                       cell=cell)
+
+
+def jitter_points(points: np.ndarray, n: int, sigma: float, seed: int) -> np.ndarray:
+    """n points drawn around randomly chosen input points with isotropic
+    N(0, sigma^2) offsets (queries of the fused field near the surface)."""
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, points.shape[0], size=n)
+    p = points[idx].astype(np.float64) + rng.normal(0.0, sigma, size=(n, 3))
+    return p.astype(np.float32)
 
 
 def shuffle_rows(a: np.ndarray, seed: int) -> np.ndarray:
