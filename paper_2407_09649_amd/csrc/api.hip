@@ -25,16 +25,11 @@ using namespace gpdf;
 
 namespace {
 
-uint32_t pow2_mask(int64_t want) {
-    uint64_t cap = 1024;
-    while (int64_t(cap) < want) cap <<= 1;
-    return uint32_t(cap - 1);
-}
 
 void release(gpdf_ctx *c) {
     void *ptrs[] = {c->d_key, c->d_key2, c->d_val, c->d_val2, c->d_flag, c->d_scan, c->d_hist,
                     c->d_part, c->d_red, c->d_pts, c->d_alpha64, c->d_ckey, c->d_coff, c->d_pd,
-                    c->d_woff, c->d_wtoff, c->d_aoff, c->d_W32, c->d_W64, c->d_Wt, c->d_A, c->d_chash,
+                    c->d_woff, c->d_aoff, c->d_W32, c->d_W64, c->d_A, c->d_chash,
                     c->d_chash_val, c->d_qhash, c->d_qhash_cnt, c->d_qhash_cell, c->d_qslot,
                     c->d_qrank, c->d_order, c->d_cell_key, c->d_cell_cnt, c->d_cell_off,
                     c->d_cell_chunks, c->d_chunk_off, c->d_cell_list, c->d_chunk, c->d_refine,
@@ -43,7 +38,7 @@ void release(gpdf_ctx *c) {
                     c->d_tmp_dist, c->d_tmp_var, c->d_tmp_grad, c->d_tmp_valid, c->d_tset,
                     c->d_tkeys, c->d_tpts, c->d_gkey, c->d_gD, c->d_gV, c->d_gstamp, c->d_offs,
                     c->d_mlp_w, c->d_mlp_m, c->d_mlp_v, c->d_mlp_g, c->d_mlp_norm, c->d_mlp_feat,
-                    c->d_mlp_perm, c->d_mlp_loss, c->d_stat};
+                    c->d_mlp_perm, c->d_mlp_loss, c->d_stat, c->d_blist, c->d_tile_cnt, c->d_tile_off};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
@@ -124,22 +119,24 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
     const int64_t nbP = (P + 4095) / 4096;
     const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(P, M), 256 * nbP) + 1;
     c->cap_w = p->max_factor_elems;
-    c->cap_a = 2 * p->max_factor_elems;
+    c->cap_a = p->max_factor_elems;
     c->chash_mask = pow2_mask(2 * C);
     c->qhash_mask = pow2_mask(2 * M);
     c->tset_mask = pow2_mask(2 * M);
     c->gmask = pow2_mask(2 * p->global_capacity);
     c->offs_cap = 1 << 16;
     const int64_t chunks = M + M / 64 + 2;
+    const int64_t ntile = compact_tiles(std::max<int64_t>(int64_t(c->qhash_mask), int64_t(c->tset_mask)) + 1);
     bool ok = dalloc(c->d_key, P + 1, e) && dalloc(c->d_key2, P + 1, e) && dalloc(c->d_val, P + 1, e) &&
               dalloc(c->d_val2, P + 1, e) && dalloc(c->d_flag, P + 1, e) &&
               dalloc(c->d_scan, scan_n, e) && dalloc(c->d_hist, 256 * nbP + 1, e) &&
               dalloc(c->d_part, scan_n / 4096 + 64, e) && dalloc(c->d_red, 8, e) &&
               dalloc(c->d_pts, P, e) && dalloc(c->d_alpha64, P, e) && dalloc(c->d_ckey, C + 1, e) &&
-              dalloc(c->d_coff, C + 1, e) && dalloc(c->d_pd, C + 1, e) && dalloc(c->d_woff, C, e) &&
-              dalloc(c->d_wtoff, C, e) && dalloc(c->d_aoff, C, e) && dalloc(c->d_W32, c->cap_w, e) &&
-              dalloc(c->d_W64, c->cap_w, e) && dalloc(c->d_Wt, c->cap_w, e) &&
+              dalloc(c->d_coff, C + 1, e) && dalloc(c->d_pd, C + 1, e) && dalloc(c->d_woff, C, e) && dalloc(c->d_blist, C, e) &&
+              dalloc(c->d_aoff, C, e) && dalloc(c->d_W32, c->cap_w, e) &&
+              dalloc(c->d_W64, c->cap_w, e) &&
               dalloc(c->d_A, c->cap_a, e) &&
+              dalloc(c->d_tile_cnt, ntile + 1, e) && dalloc(c->d_tile_off, ntile + 1, e) &&
               dalloc(c->d_chash, int64_t(c->chash_mask) + 1, e) &&
               dalloc(c->d_chash_val, int64_t(c->chash_mask) + 1, e) &&
               dalloc(c->d_qhash, int64_t(c->qhash_mask) + 1, e) &&

@@ -43,20 +43,21 @@ __global__ void k_test_insert(const float4 *__restrict__ pts, int64_t npts, doub
     if (hash_insert(set, pack_key(v[0], v[1], v[2]), &ins) < 0) atomicAdd(&stat[ST_HASH_FULL], 1ull);
 }
 
-__global__ void k_test_compact(const unsigned long long *__restrict__ keys, int64_t cap,
-                               uint64_t *__restrict__ out, int64_t out_cap, double hf,
-                               float *__restrict__ xyz, unsigned long long *__restrict__ stat) {
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const unsigned long long k = s < cap ? keys[s] : kNoKey;
-    const unsigned long long id = wave_count(&stat[ST_TESTPTS], k != kNoKey);
-    if (k == kNoKey || int64_t(id) >= out_cap) return;
-    out[id] = k;
-    int64_t c[3];
-    unpack_key(k, c);
-    // voxel centre (c + 1/2) h formed in FP64, rounded once
-    xyz[3 * id] = float((double(c[0]) + 0.5) * hf);
-    xyz[3 * id + 1] = float((double(c[1]) + 0.5) * hf);
-    xyz[3 * id + 2] = float((double(c[2]) + 0.5) * hf);
+__global__ __launch_bounds__(256) void k_test_compact(
+    const unsigned long long *__restrict__ keys, int64_t cap, const uint32_t *__restrict__ tile_off,
+    int64_t ntiles, uint64_t *__restrict__ out, int64_t out_cap, double hf, float *__restrict__ xyz,
+    unsigned long long *__restrict__ stat) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) stat[ST_TESTPTS] = tile_off[ntiles];
+    for_occupied_in_tile(keys, cap, tile_off[blockIdx.x], [&](int64_t, unsigned long long k, uint32_t id) {
+        if (int64_t(id) >= out_cap) return;
+        out[id] = k;
+        int64_t c[3];
+        unpack_key(k, c);
+        // voxel centre (c + 1/2) h formed in FP64, rounded once
+        xyz[3 * int64_t(id)] = float((double(c[0]) + 0.5) * hf);
+        xyz[3 * int64_t(id) + 1] = float((double(c[1]) + 0.5) * hf);
+        xyz[3 * int64_t(id) + 2] = float((double(c[2]) + 0.5) * hf);
+    });
 }
 
 // Eq. (7)-(8): D <- (V d + v D) / (V + v), V <- V v / (V + v); an absent voxel
@@ -218,8 +219,10 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin) {
     const int64_t work = M.npoints * int64_t(offs.size());
     hipLaunchKernelGGL(k_test_insert, dim3(blocks_for(work)), dim3(kT), 0, s, c->d_pts, M.npoints, hf,
                        c->d_offs, int(offs.size()), set, c->d_stat);
-    hipLaunchKernelGGL(k_test_compact, dim3(blocks_for(tcap)), dim3(kT), 0, s, c->d_tset, tcap,
-                       c->d_tkeys, c->p.max_queries, hf, c->d_tpts, c->d_stat);
+    count_occupied(c->d_tset, tcap, c->d_tile_cnt, c->d_tile_off, c->d_part, s);
+    const int64_t ntiles = compact_tiles(tcap);
+    hipLaunchKernelGGL(k_test_compact, dim3(unsigned(ntiles)), dim3(256), 0, s, c->d_tset, tcap,
+                       c->d_tile_off, ntiles, c->d_tkeys, c->p.max_queries, hf, c->d_tpts, c->d_stat);
     stage_end(c, GPDF_MS_TESTPTS);
     unsigned long long nt = 0;
     if ((e = hipMemcpyAsync(&nt, c->d_stat + ST_TESTPTS, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||

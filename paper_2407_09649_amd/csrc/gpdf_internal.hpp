@@ -55,14 +55,21 @@ struct HashView {
     uint32_t mask;             // capacity - 1
 };
 
-// find-or-insert; returns the slot or -1 if the probe sequence is exhausted
+// find-or-insert; returns the slot or -1 if the probe sequence is exhausted.
+// Within a launch a slot only goes from empty to a key, so a plain read that
+// already shows the key (or another key) settles the probe without an
+// atomic; only empty slots are claimed with compare-and-swap.
 __device__ inline int64_t hash_insert(HashView h, uint64_t key, bool *inserted) {
     uint64_t s = mix64(key) & h.mask;
     for (uint32_t p = 0; p <= h.mask; ++p) {
-        unsigned long long prev = atomicCAS(&h.keys[s], (unsigned long long)kNoKey,
-                                            (unsigned long long)key);
-        if (prev == kNoKey) { *inserted = true; return int64_t(s); }
-        if (prev == key) { *inserted = false; return int64_t(s); }
+        unsigned long long cur = __hip_atomic_load(&h.keys[s], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == key) { *inserted = false; return int64_t(s); }
+        if (cur == kNoKey) {
+            cur = atomicCAS(&h.keys[s], (unsigned long long)kNoKey, (unsigned long long)key);
+            if (cur == kNoKey) { *inserted = true; return int64_t(s); }
+            if (cur == key) { *inserted = false; return int64_t(s); }
+        }
         s = (s + 1) & h.mask;
     }
     *inserted = false;
@@ -117,6 +124,48 @@ __device__ inline uint32_t wave_rank(uint32_t *cnt, int64_t slot) {
         todo &= ~grp;
     }
     return rank;
+}
+
+// ---------------------------------------------------------------------------
+// slot-ordered compaction of an open-addressing table: a block of 256 threads
+// owns a tile of kCompactTile consecutive slots; count_occupied() gives each
+// tile's first output index, for_occupied_in_tile() numbers the occupied
+// slots of the calling block's tile in slot order (deterministic output, one
+// pass over the keys each, no global atomics)
+// ---------------------------------------------------------------------------
+constexpr int kCompactItems = 16;
+constexpr int kCompactTile = 256 * kCompactItems;
+
+// mask of the smallest power-of-two table (at least 1024 slots) holding want
+inline uint32_t pow2_mask(int64_t want) {
+    uint64_t cap = 1024;
+    while (int64_t(cap) < want) cap <<= 1;
+    return uint32_t(cap - 1);
+}
+
+inline int64_t compact_tiles(int64_t cap) { return (cap + kCompactTile - 1) / kCompactTile; }
+
+template <class Body>
+__device__ __forceinline__ void for_occupied_in_tile(const unsigned long long *__restrict__ keys,
+                                                     int64_t cap, uint32_t base, Body body) {
+    __shared__ uint32_t wsum[4];
+    const int w = threadIdx.x >> 6;
+    const int64_t t0 = int64_t(blockIdx.x) * kCompactTile;
+    for (int r = 0; r < kCompactItems; ++r) {
+        const int64_t s = t0 + r * 256 + threadIdx.x;
+        const unsigned long long k = s < cap ? keys[s] : kNoKey;
+        const uint64_t b = __ballot(k != kNoKey);
+        if ((threadIdx.x & 63) == 0) wsum[w] = uint32_t(__popcll(b));
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int i = 0; i < 4; ++i) {
+            before += i < w ? wsum[i] : 0u;
+            tot += wsum[i];
+        }
+        if (k != kNoKey) body(s, k, base + before + uint32_t(__popcll(b & lanes_below())));
+        __syncthreads();
+        base += tot;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -202,13 +251,15 @@ struct gpdf_ctx {
     int32_t *d_coff = nullptr;                     // CSR offsets  [max_clusters + 1]
     uint8_t *d_pd = nullptr;                       // positive definite
     int64_t *d_woff = nullptr;                     // factor offsets, query layout
-    int64_t *d_wtoff = nullptr, *d_aoff = nullptr; // workspace offsets
+    int64_t *d_aoff = nullptr;                     // workspace offsets
     float *d_W32 = nullptr;                        // L^{-1} in FP32, query layout
     double *d_W64 = nullptr;                       // L^{-1} in FP64, query layout
-    double *d_Wt = nullptr;                        // FP64 workspace: L^{-1} by packed columns
-    double *d_A = nullptr;                         // FP64 workspace (K, then L)
+    uint32_t *d_tile_cnt = nullptr, *d_tile_off = nullptr;  // table compaction
+    double *d_A = nullptr;                         // FP64 workspace: packed A, L, then L^{-1} (n > 192)
     int64_t cap_w = 0, cap_a = 0;
-    std::vector<int64_t> h_o32, h_o64, h_oa;       // factor offsets (host)
+    std::vector<int64_t> h_o32, h_oa;       // factor offsets (host)
+    std::vector<int32_t> h_blist;                  // clusters ordered by size bucket
+    int32_t *d_blist = nullptr;
     unsigned long long *d_chash = nullptr;         // cluster hash keys
     int32_t *d_chash_val = nullptr;
     uint32_t chash_mask = 0;
@@ -292,6 +343,10 @@ void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *
 void radix_sort_pairs(uint64_t *&keys, uint64_t *&keys_alt, uint32_t *&vals, uint32_t *&vals_alt,
                       int64_t n, uint64_t varying_bits, uint32_t *hist, uint32_t *partials,
                       hipStream_t s);
+// occupied slots (key != kNoKey) per tile of kCompactTile slots, scanned:
+// tile_off[t] = first output index of tile t, tile_off[ntiles] = total
+void count_occupied(const unsigned long long *keys, int64_t cap, uint32_t *tile_cnt,
+                    uint32_t *tile_off, uint32_t *partials, hipStream_t s);
 void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 

@@ -117,20 +117,19 @@ __global__ void k_qcells(const float *__restrict__ q, int64_t m, int voxel_mode,
     qrank[i] = rank;
 }
 
-__global__ void k_cells_compact(const unsigned long long *__restrict__ keys,
-                                const uint32_t *__restrict__ cnt, int64_t cap,
-                                int32_t *__restrict__ cell_of_slot, uint64_t *__restrict__ cell_key,
-                                uint32_t *__restrict__ cell_cnt, uint32_t *__restrict__ cell_chunks,
-                                unsigned long long *__restrict__ stat) {
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const unsigned long long k = s < cap ? keys[s] : kNoKey;
-    const uint32_t id = uint32_t(wave_count(&stat[ST_CELLS], k != kNoKey));
-    if (k == kNoKey) return;
-    cell_of_slot[s] = int32_t(id);
-    cell_key[id] = k;
-    const uint32_t n = cnt[s];
-    cell_cnt[id] = n;
-    cell_chunks[id] = (n + 63) / 64;
+__global__ __launch_bounds__(256) void k_cells_compact(
+    const unsigned long long *__restrict__ keys, const uint32_t *__restrict__ cnt, int64_t cap,
+    const uint32_t *__restrict__ tile_off, int64_t ntiles, int32_t *__restrict__ cell_of_slot,
+    uint64_t *__restrict__ cell_key, uint32_t *__restrict__ cell_cnt,
+    uint32_t *__restrict__ cell_chunks, unsigned long long *__restrict__ stat) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) stat[ST_CELLS] = tile_off[ntiles];
+    for_occupied_in_tile(keys, cap, tile_off[blockIdx.x], [&](int64_t s, unsigned long long k, uint32_t id) {
+        cell_of_slot[s] = int32_t(id);
+        cell_key[id] = k;
+        const uint32_t n = cnt[s];
+        cell_cnt[id] = n;
+        cell_chunks[id] = (n + 63) / 64;
+    });
 }
 
 __global__ void k_cell_lists(int64_t ncells, const uint64_t *__restrict__ cell_key,
@@ -813,16 +812,20 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
                        c->d_ckey, c->d_pd, M.nclusters, edge};
     // 1. group by cell
     stage_begin(c, GPDF_MS_GROUP);
-    const int64_t qcap = int64_t(c->qhash_mask) + 1;
+    // at most m distinct cells: a table of 2m..4m slots, within the allocation
+    const uint32_t qmask = std::min(c->qhash_mask, pow2_mask(2 * m));
+    const int64_t qcap = int64_t(qmask) + 1;
     fill_u64(c->d_qhash, (unsigned long long)kNoKey, qcap, s);
     fill_u32(c->d_qhash_cnt, 0u, qcap, s);
-    HashView qh{c->d_qhash, c->qhash_mask};
+    HashView qh{c->d_qhash, qmask};
     hipLaunchKernelGGL(k_qcells, dim3(blocks_for(m)), dim3(kQT), 0, s, d_q, m, vox ? 1 : 0,
                        c->p.voxel_size, c->p.cluster_size, qh, c->d_qhash_cnt, c->d_qslot, c->d_qrank,
                        dist, grad, var, valid, aux, c->d_stat);
-    hipLaunchKernelGGL(k_cells_compact, dim3(blocks_for(qcap)), dim3(kQT), 0, s, c->d_qhash,
-                       c->d_qhash_cnt, qcap, c->d_qhash_cell, c->d_cell_key, c->d_cell_cnt,
-                       c->d_cell_chunks, c->d_stat);
+    count_occupied(c->d_qhash, qcap, c->d_tile_cnt, c->d_tile_off, c->d_part, s);
+    const int64_t ntiles = compact_tiles(qcap);
+    hipLaunchKernelGGL(k_cells_compact, dim3(unsigned(ntiles)), dim3(256), 0, s, c->d_qhash,
+                       c->d_qhash_cnt, qcap, c->d_tile_off, ntiles, c->d_qhash_cell, c->d_cell_key,
+                       c->d_cell_cnt, c->d_cell_chunks, c->d_stat);
     unsigned long long ncells = 0;
     if ((e = hipMemcpyAsync(&ncells, c->d_stat + ST_CELLS, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)

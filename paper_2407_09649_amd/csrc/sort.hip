@@ -217,6 +217,27 @@ void radix_sort_pairs(uint64_t *&keys, uint64_t *&keys_alt, uint32_t *&vals, uin
     }
 }
 
+__global__ __launch_bounds__(256) void k_count_occupied(const unsigned long long *__restrict__ keys,
+                                                        int64_t cap, uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t wsum[4];
+    const int64_t t0 = int64_t(blockIdx.x) * kCompactTile;
+    uint32_t n = 0;
+    for (int r = 0; r < kCompactItems; ++r) {
+        const int64_t s = t0 + r * 256 + threadIdx.x;
+        n += uint32_t(__popcll(__ballot(s < cap && keys[s] != kNoKey)));
+    }
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+void count_occupied(const unsigned long long *keys, int64_t cap, uint32_t *tile_cnt,
+                    uint32_t *tile_off, uint32_t *partials, hipStream_t s) {
+    const int64_t nt = compact_tiles(cap);
+    hipLaunchKernelGGL(k_count_occupied, dim3(unsigned(nt)), dim3(256), 0, s, keys, cap, tile_cnt);
+    exclusive_scan_u32(tile_cnt, tile_off, nt, partials, s);
+}
+
 void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);

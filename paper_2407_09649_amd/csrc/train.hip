@@ -150,39 +150,41 @@ __device__ inline double kernel64(int kernel, double r, double l) {
     return exp(-r * r / (2.0 * l * l));
 }
 
-constexpr int kMaxLdsN = 64;
 constexpr int kMaxClusterN = 1024;
+constexpr int kBlockLdsN = 192;                          // packed triangle in LDS up to here
+constexpr int kBlockLdsElems = kBlockLdsN * (kBlockLdsN + 1) / 2;
 
+__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// one workgroup per cluster, n > 64: the lower triangle of A = K + s^2 I
+// packed by rows (in LDS up to n = 192, else in the FP64 workspace),
+// right-looking Cholesky, then the inverse W = L^{-1} in place, column by
+// column from the right: with L = [l 0; c L2], W = [1/l 0; -W2 c / l  W2]
 __global__ __launch_bounds__(kT) void k_train_clusters(
-    float4 *__restrict__ pts, const int32_t *__restrict__ coff, const int64_t *__restrict__ aoff,
-    const int64_t *__restrict__ woff, const int64_t *__restrict__ wtoff, double *__restrict__ Aall,
-    double *__restrict__ Wtall, double *__restrict__ W64all, float *__restrict__ W32all,
-    double *__restrict__ alpha64,
+    const int32_t *__restrict__ list, float4 *__restrict__ pts, const int32_t *__restrict__ coff,
+    const int64_t *__restrict__ aoff, const int64_t *__restrict__ woff, double *__restrict__ Aall,
+    double *__restrict__ W64all, float *__restrict__ W32all, double *__restrict__ alpha64,
     uint8_t *__restrict__ pd, int kernel, double l, double s2, unsigned long long *__restrict__ stat) {
-    __shared__ float sx[kMaxClusterN], sy[kMaxClusterN], sz[kMaxClusterN];
-    __shared__ double sA[kMaxLdsN * kMaxLdsN];
-    __shared__ double sy1[kMaxClusterN];
+    __shared__ double sA[kBlockLdsElems];
+    __shared__ double xs[kMaxClusterN];
     __shared__ int s_ok;
-    const int c = blockIdx.x;
+    const int c = list[blockIdx.x];
     const int base = coff[c];
     const int n = coff[c + 1] - base;
     const int tid = threadIdx.x;
-    double *A = (n <= kMaxLdsN) ? sA : Aall + aoff[c];
-    double *W = Wtall + wtoff[c];
-    for (int i = tid; i < n; i += kT) {
-        float4 p = pts[base + i];
-        sx[i] = p.x; sy[i] = p.y; sz[i] = p.z;
-    }
-    __syncthreads();
-    // A = K + s^2 I
-    for (int64_t idx = tid; idx < int64_t(n) * n; idx += kT) {
-        const int i = int(idx / n), j = int(idx - int64_t(i) * n);
-        const double dx = double(sx[i]) - double(sx[j]);
-        const double dy = double(sy[i]) - double(sy[j]);
-        const double dz = double(sz[i]) - double(sz[j]);
-        double v = kernel64(kernel, sqrt(dx * dx + dy * dy + dz * dz), l);
-        if (i == j) v += s2;
-        A[idx] = v;
+    double *A = (n <= kBlockLdsN) ? sA : Aall + aoff[c];
+    const int tot = n * (n + 1) / 2;
+    // A = K + s^2 I (lower triangle)
+    for (int i = tid >> 1; i < n; i += kT / 2) {
+        const float4 pi = pts[base + i];
+        for (int j = tid & 1; j <= i; j += 2) {
+            const float4 pj = pts[base + j];
+            const double dx = double(pi.x) - double(pj.x), dy = double(pi.y) - double(pj.y),
+                         dz = double(pi.z) - double(pj.z);
+            double v = kernel64(kernel, sqrt(dx * dx + dy * dy + dz * dz), l);
+            if (i == j) v += s2;
+            A[tri(i, j)] = v;
+        }
     }
     // Cholesky, right-looking; a pivot at or below 1e-10 of the original
     // diagonal 1 + s^2 marks the cluster non positive definite
@@ -191,18 +193,20 @@ __global__ __launch_bounds__(kT) void k_train_clusters(
     for (int k = 0; k < n; ++k) {
         __syncthreads();
         if (tid == 0) {
-            const double d = A[int64_t(k) * n + k];
+            const double d = A[tri(k, k)];
             if (!(d > thr)) s_ok = 0;
-            else A[int64_t(k) * n + k] = sqrt(d);
+            else A[tri(k, k)] = sqrt(d);
         }
         __syncthreads();
         if (!s_ok) break;
-        const double lkk = A[int64_t(k) * n + k];
-        for (int i = k + 1 + tid; i < n; i += kT) A[int64_t(i) * n + k] /= lkk;
+        const double lkk = A[tri(k, k)];
+        for (int i = k + 1 + tid; i < n; i += kT) A[tri(i, k)] /= lkk;
         __syncthreads();
-        for (int j = k + 1 + tid; j < n; j += kT) {
-            const double ljk = A[int64_t(j) * n + k];
-            for (int i = j; i < n; ++i) A[int64_t(i) * n + j] -= A[int64_t(i) * n + k] * ljk;
+        // trailing update, two threads per row (alternate columns)
+        for (int i = k + 1 + (tid >> 1); i < n; i += kT / 2) {
+            double *Ai = A + tri(i, 0);
+            const double lik = Ai[k];
+            for (int j = k + 1 + (tid & 1); j <= i; j += 2) Ai[j] -= lik * A[tri(j, k)];
         }
     }
     __syncthreads();
@@ -217,65 +221,274 @@ __global__ __launch_bounds__(kT) void k_train_clusters(
         }
         return;
     }
-    // W = L^{-1}, one column per thread; packed column-major storage:
-    // column j holds rows j..n-1 starting at j n - j (j - 1) / 2
-    for (int j = tid; j < n; j += kT) {
-        double *Wj = W + (int64_t(j) * n - int64_t(j) * (j - 1) / 2) - j;  // Wj[i] = W(i, j)
-        Wj[j] = 1.0 / A[int64_t(j) * n + j];
-        for (int i = j + 1; i < n; ++i) {
-            const double *Li = A + int64_t(i) * n;
-            double s = 0.0;
-            for (int m = j; m < i; ++m) s += Li[m] * Wj[m];
-            Wj[i] = -s / Li[i];
+    // in-place inverse, columns right to left
+    for (int j = n - 1; j >= 0; --j) {
+        if (tid == 0) A[tri(j, j)] = 1.0 / A[tri(j, j)];
+        for (int i = j + 1 + tid; i < n; i += kT) xs[i] = A[tri(i, j)];
+        __syncthreads();
+        const double wjj = A[tri(j, j)];
+        for (int i = j + 1 + tid; i < n; i += kT) {
+            const double *Wi = A + tri(i, 0);
+            double s0 = 0.0, s1 = 0.0, s2_ = 0.0, s3 = 0.0;
+            int m = j + 1;
+            for (; m + 3 <= i; m += 4) {
+                s0 += Wi[m] * xs[m]; s1 += Wi[m + 1] * xs[m + 1];
+                s2_ += Wi[m + 2] * xs[m + 2]; s3 += Wi[m + 3] * xs[m + 3];
+            }
+            for (; m <= i; ++m) s0 += Wi[m] * xs[m];
+            A[tri(i, j)] = -wjj * ((s0 + s1) + (s2_ + s3));
         }
+        __syncthreads();
     }
-    __threadfence_block();
-    __syncthreads();
     // y = W 1 (row sums), alpha = W^T y
     for (int i = tid; i < n; i += kT) {
-        double s = 0.0;
-        for (int j = 0; j <= i; ++j) s += W[int64_t(j) * n - int64_t(j) * (j - 1) / 2 + (i - j)];
-        sy1[i] = s;
+        const double *Wi = A + tri(i, 0);
+        double sum = 0.0;
+        for (int j = 0; j <= i; ++j) sum += Wi[j];
+        xs[i] = sum;
     }
     __syncthreads();
     for (int j = tid; j < n; j += kT) {
-        const double *Wj = W + (int64_t(j) * n - int64_t(j) * (j - 1) / 2) - j;
-        double s = 0.0;
-        for (int i = j; i < n; ++i) s += Wj[i] * sy1[i];
-        alpha64[base + j] = s;
-        pts[base + j].w = float(s);
+        double a = 0.0;
+        for (int i = j; i < n; ++i) a += A[tri(i, j)] * xs[i];
+        alpha64[base + j] = a;
+        pts[base + j].w = float(a);
     }
-    // W in the query layout, FP32 and FP64: packed rows for n <= 64, 64-row
-    // panels (column-major inside, zero above the diagonal) above that
+    // W in the query layout (FP32 and FP64): packed rows for n <= 64 (the
+    // order of the packed triangle), 64-row panels above that, column-major
+    // inside and zero above the diagonal
     float *W32 = W32all + woff[c];
     double *W64 = W64all + woff[c];
     if (n <= kPanel) {
-        for (int64_t idx = tid; idx < int64_t(n) * (n + 1) / 2; idx += kT) {
-            // row i holds entries i (i + 1) / 2 .. i (i + 1) / 2 + i
-            int i = int((sqrt(8.0 * double(idx) + 1.0) - 1.0) * 0.5);
-            while (int64_t(i + 1) * (i + 2) / 2 <= idx) ++i;
-            while (int64_t(i) * (i + 1) / 2 > idx) --i;
-            const int j = int(idx - int64_t(i) * (i + 1) / 2);
-            const double w = W[int64_t(j) * n - int64_t(j) * (j - 1) / 2 + (i - j)];
-            W32[idx] = float(w);
-            W64[idx] = w;
+        for (int idx = tid; idx < tot; idx += kT) {
+            W32[idx] = float(A[idx]);
+            W64[idx] = A[idx];
         }
-    } else {
-        const int nb = (n + kPanel - 1) / kPanel;
-        for (int r = 0; r < nb; ++r) {
-            const int64_t po = w32_panel_offset(n, r);
-            const int ncol = std::min((r + 1) * kPanel, n);
-            for (int idx = tid; idx < ncol * kPanel; idx += kT) {
-                const int j = idx / kPanel, rr = idx - j * kPanel;
-                const int i = r * kPanel + rr;
-                double v = 0.0;
-                if (i < n && j <= i) v = W[int64_t(j) * n - int64_t(j) * (j - 1) / 2 + (i - j)];
-                W32[po + idx] = float(v);
-                W64[po + idx] = v;
-            }
+        if (tid == 0) pd[c] = 1;
+        return;
+    }
+    const int nb = (n + kPanel - 1) / kPanel;
+    for (int r = 0; r < nb; ++r) {
+        const int64_t po = w32_panel_offset(n, r);
+        const int ncol = min((r + 1) * kPanel, n);
+        for (int idx = tid; idx < ncol * kPanel; idx += kT) {
+            const int j = idx / kPanel, rr = idx - j * kPanel;
+            const int i = r * kPanel + rr;
+            const double v = (i < n && j <= i) ? A[tri(i, j)] : 0.0;
+            W32[po + idx] = float(v);
+            W64[po + idx] = v;
         }
     }
     if (tid == 0) pd[c] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// size buckets: n <= 8 one lane per cluster (registers), n <= 64 one
+// wavefront per cluster (LDS), larger one workgroup per cluster (above)
+// ---------------------------------------------------------------------------
+constexpr int kTinyN = 8;
+constexpr int kWaveN = 64;
+
+// store W (FP32 and FP64, packed rows), alpha and the positive-definite flag
+__device__ inline void put_w(float *W32, double *W64, int64_t off, int idx, double w) {
+    W32[off + idx] = float(w);
+    W64[off + idx] = w;
+}
+
+__global__ __launch_bounds__(64) void k_train_tiny(
+    const int32_t *__restrict__ list, int64_t cnt, float4 *__restrict__ pts,
+    const int32_t *__restrict__ coff, const int64_t *__restrict__ woff, double *__restrict__ W64all,
+    float *__restrict__ W32all, double *__restrict__ alpha64, uint8_t *__restrict__ pd, int kernel,
+    double l, double s2, unsigned long long *__restrict__ stat) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const int c = list[t];
+    const int base = coff[c];
+    const int n = coff[c + 1] - base;
+    double px[kTinyN], py[kTinyN], pz[kTinyN];
+#pragma unroll
+    for (int i = 0; i < kTinyN; ++i) {
+        float4 p = i < n ? pts[base + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        px[i] = p.x; py[i] = p.y; pz[i] = p.z;
+    }
+    // A = K + s^2 I, lower triangle packed by rows
+    double L[kTinyN * (kTinyN + 1) / 2];
+#pragma unroll
+    for (int i = 0; i < kTinyN; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            const double dx = px[i] - px[j], dy = py[i] - py[j], dz = pz[i] - pz[j];
+            double v = kernel64(kernel, sqrt(dx * dx + dy * dy + dz * dz), l);
+            if (i == j) v += s2;
+            L[i * (i + 1) / 2 + j] = v;
+        }
+    // Cholesky, left-looking (the pivot test uses the original diagonal)
+    const double thr = 1e-10 * (1.0 + s2);
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < kTinyN; ++j) {
+        if (j < n) {
+            double d = L[j * (j + 1) / 2 + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) d -= L[j * (j + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+            ok = ok && (d > thr);
+            const double ljj = sqrt(fmax(d, thr));
+            L[j * (j + 1) / 2 + j] = ljj;
+#pragma unroll
+            for (int i = j + 1; i < kTinyN; ++i) {
+                if (i < n) {
+                    double sum = L[i * (i + 1) / 2 + j];
+#pragma unroll
+                    for (int k = 0; k < j; ++k) sum -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+                    L[i * (i + 1) / 2 + j] = sum / ljj;
+                }
+            }
+        }
+    }
+    if (!ok) {
+        for (int i = 0; i < n; ++i) { alpha64[base + i] = 0.0; pts[base + i].w = 0.0f; }
+        pd[c] = 0;
+        atomicAdd(&stat[ST_NONPD], 1ull);
+        return;
+    }
+    // W = L^{-1} (packed rows), y = W 1, alpha = W^T y
+    double W[kTinyN * (kTinyN + 1) / 2];
+#pragma unroll
+    for (int i = 0; i < kTinyN; ++i) {
+        const double inv = 1.0 / L[i * (i + 1) / 2 + i];
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double sum = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int m = j; m < i; ++m) sum -= L[i * (i + 1) / 2 + m] * W[m * (m + 1) / 2 + j];
+            W[i * (i + 1) / 2 + j] = sum * inv;
+        }
+    }
+    double y[kTinyN];
+#pragma unroll
+    for (int i = 0; i < kTinyN; ++i) {
+        double sum = 0.0;
+#pragma unroll
+        for (int j = 0; j <= i; ++j) sum += (i < n) ? W[i * (i + 1) / 2 + j] : 0.0;
+        y[i] = sum;
+    }
+    const int64_t off = woff[c];
+#pragma unroll
+    for (int j = 0; j < kTinyN; ++j) {
+        if (j < n) {
+            double a = 0.0;
+#pragma unroll
+            for (int i = j; i < kTinyN; ++i) a += (i < n) ? W[i * (i + 1) / 2 + j] * y[i] : 0.0;
+            alpha64[base + j] = a;
+            pts[base + j].w = float(a);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kTinyN; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            if (i < n) put_w(W32all, W64all, off, i * (i + 1) / 2 + j, W[i * (i + 1) / 2 + j]);
+    pd[c] = 1;
+}
+
+// one wavefront per cluster, 8 < n <= 64; lane i owns row i of A in LDS
+// (row stride 65 doubles: column reads by different lanes hit different
+// banks); W = L^{-1} kept by packed columns, lane j owning column j
+__global__ __launch_bounds__(64) void k_train_wave(
+    const int32_t *__restrict__ list, float4 *__restrict__ pts, const int32_t *__restrict__ coff,
+    const int64_t *__restrict__ woff, double *__restrict__ W64all, float *__restrict__ W32all,
+    double *__restrict__ alpha64, uint8_t *__restrict__ pd, int kernel, double l, double s2,
+    unsigned long long *__restrict__ stat) {
+    constexpr int S = kWaveN + 1;
+    __shared__ float sp[3][kWaveN];
+    __shared__ double A[kWaveN * S];
+    __shared__ double Wc[kWaveN * (kWaveN + 1) / 2];
+    __shared__ double sy[kWaveN];
+    const int c = list[blockIdx.x];
+    const int base = coff[c];
+    const int n = coff[c + 1] - base;
+    const int lane = threadIdx.x;
+    if (lane < n) {
+        const float4 p = pts[base + lane];
+        sp[0][lane] = p.x; sp[1][lane] = p.y; sp[2][lane] = p.z;
+    }
+    __syncthreads();
+    if (lane < n) {
+        const double xi = sp[0][lane], yi = sp[1][lane], zi = sp[2][lane];
+        for (int j = 0; j <= lane; ++j) {
+            const double dx = xi - double(sp[0][j]), dy = yi - double(sp[1][j]), dz = zi - double(sp[2][j]);
+            double v = kernel64(kernel, sqrt(dx * dx + dy * dy + dz * dz), l);
+            if (j == lane) v += s2;
+            A[lane * S + j] = v;
+        }
+    }
+    __syncthreads();
+    // right-looking Cholesky: lane i updates its own row
+    const double thr = 1e-10 * (1.0 + s2);
+    bool ok = true;
+    for (int k = 0; k < n; ++k) {
+        int good = 1;
+        if (lane == k) {
+            const double d = A[k * S + k];
+            good = d > thr;
+            A[k * S + k] = sqrt(fmax(d, thr));
+        }
+        good = __shfl(good, k, 64);
+        if (!good) { ok = false; break; }
+        __syncthreads();
+        const double lkk = A[k * S + k];
+        if (lane > k && lane < n) A[lane * S + k] /= lkk;
+        __syncthreads();
+        if (lane > k && lane < n) {
+            const double lik = A[lane * S + k];
+            for (int j = k + 1; j <= lane; ++j) A[lane * S + j] -= lik * A[j * S + k];
+        }
+    }
+    if (!ok) {
+        if (lane < n) { alpha64[base + lane] = 0.0; pts[base + lane].w = 0.0f; }
+        if (lane == 0) { pd[c] = 0; atomicAdd(&stat[ST_NONPD], 1ull); }
+        return;
+    }
+    __syncthreads();
+    // column j of W: W(j, j) = 1 / L(j, j), W(i, j) = -sum_{m=j}^{i-1} L(i, m) W(m, j) / L(i, i)
+    if (lane < n) {
+        const int j = lane;
+        double *Wj = Wc + (j * n - j * (j - 1) / 2) - j;  // Wj[i] = W(i, j)
+        Wj[j] = 1.0 / A[j * S + j];
+        for (int i = j + 1; i < n; ++i) {
+            const double *Li = A + i * S;
+            double s0 = 0.0, s1 = 0.0;
+            int m = j;
+            for (; m + 1 < i; m += 2) { s0 += Li[m] * Wj[m]; s1 += Li[m + 1] * Wj[m + 1]; }
+            if (m < i) s0 += Li[m] * Wj[m];
+            Wj[i] = -(s0 + s1) / Li[i];
+        }
+    }
+    __syncthreads();
+    if (lane < n) {
+        double sum = 0.0;
+        for (int j = 0; j <= lane; ++j) sum += Wc[j * n - j * (j - 1) / 2 + (lane - j)];
+        sy[lane] = sum;
+    }
+    __syncthreads();
+    if (lane < n) {
+        const int j = lane;
+        const double *Wj = Wc + (j * n - j * (j - 1) / 2) - j;
+        double a = 0.0;
+        for (int i = j; i < n; ++i) a += Wj[i] * sy[i];
+        alpha64[base + j] = a;
+        pts[base + j].w = float(a);
+    }
+    const int64_t off = woff[c];
+    const int tot = n * (n + 1) / 2;
+    for (int idx = lane; idx < tot; idx += 64) {
+        int i = int((sqrt(8.0 * double(idx) + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= idx) ++i;
+        while (i * (i + 1) / 2 > idx) --i;
+        const int j = idx - i * (i + 1) / 2;
+        put_w(W32all, W64all, off, idx, Wc[j * n - j * (j - 1) / 2 + (i - j)]);
+    }
+    if (lane == 0) pd[c] = 1;
 }
 
 __global__ void k_chash_insert(const uint64_t *__restrict__ ckey, int64_t ncl, HashView h,
@@ -362,35 +575,54 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n) {
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return hip_fail(c, e, "train: read offsets");
     // kept in the context: the uploads below read them asynchronously
-    std::vector<int64_t> &o32 = c->h_o32, &o64 = c->h_o64, &oa = c->h_oa;
-    o32.assign(ncl, 0); o64.assign(ncl, 0); oa.assign(ncl, 0);
-    int64_t s32 = 0, s64 = 0, sa = 0, maxn = 0;
+    std::vector<int64_t> &o32 = c->h_o32, &oa = c->h_oa;
+    o32.assign(ncl, 0); oa.assign(ncl, 0);
+    int64_t s32 = 0, sa = 0, maxn = 0;
     M.h_n.resize(ncl);
     for (uint32_t i = 0; i < ncl; ++i) {
         const int64_t nc = off[i + 1] - off[i];
         M.h_n[i] = int32_t(nc);
         maxn = std::max(maxn, nc);
         o32[i] = s32; s32 += w32_size(nc);
-        o64[i] = s64; s64 += nc * (nc + 1) / 2;
-        oa[i] = sa; if (nc > kMaxLdsN) sa += nc * nc;
+        oa[i] = sa; if (nc > kBlockLdsN) sa += nc * (nc + 1) / 2;
     }
     if (maxn > c->p.max_cluster_points || maxn > kMaxClusterN) {
         M.trained = false;
         return fail(c, GPDF_E_CAPACITY, "train: a cluster exceeds max_cluster_points");
     }
-    if (s32 > c->cap_w || s64 > c->cap_w || sa > c->cap_a) {
+    if (s32 > c->cap_w || sa > c->cap_a) {
         M.trained = false;
         return fail(c, GPDF_E_CAPACITY, "train: factor storage exceeds max_factor_elems");
     }
     if ((e = hipMemcpyAsync(c->d_woff, o32.data(), 8 * ncl, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(c->d_wtoff, o64.data(), 8 * ncl, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(c->d_aoff, oa.data(), 8 * ncl, hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(c, e, "train: upload offsets");
-    // 5. FP64 training
+    // 5. FP64 training, bucketed by cluster size
     const double l = c->p.length_scale, s2 = c->p.noise_sigma * c->p.noise_sigma;
-    hipLaunchKernelGGL(k_train_clusters, dim3(ncl), dim3(kT), 0, s, c->d_pts, c->d_coff, c->d_aoff,
-                       c->d_woff, c->d_wtoff, c->d_A, c->d_Wt, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
-                       c->p.kernel, l, s2, c->d_stat);
+    std::vector<int32_t> &bl = c->h_blist;
+    bl.clear();
+    for (uint32_t i = 0; i < ncl; ++i) if (M.h_n[i] <= kTinyN) bl.push_back(int32_t(i));
+    const int64_t n_tiny = int64_t(bl.size());
+    for (uint32_t i = 0; i < ncl; ++i)
+        if (M.h_n[i] > kTinyN && M.h_n[i] <= kWaveN) bl.push_back(int32_t(i));
+    const int64_t n_wave = int64_t(bl.size()) - n_tiny;
+    for (uint32_t i = 0; i < ncl; ++i) if (M.h_n[i] > kWaveN) bl.push_back(int32_t(i));
+    const int64_t n_big = int64_t(bl.size()) - n_tiny - n_wave;
+    if ((e = hipMemcpyAsync(c->d_blist, bl.data(), 4 * bl.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(c, e, "train: upload buckets");
+    if (n_tiny)
+        hipLaunchKernelGGL(k_train_tiny, dim3(unsigned((n_tiny + 63) / 64)), dim3(64), 0, s, c->d_blist,
+                           n_tiny, c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64,
+                           c->d_pd, c->p.kernel, l, s2, c->d_stat);
+    if (n_wave)
+        hipLaunchKernelGGL(k_train_wave, dim3(unsigned(n_wave)), dim3(64), 0, s, c->d_blist + n_tiny,
+                           c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
+                           c->p.kernel, l, s2, c->d_stat);
+    if (n_big)
+        hipLaunchKernelGGL(k_train_clusters, dim3(unsigned(n_big)), dim3(kT), 0, s,
+                           c->d_blist + n_tiny + n_wave, c->d_pts, c->d_coff, c->d_aoff, c->d_woff,
+                           c->d_A, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l, s2,
+                           c->d_stat);
     // 6. cluster hash
     fill_u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1, s);
     HashView hv{c->d_chash, c->chash_mask};
