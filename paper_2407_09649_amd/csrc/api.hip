@@ -105,7 +105,8 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
         (p->precision < GPDF_PREC_FP32 || p->precision > GPDF_PREC_FP64) ||
         (p->timing != 0 && p->timing != 1) || p->max_points < 1 ||
         p->max_points > (int64_t(1) << 30) || p->max_clusters < 1 || p->max_cluster_points < 1 ||
-        p->max_cluster_points > 1024 || p->max_factor_elems < 1 || p->max_queries < 1 ||
+        p->max_cluster_points > 1024 || p->max_factor_elems < 1 ||
+        p->max_factor_elems > (int64_t(1) << 31) - 1 || p->max_queries < 1 ||
         p->max_queries > (int64_t(1) << 30) || p->global_capacity < 1 ||
         p->global_capacity > (int64_t(1) << 30))
         return GPDF_E_INVALID_ARG;
@@ -120,6 +121,7 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
     const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(P, M), 256 * nbP) + 1;
     c->cap_w = p->max_factor_elems;
     c->cap_a = p->max_factor_elems;
+    c->cap_cells = std::min<int64_t>(M + 1, int64_t(1) << 16);  // grown on demand
     c->chash_mask = pow2_mask(2 * C);
     c->qhash_mask = pow2_mask(2 * M);
     c->tset_mask = pow2_mask(2 * M);
@@ -145,7 +147,7 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
               dalloc(c->d_qrank, M, e) && dalloc(c->d_order, M, e) && dalloc(c->d_cell_key, M + 1, e) &&
               dalloc(c->d_cell_cnt, M + 1, e) && dalloc(c->d_cell_off, M + 1, e) &&
               dalloc(c->d_cell_chunks, M + 1, e) && dalloc(c->d_chunk_off, M + 1, e) &&
-              dalloc(c->d_cell_list, (M + 1) * 28, e) && dalloc(c->d_chunk, chunks, e) &&
+              dalloc(c->d_cell_list, c->cap_cells * kCellListStride, e) && dalloc(c->d_chunk, chunks, e) &&
               dalloc(c->d_refine, M, e) && dalloc(c->d_rcnt, M + 1, e) && dalloc(c->d_roff, M + 1, e) &&
               dalloc(c->d_rchunks, M + 1, e) && dalloc(c->d_rchunk_off, M + 1, e) &&
               dalloc(c->d_rorder, M, e) && dalloc(c->d_rrank, M, e) && dalloc(c->d_rchunk, chunks, e) && dalloc(c->d_tmp_dist, M, e) && dalloc(c->d_tmp_var, M, e) &&

@@ -133,6 +133,7 @@ __device__ inline uint32_t wave_rank(uint32_t *cnt, int64_t slot) {
 // slots of the calling block's tile in slot order (deterministic output, one
 // pass over the keys each, no global atomics)
 // ---------------------------------------------------------------------------
+constexpr int kCellListStride = 28;  // int4 entries per cell list: count + 27 descriptors
 constexpr int kCompactItems = 16;
 constexpr int kCompactTile = 256 * kCompactItems;
 
@@ -194,7 +195,7 @@ enum Stat : int {
 
 // per-cluster FP32 factor layout: packed rows for n <= 64, 64-row panels
 // (column-major inside the panel) above that
-constexpr int kPanel = 64;
+constexpr int kPanel = 32;
 __host__ __device__ inline int64_t w32_size(int64_t n) {
     if (n <= kPanel) return n * (n + 1) / 2;
     int64_t nb = (n + kPanel - 1) / kPanel, s = 0;
@@ -275,7 +276,8 @@ struct gpdf_ctx {
     uint64_t *d_cell_key = nullptr;                // per cell
     uint32_t *d_cell_cnt = nullptr, *d_cell_off = nullptr;
     uint32_t *d_cell_chunks = nullptr, *d_chunk_off = nullptr;
-    int32_t *d_cell_list = nullptr;                // [cells][28]: count, ids
+    int4 *d_cell_list = nullptr;                   // [cells][28]: count, cluster descriptors
+    int64_t cap_cells = 0;                         // cells the lists hold
     uint2 *d_chunk = nullptr;                      // (cell, start)
     uint2 *d_refine = nullptr;                     // (cell, query) records to redo in FP64
     uint32_t *d_rcnt = nullptr, *d_roff = nullptr; // refine records per cell

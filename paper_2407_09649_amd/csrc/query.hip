@@ -14,11 +14,12 @@
 // in), so that all lanes of a wavefront share one neighbour list.  One lane
 // evaluates one query; cluster points, alpha and W are wave-uniform and come
 // through scalar loads.  The kernel vector k of a pair stays in VGPRs
-// (compile-time unrolled size classes n <= 16, 32, 64); larger clusters
-// stream W in 64-row panels and recompute k.  The same kernels are
-// instantiated in FP32 (the product path) and FP64.  FP32 results carry a
-// running first-order error estimate; queries whose estimate exceeds the
-// tolerance are regrouped by cell and re-evaluated by the FP64 instance.
+// (compile-time unrolled size classes n <= 8, 16, 32); larger clusters
+// stream W in 32-row panels and recompute the kernel values left of each
+// panel's diagonal block.  The same kernels are instantiated in FP32 (the
+// product path) and FP64.  FP32 results carry a running first-order error
+// estimate; queries whose estimate exceeds the tolerance are regrouped by
+// cell and re-evaluated by the FP64 instance.
 #include "gpdf_internal.hpp"
 
 #include <algorithm>
@@ -30,9 +31,16 @@ namespace gpdf {
 
 namespace {
 
-constexpr int kQT = 256;            // threads per workgroup (4 wavefronts)
-constexpr int kWaves = kQT / 64;
-constexpr int kListStride = 28;     // count + 27 cluster ids
+constexpr int kQT = 256;            // threads per workgroup of the helper kernels
+// evaluation kernels: one wavefront per workgroup, so that a finished
+// wavefront's slot is refilled at once (waves of one workgroup end at
+// different times)
+constexpr int kEvalT = 64;
+constexpr int kWaves = kEvalT / 64;
+constexpr int kListStride = kCellListStride;
+// combination variants, fixed per launch: smooth minimum with the weighted
+// gradient, smooth minimum with the plain gradient mean, closest node
+constexpr int kModeSmooth = 0, kModeMean = 1, kModeHard = 2;
 constexpr int kMaxKnn = 16;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kEps = 5.9604645e-08f;  // 2^-24
@@ -47,6 +55,18 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// workgroup -> work item, XCD-aware: workgroups are dispatched round-robin
+// over the 8 XCDs, so the first n items are handed out as 8 contiguous
+// ranges, one per XCD, and neighbouring items share one XCD's L2.  A
+// bijection from [0, nb) onto [0, nb), nb = min(gridDim.x, n rounded up to 8);
+// workgroups at or past nb get nb (no item).
+__device__ __forceinline__ uint32_t xcd_item(uint32_t n) {
+    const uint32_t nb = min(gridDim.x, (n + 7u) & ~7u), b = blockIdx.x;
+    if (b >= nb) return nb;
+    const uint32_t q = nb / 8, r = nb % 8, x = b % 8;
+    return x * q + min(x, r) + b / 8;
+}
 
 // elementary functions per precision: raw hardware approximations in FP32,
 // the device math library in FP64
@@ -135,12 +155,13 @@ __global__ __launch_bounds__(256) void k_cells_compact(
 __global__ void k_cell_lists(int64_t ncells, const uint64_t *__restrict__ cell_key,
                              const unsigned long long *__restrict__ chash, uint32_t cmask,
                              const int32_t *__restrict__ chash_val, const uint8_t *__restrict__ pd,
-                             const int32_t *__restrict__ coff, int32_t *__restrict__ lists) {
+                             const int32_t *__restrict__ coff, const int64_t *__restrict__ woff,
+                             int4 *__restrict__ lists) {
     int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
     int64_t cc[3];
     unpack_key(cell_key[c], cc);
-    int32_t *L = lists + c * kListStride;
+    int4 *L = lists + c * kListStride;
     int nsel = 0;
     // ascending key order: x offset outermost, z innermost
     for (int dx = -1; dx <= 1; ++dx)
@@ -149,9 +170,10 @@ __global__ void k_cell_lists(int64_t ncells, const uint64_t *__restrict__ cell_k
                 int64_t s = hash_find(chash, cmask, pack_key(cc[0] + dx, cc[1] + dy, cc[2] + dz));
                 if (s < 0) continue;
                 const int32_t id = chash_val[s];
-                if (pd[id] && coff[id + 1] > coff[id]) L[1 + nsel++] = id;
+                const int32_t b = coff[id], n = coff[id + 1] - b;
+                if (pd[id] && n > 0) L[1 + nsel++] = make_int4(id, b, n, int32_t(woff[id]));
             }
-    L[0] = nsel;
+    L[0] = make_int4(nsel, 0, 0, 0);
 }
 
 // chunk table: (cell, first query) for every 64-query chunk of every cell
@@ -295,6 +317,28 @@ __device__ __forceinline__ T alpha_of(const float4 &p, const double *__restrict_
 // n <= NMAX: k in registers, W rows packed (row i at i (i + 1) / 2).  The
 // rows are generated at compile time (index sequences), so every k_j index is
 // a constant and the vector lives in VGPRs.
+// kernel value only (a point already summed in another panel)
+template <typename T, int KERN>
+__device__ __forceinline__ T point_k(const float4 p, const QueryPoint &Q, const QueryConsts &C) {
+    T dx, dy, dz;
+    if constexpr (std::is_same<T, float>::value) {
+        dx = Q.fx - p.x; dy = Q.fy - p.y; dz = Q.fz - p.z;
+    } else {
+        dx = double(Q.fx) - double(p.x); dy = double(Q.fy) - double(p.y); dz = double(Q.fz) - double(p.z);
+    }
+    const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    if (KERN == GPDF_KERNEL_MATERN32) {
+        const T t = RT<T>::sqrt(r2) * T(std::is_same<T, float>::value ? C.a : C.ad);
+        const T e = RT<T>::expn(t);
+        return fma(t, e, e);
+    } else {
+        return RT<T>::expn(r2 * T(std::is_same<T, float>::value ? C.a : C.ad));
+    }
+}
+
+// n <= NMAX <= 32: k in registers, W rows packed (row i at i (i + 1) / 2).
+// The rows are generated at compile time (index sequences), so every k_j
+// index is a constant and the vector lives in VGPRs.
 template <typename T, int... J>
 __device__ __forceinline__ T row_dot(const T *__restrict__ Wi, const T *kr,
                                      std::integer_sequence<int, J...>) {
@@ -327,40 +371,51 @@ __device__ __forceinline__ void eval_small(const float4 *__restrict__ P, const d
     small_rows<T, KERN, NMAX, 0>(P, a64, W, n, pbase, Q, C, r, A, kr);
 }
 
-template <typename T, int... R>
+// t[R0 + R] += col[R0 + R] k_j for R = 0 .. kPanel - 1 - R0
+template <typename T, int R0, int... R>
 __device__ __forceinline__ void panel_update(T *t, const T *__restrict__ col, T kj,
                                              std::integer_sequence<int, R...>) {
-    ((t[R] = fma(col[R], kj, t[R])), ...);
+    ((t[R0 + R] = fma(col[R0 + R], kj, t[R0 + R])), ...);
 }
 
-// n > 64: point sums in one pass, then W k by 64-row panels with k recomputed
-template <typename T, int KERN>
-__device__ __forceinline__ void eval_big(const float4 *__restrict__ P, const double *__restrict__ a64,
-                                         const T *__restrict__ W, int n, int pbase,
-                                         const QueryPoint &Q, const QueryConsts &C, PairRaw<T> &r,
-                                         Acc<T> &A) {
-    for (int i = 0; i < n; ++i) {
-        const float4 p = P[i];
-        point_eval<T, KERN>(p, alpha_of<T>(p, a64, i), Q, pbase + i, C, r, A);
+// diagonal block of a panel: column J holds rows J .. kPanel - 1 (lower
+// triangle), so the update starts at row J; its points are summed here
+template <typename T, int KERN, int J>
+__device__ __forceinline__ void diag_cols(const float4 *__restrict__ P, const double *__restrict__ a64,
+                                          const T *__restrict__ D, int nrem, int pbase,
+                                          const QueryPoint &Q, const QueryConsts &C, PairRaw<T> &r,
+                                          Acc<T> &A, T *t) {
+    if constexpr (J < kPanel) {
+        if (J >= nrem) return;
+        const float4 p = P[J];
+        const T kj = point_eval<T, KERN>(p, alpha_of<T>(p, a64, J), Q, pbase + J, C, r, A);
+        panel_update<T, J>(t, D + J * kPanel, kj, std::make_integer_sequence<int, kPanel - J>{});
+        diag_cols<T, KERN, J + 1>(P, a64, D, nrem, pbase, Q, C, r, A, t);
     }
-    const int nb = (n + kPanel - 1) / kPanel;
-    PairRaw<T> dummy{};
-    Acc<T> dA;
-    dA.best = -1.f;  // never updated: r2 < -1 is false
-    dA.bidx = 0;
+}
+
+// n > 32: W in 32-row panels (column-major inside).  Panel r needs k_j for
+// every column j < 32 (r + 1): the columns left of its diagonal block belong
+// to points summed in earlier panels and only their kernel values are
+// recomputed; the diagonal block sums its own points.
+template <typename T, int KERN>
+__device__ __forceinline__ void eval_panels(const float4 *__restrict__ P, const double *__restrict__ a64,
+                                            const T *__restrict__ W, int n, int pbase,
+                                            const QueryPoint &Q, const QueryConsts &C, PairRaw<T> &r,
+                                            Acc<T> &A) {
     const T *Pn = W;
-    for (int rb = 0; rb < nb; ++rb) {
+    for (int c0 = 0; c0 < n; c0 += kPanel) {
         T t[kPanel];
 #pragma unroll
         for (int q = 0; q < kPanel; ++q) t[q] = T(0);
-        const int ncol = min((rb + 1) * kPanel, n);
-        for (int j = 0; j < ncol; ++j) {
-            const T kj = point_eval<T, KERN>(P[j], T(0), Q, 0, C, dummy, dA);
-            panel_update<T>(t, Pn + j * kPanel, kj, std::make_integer_sequence<int, kPanel>{});
+        for (int j = 0; j < c0; ++j) {
+            const T kj = point_k<T, KERN>(P[j], Q, C);
+            panel_update<T, 0>(t, Pn + j * kPanel, kj, std::make_integer_sequence<int, kPanel>{});
         }
+        diag_cols<T, KERN, 0>(P + c0, a64 + c0, Pn + c0 * kPanel, n - c0, pbase + c0, Q, C, r, A, t);
 #pragma unroll
         for (int q = 0; q < kPanel; ++q) r.ss = fma(t[q], t[q], r.ss);
-        Pn += ncol * kPanel;
+        Pn += int64_t(min(c0 + kPanel, n)) * kPanel;
     }
 }
 
@@ -478,7 +533,7 @@ struct Outputs {
 };
 
 // final combination, sign, error test and stores for one lane
-template <typename T>
+template <typename T, int MODE>
 __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell, bool active,
                                     const QueryPoint &Q, const float4 *__restrict__ pts,
                                     const QueryConsts &C, const Outputs &O) {
@@ -488,14 +543,14 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
     if (active && A.nq > 0) {
         T D, V, Gx, Gy, Gz;
         float Ed = 0.f, Eg = 0.f, Ev = 0.f;
-        if (C.combine == GPDF_COMB_HARDMIN) {
+        if constexpr (MODE == kModeHard) {
             D = A.hd; V = A.hv; Gx = A.hgx; Gy = A.hgy; Gz = A.hgz;
             Ed = A.hed; Eg = A.heg; Ev = A.hev;
         } else {
             const T iw = T(1) / A.sw;
             D = A.swd * iw;
             V = A.swv * iw;
-            if (C.grad_mode == GPDF_GRAD_PAPER_MEAN) {
+            if constexpr (MODE == kModeMean) {
                 const T iq = T(1) / T(A.nq);
                 Gx = A.pgx * iq; Gy = A.pgy * iq; Gz = A.pgz * iq;
             } else {
@@ -509,7 +564,7 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
                 // bounded by Cauchy-Schwarz through the online moments of g
                 const float Q2 = A.G2 - 2.f * (Gx * A.Ggx + Gy * A.Ggy + Gz * A.Ggz) + Gn * Gn * A.A1;
                 Eg = (A.B1 + lam * sqrtf(fmaxf(A.A1 * Q2, 0.f))) * iw;
-                if (C.grad_mode == GPDF_GRAD_PAPER_MEAN) Eg = A.sum_eg / float(A.nq) + Eg;
+                if constexpr (MODE == kModeMean) Eg = A.sum_eg / float(A.nq) + Eg;
                 Ev = A.C1 / A.swv;
             }
         }
@@ -559,23 +614,19 @@ __device__ __forceinline__ const T *factor_base(const float *W32, const double *
 }
 
 template <typename T, int KERN>
-__device__ __forceinline__ void eval_cluster(int32_t cid, const float4 *__restrict__ pts,
+__device__ __forceinline__ void eval_cluster(int base, int n, int64_t woff, const float4 *__restrict__ pts,
                                              const double *__restrict__ alpha64,
-                                             const int32_t *__restrict__ coff,
-                                             const int64_t *__restrict__ woff,
                                              const float *__restrict__ W32,
                                              const double *__restrict__ W64, const QueryPoint &Q,
                                              const QueryConsts &C, Acc<T> &A) {
-    const int base = coff[cid];
-    const int n = coff[cid + 1] - base;
     const float4 *P = pts + base;
     const double *a64 = alpha64 + base;
-    const T *W = factor_base<T>(W32, W64, woff[cid]);
+    const T *W = factor_base<T>(W32, W64, woff);
     PairRaw<T> r{T(0), T(0), T(0), T(0), T(0), 0.f};
-    if (n <= 16) eval_small<T, KERN, 16>(P, a64, W, n, base, Q, C, r, A);
-    else if (n <= 32) eval_small<T, KERN, 32>(P, a64, W, n, base, Q, C, r, A);
-    else if (n <= 64) eval_small<T, KERN, 64>(P, a64, W, n, base, Q, C, r, A);
-    else eval_big<T, KERN>(P, a64, W, n, base, Q, C, r, A);
+    if (n <= 8) eval_small<T, KERN, 8>(P, a64, W, n, base, Q, C, r, A);
+    else if (n <= 16) eval_small<T, KERN, 16>(P, a64, W, n, base, Q, C, r, A);
+    else if (n <= kPanel) eval_small<T, KERN, kPanel>(P, a64, W, n, base, Q, C, r, A);
+    else eval_panels<T, KERN>(P, a64, W, n, base, Q, C, r, A);
     finish_pair<T, KERN>(r, n, C, A);
 }
 
@@ -600,33 +651,40 @@ struct ModelView {
     double edge;
 };
 
-// NEIGHBOR27: one wavefront per (cell, 64-query chunk)
-template <typename T, int KERN>
-__global__ __launch_bounds__(kQT) void k_query_cells(const float *__restrict__ q, Grouping G,
-                                                     const int32_t *__restrict__ lists, ModelView Mo,
+// NEIGHBOR27: one wavefront per (cell, 64-query chunk).  The cell's list
+// holds a descriptor (cluster, first point, size, factor offset) per
+// selected cluster; the next descriptor is loaded while the current cluster
+// is evaluated.
+template <typename T, int KERN, int MODE>
+__global__ __launch_bounds__(kEvalT) void k_query_cells(const float *__restrict__ q, Grouping G,
+                                                     const int4 *__restrict__ lists, ModelView Mo,
                                                      QueryConsts C, Outputs O) {
-    const uint32_t wave = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const uint32_t nch = *G.nchunks;
+    const uint32_t wave = xcd_item(nch);  // one wavefront per workgroup
     const int lane = threadIdx.x & 63;
-    if (wave >= *G.nchunks) return;
+    if (wave >= nch) return;
     const uint2 ch = G.chunk[wave];
     const uint32_t cell = uniform(ch.x), start = uniform(ch.y);
     const uint32_t cnt = uniform(min(G.cell_cnt[cell] - start, 64u));
     const bool active = uint32_t(lane) < cnt;
     const uint32_t qi = G.order[G.cell_off[cell] + start + (active ? lane : 0)];
     const QueryPoint Q{q[3 * qi], q[3 * qi + 1], q[3 * qi + 2]};
-    const int32_t *L = lists + size_t(cell) * kListStride;
-    const int nsel = int(uniform(uint32_t(L[0])));
+    const int4 *L = lists + size_t(cell) * kListStride;
+    const int nsel = int(uniform(uint32_t(L[0].x)));
     Acc<T> A;
     acc_init(A);
     uint32_t sum_n = 0, sum_tri = 0;
+    int4 nxt = L[1];
     for (int s = 0; s < nsel; ++s) {
-        const int32_t cid = int32_t(uniform(uint32_t(L[1 + s])));
-        eval_cluster<T, KERN>(cid, Mo.pts, Mo.alpha64, Mo.coff, Mo.woff, Mo.W32, Mo.W64, Q, C, A);
-        const uint32_t n = uint32_t(Mo.coff[cid + 1] - Mo.coff[cid]);
-        sum_n += n;
-        sum_tri += n * (n + 1) / 2;
+        const int4 d = nxt;
+        if (s + 1 < nsel) nxt = L[2 + s];
+        const int base = int(uniform(uint32_t(d.y))), n = int(uniform(uint32_t(d.z)));
+        const int64_t woff = int64_t(uniform(uint32_t(d.w)));
+        eval_cluster<T, KERN>(base, n, woff, Mo.pts, Mo.alpha64, Mo.W32, Mo.W64, Q, C, A);
+        sum_n += uint32_t(n);
+        sum_tri += uint32_t(n * (n + 1) / 2);
     }
-    finish_query<T>(A, qi, cell, active, Q, Mo.pts, C, O);
+    finish_query<T, MODE>(A, qi, cell, active, Q, Mo.pts, C, O);
     // algorithmic work of this wavefront (active lanes), one atomic each
     if (std::is_same<T, float>::value && lane == 0 && nsel > 0) {
         atomicAdd(&O.stat[ST_PAIRS], (unsigned long long)nsel * cnt);
@@ -660,8 +718,8 @@ __device__ inline int wave_min_i32(int v) {
 // KNN: each lane picks its Q nearest clusters by cell-centre distance (ties
 // to the smaller key); the wavefront walks the union of the lanes' lists in
 // ascending cluster order and each lane evaluates exactly its own clusters
-template <typename T, int KERN>
-__global__ __launch_bounds__(kQT) void k_query_knn(const float *__restrict__ q, Grouping G,
+template <typename T, int KERN, int MODE>
+__global__ __launch_bounds__(kEvalT) void k_query_knn(const float *__restrict__ q, Grouping G,
                                                    ModelView Mo, QueryConsts C, Outputs O) {
     __shared__ int32_t lst[kWaves][kMaxKnn][64];
     const int wv = threadIdx.x >> 6;
@@ -716,29 +774,43 @@ __global__ __launch_bounds__(kQT) void k_query_knn(const float *__restrict__ q, 
         if (c == 0x7fffffff) break;
         if (mine == c) {
             ++ptr;
-            eval_cluster<T, KERN>(c, Mo.pts, Mo.alpha64, Mo.coff, Mo.woff, Mo.W32, Mo.W64, Q, C, A);
+            const int base = int(uniform(uint32_t(Mo.coff[c])));
+            const int n = int(uniform(uint32_t(Mo.coff[c + 1]))) - base;
+            eval_cluster<T, KERN>(base, n, Mo.woff[c], Mo.pts, Mo.alpha64, Mo.W32, Mo.W64, Q, C, A);
         }
     }
-    finish_query<T>(A, qi, cell, active, Q, Mo.pts, C, O);
+    finish_query<T, MODE>(A, qi, cell, active, Q, Mo.pts, C, O);
+}
+
+template <typename T, int KERN, int MODE>
+void launch_query(bool knn, unsigned grid, hipStream_t s, const float *q, const Grouping &G,
+                  const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O) {
+    if (knn)
+        hipLaunchKernelGGL((k_query_knn<T, KERN, MODE>), dim3(grid), dim3(kEvalT), 0, s, q, G, Mo, C, O);
+    else
+        hipLaunchKernelGGL((k_query_cells<T, KERN, MODE>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists, Mo,
+                           C, O);
 }
 
 template <typename T, int KERN>
-void launch_query(bool knn, unsigned grid, hipStream_t s, const float *q, const Grouping &G,
-                  const int32_t *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O) {
-    if (knn)
-        hipLaunchKernelGGL((k_query_knn<T, KERN>), dim3(grid), dim3(kQT), 0, s, q, G, Mo, C, O);
+void launch_query_m(bool knn, unsigned grid, hipStream_t s, const float *q, const Grouping &G,
+                    const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O) {
+    if (C.combine == GPDF_COMB_HARDMIN)
+        launch_query<T, KERN, kModeHard>(knn, grid, s, q, G, lists, Mo, C, O);
+    else if (C.grad_mode == GPDF_GRAD_PAPER_MEAN)
+        launch_query<T, KERN, kModeMean>(knn, grid, s, q, G, lists, Mo, C, O);
     else
-        hipLaunchKernelGGL((k_query_cells<T, KERN>), dim3(grid), dim3(kQT), 0, s, q, G, lists, Mo, C, O);
+        launch_query<T, KERN, kModeSmooth>(knn, grid, s, q, G, lists, Mo, C, O);
 }
 
 template <typename T>
 void launch_query_k(int kernel, bool knn, unsigned grid, hipStream_t s, const float *q,
-                    const Grouping &G, const int32_t *lists, const ModelView &Mo,
+                    const Grouping &G, const int4 *lists, const ModelView &Mo,
                     const QueryConsts &C, const Outputs &O) {
     if (kernel == GPDF_KERNEL_MATERN32)
-        launch_query<T, GPDF_KERNEL_MATERN32>(knn, grid, s, q, G, lists, Mo, C, O);
+        launch_query_m<T, GPDF_KERNEL_MATERN32>(knn, grid, s, q, G, lists, Mo, C, O);
     else
-        launch_query<T, GPDF_KERNEL_SE>(knn, grid, s, q, G, lists, Mo, C, O);
+        launch_query_m<T, GPDF_KERNEL_SE>(knn, grid, s, q, G, lists, Mo, C, O);
 }
 
 }  // namespace
@@ -836,16 +908,26 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     exclusive_scan_u32(c->d_cell_chunks, c->d_chunk_off, nc, c->d_part, s);
     hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, c->d_cell_chunks,
                        c->d_chunk_off, c->d_chunk);
+    if (!knn && nc > c->cap_cells) {
+        // grow the per-cell cluster lists (one reallocation per new maximum)
+        const int64_t cap = std::min<int64_t>(c->p.max_queries + 1, nc + nc / 4 + 1024);
+        if ((e = hipFree(c->d_cell_list)) != hipSuccess) return hip_fail(c, e, "query: cell lists");
+        c->d_cell_list = nullptr;
+        c->cap_cells = 0;
+        if ((e = hipMalloc((void **)&c->d_cell_list, sizeof(int4) * size_t(cap) * kCellListStride)) != hipSuccess)
+            return hip_fail(c, e, "query: cell lists");
+        c->cap_cells = cap;
+    }
     if (!knn)
         hipLaunchKernelGGL(k_cell_lists, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, c->d_cell_key,
                            c->d_chash, c->chash_mask, c->d_chash_val, c->d_pd, c->d_coff,
-                           c->d_cell_list);
+                           c->d_woff, c->d_cell_list);
     hipLaunchKernelGGL(k_scatter_order, dim3(blocks_for(m)), dim3(kQT), 0, s, c->d_qslot, c->d_qrank, m,
                        c->d_qhash_cell, c->d_cell_off, c->d_order);
     stage_end(c, GPDF_MS_GROUP);
     // 2. evaluation; the chunk count stays on the device (grid is an upper bound)
     const int64_t max_chunks = nc + (m + 63) / 64;
-    const unsigned grid = blocks_for(max_chunks * 64);
+    const unsigned grid = blocks_for(max_chunks * 64, kEvalT);
     const Grouping G{c->d_chunk, c->d_chunk_off + nc, c->d_cell_cnt, c->d_cell_off, c->d_order};
     Outputs O{dist, grad, var, aux, valid, c->d_refine, c->d_stat};
     if (c->p.precision == GPDF_PREC_FP64) {

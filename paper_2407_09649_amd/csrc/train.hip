@@ -254,8 +254,8 @@ __global__ __launch_bounds__(kT) void k_train_clusters(
         alpha64[base + j] = a;
         pts[base + j].w = float(a);
     }
-    // W in the query layout (FP32 and FP64): packed rows for n <= 64 (the
-    // order of the packed triangle), 64-row panels above that, column-major
+    // W in the query layout (FP32 and FP64): packed rows for n <= 32 (the
+    // order of the packed triangle), 32-row panels above that, column-major
     // inside and zero above the diagonal
     float *W32 = W32all + woff[c];
     double *W64 = W64all + woff[c];
@@ -479,14 +479,29 @@ __global__ __launch_bounds__(64) void k_train_wave(
         alpha64[base + j] = a;
         pts[base + j].w = float(a);
     }
+    // W in the query layout: packed rows up to 32 points, 32-row panels
+    // (column-major inside, zero above the diagonal) above that
     const int64_t off = woff[c];
-    const int tot = n * (n + 1) / 2;
-    for (int idx = lane; idx < tot; idx += 64) {
-        int i = int((sqrt(8.0 * double(idx) + 1.0) - 1.0) * 0.5);
-        while ((i + 1) * (i + 2) / 2 <= idx) ++i;
-        while (i * (i + 1) / 2 > idx) --i;
-        const int j = idx - i * (i + 1) / 2;
-        put_w(W32all, W64all, off, idx, Wc[j * n - j * (j - 1) / 2 + (i - j)]);
+    if (n <= kPanel) {
+        const int tot = n * (n + 1) / 2;
+        for (int idx = lane; idx < tot; idx += 64) {
+            int i = int((sqrt(8.0 * double(idx) + 1.0) - 1.0) * 0.5);
+            while ((i + 1) * (i + 2) / 2 <= idx) ++i;
+            while (i * (i + 1) / 2 > idx) --i;
+            const int j = idx - i * (i + 1) / 2;
+            put_w(W32all, W64all, off, idx, Wc[j * n - j * (j - 1) / 2 + (i - j)]);
+        }
+    } else {
+        const int nb = (n + kPanel - 1) / kPanel;
+        for (int r = 0; r < nb; ++r) {
+            const int64_t po = off + w32_panel_offset(n, r);
+            const int ncol = min((r + 1) * kPanel, n);
+            for (int idx = lane; idx < ncol * kPanel; idx += 64) {
+                const int j = idx / kPanel, i = r * kPanel + (idx - j * kPanel);
+                const double w = (i < n && j <= i) ? Wc[j * n - j * (j - 1) / 2 + (i - j)] : 0.0;
+                put_w(W32all, W64all, po, idx, w);
+            }
+        }
     }
     if (lane == 0) pd[c] = 1;
 }
