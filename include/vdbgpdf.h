@@ -248,6 +248,8 @@ gpdf_status gpdf_mlp_get_weights(gpdf_ctx *ctx, float *h_w, int64_t cap);
 /* feature standardisation: z = (f - mean) / std, h_mean and h_std float[7] */
 gpdf_status gpdf_mlp_set_norm(gpdf_ctx *ctx, const float *h_mean,
                               const float *h_std);
+/* the standardisation in use (set by gpdf_mlp_set_norm or by training) */
+gpdf_status gpdf_mlp_get_norm(gpdf_ctx *ctx, float *h_mean, float *h_std);
 /* raw features [n][7] from query outputs (dist, var, aux, grad) */
 gpdf_status gpdf_mlp_features(gpdf_ctx *ctx, const float *d_dist,
                               const float *d_var, const float *d_grad,

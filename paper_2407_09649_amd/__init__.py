@@ -33,7 +33,7 @@ EXPORTS = [
     "gpdf_last_error", "gpdf_export_model", "gpdf_export_global",
     "gpdf_export_test_points", "gpdf_save_global", "gpdf_load_global",
     "gpdf_nearest_distance", "gpdf_mlp_init", "gpdf_mlp_set_weights",
-    "gpdf_mlp_get_weights", "gpdf_mlp_set_norm", "gpdf_mlp_features",
+    "gpdf_mlp_get_weights", "gpdf_mlp_set_norm", "gpdf_mlp_get_norm", "gpdf_mlp_features",
     "gpdf_mlp_forward", "gpdf_mlp_grad", "gpdf_mlp_train",
 ]
 
@@ -127,6 +127,7 @@ def _bind(L):
         "gpdf_mlp_set_weights": [P, P, I64],
         "gpdf_mlp_get_weights": [P, P, I64],
         "gpdf_mlp_set_norm": [P, P, P],
+        "gpdf_mlp_get_norm": [P, P, P],
         "gpdf_mlp_features": [P, P, P, P, P, I64, P],
         "gpdf_mlp_forward": [P, P, I64, P],
         "gpdf_mlp_grad": [P, P, P, I64, P, P],
@@ -336,6 +337,14 @@ class Context:
         s = np.ascontiguousarray(std, np.float32)
         _check(self.lib.gpdf_mlp_set_norm(self._h, m.ctypes.data_as(C.c_void_p),
                                           s.ctypes.data_as(C.c_void_p)), self._h)
+
+    def mlp_get_norm(self):
+        import numpy as np
+        m = np.empty(7, np.float32)
+        s = np.empty(7, np.float32)
+        _check(self.lib.gpdf_mlp_get_norm(self._h, m.ctypes.data_as(C.c_void_p),
+                                          s.ctypes.data_as(C.c_void_p)), self._h)
+        return m, s
 
     def mlp_features(self, res):
         torch = self._torch

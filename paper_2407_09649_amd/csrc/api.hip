@@ -37,8 +37,8 @@ void release(gpdf_ctx *c) {
                     c->d_rchunk,
                     c->d_tmp_dist, c->d_tmp_var, c->d_tmp_grad, c->d_tmp_valid, c->d_tset,
                     c->d_tkeys, c->d_tpts, c->d_gkey, c->d_gD, c->d_gV, c->d_gstamp, c->d_offs,
-                    c->d_mlp_w, c->d_mlp_m, c->d_mlp_v, c->d_mlp_g, c->d_mlp_norm, c->d_mlp_feat,
-                    c->d_mlp_perm, c->d_mlp_loss, c->d_stat, c->d_blist, c->d_tile_cnt, c->d_tile_off};
+                    c->d_mlp_w, c->d_mlp_m, c->d_mlp_v, c->d_mlp_g, c->d_mlp_rec, c->d_mlp_pack,
+                    c->d_mlp_norm, c->d_mlp_loss, c->d_mlp_mom, c->d_stat, c->d_blist, c->d_tile_cnt, c->d_tile_off};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_stat) (void)hipHostFree(c->h_stat);

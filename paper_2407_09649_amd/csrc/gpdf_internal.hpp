@@ -305,12 +305,13 @@ struct gpdf_ctx {
     // ---- MLP ----------------------------------------------------------------
     float *d_mlp_w = nullptr;       // FP32 master weights [8897]
     float *d_mlp_m = nullptr, *d_mlp_v = nullptr;  // Adam moments
-    float *d_mlp_g = nullptr;       // gradient accumulator
+    float *d_mlp_g = nullptr;       // reduced gradient [8897]
+    float *d_mlp_rec = nullptr;     // per-wavefront gradient records
+    void *d_mlp_pack = nullptr;     // BF16 copies of the weight matrices
     float *d_mlp_norm = nullptr;    // mean[7], std[7]
-    float *d_mlp_feat = nullptr;    // scratch for features
-    uint32_t *d_mlp_perm = nullptr;
-    float *d_mlp_loss = nullptr;
-    int64_t mlp_cap = 0;
+    float *d_mlp_loss = nullptr;    // per-wavefront losses + accumulator
+    double *d_mlp_mom = nullptr;    // feature moments (standardisation)
+    int64_t mlp_step = 0;           // Adam step counter
     bool mlp_ready = false;
     int64_t adam_t = 0;
 
