@@ -38,7 +38,7 @@ void release(gpdf_ctx *c) {
                     c->d_tmp_dist, c->d_tmp_var, c->d_tmp_grad, c->d_tmp_valid, c->d_tset,
                     c->d_tkeys, c->d_tpts, c->d_gkey, c->d_gD, c->d_gV, c->d_gstamp, c->d_offs,
                     c->d_mlp_w, c->d_mlp_m, c->d_mlp_v, c->d_mlp_g, c->d_mlp_rec, c->d_mlp_pack,
-                    c->d_mlp_norm, c->d_mlp_loss, c->d_mlp_mom, c->d_stat, c->d_blist, c->d_tile_cnt, c->d_tile_off};
+                    c->d_mlp_norm, c->d_mlp_loss, c->d_mlp_mom, c->d_stat, c->d_blist, c->d_tile_cnt, c->d_tile_off, c->d_bfM, c->d_bfoff};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
@@ -103,6 +103,7 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
         (p->combine != GPDF_COMB_SMOOTHMIN && p->combine != GPDF_COMB_HARDMIN) ||
         (p->grad_mode != GPDF_GRAD_WEIGHTED && p->grad_mode != GPDF_GRAD_PAPER_MEAN) ||
         (p->precision < GPDF_PREC_FP32 || p->precision > GPDF_PREC_FP64) ||
+        (p->precision == GPDF_PREC_BF16 && p->selection == GPDF_SEL_KNN) ||
         (p->timing != 0 && p->timing != 1) || p->max_points < 1 ||
         p->max_points > (int64_t(1) << 30) || p->max_clusters < 1 || p->max_cluster_points < 1 ||
         p->max_cluster_points > 1024 || p->max_factor_elems < 1 ||

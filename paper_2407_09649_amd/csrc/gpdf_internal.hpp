@@ -227,6 +227,7 @@ struct QueryConsts {
 struct Model {
     int64_t nclusters = 0, npoints = 0, nonpd = 0, skipped = 0, max_n = 0;
     bool trained = false;
+    bool bf16_ready = false;   // BF16 copies of [W; alpha] built for this model
     std::vector<int32_t> h_n;  // cluster sizes (host copy)
 };
 
@@ -256,6 +257,10 @@ struct gpdf_ctx {
     float *d_W32 = nullptr;                        // L^{-1} in FP32, query layout
     double *d_W64 = nullptr;                       // L^{-1} in FP64, query layout
     uint32_t *d_tile_cnt = nullptr, *d_tile_off = nullptr;  // table compaction
+    void *d_bfM = nullptr;                         // BF16 [W; alpha] per cluster (precision BF16)
+    int64_t *d_bfoff = nullptr;                    // their offsets (elements)
+    int64_t cap_bfM = 0, cap_bfoff = 0;
+    std::vector<int64_t> h_bfoff;
     double *d_A = nullptr;                         // FP64 workspace: packed A, L, then L^{-1} (n > 192)
     int64_t cap_w = 0, cap_a = 0;
     std::vector<int64_t> h_o32, h_oa;       // factor offsets (host)

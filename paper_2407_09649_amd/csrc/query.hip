@@ -589,7 +589,7 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
         const uint64_t nv = __ballot(active && A.nq > 0);
         if (lane == 0 && nv) atomicAdd(&O.stat[ST_VALID_Q], (unsigned long long)__popcll(nv));
         const uint64_t mb = __ballot(bad);
-        if (mb) {
+        if (mb && O.refine) {
             unsigned long long base = 0;
             if (lane == 0) base = atomicAdd(&O.stat[ST_REFINE], (unsigned long long)__popcll(mb));
             base = __shfl(base, 0, 64);
@@ -687,6 +687,192 @@ __global__ __launch_bounds__(kEvalT) void k_query_cells(const float *__restrict_
     finish_query<T, MODE>(A, qi, cell, active, Q, Mo.pts, C, O);
     // algorithmic work of this wavefront (active lanes), one atomic each
     if (std::is_same<T, float>::value && lane == 0 && nsel > 0) {
+        atomicAdd(&O.stat[ST_PAIRS], (unsigned long long)nsel * cnt);
+        atomicAdd(&O.stat[ST_POINTS], (unsigned long long)sum_n * cnt);
+        atomicAdd(&O.stat[ST_TRI], (unsigned long long)sum_tri * cnt);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 precision: the kernel-vector product o = k . alpha and the variance
+// product W k of a 64-query chunk and one cluster run on MFMA
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation) as C = [W; alpha^T] K^T.
+// Kernel values, the gradient sum, reverting and the combination stay FP32.
+// Lane layout of the 16x16x32 MFMA (lane l, lr = l % 16, lg = l / 16):
+//   A[m][k] lane m + 16 (k / 8), element k % 8; B[k][n] lane n + 16 (k / 8),
+//   element k % 8; D[m][n] lane n + 16 (m / 4), element m % 4.
+// [W; alpha] is kept per cluster in BF16, row-major, rows padded to 16 and
+// columns to 32: row i < n is row i of W (zero above the diagonal), row n is
+// alpha.  Clusters above kBfMaxN points use the FP32 path.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBfMaxN = 256;
+
+__host__ __device__ inline int bf_rows(int n) { return (n + 1 + 15) & ~15; }
+__host__ __device__ inline int bf_cols(int n) { return (n + 31) & ~31; }
+
+// index of W(i, j), j <= i, in the FP32 query layout
+__device__ inline int64_t w_index(int n, int i, int j) {
+    if (n <= kPanel) return int64_t(i) * (i + 1) / 2 + j;
+    const int r = i / kPanel;
+    return w32_panel_offset(n, r) + int64_t(j) * kPanel + (i - r * kPanel);
+}
+
+// one workgroup per cluster: BF16 [W; alpha] from the FP32 factor
+__global__ void k_pack_bf16(const int32_t *__restrict__ coff, const int64_t *__restrict__ woff,
+                            const int64_t *__restrict__ bfoff, const uint8_t *__restrict__ pd,
+                            const float *__restrict__ W32, const float4 *__restrict__ pts,
+                            __bf16 *__restrict__ M) {
+    const int c = blockIdx.x;
+    const int base = coff[c], n = coff[c + 1] - base;
+    if (n > kBfMaxN || !pd[c]) return;
+    const int rows = bf_rows(n), cols = bf_cols(n);
+    __bf16 *Mc = M + bfoff[c];
+    const float *W = W32 + woff[c];
+    for (int idx = threadIdx.x; idx < rows * cols; idx += blockDim.x) {
+        const int i = idx / cols, j = idx - i * cols;
+        float v = 0.f;
+        if (i < n && j <= i) v = W[w_index(n, i, j)];
+        else if (i == n && j < n) v = pts[base + j].w;
+        Mc[idx] = (__bf16)v;
+    }
+}
+
+// one point of the BF16 path: kernel value (returned), gradient sum and the
+// nearest-point decision, FP32
+template <int KERN>
+__device__ __forceinline__ float point_eval_b(const float4 p, const QueryPoint &Q, int gidx,
+                                              const QueryConsts &C, PairRaw<float> &r, Acc<float> &A) {
+    const float dx = Q.fx - p.x, dy = Q.fy - p.y, dz = Q.fz - p.z;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    if (r2 < A.best) { A.best = r2; A.bidx = gidx; }
+    float k, e;
+    if (KERN == GPDF_KERNEL_MATERN32) {
+        const float t = fsqrt(r2) * C.a;
+        e = fexp2(-t * kLog2e);
+        k = fmaf(t, e, e);
+    } else {
+        k = fexp2(-(r2 * C.a) * kLog2e);
+        e = k;
+    }
+    const float cg = p.w * e;
+    r.gx = fmaf(cg, dx, r.gx);
+    r.gy = fmaf(cg, dy, r.gy);
+    r.gz = fmaf(cg, dz, r.gz);
+    return k;
+}
+
+__device__ __forceinline__ float pick4(const float (&v)[4], int i) {
+    return i == 0 ? v[0] : i == 1 ? v[1] : i == 2 ? v[2] : v[3];
+}
+
+template <int KERN>
+__device__ void eval_cluster_bf16(int base, int n, int64_t bfo, const float4 *__restrict__ pts,
+                                  const __bf16 *__restrict__ Mall, __bf16 *Kt, int kts,
+                                  const QueryPoint &Q, const QueryConsts &C, Acc<float> &A) {
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    PairRaw<float> r{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int cols = bf_cols(n), rows = n + 1;
+    const float4 *P = pts + base;
+    // this lane's kernel vector, BF16, as row `lane` of K (LDS)
+    __bf16 *kr = Kt + lane * kts;
+    for (int j = 0; j < cols; ++j) {
+        float k = 0.f;
+        if (j < n) k = point_eval_b<KERN>(P[j], Q, base + j, C, r, A);
+        kr[j] = (__bf16)k;
+    }
+    __syncthreads();
+    const __bf16 *M = Mall + bfo;
+    float ssp[4] = {0.f, 0.f, 0.f, 0.f}, op[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int p0 = 0; p0 < rows; p0 += 64) {
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // columns this panel needs: up to its last W row, all of them when it
+        // holds the alpha row
+        const int kend = (p0 + 64 > n) ? cols : min(cols, (p0 + 64 + 31) & ~31);
+        for (int k0 = 0; k0 < kend; k0 += 32) {
+            bf16x8 b[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                b[nt] = *reinterpret_cast<const bf16x8 *>(Kt + (16 * nt + lr) * kts + k0 + 8 * lg);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int row0 = p0 + 16 * mt;
+                if (row0 >= rows) break;
+                // blocks above the diagonal of W are zero
+                if (row0 + 15 < n && k0 > row0 + 15) continue;
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(M + int64_t(row0 + lr) * cols + k0 + 8 * lg);
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nt], acc[mt][nt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int i = p0 + 16 * mt + 4 * lg + e;
+                    const float v = acc[mt][nt][e];
+                    if (i < n) ssp[nt] = fmaf(v, v, ssp[nt]);
+                    else if (i == n) op[nt] += v;
+                }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        ssp[nt] += __shfl_xor(ssp[nt], 16, 64);
+        ssp[nt] += __shfl_xor(ssp[nt], 32, 64);
+        op[nt] += __shfl_xor(op[nt], 16, 64);
+        op[nt] += __shfl_xor(op[nt], 32, 64);
+    }
+    // query of this lane: column lr of tile lg
+    r.ss = pick4(ssp, lg);
+    r.o = pick4(op, lg);
+    __syncthreads();  // K is rewritten by the next cluster
+    finish_pair<float, KERN>(r, n, C, A);
+}
+
+template <int KERN, int MODE>
+__global__ __launch_bounds__(kEvalT) void k_query_cells_bf16(const float *__restrict__ q, Grouping G,
+                                                             const int4 *__restrict__ lists, ModelView Mo,
+                                                             const __bf16 *__restrict__ Mbf,
+                                                             const int64_t *__restrict__ bfoff, int kts,
+                                                             QueryConsts C, Outputs O) {
+    extern __shared__ __bf16 Kt[];
+    const uint32_t nch = *G.nchunks;
+    const uint32_t wave = xcd_item(nch);
+    const int lane = threadIdx.x & 63;
+    if (wave >= nch) return;
+    const uint2 ch = G.chunk[wave];
+    const uint32_t cell = uniform(ch.x), start = uniform(ch.y);
+    const uint32_t cnt = uniform(min(G.cell_cnt[cell] - start, 64u));
+    const bool active = uint32_t(lane) < cnt;
+    const uint32_t qi = G.order[G.cell_off[cell] + start + (active ? lane : 0)];
+    const QueryPoint Q{q[3 * qi], q[3 * qi + 1], q[3 * qi + 2]};
+    const int4 *L = lists + size_t(cell) * kListStride;
+    const int nsel = int(uniform(uint32_t(L[0].x)));
+    Acc<float> A;
+    acc_init(A);
+    uint32_t sum_n = 0, sum_tri = 0;
+    for (int s = 0; s < nsel; ++s) {
+        const int4 d = L[1 + s];
+        const int cid = int(uniform(uint32_t(d.x)));
+        const int base = int(uniform(uint32_t(d.y))), n = int(uniform(uint32_t(d.z)));
+        if (n <= kBfMaxN)
+            eval_cluster_bf16<KERN>(base, n, bfoff[cid], Mo.pts, Mbf, Kt, kts, Q, C, A);
+        else
+            eval_cluster<float, KERN>(base, n, int64_t(uniform(uint32_t(d.w))), Mo.pts, Mo.alpha64, Mo.W32,
+                                      Mo.W64, Q, C, A);
+        sum_n += uint32_t(n);
+        sum_tri += uint32_t(n * (n + 1) / 2);
+    }
+    finish_query<float, MODE>(A, qi, cell, active, Q, Mo.pts, C, O);
+    if (lane == 0 && nsel > 0) {
         atomicAdd(&O.stat[ST_PAIRS], (unsigned long long)nsel * cnt);
         atomicAdd(&O.stat[ST_POINTS], (unsigned long long)sum_n * cnt);
         atomicAdd(&O.stat[ST_TRI], (unsigned long long)sum_tri * cnt);
@@ -803,6 +989,21 @@ void launch_query_m(bool knn, unsigned grid, hipStream_t s, const float *q, cons
         launch_query<T, KERN, kModeSmooth>(knn, grid, s, q, G, lists, Mo, C, O);
 }
 
+template <int KERN>
+void launch_bf16_m(unsigned grid, size_t lds, hipStream_t s, const float *q, const Grouping &G, const int4 *lists,
+                   const ModelView &Mo, const __bf16 *Mbf, const int64_t *bfoff, int kts, const QueryConsts &C,
+                   const Outputs &O) {
+    if (C.combine == GPDF_COMB_HARDMIN)
+        hipLaunchKernelGGL((k_query_cells_bf16<KERN, kModeHard>), dim3(grid), dim3(kEvalT), lds, s, q, G, lists, Mo,
+                           Mbf, bfoff, kts, C, O);
+    else if (C.grad_mode == GPDF_GRAD_PAPER_MEAN)
+        hipLaunchKernelGGL((k_query_cells_bf16<KERN, kModeMean>), dim3(grid), dim3(kEvalT), lds, s, q, G, lists, Mo,
+                           Mbf, bfoff, kts, C, O);
+    else
+        hipLaunchKernelGGL((k_query_cells_bf16<KERN, kModeSmooth>), dim3(grid), dim3(kEvalT), lds, s, q, G, lists,
+                           Mo, Mbf, bfoff, kts, C, O);
+}
+
 template <typename T>
 void launch_query_k(int kernel, bool knn, unsigned grid, hipStream_t s, const float *q,
                     const Grouping &G, const int4 *lists, const ModelView &Mo,
@@ -849,6 +1050,48 @@ QueryConsts make_consts(const gpdf_params &p, const float *origin) {
     C.omind = p.occ_min;
     C.omaxd = p.occ_max;
     return C;
+}
+
+// BF16 copies of [W; alpha] for the current model (once per training)
+gpdf_status build_bf16(gpdf_ctx *c) {
+    Model &M = c->model;
+    if (M.bf16_ready) return GPDF_OK;
+    hipStream_t s = c->stream;
+    hipError_t e;
+    const int64_t ncl = M.nclusters;
+    std::vector<int64_t> &off = c->h_bfoff;
+    off.assign(size_t(ncl), 0);
+    int64_t tot = 0;
+    for (int64_t i = 0; i < ncl; ++i) {
+        const int n = M.h_n[size_t(i)];
+        off[size_t(i)] = tot;
+        if (n <= kBfMaxN) tot += int64_t(bf_rows(n)) * bf_cols(n);
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "bf16: sync");
+    if (tot > c->cap_bfM) {
+        if (c->d_bfM && (e = hipFree(c->d_bfM)) != hipSuccess) return hip_fail(c, e, "bf16: free");
+        c->d_bfM = nullptr;
+        c->cap_bfM = 0;
+        const int64_t cap = tot + tot / 4 + 4096;
+        if ((e = hipMalloc(&c->d_bfM, sizeof(__bf16) * size_t(cap))) != hipSuccess) return hip_fail(c, e, "bf16: alloc");
+        c->cap_bfM = cap;
+    }
+    if (ncl > c->cap_bfoff) {
+        if (c->d_bfoff && (e = hipFree(c->d_bfoff)) != hipSuccess) return hip_fail(c, e, "bf16: free");
+        c->d_bfoff = nullptr;
+        c->cap_bfoff = 0;
+        if ((e = hipMalloc((void **)&c->d_bfoff, sizeof(int64_t) * size_t(ncl))) != hipSuccess)
+            return hip_fail(c, e, "bf16: alloc");
+        c->cap_bfoff = ncl;
+    }
+    if ((e = hipMemcpyAsync(c->d_bfoff, off.data(), sizeof(int64_t) * size_t(ncl), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        return hip_fail(c, e, "bf16: offsets");
+    hipLaunchKernelGGL(k_pack_bf16, dim3(unsigned(ncl)), dim3(256), 0, s, c->d_coff, c->d_woff, c->d_bfoff, c->d_pd,
+                       c->d_W32, c->d_pts, static_cast<__bf16 *>(c->d_bfM));
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "bf16: pack");
+    M.bf16_ready = true;
+    return GPDF_OK;
 }
 
 gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin, float *dist,
@@ -933,6 +1176,21 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     if (c->p.precision == GPDF_PREC_FP64) {
         stage_begin(c, GPDF_MS_EVAL);
         launch_query_k<double>(kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O);
+        stage_end(c, GPDF_MS_EVAL);
+    } else if (c->p.precision == GPDF_PREC_BF16) {
+        // MFMA products in BF16; no FP64 re-evaluation (the error is the point)
+        const gpdf_status st = build_bf16(c);
+        if (st != GPDF_OK) return st;
+        const int kts = bf_cols(int(std::min<int64_t>(M.max_n, kBfMaxN))) + 8;
+        const size_t lds = size_t(64) * kts * sizeof(__bf16);
+        Outputs Ob = O;
+        Ob.refine = nullptr;
+        const __bf16 *Mbf = static_cast<const __bf16 *>(c->d_bfM);
+        stage_begin(c, GPDF_MS_EVAL);
+        if (kern == GPDF_KERNEL_MATERN32)
+            launch_bf16_m<GPDF_KERNEL_MATERN32>(grid, lds, s, d_q, G, c->d_cell_list, Mo, Mbf, c->d_bfoff, kts, C, Ob);
+        else
+            launch_bf16_m<GPDF_KERNEL_SE>(grid, lds, s, d_q, G, c->d_cell_list, Mo, Mbf, c->d_bfoff, kts, C, Ob);
         stage_end(c, GPDF_MS_EVAL);
     } else {
         stage_begin(c, GPDF_MS_EVAL);

@@ -645,6 +645,7 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n) {
                        hv, c->d_chash_val, c->d_stat);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "train: launch");
     M.nclusters = ncl;
+    M.bf16_ready = false;
     M.npoints = npts;
     M.max_n = maxn;
     return GPDF_OK;
