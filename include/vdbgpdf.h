@@ -235,6 +235,25 @@ gpdf_status gpdf_load_global(gpdf_ctx *ctx, const char *path);
 gpdf_status gpdf_nearest_distance(gpdf_ctx *ctx, const float *d_pts, int64_t n,
                                   const float *d_q, int64_t m, float *d_out);
 
+/* ---- batching: launch shapes picked by measurement (an extension) --------
+ * train_threads: workgroup of the trainer of clusters above 64 points (256,
+ * 512 or 1024).  eval_persistent: 0 launches one wavefront per 64-query
+ * chunk; 1, 2 or 4 keep that many persistent wavefronts per SIMD taking
+ * chunks from a counter (NEIGHBOR27 selection; KNN ignores it).
+ * gpdf_autotune trains on d_xyz [n][3] with each train_threads candidate and
+ * queries d_q [m][3] (signed from h_origin, or unsigned with NULL) with each
+ * eval_persistent candidate, three timed runs after a warm-up each, keeps the
+ * fastest of both and leaves the context trained on d_xyz.  h_ms (float[7] or
+ * NULL) receives the median times in ms: train 256/512/1024, query 0/1/2/4.
+ * Errors: GPDF_E_INVALID_ARG (empty input, unknown shape), GPDF_E_CAPACITY. */
+gpdf_status gpdf_set_tuning(gpdf_ctx *ctx, int32_t train_threads,
+                            int32_t eval_persistent);
+gpdf_status gpdf_get_tuning(const gpdf_ctx *ctx, int32_t *train_threads,
+                            int32_t *eval_persistent);
+gpdf_status gpdf_autotune(gpdf_ctx *ctx, const float *d_xyz, int64_t n,
+                          const float *d_q, int64_t m, const float *h_origin,
+                          float *h_ms);
+
 /* ---- learned correction (an extension; not in the paper) ----------------
  * A 7-64-64-64-1 GELU network maps standardised features
  * [d, log v, o, grad d (3), log(1 + n_local)] to a residual r.  Parameters

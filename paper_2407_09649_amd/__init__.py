@@ -33,6 +33,7 @@ EXPORTS = [
     "gpdf_last_error", "gpdf_export_model", "gpdf_export_global",
     "gpdf_export_test_points", "gpdf_save_global", "gpdf_load_global",
     "gpdf_nearest_distance", "gpdf_mlp_init", "gpdf_mlp_set_weights",
+    "gpdf_set_tuning", "gpdf_get_tuning", "gpdf_autotune",
     "gpdf_mlp_get_weights", "gpdf_mlp_set_norm", "gpdf_mlp_get_norm", "gpdf_mlp_features",
     "gpdf_mlp_forward", "gpdf_mlp_grad", "gpdf_mlp_train",
 ]
@@ -123,6 +124,9 @@ def _bind(L):
         "gpdf_save_global": [P, C.c_char_p],
         "gpdf_load_global": [P, C.c_char_p],
         "gpdf_nearest_distance": [P, P, I64, P, I64, P],
+        "gpdf_set_tuning": [P, C.c_int32, C.c_int32],
+        "gpdf_get_tuning": [P, P, P],
+        "gpdf_autotune": [P, P, I64, P, I64, P, P],
         "gpdf_mlp_init": [P, U64],
         "gpdf_mlp_set_weights": [P, P, I64],
         "gpdf_mlp_get_weights": [P, P, I64],
@@ -315,6 +319,29 @@ class Context:
 
     def load_global(self, path):
         _check(self.lib.gpdf_load_global(self._h, os.fsencode(path)), self._h)
+
+    # -- batching: tuned launch shapes ----------------------------------------
+    def set_tuning(self, train_threads=256, eval_persistent=0):
+        _check(self.lib.gpdf_set_tuning(self._h, int(train_threads), int(eval_persistent)), self._h)
+
+    def get_tuning(self):
+        t, p = C.c_int32(0), C.c_int32(0)
+        _check(self.lib.gpdf_get_tuning(self._h, C.byref(t), C.byref(p)), self._h)
+        return {"train_threads": t.value, "eval_persistent": p.value}
+
+    def autotune(self, xyz, q, origin=None):
+        """Times the launch-shape candidates on this workload, keeps the
+        fastest and leaves the context trained on xyz.  Returns the median
+        times (ms) of every candidate."""
+        import numpy as np
+        torch = self._torch
+        ms = np.zeros(7, np.float32)
+        _check(self.lib.gpdf_autotune(self._h, _dptr(xyz, torch.float32, 3), xyz.shape[0],
+                                      _dptr(q, torch.float32, 3), q.shape[0], _host3(origin),
+                                      ms.ctypes.data_as(C.c_void_p)), self._h)
+        names = ["train_256", "train_512", "train_1024", "eval_grid", "eval_persist1",
+                 "eval_persist2", "eval_persist4"]
+        return dict(zip(names, ms.tolist()))
 
     # -- learned correction ---------------------------------------------------
     def mlp_init(self, seed=0):

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvdbgpdf.so")
-SOURCES = ["api.hip", "sort.hip", "train.hip", "query.hip", "fuse.hip", "mlp.hip"]
+SOURCES = ["api.hip", "sort.hip", "train.hip", "query.hip", "fuse.hip", "mlp.hip", "tune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

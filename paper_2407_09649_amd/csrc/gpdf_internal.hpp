@@ -233,8 +233,16 @@ struct Model {
 
 }  // namespace gpdf
 
+// launch shapes picked by the autotuner (defaults until it runs)
+struct gpdf_tune {
+    int train_threads = 1024;  // workgroup of the large-cluster trainer: 256, 512 or 1024
+    int eval_persistent = 0;   // evaluation: 0 = one workgroup per chunk, else persistent waves per SIMD
+    int tuned = 0;
+};
+
 struct gpdf_ctx {
     gpdf_params p{};
+    gpdf_tune tune;
     hipStream_t stream = nullptr;
     int device = 0;
     std::string err;
@@ -247,6 +255,7 @@ struct gpdf_ctx {
     uint32_t *d_hist = nullptr;                    // radix histograms
     uint32_t *d_part = nullptr;                    // scan partials
     uint64_t *d_red = nullptr;                     // small reductions
+    uint32_t *d_work = nullptr;                    // work counters of persistent launches [8]
     float4 *d_pts = nullptr;                       // training points (x, y, z, alpha32)
     double *d_alpha64 = nullptr;                   // alpha in FP64
     uint64_t *d_ckey = nullptr;                    // cluster keys [max_clusters]

@@ -656,13 +656,10 @@ struct ModelView {
 // selected cluster; the next descriptor is loaded while the current cluster
 // is evaluated.
 template <typename T, int KERN, int MODE>
-__global__ __launch_bounds__(kEvalT) void k_query_cells(const float *__restrict__ q, Grouping G,
-                                                     const int4 *__restrict__ lists, ModelView Mo,
-                                                     QueryConsts C, Outputs O) {
-    const uint32_t nch = *G.nchunks;
-    const uint32_t wave = xcd_item(nch);  // one wavefront per workgroup
+__device__ __forceinline__ void cells_chunk(uint32_t wave, const float *__restrict__ q, const Grouping &G,
+                                            const int4 *__restrict__ lists, const ModelView &Mo,
+                                            const QueryConsts &C, const Outputs &O) {
     const int lane = threadIdx.x & 63;
-    if (wave >= nch) return;
     const uint2 ch = G.chunk[wave];
     const uint32_t cell = uniform(ch.x), start = uniform(ch.y);
     const uint32_t cnt = uniform(min(G.cell_cnt[cell] - start, 64u));
@@ -690,6 +687,28 @@ __global__ __launch_bounds__(kEvalT) void k_query_cells(const float *__restrict_
         atomicAdd(&O.stat[ST_PAIRS], (unsigned long long)nsel * cnt);
         atomicAdd(&O.stat[ST_POINTS], (unsigned long long)sum_n * cnt);
         atomicAdd(&O.stat[ST_TRI], (unsigned long long)sum_tri * cnt);
+    }
+}
+
+// work == NULL: one wavefront (workgroup) per chunk, XCD-aware order.
+// Otherwise persistent: a fixed set of wavefronts takes chunks from the
+// counter *work (zero at launch) until none is left.
+template <typename T, int KERN, int MODE>
+__global__ __launch_bounds__(kEvalT) void k_query_cells(const float *__restrict__ q, Grouping G,
+                                                     const int4 *__restrict__ lists, ModelView Mo,
+                                                     QueryConsts C, Outputs O, uint32_t *work) {
+    const uint32_t nch = *G.nchunks;
+    if (!work) {
+        const uint32_t wave = xcd_item(nch);
+        if (wave < nch) cells_chunk<T, KERN, MODE>(wave, q, G, lists, Mo, C, O);
+        return;
+    }
+    while (true) {
+        uint32_t w = 0;
+        if ((threadIdx.x & 63) == 0) w = atomicAdd(work, 1u);
+        w = uniform(uint32_t(__shfl(int(w), 0, 64)));
+        if (w >= nch) break;
+        cells_chunk<T, KERN, MODE>(w, q, G, lists, Mo, C, O);
     }
 }
 
@@ -968,25 +987,29 @@ __global__ __launch_bounds__(kEvalT) void k_query_knn(const float *__restrict__ 
     finish_query<T, MODE>(A, qi, cell, active, Q, Mo.pts, C, O);
 }
 
+// grid: one workgroup per chunk (an upper bound); with work != NULL the
+// persistent grid
 template <typename T, int KERN, int MODE>
 void launch_query(bool knn, unsigned grid, hipStream_t s, const float *q, const Grouping &G,
-                  const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O) {
+                  const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O,
+                  uint32_t *work) {
     if (knn)
         hipLaunchKernelGGL((k_query_knn<T, KERN, MODE>), dim3(grid), dim3(kEvalT), 0, s, q, G, Mo, C, O);
     else
         hipLaunchKernelGGL((k_query_cells<T, KERN, MODE>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists, Mo,
-                           C, O);
+                           C, O, work);
 }
 
 template <typename T, int KERN>
 void launch_query_m(bool knn, unsigned grid, hipStream_t s, const float *q, const Grouping &G,
-                    const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O) {
+                    const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O,
+                    uint32_t *work) {
     if (C.combine == GPDF_COMB_HARDMIN)
-        launch_query<T, KERN, kModeHard>(knn, grid, s, q, G, lists, Mo, C, O);
+        launch_query<T, KERN, kModeHard>(knn, grid, s, q, G, lists, Mo, C, O, work);
     else if (C.grad_mode == GPDF_GRAD_PAPER_MEAN)
-        launch_query<T, KERN, kModeMean>(knn, grid, s, q, G, lists, Mo, C, O);
+        launch_query<T, KERN, kModeMean>(knn, grid, s, q, G, lists, Mo, C, O, work);
     else
-        launch_query<T, KERN, kModeSmooth>(knn, grid, s, q, G, lists, Mo, C, O);
+        launch_query<T, KERN, kModeSmooth>(knn, grid, s, q, G, lists, Mo, C, O, work);
 }
 
 template <int KERN>
@@ -1005,13 +1028,20 @@ void launch_bf16_m(unsigned grid, size_t lds, hipStream_t s, const float *q, con
 }
 
 template <typename T>
-void launch_query_k(int kernel, bool knn, unsigned grid, hipStream_t s, const float *q,
+void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_t s, const float *q,
                     const Grouping &G, const int4 *lists, const ModelView &Mo,
-                    const QueryConsts &C, const Outputs &O) {
+                    const QueryConsts &C, const Outputs &O, int slot) {
+    uint32_t *work = nullptr;
+    if (c->tune.eval_persistent > 0 && !knn) {
+        // 256 CUs x 4 SIMDs x the tuned number of wavefronts per SIMD
+        work = c->d_work + slot;
+        fill_u32(work, 0u, 1, s);
+        grid = std::min<unsigned>(grid, 1024u * unsigned(c->tune.eval_persistent));
+    }
     if (kernel == GPDF_KERNEL_MATERN32)
-        launch_query_m<T, GPDF_KERNEL_MATERN32>(knn, grid, s, q, G, lists, Mo, C, O);
+        launch_query_m<T, GPDF_KERNEL_MATERN32>(knn, grid, s, q, G, lists, Mo, C, O, work);
     else
-        launch_query_m<T, GPDF_KERNEL_SE>(knn, grid, s, q, G, lists, Mo, C, O);
+        launch_query_m<T, GPDF_KERNEL_SE>(knn, grid, s, q, G, lists, Mo, C, O, work);
 }
 
 }  // namespace
@@ -1175,7 +1205,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     Outputs O{dist, grad, var, aux, valid, c->d_refine, c->d_stat};
     if (c->p.precision == GPDF_PREC_FP64) {
         stage_begin(c, GPDF_MS_EVAL);
-        launch_query_k<double>(kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O);
+        launch_query_k<double>(c, kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O, 0);
         stage_end(c, GPDF_MS_EVAL);
     } else if (c->p.precision == GPDF_PREC_BF16) {
         // MFMA products in BF16; no FP64 re-evaluation (the error is the point)
@@ -1194,7 +1224,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         stage_end(c, GPDF_MS_EVAL);
     } else {
         stage_begin(c, GPDF_MS_EVAL);
-        launch_query_k<float>(kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O);
+        launch_query_k<float>(c, kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O, 0);
         stage_end(c, GPDF_MS_EVAL);
         // 3. queries whose FP32 estimate is too large: regroup by cell
         //    (counting sort of the records) and redo them in FP64
@@ -1214,7 +1244,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         const Grouping R{c->d_rchunk, c->d_rchunk_off + nc, c->d_rcnt, c->d_roff, c->d_rorder};
         Outputs O64 = O;
         O64.refine = nullptr;
-        launch_query_k<double>(kern, knn, grid, s, d_q, R, c->d_cell_list, Mo, C, O64);
+        launch_query_k<double>(c, kern, knn, grid, s, d_q, R, c->d_cell_list, Mo, C, O64, 1);
         stage_end(c, GPDF_MS_REFINE);
     }
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "query launch");

@@ -151,33 +151,47 @@ __device__ inline double kernel64(int kernel, double r, double l) {
 }
 
 constexpr int kMaxClusterN = 1024;
-constexpr int kBlockLdsN = 192;                          // packed triangle in LDS up to here
+constexpr int kBlockLdsN = 176;                          // packed triangle in LDS up to here
 constexpr int kBlockLdsElems = kBlockLdsN * (kBlockLdsN + 1) / 2;
 
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// one workgroup per cluster, n > 64: the lower triangle of A = K + s^2 I
-// packed by rows (in LDS up to n = 192, else in the FP64 workspace),
-// right-looking Cholesky, then the inverse W = L^{-1} in place, column by
-// column from the right: with L = [l 0; c L2], W = [1/l 0; -W2 c / l  W2]
-__global__ __launch_bounds__(kT) void k_train_clusters(
-    const int32_t *__restrict__ list, float4 *__restrict__ pts, const int32_t *__restrict__ coff,
-    const int64_t *__restrict__ aoff, const int64_t *__restrict__ woff, double *__restrict__ Aall,
-    double *__restrict__ W64all, float *__restrict__ W32all, double *__restrict__ alpha64,
-    uint8_t *__restrict__ pd, int kernel, double l, double s2, unsigned long long *__restrict__ stat) {
-    __shared__ double sA[kBlockLdsElems];
-    __shared__ double xs[kMaxClusterN];
-    __shared__ int s_ok;
-    const int c = list[blockIdx.x];
-    const int base = coff[c];
-    const int n = coff[c + 1] - base;
-    const int tid = threadIdx.x;
-    double *A = (n <= kBlockLdsN) ? sA : Aall + aoff[c];
-    const int tot = n * (n + 1) / 2;
+// One workgroup of T threads per cluster (n > 64).  The lower triangle of
+// A = K + s^2 I is packed by rows, in LDS up to n = 176 (124.6 KB), else in
+// the FP64 workspace.  Cholesky and the inverse W = L^{-1} run together in
+// place: after step k, columns 0..k of the triangle hold W (rows k+1.. as
+// partial sums R) and columns k+1.. the trailing part of A.  Step k:
+//   l = sqrt(A(k,k)), L(i,k) = A(i,k) / l for i > k (kept in LDS),
+//   row k of W  = R(k, 0..k-1) / l, W(k,k) = 1 / l,
+//   for i > k:  R(i,j) -= L(i,k) W(k,j)   (j < k),   W(i,k) = -L(i,k) / l,
+//               A(i,j) -= L(i,k) L(j,k)    (k < j <= i).
+// The elements of rows k+1..n-1 are contiguous in the packed triangle, so a
+// step is one range split evenly over the workgroup: two barriers per step,
+// consecutive threads on consecutive elements.  A pivot at or below
+// 1e-10 (1 + s^2) marks the cluster non positive definite.  alpha = W^T (W 1).
+__device__ __forceinline__ int tri_row(int p) {
+    int i = int((sqrtf(8.f * float(p) + 1.f) - 1.f) * 0.5f);
+    if ((i + 1) * (i + 2) / 2 <= p) ++i;
+    if (i * (i + 1) / 2 > p) --i;
+    return i;
+}
+
+// the body, inlined once with A in LDS and once with A in global memory, so
+// that every access compiles to LDS or global instructions (a pointer that
+// may be either would compile to flat accesses)
+template <int T>
+__device__ __forceinline__ void train_block_body(double *__restrict__ A, double *__restrict__ colm,
+                                                 double *__restrict__ wrow, int c, int base, int n,
+                                                 float4 *__restrict__ pts, const int64_t *__restrict__ woff,
+                                                 double *__restrict__ W64all, float *__restrict__ W32all,
+                                                 double *__restrict__ alpha64, uint8_t *__restrict__ pd, int kernel,
+                                                 double l, double s2, unsigned long long *__restrict__ stat) {
+    constexpr int kW = T / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // A = K + s^2 I (lower triangle)
-    for (int i = tid >> 1; i < n; i += kT / 2) {
+    for (int i = wv; i < n; i += kW) {
         const float4 pi = pts[base + i];
-        for (int j = tid & 1; j <= i; j += 2) {
+        for (int j = lane; j <= i; j += 64) {
             const float4 pj = pts[base + j];
             const double dx = double(pi.x) - double(pj.x), dy = double(pi.y) - double(pj.y),
                          dz = double(pi.z) - double(pj.z);
@@ -186,71 +200,50 @@ __global__ __launch_bounds__(kT) void k_train_clusters(
             A[tri(i, j)] = v;
         }
     }
-    // Cholesky, right-looking; a pivot at or below 1e-10 of the original
-    // diagonal 1 + s^2 marks the cluster non positive definite
     const double thr = 1e-10 * (1.0 + s2);
-    if (tid == 0) s_ok = 1;
+    const int end = n * (n + 1) / 2;
     for (int k = 0; k < n; ++k) {
         __syncthreads();
-        if (tid == 0) {
-            const double d = A[tri(k, k)];
-            if (!(d > thr)) s_ok = 0;
-            else A[tri(k, k)] = sqrt(d);
-        }
-        __syncthreads();
-        if (!s_ok) break;
-        const double lkk = A[tri(k, k)];
-        for (int i = k + 1 + tid; i < n; i += kT) A[tri(i, k)] /= lkk;
-        __syncthreads();
-        // trailing update, two threads per row (alternate columns)
-        for (int i = k + 1 + (tid >> 1); i < n; i += kT / 2) {
-            double *Ai = A + tri(i, 0);
-            const double lik = Ai[k];
-            for (int j = k + 1 + (tid & 1); j <= i; j += 2) Ai[j] -= lik * A[tri(j, k)];
-        }
-    }
-    __syncthreads();
-    if (!s_ok) {
-        for (int i = tid; i < n; i += kT) {
-            alpha64[base + i] = 0.0;
-            pts[base + i].w = 0.0f;
-        }
-        if (tid == 0) {
-            pd[c] = 0;
-            atomicAdd(&stat[ST_NONPD], 1ull);
-        }
-        return;
-    }
-    // in-place inverse, columns right to left
-    for (int j = n - 1; j >= 0; --j) {
-        if (tid == 0) A[tri(j, j)] = 1.0 / A[tri(j, j)];
-        for (int i = j + 1 + tid; i < n; i += kT) xs[i] = A[tri(i, j)];
-        __syncthreads();
-        const double wjj = A[tri(j, j)];
-        for (int i = j + 1 + tid; i < n; i += kT) {
-            const double *Wi = A + tri(i, 0);
-            double s0 = 0.0, s1 = 0.0, s2_ = 0.0, s3 = 0.0;
-            int m = j + 1;
-            for (; m + 3 <= i; m += 4) {
-                s0 += Wi[m] * xs[m]; s1 += Wi[m + 1] * xs[m + 1];
-                s2_ += Wi[m + 2] * xs[m + 2]; s3 += Wi[m + 3] * xs[m + 3];
+        const double d = A[tri(k, k)];
+        if (!(d > thr)) {
+            for (int i = tid; i < n; i += T) {
+                alpha64[base + i] = 0.0;
+                pts[base + i].w = 0.0f;
             }
-            for (; m <= i; ++m) s0 += Wi[m] * xs[m];
-            A[tri(i, j)] = -wjj * ((s0 + s1) + (s2_ + s3));
+            if (tid == 0) {
+                pd[c] = 0;
+                atomicAdd(&stat[ST_NONPD], 1ull);
+            }
+            return;
         }
+        const double inv = 1.0 / sqrt(d);
+        for (int i = k + 1 + tid; i < n; i += T) colm[i] = A[tri(i, k)] * inv;
+        for (int j = tid; j < k; j += T) wrow[j] = A[tri(k, j)] * inv;
         __syncthreads();
-    }
-    // y = W 1 (row sums), alpha = W^T y
-    for (int i = tid; i < n; i += kT) {
-        const double *Wi = A + tri(i, 0);
-        double sum = 0.0;
-        for (int j = 0; j <= i; ++j) sum += Wi[j];
-        xs[i] = sum;
+        for (int j = tid; j < k; j += T) A[tri(k, j)] = wrow[j];
+        if (tid == 0) A[tri(k, k)] = inv;
+        for (int p = tri(k + 1, 0) + tid; p < end; p += T) {
+            const int i = tri_row(p), j = p - i * (i + 1) / 2;
+            const double li = colm[i];
+            if (j < k) A[p] -= li * wrow[j];
+            else if (j == k) A[p] = -li * inv;
+            else A[p] -= li * colm[j];
+        }
     }
     __syncthreads();
-    for (int j = tid; j < n; j += kT) {
+    // y = W 1 (row sums), alpha = W^T y
+    for (int i = tid; i < n; i += T) {
+        const double *Wi = A + tri(i, 0);
+        double s0 = 0.0, s1 = 0.0;
+        int j = 0;
+        for (; j + 1 <= i; j += 2) { s0 += Wi[j]; s1 += Wi[j + 1]; }
+        if (j <= i) s0 += Wi[j];
+        colm[i] = s0 + s1;
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += T) {
         double a = 0.0;
-        for (int i = j; i < n; ++i) a += A[tri(i, j)] * xs[i];
+        for (int i = j; i < n; ++i) a += A[tri(i, j)] * colm[i];
         alpha64[base + j] = a;
         pts[base + j].w = float(a);
     }
@@ -260,7 +253,7 @@ __global__ __launch_bounds__(kT) void k_train_clusters(
     float *W32 = W32all + woff[c];
     double *W64 = W64all + woff[c];
     if (n <= kPanel) {
-        for (int idx = tid; idx < tot; idx += kT) {
+        for (int idx = tid; idx < end; idx += T) {
             W32[idx] = float(A[idx]);
             W64[idx] = A[idx];
         }
@@ -271,7 +264,7 @@ __global__ __launch_bounds__(kT) void k_train_clusters(
     for (int r = 0; r < nb; ++r) {
         const int64_t po = w32_panel_offset(n, r);
         const int ncol = min((r + 1) * kPanel, n);
-        for (int idx = tid; idx < ncol * kPanel; idx += kT) {
+        for (int idx = tid; idx < ncol * kPanel; idx += T) {
             const int j = idx / kPanel, rr = idx - j * kPanel;
             const int i = r * kPanel + rr;
             const double v = (i < n && j <= i) ? A[tri(i, j)] : 0.0;
@@ -280,6 +273,25 @@ __global__ __launch_bounds__(kT) void k_train_clusters(
         }
     }
     if (tid == 0) pd[c] = 1;
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_train_block(
+    const int32_t *__restrict__ list, float4 *__restrict__ pts, const int32_t *__restrict__ coff,
+    const int64_t *__restrict__ aoff, const int64_t *__restrict__ woff, double *__restrict__ Aall,
+    double *__restrict__ W64all, float *__restrict__ W32all, double *__restrict__ alpha64,
+    uint8_t *__restrict__ pd, int kernel, double l, double s2, unsigned long long *__restrict__ stat) {
+    __shared__ double sA[kBlockLdsElems];
+    __shared__ double colm[kMaxClusterN];
+    __shared__ double wrow[kMaxClusterN];
+    const int c = list[blockIdx.x];
+    const int base = coff[c];
+    const int n = coff[c + 1] - base;
+    if (n <= kBlockLdsN)
+        train_block_body<T>(sA, colm, wrow, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel, l, s2, stat);
+    else
+        train_block_body<T>(Aall + aoff[c], colm, wrow, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel, l,
+                            s2, stat);
 }
 
 // ---------------------------------------------------------------------------
@@ -633,11 +645,16 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n) {
         hipLaunchKernelGGL(k_train_wave, dim3(unsigned(n_wave)), dim3(64), 0, s, c->d_blist + n_tiny,
                            c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
                            c->p.kernel, l, s2, c->d_stat);
-    if (n_big)
-        hipLaunchKernelGGL(k_train_clusters, dim3(unsigned(n_big)), dim3(kT), 0, s,
-                           c->d_blist + n_tiny + n_wave, c->d_pts, c->d_coff, c->d_aoff, c->d_woff,
-                           c->d_A, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l, s2,
-                           c->d_stat);
+    if (n_big) {
+#define GPDF_TRAIN_BLOCK(T)                                                                              \
+    hipLaunchKernelGGL(k_train_block<T>, dim3(unsigned(n_big)), dim3(T), 0, s, c->d_blist + n_tiny + n_wave, \
+                       c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64,   \
+                       c->d_pd, c->p.kernel, l, s2, c->d_stat)
+        if (c->tune.train_threads == 512) GPDF_TRAIN_BLOCK(512);
+        else if (c->tune.train_threads == 1024) GPDF_TRAIN_BLOCK(1024);
+        else GPDF_TRAIN_BLOCK(256);
+#undef GPDF_TRAIN_BLOCK
+    }
     // 6. cluster hash
     fill_u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1, s);
     HashView hv{c->d_chash, c->chash_mask};
