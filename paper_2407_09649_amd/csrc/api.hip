@@ -38,7 +38,7 @@ void release(gpdf_ctx *c) {
                     c->d_tmp_dist, c->d_tmp_var, c->d_tmp_grad, c->d_tmp_valid, c->d_tset,
                     c->d_tkeys, c->d_tpts, c->d_gkey, c->d_gD, c->d_gV, c->d_gstamp, c->d_offs,
                     c->d_mlp_w, c->d_mlp_m, c->d_mlp_v, c->d_mlp_g, c->d_mlp_rec, c->d_mlp_pack,
-                    c->d_mlp_norm, c->d_mlp_loss, c->d_mlp_mom, c->d_stat, c->d_blist, c->d_tile_cnt, c->d_tile_off, c->d_bfM, c->d_bfoff, c->d_work};
+                    c->d_mlp_norm, c->d_mlp_loss, c->d_mlp_mom, c->d_stat, c->d_blist, c->d_tile_cnt, c->d_tile_off, c->d_bfM, c->d_bfoff, c->d_work, c->d_cnt, c->d_wsz, c->d_asz, c->d_wo32, c->d_ao32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
@@ -133,9 +133,11 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
     bool ok = dalloc(c->d_key, P + 1, e) && dalloc(c->d_key2, P + 1, e) && dalloc(c->d_val, P + 1, e) &&
               dalloc(c->d_val2, P + 1, e) && dalloc(c->d_flag, P + 1, e) &&
               dalloc(c->d_scan, scan_n, e) && dalloc(c->d_hist, 256 * nbP + 1, e) &&
-              dalloc(c->d_part, scan_n / 4096 + 64, e) && dalloc(c->d_red, 8, e) && dalloc(c->d_work, 8, e) &&
+              dalloc(c->d_part, scan_n / 4096 + 64, e) && dalloc(c->d_red, 8, e) && dalloc(c->d_work, 8, e) && dalloc(c->d_cnt, kCnt, e) &&
+              dalloc(c->d_wsz, C + 1, e) && dalloc(c->d_asz, C + 1, e) && dalloc(c->d_wo32, C + 1, e) &&
+              dalloc(c->d_ao32, C + 1, e) &&
               dalloc(c->d_pts, P, e) && dalloc(c->d_alpha64, P, e) && dalloc(c->d_ckey, C + 1, e) &&
-              dalloc(c->d_coff, C + 1, e) && dalloc(c->d_pd, C + 1, e) && dalloc(c->d_woff, C, e) && dalloc(c->d_blist, C, e) &&
+              dalloc(c->d_coff, C + 1, e) && dalloc(c->d_pd, C + 1, e) && dalloc(c->d_woff, C, e) && dalloc(c->d_blist, 3 * C, e) &&
               dalloc(c->d_aoff, C, e) && dalloc(c->d_W32, c->cap_w, e) &&
               dalloc(c->d_W64, c->cap_w, e) &&
               dalloc(c->d_A, c->cap_a, e) &&

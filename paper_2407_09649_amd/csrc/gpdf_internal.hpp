@@ -170,6 +170,46 @@ __device__ __forceinline__ void for_occupied_in_tile(const unsigned long long *_
 }
 
 // ---------------------------------------------------------------------------
+// counts that stay on the device (u32), so that a whole frame can run
+// without a host round trip
+// ---------------------------------------------------------------------------
+enum DevCount : int {
+    CNT_IN = 0,   // points of the frame (graph input)
+    CNT_VALID,    // finite points
+    CNT_PTS,      // training points (unique voxels or valid points)
+    CNT_CL,       // clusters
+    CNT_TINY,     // size buckets: n <= 8, n <= 64, larger
+    CNT_WAVE,
+    CNT_BIG,
+    CNT_WTOT,     // factor elements
+    CNT_ATOT,     // FP64 workspace elements
+    CNT_MAXN,     // largest cluster
+    CNT_CELLS,    // query cells
+    CNT_CHUNKS,   // query chunks
+    CNT_RCHUNKS,  // re-evaluation chunks
+    CNT_TEST,     // test voxels (clamped to max_queries)
+    CNT_FRAME,    // frame stamp (graph input)
+    CNT_M,        // query count read by the kernels (graph)
+    kCnt
+};
+
+// adds pred ? 1 : 0 per lane to a u32 counter; returns the lane's slot
+__device__ inline uint32_t wave_count32(uint32_t *ctr, bool pred) {
+    const uint64_t mb = __ballot(pred);
+    if (!mb) return 0;
+    const int leader = __ffsll((long long)mb) - 1;
+    uint32_t base = 0;
+    if ((threadIdx.x & 63) == leader) base = atomicAdd(ctr, uint32_t(__popcll(mb)));
+    base = __shfl(base, leader, 64);
+    return base + uint32_t(__popcll(mb & lanes_below()));
+}
+
+// a count bounded by n, read on the device when dn is given
+__device__ __forceinline__ int64_t dev_count(int64_t n, const uint32_t *dn) {
+    return dn ? (int64_t(*dn) < n ? int64_t(*dn) : n) : n;
+}
+
+// ---------------------------------------------------------------------------
 // device status block (uint64 counters)
 // ---------------------------------------------------------------------------
 enum Stat : int {
@@ -190,6 +230,8 @@ enum Stat : int {
     ST_PAIRS,        // (query, cluster) pairs of the last evaluation pass
     ST_POINTS,       // kernel evaluations (sum of n over pairs)
     ST_TRI,          // variance multiply-adds (sum of n (n + 1) / 2 over pairs)
+    ST_CAPACITY,     // a capacity was exceeded on the device (clusters, cluster
+                     // size, factor storage, test voxels)
     ST_COUNT
 };
 
@@ -228,7 +270,7 @@ struct Model {
     int64_t nclusters = 0, npoints = 0, nonpd = 0, skipped = 0, max_n = 0;
     bool trained = false;
     bool bf16_ready = false;   // BF16 copies of [W; alpha] built for this model
-    std::vector<int32_t> h_n;  // cluster sizes (host copy)
+    bool host_counts = false;  // counts below were read back (eager calls)
 };
 
 }  // namespace gpdf
@@ -256,6 +298,9 @@ struct gpdf_ctx {
     uint32_t *d_part = nullptr;                    // scan partials
     uint64_t *d_red = nullptr;                     // small reductions
     uint32_t *d_work = nullptr;                    // work counters of persistent launches [8]
+    uint32_t *d_cnt = nullptr;                     // device counts [kCnt]
+    uint32_t *d_wsz = nullptr, *d_asz = nullptr;   // per-cluster factor / workspace sizes
+    uint32_t *d_wo32 = nullptr, *d_ao32 = nullptr; // their exclusive scans
     float4 *d_pts = nullptr;                       // training points (x, y, z, alpha32)
     double *d_alpha64 = nullptr;                   // alpha in FP64
     uint64_t *d_ckey = nullptr;                    // cluster keys [max_clusters]
@@ -272,8 +317,6 @@ struct gpdf_ctx {
     std::vector<int64_t> h_bfoff;
     double *d_A = nullptr;                         // FP64 workspace: packed A, L, then L^{-1} (n > 192)
     int64_t cap_w = 0, cap_a = 0;
-    std::vector<int64_t> h_o32, h_oa;       // factor offsets (host)
-    std::vector<int32_t> h_blist;                  // clusters ordered by size bucket
     int32_t *d_blist = nullptr;
     unsigned long long *d_chash = nullptr;         // cluster hash keys
     int32_t *d_chash_val = nullptr;
@@ -355,8 +398,12 @@ gpdf_status fail(gpdf_ctx *c, gpdf_status s, const std::string &msg);
 gpdf_status hip_fail(gpdf_ctx *c, hipError_t e, const char *what);
 
 // scans and sorting (sort.hip)
+// out[i] = sum_{j < i} in[j] for i <= n (out has n + 1 entries).  With dn,
+// the count is min(n, *dn) read on the device (n is then a bound that sizes
+// the grid); total_out, when given, receives the total.  partials needs
+// ceil(n / 4096) + 1 entries.
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
-                        hipStream_t s);
+                        hipStream_t s, const uint32_t *dn = nullptr, uint32_t *total_out = nullptr);
 void radix_sort_pairs(uint64_t *&keys, uint64_t *&keys_alt, uint32_t *&vals, uint32_t *&vals_alt,
                       int64_t n, uint64_t varying_bits, uint32_t *hist, uint32_t *partials,
                       hipStream_t s);
@@ -368,7 +415,7 @@ void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 
 // stages (train.hip, query.hip, fuse.hip, mlp.hip)
-gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n);
+gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn = nullptr);
 gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin, float *dist,
                   float *grad, float *var, uint8_t *valid, float *aux, int32_t correct);
 gpdf_status fuse(gpdf_ctx *c, const float *origin);

@@ -1089,15 +1089,19 @@ gpdf_status build_bf16(gpdf_ctx *c) {
     hipStream_t s = c->stream;
     hipError_t e;
     const int64_t ncl = M.nclusters;
+    std::vector<int32_t> coff(size_t(ncl) + 1);
+    if ((e = hipMemcpyAsync(coff.data(), c->d_coff, sizeof(int32_t) * (size_t(ncl) + 1), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(c, e, "bf16: read offsets");
     std::vector<int64_t> &off = c->h_bfoff;
     off.assign(size_t(ncl), 0);
     int64_t tot = 0;
     for (int64_t i = 0; i < ncl; ++i) {
-        const int n = M.h_n[size_t(i)];
+        const int n = coff[size_t(i) + 1] - coff[size_t(i)];
         off[size_t(i)] = tot;
         if (n <= kBfMaxN) tot += int64_t(bf_rows(n)) * bf_cols(n);
     }
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "bf16: sync");
     if (tot > c->cap_bfM) {
         if (c->d_bfM && (e = hipFree(c->d_bfM)) != hipSuccess) return hip_fail(c, e, "bf16: free");
         c->d_bfM = nullptr;

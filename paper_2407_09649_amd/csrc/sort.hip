@@ -42,9 +42,16 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds_wave, 
     return wave_off + inc - v;
 }
 
-__global__ void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
+// element count: the bound n, or the device count *dn when given (never
+// above the bound)
+__device__ __forceinline__ int64_t scan_count(int64_t n, const uint32_t *dn) {
+    return dn ? min(n, int64_t(*dn)) : n;
+}
+
+__global__ void k_scan_reduce(const uint32_t *__restrict__ in, int64_t nb_, const uint32_t *__restrict__ dn,
                               uint32_t *__restrict__ partials) {
     __shared__ uint32_t lds[kScanThreads / 64];
+    const int64_t n = scan_count(nb_, dn);
     const int64_t base = int64_t(blockIdx.x) * kScanTile;
     uint32_t s = 0;
 #pragma unroll
@@ -78,8 +85,10 @@ __global__ void k_scan_partials(uint32_t *__restrict__ partials, int64_t nb) {
 
 // each thread owns kScanItems consecutive elements
 __global__ void k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
-                            int64_t n, const uint32_t *__restrict__ partials) {
+                            int64_t nb_, const uint32_t *__restrict__ dn, const uint32_t *__restrict__ partials,
+                            uint32_t *__restrict__ total_out) {
     __shared__ uint32_t lds[kScanThreads / 64];
+    const int64_t n = scan_count(nb_, dn);
     const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
     uint32_t v[kScanItems];
     uint32_t s = 0;
@@ -100,7 +109,10 @@ __global__ void k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restric
     // the total lands one past the end: written by the thread whose range
     // holds index n, or by the last thread when n fills the final tile
     const bool last = blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1;
-    if ((base <= n && n < base + kScanItems) || (last && n == base + kScanItems)) out[n] = run;
+    if ((base <= n && n < base + kScanItems) || (last && n == base + kScanItems)) {
+        out[n] = run;
+        if (total_out) *total_out = run;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -185,16 +197,14 @@ inline unsigned grid_for(int64_t n, int threads) {
 
 }  // namespace
 
-// out[i] = sum_{j < i} in[j] for i <= n (out has n + 1 entries).
-// partials needs ceil(n / 4096) + 1 entries.
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
-                        hipStream_t s) {
+                        hipStream_t s, const uint32_t *dn, uint32_t *total_out) {
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(unsigned(nb)), dim3(kScanThreads), 0, s, in, n, partials);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(unsigned(nb)), dim3(kScanThreads), 0, s, in, n, dn, partials);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s, partials, nb);
-    hipLaunchKernelGGL(k_scan_down, dim3(unsigned(nb)), dim3(kScanThreads), 0, s, in, out, n,
-                       partials);
+    hipLaunchKernelGGL(k_scan_down, dim3(unsigned(nb)), dim3(kScanThreads), 0, s, in, out, n, dn,
+                       partials, total_out);
 }
 
 // Stable sort by key over the 8-bit digits that contain varying bits; the

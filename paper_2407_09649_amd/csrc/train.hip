@@ -23,11 +23,18 @@ inline unsigned blocks_for(int64_t n, int t = kT) {
 
 // voxel mode: composite key = (cluster cell: 3 x 18-bit offset binary) << 9 | local voxel
 // raw mode: key = packed cell of size h_c, value = input index
-__global__ void k_point_keys(const float *__restrict__ xyz, int64_t n, int voxel_mode, double h,
-                             uint64_t *__restrict__ key, uint32_t *__restrict__ val,
+// points at or past the count (dn, a device count bounded by n) are absent
+__global__ void k_point_keys(const float *__restrict__ xyz, int64_t n, const uint32_t *__restrict__ dn,
+                             int voxel_mode, double h, uint64_t *__restrict__ key, uint32_t *__restrict__ val,
                              uint32_t *__restrict__ flag, unsigned long long *__restrict__ stat) {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (i >= dev_count(n, dn)) {
+        flag[i] = 0;
+        key[i] = kNoKey;
+        val[i] = uint32_t(i);
+        return;
+    }
     int64_t c[3];
     bool ok = cell_coord(xyz[3 * i], h, c[0]) && cell_coord(xyz[3 * i + 1], h, c[1]) &&
               cell_coord(xyz[3 * i + 2], h, c[2]);
@@ -65,27 +72,24 @@ __global__ void k_compact_pairs(const uint64_t *__restrict__ kin, const uint32_t
     vout[pos[i]] = vin[i];
 }
 
-// OR over (key ^ key[0]): the bits that vary among the valid keys
-__global__ void k_varying_bits(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
-                               unsigned long long *__restrict__ out) {
-    const uint32_t n = *cnt;
-    uint64_t acc = 0;
-    if (n > 0) {
-        const uint64_t k0 = key[0];
-        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-             i += int64_t(gridDim.x) * blockDim.x)
-            acc |= key[i] ^ k0;
+// keys past the valid count sort last
+__global__ void k_pad_keys(uint64_t *__restrict__ key, uint32_t *__restrict__ val, int64_t n,
+                           const uint32_t *__restrict__ dvalid) {
+    const int64_t nv = dev_count(n, dvalid);
+    for (int64_t i = nv + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        key[i] = kNoKey;
+        val[i] = 0;
     }
-    for (int o = 32; o > 0; o >>= 1) acc |= __shfl_xor(acc, o, 64);
-    if ((threadIdx.x & 63) == 0 && acc) atomicOr(out, (unsigned long long)acc);
 }
 
-// flag[i] = 1 where (key >> sh) starts a new run
-__global__ void k_run_flags(const uint64_t *__restrict__ key, int64_t n, int sh,
+// flag[i] = 1 where (key >> sh) starts a new run among the first dn keys;
+// 0 up to the bound n
+__global__ void k_run_flags(const uint64_t *__restrict__ key, int64_t n, const uint32_t *__restrict__ dn, int sh,
                             uint32_t *__restrict__ flag) {
+    const int64_t na = dev_count(n, dn);
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x)
-        flag[i] = (i == 0 || (key[i] >> sh) != (key[i - 1] >> sh)) ? 1u : 0u;
+        flag[i] = (i < na && (i == 0 || (key[i] >> sh) != (key[i - 1] >> sh))) ? 1u : 0u;
 }
 
 __global__ void k_compact_unique(const uint64_t *__restrict__ key, int64_t n,
@@ -99,11 +103,13 @@ __global__ void k_compact_unique(const uint64_t *__restrict__ key, int64_t n,
 // clusters: offsets, keys and training points.  voxel_mode: keys are the
 // unique composite keys; raw mode: keys are cell keys, vals input indices.
 __global__ void k_clusters(const uint64_t *__restrict__ key, const uint32_t *__restrict__ val,
-                           int64_t n, const uint32_t *__restrict__ flag,
+                           int64_t nbound, const uint32_t *__restrict__ dn, const uint32_t *__restrict__ flag,
                            const uint32_t *__restrict__ pos, int voxel_mode, double hv,
                            const float *__restrict__ xyz, float4 *__restrict__ pts,
                            int32_t *__restrict__ coff, uint64_t *__restrict__ ckey,
-                           int64_t cap, uint32_t *__restrict__ ncl_out) {
+                           int64_t cap, uint32_t *__restrict__ ncl_out,
+                           unsigned long long *__restrict__ stat) {
+    const int64_t n = dev_count(nbound, dn);
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x) {
         const uint64_t k = key[i];
@@ -135,7 +141,8 @@ __global__ void k_clusters(const uint64_t *__restrict__ key, const uint32_t *__r
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const uint32_t ncl = pos[n];
         if (int64_t(ncl) <= cap) coff[ncl] = int32_t(n);
-        *ncl_out = ncl;
+        *ncl_out = uint32_t(min(int64_t(ncl), cap));
+        if (int64_t(ncl) > cap) atomicAdd(&stat[ST_CAPACITY], 1ull);
     }
 }
 
@@ -275,23 +282,36 @@ __device__ __forceinline__ void train_block_body(double *__restrict__ A, double 
     if (tid == 0) pd[c] = 1;
 }
 
+// persistent: each workgroup takes the next cluster of the bucket from the
+// counter *work (zero at launch) until none is left
 template <int T>
 __global__ __launch_bounds__(T) void k_train_block(
-    const int32_t *__restrict__ list, float4 *__restrict__ pts, const int32_t *__restrict__ coff,
+    const int32_t *__restrict__ list, const uint32_t *__restrict__ dcnt, uint32_t *__restrict__ work,
+    float4 *__restrict__ pts, const int32_t *__restrict__ coff,
     const int64_t *__restrict__ aoff, const int64_t *__restrict__ woff, double *__restrict__ Aall,
     double *__restrict__ W64all, float *__restrict__ W32all, double *__restrict__ alpha64,
     uint8_t *__restrict__ pd, int kernel, double l, double s2, unsigned long long *__restrict__ stat) {
     __shared__ double sA[kBlockLdsElems];
     __shared__ double colm[kMaxClusterN];
     __shared__ double wrow[kMaxClusterN];
-    const int c = list[blockIdx.x];
-    const int base = coff[c];
-    const int n = coff[c + 1] - base;
-    if (n <= kBlockLdsN)
-        train_block_body<T>(sA, colm, wrow, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel, l, s2, stat);
-    else
-        train_block_body<T>(Aall + aoff[c], colm, wrow, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel, l,
-                            s2, stat);
+    __shared__ uint32_t item;
+    const uint32_t cnt = *dcnt;
+    while (true) {
+        __syncthreads();  // the previous cluster is done with the LDS and item
+        if (threadIdx.x == 0) item = atomicAdd(work, 1u);
+        __syncthreads();
+        const uint32_t b = item;
+        if (b >= cnt) break;
+        const int c = list[b];
+        const int base = coff[c];
+        const int n = coff[c + 1] - base;
+        if (n <= kBlockLdsN)
+            train_block_body<T>(sA, colm, wrow, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel, l, s2,
+                                stat);
+        else
+            train_block_body<T>(Aall + aoff[c], colm, wrow, c, base, n, pts, woff, W64all, W32all, alpha64, pd,
+                                kernel, l, s2, stat);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -308,12 +328,12 @@ __device__ inline void put_w(float *W32, double *W64, int64_t off, int idx, doub
 }
 
 __global__ __launch_bounds__(64) void k_train_tiny(
-    const int32_t *__restrict__ list, int64_t cnt, float4 *__restrict__ pts,
+    const int32_t *__restrict__ list, const uint32_t *__restrict__ dcnt, float4 *__restrict__ pts,
     const int32_t *__restrict__ coff, const int64_t *__restrict__ woff, double *__restrict__ W64all,
     float *__restrict__ W32all, double *__restrict__ alpha64, uint8_t *__restrict__ pd, int kernel,
     double l, double s2, unsigned long long *__restrict__ stat) {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= cnt) return;
+    if (t >= int64_t(*dcnt)) return;
     const int c = list[t];
     const int base = coff[c];
     const int n = coff[c + 1] - base;
@@ -407,7 +427,8 @@ __global__ __launch_bounds__(64) void k_train_tiny(
 // (row stride 65 doubles: column reads by different lanes hit different
 // banks); W = L^{-1} kept by packed columns, lane j owning column j
 __global__ __launch_bounds__(64) void k_train_wave(
-    const int32_t *__restrict__ list, float4 *__restrict__ pts, const int32_t *__restrict__ coff,
+    const int32_t *__restrict__ list, const uint32_t *__restrict__ dcnt, float4 *__restrict__ pts,
+    const int32_t *__restrict__ coff,
     const int64_t *__restrict__ woff, double *__restrict__ W64all, float *__restrict__ W32all,
     double *__restrict__ alpha64, uint8_t *__restrict__ pd, int kernel, double l, double s2,
     unsigned long long *__restrict__ stat) {
@@ -416,10 +437,14 @@ __global__ __launch_bounds__(64) void k_train_wave(
     __shared__ double A[kWaveN * S];
     __shared__ double Wc[kWaveN * (kWaveN + 1) / 2];
     __shared__ double sy[kWaveN];
-    const int c = list[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int cnt = int(*dcnt);
+    // persistent: workgroup b takes clusters b, b + gridDim.x, ...
+    for (int b = blockIdx.x; b < cnt; b += gridDim.x) {
+    __syncthreads();  // the previous cluster is done with the LDS
+    const int c = list[b];
     const int base = coff[c];
     const int n = coff[c + 1] - base;
-    const int lane = threadIdx.x;
     if (lane < n) {
         const float4 p = pts[base + lane];
         sp[0][lane] = p.x; sp[1][lane] = p.y; sp[2][lane] = p.z;
@@ -459,7 +484,7 @@ __global__ __launch_bounds__(64) void k_train_wave(
     if (!ok) {
         if (lane < n) { alpha64[base + lane] = 0.0; pts[base + lane].w = 0.0f; }
         if (lane == 0) { pd[c] = 0; atomicAdd(&stat[ST_NONPD], 1ull); }
-        return;
+        continue;
     }
     __syncthreads();
     // column j of W: W(j, j) = 1 / L(j, j), W(i, j) = -sum_{m=j}^{i-1} L(i, m) W(m, j) / L(i, i)
@@ -516,12 +541,67 @@ __global__ __launch_bounds__(64) void k_train_wave(
         }
     }
     if (lane == 0) pd[c] = 1;
+    }
 }
 
-__global__ void k_chash_insert(const uint64_t *__restrict__ ckey, int64_t ncl, HashView h,
-                               int32_t *__restrict__ hval, unsigned long long *__restrict__ stat) {
+// per-cluster storage: factor elements in the query layout and, above the
+// LDS limit of the workgroup trainer, the packed FP64 workspace
+__global__ void k_cluster_sizes(const int32_t *__restrict__ coff, int64_t nbound, const uint32_t *__restrict__ dcl,
+                                uint32_t *__restrict__ wsz, uint32_t *__restrict__ asz, int max_cp,
+                                uint32_t *__restrict__ maxn) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= dev_count(nbound, dcl)) return;
+    const int n = coff[c + 1] - coff[c];
+    const bool ok = n <= max_cp && n <= kMaxClusterN;
+    wsz[c] = ok ? uint32_t(w32_size(n)) : 0u;
+    asz[c] = (ok && n > kBlockLdsN) ? uint32_t(n * (n + 1) / 2) : 0u;
+    atomicMax(maxn, uint32_t(n));
+}
+
+// offsets and size buckets: n <= 8 to list[0..], n <= 64 to list[C..],
+// larger to list[2C..]; clusters that exceed a capacity are not trained
+// (pd = 0) and counted
+__global__ void k_cluster_plan(const int32_t *__restrict__ coff, int64_t nbound, const uint32_t *__restrict__ dcl,
+                               const uint32_t *__restrict__ wsz, const uint32_t *__restrict__ asz,
+                               const uint32_t *__restrict__ wo, const uint32_t *__restrict__ ao, int64_t cap_w,
+                               int64_t cap_a, int max_cp, int64_t *__restrict__ woff, int64_t *__restrict__ aoff,
+                               int32_t *__restrict__ list, int64_t C, uint32_t *__restrict__ cnt,
+                               uint8_t *__restrict__ pd, unsigned long long *__restrict__ stat) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool in = c < dev_count(nbound, dcl);
+    int n = 0;
+    bool ok = false;
+    if (in) {
+        n = coff[c + 1] - coff[c];
+        ok = n <= max_cp && n <= kMaxClusterN && int64_t(wo[c]) + wsz[c] <= cap_w &&
+             int64_t(ao[c]) + asz[c] <= cap_a;
+        woff[c] = wo[c];
+        aoff[c] = ao[c];
+        if (!ok) {
+            pd[c] = 0;
+            atomicAdd(&stat[ST_CAPACITY], 1ull);
+        }
+    }
+    const bool tiny = in && ok && n <= kTinyN;
+    const bool wave = in && ok && n > kTinyN && n <= kWaveN;
+    const bool big = in && ok && n > kWaveN;
+    const uint32_t rt = wave_count32(&cnt[CNT_TINY], tiny);
+    const uint32_t rw = wave_count32(&cnt[CNT_WAVE], wave);
+    const uint32_t rb = wave_count32(&cnt[CNT_BIG], big);
+    if (tiny) list[rt] = int32_t(c);
+    if (wave) list[C + rw] = int32_t(c);
+    if (big) list[2 * C + rb] = int32_t(c);
+}
+
+__global__ void k_copy_count(uint32_t *__restrict__ cnt, int dst, int src) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) cnt[dst] = cnt[src];
+}
+
+__global__ void k_chash_insert(const uint64_t *__restrict__ ckey, int64_t nbound, const uint32_t *__restrict__ dn,
+                               HashView h, int32_t *__restrict__ hval,
+                               unsigned long long *__restrict__ stat) {
     int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= ncl) return;
+    if (c >= dev_count(nbound, dn)) return;
     bool ins;
     int64_t s = hash_insert(h, ckey[c], &ins);
     if (s < 0) {
@@ -533,138 +613,110 @@ __global__ void k_chash_insert(const uint64_t *__restrict__ ckey, int64_t ncl, H
 
 }  // namespace
 
-gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n) {
+// Training of one frame.  Every count stays on the device (DevCount):
+// grids are sized by the number of input points n and the capacities.  With
+// dn (a device count of input points, at most n) nothing is read back, so the
+// sequence can be captured in a graph; otherwise the counts and the
+// capacity counter are read back once at the end.
+gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn) {
     hipStream_t s = c->stream;
     Model &M = c->model;
+    const bool eager = dn == nullptr;
     if (n < 0 || n > c->p.max_points)
         return fail(c, GPDF_E_CAPACITY, "train: n exceeds max_points");
     M = Model();
     M.trained = true;
-    if (n == 0) return GPDF_OK;
+    uint32_t *cnt = c->d_cnt;
+    fill_u32(cnt + CNT_VALID, 0u, CNT_MAXN - CNT_VALID + 1, s);
+    fill_u64(c->d_stat + ST_CAPACITY, 0ull, 1, s);
+    fill_u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1, s);
+    if (n == 0) {
+        M.host_counts = true;
+        return GPDF_OK;
+    }
     const bool vox = c->p.voxel_size > 0.0;
     const double h = vox ? c->p.voxel_size : c->p.cluster_size;
+    const int64_t C = std::min<int64_t>(n, c->p.max_clusters);  // bound of the cluster count
     hipError_t e;
-    // 1. keys of valid points, compacted in input order
-    hipLaunchKernelGGL(k_point_keys, dim3(blocks_for(n)), dim3(kT), 0, s, d_xyz, n, vox ? 1 : 0, h,
+    // 1. keys of the finite points, compacted in input order; the rest sorts last
+    hipLaunchKernelGGL(k_point_keys, dim3(blocks_for(n)), dim3(kT), 0, s, d_xyz, n, dn, vox ? 1 : 0, h,
                        c->d_key, c->d_val, c->d_flag, c->d_stat);
-    exclusive_scan_u32(c->d_flag, c->d_scan, n, c->d_part, s);
+    exclusive_scan_u32(c->d_flag, c->d_scan, n, c->d_part, s, nullptr, cnt + CNT_VALID);
     hipLaunchKernelGGL(k_compact_pairs, dim3(blocks_for(n)), dim3(kT), 0, s, c->d_key, c->d_val,
                        c->d_flag, c->d_scan, n, c->d_key2, c->d_val2);
-    fill_u64(reinterpret_cast<unsigned long long *>(c->d_red), 0ull, 1, s);
-    hipLaunchKernelGGL(k_varying_bits, dim3(256), dim3(kT), 0, s, c->d_key2, c->d_scan + n,
-                       (unsigned long long *)c->d_red);
-    uint32_t nvalid = 0;
-    uint64_t vbits = 0;
-    if ((e = hipMemcpyAsync(&nvalid, c->d_scan + n, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(&vbits, c->d_red, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_fail(c, e, "train: read counts");
-    M.skipped = n - int64_t(nvalid);
-    if (nvalid == 0) return GPDF_OK;
-    // 2. stable sort by key
+    const unsigned g = std::min<unsigned>(blocks_for(n), 4096);
+    hipLaunchKernelGGL(k_pad_keys, dim3(g), dim3(kT), 0, s, c->d_key2, c->d_val2, n, cnt + CNT_VALID);
+    // 2. stable sort by key over all eight digits
     uint64_t *k = c->d_key2, *ka = c->d_key;
     uint32_t *v = c->d_val2, *va = c->d_val;
-    radix_sort_pairs(k, ka, v, va, nvalid, vbits, c->d_hist, c->d_part, s);
+    radix_sort_pairs(k, ka, v, va, n, ~uint64_t(0), c->d_hist, c->d_part, s);
     // 3. unique voxels (voxel mode) and cluster runs
     uint64_t *keys = k;
-    const unsigned g = std::min<unsigned>(blocks_for(nvalid), 4096);
-    uint32_t npts = nvalid;
     if (vox) {
-        hipLaunchKernelGGL(k_run_flags, dim3(g), dim3(kT), 0, s, k, int64_t(nvalid), 0, c->d_flag);
-        exclusive_scan_u32(c->d_flag, c->d_scan, nvalid, c->d_part, s);
-        hipLaunchKernelGGL(k_compact_unique, dim3(g), dim3(kT), 0, s, k, int64_t(nvalid), c->d_flag,
-                           c->d_scan, ka);
+        hipLaunchKernelGGL(k_run_flags, dim3(g), dim3(kT), 0, s, k, n, cnt + CNT_VALID, 0, c->d_flag);
+        exclusive_scan_u32(c->d_flag, c->d_scan, n, c->d_part, s, nullptr, cnt + CNT_PTS);
+        hipLaunchKernelGGL(k_compact_unique, dim3(g), dim3(kT), 0, s, k, n, c->d_flag, c->d_scan, ka);
         keys = ka;
-        if ((e = hipMemcpyAsync(&npts, c->d_scan + nvalid, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-            return hip_fail(c, e, "train: read voxel count");
-        hipLaunchKernelGGL(k_run_flags, dim3(g), dim3(kT), 0, s, keys, int64_t(npts), 9, c->d_flag);
+        hipLaunchKernelGGL(k_run_flags, dim3(g), dim3(kT), 0, s, keys, n, cnt + CNT_PTS, 9, c->d_flag);
     } else {
-        hipLaunchKernelGGL(k_run_flags, dim3(g), dim3(kT), 0, s, keys, int64_t(npts), 0, c->d_flag);
+        hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, s, cnt, int(CNT_PTS), int(CNT_VALID));
+        hipLaunchKernelGGL(k_run_flags, dim3(g), dim3(kT), 0, s, keys, n, cnt + CNT_VALID, 0, c->d_flag);
     }
-    exclusive_scan_u32(c->d_flag, c->d_scan, npts, c->d_part, s);
-    uint32_t *d_ncl = reinterpret_cast<uint32_t *>(c->d_red) + 2;
-    hipLaunchKernelGGL(k_clusters, dim3(g), dim3(kT), 0, s, keys, v, int64_t(npts), c->d_flag,
-                       c->d_scan, vox ? 1 : 0, c->p.voxel_size, d_xyz, c->d_pts, c->d_coff,
-                       c->d_ckey, c->p.max_clusters, d_ncl);
-    uint32_t ncl = 0;
-    if ((e = hipMemcpyAsync(&ncl, d_ncl, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_fail(c, e, "train: read cluster count");
-    if (int64_t(ncl) > c->p.max_clusters) {
-        M.trained = false;
-        return fail(c, GPDF_E_CAPACITY, "train: cluster count exceeds max_clusters");
-    }
-    // 4. factor storage offsets (host)
-    std::vector<int32_t> off(ncl + 1);
-    if ((e = hipMemcpyAsync(off.data(), c->d_coff, sizeof(int32_t) * (ncl + 1), hipMemcpyDeviceToHost,
-                            s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_fail(c, e, "train: read offsets");
-    // kept in the context: the uploads below read them asynchronously
-    std::vector<int64_t> &o32 = c->h_o32, &oa = c->h_oa;
-    o32.assign(ncl, 0); oa.assign(ncl, 0);
-    int64_t s32 = 0, sa = 0, maxn = 0;
-    M.h_n.resize(ncl);
-    for (uint32_t i = 0; i < ncl; ++i) {
-        const int64_t nc = off[i + 1] - off[i];
-        M.h_n[i] = int32_t(nc);
-        maxn = std::max(maxn, nc);
-        o32[i] = s32; s32 += w32_size(nc);
-        oa[i] = sa; if (nc > kBlockLdsN) sa += nc * (nc + 1) / 2;
-    }
-    if (maxn > c->p.max_cluster_points || maxn > kMaxClusterN) {
-        M.trained = false;
-        return fail(c, GPDF_E_CAPACITY, "train: a cluster exceeds max_cluster_points");
-    }
-    if (s32 > c->cap_w || sa > c->cap_a) {
-        M.trained = false;
-        return fail(c, GPDF_E_CAPACITY, "train: factor storage exceeds max_factor_elems");
-    }
-    if ((e = hipMemcpyAsync(c->d_woff, o32.data(), 8 * ncl, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(c->d_aoff, oa.data(), 8 * ncl, hipMemcpyHostToDevice, s)) != hipSuccess)
-        return hip_fail(c, e, "train: upload offsets");
-    // 5. FP64 training, bucketed by cluster size
+    exclusive_scan_u32(c->d_flag, c->d_scan, n, c->d_part, s);
+    hipLaunchKernelGGL(k_clusters, dim3(g), dim3(kT), 0, s, keys, v, n, cnt + CNT_PTS, c->d_flag, c->d_scan,
+                       vox ? 1 : 0, c->p.voxel_size, d_xyz, c->d_pts, c->d_coff, c->d_ckey, c->p.max_clusters,
+                       cnt + CNT_CL, c->d_stat);
+    // 4. factor storage (scans of the per-cluster sizes) and size buckets
+    hipLaunchKernelGGL(k_cluster_sizes, dim3(blocks_for(C)), dim3(kT), 0, s, c->d_coff, C, cnt + CNT_CL,
+                       c->d_wsz, c->d_asz, int(c->p.max_cluster_points), cnt + CNT_MAXN);
+    exclusive_scan_u32(c->d_wsz, c->d_wo32, C, c->d_part, s, cnt + CNT_CL, cnt + CNT_WTOT);
+    exclusive_scan_u32(c->d_asz, c->d_ao32, C, c->d_part, s, cnt + CNT_CL, cnt + CNT_ATOT);
+    hipLaunchKernelGGL(k_cluster_plan, dim3(blocks_for(C)), dim3(kT), 0, s, c->d_coff, C, cnt + CNT_CL, c->d_wsz,
+                       c->d_asz, c->d_wo32, c->d_ao32, c->cap_w, c->cap_a, int(c->p.max_cluster_points),
+                       c->d_woff, c->d_aoff, c->d_blist, C, cnt, c->d_pd, c->d_stat);
+    // 5. FP64 training, one persistent launch per size bucket
     const double l = c->p.length_scale, s2 = c->p.noise_sigma * c->p.noise_sigma;
-    std::vector<int32_t> &bl = c->h_blist;
-    bl.clear();
-    for (uint32_t i = 0; i < ncl; ++i) if (M.h_n[i] <= kTinyN) bl.push_back(int32_t(i));
-    const int64_t n_tiny = int64_t(bl.size());
-    for (uint32_t i = 0; i < ncl; ++i)
-        if (M.h_n[i] > kTinyN && M.h_n[i] <= kWaveN) bl.push_back(int32_t(i));
-    const int64_t n_wave = int64_t(bl.size()) - n_tiny;
-    for (uint32_t i = 0; i < ncl; ++i) if (M.h_n[i] > kWaveN) bl.push_back(int32_t(i));
-    const int64_t n_big = int64_t(bl.size()) - n_tiny - n_wave;
-    if ((e = hipMemcpyAsync(c->d_blist, bl.data(), 4 * bl.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
-        return hip_fail(c, e, "train: upload buckets");
-    if (n_tiny)
-        hipLaunchKernelGGL(k_train_tiny, dim3(unsigned((n_tiny + 63) / 64)), dim3(64), 0, s, c->d_blist,
-                           n_tiny, c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64,
-                           c->d_pd, c->p.kernel, l, s2, c->d_stat);
-    if (n_wave)
-        hipLaunchKernelGGL(k_train_wave, dim3(unsigned(n_wave)), dim3(64), 0, s, c->d_blist + n_tiny,
-                           c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
-                           c->p.kernel, l, s2, c->d_stat);
-    if (n_big) {
-#define GPDF_TRAIN_BLOCK(T)                                                                              \
-    hipLaunchKernelGGL(k_train_block<T>, dim3(unsigned(n_big)), dim3(T), 0, s, c->d_blist + n_tiny + n_wave, \
-                       c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64,   \
+    hipLaunchKernelGGL(k_train_tiny, dim3(blocks_for(C, 64)), dim3(64), 0, s, c->d_blist, cnt + CNT_TINY,
+                       c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l,
+                       s2, c->d_stat);
+    hipLaunchKernelGGL(k_train_wave, dim3(unsigned(std::min<int64_t>(C, 2048))), dim3(64), 0, s, c->d_blist + C,
+                       cnt + CNT_WAVE, c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
+                       c->p.kernel, l, s2, c->d_stat);
+    fill_u32(c->d_work + 2, 0u, 1, s);
+    {
+        const unsigned gb = unsigned(std::min<int64_t>(C, 256));
+#define GPDF_TRAIN_BLOCK(T)                                                                                    \
+    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, s, c->d_blist + 2 * C, cnt + CNT_BIG, c->d_work + 2, \
+                       c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64,     \
                        c->d_pd, c->p.kernel, l, s2, c->d_stat)
         if (c->tune.train_threads == 512) GPDF_TRAIN_BLOCK(512);
-        else if (c->tune.train_threads == 1024) GPDF_TRAIN_BLOCK(1024);
-        else GPDF_TRAIN_BLOCK(256);
+        else if (c->tune.train_threads == 256) GPDF_TRAIN_BLOCK(256);
+        else GPDF_TRAIN_BLOCK(1024);
 #undef GPDF_TRAIN_BLOCK
     }
     // 6. cluster hash
-    fill_u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1, s);
     HashView hv{c->d_chash, c->chash_mask};
-    hipLaunchKernelGGL(k_chash_insert, dim3(blocks_for(ncl)), dim3(kT), 0, s, c->d_ckey, int64_t(ncl),
-                       hv, c->d_chash_val, c->d_stat);
+    hipLaunchKernelGGL(k_chash_insert, dim3(blocks_for(C)), dim3(kT), 0, s, c->d_ckey, C, cnt + CNT_CL, hv,
+                       c->d_chash_val, c->d_stat);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "train: launch");
-    M.nclusters = ncl;
-    M.bf16_ready = false;
-    M.npoints = npts;
-    M.max_n = maxn;
+    if (!eager) return GPDF_OK;
+    // counts of the model and capacity check: one read-back
+    uint32_t hc[kCnt];
+    unsigned long long capx = 0;
+    if ((e = hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&capx, c->d_stat + ST_CAPACITY, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(c, e, "train: read counts");
+    M.host_counts = true;
+    M.skipped = n - int64_t(hc[CNT_VALID]);
+    M.npoints = hc[CNT_PTS];
+    M.nclusters = hc[CNT_CL];
+    M.max_n = hc[CNT_MAXN];
+    if (capx) {
+        M.trained = false;
+        return fail(c, GPDF_E_CAPACITY,
+                    "train: capacity exceeded (max_clusters, max_cluster_points or max_factor_elems)");
+    }
     return GPDF_OK;
 }
 
