@@ -139,7 +139,8 @@ enum {
     GPDF_STATUS_HASH_FULL = 1u,       /* a probe sequence exhausted a table */
     GPDF_STATUS_GLOBAL_FULL = 2u,     /* the global grid is full */
     GPDF_STATUS_NONFINITE = 4u,       /* non-finite input points or queries */
-    GPDF_STATUS_NONPD = 8u            /* some cluster was not positive definite */
+    GPDF_STATUS_NONPD = 8u,           /* some cluster was not positive definite */
+    GPDF_STATUS_CAPACITY = 16u        /* a capacity was exceeded inside a frame graph */
 };
 
 /* Fill *p with defaults: Matern-3/2, l = 0.2 m, s = 0.01, raw points in 0.4 m
@@ -192,6 +193,22 @@ gpdf_status gpdf_query_distance(gpdf_ctx *ctx, const float *d_q, int64_t m,
  * GPDF_E_NOT_TRAINED (d_xyz == NULL before any training). */
 gpdf_status gpdf_fuse_frame(gpdf_ctx *ctx, const float *d_xyz, int64_t n,
                             const float *h_origin);
+
+/* gpdf_fuse_frame as one replay of a captured HIP graph (batching
+ * extension).  The first call records training, test voxels, their query and
+ * the fusion with every count kept on the device and every grid sized by the
+ * capacities (max_points input points, max_queries test voxels); each call
+ * then copies d_xyz [n][3] (n <= max_points), the frame stamp and h_origin
+ * into context buffers and replays the graph on the context stream, with no
+ * host round trip.  Results equal gpdf_fuse_frame.  Needs NEIGHBOR27
+ * selection in FP32 or FP64.  The first call allocates cell lists for
+ * max_queries cells (448 B each).  A capacity exceeded inside the graph
+ * (max_clusters, max_cluster_points, max_factor_elems, max_queries) is not
+ * returned: the affected clusters are left out and GPDF_STATUS_CAPACITY is
+ * set in gpdf_stats.status_bits.
+ * Errors: GPDF_E_INVALID_ARG, GPDF_E_CAPACITY (n > max_points). */
+gpdf_status gpdf_fuse_frame_graph(gpdf_ctx *ctx, const float *d_xyz, int64_t n,
+                                  const float *h_origin);
 
 /* Query the fused grid at d_q [m][3]: trilinear interpolation of D over the
  * eight voxel centres around each point and its analytic gradient; valid only

@@ -14,7 +14,9 @@ import os
 __all__ = ["Params", "Stats", "Context", "load_library", "library_path",
            "KERNEL_MATERN32", "KERNEL_SE", "SEL_NEIGHBOR27", "SEL_KNN",
            "COMB_SMOOTHMIN", "COMB_HARDMIN", "GRAD_WEIGHTED", "GRAD_PAPER_MEAN",
-           "PREC_FP32", "PREC_BF16", "PREC_FP64", "MLP_NPARAM", "GpdfError"]
+           "PREC_FP32", "PREC_BF16", "PREC_FP64", "MLP_NPARAM", "GpdfError",
+           "STATUS_HASH_FULL", "STATUS_GLOBAL_FULL", "STATUS_NONFINITE", "STATUS_NONPD",
+           "STATUS_CAPACITY"]
 
 ABI_VERSION = 1
 KERNEL_MATERN32, KERNEL_SE = 0, 1
@@ -23,6 +25,7 @@ COMB_SMOOTHMIN, COMB_HARDMIN = 0, 1
 GRAD_WEIGHTED, GRAD_PAPER_MEAN = 0, 1
 PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
 MLP_NPARAM = 8897
+STATUS_HASH_FULL, STATUS_GLOBAL_FULL, STATUS_NONFINITE, STATUS_NONPD, STATUS_CAPACITY = 1, 2, 4, 8, 16
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "HIP", 4: "CAPACITY", 5: "NOT_TRAINED"}
@@ -33,7 +36,7 @@ EXPORTS = [
     "gpdf_last_error", "gpdf_export_model", "gpdf_export_global",
     "gpdf_export_test_points", "gpdf_save_global", "gpdf_load_global",
     "gpdf_nearest_distance", "gpdf_mlp_init", "gpdf_mlp_set_weights",
-    "gpdf_set_tuning", "gpdf_get_tuning", "gpdf_autotune",
+    "gpdf_set_tuning", "gpdf_get_tuning", "gpdf_autotune", "gpdf_fuse_frame_graph",
     "gpdf_mlp_get_weights", "gpdf_mlp_set_norm", "gpdf_mlp_get_norm", "gpdf_mlp_features",
     "gpdf_mlp_forward", "gpdf_mlp_grad", "gpdf_mlp_train",
 ]
@@ -124,6 +127,7 @@ def _bind(L):
         "gpdf_save_global": [P, C.c_char_p],
         "gpdf_load_global": [P, C.c_char_p],
         "gpdf_nearest_distance": [P, P, I64, P, I64, P],
+        "gpdf_fuse_frame_graph": [P, P, I64, P],
         "gpdf_set_tuning": [P, C.c_int32, C.c_int32],
         "gpdf_get_tuning": [P, P, P],
         "gpdf_autotune": [P, P, I64, P, I64, P, P],
@@ -251,6 +255,14 @@ class Context:
         _check(self.lib.gpdf_fuse_frame(
             self._h, _dptr(xyz, torch.float32, 3) if xyz is not None and n else None, n,
             _host3(origin)), self._h)
+
+    def fuse_graph(self, xyz, origin):
+        """fuse() as one replay of a captured HIP graph (captured on the first
+        call); the counts stay on the device."""
+        torch = self._torch
+        n = xyz.shape[0]
+        _check(self.lib.gpdf_fuse_frame_graph(self._h, _dptr(xyz, torch.float32, 3) if n else None, n,
+                                              _host3(origin)), self._h)
 
     def query_global(self, q, grad=True):
         torch = self._torch

@@ -27,6 +27,14 @@ namespace {
 
 
 void release(gpdf_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    if (c->d_gin) (void)hipFree(c->d_gin);
+    if (c->d_gorigin) (void)hipFree(c->d_gorigin);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->gstream = nullptr;
     void *ptrs[] = {c->d_key, c->d_key2, c->d_val, c->d_val2, c->d_flag, c->d_scan, c->d_hist,
                     c->d_part, c->d_red, c->d_pts, c->d_alpha64, c->d_ckey, c->d_coff, c->d_pd,
                     c->d_woff, c->d_aoff, c->d_W32, c->d_W64, c->d_A, c->d_chash,
@@ -236,6 +244,96 @@ extern "C" gpdf_status gpdf_fuse_frame(gpdf_ctx *c, const float *d_xyz, int64_t 
     }
 }
 
+namespace {
+
+// inputs of one graph replay, passed by value as kernel arguments
+__global__ void k_set_frame(uint32_t *cnt, uint32_t n, uint32_t frame, float ox, float oy, float oz,
+                            float *origin) {
+    if (threadIdx.x != 0) return;
+    cnt[CNT_IN] = n;
+    cnt[CNT_FRAME] = frame;
+    origin[0] = ox;
+    origin[1] = oy;
+    origin[2] = oz;
+}
+
+gpdf_status capture_frame_graph(gpdf_ctx *c) {
+    hipError_t e;
+    const int64_t P = c->p.max_points;
+    if ((e = hipMalloc((void **)&c->d_gin, sizeof(float) * 3 * size_t(P))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_gorigin, sizeof(float) * 4)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(c, e, "graph: allocate");
+    gpdf_status st = ensure_offsets(c);
+    if (st != GPDF_OK) return st;
+    if ((e = ensure_cell_lists(c, c->p.max_queries + 1)) != hipSuccess) return hip_fail(c, e, "graph: cell lists");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "graph: sync");
+    hipStream_t user = c->stream;
+    c->stream = c->gstream;
+    c->capturing = true;
+    if ((e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        st = hip_fail(c, e, "graph: begin capture");
+    } else {
+        st = train(c, c->d_gin, P, c->d_cnt + CNT_IN);
+        if (st == GPDF_OK) st = fuse(c, nullptr, c->d_gorigin, P);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(c->gstream, &g);
+        if (st == GPDF_OK && e != hipSuccess) st = hip_fail(c, e, "graph: end capture");
+        if (st == GPDF_OK) {
+            c->graph = g;
+            if ((e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0)) != hipSuccess) {
+                c->gexec = nullptr;
+                st = hip_fail(c, e, "graph: instantiate");
+            }
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    c->capturing = false;
+    c->stream = user;
+    return st;
+}
+
+}  // namespace
+
+extern "C" gpdf_status gpdf_fuse_frame_graph(gpdf_ctx *c, const float *d_xyz, int64_t n, const float *h_origin) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    if (!h_origin || !(std::isfinite(h_origin[0]) && std::isfinite(h_origin[1]) && std::isfinite(h_origin[2])))
+        return fail(c, GPDF_E_INVALID_ARG, "fuse_frame_graph: origin required");
+    if (n < 0 || n > c->p.max_points) return fail(c, GPDF_E_CAPACITY, "fuse_frame_graph: n exceeds max_points");
+    if (n > 0 && !d_xyz) return fail(c, GPDF_E_INVALID_ARG, "fuse_frame_graph: null points");
+    if (c->p.selection != GPDF_SEL_NEIGHBOR27 || c->p.precision == GPDF_PREC_BF16)
+        return fail(c, GPDF_E_INVALID_ARG, "fuse_frame_graph: needs NEIGHBOR27 selection in FP32 or FP64");
+    try {
+        if (!c->gexec) {
+            const gpdf_status st = capture_frame_graph(c);
+            if (st != GPDF_OK) {
+                if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+                if (c->graph) (void)hipGraphDestroy(c->graph);
+                c->gexec = nullptr;
+                c->graph = nullptr;
+                return st;
+            }
+        }
+        hipStream_t s = c->stream;
+        hipError_t e;
+        if (n > 0 && (e = hipMemcpyAsync(c->d_gin, d_xyz, sizeof(float) * 3 * size_t(n), hipMemcpyDeviceToDevice,
+                                         s)) != hipSuccess)
+            return hip_fail(c, e, "fuse_frame_graph: copy points");
+        hipLaunchKernelGGL(k_set_frame, dim3(1), dim3(64), 0, s, c->d_cnt, uint32_t(n), uint32_t(c->frame),
+                           h_origin[0], h_origin[1], h_origin[2], c->d_gorigin);
+        if ((e = hipGetLastError()) != hipSuccess || (e = hipGraphLaunch(c->gexec, s)) != hipSuccess)
+            return hip_fail(c, e, "fuse_frame_graph: launch");
+        c->frame++;
+        c->model = gpdf::Model();
+        c->model.trained = true;
+        c->last_test = -1;
+        return GPDF_OK;
+    } catch (...) {
+        return fail(c, GPDF_E_OOM, "fuse_frame_graph: host allocation failed");
+    }
+}
+
 extern "C" gpdf_status gpdf_query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *d_dist,
                                          float *d_grad, uint8_t *d_valid) {
     if (!c) return GPDF_E_INVALID_ARG;
@@ -256,12 +354,20 @@ extern "C" gpdf_status gpdf_get_stats(gpdf_ctx *c, gpdf_stats *out) {
     std::memset(out, 0, sizeof *out);
     out->clusters = c->model.nclusters;
     out->points = c->model.npoints;
+    if (!c->model.host_counts) {
+        // the last frame ran as a graph: its counts are on the device
+        uint32_t dc[kCnt];
+        if ((e = hipMemcpy(dc, c->d_cnt, sizeof dc, hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(c, e, "get_stats");
+        out->clusters = dc[CNT_CL];
+        out->points = dc[CNT_PTS];
+    }
     out->nonpd_clusters = int64_t(h[ST_NONPD]);
     out->skipped_points = int64_t(h[ST_SKIPPED_POINTS]);
     out->queries = c->last_queries;
     out->valid_queries = int64_t(h[ST_VALID_Q]);
     out->refined_queries = int64_t(h[ST_REFINE]);
-    out->test_points = c->last_test;
+    out->test_points = c->last_test >= 0 ? c->last_test : int64_t(h[ST_TESTPTS]);
     out->fused = int64_t(h[ST_FUSED]);
     out->fuse_skipped = int64_t(h[ST_FUSE_SKIPPED]);
     out->global_voxels = int64_t(h[ST_GLOBAL_COUNT]);
@@ -274,6 +380,7 @@ extern "C" gpdf_status gpdf_get_stats(gpdf_ctx *c, gpdf_stats *out) {
     if (h[ST_GLOBAL_FULL]) bits |= GPDF_STATUS_GLOBAL_FULL;
     if (h[ST_SKIPPED_POINTS] || h[ST_NONFINITE_Q]) bits |= GPDF_STATUS_NONFINITE;
     if (h[ST_NONPD]) bits |= GPDF_STATUS_NONPD;
+    if (h[ST_CAPACITY]) bits |= GPDF_STATUS_CAPACITY;
     out->status_bits = bits;
     for (int k = 0; k < 8; ++k) {
         float ms = -1.f;

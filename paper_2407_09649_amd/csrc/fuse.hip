@@ -25,11 +25,11 @@ inline unsigned blocks_for(int64_t n, int t = kT) {
 
 // candidate test voxels: the global-grid cell of every training point plus
 // every integer offset inside the band ball
-__global__ void k_test_insert(const float4 *__restrict__ pts, int64_t npts, double hf,
+__global__ void k_test_insert(const float4 *__restrict__ pts, int64_t nb, const uint32_t *__restrict__ dn, double hf,
                               const int4 *__restrict__ offs, int noffs, HashView set,
                               unsigned long long *__restrict__ stat) {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= npts * noffs) return;
+    if (t >= dev_count(nb, dn) * noffs) return;
     const int64_t i = t / noffs;
     const int k = int(t - i * noffs);
     const float4 p = pts[i];
@@ -46,8 +46,13 @@ __global__ void k_test_insert(const float4 *__restrict__ pts, int64_t npts, doub
 __global__ __launch_bounds__(256) void k_test_compact(
     const unsigned long long *__restrict__ keys, int64_t cap, const uint32_t *__restrict__ tile_off,
     int64_t ntiles, uint64_t *__restrict__ out, int64_t out_cap, double hf, float *__restrict__ xyz,
-    unsigned long long *__restrict__ stat) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) stat[ST_TESTPTS] = tile_off[ntiles];
+    unsigned long long *__restrict__ stat, uint32_t *__restrict__ ntest) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t t = tile_off[ntiles];
+        stat[ST_TESTPTS] = t;
+        *ntest = uint32_t(min(int64_t(t), out_cap));
+        if (int64_t(t) > out_cap) atomicAdd(&stat[ST_CAPACITY], 1ull);
+    }
     for_occupied_in_tile(keys, cap, tile_off[blockIdx.x], [&](int64_t, unsigned long long k, uint32_t id) {
         if (int64_t(id) >= out_cap) return;
         out[id] = k;
@@ -62,10 +67,11 @@ __global__ __launch_bounds__(256) void k_test_compact(
 
 // Eq. (7)-(8): D <- (V d + v D) / (V + v), V <- V v / (V + v); an absent voxel
 // takes (d, v) (the V = infinity limit)
-__global__ void k_fuse(const uint64_t *__restrict__ keys, const unsigned long long *__restrict__ nptr,
+__global__ void k_fuse(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ nptr,
                        const float *__restrict__ d, const float *__restrict__ v,
                        const uint8_t *__restrict__ ok, HashView g, float *__restrict__ gD,
-                       float *__restrict__ gV, uint32_t *__restrict__ gstamp, uint32_t frame,
+                       float *__restrict__ gV, uint32_t *__restrict__ gstamp, uint32_t frame_h,
+                       const uint32_t *__restrict__ dframe,
                        unsigned long long *__restrict__ stat) {
     const int64_t n = int64_t(*nptr);
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -90,7 +96,7 @@ __global__ void k_fuse(const uint64_t *__restrict__ keys, const unsigned long lo
         gD[s] = (Vp * di + vi * Dp) / den;
         gV[s] = (Vp * vi) / den;
     }
-    gstamp[s] = frame;
+    gstamp[s] = dframe ? *dframe : frame_h;
 }
 
 // trilinear interpolation of D over the eight voxel centres around x
@@ -186,20 +192,9 @@ __global__ void k_nearest(const float *__restrict__ pts, int64_t n, const float 
 
 }  // namespace
 
-gpdf_status fuse(gpdf_ctx *c, const float *origin) {
-    hipStream_t s = c->stream;
-    const Model &M = c->model;
-    if (!M.trained) return fail(c, GPDF_E_NOT_TRAINED, "fuse before training");
-    hipError_t e;
-    fill_u64(c->d_stat + ST_TESTPTS, 0ull, 1, s);
-    fill_u64(c->d_stat + ST_FUSED, 0ull, 1, s);
-    fill_u64(c->d_stat + ST_FUSE_SKIPPED, 0ull, 1, s);
-    if (M.npoints == 0) {
-        c->last_test = 0;
-        c->frame++;
-        return GPDF_OK;
-    }
-    // band offsets
+// band offsets of the test voxels (fixed by the parameters), uploaded once
+gpdf_status ensure_offsets(gpdf_ctx *c) {
+    if (c->offs_ready) return GPDF_OK;
     const double hf = c->p.fuse_voxel_size;
     const int R = int(std::floor(c->p.fuse_band / hf + 1e-9));
     std::vector<int4> &offs = c->h_offs;
@@ -209,37 +204,74 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin) {
             for (int d = -R; d <= R; ++d)
                 if (a * a + b * b + d * d <= R * R) offs.push_back(make_int4(a, b, d, 0));
     if (int64_t(offs.size()) > c->offs_cap) return fail(c, GPDF_E_CAPACITY, "fuse: band too wide");
+    hipError_t e;
     if ((e = hipMemcpyAsync(c->d_offs, offs.data(), sizeof(int4) * offs.size(), hipMemcpyHostToDevice,
-                            s)) != hipSuccess)
+                            c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
         return hip_fail(c, e, "fuse: upload offsets");
+    c->offs_ready = true;
+    return GPDF_OK;
+}
+
+// Test voxels of the current training points, their signed query and the
+// fusion.  With npts_bound >= 0 (graph capture) the counts stay on the
+// device: training points at cnt[CNT_PTS] (at most npts_bound), test voxels
+// at cnt[CNT_TEST], the frame stamp at cnt[CNT_FRAME] and the origin at
+// d_origin; nothing is read back.
+gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin, int64_t npts_bound) {
+    hipStream_t s = c->stream;
+    const Model &M = c->model;
+    const bool eager = npts_bound < 0;
+    if (!M.trained) return fail(c, GPDF_E_NOT_TRAINED, "fuse before training");
+    hipError_t e;
+    uint32_t *cnt = c->d_cnt;
+    fill_u64(c->d_stat + ST_TESTPTS, 0ull, 1, s);
+    fill_u64(c->d_stat + ST_FUSED, 0ull, 1, s);
+    fill_u64(c->d_stat + ST_FUSE_SKIPPED, 0ull, 1, s);
+    fill_u32(cnt + CNT_TEST, 0u, 1, s);
+    const int64_t npts = eager ? M.npoints : npts_bound;
+    if (eager && npts == 0) {
+        c->last_test = 0;
+        c->frame++;
+        return GPDF_OK;
+    }
+    gpdf_status st = ensure_offsets(c);
+    if (st != GPDF_OK) return st;
+    const double hf = c->p.fuse_voxel_size;
+    const int noffs = int(c->h_offs.size());
     const int64_t tcap = int64_t(c->tset_mask) + 1;
     stage_begin(c, GPDF_MS_TESTPTS);
     fill_u64(c->d_tset, (unsigned long long)kNoKey, tcap, s);
     HashView set{c->d_tset, c->tset_mask};
-    const int64_t work = M.npoints * int64_t(offs.size());
-    hipLaunchKernelGGL(k_test_insert, dim3(blocks_for(work)), dim3(kT), 0, s, c->d_pts, M.npoints, hf,
-                       c->d_offs, int(offs.size()), set, c->d_stat);
+    const int64_t work = npts * int64_t(noffs);
+    hipLaunchKernelGGL(k_test_insert, dim3(blocks_for(work)), dim3(kT), 0, s, c->d_pts, npts,
+                       eager ? nullptr : cnt + CNT_PTS, hf, c->d_offs, noffs, set, c->d_stat);
     count_occupied(c->d_tset, tcap, c->d_tile_cnt, c->d_tile_off, c->d_part, s);
     const int64_t ntiles = compact_tiles(tcap);
     hipLaunchKernelGGL(k_test_compact, dim3(unsigned(ntiles)), dim3(256), 0, s, c->d_tset, tcap,
-                       c->d_tile_off, ntiles, c->d_tkeys, c->p.max_queries, hf, c->d_tpts, c->d_stat);
+                       c->d_tile_off, ntiles, c->d_tkeys, c->p.max_queries, hf, c->d_tpts, c->d_stat,
+                       cnt + CNT_TEST);
     stage_end(c, GPDF_MS_TESTPTS);
-    unsigned long long nt = 0;
-    if ((e = hipMemcpyAsync(&nt, c->d_stat + ST_TESTPTS, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_fail(c, e, "fuse: read test count");
-    if (int64_t(nt) > c->p.max_queries) return fail(c, GPDF_E_CAPACITY, "fuse: test points exceed max_queries");
-    c->last_test = int64_t(nt);
-    gpdf_status st = query(c, c->d_tpts, int64_t(nt), origin, c->d_tmp_dist, nullptr, c->d_tmp_var,
-                           c->d_tmp_valid, nullptr, 0);
+    int64_t nt = c->p.max_queries;
+    if (eager) {
+        unsigned long long t = 0;
+        if ((e = hipMemcpyAsync(&t, c->d_stat + ST_TESTPTS, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(c, e, "fuse: read test count");
+        if (int64_t(t) > c->p.max_queries) return fail(c, GPDF_E_CAPACITY, "fuse: test points exceed max_queries");
+        nt = int64_t(t);
+        c->last_test = nt;
+    }
+    st = query(c, c->d_tpts, nt, origin, c->d_tmp_dist, nullptr, c->d_tmp_var, c->d_tmp_valid, nullptr, 0,
+               eager ? nullptr : cnt + CNT_TEST, d_origin);
     if (st != GPDF_OK) return st;
     HashView g{c->d_gkey, c->gmask};
     stage_begin(c, GPDF_MS_FUSE);
-    hipLaunchKernelGGL(k_fuse, dim3(blocks_for(int64_t(nt))), dim3(kT), 0, s, c->d_tkeys,
-                       c->d_stat + ST_TESTPTS, c->d_tmp_dist, c->d_tmp_var, c->d_tmp_valid, g, c->d_gD,
-                       c->d_gV, c->d_gstamp, c->frame, c->d_stat);
+    hipLaunchKernelGGL(k_fuse, dim3(blocks_for(nt)), dim3(kT), 0, s, c->d_tkeys, cnt + CNT_TEST, c->d_tmp_dist,
+                       c->d_tmp_var, c->d_tmp_valid, g, c->d_gD, c->d_gV, c->d_gstamp, c->frame,
+                       eager ? nullptr : cnt + CNT_FRAME, c->d_stat);
     stage_end(c, GPDF_MS_FUSE);
-    c->frame++;
+    if (eager) c->frame++;
     return (e = hipGetLastError()) == hipSuccess ? GPDF_OK : hip_fail(c, e, "fuse launch");
 }
 

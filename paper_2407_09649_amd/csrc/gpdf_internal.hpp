@@ -261,6 +261,7 @@ struct QueryConsts {
     int kernel, combine, grad_mode, knn_q;
     int signed_, has_origin_pad;
     float ox, oy, oz;       // sensor origin (signed queries)
+    const float *d_origin;  // when set, the origin is read here on the device (graph replays)
     double ld, sd, hv, hc;  // FP64 copies: l, s, voxel, cell
     double lamd, omind, omaxd;
     double ad, cd;          // FP64 copies of a and c
@@ -285,6 +286,14 @@ struct gpdf_tune {
 struct gpdf_ctx {
     gpdf_params p{};
     gpdf_tune tune;
+    bool capturing = false;        // recording the frame graph: no read-backs, no stage events
+    bool offs_ready = false;       // band offsets of the test voxels uploaded
+    // per-frame graph (fuse_frame with every count on the device)
+    hipStream_t gstream = nullptr; // capture stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    float *d_gin = nullptr;        // input points of the graph [max_points][3]
+    float *d_gorigin = nullptr;    // sensor origin of the graph [4]
     hipStream_t stream = nullptr;
     int device = 0;
     std::string err;
@@ -385,10 +394,10 @@ struct gpdf_ctx {
 namespace gpdf {
 // stage timers: HIP events recorded on the context stream when p.timing is set
 inline void stage_begin(gpdf_ctx *c, int k) {
-    if (c->p.timing) (void)hipEventRecord(c->ev[2 * k], c->stream);
+    if (c->p.timing && !c->capturing) (void)hipEventRecord(c->ev[2 * k], c->stream);
 }
 inline void stage_end(gpdf_ctx *c, int k) {
-    if (c->p.timing) {
+    if (c->p.timing && !c->capturing) {
         (void)hipEventRecord(c->ev[2 * k + 1], c->stream);
         c->ev_ok[k] = true;
     }
@@ -416,14 +425,19 @@ void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 
 // stages (train.hip, query.hip, fuse.hip, mlp.hip)
 gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn = nullptr);
+// With dm (a device count of queries, at most m) and optionally d_origin, the
+// call reads nothing back and can be captured in a graph.
 gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin, float *dist,
-                  float *grad, float *var, uint8_t *valid, float *aux, int32_t correct);
-gpdf_status fuse(gpdf_ctx *c, const float *origin);
+                  float *grad, float *var, uint8_t *valid, float *aux, int32_t correct,
+                  const uint32_t *dm = nullptr, const float *d_origin = nullptr);
+gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin = nullptr, int64_t npts_bound = -1);
+gpdf_status ensure_offsets(gpdf_ctx *c);
 gpdf_status query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *dist, float *grad,
                          uint8_t *valid);
 gpdf_status nearest_distance(gpdf_ctx *c, const float *pts, int64_t n, const float *q, int64_t m,
                              float *out);
 gpdf_status mlp_apply(gpdf_ctx *c, const float *d_dist, const float *d_var, const float *d_grad,
                       const float *d_aux, const uint8_t *valid, int64_t m, float *dist_out);
-QueryConsts make_consts(const gpdf_params &p, const float *origin);
+QueryConsts make_consts(const gpdf_params &p, const float *origin, const float *d_origin = nullptr);
+hipError_t ensure_cell_lists(gpdf_ctx *c, int64_t cap);
 }  // namespace gpdf

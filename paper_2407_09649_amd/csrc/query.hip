@@ -111,11 +111,12 @@ __device__ inline void write_invalid(uint32_t qi, float *dist, float *grad, floa
 // ---------------------------------------------------------------------------
 // grouping of queries by cell
 // ---------------------------------------------------------------------------
-__global__ void k_qcells(const float *__restrict__ q, int64_t m, int voxel_mode, double hv, double hc,
-                         HashView qh, uint32_t *__restrict__ cnt, int32_t *__restrict__ qslot,
+__global__ void k_qcells(const float *__restrict__ q, int64_t mb, const uint32_t *__restrict__ dm, int voxel_mode,
+                         double hv, double hc, HashView qh, uint32_t *__restrict__ cnt, int32_t *__restrict__ qslot,
                          uint32_t *__restrict__ qrank, float *dist, float *grad, float *var,
                          uint8_t *valid, float *aux, unsigned long long *__restrict__ stat) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t m = dev_count(mb, dm);
     if (int64_t(blockIdx.x) * blockDim.x >= m) return;  // whole block past the end
     int64_t c[3];
     const bool in = i < m;
@@ -141,8 +142,11 @@ __global__ __launch_bounds__(256) void k_cells_compact(
     const unsigned long long *__restrict__ keys, const uint32_t *__restrict__ cnt, int64_t cap,
     const uint32_t *__restrict__ tile_off, int64_t ntiles, int32_t *__restrict__ cell_of_slot,
     uint64_t *__restrict__ cell_key, uint32_t *__restrict__ cell_cnt,
-    uint32_t *__restrict__ cell_chunks, unsigned long long *__restrict__ stat) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) stat[ST_CELLS] = tile_off[ntiles];
+    uint32_t *__restrict__ cell_chunks, unsigned long long *__restrict__ stat, uint32_t *__restrict__ ncells) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        stat[ST_CELLS] = tile_off[ntiles];
+        *ncells = tile_off[ntiles];
+    }
     for_occupied_in_tile(keys, cap, tile_off[blockIdx.x], [&](int64_t s, unsigned long long k, uint32_t id) {
         cell_of_slot[s] = int32_t(id);
         cell_key[id] = k;
@@ -152,13 +156,13 @@ __global__ __launch_bounds__(256) void k_cells_compact(
     });
 }
 
-__global__ void k_cell_lists(int64_t ncells, const uint64_t *__restrict__ cell_key,
+__global__ void k_cell_lists(int64_t ncb, const uint32_t *__restrict__ dnc, const uint64_t *__restrict__ cell_key,
                              const unsigned long long *__restrict__ chash, uint32_t cmask,
                              const int32_t *__restrict__ chash_val, const uint8_t *__restrict__ pd,
                              const int32_t *__restrict__ coff, const int64_t *__restrict__ woff,
                              int4 *__restrict__ lists) {
     int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= ncells) return;
+    if (c >= dev_count(ncb, dnc)) return;
     int64_t cc[3];
     unpack_key(cell_key[c], cc);
     int4 *L = lists + c * kListStride;
@@ -177,19 +181,19 @@ __global__ void k_cell_lists(int64_t ncells, const uint64_t *__restrict__ cell_k
 }
 
 // chunk table: (cell, first query) for every 64-query chunk of every cell
-__global__ void k_chunk_table(int64_t ncells, const uint32_t *__restrict__ cell_chunks,
+__global__ void k_chunk_table(int64_t ncb, const uint32_t *__restrict__ dnc, const uint32_t *__restrict__ cell_chunks,
                               const uint32_t *__restrict__ chunk_off, uint2 *__restrict__ chunk) {
     int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= ncells) return;
+    if (c >= dev_count(ncb, dnc)) return;
     const uint32_t o = chunk_off[c];
     for (uint32_t j = 0; j < cell_chunks[c]; ++j) chunk[o + j] = make_uint2(uint32_t(c), j * 64);
 }
 
 __global__ void k_scatter_order(const int32_t *__restrict__ qslot, const uint32_t *__restrict__ qrank,
-                                int64_t m, const int32_t *__restrict__ cell_of_slot,
+                                int64_t mb, const uint32_t *__restrict__ dm, const int32_t *__restrict__ cell_of_slot,
                                 const uint32_t *__restrict__ cell_off, uint32_t *__restrict__ order) {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+    if (i >= dev_count(mb, dm)) return;
     const int32_t s = qslot[i];
     if (s < 0) return;
     order[cell_off[cell_of_slot[s]] + qrank[i]] = uint32_t(i);
@@ -211,10 +215,10 @@ __global__ void k_refine_count(const uint2 *__restrict__ rec, const unsigned lon
     if (i < n) rrank[i] = r;
 }
 
-__global__ void k_refine_chunks(int64_t ncells, const uint32_t *__restrict__ rcnt,
+__global__ void k_refine_chunks(int64_t ncb, const uint32_t *__restrict__ dnc, const uint32_t *__restrict__ rcnt,
                                 uint32_t *__restrict__ rchunks) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c < ncells) rchunks[c] = (rcnt[c] + 63) / 64;
+    if (c < dev_count(ncb, dnc)) rchunks[c] = (rcnt[c] + 63) / 64;
 }
 
 __global__ void k_refine_scatter(const uint2 *__restrict__ rec, const unsigned long long *__restrict__ nrec,
@@ -572,7 +576,9 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
             // sensor side of the nearest training point, decided in FP32
             const float4 p = pts[A.bidx];
             const float ax = Q.fx - p.x, ay = Q.fy - p.y, az = Q.fz - p.z;
-            const float bx = C.ox - p.x, by = C.oy - p.y, bz = C.oz - p.z;
+            const float ox = C.d_origin ? C.d_origin[0] : C.ox, oy = C.d_origin ? C.d_origin[1] : C.oy,
+                        oz = C.d_origin ? C.d_origin[2] : C.oz;
+            const float bx = ox - p.x, by = oy - p.y, bz = oz - p.z;
             const float dot = fmaf(az, bz, fmaf(ay, by, ax * bx));
             if (!(dot >= 0.f)) { D = -D; Gx = -Gx; Gy = -Gy; Gz = -Gz; }
         }
@@ -1032,11 +1038,14 @@ void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_
                     const Grouping &G, const int4 *lists, const ModelView &Mo,
                     const QueryConsts &C, const Outputs &O, int slot) {
     uint32_t *work = nullptr;
-    if (c->tune.eval_persistent > 0 && !knn) {
-        // 256 CUs x 4 SIMDs x the tuned number of wavefronts per SIMD
+    // persistent when tuned so, and always in a captured graph (its grid
+    // bound would otherwise be one workgroup per possible chunk)
+    const int per = c->tune.eval_persistent > 0 ? c->tune.eval_persistent : (c->capturing ? 2 : 0);
+    if (per > 0 && !knn) {
+        // 256 CUs x 4 SIMDs x the wavefronts per SIMD
         work = c->d_work + slot;
         fill_u32(work, 0u, 1, s);
-        grid = std::min<unsigned>(grid, 1024u * unsigned(c->tune.eval_persistent));
+        grid = std::min<unsigned>(grid, 1024u * unsigned(per));
     }
     if (kernel == GPDF_KERNEL_MATERN32)
         launch_query_m<T, GPDF_KERNEL_MATERN32>(knn, grid, s, q, G, lists, Mo, C, O, work);
@@ -1046,7 +1055,7 @@ void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_
 
 }  // namespace
 
-QueryConsts make_consts(const gpdf_params &p, const float *origin) {
+QueryConsts make_consts(const gpdf_params &p, const float *origin, const float *d_origin) {
     QueryConsts C{};
     const bool matern = p.kernel == GPDF_KERNEL_MATERN32;
     C.ad = matern ? 1.7320508075688772935 / p.length_scale : 1.0 / (2.0 * p.length_scale * p.length_scale);
@@ -1070,8 +1079,9 @@ QueryConsts make_consts(const gpdf_params &p, const float *origin) {
     C.combine = p.combine;
     C.grad_mode = p.grad_mode;
     C.knn_q = p.selection == GPDF_SEL_KNN ? p.knn_q : 0;
-    C.signed_ = origin != nullptr;
+    C.signed_ = origin != nullptr || d_origin != nullptr;
     if (origin) { C.ox = origin[0]; C.oy = origin[1]; C.oz = origin[2]; }
+    C.d_origin = d_origin;
     C.ld = p.length_scale;
     C.sd = p.noise_sigma;
     C.hv = p.voxel_size;
@@ -1080,6 +1090,19 @@ QueryConsts make_consts(const gpdf_params &p, const float *origin) {
     C.omind = p.occ_min;
     C.omaxd = p.occ_max;
     return C;
+}
+
+// per-cell cluster lists for at least cap cells (reallocated when larger)
+hipError_t ensure_cell_lists(gpdf_ctx *c, int64_t cap) {
+    if (cap <= c->cap_cells) return hipSuccess;
+    hipError_t e;
+    if (c->d_cell_list && (e = hipFree(c->d_cell_list)) != hipSuccess) return e;
+    c->d_cell_list = nullptr;
+    c->cap_cells = 0;
+    if ((e = hipMalloc((void **)&c->d_cell_list, sizeof(int4) * size_t(cap) * kCellListStride)) != hipSuccess)
+        return e;
+    c->cap_cells = cap;
+    return hipSuccess;
 }
 
 // BF16 copies of [W; alpha] for the current model (once per training)
@@ -1129,32 +1152,38 @@ gpdf_status build_bf16(gpdf_ctx *c) {
 }
 
 gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin, float *dist,
-                  float *grad, float *var, uint8_t *valid, float *aux, int32_t correct) {
+                  float *grad, float *var, uint8_t *valid, float *aux, int32_t correct, const uint32_t *dm,
+                  const float *d_origin) {
     hipStream_t s = c->stream;
     const Model &M = c->model;
+    const bool eager = dm == nullptr;
     if (!M.trained) return fail(c, GPDF_E_NOT_TRAINED, "query before training");
     if (m < 0 || m > c->p.max_queries) return fail(c, GPDF_E_CAPACITY, "query: m exceeds max_queries");
     if (m > 0 && (!dist || !valid || !d_q)) return fail(c, GPDF_E_INVALID_ARG, "query: null buffer");
     if (origin && !(std::isfinite(origin[0]) && std::isfinite(origin[1]) && std::isfinite(origin[2])))
         return fail(c, GPDF_E_INVALID_ARG, "query: non-finite origin");
     c->last_queries = m;
+    uint32_t *cnt = c->d_cnt;
     // per-call counters
     fill_u64(c->d_stat + ST_NONFINITE_Q, 0ull, 1, s);
     fill_u64(c->d_stat + ST_VALID_Q, 0ull, 1, s);
     fill_u64(c->d_stat + ST_REFINE, 0ull, 1, s);
     fill_u64(c->d_stat + ST_CELLS, 0ull, 1, s);
     fill_u64(c->d_stat + ST_PAIRS, 0ull, 3, s);
+    fill_u32(cnt + CNT_CELLS, 0u, 3, s);  // cells, chunks, re-evaluation chunks
     if (m == 0) return GPDF_OK;
     hipError_t e;
-    if (M.nclusters == 0) {
+    if (M.host_counts && M.nclusters == 0) {
         // nothing to select: every query is invalid
         hipLaunchKernelGGL(k_all_invalid, dim3(blocks_for(m)), dim3(kQT), 0, s, m, dist, grad, var,
                            valid, aux);
         return (e = hipGetLastError()) == hipSuccess ? GPDF_OK : hip_fail(c, e, "query launch");
     }
-    const QueryConsts C = make_consts(c->p, origin);
+    const QueryConsts C = make_consts(c->p, origin, d_origin);
     const bool vox = c->p.voxel_size > 0.0;
     const bool knn = C.knn_q > 0;
+    if (!eager && (knn || c->p.precision == GPDF_PREC_BF16 || correct))
+        return fail(c, GPDF_E_INVALID_ARG, "query with device counts: NEIGHBOR27, FP32/FP64, no correction");
     const double edge = vox ? 8.0 * c->p.voxel_size : c->p.cluster_size;
     const int kern = c->p.kernel;
     const ModelView Mo{c->d_pts, c->d_alpha64, c->d_coff, c->d_woff, c->d_W32, c->d_W64,
@@ -1167,45 +1196,46 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     fill_u64(c->d_qhash, (unsigned long long)kNoKey, qcap, s);
     fill_u32(c->d_qhash_cnt, 0u, qcap, s);
     HashView qh{c->d_qhash, qmask};
-    hipLaunchKernelGGL(k_qcells, dim3(blocks_for(m)), dim3(kQT), 0, s, d_q, m, vox ? 1 : 0,
+    hipLaunchKernelGGL(k_qcells, dim3(blocks_for(m)), dim3(kQT), 0, s, d_q, m, dm, vox ? 1 : 0,
                        c->p.voxel_size, c->p.cluster_size, qh, c->d_qhash_cnt, c->d_qslot, c->d_qrank,
                        dist, grad, var, valid, aux, c->d_stat);
     count_occupied(c->d_qhash, qcap, c->d_tile_cnt, c->d_tile_off, c->d_part, s);
     const int64_t ntiles = compact_tiles(qcap);
     hipLaunchKernelGGL(k_cells_compact, dim3(unsigned(ntiles)), dim3(256), 0, s, c->d_qhash,
                        c->d_qhash_cnt, qcap, c->d_tile_off, ntiles, c->d_qhash_cell, c->d_cell_key,
-                       c->d_cell_cnt, c->d_cell_chunks, c->d_stat);
-    unsigned long long ncells = 0;
-    if ((e = hipMemcpyAsync(&ncells, c->d_stat + ST_CELLS, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_fail(c, e, "query: read cell count");
-    if (ncells == 0) return GPDF_OK;
-    const int64_t nc = int64_t(ncells);
-    exclusive_scan_u32(c->d_cell_cnt, c->d_cell_off, nc, c->d_part, s);
-    exclusive_scan_u32(c->d_cell_chunks, c->d_chunk_off, nc, c->d_part, s);
-    hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, c->d_cell_chunks,
+                       c->d_cell_cnt, c->d_cell_chunks, c->d_stat, cnt + CNT_CELLS);
+    // the number of cells: read back (eager), else bounded by the queries
+    int64_t nc = std::min<int64_t>(m, qcap);
+    if (eager) {
+        uint32_t ncells = 0;
+        if ((e = hipMemcpyAsync(&ncells, cnt + CNT_CELLS, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(c, e, "query: read cell count");
+        if (ncells == 0) return GPDF_OK;
+        nc = int64_t(ncells);
+    }
+    const uint32_t *dnc = cnt + CNT_CELLS;
+    exclusive_scan_u32(c->d_cell_cnt, c->d_cell_off, nc, c->d_part, s, dnc);
+    exclusive_scan_u32(c->d_cell_chunks, c->d_chunk_off, nc, c->d_part, s, dnc, cnt + CNT_CHUNKS);
+    hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_cell_chunks,
                        c->d_chunk_off, c->d_chunk);
     if (!knn && nc > c->cap_cells) {
+        if (!eager) return fail(c, GPDF_E_CAPACITY, "query: cell lists not allocated for the bound");
         // grow the per-cell cluster lists (one reallocation per new maximum)
         const int64_t cap = std::min<int64_t>(c->p.max_queries + 1, nc + nc / 4 + 1024);
-        if ((e = hipFree(c->d_cell_list)) != hipSuccess) return hip_fail(c, e, "query: cell lists");
-        c->d_cell_list = nullptr;
-        c->cap_cells = 0;
-        if ((e = hipMalloc((void **)&c->d_cell_list, sizeof(int4) * size_t(cap) * kCellListStride)) != hipSuccess)
-            return hip_fail(c, e, "query: cell lists");
-        c->cap_cells = cap;
+        if ((e = ensure_cell_lists(c, cap)) != hipSuccess) return hip_fail(c, e, "query: cell lists");
     }
     if (!knn)
-        hipLaunchKernelGGL(k_cell_lists, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, c->d_cell_key,
+        hipLaunchKernelGGL(k_cell_lists, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_cell_key,
                            c->d_chash, c->chash_mask, c->d_chash_val, c->d_pd, c->d_coff,
                            c->d_woff, c->d_cell_list);
-    hipLaunchKernelGGL(k_scatter_order, dim3(blocks_for(m)), dim3(kQT), 0, s, c->d_qslot, c->d_qrank, m,
+    hipLaunchKernelGGL(k_scatter_order, dim3(blocks_for(m)), dim3(kQT), 0, s, c->d_qslot, c->d_qrank, m, dm,
                        c->d_qhash_cell, c->d_cell_off, c->d_order);
     stage_end(c, GPDF_MS_GROUP);
     // 2. evaluation; the chunk count stays on the device (grid is an upper bound)
     const int64_t max_chunks = nc + (m + 63) / 64;
     const unsigned grid = blocks_for(max_chunks * 64, kEvalT);
-    const Grouping G{c->d_chunk, c->d_chunk_off + nc, c->d_cell_cnt, c->d_cell_off, c->d_order};
+    const Grouping G{c->d_chunk, cnt + CNT_CHUNKS, c->d_cell_cnt, c->d_cell_off, c->d_order};
     Outputs O{dist, grad, var, aux, valid, c->d_refine, c->d_stat};
     if (c->p.precision == GPDF_PREC_FP64) {
         stage_begin(c, GPDF_MS_EVAL);
@@ -1237,15 +1267,15 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         const unsigned rgrid = blocks_for(m);
         hipLaunchKernelGGL(k_refine_count, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
                            c->d_stat + ST_REFINE, m, c->d_rcnt, c->d_rrank);
-        hipLaunchKernelGGL(k_refine_chunks, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, c->d_rcnt,
+        hipLaunchKernelGGL(k_refine_chunks, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rcnt,
                            c->d_rchunks);
-        exclusive_scan_u32(c->d_rcnt, c->d_roff, nc, c->d_part, s);
-        exclusive_scan_u32(c->d_rchunks, c->d_rchunk_off, nc, c->d_part, s);
-        hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, c->d_rchunks,
+        exclusive_scan_u32(c->d_rcnt, c->d_roff, nc, c->d_part, s, dnc);
+        exclusive_scan_u32(c->d_rchunks, c->d_rchunk_off, nc, c->d_part, s, dnc, cnt + CNT_RCHUNKS);
+        hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rchunks,
                            c->d_rchunk_off, c->d_rchunk);
         hipLaunchKernelGGL(k_refine_scatter, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
                            c->d_stat + ST_REFINE, m, c->d_rrank, c->d_roff, c->d_rorder);
-        const Grouping R{c->d_rchunk, c->d_rchunk_off + nc, c->d_rcnt, c->d_roff, c->d_rorder};
+        const Grouping R{c->d_rchunk, cnt + CNT_RCHUNKS, c->d_rcnt, c->d_roff, c->d_rorder};
         Outputs O64 = O;
         O64.refine = nullptr;
         launch_query_k<double>(c, kern, knn, grid, s, d_q, R, c->d_cell_list, Mo, C, O64, 1);

@@ -127,6 +127,8 @@ __global__ void k_clusters(const uint64_t *__restrict__ key, const uint32_t *__r
                 const uint32_t c = pos[i];
                 coff[c] = int32_t(i);
                 ckey[c] = pack_key(cl[0], cl[1], cl[2]);
+            } else if (flag[i] && int64_t(pos[i]) == cap) {
+                coff[cap] = int32_t(i);  // the last kept cluster ends where the first dropped one starts
             }
         } else {
             const uint32_t s = val[i];
@@ -135,6 +137,8 @@ __global__ void k_clusters(const uint64_t *__restrict__ key, const uint32_t *__r
                 const uint32_t c = pos[i];
                 coff[c] = int32_t(i);
                 ckey[c] = k;
+            } else if (flag[i] && int64_t(pos[i]) == cap) {
+                coff[cap] = int32_t(i);  // the last kept cluster ends where the first dropped one starts
             }
         }
     }

@@ -1,0 +1,74 @@
+"""GPU checks of the per-frame graph (batching extension): a sequence of
+frames fused through gpdf_fuse_frame_graph gives bitwise the same global grid
+as gpdf_fuse_frame after every frame, with eager library work between the
+replays; the graph reports capacity overflows in the status bits."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2407_09649_amd as P
+from paper_2407_09649_amd import scenes as S
+
+from parity import small_params
+
+pytestmark = pytest.mark.gpu
+
+
+def _frames(seed, n, beams=16, az=256):
+    path = S.sensor_path(seed, n_frames=n)
+    scene = S.lidar_scene(seed, keep_clear_xy=path[:, :2], clearance=1.5)
+    rng = np.random.default_rng(seed)
+    return path, [S.lidar_frame(scene, o, rng, n_beams=beams, n_azimuth=az) for o in path]
+
+
+def _params(**kw):
+    base = dict(voxel_size=0.1, max_points=8192, max_queries=1 << 21, global_capacity=1 << 22)
+    base.update(kw)
+    return small_params(**base)
+
+
+def test_graph_replays_equal_eager_frames(dev):
+    path, frames = _frames(5, 5)
+    p = _params()
+    eager = P.Context(p, device=dev)
+    graph = P.Context(p, device=dev)
+    probe = torch.from_numpy(S.lidar_band_queries(frames[0], radius_cells=2)[:5000]).to(dev)
+    for i, (pts, o) in enumerate(zip(frames, path)):
+        x = torch.from_numpy(pts).to(dev)
+        o32 = np.asarray(o, np.float32)
+        eager.fuse(x, o32)
+        graph.fuse_graph(x, o32)
+        # eager work on the graph's context and stream between replays
+        graph.query_global(probe)
+        torch.cuda.synchronize()
+        a, b = eager.export_global(), graph.export_global()
+        for k in ("key", "D", "V", "stamp"):
+            assert np.array_equal(a[k], b[k]), (i, k)
+        sa, sb = eager.stats(), graph.stats()
+        assert sa["test_points"] == sb["test_points"] and sa["clusters"] == sb["clusters"], (i, sa, sb)
+        assert sb["status_bits"] & P.STATUS_CAPACITY == 0
+    ra = eager.query_global(probe)
+    rb = graph.query_global(probe)
+    for k in ra:
+        assert torch.equal(ra[k], rb[k]), k
+    eager.close()
+    graph.close()
+
+
+def test_graph_reports_capacity_overflow(dev):
+    path, frames = _frames(6, 2)
+    ctx = P.Context(_params(max_clusters=32), device=dev)
+    for pts, o in zip(frames, path):
+        ctx.fuse_graph(torch.from_numpy(pts).to(dev), np.asarray(o, np.float32))
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    assert st["status_bits"] & P.STATUS_CAPACITY
+    assert st["clusters"] == 32
+    ctx.close()
+
+
+def test_graph_rejects_knn(dev):
+    ctx = P.Context(_params(selection=P.SEL_KNN, knn_q=8), device=dev)
+    with pytest.raises(P.GpdfError):
+        ctx.fuse_graph(torch.zeros((10, 3), device=dev), np.zeros(3, np.float32))
+    ctx.close()
