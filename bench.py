@@ -18,7 +18,20 @@ kernel of the band query, timed with HIP events on the context stream.
 The cpu_baseline leg runs the same step with the FP64 oracle on the host
 cores and checks every GPU output of the last step against it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+The ``extensions`` object reports, on the same GPU:
+  precision   the band query of the same frame with BF16 MFMA products and in
+              FP64, rate and distance error against the oracle;
+  batched     8,192 local GPs of 8-256 points on planar patches with 524,288
+              queries: autotuned launch shapes, FP64 training, FP32 and BF16
+              queries, error against the oracle on a sample of the patches;
+  sequence    100 frames of a moving sensor fused eagerly and through the
+              per-frame HIP graph (bitwise compared), then 4M global queries;
+  correction  the learned correction trained on the GPU on pairs the method
+              generates (GP output vs brute-force nearest point), its held-out
+              gain, and its fused inference rate.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-extensions]
 """
 from __future__ import annotations
 
@@ -34,7 +47,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GP distance+gradient queries/sec at <=1e-4 m error vs FP64 oracle, 1 GPU"
-PEAK_FP32_VECTOR = 157.3e12     # MI355X published FP32 vector peak, flop/s
+PEAK_FP32_VECTOR = 157.3e12     # MI355X published FP32 vector peak (packed FMA), flop/s
+PEAK_FP32_NONPACKED = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, the issuable peak here
 PEAK_HBM = 8.0e12               # bytes/s
 ORIGIN = (0.0, 0.0, 1.5)
 
@@ -56,12 +70,35 @@ def algorithmic_flops(st):
     return 2 * st["eval_tri"] + 24 * st["eval_points"] + 40 * st["eval_pairs"]
 
 
+class Timer:
+    """HIP events on a stream, median of repeated calls."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def median(self, fn, reps=5, warm=1):
+        torch = self.torch
+        for _ in range(warm):
+            fn()
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(self.stream)
+            fn()
+            b.record(self.stream)
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -109,12 +146,17 @@ def main():
     stages = {k: v / args.steps for k, v in stage_sum.items()}
     value = m / (ms_per_step / 1e3)
 
+    # query-only rate: the whole gpdf_query_distance call, median of 20 runs
+    timer = Timer(torch, ctx.stream)
+    q_ms = timer.median(lambda: ctx.query(qd, origin=ORIGIN, out=out), reps=20)
+
     # dominant kernel: the FP32 evaluation of the band query
     flops = algorithmic_flops(st)
     eval_s = stages["eval"] / 1e3
     achieved = flops / eval_s
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                "frac_issuable": achieved / PEAK_FP32_NONPACKED,
                 "kernel": "k_query_cells<float, Matern-3/2>",
                 "flops_per_launch": flops, "pairs": st["eval_pairs"],
                 "kernel_evals": st["eval_points"], "variance_fmas": st["eval_tri"],
@@ -131,17 +173,193 @@ def main():
                    "clusters": st["clusters"], "band_queries": m, "global_queries": int(qg.shape[0]),
                    "test_points": st["test_points"], "global_voxels": st["global_voxels"]},
         "stages_ms": stages,
-        "query_only_rate": m / ((stages["group"] + stages["eval"] + stages["refine"]) / 1e3),
+        "query_only_ms": q_ms,
+        "query_only_rate": m / (q_ms / 1e3),
         "refined_fraction": st["refined_queries"] / max(st["valid_queries"], 1),
         "roofline": roofline,
         "input_generation_s": gen_s,
     }
+    gpu_out = {k: v.cpu().numpy() for k, v in out.items()}
+    others = {}
+    ext = {}
+    if not args.no_extensions:
+        ext["precision"], others = precision_leg(P, torch, dev, x, qd, timer)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"], res["parity"] = run_cpu_baseline(
-            pts, q, qg, {k: v.cpu().numpy() for k, v in out.items()},
-            {k: v.cpu().numpy() for k, v in glob.items()}, st["test_points"])
+        res["cpu_baseline"], res["parity"], ref = run_cpu_baseline(
+            pts, q, qg, gpu_out, {k: v.cpu().numpy() for k, v in glob.items()}, st["test_points"])
+        for name, g in others.items():
+            ext["precision"][name].update(dist_errors(g, ref))
     ctx.close()
+    if not args.no_extensions:
+        ext["batched"] = batched_leg(P, torch, dev)
+        ext["sequence"] = sequence_leg(P, torch, dev)
+        ext["correction"] = correction_leg(P, torch, dev)
+        res["extensions"] = ext
     print(json.dumps(res))
+
+
+def dist_errors(g, ref):
+    v = ref["valid"]
+    e = np.abs(g["dist"][v].astype(np.float64) - ref["dist"][v])
+    ge = np.abs(g["grad"][v].astype(np.float64) - ref["grad"][v]).max(axis=1)
+    return {"validity_equal": bool((g["valid"].astype(bool) == v).all()),
+            "median_dist_err_m": float(np.median(e)), "p99_dist_err_m": float(np.quantile(e, 0.99)),
+            "max_dist_err_m": float(e.max()), "max_grad_err": float(ge.max())}
+
+
+def precision_leg(P, torch, dev, x, qd, timer):
+    """The band query of the same frame with BF16 MFMA products and in FP64."""
+    m = qd.shape[0]
+    rep, outs = {}, {}
+    for name, prec in (("bf16", P.PREC_BF16), ("fp64", P.PREC_FP64)):
+        c = P.Context(P.Params.default(voxel_size=0.1, precision=prec), device=dev)
+        c.train(x)
+        o = dict(dist=torch.empty(m, device=dev), grad=torch.empty((m, 3), device=dev),
+                 var=torch.empty(m, device=dev), valid=torch.empty(m, dtype=torch.uint8, device=dev))
+        t = Timer(torch, c.stream).median(lambda: c.query(qd, origin=ORIGIN, aux=False, out=o), reps=10)
+        rep[name] = {"query_ms": t, "query_rate": m / (t / 1e3)}
+        outs[name] = {k: v.cpu().numpy() for k, v in o.items()}
+        c.close()
+    return rep, outs
+
+
+def batched_leg(P, torch, dev):
+    """8,192 local GPs of U{8..256} points on planar patches, 64 queries each:
+    autotuned launch shapes, then FP32 and BF16 queries; the error against the
+    oracle is taken on a sample of 256 patches (each query's 27 neighbour
+    cells hold only its own patch, so a model of the sampled patches gives
+    the oracle value of their queries)."""
+    import oracle as O
+    from paper_2407_09649_amd import scenes as S
+    ps = S.planar_patches(3)
+    x = torch.from_numpy(ps.points).to(dev)
+    q = torch.from_numpy(ps.queries).to(dev)
+    base = dict(cluster_size=0.8, max_points=1 << 21, max_factor_elems=(1 << 31) - 1, max_queries=1 << 20)
+    rep = {"gps": int(len(ps.sizes)), "points": int(ps.points.shape[0]), "queries": int(ps.queries.shape[0]),
+           "fp64_train_flop": float((ps.sizes.astype(np.float64) ** 3 / 3 + 2 * ps.sizes ** 2).sum())}
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(len(ps.sizes), 256, replace=False))
+    starts = np.concatenate([[0], np.cumsum(ps.sizes)])
+    sp = np.concatenate([ps.points[starts[i]:starts[i + 1]] for i in sample])
+    qi = np.concatenate([np.arange(64 * i, 64 * i + 64) for i in sample])
+    ref = O.Model(O.Params(cell=0.8), sp).query(ps.queries[qi])
+    for name, prec in (("fp32", P.PREC_FP32), ("bf16", P.PREC_BF16)):
+        c = P.Context(P.Params.default(precision=prec, timing=1, **base), device=dev)
+        tune = c.autotune(x, q)
+        t = Timer(torch, c.stream)
+        train_ms = t.median(lambda: c.train(x), reps=3)
+        r = {}
+        q_ms = t.median(lambda: r.update(c.query(q)), reps=5)
+        g = {k: v.cpu().numpy()[qi] for k, v in r.items()}
+        st = c.stats()
+        rep[name] = {"tuning": c.get_tuning(), "autotune_ms": tune, "train_ms": train_ms,
+                     "query_ms": q_ms, "query_rate": ps.queries.shape[0] / (q_ms / 1e3),
+                     "refined_queries": st["refined_queries"], **dist_errors(g, ref)}
+        c.close()
+    return rep
+
+
+def sequence_leg(P, torch, dev, n_frames=100):
+    """100 frames of the LiDAR scene from a sensor moving 0.5 m per frame,
+    fused eagerly and through the per-frame HIP graph; then 4M global queries
+    at observed voxels jittered within the voxel."""
+    from paper_2407_09649_amd import scenes as S
+    t0 = time.time()
+    path = S.sensor_path(4, n_frames=n_frames)
+    scene = S.lidar_scene(4, keep_clear_xy=path[:, :2], clearance=1.5)
+    rng = np.random.default_rng(4)
+    frames = [torch.from_numpy(S.lidar_frame(scene, o, rng)).to(dev) for o in path]
+    gen = time.time() - t0
+    prm = dict(voxel_size=0.1, max_points=1 << 16, max_queries=3_600_000, global_capacity=1 << 26)
+    rep = {"frames": n_frames, "input_generation_s": gen, "max_points": prm["max_points"]}
+    grids = {}
+    for mode in ("eager", "graph"):
+        c = P.Context(P.Params.default(**prm), device=dev)
+        if mode == "graph":
+            c.fuse_graph(frames[0], path[0].astype(np.float32))  # capture + frame 0
+        else:
+            c.fuse(frames[0], path[0].astype(np.float32))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(1, n_frames):
+            o = path[i].astype(np.float32)
+            (c.fuse_graph if mode == "graph" else c.fuse)(frames[i], o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        st = c.stats()
+        rep[mode] = {"ms_per_frame": 1e3 * dt / (n_frames - 1), "global_voxels": st["global_voxels"],
+                     "status_bits": st["status_bits"]}
+        grids[mode] = c.export_global()
+        if mode == "graph":
+            keys = grids[mode]["key"]
+            r = np.random.default_rng(5)
+            kk = keys[r.integers(0, len(keys), 4_000_000)]
+            cc = np.stack([(kk >> np.uint64(42)) & np.uint64(0x1FFFFF), (kk >> np.uint64(21)) & np.uint64(0x1FFFFF),
+                           kk & np.uint64(0x1FFFFF)], 1).astype(np.int64) - (1 << 20)
+            qg = torch.from_numpy(((cc + 0.5 + r.uniform(-0.5, 0.5, size=cc.shape)) * 0.05).astype(np.float32)).to(dev)
+            out = {}
+            tq = Timer(torch, c.stream).median(lambda: out.update(c.query_global(qg)), reps=10)
+            rep["global_query"] = {"queries": 4_000_000, "ms": tq, "rate": 4e6 / (tq / 1e3),
+                                   "valid_fraction": float(out["valid"].float().mean())}
+        c.close()
+    rep["graph_equals_eager"] = all(np.array_equal(grids["eager"][k], grids["graph"][k])
+                                    for k in ("key", "D", "V", "stamp"))
+    return rep
+
+
+def correction_leg(P, torch, dev, n_train_scenes=40, n_eval_scenes=32, per_scene=250_000):
+    """The learned correction: pairs (GP output, brute-force nearest training
+    point) from sphere scenes with new seeds, KNN Q = 8, queries 0.1-3 m
+    outside the sphere; trained on the GPU (BF16 MFMA, FP32 master weights)
+    and evaluated on held-out scenes, gated and ungated."""
+    from paper_2407_09649_amd import scenes as S
+    c = P.Context(P.Params.default(selection=P.SEL_KNN, knn_q=8, cluster_size=0.4, max_queries=1 << 20),
+                  device=dev)
+
+    def pairs(seed0, n):
+        fs, ts, ds, trs, vs = [], [], [], [], []
+        for i in range(n):
+            sc = S.sphere_scene(seed0 + i, n_queries=0)
+            p = torch.from_numpy(sc.points).to(dev)
+            qq = torch.from_numpy(S.sphere_eval_queries(seed0 + 50_000 + i, per_scene)).to(dev)
+            c.train(p)
+            r = c.query(qq)
+            f = c.mlp_features(r)
+            tr = c.nearest_distance(p, qq)
+            ok = r["valid"].bool() & torch.isfinite(f).all(1)
+            fs.append(f[ok]); ts.append((tr - r["dist"])[ok]); ds.append(r["dist"][ok])
+            trs.append(tr[ok]); vs.append(r["var"][ok])
+        return torch.cat(fs), torch.cat(ts), torch.cat(ds), torch.cat(trs), torch.cat(vs)
+
+    t0 = time.time()
+    f, t, _, _, _ = pairs(10_000, n_train_scenes)
+    torch.cuda.synchronize()
+    gen = time.time() - t0
+    c.mlp_init(seed=0)
+    epochs, batch = 2, 4096
+    t1 = time.perf_counter()
+    loss = c.mlp_train(f, t, epochs=epochs, batch=batch, lr=2e-3, seed=1)
+    train_s = time.perf_counter() - t1
+    fe, te, de, tre, ve = pairs(20_000, n_eval_scenes)
+    r = {}
+    tm = Timer(torch, c.stream).median(lambda: r.update(rr=c.mlp_forward(fe)), reps=5)
+    rr = r["rr"]
+    gate = c.params.mlp_gate
+    g = ve <= gate
+
+    def err(mask):
+        e0 = (de - tre)[mask].double()
+        e1 = (de + rr - tre)[mask].double()
+        return {"n": int(mask.sum()), "mse_plain": float((e0 ** 2).mean()), "mse_corrected": float((e1 ** 2).mean()),
+                "mae_plain": float(e0.abs().mean()), "mae_corrected": float(e1.abs().mean())}
+
+    rep = {"train_pairs": int(f.shape[0]), "pair_generation_s": gen, "epochs": epochs, "batch": batch,
+           "train_s": train_s, "train_samples_per_s": epochs * f.shape[0] / train_s, "final_loss": loss,
+           "eval_queries": int(fe.shape[0]), "forward_ms": tm, "forward_rate": fe.shape[0] / (tm / 1e3),
+           "gate": gate, "gated_fraction": float(g.float().mean()),
+           "gated": err(g), "ungated": err(torch.ones_like(g))}
+    c.close()
+    return rep
 
 
 def run_cpu_baseline(pts, q, qg, g, gg, n_test):
@@ -184,7 +402,7 @@ def run_cpu_baseline(pts, q, qg, g, gg, n_test):
                       f"{ntp} test voxels {dt[1]:.2f} s, {q.shape[0]} band queries "
                       f"{dt[2]:.2f} s, {qg.shape[0]} global queries {dt[3]:.2f} s"),
            "host_cpu": _cpu_model()}
-    return cpu, parity
+    return cpu, parity, ref
 
 
 def _cpu_model():

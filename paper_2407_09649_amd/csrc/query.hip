@@ -696,25 +696,26 @@ __device__ __forceinline__ void cells_chunk(uint32_t wave, const float *__restri
     }
 }
 
-// work == NULL: one wavefront (workgroup) per chunk, XCD-aware order.
-// Otherwise persistent: a fixed set of wavefronts takes chunks from the
-// counter *work (zero at launch) until none is left.
-template <typename T, int KERN, int MODE>
+// PERSIST == false: one wavefront (workgroup) per chunk, XCD-aware order.
+// PERSIST: a fixed set of wavefronts takes chunks from the counter *work
+// (zero at launch) until none is left.  Two instances, so that each keeps
+// the register allocation of a single chunk body.
+template <typename T, int KERN, int MODE, bool PERSIST>
 __global__ __launch_bounds__(kEvalT) void k_query_cells(const float *__restrict__ q, Grouping G,
                                                      const int4 *__restrict__ lists, ModelView Mo,
                                                      QueryConsts C, Outputs O, uint32_t *work) {
     const uint32_t nch = *G.nchunks;
-    if (!work) {
+    if constexpr (!PERSIST) {
         const uint32_t wave = xcd_item(nch);
         if (wave < nch) cells_chunk<T, KERN, MODE>(wave, q, G, lists, Mo, C, O);
-        return;
-    }
-    while (true) {
-        uint32_t w = 0;
-        if ((threadIdx.x & 63) == 0) w = atomicAdd(work, 1u);
-        w = uniform(uint32_t(__shfl(int(w), 0, 64)));
-        if (w >= nch) break;
-        cells_chunk<T, KERN, MODE>(w, q, G, lists, Mo, C, O);
+    } else {
+        while (true) {
+            uint32_t w = 0;
+            if ((threadIdx.x & 63) == 0) w = atomicAdd(work, 1u);
+            w = uniform(uint32_t(__shfl(int(w), 0, 64)));
+            if (w >= nch) break;
+            cells_chunk<T, KERN, MODE>(w, q, G, lists, Mo, C, O);
+        }
     }
 }
 
@@ -1001,9 +1002,12 @@ void launch_query(bool knn, unsigned grid, hipStream_t s, const float *q, const 
                   uint32_t *work) {
     if (knn)
         hipLaunchKernelGGL((k_query_knn<T, KERN, MODE>), dim3(grid), dim3(kEvalT), 0, s, q, G, Mo, C, O);
+    else if (work)
+        hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, true>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
+                           Mo, C, O, work);
     else
-        hipLaunchKernelGGL((k_query_cells<T, KERN, MODE>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists, Mo,
-                           C, O, work);
+        hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, false>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
+                           Mo, C, O, work);
 }
 
 template <typename T, int KERN>
