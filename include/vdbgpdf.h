@@ -117,6 +117,9 @@ typedef struct {
     int64_t eval_pairs;        /* last query, FP32 27-cell pass: (query, cluster) pairs */
     int64_t eval_points;       /*   kernel evaluations, sum of n over the pairs */
     int64_t eval_tri;          /*   variance multiply-adds, sum of n (n + 1) / 2 */
+    int64_t refine_dist;       /* last query: FP32 estimates above the distance, */
+    int64_t refine_grad;       /*   gradient and variance thresholds (a query   */
+    int64_t refine_var;        /*   can count in several)                       */
     uint32_t status_bits;      /* GPDF_STATUS_* set since the last read */
     uint32_t pad0;
     float ms[8];               /* with timing = 1: GPU time of the last run of

@@ -81,7 +81,7 @@ class Stats(C.Structure):
         "clusters", "points", "nonpd_clusters", "skipped_points", "queries",
         "valid_queries", "refined_queries", "test_points", "fused",
         "fuse_skipped", "global_voxels", "gated", "eval_pairs", "eval_points",
-        "eval_tri")] + [
+        "eval_tri", "refine_dist", "refine_grad", "refine_var")] + [
         ("status_bits", C.c_uint32), ("pad0", C.c_uint32), ("ms", C.c_float * 8)]
 
     STAGES = ("train", "group", "eval", "refine", "testpts", "fuse", "global", "mlp")

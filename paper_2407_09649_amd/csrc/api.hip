@@ -375,6 +375,9 @@ extern "C" gpdf_status gpdf_get_stats(gpdf_ctx *c, gpdf_stats *out) {
     out->eval_pairs = int64_t(h[ST_PAIRS]);
     out->eval_points = int64_t(h[ST_POINTS]);
     out->eval_tri = int64_t(h[ST_TRI]);
+    out->refine_dist = int64_t(h[ST_REF_D]);
+    out->refine_grad = int64_t(h[ST_REF_G]);
+    out->refine_var = int64_t(h[ST_REF_V]);
     uint32_t bits = 0;
     if (h[ST_HASH_FULL]) bits |= GPDF_STATUS_HASH_FULL;
     if (h[ST_GLOBAL_FULL]) bits |= GPDF_STATUS_GLOBAL_FULL;

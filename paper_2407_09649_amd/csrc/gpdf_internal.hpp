@@ -230,6 +230,9 @@ enum Stat : int {
     ST_PAIRS,        // (query, cluster) pairs of the last evaluation pass
     ST_POINTS,       // kernel evaluations (sum of n over pairs)
     ST_TRI,          // variance multiply-adds (sum of n (n + 1) / 2 over pairs)
+    ST_REF_D,        // last query: FP32 error estimates above the distance,
+    ST_REF_G,        // gradient and variance thresholds
+    ST_REF_V,
     ST_CAPACITY,     // a capacity was exceeded on the device (clusters, cluster
                      // size, factor storage, test voxels)
     ST_COUNT
@@ -265,6 +268,8 @@ struct QueryConsts {
     double ld, sd, hv, hc;  // FP64 copies: l, s, voxel, cell
     double lamd, omind, omaxd;
     double ad, cd;          // FP64 copies of a and c
+    float cap_hi[3], cap_lo[3];     // d, Lambda, gradient scale at occ_max and occ_min
+    double cap_hid[3], cap_lod[3];  // the same in FP64
 };
 
 struct Model {

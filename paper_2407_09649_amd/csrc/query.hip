@@ -471,8 +471,20 @@ __device__ __forceinline__ void finish_pair(const PairRaw<T> &r, int n, const Qu
         gsc = RT<T>::rcp(oc * d);            // grad d = G / (o d)
         sens = float(RT<T>::rcp(oc) + fabs(lam) * RT<T>::rcp(d));
     }
-    // below the lower cap the returned distance is the constant r(occ_min):
-    // its gradient is zero (at the upper cap Lambda(occ_max) grad o is kept)
+    // at a cap the distance, Lambda and the gradient scale are the constants
+    // of that cap, evaluated once in FP64 (in FP32, 1 - occ_max itself would
+    // carry a relative error of ~1e-2); below the lower cap the returned
+    // distance is the constant r(occ_min) and its gradient is zero, at the
+    // upper cap Lambda(occ_max) grad o is kept
+    if (o >= omax) {
+        d = f32 ? T(C.cap_hi[0]) : T(C.cap_hid[0]);
+        lam = f32 ? T(C.cap_hi[1]) : T(C.cap_hid[1]);
+        gsc = f32 ? T(C.cap_hi[2]) : T(C.cap_hid[2]);
+    } else if (o <= omin) {
+        d = f32 ? T(C.cap_lo[0]) : T(C.cap_lod[0]);
+        lam = f32 ? T(C.cap_lo[1]) : T(C.cap_lod[1]);
+        gsc = f32 ? T(C.cap_lo[2]) : T(C.cap_lod[2]);
+    }
     const T gs = o < omin ? T(0) : gsc;
     const T gx = gs * r.gx, gy = gs * r.gy, gz = gs * r.gz;
     const T v = lam * lam * u;
@@ -485,12 +497,21 @@ __device__ __forceinline__ void finish_pair(const PairRaw<T> &r, int n, const Qu
         const float sS = fsqrt(r.S);
         const float dO = C.err_c * kEps * sS + 2.f * kEps * oc;
         gn = fsqrt(fmaf(gz, gz, fmaf(gy, gy, gx * gx)));
-        ed = fabsf(lam) * dO + 4.f * kEps * d;
-        eg = gsc * C.err_c * kEps * sS * frcp(C.a) + gn * sens * dO + 8.f * kEps * gn;
-        ev = 2.f * sens * dO + 4.f * kEps * float(n) * frcp(fmaxf(u, 1e-30f)) + 8.f * kEps;
-        // the lower-cap decision switches the gradient off: when o is within
-        // its error of the cap the FP32 decision is not reliable
-        if (fabsf(o - omin) <= 4.f * dO) eg = INFINITY;
+        // o clearly beyond a cap (by more than its error): d, Lambda and v are
+        // the constants of the cap and do not see the error of o; below the
+        // lower cap the gradient is exactly zero
+        const bool low = o < omin - 4.f * dO, high = o > omax + 4.f * dO;
+        const float dOe = (low || high) ? 0.f : dO;
+        ed = fabsf(lam) * dOe + 4.f * kEps * d;
+        eg = low ? 0.f : gsc * C.err_c * kEps * sS * frcp(C.a) + gn * sens * dOe + 8.f * kEps * gn;
+        ev = 2.f * sens * dOe + 4.f * kEps * float(n) * frcp(fmaxf(u, 1e-30f)) + 8.f * kEps;
+        // o within its error of the lower cap: the FP32 decision that switches
+        // the gradient off is not reliable, and the gradient is either zero
+        // or about gsc |grad o|
+        if (fabsf(o - omin) <= 4.f * dO) {
+            const float go = fsqrt(fmaf(float(r.gz), float(r.gz), fmaf(float(r.gy), float(r.gy), float(r.gx) * float(r.gx))));
+            eg += float(gsc) * go;
+        }
     }
     if (d < A.hd) {
         A.hd = d; A.hv = v; A.hgx = gx; A.hgy = gy; A.hgz = gz; A.ho = o; A.hu = u;
@@ -542,7 +563,7 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
                                     const QueryPoint &Q, const float4 *__restrict__ pts,
                                     const QueryConsts &C, const Outputs &O) {
     constexpr bool f32 = std::is_same<T, float>::value;
-    bool bad = false;
+    bool bad = false, bd = false, bg = false, bv = false;
     if (active && A.nq == 0) write_invalid(qi, O.dist, O.grad, O.var, O.valid, O.aux);
     if (active && A.nq > 0) {
         T D, V, Gx, Gy, Gz;
@@ -587,7 +608,12 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
         if (O.grad) { O.grad[3 * qi] = float(Gx); O.grad[3 * qi + 1] = float(Gy); O.grad[3 * qi + 2] = float(Gz); }
         if (O.var) O.var[qi] = float(V);
         if (O.aux) { O.aux[3 * qi] = float(A.ho); O.aux[3 * qi + 1] = float(A.hu); O.aux[3 * qi + 2] = float(A.ntot); }
-        if constexpr (f32) bad = !(Ed <= C.tau_d) || !(Eg <= C.tau_g) || !(Ev <= C.tau_v);
+        if constexpr (f32) {
+            bd = !(Ed <= C.tau_d);
+            bg = !(Eg <= C.tau_g);
+            bv = !(Ev <= C.tau_v);
+            bad = bd || bg || bv;
+        }
     }
     // one atomic per wavefront for the valid count and the refine records
     const int lane = threadIdx.x & 63;
@@ -595,6 +621,14 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
         const uint64_t nv = __ballot(active && A.nq > 0);
         if (lane == 0 && nv) atomicAdd(&O.stat[ST_VALID_Q], (unsigned long long)__popcll(nv));
         const uint64_t mb = __ballot(bad);
+        if (mb) {
+            const uint64_t b1 = __ballot(bd), b2 = __ballot(bg), b3 = __ballot(bv);
+            if (lane == 0) {
+                atomicAdd(&O.stat[ST_REF_D], (unsigned long long)__popcll(b1));
+                atomicAdd(&O.stat[ST_REF_G], (unsigned long long)__popcll(b2));
+                atomicAdd(&O.stat[ST_REF_V], (unsigned long long)__popcll(b3));
+            }
+        }
         if (mb && O.refine) {
             unsigned long long base = 0;
             if (lane == 0) base = atomicAdd(&O.stat[ST_REFINE], (unsigned long long)__popcll(mb));
@@ -1086,6 +1120,36 @@ QueryConsts make_consts(const gpdf_params &p, const float *origin, const float *
     C.signed_ = origin != nullptr || d_origin != nullptr;
     if (origin) { C.ox = origin[0]; C.oy = origin[1]; C.oz = origin[2]; }
     C.d_origin = d_origin;
+    // distance, Lambda and gradient scale at the two caps, in FP64
+    auto cap = [&](double o, double *out) {
+        if (matern) {
+            // t >= 0 with (1 + t) e^{-t} = o: Newton from the branch-point
+            // series (o near 1) or the asymptote t = y + log(1 + t), y = -log o
+            const double y = -std::log(o);
+            double t = o > 0.5 ? std::sqrt(2.0 * (1.0 - o)) : y + std::log(1.0 + y + std::log(1.0 + y));
+            for (int it = 0; it < 60; ++it) {
+                const double E = std::exp(-t), f = (1.0 + t) * E - o;
+                const double tn = t + f / (t * E);
+                if (tn == t) break;
+                t = tn;
+            }
+            const double tE = t * std::exp(-t);
+            out[0] = C.cd * t;
+            out[1] = -C.cd / tE;
+            out[2] = C.ad / tE;
+        } else {
+            const double dd = C.cd * std::sqrt(-2.0 * std::log(o));
+            out[0] = dd;
+            out[1] = -C.cd * C.cd / (o * dd);
+            out[2] = 1.0 / (o * dd);
+        }
+    };
+    cap(p.occ_max, C.cap_hid);
+    cap(p.occ_min, C.cap_lod);
+    for (int k = 0; k < 3; ++k) {
+        C.cap_hi[k] = float(C.cap_hid[k]);
+        C.cap_lo[k] = float(C.cap_lod[k]);
+    }
     C.ld = p.length_scale;
     C.sd = p.noise_sigma;
     C.hv = p.voxel_size;
@@ -1174,6 +1238,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     fill_u64(c->d_stat + ST_REFINE, 0ull, 1, s);
     fill_u64(c->d_stat + ST_CELLS, 0ull, 1, s);
     fill_u64(c->d_stat + ST_PAIRS, 0ull, 3, s);
+    fill_u64(c->d_stat + ST_REF_D, 0ull, 3, s);
     fill_u32(cnt + CNT_CELLS, 0u, 3, s);  // cells, chunks, re-evaluation chunks
     if (m == 0) return GPDF_OK;
     hipError_t e;
