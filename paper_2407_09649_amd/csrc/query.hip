@@ -38,6 +38,8 @@ constexpr int kQT = 256;            // threads per workgroup of the helper kerne
 constexpr int kEvalT = 64;
 constexpr int kWaves = kEvalT / 64;
 constexpr int kListStride = kCellListStride;
+// queries per chunk of the pair-parallel FP64 pass: one lane per pair
+__device__ __forceinline__ int refine_qpw(int nsel) { return nsel > 0 ? max(1, 64 / nsel) : 64; }
 // combination variants, fixed per launch: smooth minimum with the weighted
 // gradient, smooth minimum with the plain gradient mean, closest node
 constexpr int kModeSmooth = 0, kModeMean = 1, kModeHard = 2;
@@ -182,11 +184,13 @@ __global__ void k_cell_lists(int64_t ncb, const uint32_t *__restrict__ dnc, cons
 
 // chunk table: (cell, first query) for every 64-query chunk of every cell
 __global__ void k_chunk_table(int64_t ncb, const uint32_t *__restrict__ dnc, const uint32_t *__restrict__ cell_chunks,
-                              const uint32_t *__restrict__ chunk_off, uint2 *__restrict__ chunk) {
+                              const uint32_t *__restrict__ chunk_off, const int4 *__restrict__ lists,
+                              uint2 *__restrict__ chunk) {
     int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= dev_count(ncb, dnc)) return;
     const uint32_t o = chunk_off[c];
-    for (uint32_t j = 0; j < cell_chunks[c]; ++j) chunk[o + j] = make_uint2(uint32_t(c), j * 64);
+    const uint32_t per = lists ? uint32_t(refine_qpw(lists[c * kListStride].x)) : 64u;
+    for (uint32_t j = 0; j < cell_chunks[c]; ++j) chunk[o + j] = make_uint2(uint32_t(c), j * per);
 }
 
 __global__ void k_scatter_order(const int32_t *__restrict__ qslot, const uint32_t *__restrict__ qrank,
@@ -215,10 +219,14 @@ __global__ void k_refine_count(const uint2 *__restrict__ rec, const unsigned lon
     if (i < n) rrank[i] = r;
 }
 
+// chunks of the re-evaluation: 64 queries per chunk, or with the cell lists
+// (pair-parallel pass) floor(64 / nsel)
 __global__ void k_refine_chunks(int64_t ncb, const uint32_t *__restrict__ dnc, const uint32_t *__restrict__ rcnt,
-                                uint32_t *__restrict__ rchunks) {
+                                const int4 *__restrict__ lists, uint32_t *__restrict__ rchunks) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c < dev_count(ncb, dnc)) rchunks[c] = (rcnt[c] + 63) / 64;
+    if (c >= dev_count(ncb, dnc)) return;
+    const uint32_t per = lists ? uint32_t(refine_qpw(lists[c * kListStride].x)) : 64u;
+    rchunks[c] = (rcnt[c] + per - 1) / per;
 }
 
 __global__ void k_refine_scatter(const uint2 *__restrict__ rec, const unsigned long long *__restrict__ nrec,
@@ -445,9 +453,16 @@ __device__ __forceinline__ T matern_t(T o) {
     return t;
 }
 
+// one pair's outputs: distance, variance, gradient, latent occupancy and
+// variance, and (FP32) the first-order error estimates of d, grad d and v
+template <typename T>
+struct PairOut {
+    T d, v, gx, gy, gz, o, u;
+    float ed, eg, ev, gn;
+};
+
 template <typename T, int KERN>
-__device__ __forceinline__ void finish_pair(const PairRaw<T> &r, int n, const QueryConsts &C,
-                                            Acc<T> &A) {
+__device__ __forceinline__ PairOut<T> pair_out(const PairRaw<T> &r, int n, const QueryConsts &C) {
     constexpr bool f32 = std::is_same<T, float>::value;
     const T o = r.o;
     const T u = fmin(fmax(T(1) - r.ss, T(0)), T(1));
@@ -488,7 +503,6 @@ __device__ __forceinline__ void finish_pair(const PairRaw<T> &r, int n, const Qu
     const T gs = o < omin ? T(0) : gsc;
     const T gx = gs * r.gx, gy = gs * r.gy, gz = gs * r.gz;
     const T v = lam * lam * u;
-    // closest node (strict <: the first in ascending key order wins ties)
     float ed = 0.f, eg = 0.f, ev = 0.f, gn = 0.f;
     if constexpr (f32) {
         // first-order error estimates of this pair's distance, gradient and
@@ -513,6 +527,17 @@ __device__ __forceinline__ void finish_pair(const PairRaw<T> &r, int n, const Qu
             eg += float(gsc) * go;
         }
     }
+    return PairOut<T>{d, v, gx, gy, gz, o, u, ed, eg, ev, gn};
+}
+
+// accumulation of one pair into the combination of its query (closest node,
+// online smooth minimum, plain gradient sum, counts)
+template <typename T>
+__device__ __forceinline__ void pair_accumulate(const PairOut<T> &P, int n, const QueryConsts &C, Acc<T> &A) {
+    constexpr bool f32 = std::is_same<T, float>::value;
+    const T d = P.d, v = P.v, gx = P.gx, gy = P.gy, gz = P.gz, o = P.o, u = P.u;
+    const float ed = P.ed, eg = P.eg, ev = P.ev, gn = P.gn;
+    // closest node (strict <: the first in ascending key order wins ties)
     if (d < A.hd) {
         A.hd = d; A.hv = v; A.hgx = gx; A.hgy = gy; A.hgz = gz; A.ho = o; A.hu = u;
         A.hed = ed; A.heg = eg; A.hev = ev;
@@ -548,6 +573,11 @@ __device__ __forceinline__ void finish_pair(const PairRaw<T> &r, int n, const Qu
     A.pgx += gx; A.pgy += gy; A.pgz += gz;
     A.nq += 1;
     A.ntot += n;
+}
+
+template <typename T, int KERN>
+__device__ __forceinline__ void finish_pair(const PairRaw<T> &r, int n, const QueryConsts &C, Acc<T> &A) {
+    pair_accumulate<T>(pair_out<T, KERN>(r, n, C), n, C, A);
 }
 
 struct Outputs {
@@ -751,6 +781,88 @@ __global__ __launch_bounds__(kEvalT) void k_query_cells(const float *__restrict_
             cells_chunk<T, KERN, MODE>(w, q, G, lists, Mo, C, O);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 re-evaluation, one (query, cluster) pair per lane.  A chunk holds
+// floor(64 / nsel) queries of one cell (nsel: its selected clusters); lane
+// l evaluates query l / nsel against cluster l % nsel, stores the pair in
+// LDS, and one lane per query replays the accumulation over its pairs in
+// ascending cluster order: the same arithmetic, in the same order, as the
+// one-query-per-lane FP64 kernel, with the latency of one pair instead of
+// nsel.  Persistent: wavefronts take chunks from the counter *work.
+// ---------------------------------------------------------------------------
+
+struct PairSlot {
+    PairOut<double> p;
+    float best;
+    int bidx, n;
+};
+
+template <int KERN, int MODE>
+__global__ __launch_bounds__(kEvalT, 2) void k_refine_pairs(const float *__restrict__ q, Grouping G,
+                                                        const int4 *__restrict__ lists, ModelView Mo, QueryConsts C,
+                                                        Outputs O, uint32_t *work) {
+    __shared__ PairSlot slot[64];
+    const int lane = threadIdx.x & 63;
+    const uint32_t nch = *G.nchunks;
+    while (true) {
+        uint32_t w = 0;
+        if (lane == 0) w = atomicAdd(work, 1u);
+        w = uniform(uint32_t(__shfl(int(w), 0, 64)));
+        if (w >= nch) break;
+        const uint2 ch = G.chunk[w];
+        const uint32_t cell = uniform(ch.x), start = uniform(ch.y);
+        const int4 *L = lists + size_t(cell) * kListStride;
+        const int nsel = int(uniform(uint32_t(L[0].x)));
+        const int qpw = refine_qpw(nsel);
+        const uint32_t cnt = uniform(min(G.cell_cnt[cell] - start, uint32_t(qpw)));
+        const int qa = nsel > 0 ? lane / nsel : 0, sl = nsel > 0 ? lane - qa * nsel : 0;
+        const bool pair_on = nsel > 0 && uint32_t(qa) < cnt;
+        const uint32_t qi = G.order[G.cell_off[cell] + start + (pair_on ? qa : 0)];
+        const QueryPoint Q{q[3 * qi], q[3 * qi + 1], q[3 * qi + 2]};
+        Acc<double> A;
+        acc_init(A);
+        if (pair_on) {
+            const int4 d = L[1 + sl];
+            const int base = d.y, n = d.z;
+            const float4 *P = Mo.pts + base;
+            const double *a64 = Mo.alpha64 + base;
+            const double *W = Mo.W64 + d.w;
+            PairRaw<double> r{0.0, 0.0, 0.0, 0.0, 0.0, 0.f};
+            if (n <= 8) eval_small<double, KERN, 8>(P, a64, W, n, base, Q, C, r, A);
+            else if (n <= 16) eval_small<double, KERN, 16>(P, a64, W, n, base, Q, C, r, A);
+            else if (n <= kPanel) eval_small<double, KERN, kPanel>(P, a64, W, n, base, Q, C, r, A);
+            else eval_panels<double, KERN>(P, a64, W, n, base, Q, C, r, A);
+            slot[lane] = PairSlot{pair_out<double, KERN>(r, n, C), A.best, A.bidx, n};
+        }
+        __syncthreads();
+        // the first lane of each query accumulates its pairs in cluster order
+        const bool leader = pair_on && sl == 0;
+        Acc<double> B;
+        acc_init(B);
+        if (leader) {
+            for (int k = 0; k < nsel; ++k) {
+                const PairSlot &ps = slot[lane + k];
+                pair_accumulate<double>(ps.p, ps.n, C, B);
+                if (ps.best < B.best) { B.best = ps.best; B.bidx = ps.bidx; }
+            }
+        }
+        __syncthreads();  // the slots are rewritten by the next chunk
+        finish_query<double, MODE>(B, qi, cell, leader, Q, Mo.pts, C, O);
+    }
+}
+
+template <int KERN>
+void launch_refine_pairs(unsigned grid, hipStream_t s, const float *q, const Grouping &G, const int4 *lists,
+                         const ModelView &Mo, const QueryConsts &C, const Outputs &O, uint32_t *work) {
+    if (C.combine == GPDF_COMB_HARDMIN)
+        hipLaunchKernelGGL((k_refine_pairs<KERN, kModeHard>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists, Mo, C, O, work);
+    else if (C.grad_mode == GPDF_GRAD_PAPER_MEAN)
+        hipLaunchKernelGGL((k_refine_pairs<KERN, kModeMean>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists, Mo, C, O, work);
+    else
+        hipLaunchKernelGGL((k_refine_pairs<KERN, kModeSmooth>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists, Mo, C, O,
+                           work);
 }
 
 // ---------------------------------------------------------------------------
@@ -1287,7 +1399,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     exclusive_scan_u32(c->d_cell_cnt, c->d_cell_off, nc, c->d_part, s, dnc);
     exclusive_scan_u32(c->d_cell_chunks, c->d_chunk_off, nc, c->d_part, s, dnc, cnt + CNT_CHUNKS);
     hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_cell_chunks,
-                       c->d_chunk_off, c->d_chunk);
+                       c->d_chunk_off, nullptr, c->d_chunk);
     if (!knn && nc > c->cap_cells) {
         if (!eager) return fail(c, GPDF_E_CAPACITY, "query: cell lists not allocated for the bound");
         // grow the per-cell cluster lists (one reallocation per new maximum)
@@ -1336,18 +1448,30 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         const unsigned rgrid = blocks_for(m);
         hipLaunchKernelGGL(k_refine_count, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
                            c->d_stat + ST_REFINE, m, c->d_rcnt, c->d_rrank);
-        hipLaunchKernelGGL(k_refine_chunks, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rcnt,
+        const int4 *rl = knn ? nullptr : c->d_cell_list;
+        hipLaunchKernelGGL(k_refine_chunks, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rcnt, rl,
                            c->d_rchunks);
         exclusive_scan_u32(c->d_rcnt, c->d_roff, nc, c->d_part, s, dnc);
         exclusive_scan_u32(c->d_rchunks, c->d_rchunk_off, nc, c->d_part, s, dnc, cnt + CNT_RCHUNKS);
         hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rchunks,
-                           c->d_rchunk_off, c->d_rchunk);
+                           c->d_rchunk_off, rl, c->d_rchunk);
         hipLaunchKernelGGL(k_refine_scatter, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
                            c->d_stat + ST_REFINE, m, c->d_rrank, c->d_roff, c->d_rorder);
         const Grouping R{c->d_rchunk, cnt + CNT_RCHUNKS, c->d_rcnt, c->d_roff, c->d_rorder};
         Outputs O64 = O;
         O64.refine = nullptr;
-        launch_query_k<double>(c, kern, knn, grid, s, d_q, R, c->d_cell_list, Mo, C, O64, 1);
+        if (knn) {
+            launch_query_k<double>(c, kern, knn, grid, s, d_q, R, c->d_cell_list, Mo, C, O64, 1);
+        } else {
+            // pair-parallel, persistent: one wavefront per SIMD
+            uint32_t *work = c->d_work + 1;
+            fill_u32(work, 0u, 1, s);
+            const unsigned rg = 2048;
+            if (kern == GPDF_KERNEL_MATERN32)
+                launch_refine_pairs<GPDF_KERNEL_MATERN32>(rg, s, d_q, R, c->d_cell_list, Mo, C, O64, work);
+            else
+                launch_refine_pairs<GPDF_KERNEL_SE>(rg, s, d_q, R, c->d_cell_list, Mo, C, O64, work);
+        }
         stage_end(c, GPDF_MS_REFINE);
     }
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "query launch");
