@@ -238,9 +238,27 @@ enum Stat : int {
     ST_COUNT
 };
 
-// per-cluster FP32 factor layout: packed rows for n <= 64, 64-row panels
+// Per-wavefront statistics of the hot kernels are spread over kSpread rows
+// of counters, one 128-byte line each, picked by the workgroup index: device
+// atomics on one address serialise, and tens of thousands of wavefronts
+// adding to a single line queue behind each other.  fold_stats adds the rows
+// into the statistics array and clears them (a kernel, so that it can be
+// captured in a graph).
+constexpr int kSpread = 64;
+constexpr int kSpreadStride = 16 * ((ST_COUNT + 15) / 16);
+static_assert(ST_COUNT <= 64, "fold_stats takes one lane per counter");
+__device__ __forceinline__ void spread_add(unsigned long long *sp, int st, unsigned long long v) {
+    atomicAdd(&sp[size_t(blockIdx.x % kSpread) * kSpreadStride + st], v);
+}
+
+// per-cluster FP32 factor layout: packed rows for n <= 32, 32-row panels
 // (column-major inside the panel) above that
 constexpr int kPanel = 32;
+// tail pads of the FP32 point and factor arrays (zero at create): the FP32
+// evaluation loads whole groups of rows or column pairs and reads up to
+// kPanel points and kPanel^2 factor elements past the last cluster
+constexpr int64_t kPtsPad = 2 * kPanel;
+constexpr int64_t kW32Pad = 2 * kPanel * kPanel;
 __host__ __device__ inline int64_t w32_size(int64_t n) {
     if (n <= kPanel) return n * (n + 1) / 2;
     int64_t nb = (n + kPanel - 1) / kPanel, s = 0;
@@ -392,6 +410,7 @@ struct gpdf_ctx {
 
     // ---- counters ----------------------------------------------------------
     unsigned long long *d_stat = nullptr;          // [ST_COUNT]
+    unsigned long long *d_spread = nullptr;        // [kSpread][kSpreadStride], zero between calls
     unsigned long long *h_stat = nullptr;          // pinned mirror
     int64_t last_queries = 0;
 };
@@ -427,6 +446,7 @@ void count_occupied(const unsigned long long *keys, int64_t cap, uint32_t *tile_
                     uint32_t *tile_off, uint32_t *partials, hipStream_t s);
 void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+void fold_stats(unsigned long long *spread, unsigned long long *stat, hipStream_t s);
 
 // stages (train.hip, query.hip, fuse.hip, mlp.hip)
 gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn = nullptr);

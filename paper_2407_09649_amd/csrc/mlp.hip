@@ -433,7 +433,7 @@ __global__ __launch_bounds__(64) void k_mlp_infer(const float *__restrict__ feat
                                                   const float *__restrict__ var, const float *__restrict__ grad,
                                                   const float *__restrict__ aux, const uint8_t *__restrict__ valid,
                                                   int64_t n, float gate, MlpView V, float *__restrict__ r_out,
-                                                  float *__restrict__ d_out, unsigned long long *__restrict__ stat) {
+                                                  float *__restrict__ d_out, unsigned long long *__restrict__ spread) {
     __shared__ MlpLds S;
     const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
     const int64_t s0 = int64_t(blockIdx.x) * kS;
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(64) void k_mlp_infer(const float *__restrict__ feat
     }
     if (d_out) {
         const uint64_t mb = __ballot(have && use);
-        if (lane == 0 && mb) atomicAdd(&stat[ST_GATED], (unsigned long long)__popcll(mb));
+        if (lane == 0 && mb) spread_add(spread, ST_GATED, (unsigned long long)__popcll(mb));
     }
 }
 
@@ -554,7 +554,8 @@ gpdf_status mlp_apply(gpdf_ctx *c, const float *dist, const float *var, const fl
     stage_begin(c, GPDF_MS_MLP);
     fill_u64(c->d_stat + ST_GATED, 0ull, 1, c->stream);
     hipLaunchKernelGGL(k_mlp_infer, dim3(blocks(m, kS)), dim3(64), 0, c->stream, nullptr, dist, var, grad, aux,
-                       valid, m, float(c->p.mlp_gate), view(c), nullptr, out, c->d_stat);
+                       valid, m, float(c->p.mlp_gate), view(c), nullptr, out, c->d_spread);
+    fold_stats(c->d_spread, c->d_stat, c->stream);
     stage_end(c, GPDF_MS_MLP);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GPDF_OK : hip_fail(c, e, "mlp: apply");
@@ -675,7 +676,7 @@ extern "C" gpdf_status gpdf_mlp_forward(gpdf_ctx *c, const float *d_feat, int64_
     if (n == 0) return GPDF_OK;
     if (!d_feat || !d_r) return fail(c, GPDF_E_INVALID_ARG, "mlp_forward: null");
     hipLaunchKernelGGL(k_mlp_infer, dim3(blocks(n, kS)), dim3(64), 0, c->stream, d_feat, nullptr, nullptr, nullptr,
-                       nullptr, nullptr, n, 0.f, view(c), d_r, nullptr, c->d_stat);
+                       nullptr, nullptr, n, 0.f, view(c), d_r, nullptr, c->d_spread);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GPDF_OK : hip_fail(c, e, "mlp_forward");
 }

@@ -58,6 +58,40 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Data that no kernel of a launch writes (model arrays, cell lists, chunk
+// table, counts) is read through the constant address space.  That tells
+// the compiler that no store of the kernel can change it, so its uniform
+// loads stay scalar loads also inside loops that store (the persistent
+// instances), where it could not otherwise prove it.
+// Vector types are read component by component (their copy constructors
+// cannot bind to the constant address space); the compiler merges the
+// components back into one wide load.
+template <typename T>
+using ro_ptr = const __attribute__((address_space(4))) T *;
+__device__ __forceinline__ float ld_ro(const float *p) { return *(ro_ptr<float>)p; }
+__device__ __forceinline__ double ld_ro(const double *p) { return *(ro_ptr<double>)p; }
+__device__ __forceinline__ uint32_t ld_ro(const uint32_t *p) { return *(ro_ptr<uint32_t>)p; }
+__device__ __forceinline__ float4 ld_ro(const float4 *p) {
+    const ro_ptr<float> f = (ro_ptr<float>)p;
+    return make_float4(f[0], f[1], f[2], f[3]);
+}
+__device__ __forceinline__ int4 ld_ro(const int4 *p) {
+    const ro_ptr<int> f = (ro_ptr<int>)p;
+    return make_int4(f[0], f[1], f[2], f[3]);
+}
+__device__ __forceinline__ uint2 ld_ro(const uint2 *p) {
+    const ro_ptr<uint32_t> f = (ro_ptr<uint32_t>)p;
+    return make_uint2(f[0], f[1]);
+}
+template <typename T>
+struct RoPtr {
+    const T *p;
+    __device__ __forceinline__ T operator[](int64_t i) const { return ld_ro(p + i); }
+    __device__ __forceinline__ T operator*() const { return ld_ro(p); }
+};
+template <typename T>
+__device__ __forceinline__ RoPtr<T> ro(const T *p) { return RoPtr<T>{p}; }
+
 // workgroup -> work item, XCD-aware: workgroups are dispatched round-robin
 // over the 8 XCDs, so the first n items are handed out as 8 contiguous
 // ranges, one per XCD, and neighbouring items share one XCD's L2.  A
@@ -280,15 +314,21 @@ struct QueryPoint {
 
 // one point: kernel value k, the factor e multiplying alpha (x - x_i) in the
 // gradient sum, and the point's contribution to the running sums
+//
+// live == false marks a row loaded past the end of the cluster (batched FP32
+// loads): its alpha is taken as 0 and it takes no part in the nearest-point
+// decision, so every sum is left bitwise unchanged.
 template <typename T, int KERN>
 __device__ __forceinline__ T point_eval(const float4 p, T alpha, const QueryPoint &Q, int gidx,
-                                        const QueryConsts &C, PairRaw<T> &r, Acc<T> &A) {
+                                        const QueryConsts &C, PairRaw<T> &r, Acc<T> &A,
+                                        bool live = true) {
     // nearest training point, decided in FP32 in a fixed order
     {
         const float ex = Q.fx - p.x, ey = Q.fy - p.y, ez = Q.fz - p.z;
         const float r2f = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
-        if (r2f < A.best) { A.best = r2f; A.bidx = gidx; }
+        if (live && r2f < A.best) { A.best = r2f; A.bidx = gidx; }
     }
+    alpha = live ? alpha : T(0);
     T dx, dy, dz;
     if constexpr (std::is_same<T, float>::value) {
         dx = Q.fx - p.x; dy = Q.fy - p.y; dz = Q.fz - p.z;
@@ -351,9 +391,8 @@ __device__ __forceinline__ T point_k(const float4 p, const QueryPoint &Q, const 
 // n <= NMAX <= 32: k in registers, W rows packed (row i at i (i + 1) / 2).
 // The rows are generated at compile time (index sequences), so every k_j
 // index is a constant and the vector lives in VGPRs.
-template <typename T, int... J>
-__device__ __forceinline__ T row_dot(const T *__restrict__ Wi, const T *kr,
-                                     std::integer_sequence<int, J...>) {
+template <typename T, typename PW, int... J>
+__device__ __forceinline__ T row_dot(PW Wi, const T *kr, std::integer_sequence<int, J...>) {
     T t[2] = {T(0), T(0)};
     ((t[J & 1] = fma(Wi[J], kr[J], t[J & 1])), ...);
     return t[0] + t[1];
@@ -366,11 +405,60 @@ __device__ __forceinline__ void small_rows(const float4 *__restrict__ P, const d
                                            Acc<T> &A, T *kr) {
     if constexpr (I < NMAX) {
         if (I >= n) return;
-        const float4 p = P[I];
+        const float4 p = ro(P)[I];
         kr[I] = point_eval<T, KERN>(p, alpha_of<T>(p, a64, I), Q, pbase + I, C, r, A);
-        const T t = row_dot<T>(W + (I * (I + 1)) / 2, kr, std::make_integer_sequence<int, I + 1>{});
+        const T t = row_dot<T>(ro(W + (I * (I + 1)) / 2), kr, std::make_integer_sequence<int, I + 1>{});
         r.ss = fma(t, t, r.ss);
         small_rows<T, KERN, NMAX, I + 1>(P, a64, W, n, pbase, Q, C, r, A, kr);
+    }
+}
+
+// FP32: the points and factor rows of a group of rows are loaded as one
+// batch of scalar loads, so the wavefront waits once per group instead of
+// once per row.  Scalar loads may return out of order, so a wait always
+// covers every load in flight; batching is the way to overlap them.  Rows of
+// the last group at or past n are loaded but masked (point_eval with
+// live == false, their squared products dropped); the point and factor
+// arrays carry a tail pad so that these loads stay inside the allocation.
+constexpr int f32_group(int i) { return i < 16 ? 4 : 2; }   // rows per batch
+
+template <int KERN, int I, int WO>
+__device__ __forceinline__ void group_row_f32(const float4 pp, const float *w, int n, int pbase,
+                                              const QueryPoint &Q, const QueryConsts &C,
+                                              PairRaw<float> &r, Acc<float> &A, float *kr) {
+    const bool live = I < n;
+    kr[I] = point_eval<float, KERN>(pp, pp.w, Q, pbase + I, C, r, A, live);
+    const float t = row_dot<float>(w + WO, kr, std::make_integer_sequence<int, I + 1>{});
+    r.ss = live ? fmaf(t, t, r.ss) : r.ss;
+}
+
+template <int KERN, int I0, int... R>
+__device__ __forceinline__ void group_rows_f32(const float4 *p, const float *w, int n, int pbase,
+                                               const QueryPoint &Q, const QueryConsts &C,
+                                               PairRaw<float> &r, Acc<float> &A, float *kr,
+                                               std::integer_sequence<int, R...>) {
+    // row I0 + R starts at R I0 + R (R + 1) / 2 inside the batch
+    (group_row_f32<KERN, I0 + R, R * I0 + R * (R + 1) / 2>(p[R], w, n, pbase, Q, C, r, A, kr), ...);
+}
+
+template <int KERN, int NMAX, int I0>
+__device__ __forceinline__ void small_groups_f32(const float4 *__restrict__ P, const float *__restrict__ W,
+                                                 int n, int pbase, const QueryPoint &Q,
+                                                 const QueryConsts &C, PairRaw<float> &r,
+                                                 Acc<float> &A, float *kr) {
+    if constexpr (I0 < NMAX) {
+        if (I0 >= n) return;
+        constexpr int G = f32_group(I0);
+        constexpr int WB = I0 * (I0 + 1) / 2;        // first element of row I0
+        constexpr int WL = G * I0 + G * (G + 1) / 2;  // elements of rows I0 .. I0 + G - 1
+        float4 p[G];
+        float w[WL];
+#pragma unroll
+        for (int i = 0; i < G; ++i) p[i] = ro(P)[I0 + i];
+#pragma unroll
+        for (int i = 0; i < WL; ++i) w[i] = ro(W)[WB + i];
+        group_rows_f32<KERN, I0>(p, w, n, pbase, Q, C, r, A, kr, std::make_integer_sequence<int, G>{});
+        small_groups_f32<KERN, NMAX, I0 + G>(P, W, n, pbase, Q, C, r, A, kr);
     }
 }
 
@@ -380,13 +468,15 @@ __device__ __forceinline__ void eval_small(const float4 *__restrict__ P, const d
                                            const QueryPoint &Q, const QueryConsts &C, PairRaw<T> &r,
                                            Acc<T> &A) {
     T kr[NMAX];
-    small_rows<T, KERN, NMAX, 0>(P, a64, W, n, pbase, Q, C, r, A, kr);
+    if constexpr (std::is_same<T, float>::value)
+        small_groups_f32<KERN, NMAX, 0>(P, W, n, pbase, Q, C, r, A, kr);
+    else
+        small_rows<T, KERN, NMAX, 0>(P, a64, W, n, pbase, Q, C, r, A, kr);
 }
 
 // t[R0 + R] += col[R0 + R] k_j for R = 0 .. kPanel - 1 - R0
-template <typename T, int R0, int... R>
-__device__ __forceinline__ void panel_update(T *t, const T *__restrict__ col, T kj,
-                                             std::integer_sequence<int, R...>) {
+template <typename T, int R0, typename PC, int... R>
+__device__ __forceinline__ void panel_update(T *t, PC col, T kj, std::integer_sequence<int, R...>) {
     ((t[R0 + R] = fma(col[R0 + R], kj, t[R0 + R])), ...);
 }
 
@@ -399,10 +489,36 @@ __device__ __forceinline__ void diag_cols(const float4 *__restrict__ P, const do
                                           Acc<T> &A, T *t) {
     if constexpr (J < kPanel) {
         if (J >= nrem) return;
-        const float4 p = P[J];
+        const float4 p = ro(P)[J];
         const T kj = point_eval<T, KERN>(p, alpha_of<T>(p, a64, J), Q, pbase + J, C, r, A);
-        panel_update<T, J>(t, D + J * kPanel, kj, std::make_integer_sequence<int, kPanel - J>{});
+        panel_update<T, J>(t, ro(D + J * kPanel), kj, std::make_integer_sequence<int, kPanel - J>{});
         diag_cols<T, KERN, J + 1>(P, a64, D, nrem, pbase, Q, C, r, A, t);
+    }
+}
+
+// FP32 diagonal block, two columns per batch of scalar loads; the second
+// column of the last pair may lie past the cluster and is then masked
+template <int KERN, int J>
+__device__ __forceinline__ void diag_pairs_f32(const float4 *__restrict__ P, const float *__restrict__ D,
+                                               int nrem, int pbase, const QueryPoint &Q,
+                                               const QueryConsts &C, PairRaw<float> &r, Acc<float> &A,
+                                               float *t) {
+    if constexpr (J < kPanel) {
+        if (J >= nrem) return;
+        const float4 p0 = ro(P)[J], p1 = ro(P)[J + 1];
+        float a[kPanel - J], b[kPanel - J - 1];
+#pragma unroll
+        for (int i = 0; i < kPanel - J; ++i) a[i] = ro(D)[J * kPanel + J + i];
+#pragma unroll
+        for (int i = 0; i < kPanel - J - 1; ++i) b[i] = ro(D)[(J + 1) * kPanel + J + 1 + i];
+        const float k0 = point_eval<float, KERN>(p0, p0.w, Q, pbase + J, C, r, A);
+#pragma unroll
+        for (int i = 0; i < kPanel - J; ++i) t[J + i] = fmaf(a[i], k0, t[J + i]);
+        const bool live = J + 1 < nrem;
+        const float k1 = point_eval<float, KERN>(p1, p1.w, Q, pbase + J + 1, C, r, A, live);
+#pragma unroll
+        for (int i = 0; i < kPanel - J - 1; ++i) t[J + 1 + i] = live ? fmaf(b[i], k1, t[J + 1 + i]) : t[J + 1 + i];
+        diag_pairs_f32<KERN, J + 2>(P, D, nrem, pbase, Q, C, r, A, t);
     }
 }
 
@@ -420,11 +536,26 @@ __device__ __forceinline__ void eval_panels(const float4 *__restrict__ P, const 
         T t[kPanel];
 #pragma unroll
         for (int q = 0; q < kPanel; ++q) t[q] = T(0);
-        for (int j = 0; j < c0; ++j) {
-            const T kj = point_k<T, KERN>(P[j], Q, C);
-            panel_update<T, 0>(t, Pn + j * kPanel, kj, std::make_integer_sequence<int, kPanel>{});
+        if constexpr (std::is_same<T, float>::value) {
+            // c0 is a multiple of the panel height: columns go in pairs
+            for (int j = 0; j < c0; j += 2) {
+                const float4 p0 = ro(P)[j], p1 = ro(P)[j + 1];
+                float a[kPanel], b[kPanel];
+#pragma unroll
+                for (int i = 0; i < kPanel; ++i) { a[i] = ro(Pn)[j * kPanel + i]; b[i] = ro(Pn)[(j + 1) * kPanel + i]; }
+                const float k0 = point_k<float, KERN>(p0, Q, C);
+                const float k1 = point_k<float, KERN>(p1, Q, C);
+                panel_update<float, 0>(t, a, k0, std::make_integer_sequence<int, kPanel>{});
+                panel_update<float, 0>(t, b, k1, std::make_integer_sequence<int, kPanel>{});
+            }
+            diag_pairs_f32<KERN, 0>(P + c0, Pn + c0 * kPanel, n - c0, pbase + c0, Q, C, r, A, t);
+        } else {
+            for (int j = 0; j < c0; ++j) {
+                const T kj = point_k<T, KERN>(ro(P)[j], Q, C);
+                panel_update<T, 0>(t, ro(Pn + j * kPanel), kj, std::make_integer_sequence<int, kPanel>{});
+            }
+            diag_cols<T, KERN, 0>(P + c0, a64 + c0, Pn + c0 * kPanel, n - c0, pbase + c0, Q, C, r, A, t);
         }
-        diag_cols<T, KERN, 0>(P + c0, a64 + c0, Pn + c0 * kPanel, n - c0, pbase + c0, Q, C, r, A, t);
 #pragma unroll
         for (int q = 0; q < kPanel; ++q) r.ss = fma(t[q], t[q], r.ss);
         Pn += int64_t(min(c0 + kPanel, n)) * kPanel;
@@ -584,7 +715,8 @@ struct Outputs {
     float *dist, *grad, *var, *aux;
     uint8_t *valid;
     uint2 *refine;              // FP32 pass: (cell, query) records to redo in FP64
-    unsigned long long *stat;
+    unsigned long long *stat;   // the refine record counter (its value is used)
+    unsigned long long *spread; // every other per-wavefront count (spread_add)
 };
 
 // final combination, sign, error test and stores for one lane
@@ -649,14 +781,14 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
     const int lane = threadIdx.x & 63;
     if constexpr (f32) {
         const uint64_t nv = __ballot(active && A.nq > 0);
-        if (lane == 0 && nv) atomicAdd(&O.stat[ST_VALID_Q], (unsigned long long)__popcll(nv));
+        if (lane == 0 && nv) spread_add(O.spread, ST_VALID_Q, (unsigned long long)__popcll(nv));
         const uint64_t mb = __ballot(bad);
         if (mb) {
             const uint64_t b1 = __ballot(bd), b2 = __ballot(bg), b3 = __ballot(bv);
             if (lane == 0) {
-                atomicAdd(&O.stat[ST_REF_D], (unsigned long long)__popcll(b1));
-                atomicAdd(&O.stat[ST_REF_G], (unsigned long long)__popcll(b2));
-                atomicAdd(&O.stat[ST_REF_V], (unsigned long long)__popcll(b3));
+                spread_add(O.spread, ST_REF_D, (unsigned long long)__popcll(b1));
+                spread_add(O.spread, ST_REF_G, (unsigned long long)__popcll(b2));
+                spread_add(O.spread, ST_REF_V, (unsigned long long)__popcll(b3));
             }
         }
         if (mb && O.refine) {
@@ -673,7 +805,7 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
         // whose queries the FP32 pass already counted; otherwise this is the
         // FP64 evaluation of every query and counts them here
         const uint64_t nv = __ballot(active && A.nq > 0);
-        if (lane == 0 && nv) atomicAdd(&O.stat[ST_VALID_Q], (unsigned long long)__popcll(nv));
+        if (lane == 0 && nv) spread_add(O.spread, ST_VALID_Q, (unsigned long long)__popcll(nv));
     }
 }
 
@@ -730,13 +862,13 @@ __device__ __forceinline__ void cells_chunk(uint32_t wave, const float *__restri
                                             const int4 *__restrict__ lists, const ModelView &Mo,
                                             const QueryConsts &C, const Outputs &O) {
     const int lane = threadIdx.x & 63;
-    const uint2 ch = G.chunk[wave];
+    const uint2 ch = ro(G.chunk)[wave];
     const uint32_t cell = uniform(ch.x), start = uniform(ch.y);
-    const uint32_t cnt = uniform(min(G.cell_cnt[cell] - start, 64u));
+    const uint32_t cnt = uniform(min(ro(G.cell_cnt)[cell] - start, 64u));
     const bool active = uint32_t(lane) < cnt;
-    const uint32_t qi = G.order[G.cell_off[cell] + start + (active ? lane : 0)];
+    const uint32_t qi = G.order[ro(G.cell_off)[cell] + start + (active ? lane : 0)];
     const QueryPoint Q{q[3 * qi], q[3 * qi + 1], q[3 * qi + 2]};
-    const int4 *L = lists + size_t(cell) * kListStride;
+    const RoPtr<int4> L = ro(lists + size_t(cell) * kListStride);
     const int nsel = int(uniform(uint32_t(L[0].x)));
     Acc<T> A;
     acc_init(A);
@@ -754,9 +886,9 @@ __device__ __forceinline__ void cells_chunk(uint32_t wave, const float *__restri
     finish_query<T, MODE>(A, qi, cell, active, Q, Mo.pts, C, O);
     // algorithmic work of this wavefront (active lanes), one atomic each
     if (std::is_same<T, float>::value && lane == 0 && nsel > 0) {
-        atomicAdd(&O.stat[ST_PAIRS], (unsigned long long)nsel * cnt);
-        atomicAdd(&O.stat[ST_POINTS], (unsigned long long)sum_n * cnt);
-        atomicAdd(&O.stat[ST_TRI], (unsigned long long)sum_tri * cnt);
+        spread_add(O.spread, ST_PAIRS, (unsigned long long)nsel * cnt);
+        spread_add(O.spread, ST_POINTS, (unsigned long long)sum_n * cnt);
+        spread_add(O.spread, ST_TRI, (unsigned long long)sum_tri * cnt);
     }
 }
 
@@ -764,21 +896,33 @@ __device__ __forceinline__ void cells_chunk(uint32_t wave, const float *__restri
 // PERSIST: a fixed set of wavefronts takes chunks from the counter *work
 // (zero at launch) until none is left.  Two instances, so that each keeps
 // the register allocation of a single chunk body.
+// the persistent FP32 instance is held to the occupancy of the one-chunk
+// instance (four wavefronts per SIMD); left alone, the compiler keeps far more
+// live across the chunk loop
+template <typename T, bool PERSIST>
+constexpr int eval_min_waves() { return PERSIST && std::is_same<T, float>::value ? 4 : 1; }
+
 template <typename T, int KERN, int MODE, bool PERSIST>
-__global__ __launch_bounds__(kEvalT) void k_query_cells(const float *__restrict__ q, Grouping G,
+__global__ __launch_bounds__(kEvalT, (eval_min_waves<T, PERSIST>())) void k_query_cells(const float *__restrict__ q, Grouping G,
                                                      const int4 *__restrict__ lists, ModelView Mo,
                                                      QueryConsts C, Outputs O, uint32_t *work) {
-    const uint32_t nch = *G.nchunks;
+    const uint32_t nch = *ro(G.nchunks);
     if constexpr (!PERSIST) {
         const uint32_t wave = xcd_item(nch);
         if (wave < nch) cells_chunk<T, KERN, MODE>(wave, q, G, lists, Mo, C, O);
     } else {
-        while (true) {
-            uint32_t w = 0;
-            if ((threadIdx.x & 63) == 0) w = atomicAdd(work, 1u);
-            w = uniform(uint32_t(__shfl(int(w), 0, 64)));
-            if (w >= nch) break;
+        // the next chunk index is requested before the current chunk is
+        // evaluated, so the round trip of the counter overlaps the work;
+        // every wavefront stops at its first index past the last chunk
+        const bool lead = (threadIdx.x & 63) == 0;
+        uint32_t w = 0;
+        if (lead) w = atomicAdd(work, 1u);
+        w = uniform(uint32_t(__shfl(int(w), 0, 64)));
+        while (w < nch) {
+            uint32_t nx = 0;
+            if (lead) nx = atomicAdd(work, 1u);
             cells_chunk<T, KERN, MODE>(w, q, G, lists, Mo, C, O);
+            w = uniform(uint32_t(__shfl(int(nx), 0, 64)));
         }
     }
 }
@@ -805,21 +949,21 @@ __global__ __launch_bounds__(kEvalT, 2) void k_refine_pairs(const float *__restr
                                                         Outputs O, uint32_t *work) {
     __shared__ PairSlot slot[64];
     const int lane = threadIdx.x & 63;
-    const uint32_t nch = *G.nchunks;
+    const uint32_t nch = *ro(G.nchunks);
     while (true) {
         uint32_t w = 0;
         if (lane == 0) w = atomicAdd(work, 1u);
         w = uniform(uint32_t(__shfl(int(w), 0, 64)));
         if (w >= nch) break;
-        const uint2 ch = G.chunk[w];
+        const uint2 ch = ro(G.chunk)[w];
         const uint32_t cell = uniform(ch.x), start = uniform(ch.y);
-        const int4 *L = lists + size_t(cell) * kListStride;
+        const RoPtr<int4> L = ro(lists + size_t(cell) * kListStride);
         const int nsel = int(uniform(uint32_t(L[0].x)));
         const int qpw = refine_qpw(nsel);
-        const uint32_t cnt = uniform(min(G.cell_cnt[cell] - start, uint32_t(qpw)));
+        const uint32_t cnt = uniform(min(ro(G.cell_cnt)[cell] - start, uint32_t(qpw)));
         const int qa = nsel > 0 ? lane / nsel : 0, sl = nsel > 0 ? lane - qa * nsel : 0;
         const bool pair_on = nsel > 0 && uint32_t(qa) < cnt;
-        const uint32_t qi = G.order[G.cell_off[cell] + start + (pair_on ? qa : 0)];
+        const uint32_t qi = G.order[ro(G.cell_off)[cell] + start + (pair_on ? qa : 0)];
         const QueryPoint Q{q[3 * qi], q[3 * qi + 1], q[3 * qi + 2]};
         Acc<double> A;
         acc_init(A);
@@ -1016,17 +1160,17 @@ __global__ __launch_bounds__(kEvalT) void k_query_cells_bf16(const float *__rest
                                                              const int64_t *__restrict__ bfoff, int kts,
                                                              QueryConsts C, Outputs O) {
     extern __shared__ __bf16 Kt[];
-    const uint32_t nch = *G.nchunks;
+    const uint32_t nch = *ro(G.nchunks);
     const uint32_t wave = xcd_item(nch);
     const int lane = threadIdx.x & 63;
     if (wave >= nch) return;
-    const uint2 ch = G.chunk[wave];
+    const uint2 ch = ro(G.chunk)[wave];
     const uint32_t cell = uniform(ch.x), start = uniform(ch.y);
-    const uint32_t cnt = uniform(min(G.cell_cnt[cell] - start, 64u));
+    const uint32_t cnt = uniform(min(ro(G.cell_cnt)[cell] - start, 64u));
     const bool active = uint32_t(lane) < cnt;
-    const uint32_t qi = G.order[G.cell_off[cell] + start + (active ? lane : 0)];
+    const uint32_t qi = G.order[ro(G.cell_off)[cell] + start + (active ? lane : 0)];
     const QueryPoint Q{q[3 * qi], q[3 * qi + 1], q[3 * qi + 2]};
-    const int4 *L = lists + size_t(cell) * kListStride;
+    const RoPtr<int4> L = ro(lists + size_t(cell) * kListStride);
     const int nsel = int(uniform(uint32_t(L[0].x)));
     Acc<float> A;
     acc_init(A);
@@ -1045,9 +1189,9 @@ __global__ __launch_bounds__(kEvalT) void k_query_cells_bf16(const float *__rest
     }
     finish_query<float, MODE>(A, qi, cell, active, Q, Mo.pts, C, O);
     if (lane == 0 && nsel > 0) {
-        atomicAdd(&O.stat[ST_PAIRS], (unsigned long long)nsel * cnt);
-        atomicAdd(&O.stat[ST_POINTS], (unsigned long long)sum_n * cnt);
-        atomicAdd(&O.stat[ST_TRI], (unsigned long long)sum_tri * cnt);
+        spread_add(O.spread, ST_PAIRS, (unsigned long long)nsel * cnt);
+        spread_add(O.spread, ST_POINTS, (unsigned long long)sum_n * cnt);
+        spread_add(O.spread, ST_TRI, (unsigned long long)sum_tri * cnt);
     }
 }
 
@@ -1083,12 +1227,12 @@ __global__ __launch_bounds__(kEvalT) void k_query_knn(const float *__restrict__ 
     const int wv = threadIdx.x >> 6;
     const uint32_t wave = blockIdx.x * kWaves + wv;
     const int lane = threadIdx.x & 63;
-    if (wave >= *G.nchunks) return;
-    const uint2 ch = G.chunk[wave];
+    if (wave >= *ro(G.nchunks)) return;
+    const uint2 ch = ro(G.chunk)[wave];
     const uint32_t cell = uniform(ch.x), start = uniform(ch.y);
-    const uint32_t cnt = uniform(min(G.cell_cnt[cell] - start, 64u));
+    const uint32_t cnt = uniform(min(ro(G.cell_cnt)[cell] - start, 64u));
     const bool active = uint32_t(lane) < cnt;
-    const uint32_t qi = G.order[G.cell_off[cell] + start + (active ? lane : 0)];
+    const uint32_t qi = G.order[ro(G.cell_off)[cell] + start + (active ? lane : 0)];
     const QueryPoint Q{q[3 * qi], q[3 * qi + 1], q[3 * qi + 2]};
     const int Qn = C.knn_q;
     double bd[kMaxKnn];
@@ -1189,8 +1333,9 @@ void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_
                     const QueryConsts &C, const Outputs &O, int slot) {
     uint32_t *work = nullptr;
     // persistent when tuned so, and always in a captured graph (its grid
-    // bound would otherwise be one workgroup per possible chunk)
-    const int per = c->tune.eval_persistent > 0 ? c->tune.eval_persistent : (c->capturing ? 2 : 0);
+    // bound would otherwise be one workgroup per possible chunk); the FP32
+    // instance holds four wavefronts per SIMD
+    const int per = c->tune.eval_persistent > 0 ? c->tune.eval_persistent : (c->capturing ? 4 : 0);
     if (per > 0 && !knn) {
         // 256 CUs x 4 SIMDs x the wavefronts per SIMD
         work = c->d_work + slot;
@@ -1417,7 +1562,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     const int64_t max_chunks = nc + (m + 63) / 64;
     const unsigned grid = blocks_for(max_chunks * 64, kEvalT);
     const Grouping G{c->d_chunk, cnt + CNT_CHUNKS, c->d_cell_cnt, c->d_cell_off, c->d_order};
-    Outputs O{dist, grad, var, aux, valid, c->d_refine, c->d_stat};
+    Outputs O{dist, grad, var, aux, valid, c->d_refine, c->d_stat, c->d_spread};
     if (c->p.precision == GPDF_PREC_FP64) {
         stage_begin(c, GPDF_MS_EVAL);
         launch_query_k<double>(c, kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O, 0);
@@ -1463,7 +1608,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         if (knn) {
             launch_query_k<double>(c, kern, knn, grid, s, d_q, R, c->d_cell_list, Mo, C, O64, 1);
         } else {
-            // pair-parallel, persistent: one wavefront per SIMD
+            // pair-parallel, persistent: two wavefronts per SIMD
             uint32_t *work = c->d_work + 1;
             fill_u32(work, 0u, 1, s);
             const unsigned rg = 2048;
@@ -1474,6 +1619,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         }
         stage_end(c, GPDF_MS_REFINE);
     }
+    fold_stats(c->d_spread, c->d_stat, s);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "query launch");
     if (correct) return mlp_apply(c, dist, var, grad, aux, valid, m, dist);
     return GPDF_OK;

@@ -257,4 +257,22 @@ void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
 }
 
+// one thread per counter: sum its spread rows into the statistics array and
+// clear them (stream-ordered after the kernels that added to them)
+__global__ __launch_bounds__(64) void k_fold_stats(unsigned long long *sp, unsigned long long *stat) {
+    const int st = int(threadIdx.x);
+    if (st >= ST_COUNT) return;
+    unsigned long long sum = 0;
+    for (int r = 0; r < kSpread; ++r) {
+        unsigned long long &x = sp[size_t(r) * kSpreadStride + st];
+        sum += x;
+        x = 0;
+    }
+    if (sum) atomicAdd(&stat[st], sum);
+}
+
+void fold_stats(unsigned long long *spread, unsigned long long *stat, hipStream_t s) {
+    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(64), 0, s, spread, stat);
+}
+
 }  // namespace gpdf
