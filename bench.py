@@ -50,6 +50,10 @@ METRIC = "GP distance+gradient queries/sec at <=1e-4 m error vs FP64 oracle, 1 G
 PEAK_FP32_VECTOR = 157.3e12     # MI355X published FP32 vector peak (packed FMA), flop/s
 PEAK_FP32_NONPACKED = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, the issuable peak here
 PEAK_HBM = 8.0e12               # bytes/s
+# VALU roofline of the evaluation: FMA work at the FMA rate plus the
+# transcendentals (exp, sqrt, log, rcp) at quarter rate, per CU and clock
+CUS, CLOCK = 256, 2.4e9
+FMA_CLK_PACKED, FMA_CLK, TRANS_CLK = 128, 64, 16
 ORIGIN = (0.0, 0.0, 1.5)
 
 
@@ -62,12 +66,43 @@ def workload():
     return pts, q, qg
 
 
-def algorithmic_flops(st):
-    """Counted work of the FP32 evaluation pass: per (query, cluster) pair of
-    n points, n^2 + 25 n + 40 flops (kernel values, occupancy, gradient sum,
-    the triangular variance product and the reverting).  With
-    tri = sum n (n + 1) / 2: sum n^2 = 2 tri - sum n."""
-    return 2 * st["eval_tri"] + 24 * st["eval_points"] + 40 * st["eval_pairs"]
+def algorithmic_work(st):
+    """Counted work of the FP32 evaluation pass (Matern-3/2): per (query,
+    cluster) pair of n points, n^2 + 25 n + 40 flops (kernel values,
+    occupancy, gradient sum, the triangular variance product, reverting and
+    combination) and 2 n + 4 transcendentals (sqrt and exp per point, the
+    reverting).  With tri = sum n (n + 1) / 2: sum n^2 = 2 tri - sum n."""
+    flops = 2 * st["eval_tri"] + 24 * st["eval_points"] + 40 * st["eval_pairs"]
+    trans = 2 * st["eval_points"] + 4 * st["eval_pairs"]
+    return flops, trans
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_lidar_frame_step.md")
+EVAL_SOURCE = os.path.join(ROOT, "paper_2407_09649_amd", "csrc", "query.hip")
+
+
+def profiled_traffic():
+    """HBM bytes of one band evaluation launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the evaluation source has
+    changed since the counters were taken (the summary records its sha256)."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(EVAL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        if line.startswith("band-eval-traffic-bytes:"):
+            f = line.split()
+            if len(f) >= 4 and f[2] == "query.hip-sha256:" and f[3] == src:
+                return int(f[1])
+    return None
+
+
+def valu_roofline_s(flops, trans, fma_clk):
+    """Time of the work at 100 % VALU: FMAs (2 flops) at fma_clk per CU and
+    clock, transcendentals at quarter rate."""
+    return (flops / 2) / (fma_clk * CUS * CLOCK) + trans / (TRANS_CLK * CUS * CLOCK)
 
 
 class Timer:
@@ -151,16 +186,20 @@ def main():
     q_ms = timer.median(lambda: ctx.query(qd, origin=ORIGIN, out=out), reps=20)
 
     # dominant kernel: the FP32 evaluation of the band query
-    flops = algorithmic_flops(st)
+    # frac = time of the counted work at 100 % VALU (published packed-FMA
+    # rate) / measured time; achieved = frac x peak, in flop-equivalents
+    # (a transcendental costs 16 flops of packed-FMA issue)
+    flops, trans = algorithmic_work(st)
     eval_s = stages["eval"] / 1e3
-    achieved = flops / eval_s
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-                "frac_issuable": achieved / PEAK_FP32_NONPACKED,
+    frac = valu_roofline_s(flops, trans, FMA_CLK_PACKED) / eval_s
+    roofline = {"bound": "alu", "achieved": frac * PEAK_FP32_VECTOR / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                "unit": "TFLOP/s", "frac": frac, "traffic": profiled_traffic(),
+                "frac_issuable": valu_roofline_s(flops, trans, FMA_CLK) / eval_s,
+                "flops_only_tflops": flops / eval_s / 1e12,
                 "kernel": "k_query_cells<float, Matern-3/2>",
-                "flops_per_launch": flops, "pairs": st["eval_pairs"],
-                "kernel_evals": st["eval_points"], "variance_fmas": st["eval_tri"],
-                "avg_launch_ms": stages["eval"]}
+                "flops_per_launch": flops, "transcendentals_per_launch": trans,
+                "pairs": st["eval_pairs"], "kernel_evals": st["eval_points"],
+                "variance_fmas": st["eval_tri"], "avg_launch_ms": stages["eval"]}
     res = {
         "metric": METRIC, "value": value, "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,

@@ -44,7 +44,7 @@ void release(gpdf_ctx *c) {
                     c->d_rcnt, c->d_roff, c->d_rchunks, c->d_rchunk_off, c->d_rorder, c->d_rrank,
                     c->d_rchunk,
                     c->d_tmp_dist, c->d_tmp_var, c->d_tmp_grad, c->d_tmp_valid, c->d_tset,
-                    c->d_tkeys, c->d_tpts, c->d_gkey, c->d_gD, c->d_gV, c->d_gstamp, c->d_offs,
+                    c->d_tkeys, c->d_tpts, c->d_gslot, c->d_gstamp, c->d_offs,
                     c->d_mlp_w, c->d_mlp_m, c->d_mlp_v, c->d_mlp_g, c->d_mlp_rec, c->d_mlp_pack,
                     c->d_mlp_norm, c->d_mlp_loss, c->d_mlp_mom, c->d_stat, c->d_spread, c->d_blist, c->d_tile_cnt, c->d_tile_off, c->d_bfM, c->d_bfoff, c->d_work, c->d_cnt, c->d_wsz, c->d_asz, c->d_wo32, c->d_ao32};
     for (void *p : ptrs)
@@ -141,7 +141,7 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
     bool ok = dalloc(c->d_key, P + 1, e) && dalloc(c->d_key2, P + 1, e) && dalloc(c->d_val, P + 1, e) &&
               dalloc(c->d_val2, P + 1, e) && dalloc(c->d_flag, P + 1, e) &&
               dalloc(c->d_scan, scan_n, e) && dalloc(c->d_hist, 256 * nbP + 1, e) &&
-              dalloc(c->d_part, scan_n / 4096 + 64, e) && dalloc(c->d_red, 8, e) && dalloc(c->d_work, 8, e) && dalloc(c->d_cnt, kCnt, e) &&
+              dalloc(c->d_part, scan_n / 4096 + 64, e) && dalloc(c->d_red, 8, e) && dalloc(c->d_work, int64_t(kWorkSlots) * kWorkSlot, e) && dalloc(c->d_cnt, kCnt, e) &&
               dalloc(c->d_wsz, C + 1, e) && dalloc(c->d_asz, C + 1, e) && dalloc(c->d_wo32, C + 1, e) &&
               dalloc(c->d_ao32, C + 1, e) &&
               dalloc(c->d_pts, P + kPtsPad, e) && dalloc(c->d_alpha64, P, e) && dalloc(c->d_ckey, C + 1, e) &&
@@ -164,8 +164,7 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
               dalloc(c->d_rorder, M, e) && dalloc(c->d_rrank, M, e) && dalloc(c->d_rchunk, chunks, e) && dalloc(c->d_tmp_dist, M, e) && dalloc(c->d_tmp_var, M, e) &&
               dalloc(c->d_tmp_grad, 3 * M, e) && dalloc(c->d_tmp_valid, M, e) &&
               dalloc(c->d_tset, int64_t(c->tset_mask) + 1, e) && dalloc(c->d_tkeys, M, e) &&
-              dalloc(c->d_tpts, 3 * M, e) && dalloc(c->d_gkey, int64_t(c->gmask) + 1, e) &&
-              dalloc(c->d_gD, int64_t(c->gmask) + 1, e) && dalloc(c->d_gV, int64_t(c->gmask) + 1, e) &&
+              dalloc(c->d_tpts, 3 * M, e) && dalloc(c->d_gslot, int64_t(c->gmask) + 1, e) &&
               dalloc(c->d_gstamp, int64_t(c->gmask) + 1, e) && dalloc(c->d_offs, c->offs_cap, e) &&
               dalloc(c->d_stat, ST_COUNT, e) && dalloc(c->d_spread, int64_t(kSpread) * kSpreadStride, e);
     if (ok) {
@@ -186,7 +185,7 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
     // finite contents everywhere, pads included (masked FP32 rows read them)
     fill_u32(reinterpret_cast<uint32_t *>(c->d_pts), 0u, 4 * (P + kPtsPad), c->stream);
     fill_u32(reinterpret_cast<uint32_t *>(c->d_W32), 0u, c->cap_w + kW32Pad, c->stream);
-    fill_u64(c->d_gkey, (unsigned long long)kNoKey, int64_t(c->gmask) + 1, c->stream);
+    grid_clear(c, c->stream);
     fill_u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1, c->stream);
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) {
         release(c);

@@ -50,6 +50,13 @@ __host__ __device__ inline uint64_t mix64(uint64_t k) {
 }
 
 // open-addressing table of 64-bit keys, linear probing, capacity 2^k
+// One slot of the global grid: the voxel key and its fused D and V in one
+// 16-byte record, so that a group of 8 slots fills one 128-byte line.
+struct GSlot {
+    unsigned long long key;    // kNoKey = empty
+    float D, V;
+};
+
 struct HashView {
     unsigned long long *keys;  // kNoKey = empty
     uint32_t mask;             // capacity - 1
@@ -71,6 +78,36 @@ __device__ inline int64_t hash_insert(HashView h, uint64_t key, bool *inserted) 
             if (cur == key) { *inserted = false; return int64_t(s); }
         }
         s = (s + 1) & h.mask;
+    }
+    *inserted = false;
+    return -1;
+}
+
+// Voxel tables hashed by 2x2x2 mini-brick: the key with the lowest bit of
+// each coordinate cleared picks a group of 8 consecutive slots, the voxel's
+// position in the brick (the three low bits) its slot in the group, and
+// probing moves by whole groups (every voxel keeps one probe sequence).
+// Neighbouring voxels then share cache lines.  The mask is at least 1023.
+constexpr uint64_t kBrickLowBits = (1ull << 42) | (1ull << 21) | 1ull;
+__device__ __forceinline__ uint64_t brick_slot(uint64_t key, uint32_t mask) {
+    const uint64_t local = ((key >> 40) & 4ull) | ((key >> 20) & 2ull) | (key & 1ull);
+    return ((mix64(key & ~kBrickLowBits) << 3) | local) & mask;
+}
+
+// hash_insert with the mini-brick probe sequence
+__device__ inline int64_t brick_insert(HashView h, uint64_t key, bool *inserted) {
+    uint64_t s = brick_slot(key, h.mask);
+    const uint32_t ngroups = (h.mask >> 3) + 1;
+    for (uint32_t p = 0; p < ngroups; ++p) {
+        unsigned long long cur = __hip_atomic_load(&h.keys[s], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == key) { *inserted = false; return int64_t(s); }
+        if (cur == kNoKey) {
+            cur = atomicCAS(&h.keys[s], (unsigned long long)kNoKey, (unsigned long long)key);
+            if (cur == kNoKey) { *inserted = true; return int64_t(s); }
+            if (cur == key) { *inserted = false; return int64_t(s); }
+        }
+        s = (s + 8) & h.mask;
     }
     *inserted = false;
     return -1;
@@ -244,6 +281,14 @@ enum Stat : int {
 // adding to a single line queue behind each other.  fold_stats adds the rows
 // into the statistics array and clears them (a kernel, so that it can be
 // captured in a graph).
+// Work counters of persistent launches: a slot per launch kind (0 FP32 /
+// FP64 evaluation, 1 FP64 re-evaluation, 2 large-cluster training), each
+// with one counter per XCD on its own 128-byte line.
+constexpr int kXcds = 8;
+constexpr int kCtrStride = 32;                     // u32 per counter line
+constexpr int kWorkSlot = kXcds * kCtrStride;
+constexpr int kWorkSlots = 3;
+
 constexpr int kSpread = 64;
 constexpr int kSpreadStride = 16 * ((ST_COUNT + 15) / 16);
 static_assert(ST_COUNT <= 64, "fold_stats takes one lane per counter");
@@ -329,7 +374,7 @@ struct gpdf_ctx {
     uint32_t *d_hist = nullptr;                    // radix histograms
     uint32_t *d_part = nullptr;                    // scan partials
     uint64_t *d_red = nullptr;                     // small reductions
-    uint32_t *d_work = nullptr;                    // work counters of persistent launches [8]
+    uint32_t *d_work = nullptr;                    // work counters of persistent launches [kWorkSlots][kWorkSlot]
     uint32_t *d_cnt = nullptr;                     // device counts [kCnt]
     uint32_t *d_wsz = nullptr, *d_asz = nullptr;   // per-cluster factor / workspace sizes
     uint32_t *d_wo32 = nullptr, *d_ao32 = nullptr; // their exclusive scans
@@ -381,8 +426,7 @@ struct gpdf_ctx {
     uint32_t tset_mask = 0;
     uint64_t *d_tkeys = nullptr;                   // compacted test keys
     float *d_tpts = nullptr;                       // test points [3]
-    unsigned long long *d_gkey = nullptr;          // global grid keys
-    float *d_gD = nullptr, *d_gV = nullptr;
+    gpdf::GSlot *d_gslot = nullptr;                // global grid slots (key, D, V)
     uint32_t *d_gstamp = nullptr;
     uint32_t gmask = 0;
     uint32_t frame = 0;
@@ -447,6 +491,7 @@ void count_occupied(const unsigned long long *keys, int64_t cap, uint32_t *tile_
 void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void fold_stats(unsigned long long *spread, unsigned long long *stat, hipStream_t s);
+void grid_clear(gpdf_ctx *c, hipStream_t s);
 
 // stages (train.hip, query.hip, fuse.hip, mlp.hip)
 gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn = nullptr);

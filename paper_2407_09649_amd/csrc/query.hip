@@ -911,18 +911,30 @@ __global__ __launch_bounds__(kEvalT, (eval_min_waves<T, PERSIST>())) void k_quer
         const uint32_t wave = xcd_item(nch);
         if (wave < nch) cells_chunk<T, KERN, MODE>(wave, q, G, lists, Mo, C, O);
     } else {
-        // the next chunk index is requested before the current chunk is
-        // evaluated, so the round trip of the counter overlaps the work;
-        // every wavefront stops at its first index past the last chunk
+        // The chunks form kXcds contiguous ranges, one per XCD (workgroups
+        // are dispatched round-robin over the XCDs), each taken through its
+        // own counter (zero at launch, one cache line each).  A wavefront
+        // drains the range of its XCD, then those of the following XCDs:
+        // neighbouring chunks share an L2 and the load still balances.  The
+        // next index is requested before the current chunk is evaluated, so
+        // the round trip of the counter overlaps the work.
         const bool lead = (threadIdx.x & 63) == 0;
-        uint32_t w = 0;
-        if (lead) w = atomicAdd(work, 1u);
-        w = uniform(uint32_t(__shfl(int(w), 0, 64)));
-        while (w < nch) {
-            uint32_t nx = 0;
-            if (lead) nx = atomicAdd(work, 1u);
-            cells_chunk<T, KERN, MODE>(w, q, G, lists, Mo, C, O);
-            w = uniform(uint32_t(__shfl(int(nx), 0, 64)));
+        const uint32_t per = (nch + kXcds - 1) / kXcds;
+        const uint32_t x0 = blockIdx.x % kXcds;
+        for (uint32_t r = 0; r < uint32_t(kXcds); ++r) {
+            const uint32_t x = (x0 + r) % kXcds;
+            const uint32_t lo = x * per, hi = min(nch, lo + per);
+            if (lo >= hi) continue;
+            uint32_t *ctr = work + x * kCtrStride;
+            uint32_t i = 0;
+            if (lead) i = atomicAdd(ctr, 1u);
+            i = uniform(uint32_t(__shfl(int(i), 0, 64)));
+            while (i < hi - lo) {
+                uint32_t nx = 0;
+                if (lead) nx = atomicAdd(ctr, 1u);
+                cells_chunk<T, KERN, MODE>(lo + i, q, G, lists, Mo, C, O);
+                i = uniform(uint32_t(__shfl(int(nx), 0, 64)));
+            }
         }
     }
 }
@@ -943,11 +955,93 @@ struct PairSlot {
     int bidx, n;
 };
 
+// Clusters above one panel are evaluated by the whole wavefront, one pair
+// at a time, in FP64.  Lanes take the points j = lane + 64 m for the kernel
+// values and the sums of Eq. (1) and (5), the kernel values go to LDS, and
+// then lanes take the rows of the factor panels (lanes 0-31 one panel,
+// 32-63 the next), so that each column of two panels is one coalesced read
+// of the FP64 factor; the partial sums are added over the wavefront.  The
+// nearest training point is the minimum of (distance, index): the same
+// decision as the scan in index order.  (Serially, one lane would stream the
+// whole factor of the cluster one column at a time.)
+constexpr int kCoopMaxN = 1024;   // the largest cluster the library accepts
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int KERN>
+__device__ PairSlot coop_pair(const QueryPoint &Q, int base, int n, int64_t woff, const ModelView &Mo,
+                              const QueryConsts &C, double *kbuf) {
+    const int lane = threadIdx.x & 63;
+    double o = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    float best = INFINITY;
+    int bidx = 0x7fffffff;
+    for (int j = lane; j < n; j += 64) {
+        const float4 p = Mo.pts[base + j];
+        const double a = Mo.alpha64[base + j];
+        const float ex = Q.fx - p.x, ey = Q.fy - p.y, ez = Q.fz - p.z;
+        const float r2f = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+        if (r2f < best) { best = r2f; bidx = base + j; }
+        const double dx = double(Q.fx) - double(p.x), dy = double(Q.fy) - double(p.y),
+                     dz = double(Q.fz) - double(p.z);
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        double k, e;
+        if (KERN == GPDF_KERNEL_MATERN32) {
+            const double t = ::sqrt(r2) * C.ad;
+            e = ::exp(-t);
+            k = fma(t, e, e);
+        } else {
+            k = ::exp(-(r2 * C.ad));
+            e = k;
+        }
+        o = fma(a, k, o);
+        const double cg = a * e;
+        gx = fma(cg, dx, gx);
+        gy = fma(cg, dy, gy);
+        gz = fma(cg, dz, gz);
+        kbuf[j] = k;
+    }
+    o = wave_sum(o); gx = wave_sum(gx); gy = wave_sum(gy); gz = wave_sum(gz);
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const float b2 = __shfl_xor(best, s, 64);
+        const int i2 = __shfl_xor(bidx, s, 64);
+        if (b2 < best || (b2 == best && i2 < bidx)) { best = b2; bidx = i2; }
+    }
+    __syncthreads();  // kernel values visible to every lane
+    const int nb = (n + kPanel - 1) / kPanel;
+    double ss = 0.0;
+    for (int r0 = 0; r0 < nb; r0 += 2) {
+        const int r = r0 + (lane >> 5);
+        if (r < nb) {
+            const double *Wp = Mo.W64 + woff + w32_panel_offset(n, r) + (lane & 31);
+            const int ncol = min((r + 1) * kPanel, n);
+            double v0 = 0.0, v1 = 0.0;
+            int j = 0;
+            for (; j + 1 < ncol; j += 2) {
+                v0 = fma(Wp[int64_t(j) * kPanel], kbuf[j], v0);
+                v1 = fma(Wp[int64_t(j + 1) * kPanel], kbuf[j + 1], v1);
+            }
+            if (j < ncol) v0 = fma(Wp[int64_t(j) * kPanel], kbuf[j], v0);
+            const double v = v0 + v1;
+            ss = fma(v, v, ss);
+        }
+    }
+    ss = wave_sum(ss);
+    __syncthreads();  // kbuf is rewritten by the next pair
+    const PairRaw<double> rr{o, gx, gy, gz, ss, 0.f};
+    return PairSlot{pair_out<double, KERN>(rr, n, C), best, bidx, n};
+}
+
 template <int KERN, int MODE>
 __global__ __launch_bounds__(kEvalT, 2) void k_refine_pairs(const float *__restrict__ q, Grouping G,
                                                         const int4 *__restrict__ lists, ModelView Mo, QueryConsts C,
                                                         Outputs O, uint32_t *work) {
     __shared__ PairSlot slot[64];
+    __shared__ double kbuf[kCoopMaxN];
     const int lane = threadIdx.x & 63;
     const uint32_t nch = *ro(G.nchunks);
     while (true) {
@@ -970,15 +1064,30 @@ __global__ __launch_bounds__(kEvalT, 2) void k_refine_pairs(const float *__restr
         if (pair_on) {
             const int4 d = L[1 + sl];
             const int base = d.y, n = d.z;
-            const float4 *P = Mo.pts + base;
-            const double *a64 = Mo.alpha64 + base;
-            const double *W = Mo.W64 + d.w;
-            PairRaw<double> r{0.0, 0.0, 0.0, 0.0, 0.0, 0.f};
-            if (n <= 8) eval_small<double, KERN, 8>(P, a64, W, n, base, Q, C, r, A);
-            else if (n <= 16) eval_small<double, KERN, 16>(P, a64, W, n, base, Q, C, r, A);
-            else if (n <= kPanel) eval_small<double, KERN, kPanel>(P, a64, W, n, base, Q, C, r, A);
-            else eval_panels<double, KERN>(P, a64, W, n, base, Q, C, r, A);
-            slot[lane] = PairSlot{pair_out<double, KERN>(r, n, C), A.best, A.bidx, n};
+            if (n <= kPanel) {
+                const float4 *P = Mo.pts + base;
+                const double *a64 = Mo.alpha64 + base;
+                const double *W = Mo.W64 + d.w;
+                PairRaw<double> r{0.0, 0.0, 0.0, 0.0, 0.0, 0.f};
+                if (n <= 8) eval_small<double, KERN, 8>(P, a64, W, n, base, Q, C, r, A);
+                else if (n <= 16) eval_small<double, KERN, 16>(P, a64, W, n, base, Q, C, r, A);
+                else eval_small<double, KERN, kPanel>(P, a64, W, n, base, Q, C, r, A);
+                slot[lane] = PairSlot{pair_out<double, KERN>(r, n, C), A.best, A.bidx, n};
+            }
+        }
+        // clusters above one panel: every pair by the whole wavefront
+        for (int s = 0; s < nsel; ++s) {
+            const int4 d = L[1 + s];
+            const int n = int(uniform(uint32_t(d.z)));
+            if (n <= kPanel) continue;
+            const int base = int(uniform(uint32_t(d.y)));
+            const int64_t woff = int64_t(uniform(uint32_t(d.w)));
+            for (uint32_t a = 0; a < cnt; ++a) {
+                const uint32_t qj = uniform(ro(G.order)[ro(G.cell_off)[cell] + start + a]);
+                const QueryPoint Qa{ro(q)[3 * qj], ro(q)[3 * qj + 1], ro(q)[3 * qj + 2]};
+                const PairSlot ps = coop_pair<KERN>(Qa, base, n, woff, Mo, C, kbuf);
+                if (lane == 0) slot[a * nsel + s] = ps;
+            }
         }
         __syncthreads();
         // the first lane of each query accumulates its pairs in cluster order
@@ -1338,8 +1447,8 @@ void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_
     const int per = c->tune.eval_persistent > 0 ? c->tune.eval_persistent : (c->capturing ? 4 : 0);
     if (per > 0 && !knn) {
         // 256 CUs x 4 SIMDs x the wavefronts per SIMD
-        work = c->d_work + slot;
-        fill_u32(work, 0u, 1, s);
+        work = c->d_work + int64_t(slot) * kWorkSlot;
+        fill_u32(work, 0u, kWorkSlot, s);
         grid = std::min<unsigned>(grid, 1024u * unsigned(per));
     }
     if (kernel == GPDF_KERNEL_MATERN32)
@@ -1609,7 +1718,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
             launch_query_k<double>(c, kern, knn, grid, s, d_q, R, c->d_cell_list, Mo, C, O64, 1);
         } else {
             // pair-parallel, persistent: two wavefronts per SIMD
-            uint32_t *work = c->d_work + 1;
+            uint32_t *work = c->d_work + kWorkSlot;
             fill_u32(work, 0u, 1, s);
             const unsigned rg = 2048;
             if (kern == GPDF_KERNEL_MATERN32)

@@ -686,11 +686,11 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
     hipLaunchKernelGGL(k_train_wave, dim3(unsigned(std::min<int64_t>(C, 2048))), dim3(64), 0, s, c->d_blist + C,
                        cnt + CNT_WAVE, c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
                        c->p.kernel, l, s2, c->d_stat);
-    fill_u32(c->d_work + 2, 0u, 1, s);
+    fill_u32(c->d_work + 2 * kWorkSlot, 0u, 1, s);
     {
         const unsigned gb = unsigned(std::min<int64_t>(C, 256));
 #define GPDF_TRAIN_BLOCK(T)                                                                                    \
-    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, s, c->d_blist + 2 * C, cnt + CNT_BIG, c->d_work + 2, \
+    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, s, c->d_blist + 2 * C, cnt + CNT_BIG, c->d_work + 2 * kWorkSlot, \
                        c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64,     \
                        c->d_pd, c->p.kernel, l, s2, c->d_stat)
         if (c->tune.train_threads == 512) GPDF_TRAIN_BLOCK(512);
