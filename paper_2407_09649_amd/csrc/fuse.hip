@@ -110,20 +110,20 @@ __global__ void k_fuse(const uint64_t *__restrict__ keys, const uint32_t *__rest
                        const float *__restrict__ d, const float *__restrict__ v,
                        const uint8_t *__restrict__ ok, GSlot *__restrict__ g, uint32_t gmask,
                        uint32_t *__restrict__ gstamp, uint32_t frame_h, const uint32_t *__restrict__ dframe,
-                       unsigned long long *__restrict__ stat) {
+                       unsigned long long *__restrict__ spread) {
     const int64_t n = int64_t(*nptr);
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (int64_t(blockIdx.x) * blockDim.x >= n) return;  // whole block past the end
     const bool in = i < n;
     const float di = in ? d[i] : 0.f, vi = in ? v[i] : 0.f;
     const bool use = in && ok[i] && isfinite(di) && isfinite(vi) && vi > 0.f;
-    wave_count(&stat[ST_FUSE_SKIPPED], in && !use);
+    spread_count(spread, ST_FUSE_SKIPPED, in && !use);
     bool ins = false;
     int64_t s = -1;
     if (use) s = grid_insert(g, gmask, keys[i], &ins);
-    wave_count(&stat[ST_GLOBAL_FULL], use && s < 0);
-    wave_count(&stat[ST_GLOBAL_COUNT], s >= 0 && ins);
-    wave_count(&stat[ST_FUSED], s >= 0);
+    spread_count(spread, ST_GLOBAL_FULL, use && s < 0);
+    spread_count(spread, ST_GLOBAL_COUNT, s >= 0 && ins);
+    spread_count(spread, ST_FUSED, s >= 0);
     if (s < 0) return;
     if (ins) {
         g[s].D = di;
@@ -323,7 +323,8 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin, int64_
     stage_begin(c, GPDF_MS_FUSE);
     hipLaunchKernelGGL(k_fuse, dim3(blocks_for(nt)), dim3(kT), 0, s, c->d_tkeys, cnt + CNT_TEST, c->d_tmp_dist,
                        c->d_tmp_var, c->d_tmp_valid, c->d_gslot, c->gmask, c->d_gstamp, c->frame,
-                       eager ? nullptr : cnt + CNT_FRAME, c->d_stat);
+                       eager ? nullptr : cnt + CNT_FRAME, c->d_spread);
+    fold_stats(c->d_spread, c->d_stat, s);
     stage_end(c, GPDF_MS_FUSE);
     if (eager) c->frame++;
     return (e = hipGetLastError()) == hipSuccess ? GPDF_OK : hip_fail(c, e, "fuse launch");

@@ -295,6 +295,12 @@ static_assert(ST_COUNT <= 64, "fold_stats takes one lane per counter");
 __device__ __forceinline__ void spread_add(unsigned long long *sp, int st, unsigned long long v) {
     atomicAdd(&sp[size_t(blockIdx.x % kSpread) * kSpreadStride + st], v);
 }
+// adds the wavefront's count of pred to counter st of the spread rows; no
+// value comes back, so no lane waits for the atomic
+__device__ __forceinline__ void spread_count(unsigned long long *sp, int st, bool pred) {
+    const uint64_t mb = __ballot(pred);
+    if (mb && int(threadIdx.x & 63) == __ffsll((long long)mb) - 1) spread_add(sp, st, __popcll(mb));
+}
 
 // per-cluster FP32 factor layout: packed rows for n <= 32, 32-row panels
 // (column-major inside the panel) above that

@@ -233,12 +233,16 @@ __device__ __forceinline__ void train_block_body(double *__restrict__ A, double 
         __syncthreads();
         for (int j = tid; j < k; j += T) A[tri(k, j)] = wrow[j];
         if (tid == 0) A[tri(k, k)] = inv;
-        for (int p = tri(k + 1, 0) + tid; p < end; p += T) {
-            const int i = tri_row(p), j = p - i * (i + 1) / 2;
+        // rows below k: a packed row (contiguous) per wavefront, its columns
+        // over the lanes
+        for (int i = k + 1 + wv; i < n; i += kW) {
+            double *Ai = A + tri(i, 0);
             const double li = colm[i];
-            if (j < k) A[p] -= li * wrow[j];
-            else if (j == k) A[p] = -li * inv;
-            else A[p] -= li * colm[j];
+            for (int j = lane; j <= i; j += 64) {
+                if (j < k) Ai[j] -= li * wrow[j];
+                else if (j == k) Ai[j] = -li * inv;
+                else Ai[j] -= li * colm[j];
+            }
         }
     }
     __syncthreads();
