@@ -970,83 +970,83 @@ struct PairSlot {
     int bidx, n;
 };
 
-// Clusters above one panel are evaluated by the whole wavefront, one pair
-// at a time, in FP64.  Lanes take the points j = lane + 64 m for the kernel
-// values and the sums of Eq. (1) and (5), the kernel values go to LDS, and
-// then lanes take the rows of the factor panels (lanes 0-31 one panel,
-// 32-63 the next), so that each column of two panels is one coalesced read
-// of the FP64 factor; the partial sums are added over the wavefront.  The
-// nearest training point is the minimum of (distance, index): the same
-// decision as the scan in index order.  (Serially, one lane would stream the
-// whole factor of the cluster one column at a time.)
+// Clusters above one panel are evaluated in FP64 by groups of L lanes (L a
+// power of two, 8 to 64), one query per group, so that one pass serves up to
+// 64 / L queries of the chunk.  Within a group, lanes take the points
+// j = g + L m for the kernel values and the sums of Eq. (1) and (5), the
+// kernel values go to the group's slice of LDS, and then lanes take the rows
+// i = g + L m of the factor: rows of a panel are consecutive in a column, so
+// the lanes of a group read consecutive elements of the FP64 factor, and a
+// row stops at its diagonal.  The partial sums are added within the group;
+// the nearest training point is the minimum of (distance, index), the same
+// decision as the scan in index order.
 constexpr int kCoopMaxN = 1024;   // the largest cluster the library accepts
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+template <typename V>
+__device__ __forceinline__ V group_sum(V v, int L) {
+    for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
 template <int KERN>
-__device__ PairSlot coop_pair(const QueryPoint &Q, int base, int n, int64_t woff, const ModelView &Mo,
-                              const QueryConsts &C, double *kbuf) {
-    const int lane = threadIdx.x & 63;
+__device__ PairSlot coop_group(const QueryPoint &Q, bool on, int L, int base, int n, int64_t woff,
+                               const ModelView &Mo, const QueryConsts &C, double *kb) {
+    const int g = int(threadIdx.x & 63) & (L - 1);
     double o = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
     float best = INFINITY;
     int bidx = 0x7fffffff;
-    for (int j = lane; j < n; j += 64) {
-        const float4 p = Mo.pts[base + j];
-        const double a = Mo.alpha64[base + j];
-        const float ex = Q.fx - p.x, ey = Q.fy - p.y, ez = Q.fz - p.z;
-        const float r2f = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
-        if (r2f < best) { best = r2f; bidx = base + j; }
-        const double dx = double(Q.fx) - double(p.x), dy = double(Q.fy) - double(p.y),
-                     dz = double(Q.fz) - double(p.z);
-        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        double k, e;
-        if (KERN == GPDF_KERNEL_MATERN32) {
-            const double t = ::sqrt(r2) * C.ad;
-            e = ::exp(-t);
-            k = fma(t, e, e);
-        } else {
-            k = ::exp(-(r2 * C.ad));
-            e = k;
+    if (on) {
+        for (int j = g; j < n; j += L) {
+            const float4 p = Mo.pts[base + j];
+            const double a = Mo.alpha64[base + j];
+            const float ex = Q.fx - p.x, ey = Q.fy - p.y, ez = Q.fz - p.z;
+            const float r2f = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+            if (r2f < best) { best = r2f; bidx = base + j; }
+            const double dx = double(Q.fx) - double(p.x), dy = double(Q.fy) - double(p.y),
+                         dz = double(Q.fz) - double(p.z);
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            double k, e;
+            if (KERN == GPDF_KERNEL_MATERN32) {
+                const double t = ::sqrt(r2) * C.ad;
+                e = ::exp(-t);
+                k = fma(t, e, e);
+            } else {
+                k = ::exp(-(r2 * C.ad));
+                e = k;
+            }
+            o = fma(a, k, o);
+            const double cg = a * e;
+            gx = fma(cg, dx, gx);
+            gy = fma(cg, dy, gy);
+            gz = fma(cg, dz, gz);
+            kb[j] = k;
         }
-        o = fma(a, k, o);
-        const double cg = a * e;
-        gx = fma(cg, dx, gx);
-        gy = fma(cg, dy, gy);
-        gz = fma(cg, dz, gz);
-        kbuf[j] = k;
     }
-    o = wave_sum(o); gx = wave_sum(gx); gy = wave_sum(gy); gz = wave_sum(gz);
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
+    o = group_sum(o, L); gx = group_sum(gx, L); gy = group_sum(gy, L); gz = group_sum(gz, L);
+    for (int s = 1; s < L; s <<= 1) {
         const float b2 = __shfl_xor(best, s, 64);
         const int i2 = __shfl_xor(bidx, s, 64);
         if (b2 < best || (b2 == best && i2 < bidx)) { best = b2; bidx = i2; }
     }
-    __syncthreads();  // kernel values visible to every lane
-    const int nb = (n + kPanel - 1) / kPanel;
+    __syncthreads();  // kernel values visible to the group
     double ss = 0.0;
-    for (int r0 = 0; r0 < nb; r0 += 2) {
-        const int r = r0 + (lane >> 5);
-        if (r < nb) {
-            const double *Wp = Mo.W64 + woff + w32_panel_offset(n, r) + (lane & 31);
-            const int ncol = min((r + 1) * kPanel, n);
+    if (on) {
+        for (int i = g; i < n; i += L) {
+            const int r = i / kPanel;
+            const double *Wp = Mo.W64 + woff + w32_panel_offset(n, r) + (i - r * kPanel);
             double v0 = 0.0, v1 = 0.0;
             int j = 0;
-            for (; j + 1 < ncol; j += 2) {
-                v0 = fma(Wp[int64_t(j) * kPanel], kbuf[j], v0);
-                v1 = fma(Wp[int64_t(j + 1) * kPanel], kbuf[j + 1], v1);
+            for (; j + 1 <= i; j += 2) {
+                v0 = fma(Wp[int64_t(j) * kPanel], kb[j], v0);
+                v1 = fma(Wp[int64_t(j + 1) * kPanel], kb[j + 1], v1);
             }
-            if (j < ncol) v0 = fma(Wp[int64_t(j) * kPanel], kbuf[j], v0);
+            if (j <= i) v0 = fma(Wp[int64_t(j) * kPanel], kb[j], v0);
             const double v = v0 + v1;
             ss = fma(v, v, ss);
         }
     }
-    ss = wave_sum(ss);
-    __syncthreads();  // kbuf is rewritten by the next pair
+    ss = group_sum(ss, L);
+    __syncthreads();  // the slices are rewritten by the next pass
     const PairRaw<double> rr{o, gx, gy, gz, ss, 0.f};
     return PairSlot{pair_out<double, KERN>(rr, n, C), best, bidx, n};
 }
@@ -1090,18 +1090,27 @@ __global__ __launch_bounds__(kEvalT, 2) void k_refine_pairs(const float *__restr
                 slot[lane] = PairSlot{pair_out<double, KERN>(r, n, C), A.best, A.bidx, n};
             }
         }
-        // clusters above one panel: every pair by the whole wavefront
+        // clusters above one panel: groups of lanes, one query per group
         for (int s = 0; s < nsel; ++s) {
             const int4 d = L[1 + s];
             const int n = int(uniform(uint32_t(d.z)));
             if (n <= kPanel) continue;
             const int base = int(uniform(uint32_t(d.y)));
             const int64_t woff = int64_t(uniform(uint32_t(d.w)));
-            for (uint32_t a = 0; a < cnt; ++a) {
-                const uint32_t qj = uniform(ro(G.order)[ro(G.cell_off)[cell] + start + a]);
-                const QueryPoint Qa{ro(q)[3 * qj], ro(q)[3 * qj + 1], ro(q)[3 * qj + 2]};
-                const PairSlot ps = coop_pair<KERN>(Qa, base, n, woff, Mo, C, kbuf);
-                if (lane == 0) slot[a * nsel + s] = ps;
+            // groups: at most 8, at most cnt, and their kernel values fit LDS
+            const int gmax = min(min(8, int(cnt)), kCoopMaxN / n);
+            int ng = 1;
+            while (ng < gmax) ng <<= 1;
+            if (ng > gmax && ng > 1) ng >>= 1;
+            const int Lg = 64 / ng;
+            const int gi = lane / Lg;
+            for (uint32_t a0 = 0; a0 < cnt; a0 += uint32_t(ng)) {
+                const uint32_t a = a0 + uint32_t(gi);
+                const bool on = a < cnt;
+                const uint32_t qj = G.order[ro(G.cell_off)[cell] + start + (on ? a : 0u)];
+                const QueryPoint Qa{q[3 * qj], q[3 * qj + 1], q[3 * qj + 2]};
+                const PairSlot ps = coop_group<KERN>(Qa, on, Lg, base, n, woff, Mo, C, kbuf + gi * n);
+                if (on && (lane & (Lg - 1)) == 0) slot[a * nsel + s] = ps;
             }
         }
         __syncthreads();
@@ -1732,10 +1741,10 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         if (knn) {
             launch_query_k<double>(c, kern, knn, grid, s, d_q, R, c->d_cell_list, Mo, C, O64, 1);
         } else {
-            // pair-parallel, persistent: two wavefronts per SIMD
+            // pair-parallel, persistent: three wavefronts per SIMD
             uint32_t *work = c->d_work + kWorkSlot;
             fill_u32(work, 0u, 1, s);
-            const unsigned rg = 2048;
+            const unsigned rg = 3072;
             if (kern == GPDF_KERNEL_MATERN32)
                 launch_refine_pairs<GPDF_KERNEL_MATERN32>(rg, s, d_q, R, c->d_cell_list, Mo, C, O64, work);
             else
