@@ -180,6 +180,9 @@ gpdf_status gpdf_train_local_gps(gpdf_ctx *ctx, const float *d_xyz, int64_t n);
  * occupancy and latent variance of the closest cluster and the number of
  * training points used.  correct != 0 applies the learned correction where
  * the variance is at most mlp_gate (requires gpdf_mlp_* weights).
+ * Precision: FP32 with an FP64 re-evaluation of the queries whose estimated
+ * FP32 error exceeds the tolerance of a requested output (distance always,
+ * gradient and variance when their buffers are given).
  * Errors: GPDF_E_NOT_TRAINED, GPDF_E_CAPACITY (m > max_queries). */
 gpdf_status gpdf_query_distance(gpdf_ctx *ctx, const float *d_q, int64_t m,
                                 const float *h_origin, float *d_dist,

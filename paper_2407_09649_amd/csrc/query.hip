@@ -786,9 +786,10 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
         if (O.var) O.var[qi] = float(V);
         if (O.aux) { O.aux[3 * qi] = float(A.ho); O.aux[3 * qi + 1] = float(A.hu); O.aux[3 * qi + 2] = float(A.ntot); }
         if constexpr (f32) {
+            // an output the caller did not ask for is not refined for
             bd = !(Ed <= C.tau_d);
-            bg = !(Eg <= C.tau_g);
-            bv = !(Ev <= C.tau_v);
+            bg = O.grad && !(Eg <= C.tau_g);
+            bv = O.var && !(Ev <= C.tau_v);
             bad = bd || bg || bv;
         }
     }

@@ -100,6 +100,35 @@ def test_small_lidar_frame_full_parity(dev):
     assert (g["dist"][g["valid"].astype(bool)] < 0).any()  # both sides of surfaces
 
 
+def test_unrequested_outputs_are_not_refined(dev):
+    """The FP64 re-evaluation serves the outputs a call asks for: without a
+    gradient buffer no query is redone for its gradient, without a variance
+    buffer none for its variance, and the requested outputs keep their
+    tolerance against the oracle."""
+    pts = _lidar(7, beams=16, az=256)
+    q = S.lidar_band_queries(pts, radius_cells=4)
+    origin = np.array([0.0, 0.0, 1.5], np.float32)
+    with _ctx(dev, voxel_size=0.1) as ctx:
+        _train(ctx, pts)
+        qd = torch.from_numpy(q).to(dev)
+        full = ctx.query(qd, origin=origin)
+        st_full = ctx.stats()
+        dv = ctx.query(qd, origin=origin, grad=False, aux=False)
+        st_dv = ctx.stats()
+        d = ctx.query(qd, origin=origin, grad=False, var=False, aux=False)
+        st_d = ctx.stats()
+        om = O.Model(oracle_params(ctx.params), pts)
+    assert st_full["refine_grad"] > 0 and st_full["refine_var"] > 0
+    assert st_dv["refine_grad"] == 0 and st_d["refine_grad"] == 0 and st_d["refine_var"] == 0
+    assert st_d["refined_queries"] <= st_dv["refined_queries"] < st_full["refined_queries"]
+    ref = om.query(q, origin=origin)
+    v = ref["valid"]
+    for out in (full, dv, d):
+        assert np.array_equal(out["valid"].cpu().numpy().astype(bool), v)
+        assert np.abs(out["dist"].cpu().numpy()[v] - ref["dist"][v]).max() <= 1e-4
+    assert np.abs(dv["var"].cpu().numpy()[v] / ref["var"][v] - 1).max() <= 2e-3
+
+
 def test_full_lidar_frame_sampled_parity(dev):
     """The benchmark's workload: one 64 x 1024 scan, ~4.9M band queries,
     evaluated in one call; 30,000 sampled queries against the oracle."""
