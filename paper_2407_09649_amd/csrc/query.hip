@@ -58,6 +58,13 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// The template argument KERN carries the kernel (GPDF_KERNEL_*) and, in the
+// bit kNoGrad, that the call asked for no gradient: the FP32 instances then
+// leave out the gradient sums, its reverting and its error estimate.
+constexpr int kNoGrad = 8;
+constexpr int kern_kind(int k) { return k & 7; }
+constexpr bool kern_grad(int k) { return (k & kNoGrad) == 0; }
+
 // Data that no kernel of a launch writes (model arrays, cell lists, chunk
 // table, counts) is read through the constant address space.  That tells
 // the compiler that no store of the kernel can change it, so its uniform
@@ -337,7 +344,7 @@ __device__ __forceinline__ T point_eval(const float4 p, T alpha, const QueryPoin
     }
     const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     T k, e, t;
-    if (KERN == GPDF_KERNEL_MATERN32) {
+    if (kern_kind(KERN) == GPDF_KERNEL_MATERN32) {
         t = RT<T>::sqrt(r2) * T(std::is_same<T, float>::value ? C.a : C.ad);  // sqrt(3) r / l
         e = RT<T>::expn(t);
         k = fma(t, e, e);                   // (1 + t) e^{-t}
@@ -347,10 +354,12 @@ __device__ __forceinline__ T point_eval(const float4 p, T alpha, const QueryPoin
         e = k;
     }
     r.o = fma(alpha, k, r.o);
-    const T cg = alpha * e;
-    r.gx = fma(cg, dx, r.gx);
-    r.gy = fma(cg, dy, r.gy);
-    r.gz = fma(cg, dz, r.gz);
+    if constexpr (kern_grad(KERN)) {
+        const T cg = alpha * e;
+        r.gx = fma(cg, dx, r.gx);
+        r.gy = fma(cg, dy, r.gy);
+        r.gz = fma(cg, dz, r.gz);
+    }
     if constexpr (std::is_same<T, float>::value) {
         // root-sum-square scale of the rounding errors of the terms alpha k,
         // whose relative error grows like (1 + t) through the exponent
@@ -379,7 +388,7 @@ __device__ __forceinline__ T point_k(const float4 p, const QueryPoint &Q, const 
         dx = double(Q.fx) - double(p.x); dy = double(Q.fy) - double(p.y); dz = double(Q.fz) - double(p.z);
     }
     const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    if (KERN == GPDF_KERNEL_MATERN32) {
+    if (kern_kind(KERN) == GPDF_KERNEL_MATERN32) {
         const T t = RT<T>::sqrt(r2) * T(std::is_same<T, float>::value ? C.a : C.ad);
         const T e = RT<T>::expn(t);
         return fma(t, e, e);
@@ -617,7 +626,7 @@ __device__ __forceinline__ PairOut<T> pair_out(const PairRaw<T> &r, int n, const
     const T cc = f32 ? T(C.c) : T(C.cd), aa = f32 ? T(C.a) : T(C.ad);
     T d, lam, gsc;    // distance, Lambda, gradient scale
     float sens;       // |d ln(gsc) / d o| (error estimate)
-    if (KERN == GPDF_KERNEL_MATERN32) {
+    if (kern_kind(KERN) == GPDF_KERNEL_MATERN32) {
         const T t = matern_t<T>(oc);
         const T E = RT<T>::expn(t);
         const T tE = t * E;
@@ -646,8 +655,9 @@ __device__ __forceinline__ PairOut<T> pair_out(const PairRaw<T> &r, int n, const
         lam = f32 ? T(C.cap_lo[1]) : T(C.cap_lod[1]);
         gsc = f32 ? T(C.cap_lo[2]) : T(C.cap_lod[2]);
     }
+    constexpr bool grad = kern_grad(KERN);
     const T gs = o < omin ? T(0) : gsc;
-    const T gx = gs * r.gx, gy = gs * r.gy, gz = gs * r.gz;
+    const T gx = grad ? gs * r.gx : T(0), gy = grad ? gs * r.gy : T(0), gz = grad ? gs * r.gz : T(0);
     const T v = lam * lam * u;
     float ed = 0.f, eg = 0.f, ev = 0.f, gn = 0.f;
     if constexpr (f32) {
@@ -656,19 +666,20 @@ __device__ __forceinline__ PairOut<T> pair_out(const PairRaw<T> &r, int n, const
         // term errors plus the reverting solve, which settles at ~ eps o
         const float sS = fsqrt(r.S);
         const float dO = C.err_c * kEps * sS + 2.f * kEps * oc;
-        gn = fsqrt(fmaf(gz, gz, fmaf(gy, gy, gx * gx)));
+        if constexpr (grad) gn = fsqrt(fmaf(gz, gz, fmaf(gy, gy, gx * gx)));
         // o clearly beyond a cap (by more than its error): d, Lambda and v are
         // the constants of the cap and do not see the error of o; below the
         // lower cap the gradient is exactly zero
         const bool low = o < omin - 4.f * dO, high = o > omax + 4.f * dO;
         const float dOe = (low || high) ? 0.f : dO;
         ed = fabsf(lam) * dOe + 4.f * kEps * d;
-        eg = low ? 0.f : gsc * C.err_c * kEps * sS * frcp(C.a) + gn * sens * dOe + 8.f * kEps * gn;
+        if constexpr (grad)
+            eg = low ? 0.f : gsc * C.err_c * kEps * sS * frcp(C.a) + gn * sens * dOe + 8.f * kEps * gn;
         ev = 2.f * sens * dOe + 4.f * kEps * float(n) * frcp(fmaxf(u, 1e-30f)) + 8.f * kEps;
         // o within its error of the lower cap: the FP32 decision that switches
         // the gradient off is not reliable, and the gradient is either zero
         // or about gsc |grad o|
-        if (fabsf(o - omin) <= 4.f * dO) {
+        if (grad && fabsf(o - omin) <= 4.f * dO) {
             const float go = fsqrt(fmaf(float(r.gz), float(r.gz), fmaf(float(r.gy), float(r.gy), float(r.gx) * float(r.gx))));
             eg += float(gsc) * go;
         }
@@ -678,15 +689,16 @@ __device__ __forceinline__ PairOut<T> pair_out(const PairRaw<T> &r, int n, const
 
 // accumulation of one pair into the combination of its query (closest node,
 // online smooth minimum, plain gradient sum, counts)
-template <typename T>
+template <typename T, bool GRAD = true>
 __device__ __forceinline__ void pair_accumulate(const PairOut<T> &P, int n, const QueryConsts &C, Acc<T> &A) {
     constexpr bool f32 = std::is_same<T, float>::value;
     const T d = P.d, v = P.v, gx = P.gx, gy = P.gy, gz = P.gz, o = P.o, u = P.u;
     const float ed = P.ed, eg = P.eg, ev = P.ev, gn = P.gn;
     // closest node (strict <: the first in ascending key order wins ties)
     if (d < A.hd) {
-        A.hd = d; A.hv = v; A.hgx = gx; A.hgy = gy; A.hgz = gz; A.ho = o; A.hu = u;
-        A.hed = ed; A.heg = eg; A.hev = ev;
+        A.hd = d; A.hv = v; A.ho = o; A.hu = u;
+        A.hed = ed; A.hev = ev;
+        if constexpr (GRAD) { A.hgx = gx; A.hgy = gy; A.hgz = gz; A.heg = eg; }
     }
     // smooth minimum, online: rescale the sums when the minimum moves
     const T delta = d - A.m;
@@ -700,30 +712,34 @@ __device__ __forceinline__ void pair_accumulate(const PairOut<T> &P, int n, cons
         A.A2 = so * fmaf(shift, A.A1, A.A2) + w * ed * (newmin ? 0.f : float(delta));
         if (!(A.m < INFINITY)) A.A2 = 0.f;
         A.A1 = fmaf(so, A.A1, w * ed);
-        A.B1 = fmaf(so, A.B1, w * eg);
-        const float wed = w * ed;
-        A.Ggx = fmaf(so, A.Ggx, wed * gx);
-        A.Ggy = fmaf(so, A.Ggy, wed * gy);
-        A.Ggz = fmaf(so, A.Ggz, wed * gz);
-        A.G2 = fmaf(so, A.G2, wed * gn * gn);
         A.C1 = fmaf(so, A.C1, w * v * ev);
-        A.sum_eg += eg;
+        if constexpr (GRAD) {
+            A.B1 = fmaf(so, A.B1, w * eg);
+            const float wed = w * ed;
+            A.Ggx = fmaf(so, A.Ggx, wed * gx);
+            A.Ggy = fmaf(so, A.Ggy, wed * gy);
+            A.Ggz = fmaf(so, A.Ggz, wed * gz);
+            A.G2 = fmaf(so, A.G2, wed * gn * gn);
+            A.sum_eg += eg;
+        }
     }
     A.sw = fma(so, A.sw, w);
     A.swd = fma(so, A.swd, w * d);
     A.swv = fma(so, A.swv, w * v);
-    A.sgx = fma(so, A.sgx, w * gx);
-    A.sgy = fma(so, A.sgy, w * gy);
-    A.sgz = fma(so, A.sgz, w * gz);
+    if constexpr (GRAD) {
+        A.sgx = fma(so, A.sgx, w * gx);
+        A.sgy = fma(so, A.sgy, w * gy);
+        A.sgz = fma(so, A.sgz, w * gz);
+        A.pgx += gx; A.pgy += gy; A.pgz += gz;
+    }
     A.m = fmin(A.m, d);
-    A.pgx += gx; A.pgy += gy; A.pgz += gz;
     A.nq += 1;
     A.ntot += n;
 }
 
 template <typename T, int KERN>
 __device__ __forceinline__ void finish_pair(const PairRaw<T> &r, int n, const QueryConsts &C, Acc<T> &A) {
-    pair_accumulate<T>(pair_out<T, KERN>(r, n, C), n, C, A);
+    pair_accumulate<T, kern_grad(KERN)>(pair_out<T, KERN>(r, n, C), n, C, A);
 }
 
 struct Outputs {
@@ -1007,7 +1023,7 @@ __device__ PairSlot coop_group(const QueryPoint &Q, bool on, int L, int base, in
                          dz = double(Q.fz) - double(p.z);
             const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             double k, e;
-            if (KERN == GPDF_KERNEL_MATERN32) {
+            if (kern_kind(KERN) == GPDF_KERNEL_MATERN32) {
                 const double t = ::sqrt(r2) * C.ad;
                 e = ::exp(-t);
                 k = fma(t, e, e);
@@ -1198,7 +1214,7 @@ __device__ __forceinline__ float point_eval_b(const float4 p, const QueryPoint &
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     if (r2 < A.best) { A.best = r2; A.bidx = gidx; }
     float k, e;
-    if (KERN == GPDF_KERNEL_MATERN32) {
+    if (kern_kind(KERN) == GPDF_KERNEL_MATERN32) {
         const float t = fsqrt(r2) * C.a;
         e = fexp2(-t * kLog2e);
         k = fmaf(t, e, e);
@@ -1475,6 +1491,15 @@ void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_
         work = c->d_work + int64_t(slot) * kWorkSlot;
         fill_u32(work, 0u, kWorkSlot, s);
         grid = std::min<unsigned>(grid, 1024u * unsigned(per));
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        if (!O.grad) {
+            if (kernel == GPDF_KERNEL_MATERN32)
+                launch_query_m<T, GPDF_KERNEL_MATERN32 | kNoGrad>(knn, grid, s, q, G, lists, Mo, C, O, work);
+            else
+                launch_query_m<T, GPDF_KERNEL_SE | kNoGrad>(knn, grid, s, q, G, lists, Mo, C, O, work);
+            return;
+        }
     }
     if (kernel == GPDF_KERNEL_MATERN32)
         launch_query_m<T, GPDF_KERNEL_MATERN32>(knn, grid, s, q, G, lists, Mo, C, O, work);
