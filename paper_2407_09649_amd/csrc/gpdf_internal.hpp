@@ -227,6 +227,7 @@ enum DevCount : int {
     CNT_TEST,     // test voxels (clamped to max_queries)
     CNT_FRAME,    // frame stamp (graph input)
     CNT_M,        // query count read by the kernels (graph)
+    CNT_RHEAVY,   // re-evaluation chunks of cells with a cluster above one panel
     kCnt
 };
 

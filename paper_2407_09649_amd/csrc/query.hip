@@ -262,12 +262,38 @@ __global__ void k_refine_count(const uint2 *__restrict__ rec, const unsigned lon
 
 // chunks of the re-evaluation: 64 queries per chunk, or with the cell lists
 // (pair-parallel pass) floor(64 / nsel)
+// re-evaluation chunks per cell; rheavy repeats the count for cells whose
+// list holds a cluster above one panel (their chunks cost far more) and is
+// zero elsewhere
 __global__ void k_refine_chunks(int64_t ncb, const uint32_t *__restrict__ dnc, const uint32_t *__restrict__ rcnt,
-                                const int4 *__restrict__ lists, uint32_t *__restrict__ rchunks) {
+                                const int4 *__restrict__ lists, uint32_t *__restrict__ rchunks,
+                                uint32_t *__restrict__ rheavy) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= dev_count(ncb, dnc)) return;
     const uint32_t per = lists ? uint32_t(refine_qpw(lists[c * kListStride].x)) : 64u;
-    rchunks[c] = (rcnt[c] + per - 1) / per;
+    const uint32_t k = (rcnt[c] + per - 1) / per;
+    bool heavy = false;
+    if (lists && k > 0) {
+        const int4 *L = lists + c * kListStride;
+        for (int s = 0; s < L[0].x; ++s) heavy = heavy || L[1 + s].z > kPanel;
+    }
+    rchunks[c] = k;
+    rheavy[c] = heavy ? k : 0u;
+}
+
+// chunk table of the re-evaluation, the chunks of heavy cells first (so that
+// the persistent pass starts its longest chunks early), then the others in
+// cell order: roff counts the chunks of all cells before c, hoff those of
+// the heavy cells, *nheavy all heavy chunks
+__global__ void k_refine_table(int64_t ncb, const uint32_t *__restrict__ dnc, const uint32_t *__restrict__ rchunks,
+                               const uint32_t *__restrict__ roff, const uint32_t *__restrict__ rheavy,
+                               const uint32_t *__restrict__ hoff, const uint32_t *__restrict__ nheavy,
+                               const int4 *__restrict__ lists, uint2 *__restrict__ chunk) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= dev_count(ncb, dnc)) return;
+    const uint32_t per = lists ? uint32_t(refine_qpw(lists[c * kListStride].x)) : 64u;
+    const uint32_t o = rheavy[c] ? hoff[c] : *nheavy + (roff[c] - hoff[c]);
+    for (uint32_t j = 0; j < rchunks[c]; ++j) chunk[o + j] = make_uint2(uint32_t(c), j * per);
 }
 
 __global__ void k_refine_scatter(const uint2 *__restrict__ rec, const unsigned long long *__restrict__ nrec,
@@ -1051,14 +1077,17 @@ __device__ PairSlot coop_group(const QueryPoint &Q, bool on, int L, int base, in
         for (int i = g; i < n; i += L) {
             const int r = i / kPanel;
             const double *Wp = Mo.W64 + woff + w32_panel_offset(n, r) + (i - r * kPanel);
-            double v0 = 0.0, v1 = 0.0;
+            // four independent partial sums keep four loads in flight
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
             int j = 0;
-            for (; j + 1 <= i; j += 2) {
+            for (; j + 3 <= i; j += 4) {
                 v0 = fma(Wp[int64_t(j) * kPanel], kb[j], v0);
                 v1 = fma(Wp[int64_t(j + 1) * kPanel], kb[j + 1], v1);
+                v2 = fma(Wp[int64_t(j + 2) * kPanel], kb[j + 2], v2);
+                v3 = fma(Wp[int64_t(j + 3) * kPanel], kb[j + 3], v3);
             }
-            if (j <= i) v0 = fma(Wp[int64_t(j) * kPanel], kb[j], v0);
-            const double v = v0 + v1;
+            for (; j <= i; ++j) v0 = fma(Wp[int64_t(j) * kPanel], kb[j], v0);
+            const double v = (v0 + v1) + (v2 + v3);
             ss = fma(v, v, ss);
         }
     }
@@ -1114,11 +1143,11 @@ __global__ __launch_bounds__(kEvalT, 2) void k_refine_pairs(const float *__restr
             if (n <= kPanel) continue;
             const int base = int(uniform(uint32_t(d.y)));
             const int64_t woff = int64_t(uniform(uint32_t(d.w)));
-            // groups: at most 8, at most cnt, and their kernel values fit LDS
-            const int gmax = min(min(8, int(cnt)), kCoopMaxN / n);
+            // groups: a power of two covering the chunk's queries in one pass
+            // where their kernel values fit LDS (at most 8 groups)
+            const int gfit = min(8, kCoopMaxN / n);
             int ng = 1;
-            while (ng < gmax) ng <<= 1;
-            if (ng > gmax && ng > 1) ng >>= 1;
+            while (ng < int(cnt) && 2 * ng <= gfit) ng <<= 1;
             const int Lg = 64 / ng;
             const int gi = lane / Lg;
             for (uint32_t a0 = 0; a0 < cnt; a0 += uint32_t(ng)) {
@@ -1753,12 +1782,16 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         hipLaunchKernelGGL(k_refine_count, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
                            c->d_stat + ST_REFINE, m, c->d_rcnt, c->d_rrank);
         const int4 *rl = knn ? nullptr : c->d_cell_list;
+        // the per-cell arrays of the FP32 chunk table are free again: they
+        // hold the heavy-cell chunk counts and their offsets
+        uint32_t *rheavy = c->d_cell_chunks, *hoff = c->d_chunk_off;
         hipLaunchKernelGGL(k_refine_chunks, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rcnt, rl,
-                           c->d_rchunks);
+                           c->d_rchunks, rheavy);
         exclusive_scan_u32(c->d_rcnt, c->d_roff, nc, c->d_part, s, dnc);
         exclusive_scan_u32(c->d_rchunks, c->d_rchunk_off, nc, c->d_part, s, dnc, cnt + CNT_RCHUNKS);
-        hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rchunks,
-                           c->d_rchunk_off, rl, c->d_rchunk);
+        exclusive_scan_u32(rheavy, hoff, nc, c->d_part, s, dnc, cnt + CNT_RHEAVY);
+        hipLaunchKernelGGL(k_refine_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rchunks,
+                           c->d_rchunk_off, rheavy, hoff, cnt + CNT_RHEAVY, rl, c->d_rchunk);
         hipLaunchKernelGGL(k_refine_scatter, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
                            c->d_stat + ST_REFINE, m, c->d_rrank, c->d_roff, c->d_rorder);
         const Grouping R{c->d_rchunk, cnt + CNT_RCHUNKS, c->d_rcnt, c->d_roff, c->d_rorder};
