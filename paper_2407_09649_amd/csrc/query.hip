@@ -455,7 +455,7 @@ __device__ __forceinline__ void small_rows(const float4 *__restrict__ P, const d
 // the last group at or past n are loaded but masked (point_eval with
 // live == false, their squared products dropped); the point and factor
 // arrays carry a tail pad so that these loads stay inside the allocation.
-constexpr int f32_group(int i) { return i < 16 ? 4 : 2; }   // rows per batch
+constexpr int f32_group(int i) { return i < 8 ? 4 : 2; }   // rows per batch
 
 template <int KERN, int I, int WO>
 __device__ __forceinline__ void group_row_f32(const float4 pp, const float *w, int n, int pbase,
