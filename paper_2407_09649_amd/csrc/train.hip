@@ -191,8 +191,9 @@ __device__ __forceinline__ int tri_row(int p) {
 // that every access compiles to LDS or global instructions (a pointer that
 // may be either would compile to flat accesses)
 template <int T>
-__device__ __forceinline__ void train_block_body(double *__restrict__ A, double *__restrict__ colm,
-                                                 double *__restrict__ wrow, int c, int base, int n,
+__device__ __forceinline__ void train_block_body(double *__restrict__ A, double *__restrict__ craw,
+                                                 double *__restrict__ wraw, double *__restrict__ piv,
+                                                 int c, int base, int n,
                                                  float4 *__restrict__ pts, const int64_t *__restrict__ woff,
                                                  double *__restrict__ W64all, float *__restrict__ W32all,
                                                  double *__restrict__ alpha64, uint8_t *__restrict__ pd, int kernel,
@@ -213,9 +214,21 @@ __device__ __forceinline__ void train_block_body(double *__restrict__ A, double 
     }
     const double thr = 1e-10 * (1.0 + s2);
     const int end = n * (n + 1) / 2;
+    // Step k needs column k below the pivot (craw), row k left of it (wraw)
+    // and the pivot, unscaled, double-buffered: the wavefront that updates
+    // row i in step k also stages its entry (i, k + 1) for step k + 1, and
+    // the one that updates row k + 1 stages that row and the next pivot, so
+    // one barrier per step suffices.  With inv = 1 / sqrt(pivot) every
+    // update scales by lii = craw_i inv^2.
+    __syncthreads();  // A assembled
+    for (int i = 1 + tid; i < n; i += T) craw[i] = A[tri(i, 0)];
+    if (tid == 0) piv[0] = A[0];
+    __syncthreads();
     for (int k = 0; k < n; ++k) {
-        __syncthreads();
-        const double d = A[tri(k, k)];
+        const int b = k & 1;
+        const double *cr = craw + b * kMaxClusterN, *wr = wraw + b * kMaxClusterN;
+        double *crn = craw + (b ^ 1) * kMaxClusterN, *wrn = wraw + (b ^ 1) * kMaxClusterN;
+        const double d = piv[b];
         if (!(d > thr)) {
             for (int i = tid; i < n; i += T) {
                 alpha64[base + i] = 0.0;
@@ -228,24 +241,31 @@ __device__ __forceinline__ void train_block_body(double *__restrict__ A, double 
             return;
         }
         const double inv = 1.0 / sqrt(d);
-        for (int i = k + 1 + tid; i < n; i += T) colm[i] = A[tri(i, k)] * inv;
-        for (int j = tid; j < k; j += T) wrow[j] = A[tri(k, j)] * inv;
-        __syncthreads();
-        for (int j = tid; j < k; j += T) A[tri(k, j)] = wrow[j];
+        const double inv2 = inv * inv;
+        // row k of W (nobody reads row k during this step)
+        for (int j = tid; j < k; j += T) A[tri(k, j)] = wr[j] * inv;
         if (tid == 0) A[tri(k, k)] = inv;
         // rows below k: a packed row (contiguous) per wavefront, its columns
         // over the lanes
         for (int i = k + 1 + wv; i < n; i += kW) {
             double *Ai = A + tri(i, 0);
-            const double li = colm[i];
+            const double lii = cr[i] * inv2;
             for (int j = lane; j <= i; j += 64) {
-                if (j < k) Ai[j] -= li * wrow[j];
-                else if (j == k) Ai[j] = -li * inv;
-                else Ai[j] -= li * colm[j];
+                double a;
+                if (j < k) a = Ai[j] - lii * wr[j];
+                else if (j == k) a = -lii;
+                else a = Ai[j] - lii * cr[j];
+                Ai[j] = a;
+                if (i == k + 1) {
+                    if (j <= k) wrn[j] = a;
+                    else piv[b ^ 1] = a;
+                } else if (j == k + 1) {
+                    crn[i] = a;
+                }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
     // y = W 1 (row sums), alpha = W^T y
     for (int i = tid; i < n; i += T) {
         const double *Wi = A + tri(i, 0);
@@ -253,12 +273,12 @@ __device__ __forceinline__ void train_block_body(double *__restrict__ A, double 
         int j = 0;
         for (; j + 1 <= i; j += 2) { s0 += Wi[j]; s1 += Wi[j + 1]; }
         if (j <= i) s0 += Wi[j];
-        colm[i] = s0 + s1;
+        craw[i] = s0 + s1;
     }
     __syncthreads();
     for (int j = tid; j < n; j += T) {
         double a = 0.0;
-        for (int i = j; i < n; ++i) a += A[tri(i, j)] * colm[i];
+        for (int i = j; i < n; ++i) a += A[tri(i, j)] * craw[i];
         alpha64[base + j] = a;
         pts[base + j].w = float(a);
     }
@@ -300,8 +320,9 @@ __global__ __launch_bounds__(T) void k_train_block(
     double *__restrict__ W64all, float *__restrict__ W32all, double *__restrict__ alpha64,
     uint8_t *__restrict__ pd, int kernel, double l, double s2, unsigned long long *__restrict__ stat) {
     __shared__ double sA[kBlockLdsElems];
-    __shared__ double colm[kMaxClusterN];
-    __shared__ double wrow[kMaxClusterN];
+    __shared__ double craw[2 * kMaxClusterN];
+    __shared__ double wraw[2 * kMaxClusterN];
+    __shared__ double piv[2];
     __shared__ uint32_t item;
     const uint32_t cnt = *dcnt;
     while (true) {
@@ -314,11 +335,11 @@ __global__ __launch_bounds__(T) void k_train_block(
         const int base = coff[c];
         const int n = coff[c + 1] - base;
         if (n <= kBlockLdsN)
-            train_block_body<T>(sA, colm, wrow, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel, l, s2,
-                                stat);
+            train_block_body<T>(sA, craw, wraw, piv, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel,
+                                l, s2, stat);
         else
-            train_block_body<T>(Aall + aoff[c], colm, wrow, c, base, n, pts, woff, W64all, W32all, alpha64, pd,
-                                kernel, l, s2, stat);
+            train_block_body<T>(Aall + aoff[c], craw, wraw, piv, c, base, n, pts, woff, W64all, W32all, alpha64,
+                                pd, kernel, l, s2, stat);
     }
 }
 
