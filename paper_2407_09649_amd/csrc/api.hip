@@ -30,6 +30,11 @@ void release(gpdf_ctx *c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
+    c->side = nullptr;
+    c->fork_ev = c->join_ev = nullptr;
     if (c->d_gin) (void)hipFree(c->d_gin);
     if (c->d_gorigin) (void)hipFree(c->d_gorigin);
     c->gexec = nullptr;
@@ -174,6 +179,12 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
     for (int i = 0; ok && p->timing && i < 16; ++i) {
         e = hipEventCreate(&c->ev[i]);
         ok = e == hipSuccess;
+    }
+    if (ok) {
+        // default priority, like the caller's stream
+        ok = (e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) == hipSuccess &&
+             (e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) == hipSuccess &&
+             (e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming)) == hipSuccess;
     }
     if (!ok) {
         release(c);

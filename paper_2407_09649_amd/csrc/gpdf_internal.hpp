@@ -365,6 +365,8 @@ struct gpdf_ctx {
     bool offs_ready = false;       // band offsets of the test voxels uploaded
     // per-frame graph (fuse_frame with every count on the device)
     hipStream_t gstream = nullptr; // capture stream
+    hipStream_t side = nullptr;    // second stream: the large-cluster trainer beside the others
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     float *d_gin = nullptr;        // input points of the graph [max_points][3]

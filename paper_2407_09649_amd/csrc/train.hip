@@ -703,19 +703,18 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
     hipLaunchKernelGGL(k_cluster_plan, dim3(blocks_for(C)), dim3(kT), 0, s, c->d_coff, C, cnt + CNT_CL, c->d_wsz,
                        c->d_asz, c->d_wo32, c->d_ao32, c->cap_w, c->cap_a, int(c->p.max_cluster_points),
                        c->d_woff, c->d_aoff, c->d_blist, C, cnt, c->d_pd, c->d_stat);
-    // 5. FP64 training, one persistent launch per size bucket
+    // 5. FP64 training, one persistent launch per size bucket.  The
+    //    large-cluster trainer (few workgroups, each for long) runs on a
+    //    second stream beside the other two; the buckets are disjoint.
     const double l = c->p.length_scale, s2 = c->p.noise_sigma * c->p.noise_sigma;
-    hipLaunchKernelGGL(k_train_tiny, dim3(blocks_for(C, 64)), dim3(64), 0, s, c->d_blist, cnt + CNT_TINY,
-                       c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l,
-                       s2, c->d_stat);
-    hipLaunchKernelGGL(k_train_wave, dim3(unsigned(std::min<int64_t>(C, 2048))), dim3(64), 0, s, c->d_blist + C,
-                       cnt + CNT_WAVE, c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
-                       c->p.kernel, l, s2, c->d_stat);
-    fill_u32(c->d_work + 2 * kWorkSlot, 0u, 1, s);
+    hipStream_t sb = c->side;
+    if ((e = hipEventRecord(c->fork_ev, s)) != hipSuccess || (e = hipStreamWaitEvent(sb, c->fork_ev, 0)) != hipSuccess)
+        return hip_fail(c, e, "train: fork");
+    fill_u32(c->d_work + 2 * kWorkSlot, 0u, 1, sb);
     {
         const unsigned gb = unsigned(std::min<int64_t>(C, 256));
 #define GPDF_TRAIN_BLOCK(T)                                                                                    \
-    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, s, c->d_blist + 2 * C, cnt + CNT_BIG, c->d_work + 2 * kWorkSlot, \
+    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, sb, c->d_blist + 2 * C, cnt + CNT_BIG, c->d_work + 2 * kWorkSlot, \
                        c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64,     \
                        c->d_pd, c->p.kernel, l, s2, c->d_stat)
         if (c->tune.train_threads == 512) GPDF_TRAIN_BLOCK(512);
@@ -723,6 +722,14 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
         else GPDF_TRAIN_BLOCK(1024);
 #undef GPDF_TRAIN_BLOCK
     }
+    if ((e = hipEventRecord(c->join_ev, sb)) != hipSuccess) return hip_fail(c, e, "train: join");
+    hipLaunchKernelGGL(k_train_tiny, dim3(blocks_for(C, 64)), dim3(64), 0, s, c->d_blist, cnt + CNT_TINY,
+                       c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l,
+                       s2, c->d_stat);
+    hipLaunchKernelGGL(k_train_wave, dim3(unsigned(std::min<int64_t>(C, 2048))), dim3(64), 0, s, c->d_blist + C,
+                       cnt + CNT_WAVE, c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
+                       c->p.kernel, l, s2, c->d_stat);
+    if ((e = hipStreamWaitEvent(s, c->join_ev, 0)) != hipSuccess) return hip_fail(c, e, "train: join");
     // 6. cluster hash
     HashView hv{c->d_chash, c->chash_mask};
     hipLaunchKernelGGL(k_chash_insert, dim3(blocks_for(C)), dim3(kT), 0, s, c->d_ckey, C, cnt + CNT_CL, hv,
