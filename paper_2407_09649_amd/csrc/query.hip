@@ -164,9 +164,23 @@ __global__ void k_qcells(const float *__restrict__ q, int64_t mb, const uint32_t
     int64_t c[3];
     const bool in = i < m;
     const bool okc = in && query_cell(q + 3 * i, voxel_mode, hv, hc, c);
+    // the queries of one wavefront mostly share a few cells: one lane per
+    // distinct cell probes the table
+    const unsigned long long key = okc ? pack_key(c[0], c[1], c[2]) : 0ull;
     int64_t s = -1;
-    bool ins;
-    if (okc) s = hash_insert(qh, pack_key(c[0], c[1], c[2]), &ins);
+    for (uint64_t todo = __ballot(okc); todo;) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const unsigned long long k0 = __shfl(key, leader, 64);
+        const uint64_t grp = __ballot(okc && key == k0) & todo;
+        int64_t s0 = -1;
+        if ((threadIdx.x & 63) == leader) {
+            bool ins;
+            s0 = hash_insert(qh, k0, &ins);
+        }
+        s0 = __shfl(s0, leader, 64);
+        if (okc && key == k0) s = s0;
+        todo &= ~grp;
+    }
     wave_count(&stat[ST_NONFINITE_Q], in && !okc);
     wave_count(&stat[ST_HASH_FULL], okc && s < 0);
     // queries of one wavefront mostly share a cell: one atomic per cell
@@ -1013,40 +1027,60 @@ struct PairSlot {
     int bidx, n;
 };
 
-// Clusters above one panel are evaluated in FP64 by groups of L lanes (L a
-// power of two, 8 to 64), one query per group, so that one pass serves up to
-// 64 / L queries of the chunk.  Within a group, lanes take the points
-// j = g + L m for the kernel values and the sums of Eq. (1) and (5), the
-// kernel values go to the group's slice of LDS, and then lanes take the rows
-// i = g + L m of the factor: rows of a panel are consecutive in a column, so
-// the lanes of a group read consecutive elements of the FP64 factor, and a
-// row stops at its diagonal.  The partial sums are added within the group;
-// the nearest training point is the minimum of (distance, index), the same
-// decision as the scan in index order.
+// Clusters above one panel are evaluated in FP64 for a batch of NB queries
+// of the chunk at a time.  First, for each query of the batch, the lanes take
+// the points j = lane + 64 m for the kernel values and the sums of Eq. (1)
+// and (5); the kernel values go to LDS as kb[j][NB].  Then the lanes take the
+// rows of the factor, 64 consecutive rows per pass (two 32-row panels, whose
+// rows are consecutive in a column), so that each element of the FP64 factor
+// read from memory is applied to every query of the batch.  A panel is stored
+// up to its last column with zeros above the diagonal and below row n, so a
+// lane runs its panel's full width.  The nearest training point is the
+// minimum of (distance, index), the same decision as the scan in index order.
 constexpr int kCoopMaxN = 1024;   // the largest cluster the library accepts
 
 template <typename V>
-__device__ __forceinline__ V group_sum(V v, int L) {
-    for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o, 64);
+__device__ __forceinline__ V wave_sum(V v) {
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-template <int KERN>
-__device__ PairSlot coop_group(const QueryPoint &Q, bool on, int L, int base, int n, int64_t woff,
-                               const ModelView &Mo, const QueryConsts &C, double *kb) {
-    const int g = int(threadIdx.x & 63) & (L - 1);
-    double o = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-    float best = INFINITY;
-    int bidx = 0x7fffffff;
-    if (on) {
-        for (int j = g; j < n; j += L) {
+// Batch size for `rem` queries left on a cluster of n points: a power of two
+// up to 4 whose kernel values fit the LDS buffer.
+__device__ __forceinline__ int coop_nb(int rem, int n) {
+    const int fit = kCoopMaxN / n;
+    int nb = 1;
+    while (nb < rem && 2 * nb <= fit && nb < 4) nb <<= 1;
+    return nb;
+}
+
+template <int KERN, int NB>
+__device__ void coop_batch(const float *__restrict__ q, const Grouping &G, uint32_t first, int rem, int base,
+                           int n, int64_t woff, const ModelView &Mo, const QueryConsts &C, double *kb,
+                           PairSlot *slot, int sidx, int nsel, uint32_t a0) {
+    const int lane = int(threadIdx.x & 63);
+    // kernel values and the Eq. (1)/(5) sums of each query, the sums to LDS
+    __shared__ double sums[4][4];
+    __shared__ float sbest[4];
+    __shared__ int sbidx[4];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        if (a >= rem) {
+            for (int j = lane; j < n; j += 64) kb[j * NB + a] = 0.0;
+            continue;
+        }
+        const uint32_t qj = G.order[first + uint32_t(a)];
+        const float fx = q[3 * qj], fy = q[3 * qj + 1], fz = q[3 * qj + 2];
+        double o = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        float best = INFINITY;
+        int bidx = 0x7fffffff;
+        for (int j = lane; j < n; j += 64) {
             const float4 p = Mo.pts[base + j];
-            const double a = Mo.alpha64[base + j];
-            const float ex = Q.fx - p.x, ey = Q.fy - p.y, ez = Q.fz - p.z;
+            const double al = Mo.alpha64[base + j];
+            const float ex = fx - p.x, ey = fy - p.y, ez = fz - p.z;
             const float r2f = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
             if (r2f < best) { best = r2f; bidx = base + j; }
-            const double dx = double(Q.fx) - double(p.x), dy = double(Q.fy) - double(p.y),
-                         dz = double(Q.fz) - double(p.z);
+            const double dx = double(fx) - double(p.x), dy = double(fy) - double(p.y), dz = double(fz) - double(p.z);
             const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             double k, e;
             if (kern_kind(KERN) == GPDF_KERNEL_MATERN32) {
@@ -1057,48 +1091,79 @@ __device__ PairSlot coop_group(const QueryPoint &Q, bool on, int L, int base, in
                 k = ::exp(-(r2 * C.ad));
                 e = k;
             }
-            o = fma(a, k, o);
-            const double cg = a * e;
+            o = fma(al, k, o);
+            const double cg = al * e;
             gx = fma(cg, dx, gx);
             gy = fma(cg, dy, gy);
             gz = fma(cg, dz, gz);
-            kb[j] = k;
+            kb[j * NB + a] = k;
+        }
+        o = wave_sum(o); gx = wave_sum(gx); gy = wave_sum(gy); gz = wave_sum(gz);
+        for (int s = 1; s < 64; s <<= 1) {
+            const float b2 = __shfl_xor(best, s, 64);
+            const int i2 = __shfl_xor(bidx, s, 64);
+            if (b2 < best || (b2 == best && i2 < bidx)) { best = b2; bidx = i2; }
+        }
+        if (lane == 0) {
+            sums[a][0] = o; sums[a][1] = gx; sums[a][2] = gy; sums[a][3] = gz;
+            sbest[a] = best; sbidx[a] = bidx;
         }
     }
-    o = group_sum(o, L); gx = group_sum(gx, L); gy = group_sum(gy, L); gz = group_sum(gz, L);
-    for (int s = 1; s < L; s <<= 1) {
-        const float b2 = __shfl_xor(best, s, 64);
-        const int i2 = __shfl_xor(bidx, s, 64);
-        if (b2 < best || (b2 == best && i2 < bidx)) { best = b2; bidx = i2; }
-    }
-    __syncthreads();  // kernel values visible to the group
-    double ss = 0.0;
-    if (on) {
-        for (int i = g; i < n; i += L) {
-            const int r = i / kPanel;
-            const double *Wp = Mo.W64 + woff + w32_panel_offset(n, r) + (i - r * kPanel);
-            // four independent partial sums keep four loads in flight
-            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-            int j = 0;
-            for (; j + 3 <= i; j += 4) {
-                v0 = fma(Wp[int64_t(j) * kPanel], kb[j], v0);
-                v1 = fma(Wp[int64_t(j + 1) * kPanel], kb[j + 1], v1);
-                v2 = fma(Wp[int64_t(j + 2) * kPanel], kb[j + 2], v2);
-                v3 = fma(Wp[int64_t(j + 3) * kPanel], kb[j + 3], v3);
-            }
-            for (; j <= i; ++j) v0 = fma(Wp[int64_t(j) * kPanel], kb[j], v0);
-            const double v = (v0 + v1) + (v2 + v3);
-            ss = fma(v, v, ss);
+    __syncthreads();  // kernel values visible to the wave
+    // ||W k||^2 for every query of the batch
+    constexpr int P = 4 / NB;  // partial sums per query
+    double ss[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) ss[a] = 0.0;
+    for (int r0 = 0; r0 * kPanel < n; r0 += 2) {
+        const int r = r0 + (lane >> 5);
+        if (r * kPanel >= n) continue;
+        const int ncol = min((r + 1) * kPanel, n);
+        const double *Wp = Mo.W64 + woff + w32_panel_offset(n, r) + (lane & 31);
+        double v[NB][P];
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int u = 0; u < P; ++u) v[a][u] = 0.0;
+        int j = 0;
+        for (; j + 4 <= ncol; j += 4) {
+            double w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w[u] = Wp[int64_t(j + u) * kPanel];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int a = 0; a < NB; ++a) v[a][u % P] = fma(w[u], kb[(j + u) * NB + a], v[a][u % P]);
+        }
+        for (; j < ncol; ++j) {
+            const double w = Wp[int64_t(j) * kPanel];
+#pragma unroll
+            for (int a = 0; a < NB; ++a) v[a][0] = fma(w, kb[j * NB + a], v[a][0]);
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            double t = v[a][0];
+#pragma unroll
+            for (int u = 1; u < P; ++u) t += v[a][u];
+            ss[a] = fma(t, t, ss[a]);
         }
     }
-    ss = group_sum(ss, L);
-    __syncthreads();  // the slices are rewritten by the next pass
-    const PairRaw<double> rr{o, gx, gy, gz, ss, 0.f};
-    return PairSlot{pair_out<double, KERN>(rr, n, C), best, bidx, n};
+    double mss = 0.0;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        const double t = wave_sum(ss[a]);
+        if (lane == a) mss = t;
+    }
+    if (lane < rem && lane < NB) {
+        const PairRaw<double> rr{sums[lane][0], sums[lane][1], sums[lane][2], sums[lane][3], mss, 0.f};
+        slot[(a0 + uint32_t(lane)) * nsel + sidx] =
+            PairSlot{pair_out<double, KERN>(rr, n, C), sbest[lane], sbidx[lane], n};
+    }
+    __syncthreads();  // kb and the sums are rewritten by the next batch
 }
 
 template <int KERN, int MODE>
-__global__ __launch_bounds__(kEvalT, 2) void k_refine_pairs(const float *__restrict__ q, Grouping G,
+__global__ __launch_bounds__(kEvalT, 3) void k_refine_pairs(const float *__restrict__ q, Grouping G,
                                                         const int4 *__restrict__ lists, ModelView Mo, QueryConsts C,
                                                         Outputs O, uint32_t *work) {
     __shared__ PairSlot slot[64];
@@ -1136,27 +1201,20 @@ __global__ __launch_bounds__(kEvalT, 2) void k_refine_pairs(const float *__restr
                 slot[lane] = PairSlot{pair_out<double, KERN>(r, n, C), A.best, A.bidx, n};
             }
         }
-        // clusters above one panel: groups of lanes, one query per group
+        // clusters above one panel: the chunk's queries in batches
+        const uint32_t first = ro(G.cell_off)[cell] + start;
         for (int s = 0; s < nsel; ++s) {
             const int4 d = L[1 + s];
             const int n = int(uniform(uint32_t(d.z)));
             if (n <= kPanel) continue;
             const int base = int(uniform(uint32_t(d.y)));
             const int64_t woff = int64_t(uniform(uint32_t(d.w)));
-            // groups: a power of two covering the chunk's queries in one pass
-            // where their kernel values fit LDS (at most 8 groups)
-            const int gfit = min(8, kCoopMaxN / n);
-            int ng = 1;
-            while (ng < int(cnt) && 2 * ng <= gfit) ng <<= 1;
-            const int Lg = 64 / ng;
-            const int gi = lane / Lg;
-            for (uint32_t a0 = 0; a0 < cnt; a0 += uint32_t(ng)) {
-                const uint32_t a = a0 + uint32_t(gi);
-                const bool on = a < cnt;
-                const uint32_t qj = G.order[ro(G.cell_off)[cell] + start + (on ? a : 0u)];
-                const QueryPoint Qa{q[3 * qj], q[3 * qj + 1], q[3 * qj + 2]};
-                const PairSlot ps = coop_group<KERN>(Qa, on, Lg, base, n, woff, Mo, C, kbuf + gi * n);
-                if (on && (lane & (Lg - 1)) == 0) slot[a * nsel + s] = ps;
+            for (uint32_t a0 = 0; a0 < cnt;) {
+                const int rem = int(cnt - a0), nb = coop_nb(rem, n);
+                if (nb == 4) coop_batch<KERN, 4>(q, G, first + a0, rem, base, n, woff, Mo, C, kbuf, slot, s, nsel, a0);
+                else if (nb == 2) coop_batch<KERN, 2>(q, G, first + a0, rem, base, n, woff, Mo, C, kbuf, slot, s, nsel, a0);
+                else coop_batch<KERN, 1>(q, G, first + a0, rem, base, n, woff, Mo, C, kbuf, slot, s, nsel, a0);
+                a0 += uint32_t(nb);
             }
         }
         __syncthreads();
