@@ -115,6 +115,64 @@ __global__ void k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restric
     }
 }
 
+// one block for inputs up to a few tiles: the whole scan in one launch (most
+// scans here are over per-cell, per-cluster or per-tile counts).  A tile is
+// read and written with coalesced accesses through LDS; in LDS each thread
+// owns kScan1Items consecutive elements (one pad word per kScan1Items keeps
+// the strided accesses off a single bank).  Tiles run in order with a carry;
+// a tile is read whole before it is written, so in place is fine.
+constexpr int kScan1Threads = 1024;
+constexpr int kScan1Items = 16;
+constexpr int64_t kScan1Tile = int64_t(kScan1Threads) * kScan1Items;
+constexpr int64_t kScan1Max = 4 * kScan1Tile;
+
+__device__ __forceinline__ int scan1_pad(int j) { return j + j / kScan1Items; }
+
+__global__ __launch_bounds__(kScan1Threads) void k_scan_single(const uint32_t *__restrict__ in,
+                                                               uint32_t *__restrict__ out, int64_t nb_,
+                                                               const uint32_t *__restrict__ dn,
+                                                               uint32_t *__restrict__ total_out) {
+    __shared__ uint32_t lds[kScan1Threads / 64];
+    __shared__ uint32_t buf[kScan1Tile + kScan1Tile / kScan1Items];
+    const int64_t n = scan_count(nb_, dn);
+    const int t = int(threadIdx.x);
+    uint32_t carry = 0;
+    for (int64_t t0 = 0; t0 < n; t0 += kScan1Tile) {
+#pragma unroll
+        for (int i = 0; i < kScan1Items; ++i) {
+            const int j = i * kScan1Threads + t;
+            buf[scan1_pad(j)] = t0 + j < n ? in[t0 + j] : 0u;
+        }
+        __syncthreads();
+        uint32_t v[kScan1Items];
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < kScan1Items; ++i) {
+            v[i] = buf[scan1_pad(t * kScan1Items + i)];
+            s += v[i];
+        }
+        uint32_t tot;
+        uint32_t run = block_exclusive_scan(s, lds, tot) + carry;  // ends with a barrier
+#pragma unroll
+        for (int i = 0; i < kScan1Items; ++i) {
+            buf[scan1_pad(t * kScan1Items + i)] = run;
+            run += v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kScan1Items; ++i) {
+            const int j = i * kScan1Threads + t;
+            if (t0 + j < n) out[t0 + j] = buf[scan1_pad(j)];
+        }
+        __syncthreads();  // buf is refilled by the next tile
+        carry += tot;
+    }
+    if (t == 0) {
+        out[n] = carry;
+        if (total_out) *total_out = carry;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // radix sort, 8-bit digits
 // ---------------------------------------------------------------------------
@@ -199,6 +257,10 @@ inline unsigned grid_for(int64_t n, int threads) {
 
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
                         hipStream_t s, const uint32_t *dn, uint32_t *total_out) {
+    if (n <= kScan1Max) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScan1Threads), 0, s, in, out, n, dn, total_out);
+        return;
+    }
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_scan_reduce, dim3(unsigned(nb)), dim3(kScanThreads), 0, s, in, n, dn, partials);
