@@ -407,8 +407,10 @@ extern "C" gpdf_status gpdf_get_stats(gpdf_ctx *c, gpdf_stats *out) {
     }
     // the status bits and training counters are read once; per-call counters
     // are reset by the calls themselves
-    fill_u64(c->d_stat + ST_HASH_FULL, 0ull, 1, c->stream);
-    fill_u64(c->d_stat + ST_GLOBAL_FULL, 0ull, 1, c->stream);
+    FillList F;
+    F.u64(c->d_stat + ST_HASH_FULL, 0ull, 1);
+    F.u64(c->d_stat + ST_GLOBAL_FULL, 0ull, 1);
+    fill_multi(F, c->stream);
     return GPDF_OK;
 }
 

@@ -280,23 +280,29 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin, int64_
     if (!M.trained) return fail(c, GPDF_E_NOT_TRAINED, "fuse before training");
     hipError_t e;
     uint32_t *cnt = c->d_cnt;
-    fill_u64(c->d_stat + ST_TESTPTS, 0ull, 1, s);
-    fill_u64(c->d_stat + ST_FUSED, 0ull, 1, s);
-    fill_u64(c->d_stat + ST_FUSE_SKIPPED, 0ull, 1, s);
-    fill_u32(cnt + CNT_TEST, 0u, 1, s);
+    FillList F;
+    F.u64(c->d_stat + ST_TESTPTS, 0ull, 1);
+    F.u64(c->d_stat + ST_FUSED, 0ull, 1);
+    F.u64(c->d_stat + ST_FUSE_SKIPPED, 0ull, 1);
+    F.u32(cnt + CNT_TEST, 0u, 1);
     const int64_t npts = eager ? M.npoints : npts_bound;
     if (eager && npts == 0) {
+        fill_multi(F, s);
         c->last_test = 0;
         c->frame++;
         return GPDF_OK;
     }
     gpdf_status st = ensure_offsets(c);
-    if (st != GPDF_OK) return st;
+    if (st != GPDF_OK) {
+        fill_multi(F, s);
+        return st;
+    }
     const double hf = c->p.fuse_voxel_size;
     const int noffs = int(c->h_offs.size());
     const int64_t tcap = int64_t(c->tset_mask) + 1;
     stage_begin(c, GPDF_MS_TESTPTS);
-    fill_u64(c->d_tset, (unsigned long long)kNoKey, tcap, s);
+    F.u64(c->d_tset, (unsigned long long)kNoKey, tcap);
+    fill_multi(F, s);
     HashView set{c->d_tset, c->tset_mask};
     const int64_t work = npts * int64_t(noffs);
     hipLaunchKernelGGL(k_test_insert, dim3(blocks_for(work)), dim3(kT), 0, s, c->d_pts, npts,

@@ -499,6 +499,23 @@ void count_occupied(const unsigned long long *keys, int64_t cap, uint32_t *tile_
                     uint32_t *tile_off, uint32_t *partials, hipStream_t s);
 void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+// several fills in one launch (counters and tables cleared together at the
+// start of a call, where each separate launch would cost a host round trip)
+struct FillOp {
+    void *p;
+    unsigned long long v;
+    int64_t n;
+    int bytes;  // 4 or 8
+};
+struct FillList {
+    static constexpr int kMax = 12;
+    FillOp op[kMax];
+    int count = 0;
+    void u64(unsigned long long *p, unsigned long long v, int64_t n) { op[count++] = FillOp{p, v, n, 8}; }
+    void u32(uint32_t *p, uint32_t v, int64_t n) { op[count++] = FillOp{p, v, n, 4}; }
+};
+void fill_multi(const FillList &L, hipStream_t s);
 void fold_stats(unsigned long long *spread, unsigned long long *stat, hipStream_t s);
 void grid_clear(gpdf_ctx *c, hipStream_t s);
 

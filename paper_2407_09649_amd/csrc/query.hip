@@ -1736,17 +1736,22 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     c->last_queries = m;
     uint32_t *cnt = c->d_cnt;
     // per-call counters
-    fill_u64(c->d_stat + ST_NONFINITE_Q, 0ull, 1, s);
-    fill_u64(c->d_stat + ST_VALID_Q, 0ull, 1, s);
-    fill_u64(c->d_stat + ST_REFINE, 0ull, 1, s);
-    fill_u64(c->d_stat + ST_CELLS, 0ull, 1, s);
-    fill_u64(c->d_stat + ST_PAIRS, 0ull, 3, s);
-    fill_u64(c->d_stat + ST_REF_D, 0ull, 3, s);
-    fill_u32(cnt + CNT_CELLS, 0u, 3, s);  // cells, chunks, re-evaluation chunks
-    if (m == 0) return GPDF_OK;
+    FillList F;
+    F.u64(c->d_stat + ST_NONFINITE_Q, 0ull, 1);
+    F.u64(c->d_stat + ST_VALID_Q, 0ull, 1);
+    F.u64(c->d_stat + ST_REFINE, 0ull, 1);
+    F.u64(c->d_stat + ST_CELLS, 0ull, 1);
+    F.u64(c->d_stat + ST_PAIRS, 0ull, 3);
+    F.u64(c->d_stat + ST_REF_D, 0ull, 3);
+    F.u32(cnt + CNT_CELLS, 0u, 3);  // cells, chunks, re-evaluation chunks
+    if (m == 0) {
+        fill_multi(F, s);
+        return GPDF_OK;
+    }
     hipError_t e;
     if (M.host_counts && M.nclusters == 0) {
         // nothing to select: every query is invalid
+        fill_multi(F, s);
         hipLaunchKernelGGL(k_all_invalid, dim3(blocks_for(m)), dim3(kQT), 0, s, m, dist, grad, var,
                            valid, aux);
         return (e = hipGetLastError()) == hipSuccess ? GPDF_OK : hip_fail(c, e, "query launch");
@@ -1754,8 +1759,10 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     const QueryConsts C = make_consts(c->p, origin, d_origin);
     const bool vox = c->p.voxel_size > 0.0;
     const bool knn = C.knn_q > 0;
-    if (!eager && (knn || c->p.precision == GPDF_PREC_BF16 || correct))
+    if (!eager && (knn || c->p.precision == GPDF_PREC_BF16 || correct)) {
+        fill_multi(F, s);
         return fail(c, GPDF_E_INVALID_ARG, "query with device counts: NEIGHBOR27, FP32/FP64, no correction");
+    }
     const double edge = vox ? 8.0 * c->p.voxel_size : c->p.cluster_size;
     const int kern = c->p.kernel;
     const ModelView Mo{c->d_pts, c->d_alpha64, c->d_coff, c->d_woff, c->d_W32, c->d_W64,
@@ -1765,8 +1772,9 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     // at most m distinct cells: a table of 2m..4m slots, within the allocation
     const uint32_t qmask = std::min(c->qhash_mask, pow2_mask(2 * m));
     const int64_t qcap = int64_t(qmask) + 1;
-    fill_u64(c->d_qhash, (unsigned long long)kNoKey, qcap, s);
-    fill_u32(c->d_qhash_cnt, 0u, qcap, s);
+    F.u64(c->d_qhash, (unsigned long long)kNoKey, qcap);
+    F.u32(c->d_qhash_cnt, 0u, qcap);
+    fill_multi(F, s);
     HashView qh{c->d_qhash, qmask};
     hipLaunchKernelGGL(k_qcells, dim3(blocks_for(m)), dim3(kQT), 0, s, d_q, m, dm, vox ? 1 : 0,
                        c->p.voxel_size, c->p.cluster_size, qh, c->d_qhash_cnt, c->d_qslot, c->d_qrank,

@@ -247,6 +247,14 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
     for (; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
 }
 
+__global__ void k_fill_multi(FillList L) {
+    const FillOp o = L.op[blockIdx.y];
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < o.n; i += int64_t(gridDim.x) * blockDim.x) {
+        if (o.bytes == 8) static_cast<unsigned long long *>(o.p)[i] = o.v;
+        else static_cast<uint32_t *>(o.p)[i] = uint32_t(o.v);
+    }
+}
+
 inline unsigned grid_for(int64_t n, int threads) {
     int64_t g = (n + threads - 1) / threads;
     if (g > 65536) g = 65536;
@@ -314,6 +322,14 @@ void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
 }
+void fill_multi(const FillList &L, hipStream_t s) {
+    if (L.count <= 0) return;
+    int64_t nmax = 1;
+    for (int k = 0; k < L.count; ++k) nmax = std::max(nmax, L.op[k].n);
+    hipLaunchKernelGGL(k_fill_multi, dim3(std::min<unsigned>(grid_for(nmax, 256), 4096), unsigned(L.count)),
+                       dim3(256), 0, s, L);
+}
+
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);

@@ -656,9 +656,11 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
     M = Model();
     M.trained = true;
     uint32_t *cnt = c->d_cnt;
-    fill_u32(cnt + CNT_VALID, 0u, CNT_MAXN - CNT_VALID + 1, s);
-    fill_u64(c->d_stat + ST_CAPACITY, 0ull, 1, s);
-    fill_u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1, s);
+    FillList F;
+    F.u32(cnt + CNT_VALID, 0u, CNT_MAXN - CNT_VALID + 1);
+    F.u64(c->d_stat + ST_CAPACITY, 0ull, 1);
+    F.u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1);
+    fill_multi(F, s);
     if (n == 0) {
         M.host_counts = true;
         return GPDF_OK;
