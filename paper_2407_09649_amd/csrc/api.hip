@@ -55,6 +55,7 @@ void release(gpdf_ctx *c) {
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
+    if (c->h_read) (void)hipHostFree(c->h_read);
     for (hipEvent_t &e : c->ev)
         if (e) (void)hipEventDestroy(e);
 }
@@ -173,8 +174,8 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
               dalloc(c->d_gstamp, int64_t(c->gmask) + 1, e) && dalloc(c->d_offs, c->offs_cap, e) &&
               dalloc(c->d_stat, ST_COUNT, e) && dalloc(c->d_spread, int64_t(kSpread) * kSpreadStride, e);
     if (ok) {
-        e = hipHostMalloc((void **)&c->h_stat, sizeof(unsigned long long) * ST_COUNT, 0);
-        ok = e == hipSuccess;
+        ok = (e = hipHostMalloc((void **)&c->h_stat, sizeof(unsigned long long) * ST_COUNT, 0)) == hipSuccess &&
+             (e = hipHostMalloc((void **)&c->h_read, sizeof(unsigned long long) * ReadList::kMax, 0)) == hipSuccess;
     }
     for (int i = 0; ok && p->timing && i < 16; ++i) {
         e = hipEventCreate(&c->ev[i]);

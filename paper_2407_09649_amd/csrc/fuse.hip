@@ -315,10 +315,10 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin, int64_
     stage_end(c, GPDF_MS_TESTPTS);
     int64_t nt = c->p.max_queries;
     if (eager) {
-        unsigned long long t = 0;
-        if ((e = hipMemcpyAsync(&t, c->d_stat + ST_TESTPTS, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-            return hip_fail(c, e, "fuse: read test count");
+        ReadList R;
+        R.u64(c->d_stat + ST_TESTPTS);
+        if ((e = read_back(c, R, s)) != hipSuccess) return hip_fail(c, e, "fuse: read test count");
+        const unsigned long long t = c->h_read[0];
         if (int64_t(t) > c->p.max_queries) return fail(c, GPDF_E_CAPACITY, "fuse: test points exceed max_queries");
         nt = int64_t(t);
         c->last_test = nt;

@@ -465,6 +465,7 @@ struct gpdf_ctx {
     unsigned long long *d_stat = nullptr;          // [ST_COUNT]
     unsigned long long *d_spread = nullptr;        // [kSpread][kSpreadStride], zero between calls
     unsigned long long *h_stat = nullptr;          // pinned mirror
+    unsigned long long *h_read = nullptr;          // pinned words of read_back()
     int64_t last_queries = 0;
 };
 
@@ -516,7 +517,22 @@ struct FillList {
     void u32(uint32_t *p, uint32_t v, int64_t n) { op[count++] = FillOp{p, v, n, 4}; }
 };
 void fill_multi(const FillList &L, hipStream_t s);
+
+// small read-backs: one kernel stores the listed device words into the
+// context's pinned host words (as u64), then the stream is synchronised
+struct ReadList {
+    static constexpr int kMax = 32;
+    const void *src[kMax];
+    int bytes[kMax];
+    int count = 0;
+    void u32(const uint32_t *p, int n = 1) {
+        for (int k = 0; k < n; ++k) { src[count] = p + k; bytes[count++] = 4; }
+    }
+    void u64(const unsigned long long *p) { src[count] = p; bytes[count++] = 8; }
+};
 void fold_stats(unsigned long long *spread, unsigned long long *stat, hipStream_t s);
+// the values land in c->h_read[0 .. L.count)
+hipError_t read_back(gpdf_ctx *c, const ReadList &L, hipStream_t s);
 void grid_clear(gpdf_ctx *c, hipStream_t s);
 
 // stages (train.hip, query.hip, fuse.hip, mlp.hip)

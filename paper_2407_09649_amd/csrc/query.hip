@@ -1787,10 +1787,10 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     // the number of cells: read back (eager), else bounded by the queries
     int64_t nc = std::min<int64_t>(m, qcap);
     if (eager) {
-        uint32_t ncells = 0;
-        if ((e = hipMemcpyAsync(&ncells, cnt + CNT_CELLS, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-            return hip_fail(c, e, "query: read cell count");
+        ReadList R;
+        R.u32(cnt + CNT_CELLS);
+        if ((e = read_back(c, R, s)) != hipSuccess) return hip_fail(c, e, "query: read cell count");
+        const uint32_t ncells = uint32_t(c->h_read[0]);
         if (ncells == 0) return GPDF_OK;
         nc = int64_t(ncells);
     }

@@ -255,6 +255,14 @@ __global__ void k_fill_multi(FillList L) {
     }
 }
 
+__global__ void k_read_words(ReadList L, unsigned long long *out) {
+    const int i = int(threadIdx.x);
+    if (i < L.count)
+        out[i] = L.bytes[i] == 8 ? *static_cast<const unsigned long long *>(L.src[i])
+                                 : (unsigned long long)(*static_cast<const uint32_t *>(L.src[i]));
+    __threadfence_system();
+}
+
 inline unsigned grid_for(int64_t n, int threads) {
     int64_t g = (n + threads - 1) / threads;
     if (g > 65536) g = 65536;
@@ -322,6 +330,12 @@ void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
 }
+hipError_t read_back(gpdf_ctx *c, const ReadList &L, hipStream_t s) {
+    hipLaunchKernelGGL(k_read_words, dim3(1), dim3(ReadList::kMax), 0, s, L, c->h_read);
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : hipStreamSynchronize(s);
+}
+
 void fill_multi(const FillList &L, hipStream_t s) {
     if (L.count <= 0) return;
     int64_t nmax = 1;

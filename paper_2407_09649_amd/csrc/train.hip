@@ -739,12 +739,14 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "train: launch");
     if (!eager) return GPDF_OK;
     // counts of the model and capacity check: one read-back
+    static_assert(kCnt + 1 <= ReadList::kMax, "read-back list too short");
+    ReadList R;
+    R.u32(cnt, kCnt);
+    R.u64(c->d_stat + ST_CAPACITY);
+    if ((e = read_back(c, R, s)) != hipSuccess) return hip_fail(c, e, "train: read counts");
     uint32_t hc[kCnt];
-    unsigned long long capx = 0;
-    if ((e = hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(&capx, c->d_stat + ST_CAPACITY, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_fail(c, e, "train: read counts");
+    for (int k = 0; k < kCnt; ++k) hc[k] = uint32_t(c->h_read[k]);
+    const unsigned long long capx = c->h_read[kCnt];
     M.host_counts = true;
     M.skipped = n - int64_t(hc[CNT_VALID]);
     M.npoints = hc[CNT_PTS];
