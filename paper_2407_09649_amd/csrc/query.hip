@@ -1112,6 +1112,7 @@ __device__ void coop_batch(const float *__restrict__ q, const Grouping &G, uint3
     __syncthreads();  // kernel values visible to the wave
     // ||W k||^2 for every query of the batch
     constexpr int P = 4 / NB;  // partial sums per query
+    static_assert(NB == 1 || NB == 2 || NB == 4, "batch of 1, 2 or 4 queries");
     double ss[NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) ss[a] = 0.0;
