@@ -179,6 +179,7 @@ __global__ __launch_bounds__(kScan1Threads) void k_scan_single(const uint32_t *_
 constexpr int kRsThreads = 256;
 constexpr int kRsItems = 16;
 constexpr int kRsTile = kRsThreads * kRsItems;
+constexpr int64_t kRsRawBlocks = 64;  // up to this many blocks the scatter scans the counts itself
 
 __global__ void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
                           uint32_t *__restrict__ hist, int64_t nblocks) {
@@ -195,14 +196,29 @@ __global__ void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shif
     hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// hist: the exclusive scan of the digit-major counts, or (raw != 0, for a
+// few blocks) the counts themselves, from which each block forms its own
+// offsets: the digits below d in all blocks plus digit d in the blocks before
 __global__ void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                              uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
-                             int shift, const uint32_t *__restrict__ hist, int64_t nblocks) {
+                             int shift, const uint32_t *__restrict__ hist, int64_t nblocks, int raw) {
     constexpr int W = kRsThreads / 64;
     __shared__ uint32_t base_d[256];
     __shared__ uint32_t wcnt[W][256];
+    __shared__ uint32_t lds_w[W];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    base_d[threadIdx.x] = hist[int64_t(threadIdx.x) * nblocks + blockIdx.x];
+    if (raw) {
+        uint32_t tot = 0, before = 0;
+        for (int64_t b = 0; b < nblocks; ++b) {
+            const uint32_t h = hist[int64_t(threadIdx.x) * nblocks + b];
+            tot += h;
+            before += b < int64_t(blockIdx.x) ? h : 0u;
+        }
+        uint32_t all;
+        base_d[threadIdx.x] = block_exclusive_scan(tot, lds_w, all) + before;
+    } else {
+        base_d[threadIdx.x] = hist[int64_t(threadIdx.x) * nblocks + blockIdx.x];
+    }
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     const int64_t tile = int64_t(blockIdx.x) * kRsTile;
     for (int r = 0; r < kRsItems; ++r) {
@@ -297,9 +313,10 @@ void radix_sort_pairs(uint64_t *&keys, uint64_t *&keys_alt, uint32_t *&vals, uin
         if (((varying_bits >> shift) & 0xFF) == 0) continue;
         hipLaunchKernelGGL(k_rs_hist, dim3(unsigned(nb)), dim3(kRsThreads), 0, s, keys, n, shift,
                            hist, nb);
-        exclusive_scan_u32(hist, hist, 256 * nb, partials, s);
+        const int raw = nb <= kRsRawBlocks ? 1 : 0;
+        if (!raw) exclusive_scan_u32(hist, hist, 256 * nb, partials, s);
         hipLaunchKernelGGL(k_rs_scatter, dim3(unsigned(nb)), dim3(kRsThreads), 0, s, keys, vals,
-                           keys_alt, vals_alt, n, shift, hist, nb);
+                           keys_alt, vals_alt, n, shift, hist, nb, raw);
         std::swap(keys, keys_alt);
         std::swap(vals, vals_alt);
     }
