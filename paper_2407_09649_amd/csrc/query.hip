@@ -164,27 +164,33 @@ __global__ void k_qcells(const float *__restrict__ q, int64_t mb, const uint32_t
     int64_t c[3];
     const bool in = i < m;
     const bool okc = in && query_cell(q + 3 * i, voxel_mode, hv, hc, c);
-    // the queries of one wavefront mostly share a few cells: one lane per
-    // distinct cell probes the table
+    // the queries of one wavefront mostly share a few cells: the lanes form
+    // groups of equal cell key (ballots only), then the first lane of every
+    // group probes the table and adds its group's size to the cell count,
+    // all groups at once, so the wavefront waits for one probe and one
+    // atomic instead of one per cell
+    const int lane = int(threadIdx.x & 63);
     const unsigned long long key = okc ? pack_key(c[0], c[1], c[2]) : 0ull;
-    int64_t s = -1;
+    int leader = lane;
+    uint64_t group = 0;
     for (uint64_t todo = __ballot(okc); todo;) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const unsigned long long k0 = __shfl(key, leader, 64);
+        const int l0 = __ffsll((long long)todo) - 1;
+        const unsigned long long k0 = __shfl(key, l0, 64);
         const uint64_t grp = __ballot(okc && key == k0) & todo;
-        int64_t s0 = -1;
-        if ((threadIdx.x & 63) == leader) {
-            bool ins;
-            s0 = hash_insert(qh, k0, &ins);
-        }
-        s0 = __shfl(s0, leader, 64);
-        if (okc && key == k0) s = s0;
+        if ((grp >> lane) & 1ull) { leader = l0; group = grp; }
         todo &= ~grp;
     }
+    int64_t s0 = -1;
+    uint32_t base = 0;
+    if (okc && leader == lane) {
+        bool ins;
+        s0 = hash_insert(qh, key, &ins);
+        if (s0 >= 0) base = atomicAdd(&cnt[s0], uint32_t(__popcll(group)));
+    }
+    const int64_t s = okc ? __shfl(s0, leader, 64) : int64_t(-1);
+    const uint32_t rank = __shfl(base, leader, 64) + uint32_t(__popcll(group & lanes_below()));
     wave_count(&stat[ST_NONFINITE_Q], in && !okc);
     wave_count(&stat[ST_HASH_FULL], okc && s < 0);
-    // queries of one wavefront mostly share a cell: one atomic per cell
-    const uint32_t rank = wave_rank(cnt, s);
     if (!in) return;
     if (s < 0) {
         qslot[i] = -1;
