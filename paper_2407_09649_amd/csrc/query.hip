@@ -1776,8 +1776,9 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
                        c->d_ckey, c->d_pd, M.nclusters, edge};
     // 1. group by cell
     stage_begin(c, GPDF_MS_GROUP);
-    // at most m distinct cells: a table of 2m..4m slots, within the allocation
-    const uint32_t qmask = std::min(c->qhash_mask, pow2_mask(2 * m));
+    // at most m distinct cells (far fewer in practice): a table of 1.25m to
+    // 2.5m slots, within the allocation; it is cleared and compacted per call
+    const uint32_t qmask = std::min(c->qhash_mask, pow2_mask(m + m / 4 + 1));
     const int64_t qcap = int64_t(qmask) + 1;
     F.u64(c->d_qhash, (unsigned long long)kNoKey, qcap);
     F.u32(c->d_qhash_cnt, 0u, qcap);
