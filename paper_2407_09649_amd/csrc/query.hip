@@ -230,16 +230,43 @@ __global__ void k_cell_lists(int64_t ncb, const uint32_t *__restrict__ dnc, cons
     unpack_key(cell_key[c], cc);
     int4 *L = lists + c * kListStride;
     int nsel = 0;
-    // ascending key order: x offset outermost, z innermost
-    for (int dx = -1; dx <= 1; ++dx)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dz = -1; dz <= 1; ++dz) {
-                int64_t s = hash_find(chash, cmask, pack_key(cc[0] + dx, cc[1] + dy, cc[2] + dz));
-                if (s < 0) continue;
-                const int32_t id = chash_val[s];
-                const int32_t b = coff[id], n = coff[id + 1] - b;
-                if (pd[id] && n > 0) L[1 + nsel++] = make_int4(id, b, n, int32_t(woff[id]));
-            }
+    // ascending key order: x offset outermost, z innermost.  The nine cells
+    // of one x offset are looked up together: their first probes are loaded
+    // at once (a key mostly sits in its first slot or meets an empty one),
+    // only the others probe on, then the clusters' records are loaded at once
+    for (int dx = -1; dx <= 1; ++dx) {
+        uint64_t key[9];
+        unsigned long long k0[9];
+        uint32_t s0[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            key[t] = pack_key(cc[0] + dx, cc[1] + t / 3 - 1, cc[2] + t % 3 - 1);
+            s0[t] = uint32_t(mix64(key[t]) & cmask);
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) k0[t] = chash[s0[t]];
+        int32_t id[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int64_t sl = k0[t] == key[t] ? int64_t(s0[t])
+                               : k0[t] == kNoKey ? int64_t(-1) : hash_find(chash, cmask, key[t]);
+            id[t] = sl < 0 ? -1 : chash_val[sl];
+        }
+        int32_t b[9], e[9];
+        uint8_t ok[9];
+        int64_t wo[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int32_t j = id[t] < 0 ? 0 : id[t];
+            b[t] = coff[j];
+            e[t] = coff[j + 1];
+            ok[t] = pd[j];
+            wo[t] = woff[j];
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+            if (id[t] >= 0 && ok[t] && e[t] > b[t]) L[1 + nsel++] = make_int4(id[t], b[t], e[t] - b[t], int32_t(wo[t]));
+    }
     L[0] = make_int4(nsel, 0, 0, 0);
 }
 
