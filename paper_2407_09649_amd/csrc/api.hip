@@ -411,7 +411,7 @@ extern "C" gpdf_status gpdf_get_stats(gpdf_ctx *c, gpdf_stats *out) {
     FillList F;
     F.u64(c->d_stat + ST_HASH_FULL, 0ull, 1);
     F.u64(c->d_stat + ST_GLOBAL_FULL, 0ull, 1);
-    fill_multi(F, c->stream);
+    if (hipError_t e = fill_multi(F, c->stream); e != hipSuccess) return hip_fail(c, e, "stats: reset");
     return GPDF_OK;
 }
 

@@ -287,14 +287,14 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin, int64_
     F.u32(cnt + CNT_TEST, 0u, 1);
     const int64_t npts = eager ? M.npoints : npts_bound;
     if (eager && npts == 0) {
-        fill_multi(F, s);
+        (void)fill_multi(F, s);
         c->last_test = 0;
         c->frame++;
         return GPDF_OK;
     }
     gpdf_status st = ensure_offsets(c);
     if (st != GPDF_OK) {
-        fill_multi(F, s);
+        (void)fill_multi(F, s);
         return st;
     }
     const double hf = c->p.fuse_voxel_size;
@@ -302,7 +302,7 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin, int64_
     const int64_t tcap = int64_t(c->tset_mask) + 1;
     stage_begin(c, GPDF_MS_TESTPTS);
     F.u64(c->d_tset, (unsigned long long)kNoKey, tcap);
-    fill_multi(F, s);
+    if ((e = fill_multi(F, s)) != hipSuccess) return hip_fail(c, e, "fuse: clear");
     HashView set{c->d_tset, c->tset_mask};
     const int64_t work = npts * int64_t(noffs);
     hipLaunchKernelGGL(k_test_insert, dim3(blocks_for(work)), dim3(kT), 0, s, c->d_pts, npts,

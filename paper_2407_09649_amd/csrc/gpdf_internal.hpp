@@ -513,10 +513,15 @@ struct FillList {
     static constexpr int kMax = 12;
     FillOp op[kMax];
     int count = 0;
-    void u64(unsigned long long *p, unsigned long long v, int64_t n) { op[count++] = FillOp{p, v, n, 8}; }
-    void u32(uint32_t *p, uint32_t v, int64_t n) { op[count++] = FillOp{p, v, n, 4}; }
+    bool overflow = false;  // an op past kMax was dropped (fill_multi then fails)
+    void add(const FillOp &o) {
+        if (count < kMax) op[count++] = o;
+        else overflow = true;
+    }
+    void u64(unsigned long long *p, unsigned long long v, int64_t n) { add(FillOp{p, v, n, 8}); }
+    void u32(uint32_t *p, uint32_t v, int64_t n) { add(FillOp{p, v, n, 4}); }
 };
-void fill_multi(const FillList &L, hipStream_t s);
+hipError_t fill_multi(const FillList &L, hipStream_t s);
 
 // small read-backs: one kernel stores the listed device words into the
 // context's pinned host words (as u64), then the stream is synchronised
@@ -525,10 +530,15 @@ struct ReadList {
     const void *src[kMax];
     int bytes[kMax];
     int count = 0;
-    void u32(const uint32_t *p, int n = 1) {
-        for (int k = 0; k < n; ++k) { src[count] = p + k; bytes[count++] = 4; }
+    bool overflow = false;  // a word past kMax was dropped (read_back then fails)
+    void add(const void *p, int b) {
+        if (count < kMax) { src[count] = p; bytes[count++] = b; }
+        else overflow = true;
     }
-    void u64(const unsigned long long *p) { src[count] = p; bytes[count++] = 8; }
+    void u32(const uint32_t *p, int n = 1) {
+        for (int k = 0; k < n; ++k) add(p + k, 4);
+    }
+    void u64(const unsigned long long *p) { add(p, 8); }
 };
 void fold_stats(unsigned long long *spread, unsigned long long *stat, hipStream_t s);
 // the values land in c->h_read[0 .. L.count)

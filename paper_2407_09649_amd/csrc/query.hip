@@ -1779,13 +1779,13 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     F.u64(c->d_stat + ST_REF_D, 0ull, 3);
     F.u32(cnt + CNT_CELLS, 0u, 3);  // cells, chunks, re-evaluation chunks
     if (m == 0) {
-        fill_multi(F, s);
+        (void)fill_multi(F, s);
         return GPDF_OK;
     }
     hipError_t e;
     if (M.host_counts && M.nclusters == 0) {
         // nothing to select: every query is invalid
-        fill_multi(F, s);
+        (void)fill_multi(F, s);
         hipLaunchKernelGGL(k_all_invalid, dim3(blocks_for(m)), dim3(kQT), 0, s, m, dist, grad, var,
                            valid, aux);
         return (e = hipGetLastError()) == hipSuccess ? GPDF_OK : hip_fail(c, e, "query launch");
@@ -1794,7 +1794,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     const bool vox = c->p.voxel_size > 0.0;
     const bool knn = C.knn_q > 0;
     if (!eager && (knn || c->p.precision == GPDF_PREC_BF16 || correct)) {
-        fill_multi(F, s);
+        (void)fill_multi(F, s);
         return fail(c, GPDF_E_INVALID_ARG, "query with device counts: NEIGHBOR27, FP32/FP64, no correction");
     }
     const double edge = vox ? 8.0 * c->p.voxel_size : c->p.cluster_size;
@@ -1809,7 +1809,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     const int64_t qcap = int64_t(qmask) + 1;
     F.u64(c->d_qhash, (unsigned long long)kNoKey, qcap);
     F.u32(c->d_qhash_cnt, 0u, qcap);
-    fill_multi(F, s);
+    if ((e = fill_multi(F, s)) != hipSuccess) return hip_fail(c, e, "query: clear");
     HashView qh{c->d_qhash, qmask};
     hipLaunchKernelGGL(k_qcells, dim3(blocks_for(m)), dim3(kQT), 0, s, d_q, m, dm, vox ? 1 : 0,
                        c->p.voxel_size, c->p.cluster_size, qh, c->d_qhash_cnt, c->d_qslot, c->d_qrank,

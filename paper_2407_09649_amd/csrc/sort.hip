@@ -348,17 +348,20 @@ void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
 }
 hipError_t read_back(gpdf_ctx *c, const ReadList &L, hipStream_t s) {
+    if (L.overflow) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_read_words, dim3(1), dim3(ReadList::kMax), 0, s, L, c->h_read);
     hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : hipStreamSynchronize(s);
 }
 
-void fill_multi(const FillList &L, hipStream_t s) {
-    if (L.count <= 0) return;
+hipError_t fill_multi(const FillList &L, hipStream_t s) {
+    if (L.overflow) return hipErrorInvalidValue;
+    if (L.count <= 0) return hipSuccess;
     int64_t nmax = 1;
     for (int k = 0; k < L.count; ++k) nmax = std::max(nmax, L.op[k].n);
     hipLaunchKernelGGL(k_fill_multi, dim3(std::min<unsigned>(grid_for(nmax, 256), 4096), unsigned(L.count)),
                        dim3(256), 0, s, L);
+    return hipGetLastError();
 }
 
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {

@@ -660,7 +660,7 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
     F.u32(cnt + CNT_VALID, 0u, CNT_MAXN - CNT_VALID + 1);
     F.u64(c->d_stat + ST_CAPACITY, 0ull, 1);
     F.u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1);
-    fill_multi(F, s);
+    if (hipError_t fe = fill_multi(F, s); fe != hipSuccess) return hip_fail(c, fe, "train: clear");
     if (n == 0) {
         M.host_counts = true;
         return GPDF_OK;
