@@ -192,7 +192,7 @@ __device__ __forceinline__ int tri_row(int p) {
 // may be either would compile to flat accesses)
 template <int T>
 __device__ __forceinline__ void train_block_body(double *__restrict__ A, double *__restrict__ craw,
-                                                 double *__restrict__ wraw, double *__restrict__ piv,
+                                                 double *__restrict__ piv,
                                                  int c, int base, int n,
                                                  float4 *__restrict__ pts, const int64_t *__restrict__ woff,
                                                  double *__restrict__ W64all, float *__restrict__ W32all,
@@ -214,20 +214,21 @@ __device__ __forceinline__ void train_block_body(double *__restrict__ A, double 
     }
     const double thr = 1e-10 * (1.0 + s2);
     const int end = n * (n + 1) / 2;
-    // Step k needs column k below the pivot (craw), row k left of it (wraw)
-    // and the pivot, unscaled, double-buffered: the wavefront that updates
-    // row i in step k also stages its entry (i, k + 1) for step k + 1, and
-    // the one that updates row k + 1 stages that row and the next pivot, so
-    // one barrier per step suffices.  With inv = 1 / sqrt(pivot) every
-    // update scales by lii = craw_i inv^2.
+    // Step k needs row k left of the pivot and column k below it, unscaled:
+    // both live in one vector x (x[j] = A(k, j) for j < k, A(j, k) for
+    // j > k), double-buffered with the pivot.  The wavefront that updates
+    // row k + 1 in step k stages that row and the next pivot; the lane that
+    // updates element (i, k + 1) of a lower row stages it, so one barrier per
+    // step suffices.  With inv = 1 / sqrt(pivot) every element of row i takes
+    // l_i = x_i inv^2 and becomes -l_i in column k, A(i, j) - l_i x_j elsewhere.
     __syncthreads();  // A assembled
     for (int i = 1 + tid; i < n; i += T) craw[i] = A[tri(i, 0)];
     if (tid == 0) piv[0] = A[0];
     __syncthreads();
     for (int k = 0; k < n; ++k) {
         const int b = k & 1;
-        const double *cr = craw + b * kMaxClusterN, *wr = wraw + b * kMaxClusterN;
-        double *crn = craw + (b ^ 1) * kMaxClusterN, *wrn = wraw + (b ^ 1) * kMaxClusterN;
+        const double *x = craw + b * kMaxClusterN;
+        double *xn = craw + (b ^ 1) * kMaxClusterN;
         const double d = piv[b];
         if (!(d > thr)) {
             for (int i = tid; i < n; i += T) {
@@ -243,25 +244,29 @@ __device__ __forceinline__ void train_block_body(double *__restrict__ A, double 
         const double inv = 1.0 / sqrt(d);
         const double inv2 = inv * inv;
         // row k of W (nobody reads row k during this step)
-        for (int j = tid; j < k; j += T) A[tri(k, j)] = wr[j] * inv;
+        for (int j = tid; j < k; j += T) A[tri(k, j)] = x[j] * inv;
         if (tid == 0) A[tri(k, k)] = inv;
         // rows below k: a packed row (contiguous) per wavefront, its columns
         // over the lanes
         for (int i = k + 1 + wv; i < n; i += kW) {
             double *Ai = A + tri(i, 0);
-            const double lii = cr[i] * inv2;
-            for (int j = lane; j <= i; j += 64) {
-                double a;
-                if (j < k) a = Ai[j] - lii * wr[j];
-                else if (j == k) a = -lii;
-                else a = Ai[j] - lii * cr[j];
-                Ai[j] = a;
-                if (i == k + 1) {
-                    if (j <= k) wrn[j] = a;
+            const double lii = x[i] * inv2;
+            if (i == k + 1) {
+                for (int j = lane; j <= i; j += 64) {
+                    const double a = j == k ? -lii : Ai[j] - lii * x[j];
+                    Ai[j] = a;
+                    if (j <= k) xn[j] = a;
                     else piv[b ^ 1] = a;
-                } else if (j == k + 1) {
-                    crn[i] = a;
                 }
+            } else {
+                // both loads unconditional (x[k] is read and then not used), so
+                // that column k costs a select instead of a branch
+                for (int j = lane; j <= i; j += 64) {
+                    const double aij = Ai[j], xj = x[j];
+                    const double t = aij - lii * xj;
+                    Ai[j] = j == k ? -lii : t;
+                }
+                if (lane == ((k + 1) & 63)) xn[i] = Ai[k + 1];  // this lane's own update
             }
         }
         __syncthreads();
@@ -321,7 +326,6 @@ __global__ __launch_bounds__(T) void k_train_block(
     uint8_t *__restrict__ pd, int kernel, double l, double s2, unsigned long long *__restrict__ stat) {
     __shared__ double sA[kBlockLdsElems];
     __shared__ double craw[2 * kMaxClusterN];
-    __shared__ double wraw[2 * kMaxClusterN];
     __shared__ double piv[2];
     __shared__ uint32_t item;
     const uint32_t cnt = *dcnt;
@@ -335,10 +339,10 @@ __global__ __launch_bounds__(T) void k_train_block(
         const int base = coff[c];
         const int n = coff[c + 1] - base;
         if (n <= kBlockLdsN)
-            train_block_body<T>(sA, craw, wraw, piv, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel,
+            train_block_body<T>(sA, craw, piv, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel,
                                 l, s2, stat);
         else
-            train_block_body<T>(Aall + aoff[c], craw, wraw, piv, c, base, n, pts, woff, W64all, W32all, alpha64,
+            train_block_body<T>(Aall + aoff[c], craw, piv, c, base, n, pts, woff, W64all, W32all, alpha64,
                                 pd, kernel, l, s2, stat);
     }
 }
