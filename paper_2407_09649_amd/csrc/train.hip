@@ -190,7 +190,7 @@ __device__ __forceinline__ int tri_row(int p) {
 // the body, inlined once with A in LDS and once with A in global memory, so
 // that every access compiles to LDS or global instructions (a pointer that
 // may be either would compile to flat accesses)
-template <int T>
+template <int T, int MAXC>
 __device__ __forceinline__ void train_block_body(double *__restrict__ A, double *__restrict__ craw,
                                                  double *__restrict__ piv,
                                                  int c, int base, int n,
@@ -260,11 +260,25 @@ __device__ __forceinline__ void train_block_body(double *__restrict__ A, double 
                 }
             } else {
                 // both loads unconditional (x[k] is read and then not used), so
-                // that column k costs a select instead of a branch
-                for (int j = lane; j <= i; j += 64) {
-                    const double aij = Ai[j], xj = x[j];
-                    const double t = aij - lii * xj;
-                    Ai[j] = j == k ? -lii : t;
+                // that column k costs a select instead of a branch; with A in
+                // LDS a row has at most MAXC chunks of 64 columns, unrolled so
+                // that their loads are issued together
+                if constexpr (MAXC > 0) {
+#pragma unroll
+                    for (int cc = 0; cc < MAXC; ++cc) {
+                        const int j = lane + 64 * cc;
+                        if (j <= i) {
+                            const double aij = Ai[j], xj = x[j];
+                            const double t = aij - lii * xj;
+                            Ai[j] = j == k ? -lii : t;
+                        }
+                    }
+                } else {
+                    for (int j = lane; j <= i; j += 64) {
+                        const double aij = Ai[j], xj = x[j];
+                        const double t = aij - lii * xj;
+                        Ai[j] = j == k ? -lii : t;
+                    }
                 }
                 if (lane == ((k + 1) & 63)) xn[i] = Ai[k + 1];  // this lane's own update
             }
@@ -339,10 +353,10 @@ __global__ __launch_bounds__(T) void k_train_block(
         const int base = coff[c];
         const int n = coff[c + 1] - base;
         if (n <= kBlockLdsN)
-            train_block_body<T>(sA, craw, piv, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel,
+            train_block_body<T, (kBlockLdsN + 63) / 64>(sA, craw, piv, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel,
                                 l, s2, stat);
         else
-            train_block_body<T>(Aall + aoff[c], craw, piv, c, base, n, pts, woff, W64all, W32all, alpha64,
+            train_block_body<T, 0>(Aall + aoff[c], craw, piv, c, base, n, pts, woff, W64all, W32all, alpha64,
                                 pd, kernel, l, s2, stat);
     }
 }
