@@ -137,11 +137,21 @@ __global__ __launch_bounds__(kScan1Threads) void k_scan_single(const uint32_t *_
     const int64_t n = scan_count(nb_, dn);
     const int t = int(threadIdx.x);
     uint32_t carry = 0;
+    // the next tile's loads are issued before the current tile is scanned
+    uint32_t nx[kScan1Items];
+#pragma unroll
+    for (int i = 0; i < kScan1Items; ++i) {
+        const int j = i * kScan1Threads + t;
+        nx[i] = j < n ? in[j] : 0u;
+    }
     for (int64_t t0 = 0; t0 < n; t0 += kScan1Tile) {
 #pragma unroll
+        for (int i = 0; i < kScan1Items; ++i) buf[scan1_pad(i * kScan1Threads + t)] = nx[i];
+        const int64_t t1 = t0 + kScan1Tile;
+#pragma unroll
         for (int i = 0; i < kScan1Items; ++i) {
-            const int j = i * kScan1Threads + t;
-            buf[scan1_pad(j)] = t0 + j < n ? in[t0 + j] : 0u;
+            const int64_t j = t1 + i * kScan1Threads + t;
+            nx[i] = j < n ? in[j] : 0u;
         }
         __syncthreads();
         uint32_t v[kScan1Items];
