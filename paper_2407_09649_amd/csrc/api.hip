@@ -132,7 +132,7 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
     (void)hipGetDevice(&c->device);
     hipError_t e = hipSuccess;
     const int64_t P = p->max_points, C = p->max_clusters, M = p->max_queries;
-    const int64_t nbP = (P + 4095) / 4096;
+    const int64_t nbP = (P + kRsTileKeys - 1) / kRsTileKeys;
     const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(P, M), 256 * nbP) + 1;
     c->cap_w = p->max_factor_elems;
     c->cap_a = p->max_factor_elems;

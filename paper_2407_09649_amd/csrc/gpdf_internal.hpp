@@ -498,6 +498,8 @@ void radix_sort_pairs(uint64_t *&keys, uint64_t *&keys_alt, uint32_t *&vals, uin
 // tile_off[t] = first output index of tile t, tile_off[ntiles] = total
 void count_occupied(const unsigned long long *keys, int64_t cap, uint32_t *tile_cnt,
                     uint32_t *tile_off, uint32_t *partials, hipStream_t s);
+// keys per block of the radix sort (its histogram holds 256 counts per block)
+constexpr int64_t kRsTileKeys = 1024;
 void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 

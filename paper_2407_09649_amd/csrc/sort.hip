@@ -187,8 +187,9 @@ __global__ __launch_bounds__(kScan1Threads) void k_scan_single(const uint32_t *_
 // radix sort, 8-bit digits
 // ---------------------------------------------------------------------------
 constexpr int kRsThreads = 256;
-constexpr int kRsItems = 16;
+constexpr int kRsItems = 4;  // rounds per block: short serial chains, many blocks
 constexpr int kRsTile = kRsThreads * kRsItems;
+static_assert(kRsTile == kRsTileKeys, "histogram sizing");
 constexpr int64_t kRsRawBlocks = 64;  // up to this many blocks the scatter scans the counts itself
 
 __global__ void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
@@ -219,6 +220,7 @@ __global__ void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (raw) {
         uint32_t tot = 0, before = 0;
+#pragma unroll 16
         for (int64_t b = 0; b < nblocks; ++b) {
             const uint32_t h = hist[int64_t(threadIdx.x) * nblocks + b];
             tot += h;
@@ -313,7 +315,7 @@ void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *
 
 // Stable sort by key over the 8-bit digits that contain varying bits; the
 // result ends in (keys, vals) (pointers are swapped as needed).  hist needs
-// 256 * ceil(n / 4096) entries, partials ceil(256 * ceil(n / 4096) / 4096) + 1.
+// 256 * ceil(n / kRsTileKeys) entries, partials ceil(256 * ceil(n / kRsTileKeys) / 4096) + 1.
 void radix_sort_pairs(uint64_t *&keys, uint64_t *&keys_alt, uint32_t *&vals, uint32_t *&vals_alt,
                       int64_t n, uint64_t varying_bits, uint32_t *hist, uint32_t *partials,
                       hipStream_t s) {
