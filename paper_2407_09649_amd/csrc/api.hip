@@ -27,6 +27,7 @@ namespace {
 
 
 void release(gpdf_ctx *c) {
+    if (c->side) (void)hipStreamSynchronize(c->side);  // a trainer may still run there
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->gstream) (void)hipStreamDestroy(c->gstream);
@@ -243,6 +244,7 @@ extern "C" gpdf_status gpdf_query_distance(gpdf_ctx *c, const float *d_q, int64_
 extern "C" gpdf_status gpdf_fuse_frame(gpdf_ctx *c, const float *d_xyz, int64_t n,
                                        const float *h_origin) {
     if (!c) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     if (!h_origin || !(std::isfinite(h_origin[0]) && std::isfinite(h_origin[1]) &&
                        std::isfinite(h_origin[2])))
         return fail(c, GPDF_E_INVALID_ARG, "fuse: origin required");
@@ -313,6 +315,7 @@ gpdf_status capture_frame_graph(gpdf_ctx *c) {
 
 extern "C" gpdf_status gpdf_fuse_frame_graph(gpdf_ctx *c, const float *d_xyz, int64_t n, const float *h_origin) {
     if (!c) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     if (!h_origin || !(std::isfinite(h_origin[0]) && std::isfinite(h_origin[1]) && std::isfinite(h_origin[2])))
         return fail(c, GPDF_E_INVALID_ARG, "fuse_frame_graph: origin required");
     if (n < 0 || n > c->p.max_points) return fail(c, GPDF_E_CAPACITY, "fuse_frame_graph: n exceeds max_points");
@@ -352,6 +355,7 @@ extern "C" gpdf_status gpdf_fuse_frame_graph(gpdf_ctx *c, const float *d_xyz, in
 extern "C" gpdf_status gpdf_query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *d_dist,
                                          float *d_grad, uint8_t *d_valid) {
     if (!c) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     stage_begin(c, GPDF_MS_GLOBAL);
     gpdf_status s = query_global(c, d_q, m, d_dist, d_grad, d_valid);
     stage_end(c, GPDF_MS_GLOBAL);
@@ -360,6 +364,7 @@ extern "C" gpdf_status gpdf_query_global(gpdf_ctx *c, const float *d_q, int64_t 
 
 extern "C" gpdf_status gpdf_get_stats(gpdf_ctx *c, gpdf_stats *out) {
     if (!c || !out) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     hipError_t e;
     if ((e = hipMemcpyAsync(c->h_stat, c->d_stat, sizeof(unsigned long long) * ST_COUNT,
                             hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
@@ -422,6 +427,7 @@ extern "C" const char *gpdf_last_error(const gpdf_ctx *c) {
 extern "C" gpdf_status gpdf_export_model(gpdf_ctx *c, uint64_t *h_ckey, int64_t *h_off,
                                          float *h_points, double *h_alpha, uint8_t *h_pd) {
     if (!c) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     if (!c->model.trained) return fail(c, GPDF_E_NOT_TRAINED, "export before training");
     const int64_t nc = c->model.nclusters, np = c->model.npoints;
     hipError_t e;
@@ -452,5 +458,6 @@ extern "C" gpdf_status gpdf_export_model(gpdf_ctx *c, uint64_t *h_ckey, int64_t 
 extern "C" gpdf_status gpdf_nearest_distance(gpdf_ctx *c, const float *d_pts, int64_t n,
                                              const float *d_q, int64_t m, float *d_out) {
     if (!c) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     return nearest_distance(c, d_pts, n, d_q, m, d_out);
 }

@@ -394,6 +394,7 @@ gpdf_status read_global(gpdf_ctx *c, std::vector<Rec> &out) {
 extern "C" gpdf_status gpdf_export_global(gpdf_ctx *c, uint64_t *h_key, float *h_D, float *h_V,
                                           uint32_t *h_stamp, int64_t cap, int64_t *count) {
     if (!c || !count) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     std::vector<Rec> r;
     gpdf_status s = read_global(c, r);
     if (s != GPDF_OK) return s;
@@ -411,6 +412,7 @@ extern "C" gpdf_status gpdf_export_global(gpdf_ctx *c, uint64_t *h_key, float *h
 extern "C" gpdf_status gpdf_export_test_points(gpdf_ctx *c, uint64_t *h_key, int64_t cap,
                                                int64_t *count) {
     if (!c || !count) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     hipError_t e;
     const int64_t n = c->last_test;
     *count = n;
@@ -436,6 +438,7 @@ struct FileHeader {
 
 extern "C" gpdf_status gpdf_save_global(gpdf_ctx *c, const char *path) {
     if (!c || !path) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     std::vector<Rec> r;
     gpdf_status s = read_global(c, r);
     if (s != GPDF_OK) return s;
@@ -453,6 +456,7 @@ extern "C" gpdf_status gpdf_save_global(gpdf_ctx *c, const char *path) {
 
 extern "C" gpdf_status gpdf_load_global(gpdf_ctx *c, const char *path) {
     if (!c || !path) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     FILE *f = std::fopen(path, "rb");
     if (!f) return fail(c, GPDF_E_INVALID_ARG, "load_global: cannot open file");
     FileHeader h{};

@@ -367,6 +367,10 @@ struct gpdf_ctx {
     hipStream_t gstream = nullptr; // capture stream
     hipStream_t side = nullptr;    // second stream: the large-cluster trainer beside the others
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    // an eager training leaves the large-cluster trainer running on `side`;
+    // the first later operation that needs the model (or its buffers) makes
+    // the caller's stream wait for join_ev (join_train)
+    bool join_pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     float *d_gin = nullptr;        // input points of the graph [max_points][3]
@@ -476,9 +480,23 @@ inline void stage_begin(gpdf_ctx *c, int k) {
 }
 inline void stage_end(gpdf_ctx *c, int k) {
     if (c->p.timing && !c->capturing) {
-        (void)hipEventRecord(c->ev[2 * k + 1], c->stream);
+        if (c->join_pending) {
+            // the stage ends when both streams have: record on `side` after
+            // it has waited for the caller's stream (which does not wait)
+            (void)hipEventRecord(c->fork_ev, c->stream);
+            (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
+            (void)hipEventRecord(c->ev[2 * k + 1], c->side);
+        } else {
+            (void)hipEventRecord(c->ev[2 * k + 1], c->stream);
+        }
         c->ev_ok[k] = true;
     }
+}
+// makes the caller's stream wait for a pending large-cluster trainer
+inline hipError_t join_train(gpdf_ctx *c) {
+    if (!c->join_pending) return hipSuccess;
+    c->join_pending = false;
+    return hipStreamWaitEvent(c->stream, c->join_ev, 0);
 }
 // error helpers
 gpdf_status fail(gpdf_ctx *c, gpdf_status s, const std::string &msg);

@@ -534,6 +534,7 @@ gpdf_status mlp_batch(gpdf_ctx *c, const float *feat, const float *tgt, int64_t 
 
 gpdf_status need_ready(gpdf_ctx *c) {
     if (!c) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     if (!c->mlp_ready) return fail(c, GPDF_E_INVALID_ARG, "learned correction: no weights (gpdf_mlp_init)");
     return GPDF_OK;
 }
@@ -567,6 +568,7 @@ using namespace gpdf;
 
 extern "C" gpdf_status gpdf_mlp_init(gpdf_ctx *c, uint64_t seed) {
     if (!c) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     gpdf_status st = mlp_alloc(c);
     if (st != GPDF_OK) return st;
     // W ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)), biases 0, identity standardisation
@@ -596,6 +598,7 @@ extern "C" gpdf_status gpdf_mlp_init(gpdf_ctx *c, uint64_t seed) {
 
 extern "C" gpdf_status gpdf_mlp_set_weights(gpdf_ctx *c, const float *h_w, int64_t n) {
     if (!c || !h_w) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     if (n != kNP) return fail(c, GPDF_E_INVALID_ARG, "mlp_set_weights: expected 8897 parameters");
     gpdf_status st = mlp_alloc(c);
     if (st != GPDF_OK) return st;
@@ -660,6 +663,7 @@ extern "C" gpdf_status gpdf_mlp_get_norm(gpdf_ctx *c, float *h_mean, float *h_st
 extern "C" gpdf_status gpdf_mlp_features(gpdf_ctx *c, const float *d_dist, const float *d_var,
                                          const float *d_grad, const float *d_aux, int64_t n, float *d_feat) {
     if (!c) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     if (n < 0) return fail(c, GPDF_E_INVALID_ARG, "mlp_features: n < 0");
     if (n == 0) return GPDF_OK;
     if (!d_dist || !d_var || !d_grad || !d_aux || !d_feat) return fail(c, GPDF_E_INVALID_ARG, "mlp_features: null");

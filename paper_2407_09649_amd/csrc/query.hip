@@ -1759,6 +1759,7 @@ gpdf_status build_bf16(gpdf_ctx *c) {
 gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin, float *dist,
                   float *grad, float *var, uint8_t *valid, float *aux, int32_t correct, const uint32_t *dm,
                   const float *d_origin) {
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "query: join");
     hipStream_t s = c->stream;
     const Model &M = c->model;
     const bool eager = dm == nullptr;

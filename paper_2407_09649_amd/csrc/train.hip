@@ -666,6 +666,7 @@ __global__ void k_chash_insert(const uint64_t *__restrict__ ckey, int64_t nbound
 // sequence can be captured in a graph; otherwise the counts and the
 // capacity counter are read back once at the end.
 gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn) {
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "train: join");
     hipStream_t s = c->stream;
     Model &M = c->model;
     const bool eager = dn == nullptr;
@@ -749,7 +750,11 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
     hipLaunchKernelGGL(k_train_wave, dim3(unsigned(std::min<int64_t>(C, 2048))), dim3(64), 0, s, c->d_blist + C,
                        cnt + CNT_WAVE, c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
                        c->p.kernel, l, s2, c->d_stat);
-    if ((e = hipStreamWaitEvent(s, c->join_ev, 0)) != hipSuccess) return hip_fail(c, e, "train: join");
+    // eager: the join is left to the first operation that needs the model
+    // (the test voxels of a fusion, which need only the points, run beside
+    // the trainer); a captured frame joins here
+    if (eager) c->join_pending = true;
+    else if ((e = hipStreamWaitEvent(s, c->join_ev, 0)) != hipSuccess) return hip_fail(c, e, "train: join");
     // 6. cluster hash
     HashView hv{c->d_chash, c->chash_mask};
     hipLaunchKernelGGL(k_chash_insert, dim3(blocks_for(C)), dim3(kT), 0, s, c->d_ckey, C, cnt + CNT_CL, hv,

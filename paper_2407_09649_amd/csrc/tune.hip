@@ -76,6 +76,7 @@ extern "C" gpdf_status gpdf_get_tuning(const gpdf_ctx *c, int32_t *train_threads
 extern "C" gpdf_status gpdf_autotune(gpdf_ctx *c, const float *d_xyz, int64_t n, const float *d_q, int64_t m,
                                      const float *h_origin, float *h_ms) {
     if (!c) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
     if (n < 1 || !d_xyz || m < 1 || !d_q) return fail(c, GPDF_E_INVALID_ARG, "autotune: empty or null input");
     if (m > c->p.max_queries) return fail(c, GPDF_E_CAPACITY, "autotune: m exceeds max_queries");
     float ms[7] = {};
@@ -84,7 +85,12 @@ extern "C" gpdf_status gpdf_autotune(gpdf_ctx *c, const float *d_xyz, int64_t n,
         float best = 0.f;
         for (int i = 0; i < 3; ++i) {
             c->tune.train_threads = kTrainCand[i];
-            gpdf_status st = time_median(c, [&] { return train(c, d_xyz, n); }, &ms[i]);
+            gpdf_status st = time_median(c, [&] {
+                // the timed region covers the large-cluster trainer too
+                const gpdf_status ts = train(c, d_xyz, n);
+                (void)join_train(c);
+                return ts;
+            }, &ms[i]);
             if (st != GPDF_OK) return st;
             if (i == 0 || ms[i] < best) { best = ms[i]; best_t = kTrainCand[i]; }
         }
