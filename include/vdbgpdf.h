@@ -19,6 +19,13 @@
  *    it finishes; the caller keeps device buffers alive until the stream is
  *    synchronised.  gpdf_train_local_gps and gpdf_fuse_frame synchronise the
  *    stream once internally to size their launches.
+ *  - Training runs its clusters above 64 points on a second, internal stream
+ *    of the same context.  After gpdf_train_local_gps returns that part may
+ *    still run: the next call of this library that needs the model or its
+ *    buffers (any call below except gpdf_params_default, gpdf_create,
+ *    gpdf_last_error and the tuning getters/setters) first makes the
+ *    context's stream wait for it, and gpdf_destroy waits for it.  Work that
+ *    the caller enqueues on the stream directly does not wait for it.
  *  - The library owns its arenas.  They are sized at gpdf_create from the
  *    capacities in gpdf_params and never grow: a call that would exceed one
  *    returns GPDF_E_CAPACITY and leaves the previous state untouched.
