@@ -524,8 +524,22 @@ __global__ __launch_bounds__(64) void k_train_wave(
         if (lane > k && lane < n) A[lane * S + k] /= lkk;
         __syncthreads();
         if (lane > k && lane < n) {
+            // four columns at a time, their loads before their stores: the
+            // row elements (lane, j > k) written here are never the column
+            // elements (j, k) read here (S > kWaveN), so they do not alias
             const double lik = A[lane * S + k];
-            for (int j = k + 1; j <= lane; ++j) A[lane * S + j] -= lik * A[j * S + k];
+            double *Ar = A + lane * S;
+            int j = k + 1;
+            for (; j + 3 <= lane; j += 4) {
+                const double c0 = A[j * S + k], c1 = A[(j + 1) * S + k], c2 = A[(j + 2) * S + k],
+                             c3 = A[(j + 3) * S + k];
+                const double r0 = Ar[j], r1 = Ar[j + 1], r2 = Ar[j + 2], r3 = Ar[j + 3];
+                Ar[j] = r0 - lik * c0;
+                Ar[j + 1] = r1 - lik * c1;
+                Ar[j + 2] = r2 - lik * c2;
+                Ar[j + 3] = r3 - lik * c3;
+            }
+            for (; j <= lane; ++j) Ar[j] -= lik * A[j * S + k];
         }
     }
     if (!ok) {
