@@ -1160,12 +1160,12 @@ __device__ void coop_batch(const float *__restrict__ q, const Grouping &G, uint3
 #pragma unroll
             for (int u = 0; u < P; ++u) v[a][u] = 0.0;
         int j = 0;
-        for (; j + 4 <= ncol; j += 4) {
-            double w[4];
+        for (; j + 8 <= ncol; j += 8) {
+            double w[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) w[u] = Wp[int64_t(j + u) * kPanel];
+            for (int u = 0; u < 8; ++u) w[u] = Wp[int64_t(j + u) * kPanel];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 8; ++u)
 #pragma unroll
                 for (int a = 0; a < NB; ++a) v[a][u % P] = fma(w[u], kb[(j + u) * NB + a], v[a][u % P]);
         }
