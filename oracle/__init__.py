@@ -92,7 +92,7 @@ def _bind(L):
     L.orc_model_sizes.argtypes = [_P, _P]
     L.orc_model_export.argtypes = [_P, _P, _P, _P, _P, _P]
     L.orc_model_factor.argtypes = [_P, _I64, _P]
-    L.orc_query.argtypes = [_P, _P, _I64, _P, _P, _P, _P, _P, _P, C.c_int]
+    L.orc_query.argtypes = [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, C.c_int]
     L.orc_test_points.argtypes = [_P, _P, _I64]
     L.orc_test_points.restype = _I64
     L.orc_voxel_centres.argtypes = [_P, _I64, _D, _P]
@@ -100,12 +100,12 @@ def _bind(L):
     L.orc_map_free.argtypes = [_P]
     L.orc_map_size.argtypes = [_P]
     L.orc_map_size.restype = _I64
-    L.orc_map_export.argtypes = [_P, _P, _P, _P, _P]
-    L.orc_map_merge.argtypes = [_P, _P, _P, _P, _P, _I64, C.c_uint32]
+    L.orc_map_export.argtypes = [_P, _P, _P, _P, _P, _P]
+    L.orc_map_merge.argtypes = [_P, _P, _P, _P, _P, _P, _I64, C.c_uint32]
     L.orc_map_merge.restype = _I64
     L.orc_fuse.argtypes = [_P, _P, _P, C.c_uint32, C.POINTER(_I64), C.c_int]
     L.orc_fuse.restype = _I64
-    L.orc_query_global.argtypes = [_P, _D, _P, _I64, _P, _P, _P]
+    L.orc_query_global.argtypes = [_P, _D, _P, _I64, _P, _P, _P, _P]
     L.orc_nearest_distance.argtypes = [_P, _I64, _P, _I64, _P, C.c_int]
     L.orc_max_threads.restype = C.c_int
     return L
@@ -186,15 +186,22 @@ class Model:
         return L
 
     def query(self, q, origin=None, nthreads: int = 0):
+        """Distance, gradient, variance, validity and aux (occupancy and
+        latent variance of the closest node, points used) per query.  With an
+        origin the result is signed and ``sign_tie`` marks the queries whose
+        sign an FP32 evaluation could decide the other way."""
         x = _f32(q).reshape(-1, 3)
         m = x.shape[0]
         out = dict(dist=np.empty(m), grad=np.empty((m, 3)), var=np.empty(m),
-                   valid=np.empty(m, np.uint8), aux=np.empty((m, 3)))
+                   valid=np.empty(m, np.uint8), aux=np.empty((m, 3)),
+                   sign_tie=np.zeros(m, np.uint8))
         o = None if origin is None else _f32(origin).reshape(3)
         lib().orc_query(self._h, _ptr(x), m, _ptr(o), _ptr(out["dist"]),
                         _ptr(out["grad"]), _ptr(out["var"]),
-                        _ptr(out["valid"]), _ptr(out["aux"]), int(nthreads))
+                        _ptr(out["valid"]), _ptr(out["aux"]), _ptr(out["sign_tie"]),
+                        int(nthreads))
         out["valid"] = out["valid"].astype(bool)
+        out["sign_tie"] = out["sign_tie"].astype(bool)
         return out
 
     def test_points(self):
@@ -230,13 +237,14 @@ class Map:
                            C.byref(sk), int(nthreads))
         return int(n), int(sk.value)
 
-    def merge(self, keys_, d, v, ok, frame: int):
+    def merge(self, keys_, d, v, ok, frame: int, tie=None):
         k = np.ascontiguousarray(keys_, np.uint64)
         d = np.ascontiguousarray(d, np.float64)
         v = np.ascontiguousarray(v, np.float64)
         ok = np.ascontiguousarray(ok, np.uint8)
+        t = None if tie is None else np.ascontiguousarray(tie, np.uint8)
         return int(lib().orc_map_merge(self._h, _ptr(k), _ptr(d), _ptr(v),
-                                       _ptr(ok), k.shape[0], int(frame)))
+                                       _ptr(ok), _ptr(t), k.shape[0], int(frame)))
 
     def size(self) -> int:
         return int(lib().orc_map_size(self._h))
@@ -247,8 +255,9 @@ class Map:
         D = np.empty(n)
         V = np.empty(n)
         s = np.empty(n, np.uint32)
-        lib().orc_map_export(self._h, _ptr(k), _ptr(D), _ptr(V), _ptr(s))
-        return dict(key=k, D=D, V=V, stamp=s)
+        t = np.empty(n, np.uint8)
+        lib().orc_map_export(self._h, _ptr(k), _ptr(D), _ptr(V), _ptr(s), _ptr(t))
+        return dict(key=k, D=D, V=V, stamp=s, sign_tie=t.astype(bool))
 
     def query(self, h, q):
         x = _f32(q).reshape(-1, 3)
@@ -256,9 +265,10 @@ class Map:
         d = np.empty(m)
         g = np.empty((m, 3))
         ok = np.empty(m, np.uint8)
+        t = np.empty(m, np.uint8)
         lib().orc_query_global(self._h, float(h), _ptr(x), m, _ptr(d), _ptr(g),
-                               _ptr(ok))
-        return dict(dist=d, grad=g, valid=ok.astype(bool))
+                               _ptr(ok), _ptr(t))
+        return dict(dist=d, grad=g, valid=ok.astype(bool), sign_tie=t.astype(bool))
 
 
 def nearest_distance(points, q, nthreads: int = 0):

@@ -22,10 +22,14 @@
  * place (variance sign, smooth-min sign, cap values, sign rule, test points,
  * global interpolation).
  *
- * Two integer decisions are taken in FP32 on purpose, in the order the GPU
- * kernels use: the nearest training point for the distance sign and the sign
- * of the sensor-side dot product.  Both sides then agree bit for bit on these
- * decisions instead of disagreeing on near-ties that FP32 cannot resolve.
+ * The sign of the distance follows the sensor side of the nearest training
+ * point.  That point and the side are decided here in FP64 from the FP32
+ * inputs (ties to the smaller cluster key, then the smaller member index).
+ * A query whose decision an FP32 evaluation could take the other way (two
+ * candidates on different sides whose squared distances lie within FP32
+ * rounding of each other, or a side product within its FP32 rounding of
+ * zero) is flagged as a sign near-tie, so that a comparison can tell such a
+ * query from a wrong sign.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math, no
  * contraction: every double operation is a single rounded IEEE operation).
@@ -546,11 +550,80 @@ static void orc_eval_pair(const orc_model *m, int64_t c, const double x[3],
 }
 
 /* ------------------------------------------------------------------------ */
+/* sign of the distance: the sensor side of the nearest training point        */
+/* (Sec. IV overview: the sign comes from the sensor origin and the points)   */
+/* ------------------------------------------------------------------------ */
+#define ORC_U32 5.9604644775390625e-08 /* 2^-24, unit roundoff of FP32 */
+
+/* (x - p).(o - p) in FP64 and the sum of |products| that bounds its rounding */
+static double orc_side(const float *x, const float *p, const float *o, double *mag)
+{
+    double dot = 0.0, m = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double t = ((double)x[a] - (double)p[a]) * ((double)o[a] - (double)p[a]);
+        dot += t;
+        m += fabs(t);
+    }
+    *mag = m;
+    return dot;
+}
+
+static double orc_r2(const float *x, const float *p)
+{
+    double r2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double d = (double)x[a] - (double)p[a];
+        r2 += d * d;
+    }
+    return r2;
+}
+
+/* Returns -1 if the query lies behind its nearest training point as seen
+ * from the origin, +1 otherwise, 0 if no point is selected.  *tie is set when
+ * FP32 arithmetic could decide differently.  Bounds: an FP32 coordinate
+ * difference has relative error at most u = 2^-24, and a three-term sum of
+ * products adds three roundings, so an FP32 squared distance or side product
+ * is within 6u of the exact value (times r^2, or times the sum of |products|);
+ * 8u is used. */
+static int orc_sign(const orc_model *m, const int64_t *sel, int ns, const float *x,
+                    const float *origin, uint8_t *tie)
+{
+    const float *best = NULL;
+    double b2 = INFINITY, mag, dot, side;
+    int t = 0;
+    /* the exact nearest point; strict < keeps the first in ascending
+     * cluster key and member order */
+    for (int s = 0; s < ns; ++s)
+        for (int64_t i = m->off[sel[s]]; i < m->off[sel[s] + 1]; ++i) {
+            double r2 = orc_r2(x, m->pts + 3 * i);
+            if (r2 < b2) { b2 = r2; best = m->pts + 3 * i; }
+        }
+    if (!best) { *tie = 0; return 0; }
+    dot = orc_side(x, best, origin, &mag);
+    side = dot >= 0.0 ? 1.0 : -1.0;
+    if (fabs(dot) < 8.0 * ORC_U32 * mag) t = 1;
+    /* any candidate FP32 could take for the nearest that lies on the other
+     * side (or on an undecidable side) */
+    for (int s = 0; s < ns && !t; ++s)
+        for (int64_t i = m->off[sel[s]]; i < m->off[sel[s] + 1] && !t; ++i) {
+            const float *p = m->pts + 3 * i;
+            double r2, d2, m2;
+            if (p == best) continue;
+            r2 = orc_r2(x, p);
+            if (r2 - b2 > 8.0 * ORC_U32 * (r2 + b2)) continue;
+            d2 = orc_side(x, p, origin, &m2);
+            if ((d2 >= 0.0 ? 1.0 : -1.0) != side || fabs(d2) < 8.0 * ORC_U32 * m2) t = 1;
+        }
+    *tie = (uint8_t)t;
+    return side > 0.0 ? 1 : -1;
+}
+
+/* ------------------------------------------------------------------------ */
 /* query: selection, per-pair inference, Eq. (10), sign                      */
 /* ------------------------------------------------------------------------ */
 void orc_query(const orc_model *m, const float *q, int64_t nq,
                const float *origin, double *dist, double *grad, double *var,
-               uint8_t *valid, double *aux, int nthreads)
+               uint8_t *valid, double *aux, uint8_t *tie, int nthreads)
 {
     const orc_params *p = &m->p;
     int64_t maxn = 1;
@@ -572,6 +645,7 @@ void orc_query(const orc_model *m, const float *q, int64_t nq,
             int64_t sel[ORC_MAXSEL];
             int ns = orc_select(m, xf, sel);
             int64_t ntot = 0;
+            if (tie) tie[j] = 0;
             if (ns == 0) {
                 dist[j] = INFINITY; var[j] = INFINITY; valid[j] = 0;
                 for (int a = 0; a < 3; ++a) grad[3 * j + a] = 0.0;
@@ -614,31 +688,12 @@ void orc_query(const orc_model *m, const float *q, int64_t nq,
                     }
                 }
                 if (origin) {
-                    /* Sign from the sensor origin and the training points
-                     * (Sec. IV overview): the query lies on the sensor side
-                     * of its nearest training point p* when
-                     * (x - p*).(o - p*) >= 0.  Nearest point and dot product
-                     * are decided in FP32 (see file header). */
-                    float best = INFINITY;
-                    const float *ps = NULL;
-                    for (int s = 0; s < ns; ++s) {
-                        int64_t c = sel[s];
-                        for (int64_t i = m->off[c]; i < m->off[c + 1]; ++i) {
-                            const float *pi = m->pts + 3 * i;
-                            float ex = xf[0] - pi[0], ey = xf[1] - pi[1], ez = xf[2] - pi[2];
-                            float r2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
-                            if (r2 < best) { best = r2; ps = pi; }
-                        }
+                    uint8_t t = 0;
+                    if (orc_sign(m, sel, ns, xf, origin, &t) < 0) {
+                        D = -D;
+                        for (int a = 0; a < 3; ++a) G[a] = -G[a];
                     }
-                    if (ps) {
-                        float ax = xf[0] - ps[0], ay = xf[1] - ps[1], az = xf[2] - ps[2];
-                        float bx = origin[0] - ps[0], by = origin[1] - ps[1], bz = origin[2] - ps[2];
-                        float dot = fmaf(az, bz, fmaf(ay, by, ax * bx));
-                        if (!(dot >= 0.0f)) {
-                            D = -D;
-                            for (int a = 0; a < 3; ++a) G[a] = -G[a];
-                        }
-                    }
+                    if (tie) tie[j] = t;
                 }
                 dist[j] = D; var[j] = V; valid[j] = 1;
                 for (int a = 0; a < 3; ++a) grad[3 * j + a] = G[a];
@@ -729,6 +784,7 @@ typedef struct {
     uint64_t *key;
     double *D, *V;
     uint32_t *stamp;
+    uint8_t *tie;     /* some fused observation had a sign near-tie */
 } orc_map;
 
 orc_map *orc_map_new(void) { return (orc_map *)calloc(1, sizeof(orc_map)); }
@@ -736,34 +792,38 @@ orc_map *orc_map_new(void) { return (orc_map *)calloc(1, sizeof(orc_map)); }
 void orc_map_free(orc_map *g)
 {
     if (!g) return;
-    free(g->key); free(g->D); free(g->V); free(g->stamp); free(g);
+    free(g->key); free(g->D); free(g->V); free(g->stamp); free(g->tie); free(g);
 }
 
 int64_t orc_map_size(const orc_map *g) { return g->n; }
 
 void orc_map_export(const orc_map *g, uint64_t *key, double *D, double *V,
-                    uint32_t *stamp)
+                    uint32_t *stamp, uint8_t *tie)
 {
     memcpy(key, g->key, sizeof(uint64_t) * (size_t)g->n);
     memcpy(D, g->D, sizeof(double) * (size_t)g->n);
     memcpy(V, g->V, sizeof(double) * (size_t)g->n);
     memcpy(stamp, g->stamp, sizeof(uint32_t) * (size_t)g->n);
+    if (tie) memcpy(tie, g->tie, (size_t)g->n);
 }
 
 /* Merge one frame of observations (sorted unique keys) into the map.
  * An absent voxel takes the observation (the V_{i-1} = infinity limit of
  * Eq. (8)); a present one is updated by Eq. (7)-(8):
  *   D <- (V d + v D) / (V + v),  V <- (1/V + 1/v)^{-1} = V v / (V + v).
- * Observations with a non-finite or non-positive variance are skipped. */
+ * Observations with a non-finite or non-positive variance are skipped.
+ * tie (may be NULL) marks observations whose sign was a near-tie; the mark
+ * stays on the voxel. */
 int64_t orc_map_merge(orc_map *g, const uint64_t *k, const double *d,
-                      const double *v, const uint8_t *ok, int64_t n,
-                      uint32_t frame)
+                      const double *v, const uint8_t *ok, const uint8_t *tie,
+                      int64_t n, uint32_t frame)
 {
     int64_t cap = g->n + n, i = 0, j = 0, w = 0, skipped = 0;
     uint64_t *nk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(cap + 1));
     double *nD = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
     double *nV = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
     uint32_t *ns = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(cap + 1));
+    uint8_t *nt = (uint8_t *)malloc((size_t)(cap + 1));
     while (i < g->n || j < n) {
         int use_obs;
         if (j < n && !(ok[j] && isfinite(v[j]) && v[j] > 0.0 && isfinite(d[j]))) {
@@ -776,6 +836,7 @@ int64_t orc_map_merge(orc_map *g, const uint64_t *k, const double *d,
         else use_obs = k[j] <= g->key[i];
         if (!use_obs) {
             nk[w] = g->key[i]; nD[w] = g->D[i]; nV[w] = g->V[i]; ns[w] = g->stamp[i];
+            nt[w] = g->tie[i];
             i++; w++;
         } else if (i < g->n && k[j] == g->key[i]) {
             double Vp = g->V[i], Dp = g->D[i];
@@ -783,14 +844,16 @@ int64_t orc_map_merge(orc_map *g, const uint64_t *k, const double *d,
             nD[w] = (Vp * d[j] + v[j] * Dp) / (Vp + v[j]);
             nV[w] = (Vp * v[j]) / (Vp + v[j]);
             ns[w] = frame;
+            nt[w] = (uint8_t)(g->tie[i] | (tie ? tie[j] : 0));
             i++; j++; w++;
         } else {
             nk[w] = k[j]; nD[w] = d[j]; nV[w] = v[j]; ns[w] = frame;
+            nt[w] = tie ? tie[j] : 0;
             j++; w++;
         }
     }
-    free(g->key); free(g->D); free(g->V); free(g->stamp);
-    g->key = nk; g->D = nD; g->V = nV; g->stamp = ns; g->n = w;
+    free(g->key); free(g->D); free(g->V); free(g->stamp); free(g->tie);
+    g->key = nk; g->D = nD; g->V = nV; g->stamp = ns; g->tie = nt; g->n = w;
     return skipped;
 }
 
@@ -806,13 +869,14 @@ int64_t orc_fuse(orc_map *g, const orc_model *m, const float origin[3],
     double *gr = (double *)malloc(sizeof(double) * 3 * (size_t)(n + 1));
     double *v = (double *)malloc(sizeof(double) * (size_t)(n + 1));
     uint8_t *ok = (uint8_t *)malloc((size_t)(n + 1));
+    uint8_t *tie = (uint8_t *)malloc((size_t)(n + 1));
     int64_t sk;
     orc_test_points(m, k, n);
     orc_voxel_centres(k, n, m->p.fuse_voxel, x);
-    orc_query(m, x, n, origin, d, gr, v, ok, NULL, nthreads);
-    sk = orc_map_merge(g, k, d, v, ok, n, frame);
+    orc_query(m, x, n, origin, d, gr, v, ok, NULL, tie, nthreads);
+    sk = orc_map_merge(g, k, d, v, ok, tie, n, frame);
     if (skipped) *skipped = sk;
-    free(k); free(x); free(d); free(gr); free(v); free(ok);
+    free(k); free(x); free(d); free(gr); free(v); free(ok); free(tie);
     return n;
 }
 
@@ -832,12 +896,13 @@ static int64_t orc_map_find(const orc_map *g, uint64_t key)
  * interpolant; valid only when all eight voxels exist.  (Stand-in for the
  * G-GPDF query of Sec. IV-D.) */
 void orc_query_global(const orc_map *g, double h, const float *q, int64_t nq,
-                      double *dist, double *grad, uint8_t *valid)
+                      double *dist, double *grad, uint8_t *valid, uint8_t *tie)
 {
     for (int64_t j = 0; j < nq; ++j) {
         double u[3], f[3], Dc[8];
         int64_t i0[3];
         int okq = 1;
+        if (tie) tie[j] = 0;
         for (int a = 0; a < 3; ++a) {
             if (!isfinite(q[3 * j + a])) { okq = 0; break; }
             u[a] = (double)q[3 * j + a] / h - 0.5;
@@ -849,7 +914,11 @@ void orc_query_global(const orc_map *g, double h, const float *q, int64_t nq,
             int64_t k = orc_map_find(g, orc_pack(i0[0] + ((b >> 2) & 1),
                                                  i0[1] + ((b >> 1) & 1),
                                                  i0[2] + (b & 1)));
-            if (k < 0) okq = 0; else Dc[b] = g->D[k];
+            if (k < 0) okq = 0;
+            else {
+                Dc[b] = g->D[k];
+                if (tie && g->tie[k]) tie[j] = 1;
+            }
         }
         if (!okq) {
             dist[j] = INFINITY; valid[j] = 0;

@@ -7,7 +7,10 @@ Tolerances (FP32 path against the FP64 oracle):
   variance   |v / v_o - 1| <= 2e-3 (the FP32 path sends queries whose
              estimated relative variance error exceeds 1e-3 to FP64; 2e-3
              leaves a factor 2 for the estimate)
-  validity, sign, n_local: exact
+  validity, n_local: exact
+  sign: equal except at the oracle's sign near-ties (queries whose nearest
+        training points on different sides of the surface lie within FP32
+        rounding of each other), which are counted
 FP64 path: FP64-level agreement plus the final rounding of the FP32 outputs.
 """
 import numpy as np
@@ -42,18 +45,27 @@ def gpu_query(ctx, q, origin=None):
 
 
 def compare(g, o, fp64=False, check_aux=True, label=""):
-    """Element-wise comparison; returns a dict of maximum errors."""
+    """Element-wise comparison; returns a dict of maximum errors and the sign
+    counts.  The oracle decides the sign from the exact nearest training point
+    and flags the queries whose decision an FP32 evaluation can take the other
+    way (``sign_tie``); a sign may differ only there, and the magnitude and
+    gradient are still compared with the sign aligned."""
     vg = g["valid"].astype(bool)
     vo = np.asarray(o["valid"]).astype(bool)
     assert (vg == vo).all(), f"{label}: validity differs on {(vg != vo).sum()} queries"
     v = vo
     inval = ~v
     assert np.isinf(g["dist"][inval]).all() and (g["grad"][inval] == 0).all()
-    out = dict(n=int(v.sum()))
+    out = dict(n=int(v.sum()), sign_ties=0, sign_flips=0)
     if not v.any():
         return out
-    d_err = np.abs(g["dist"][v] - o["dist"][v])
-    g_err = np.abs(g["grad"][v] - o["grad"][v]).max(1)
+    tie = np.asarray(o.get("sign_tie", np.zeros(len(vo), bool)))[v]
+    flip = np.sign(g["dist"][v]) != np.sign(o["dist"][v])
+    assert not (flip & ~tie).any(), f"{label}: sign differs on {(flip & ~tie).sum()} queries with no near-tie"
+    s = np.where(flip, -1.0, 1.0)
+    out.update(sign_ties=int(tie.sum()), sign_flips=int(flip.sum()))
+    d_err = np.abs(s * g["dist"][v] - o["dist"][v])
+    g_err = np.abs(s[:, None] * g["grad"][v] - o["grad"][v]).max(1)
     v_rel = np.abs(g["var"][v] / o["var"][v] - 1.0)
     out.update(d=float(d_err.max()), g=float(g_err.max()), v=float(v_rel.max()))
     if fp64:
@@ -68,8 +80,6 @@ def compare(g, o, fp64=False, check_aux=True, label=""):
         assert (d_err <= TOL_D).all(), (label, d_err.max())
         assert (g_err <= TOL_G).all(), (label, g_err.max())
         assert (v_rel <= TOL_V).all(), (label, v_rel.max())
-    # the sign is decided identically on both sides
-    assert (np.sign(g["dist"][v]) == np.sign(o["dist"][v])).all(), label
     if check_aux:
         assert (g["aux"][v, 2] == o["aux"][v, 2]).all(), f"{label}: n_local differs"
     return out

@@ -75,3 +75,19 @@ def test_gate():
     r = np.array([0.1, 0.2, 0.3])
     out = M.corrected(d, np.array([0.01, 0.05, 0.06]), r, gate=0.05)
     assert out.tolist() == [1.1, 2.2, 3.0]
+
+
+def test_features_hand_built_row():
+    # [d, log v, o, grad d (3), log(1 + n_local)], worked by hand:
+    # log 0.02 = log 2 - log 100 = 0.693147... - 4.605170... = -3.912023...
+    # log 38 = 3.637586...
+    f = M.features([0.3], [0.02], [0.4], [[0.1, -0.2, 0.9]], [37])
+    want = [0.3, -3.912023005428146, 0.4, 0.1, -0.2, 0.9, 3.6375861597263857]
+    assert f.shape == (1, 7)
+    assert np.abs(f[0] - want).max() < 1e-15
+    # columns follow their inputs: permuting one input permutes one column
+    g = M.features([1.0, 2.0], [1.0, math.e], [0.5, 0.25], [[1, 2, 3], [4, 5, 6]], [0, math.e - 1])
+    assert g[:, 0].tolist() == [1.0, 2.0] and g[:, 2].tolist() == [0.5, 0.25]
+    assert np.abs(g[:, 1] - [0.0, 1.0]).max() < 1e-15
+    assert g[:, 3:6].tolist() == [[1, 2, 3], [4, 5, 6]]
+    assert np.abs(g[:, 6] - [0.0, 1.0]).max() < 1e-15

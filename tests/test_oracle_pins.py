@@ -374,6 +374,40 @@ def test_smooth_min_combination_against_separately_trained_clusters():
     assert np.abs(r3["grad"] - G[np.arange(len(q)), amin]).max() < 1e-9
 
 
+def test_variance_and_aux_combination_against_separately_trained_clusters():
+    # The variance takes the distance's weights (no rule in the paper): the
+    # weighted mean of the per-cluster variances, and under the closest-node
+    # rule the variance of that node.  aux = (occupancy and latent variance of
+    # the closest node, total points over the selected clusters).
+    sc = S.sphere_scene(seed=6, n_points=200)
+    prm = O.Params(selection=1, knn_q=64, cell=0.8)
+    rng = np.random.default_rng(8)
+    q = rng.uniform(-1.3, 1.3, size=(50, 3)).astype(np.float32)
+    m, e, res = _per_cluster_results(sc.points, prm, q)
+    D = np.stack([x["dist"] for x in res], 1)
+    V = np.stack([x["var"] for x in res], 1)
+    Oc = np.stack([x["aux"][:, 0] for x in res], 1)
+    U = np.stack([x["aux"][:, 1] for x in res], 1)
+    sizes = np.diff(e["off"])
+    # the per-cluster variances differ, so a wrong weight shows
+    assert (V.max(1) / V.min(1) > 2).all()
+    w = np.exp(-100 * (D - D.min(1, keepdims=True)))
+    amin = D.argmin(1)
+    ii = np.arange(len(q))
+    for grad_mode in (0, 1):
+        r = O.Model(prm.copy(grad_mode=grad_mode), sc.points).query(q)
+        v_ref = (w * V).sum(1) / w.sum(1)
+        assert np.abs(r["var"] / v_ref - 1).max() < 1e-12
+        assert np.abs(r["aux"][:, 0] - Oc[ii, amin]).max() < 1e-15
+        assert np.abs(r["aux"][:, 1] - U[ii, amin]).max() < 1e-15
+        assert (r["aux"][:, 2] == sizes.sum()).all()
+    r3 = O.Model(prm.copy(combine=1), sc.points).query(q)
+    assert np.abs(r3["var"] / V[ii, amin] - 1).max() < 1e-12
+    assert np.abs(r3["aux"][:, 0] - Oc[ii, amin]).max() < 1e-15
+    assert np.abs(r3["aux"][:, 1] - U[ii, amin]).max() < 1e-15
+    assert (r3["aux"][:, 2] == sizes.sum()).all()
+
+
 def test_smooth_min_limits():
     sc = S.sphere_scene(seed=8)
     prm = O.Params()
@@ -457,6 +491,57 @@ def test_sign_from_sensor_origin():
     assert (np.sign(r["dist"][v]) == np.where(rad[v] < 1, 1, -1)).all()
     un = m.query(q)
     assert np.allclose(np.abs(r["dist"][v]), un["dist"][v])
+
+
+def test_sign_follows_brute_force_nearest_point():
+    # the sensor side of the exact nearest training point: a kd-tree nearest
+    # neighbour over the whole cloud (one cluster) and the side product in
+    # numpy give the sign wherever the oracle reports no near-tie
+    sc = S.sphere_scene(seed=18, n_points=1500)
+    pts = (sc.points * np.float32(0.3) + np.float32(5.0)).astype(np.float32)
+    m = O.Model(O.Params(cell=100.0), pts)
+    assert m.nclusters == 1
+    rng = np.random.default_rng(19)
+    q = (5.0 + rng.uniform(-0.45, 0.45, size=(4000, 3))).astype(np.float32)
+    origin = np.array([5.1, 4.9, 5.05], np.float32)
+    r = m.query(q, origin=origin)
+    _, nn = cKDTree(pts.astype(np.float64)).query(q.astype(np.float64))
+    p = pts[nn].astype(np.float64)
+    side = np.einsum("ij,ij->i", q.astype(np.float64) - p, origin.astype(np.float64) - p)
+    want = np.where(side >= 0, 1.0, -1.0)
+    t = r["sign_tie"]
+    assert t.mean() < 0.01
+    assert (np.sign(r["dist"][~t]) == want[~t]).all()
+    assert not m.query(q)["sign_tie"].any()   # unsigned: no sign decision
+
+
+def test_sign_tie_break_and_flag():
+    # dyadic coordinates: both points at exactly the same distance from the
+    # query, on opposite sides as seen from the origin.  The first in cluster
+    # key order (then member order) decides, and the query is flagged.
+    x = np.array([[2.0, 2.0, 2.0]], np.float32)
+    a = np.array([2.25, 2.0, 2.0], np.float32)    # origin side of the query
+    b = np.array([1.75, 2.0, 2.0], np.float32)    # far side
+    o = np.array([4.0, 2.0, 2.0], np.float32)
+    for first, second, sign in ((a, b, -1.0), (b, a, 1.0)):
+        m = O.Model(O.Params(cell=100.0), np.stack([first, second]))
+        r = m.query(x, origin=o)
+        # side of the first point: (x - first).(o - first)
+        assert np.sign(r["dist"][0]) == sign and r["sign_tie"][0]
+    # different clusters: the smaller cluster key wins whatever the order
+    m = O.Model(O.Params(cell=2.0), np.stack([a, b]))   # b in cell 0, a in cell 1
+    assert m.nclusters == 2
+    r = m.query(x, origin=o)
+    assert np.sign(r["dist"][0]) == 1.0 and r["sign_tie"][0]
+    # equidistant on the same side: no near-tie
+    c = np.array([2.0, 2.25, 2.0], np.float32)
+    m = O.Model(O.Params(cell=100.0), np.stack([a, c]))
+    r = m.query(x, origin=np.array([4.0, 4.0, 2.0], np.float32))
+    assert np.sign(r["dist"][0]) == -1.0 and not r["sign_tie"][0]
+    # a unique nearest point well off the tie: no flag
+    m = O.Model(O.Params(cell=100.0), np.stack([a, np.array([1.5, 2.0, 2.0], np.float32)]))
+    r = m.query(x, origin=o)
+    assert np.sign(r["dist"][0]) == -1.0 and not r["sign_tie"][0]
 
 
 # ----------------------------------------------------------------------------
