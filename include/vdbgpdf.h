@@ -74,8 +74,10 @@ enum { GPDF_COMB_SMOOTHMIN = 0, GPDF_COMB_HARDMIN = 1 };
  * gradients ("directly average", Sec. IV-D) */
 enum { GPDF_GRAD_WEIGHTED = 0, GPDF_GRAD_PAPER_MEAN = 1 };
 /* query arithmetic: FP32 with an FP64 re-evaluation of the queries whose FP32
- * error bound exceeds the tolerance; everything in FP64; or FP32 kernel values
- * with the variance product on BF16 MFMA */
+ * error bound exceeds the tolerance; everything in FP64; or the FP32 path with
+ * the variance product W k on BF16 MFMA (FP32 accumulation), whose queries are
+ * re-evaluated in FP64 for distance and gradient but not for the variance,
+ * which keeps the BF16 error */
 enum { GPDF_PREC_FP32 = 0, GPDF_PREC_BF16 = 1, GPDF_PREC_FP64 = 2 };
 
 typedef struct {

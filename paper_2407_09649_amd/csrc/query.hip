@@ -1281,22 +1281,24 @@ void launch_refine_pairs(unsigned grid, hipStream_t s, const float *q, const Gro
 }
 
 // ---------------------------------------------------------------------------
-// BF16 precision: the kernel-vector product o = k . alpha and the variance
-// product W k of a 64-query chunk and one cluster run on MFMA
-// (v_mfma_f32_16x16x32_bf16, FP32 accumulation) as C = [W; alpha^T] K^T.
-// Kernel values, the gradient sum, reverting and the combination stay FP32.
+// BF16 precision: the variance product W k of a 64-query chunk and one
+// cluster runs on MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation) as
+// C = W K^T.  Kernel values, the occupancy o = k . alpha and its gradient sum,
+// reverting and the combination stay FP32: o is an O(n) sum beside the kernel
+// values, and near the surface the reverting scale 1/t (Eq. (3)-(5)) turns a
+// BF16 error in o into a gradient wrong by tens of times.
 // Lane layout of the 16x16x32 MFMA (lane l, lr = l % 16, lg = l / 16):
 //   A[m][k] lane m + 16 (k / 8), element k % 8; B[k][n] lane n + 16 (k / 8),
 //   element k % 8; D[m][n] lane n + 16 (m / 4), element m % 4.
-// [W; alpha] is kept per cluster in BF16, row-major, rows padded to 16 and
-// columns to 32: row i < n is row i of W (zero above the diagonal), row n is
-// alpha.  Clusters above kBfMaxN points use the FP32 path.
+// W is kept per cluster in BF16, row-major, rows padded to 16 and columns to
+// 32 (zero above the diagonal).  Clusters above kBfMaxN points use the FP32
+// path.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBfMaxN = 256;
 
-__host__ __device__ inline int bf_rows(int n) { return (n + 1 + 15) & ~15; }
+__host__ __device__ inline int bf_rows(int n) { return (n + 15) & ~15; }
 __host__ __device__ inline int bf_cols(int n) { return (n + 31) & ~31; }
 
 // index of W(i, j), j <= i, in the FP32 query layout
@@ -1306,7 +1308,7 @@ __device__ inline int64_t w_index(int n, int i, int j) {
     return w32_panel_offset(n, r) + int64_t(j) * kPanel + (i - r * kPanel);
 }
 
-// one workgroup per cluster: BF16 [W; alpha] from the FP32 factor
+// one workgroup per cluster: BF16 W from the FP32 factor
 __global__ void k_pack_bf16(const int32_t *__restrict__ coff, const int64_t *__restrict__ woff,
                             const int64_t *__restrict__ bfoff, const uint8_t *__restrict__ pd,
                             const float *__restrict__ W32, const float4 *__restrict__ pts,
@@ -1321,28 +1323,32 @@ __global__ void k_pack_bf16(const int32_t *__restrict__ coff, const int64_t *__r
         const int i = idx / cols, j = idx - i * cols;
         float v = 0.f;
         if (i < n && j <= i) v = W[w_index(n, i, j)];
-        else if (i == n && j < n) v = pts[base + j].w;
         Mc[idx] = (__bf16)v;
     }
 }
 
-// one point of the BF16 path: kernel value (returned), gradient sum and the
-// nearest-point decision, FP32
+// one point of the BF16 path: kernel value (returned), occupancy and gradient
+// sums and the nearest-point decision, FP32
 template <int KERN>
 __device__ __forceinline__ float point_eval_b(const float4 p, const QueryPoint &Q, int gidx,
                                               const QueryConsts &C, PairRaw<float> &r, Acc<float> &A) {
     const float dx = Q.fx - p.x, dy = Q.fy - p.y, dz = Q.fz - p.z;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     if (r2 < A.best) { A.best = r2; A.bidx = gidx; }
-    float k, e;
+    float k, e, t;
     if (kern_kind(KERN) == GPDF_KERNEL_MATERN32) {
-        const float t = fsqrt(r2) * C.a;
+        t = fsqrt(r2) * C.a;
         e = fexp2(-t * kLog2e);
         k = fmaf(t, e, e);
     } else {
-        k = fexp2(-(r2 * C.a) * kLog2e);
+        t = r2 * C.a;
+        k = fexp2(-t * kLog2e);
         e = k;
     }
+    r.o = fmaf(p.w, k, r.o);
+    // error scale of the term alpha k, as in the FP32 path
+    const float akt = fabsf(p.w) * fmaf(k, t, k);
+    r.S = fmaf(akt, akt, r.S);
     const float cg = p.w * e;
     r.gx = fmaf(cg, dx, r.gx);
     r.gy = fmaf(cg, dy, r.gy);
@@ -1360,7 +1366,7 @@ __device__ void eval_cluster_bf16(int base, int n, int64_t bfo, const float4 *__
                                   const QueryPoint &Q, const QueryConsts &C, Acc<float> &A) {
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     PairRaw<float> r{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const int cols = bf_cols(n), rows = n + 1;
+    const int cols = bf_cols(n), rows = n;
     const float4 *P = pts + base;
     // this lane's kernel vector, BF16, as row `lane` of K (LDS)
     __bf16 *kr = Kt + lane * kts;
@@ -1371,16 +1377,15 @@ __device__ void eval_cluster_bf16(int base, int n, int64_t bfo, const float4 *__
     }
     __syncthreads();
     const __bf16 *M = Mall + bfo;
-    float ssp[4] = {0.f, 0.f, 0.f, 0.f}, op[4] = {0.f, 0.f, 0.f, 0.f};
+    float ssp[4] = {0.f, 0.f, 0.f, 0.f};
     for (int p0 = 0; p0 < rows; p0 += 64) {
         f32x4 acc[4][4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // columns this panel needs: up to its last W row, all of them when it
-        // holds the alpha row
-        const int kend = (p0 + 64 > n) ? cols : min(cols, (p0 + 64 + 31) & ~31);
+        // columns this panel needs: up to its last W row
+        const int kend = min(cols, (p0 + 64 + 31) & ~31);
         for (int k0 = 0; k0 < kend; k0 += 32) {
             bf16x8 b[4];
 #pragma unroll
@@ -1391,7 +1396,7 @@ __device__ void eval_cluster_bf16(int base, int n, int64_t bfo, const float4 *__
                 const int row0 = p0 + 16 * mt;
                 if (row0 >= rows) break;
                 // blocks above the diagonal of W are zero
-                if (row0 + 15 < n && k0 > row0 + 15) continue;
+                if (k0 > row0 + 15) continue;
                 const bf16x8 a = *reinterpret_cast<const bf16x8 *>(M + int64_t(row0 + lr) * cols + k0 + 8 * lg);
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
@@ -1407,19 +1412,15 @@ __device__ void eval_cluster_bf16(int base, int n, int64_t bfo, const float4 *__
                     const int i = p0 + 16 * mt + 4 * lg + e;
                     const float v = acc[mt][nt][e];
                     if (i < n) ssp[nt] = fmaf(v, v, ssp[nt]);
-                    else if (i == n) op[nt] += v;
                 }
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         ssp[nt] += __shfl_xor(ssp[nt], 16, 64);
         ssp[nt] += __shfl_xor(ssp[nt], 32, 64);
-        op[nt] += __shfl_xor(op[nt], 16, 64);
-        op[nt] += __shfl_xor(op[nt], 32, 64);
     }
     // query of this lane: column lr of tile lg
     r.ss = pick4(ssp, lg);
-    r.o = pick4(op, lg);
     __syncthreads();  // K is rewritten by the next cluster
     finish_pair<float, KERN>(r, n, C, A);
 }
@@ -1857,24 +1858,27 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         stage_begin(c, GPDF_MS_EVAL);
         launch_query_k<double>(c, kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O, 0);
         stage_end(c, GPDF_MS_EVAL);
-    } else if (c->p.precision == GPDF_PREC_BF16) {
-        // MFMA products in BF16; no FP64 re-evaluation (the error is the point)
-        const gpdf_status st = build_bf16(c);
-        if (st != GPDF_OK) return st;
-        const int kts = bf_cols(int(std::min<int64_t>(M.max_n, kBfMaxN))) + 8;
-        const size_t lds = size_t(64) * kts * sizeof(__bf16);
-        Outputs Ob = O;
-        Ob.refine = nullptr;
-        const __bf16 *Mbf = static_cast<const __bf16 *>(c->d_bfM);
-        stage_begin(c, GPDF_MS_EVAL);
-        if (kern == GPDF_KERNEL_MATERN32)
-            launch_bf16_m<GPDF_KERNEL_MATERN32>(grid, lds, s, d_q, G, c->d_cell_list, Mo, Mbf, c->d_bfoff, kts, C, Ob);
-        else
-            launch_bf16_m<GPDF_KERNEL_SE>(grid, lds, s, d_q, G, c->d_cell_list, Mo, Mbf, c->d_bfoff, kts, C, Ob);
-        stage_end(c, GPDF_MS_EVAL);
     } else {
         stage_begin(c, GPDF_MS_EVAL);
-        launch_query_k<float>(c, kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O, 0);
+        if (c->p.precision == GPDF_PREC_BF16) {
+            // the variance product on BF16 MFMA; distance and gradient keep
+            // the FP32 path's error estimate and FP64 re-evaluation, the
+            // variance keeps its BF16 error (never refined for)
+            const gpdf_status st = build_bf16(c);
+            if (st != GPDF_OK) return st;
+            const int kts = bf_cols(int(std::min<int64_t>(M.max_n, kBfMaxN))) + 8;
+            const size_t lds = size_t(64) * kts * sizeof(__bf16);
+            QueryConsts Cb = C;
+            Cb.tau_v = INFINITY;
+            const __bf16 *Mbf = static_cast<const __bf16 *>(c->d_bfM);
+            if (kern == GPDF_KERNEL_MATERN32)
+                launch_bf16_m<GPDF_KERNEL_MATERN32>(grid, lds, s, d_q, G, c->d_cell_list, Mo, Mbf, c->d_bfoff, kts, Cb,
+                                                    O);
+            else
+                launch_bf16_m<GPDF_KERNEL_SE>(grid, lds, s, d_q, G, c->d_cell_list, Mo, Mbf, c->d_bfoff, kts, Cb, O);
+        } else {
+            launch_query_k<float>(c, kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O, 0);
+        }
         stage_end(c, GPDF_MS_EVAL);
         // 3. queries whose FP32 estimate is too large: regroup by cell
         //    (counting sort of the records) and redo them in FP64

@@ -1,15 +1,17 @@
-"""GPU checks of the BF16 precision mode: the kernel-vector product k . alpha
-and the variance product W k run on BF16 MFMA with FP32 accumulation, and
-everything else stays FP32.
+"""GPU checks of the BF16 precision mode: the variance product W k runs on
+BF16 MFMA with FP32 accumulation; the occupancy k . alpha, its gradient sum,
+reverting and the combination stay FP32, with the FP32 path's error estimate
+and FP64 re-evaluation of distance and gradient.
 
-BF16 is not expected to meet 1e-4 m.  The relative error of a BF16 operand
-is 2^-9, so the latent occupancy carries an error of about
-2^-9 sum |alpha_i k_i|.  These tests therefore check:
-  - what the precision cannot change: validity, and the sign away from the
-    surface;
-  - error bands wide enough for BF16 and far below what a wrong MFMA lane
-    layout or a wrong tile gives (errors of decimetres to metres).
-They print the error statistics that the benchmark reports.
+Stated per result:
+  distance, gradient   the FP32 path's tolerances (1e-4 m, 1e-3)
+  variance             BF16 error.  The relative error of a BF16 operand is
+                       2^-9, so u = 1 - |W k|^2 carries about 2^-8 |W k|^2;
+                       relative to u that is small where u is near 1 (far
+                       from the data) and unbounded where |W k|^2 cancels
+                       toward 1 (at the data).  The tests bound it on queries
+                       with u >= 0.5 and report the rest.
+  validity, sign       as the FP32 path
 """
 import numpy as np
 import pytest
@@ -42,23 +44,38 @@ def _stats(g, ref):
     return dict(median=float(np.median(e)), p99=float(np.quantile(e, 0.99)), max=float(e.max()))
 
 
-def _check(g32, g16, ref, med, p99, label):
+def _check(g32, g16, ref, label):
     v = ref["valid"]
     assert np.array_equal(g16["valid"].astype(bool), v), label
     assert np.array_equal(g32["valid"].astype(bool), v), label
-    s16, s32 = _stats(g16, ref), _stats(g32, ref)
-    print(label, "BF16", s16, "FP32", s32)
-    assert s32["max"] <= 1e-4
-    assert s16["median"] <= med and s16["p99"] <= p99, (label, s16)
-    far = v & (np.abs(ref["dist"]) > 0.05)
-    assert np.array_equal(np.sign(g16["dist"][far]), np.sign(ref["dist"][far])), label
+    # distance and gradient: FP32 with FP64 re-evaluation on both paths
+    for name, g in (("FP32", g32), ("BF16", g16)):
+        tie = ref["sign_tie"][v]
+        flip = np.sign(g["dist"][v]) != np.sign(ref["dist"][v])
+        assert not (flip & ~tie).any(), (label, name)
+        sg = np.where(flip, -1.0, 1.0)
+        de = np.abs(sg * g["dist"][v] - ref["dist"][v])
+        ge = np.abs(sg[:, None] * g["grad"][v] - ref["grad"][v]).max(1)
+        print(label, name, "dist max", de.max(), "grad max", ge.max())
+        assert de.max() <= 1e-4 and ge.max() <= 1e-3, (label, name, de.max(), ge.max())
+    # variance: BF16 error, bounded where the latent variance is not small
+    u = ref["aux"][v, 1]
+    rel = np.abs(g16["var"][v] / ref["var"][v] - 1)
+    far = u >= 0.5
+    print(label, "BF16 variance rel. error: u>=0.5 median", np.median(rel[far]), "p99",
+          np.quantile(rel[far], 0.99), "max", rel[far].max(), "| u<0.5 median", np.median(rel[~far]),
+          "max", rel[~far].max(), "n", int(far.sum()), int((~far).sum()))
+    assert far.sum() > 100
+    assert np.median(rel[far]) <= 2e-3 and np.quantile(rel[far], 0.99) <= 2e-2 and rel[far].max() <= 0.1, label
+    rel32 = np.abs(g32["var"][v] / ref["var"][v] - 1)
+    assert rel32.max() <= 2e-3, label
 
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_bf16_sphere(dev, seed):
     sc = S.sphere_scene(seed)
     g32, g16, ref = _run(dev, sc.points, sc.queries, cluster_size=0.4)
-    _check(g32, g16, ref, 3e-3, 3e-2, f"sphere{seed}")
+    _check(g32, g16, ref, f"sphere{seed}")
 
 
 def test_bf16_lidar(dev):
@@ -68,7 +85,7 @@ def test_bf16_lidar(dev):
     q = q[np.random.default_rng(0).choice(len(q), 30000, replace=False)]
     origin = np.array([0.0, 0.0, 1.5], np.float32)
     g32, g16, ref = _run(dev, pts, q, origin=origin, voxel_size=0.1)
-    _check(g32, g16, ref, 3e-3, 3e-2, "lidar")
+    _check(g32, g16, ref, "lidar")
 
 
 def test_bf16_uneven_patches(dev):
@@ -77,4 +94,4 @@ def test_bf16_uneven_patches(dev):
     ps = S.planar_patches(3, n_patches=96, grid=(4, 4, 6))
     q = ps.queries
     g32, g16, ref = _run(dev, ps.points, q, cluster_size=0.8, max_factor_elems=1 << 24)
-    _check(g32, g16, ref, 5e-3, 5e-2, "patches")
+    _check(g32, g16, ref, "patches")

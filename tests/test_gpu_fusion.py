@@ -39,31 +39,79 @@ def _fuse_both(dev, frames, path, **kw):
     return ctx, omap
 
 
-def test_fusion_three_frames_parity(dev):
-    path, frames = _frames(4, 3)
-    ctx, omap = _fuse_both(dev, frames, path)
-    g = ctx.export_global()
-    o = omap.export()
-    assert np.array_equal(g["key"], o["key"]), "fused voxel sets differ"
-    assert np.array_equal(g["stamp"], o["stamp"])
-    assert np.abs(g["D"] - o["D"]).max() <= TOL_D
-    assert np.abs(g["V"] / o["V"] - 1).max() <= 2e-3
-    st = ctx.stats()
-    assert st["global_voxels"] == len(o["key"])
-    # the global query: trilinear interpolation of the fused field
-    rng = np.random.default_rng(0)
-    keys = o["key"][rng.choice(len(o["key"]), 20000)]
+def _keys_to_centres(keys, h, rng):
     c = np.stack([(keys >> np.uint64(42)) & np.uint64(0x1FFFFF), (keys >> np.uint64(21)) & np.uint64(0x1FFFFF),
                   keys & np.uint64(0x1FFFFF)], 1).astype(np.int64) - (1 << 20)
-    q = ((c + 0.5 + rng.uniform(-0.5, 0.5, size=c.shape)) * 0.05).astype(np.float32)
+    return ((c + 0.5 + rng.uniform(-0.5, 0.5, size=c.shape)) * h).astype(np.float32)
+
+
+def check_grid(ctx, omap, label, max_tie_frac=0.05):
+    """The fused grid against the oracle's: keys and stamps exact; V within
+    2e-3 relative everywhere; D within 1e-4 m except at voxels where some
+    fused observation had a sign near-tie (counted, a small fraction)."""
+    g = ctx.export_global()
+    o = omap.export()
+    assert np.array_equal(g["key"], o["key"]), f"{label}: fused voxel sets differ"
+    assert np.array_equal(g["stamp"], o["stamp"]), label
+    t = o["sign_tie"]
+    assert t.mean() <= max_tie_frac, (label, t.mean())
+    assert np.abs(g["D"][~t] - o["D"][~t]).max() <= TOL_D, label
+    assert np.abs(g["V"] / o["V"] - 1).max() <= 2e-3, label
+    assert ctx.stats()["global_voxels"] == len(o["key"])
+    return g, o
+
+
+def check_global(ctx, omap, q, dev, label, min_valid=0.0):
     r = ctx.query_global(torch.from_numpy(q).to(dev))
     gd = {k: v.cpu().numpy() for k, v in r.items()}
     ro = omap.query(0.05, q)
-    assert (gd["valid"].astype(bool) == ro["valid"]).all()
+    assert (gd["valid"].astype(bool) == ro["valid"]).all(), label
     v = ro["valid"]
-    assert v.mean() > 0.5
-    assert np.abs(gd["dist"][v] - ro["dist"][v]).max() <= TOL_D
-    assert np.abs(gd["grad"][v] - ro["grad"][v]).max() <= TOL_G
+    assert v.mean() >= min_valid, (label, v.mean())
+    c = v & ~ro["sign_tie"]
+    assert np.isinf(gd["dist"][~v]).all() and (gd["grad"][~v] == 0).all()
+    if c.any():
+        assert np.abs(gd["dist"][c] - ro["dist"][c]).max() <= TOL_D, label
+        assert np.abs(gd["grad"][c] - ro["grad"][c]).max() <= TOL_G, label
+    return v.mean()
+
+
+def test_fusion_three_frames_parity(dev):
+    path, frames = _frames(4, 3)
+    ctx, omap = _fuse_both(dev, frames, path)
+    _, o = check_grid(ctx, omap, "three frames")
+    # the global query: trilinear interpolation of the fused field
+    rng = np.random.default_rng(0)
+    q = _keys_to_centres(o["key"][rng.choice(len(o["key"]), 20000)], 0.05, rng)
+    check_global(ctx, omap, q, dev, "observed voxels", min_valid=0.5)
+    # uniform points in the scene volume: mostly outside the fused band
+    qu = rng.uniform([-20, -20, -1], [20, 20, 5], size=(20000, 3)).astype(np.float32)
+    check_global(ctx, omap, qu, dev, "uniform")
+    ctx.close()
+
+
+def test_fusion_full_resolution_sequence_parity(dev):
+    """Ten 64 x 1024 frames of the moving-sensor sequence (the benchmark's
+    fusion workload) fused on the GPU and by the oracle: the grid after the
+    last frame and global queries at observed voxels and uniform points."""
+    path, frames = _frames(4, 10, beams=64, az=1024)
+    p = small_params(voxel_size=0.1, max_points=1 << 17, max_queries=3_600_000,
+                     global_capacity=1 << 25)
+    ctx = P.Context(p, device=dev)
+    omap = O.Map()
+    for i, (pts, o) in enumerate(zip(frames, path)):
+        o32 = np.asarray(o, np.float32)
+        ctx.fuse(torch.from_numpy(pts).to(dev), o32)
+        n, _ = omap.fuse(O.Model(oracle_params(p), pts), o32, i)
+        assert ctx.stats()["test_points"] == n, i
+        print(f"frame {i}: {n} test voxels", flush=True)
+    torch.cuda.synchronize()
+    _, o = check_grid(ctx, omap, "ten frames")
+    rng = np.random.default_rng(1)
+    q = _keys_to_centres(o["key"][rng.choice(len(o["key"]), 200000)], 0.05, rng)
+    check_global(ctx, omap, q, dev, "observed voxels", min_valid=0.5)
+    qu = rng.uniform([-20, -20, -1], [20, 20, 5], size=(200000, 3)).astype(np.float32)
+    check_global(ctx, omap, qu, dev, "uniform")
     ctx.close()
 
 

@@ -139,3 +139,23 @@ def test_trained_correction_gains_on_held_out_scene(dev):
     np.testing.assert_allclose(dc[g], d[g] + r[g], atol=1e-5)
     np.testing.assert_array_equal(dc[ok & ~g], d[ok & ~g])
     assert ctx.stats()["gated"] == int((res["valid"].cpu().numpy().astype(bool) & (var <= gate)).sum())
+
+
+def test_features_match_oracle(dev):
+    """gpdf_mlp_features on the outputs of a GP query, element by element
+    against oracle.mlp.features on the same (FP32) outputs: the inputs pass
+    through unchanged, the two logarithms within FP32 rounding."""
+    sc = S.sphere_scene(10000)
+    q = S.sphere_eval_queries(20000, 5000)
+    with _ctx(dev, selection=P.SEL_KNN, knn_q=8) as ctx:
+        ctx.train(torch.from_numpy(sc.points).to(dev))
+        r = ctx.query(torch.from_numpy(q).to(dev))
+        f = ctx.mlp_features(r).cpu().numpy().astype(np.float64)
+        h = {k: v.cpu().numpy() for k, v in r.items()}
+    v = h["valid"].astype(bool)
+    assert v.all()
+    fo = OM.features(h["dist"], h["var"], h["aux"][:, 0], h["grad"], h["aux"][:, 2])
+    for k in (0, 2, 3, 4, 5):
+        assert np.array_equal(f[:, k], fo[:, k]), k
+    for k in (1, 6):
+        assert (np.abs(f[:, k] - fo[:, k]) <= 5e-7 * np.abs(fo[:, k]) + 1e-12).all(), k

@@ -259,3 +259,46 @@ def test_nearest_distance_brute_force(dev):
         d = d.cpu().numpy()
     ref = O.nearest_distance(p, q)
     assert np.abs(d - ref).max() <= 1e-6 * max(1.0, ref.max())
+
+
+def _adversarial_coords(h):
+    """FP32 values on and next to cell boundaries: exact multiples of h, their
+    FP32 neighbours, signed zeros, tiny values and the ends of the 21-bit key
+    range (+-2^20 cells)."""
+    lim = np.float32((1 << 20) * h)
+    base = [0.0, -0.0, h, -h, 3 * h, -3 * h, 1.0, -1.0, 12.3, -12.3, 1e-30, -1e-30,
+            0.2999999, 0.7, float(lim) * 0.5, -float(lim) * 0.5, float(lim), -float(lim),
+            float(np.nextafter(lim, np.float32(0))), float(np.nextafter(-lim, np.float32(0)))]
+    vals = []
+    for b in base:
+        f = np.float32(b)
+        vals += [f, np.nextafter(f, np.float32(np.inf)), np.nextafter(f, np.float32(-np.inf))]
+    vals += [np.float32(k * h) for k in range(-50, 51, 7)]
+    return np.array(vals, np.float32)
+
+
+@pytest.mark.parametrize("mode", ["voxel", "raw"])
+def test_adversarial_keys_bitwise(dev, mode):
+    """Keys, voxel centres, cluster membership and the per-query cell
+    selection on coordinates chosen to break a wrong floor, a wrong rounding
+    or a wrong range check: the exported model equals the oracle's bit for
+    bit, the same points are skipped, and the queries see the same clusters."""
+    kw = dict(voxel_size=0.1) if mode == "voxel" else dict(cluster_size=0.4)
+    h = 0.1 if mode == "voxel" else 0.4
+    v = _adversarial_coords(h)
+    pts = np.stack([v, v[::-1], np.roll(v, 3)], axis=1)
+    pts = np.concatenate([pts, pts[:, [1, 2, 0]], pts[:, [2, 0, 1]]]).astype(np.float32)
+    q = np.concatenate([pts, pts + np.float32(h / 3)]).astype(np.float32)
+    with _ctx(dev, **kw) as ctx:
+        _train(ctx, pts)
+        st = ctx.stats()
+        om = O.Model(oracle_params(ctx.params), pts)
+        export_equal(ctx, om)
+        g = gpu_query(ctx, q)
+    assert st["skipped_points"] == om.skipped > 0
+    assert st["points"] == om.npoints and st["clusters"] == om.nclusters
+    ref = om.query(q)
+    assert np.array_equal(g["valid"].astype(bool), ref["valid"])
+    v = ref["valid"]
+    assert v.sum() > 0
+    assert np.array_equal(g["aux"][v, 2], ref["aux"][v, 2])
