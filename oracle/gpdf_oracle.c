@@ -454,11 +454,17 @@ static int orc_select(const orc_model *m, const float *x, int64_t *sel)
     int ns = 0;
     if (!orc_cell_of(p, x, c)) return 0;
     if (p->selection == 0) {
-        /* the cell of the query and its 26 neighbours, ascending key */
+        /* the cell of the query and its 26 neighbours, ascending key; a
+         * neighbour outside the key range holds no cluster (and has no key) */
         for (int dx = -1; dx <= 1; ++dx)
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dz = -1; dz <= 1; ++dz) {
-                    int64_t k = orc_find(m, orc_pack(c[0] + dx, c[1] + dy, c[2] + dz));
+                    int64_t n3[3] = {c[0] + dx, c[1] + dy, c[2] + dz}, k;
+                    int inr = 1;
+                    for (int a = 0; a < 3; ++a)
+                        if (n3[a] < -ORC_KEY_BIAS || n3[a] >= ORC_KEY_BIAS) inr = 0;
+                    if (!inr) continue;
+                    k = orc_find(m, orc_pack(n3[0], n3[1], n3[2]));
                     if (k >= 0 && m->pd[k] && m->off[k + 1] > m->off[k]) sel[ns++] = k;
                 }
         return ns;

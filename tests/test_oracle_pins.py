@@ -433,6 +433,23 @@ def test_neighbour27_selection_brute_force():
     assert (r["aux"][r["valid"], 2] == n_local[r["valid"]]).all()
 
 
+def test_neighbours_outside_the_key_range_hold_no_cluster():
+    # A query in the last cell of the key range (z cell 2^20 - 1) has its
+    # z + 1 neighbours outside the range.  Packed as 21-bit fields, cell
+    # (0, 0, 2^20) would carry into y and read as cell (0, 1, -2^20), where a
+    # training point sits; that cluster is not a neighbour.
+    h = 0.4
+    q = np.array([[0.2, 0.2, 419430.2], [0.2, 0.6, -419430.2]], np.float32)
+    p = np.array([[0.2, 0.6, -419430.2]], np.float32)
+    k, ok = O.keys(np.concatenate([q[:1], p]), h)
+    assert ok.all()
+    assert int(k[0]) == _pack([0, 0, (1 << 20) - 1]) and int(k[1]) == _pack([0, 1, -(1 << 20)])
+    m = O.Model(O.Params(cell=h), p)
+    r = m.query(q)
+    assert not r["valid"][0]          # no genuine neighbour cluster
+    assert r["valid"][1]              # the point's own cell sees it
+
+
 def test_knn_selects_nearest_cell_centres():
     sc = S.sphere_scene(seed=10, n_points=600, n_queries=200)
     prm = O.Params(selection=1, knn_q=3, cell=0.4)
