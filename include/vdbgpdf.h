@@ -198,6 +198,27 @@ gpdf_status gpdf_query_distance(gpdf_ctx *ctx, const float *d_q, int64_t m,
                                 float *d_grad, float *d_var, uint8_t *d_valid,
                                 float *d_aux, int32_t correct);
 
+/* gpdf_query_distance for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation, arguments and results, and no hipMalloc,
+ * hipFree or other allocating call.  gpdf_query_distance keeps its per-cell
+ * cluster lists in a context buffer that it grows when a call meets more
+ * cells than before; this variant uses a fixed array in device memory
+ * instead, 28 MiB per GPU (one copy per GPU that the library runs on, held
+ * until the process ends), holding the lists of at most 65,536 query cells
+ * (cells of the cluster grid that hold at least one query).
+ * Every call of this function on a GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (other contexts, other streams) race and must
+ * be serialised by the caller.  Each call rebuilds the lists it reads, so no
+ * contents carry over between calls.
+ * Errors: as gpdf_query_distance; GPDF_E_CAPACITY when the queries fall in
+ * more than 65,536 cells (nothing is evaluated); GPDF_E_INVALID_ARG for a
+ * context with BF16 precision (its factor copy is built on first use). */
+gpdf_status gpdf_query_distance_noalloc(gpdf_ctx *ctx, const float *d_q, int64_t m,
+                                        const float *h_origin, float *d_dist,
+                                        float *d_grad, float *d_var, uint8_t *d_valid,
+                                        float *d_aux, int32_t correct);
+
 /* One frame of fusion (Sec. IV-B, IV-C): train on d_xyz [n][3] (or, with
  * d_xyz == NULL, reuse the current local GPs), generate the test voxels of
  * the global grid within fuse_band of the training points, query them signed

@@ -38,7 +38,7 @@ EXPORTS = [
     "gpdf_nearest_distance", "gpdf_mlp_init", "gpdf_mlp_set_weights",
     "gpdf_set_tuning", "gpdf_get_tuning", "gpdf_autotune", "gpdf_fuse_frame_graph",
     "gpdf_mlp_get_weights", "gpdf_mlp_set_norm", "gpdf_mlp_get_norm", "gpdf_mlp_features",
-    "gpdf_mlp_forward", "gpdf_mlp_grad", "gpdf_mlp_train",
+    "gpdf_mlp_forward", "gpdf_mlp_grad", "gpdf_mlp_train", "gpdf_query_distance_noalloc",
 ]
 
 
@@ -118,6 +118,7 @@ def _bind(L):
         "gpdf_create": [P, P, P],
         "gpdf_train_local_gps": [P, P, I64],
         "gpdf_query_distance": [P, P, I64, P, P, P, P, P, P, C.c_int32],
+        "gpdf_query_distance_noalloc": [P, P, I64, P, P, P, P, P, P, C.c_int32],
         "gpdf_fuse_frame": [P, P, I64, P],
         "gpdf_query_global": [P, P, I64, P, P, P],
         "gpdf_get_stats": [P, P],
@@ -248,6 +249,18 @@ class Context:
         if aux:
             r["aux"] = a
         return r
+
+    def query_noalloc(self, q, out, origin=None, correct=False):
+        """gpdf_query_distance_noalloc: the query into caller-provided
+        buffers (``out``: dist, valid and optionally grad, var, aux), with no
+        device allocation in the library."""
+        torch = self._torch
+        m = q.shape[0]
+        _check(self.lib.gpdf_query_distance_noalloc(
+            self._h, _dptr(q, torch.float32, 3) if m else None, m, _host3(origin),
+            _dptr(out["dist"]), _dptr(out.get("grad")), _dptr(out.get("var")), _dptr(out["valid"]),
+            _dptr(out.get("aux")), int(bool(correct))), self._h)
+        return out
 
     def fuse(self, xyz, origin):
         torch = self._torch

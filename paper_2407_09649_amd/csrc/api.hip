@@ -193,6 +193,12 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
         delete c;
         return e == hipErrorOutOfMemory ? GPDF_E_OOM : GPDF_E_HIP;
     }
+    // this device's fixed scratch of gpdf_query_distance_noalloc
+    if (scratch_setup(c) != GPDF_OK) {
+        release(c);
+        delete c;
+        return GPDF_E_HIP;
+    }
     fill_u64(c->d_stat, 0ull, ST_COUNT, c->stream);
     fill_u64(c->d_spread, 0ull, int64_t(kSpread) * kSpreadStride, c->stream);
     // finite contents everywhere, pads included (masked FP32 rows read them)
@@ -238,6 +244,18 @@ extern "C" gpdf_status gpdf_query_distance(gpdf_ctx *c, const float *d_q, int64_
         return query(c, d_q, m, h_origin, d_dist, d_grad, d_var, d_valid, d_aux, correct);
     } catch (...) {
         return fail(c, GPDF_E_OOM, "query: host allocation failed");
+    }
+}
+
+extern "C" gpdf_status gpdf_query_distance_noalloc(gpdf_ctx *c, const float *d_q, int64_t m,
+                                                   const float *h_origin, float *d_dist, float *d_grad,
+                                                   float *d_var, uint8_t *d_valid, float *d_aux,
+                                                   int32_t correct) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    try {
+        return query(c, d_q, m, h_origin, d_dist, d_grad, d_var, d_valid, d_aux, correct, nullptr, nullptr, true);
+    } catch (...) {
+        return fail(c, GPDF_E_OOM, "query_distance_noalloc: host exception");
     }
 }
 

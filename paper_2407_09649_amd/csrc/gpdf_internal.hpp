@@ -171,6 +171,8 @@ __device__ inline uint32_t wave_rank(uint32_t *cnt, int64_t slot) {
 // pass over the keys each, no global atomics)
 // ---------------------------------------------------------------------------
 constexpr int kCellListStride = 28;  // int4 entries per cell list: count + 27 descriptors
+// cells of the fixed cell-list scratch of the allocation-free query (28 MiB)
+constexpr int64_t kNoAllocCells = int64_t(1) << 16;
 constexpr int kCompactItems = 16;
 constexpr int kCompactTile = 256 * kCompactItems;
 
@@ -425,6 +427,7 @@ struct gpdf_ctx {
     uint32_t *d_cell_chunks = nullptr, *d_chunk_off = nullptr;
     int4 *d_cell_list = nullptr;                   // [cells][28]: count, cluster descriptors
     int64_t cap_cells = 0;                         // cells the lists hold
+    int4 *scratch_lists = nullptr;                 // this device's fixed cell lists (noalloc query)
     uint2 *d_chunk = nullptr;                      // (cell, start)
     uint2 *d_refine = nullptr;                     // (cell, query) records to redo in FP64
     uint32_t *d_rcnt = nullptr, *d_roff = nullptr; // refine records per cell
@@ -569,9 +572,10 @@ void grid_clear(gpdf_ctx *c, hipStream_t s);
 gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn = nullptr);
 // With dm (a device count of queries, at most m) and optionally d_origin, the
 // call reads nothing back and can be captured in a graph.
+gpdf_status scratch_setup(gpdf_ctx *c);
 gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin, float *dist,
                   float *grad, float *var, uint8_t *valid, float *aux, int32_t correct,
-                  const uint32_t *dm = nullptr, const float *d_origin = nullptr);
+                  const uint32_t *dm = nullptr, const float *d_origin = nullptr, bool noalloc = false);
 gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin = nullptr, int64_t npts_bound = -1);
 gpdf_status ensure_offsets(gpdf_ctx *c);
 gpdf_status query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *dist, float *grad,

@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -1638,6 +1639,39 @@ void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Per-cell cluster lists of gpdf_query_distance_noalloc: a fixed array in
+// device memory instead of the context's buffer (which a call grows when it
+// meets more cells than before), for callers that cannot allocate.  Each GPU
+// holds one copy of the array for the life of the process, shared by every
+// call on that GPU.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) int4 scratch[size_t(kNoAllocCells) * kCellListStride];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int4 *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this GPU's copy of `scratch`, taken once per device with
+// that device current (the host-side name is not a device address).
+gpdf_status scratch_setup(gpdf_ctx *c) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(c, e, "scratch: device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, GPDF_E_INVALID_ARG, "scratch: device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess)
+            return hip_fail(c, e, "scratch: symbol address");
+        g_scratch_ptr[dev] = static_cast<int4 *>(ptr);
+    }
+    c->scratch_lists = g_scratch_ptr[dev];
+    return GPDF_OK;
+}
+
 QueryConsts make_consts(const gpdf_params &p, const float *origin, const float *d_origin) {
     QueryConsts C{};
     const bool matern = p.kernel == GPDF_KERNEL_MATERN32;
@@ -1766,7 +1800,14 @@ gpdf_status build_bf16(gpdf_ctx *c) {
 
 gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin, float *dist,
                   float *grad, float *var, uint8_t *valid, float *aux, int32_t correct, const uint32_t *dm,
-                  const float *d_origin) {
+                  const float *d_origin, bool noalloc) {
+    if (noalloc) {
+        // nothing below may allocate: the BF16 copy of the factors is built
+        // (and its buffer sized) on the first BF16 query of a training
+        if (c->p.precision == GPDF_PREC_BF16)
+            return fail(c, GPDF_E_INVALID_ARG, "query_distance_noalloc: BF16 precision is not supported");
+        if (!c->scratch_lists) return fail(c, GPDF_E_INVALID_ARG, "query_distance_noalloc: no scratch on this device");
+    }
     if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "query: join");
     hipStream_t s = c->stream;
     const Model &M = c->model;
@@ -1843,16 +1884,22 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     exclusive_scan_u32(c->d_cell_chunks, c->d_chunk_off, nc, c->d_part, s, dnc, cnt + CNT_CHUNKS);
     hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_cell_chunks,
                        c->d_chunk_off, nullptr, c->d_chunk);
-    if (!knn && nc > c->cap_cells) {
+    int4 *lists = noalloc ? c->scratch_lists : c->d_cell_list;
+    if (!knn && noalloc && nc > kNoAllocCells)
+        return fail(c, GPDF_E_CAPACITY,
+                    "query_distance_noalloc: the queries fall in " + std::to_string(nc) +
+                        " cells, more than the " + std::to_string(kNoAllocCells) + " cell lists of the fixed scratch");
+    if (!knn && !noalloc && nc > c->cap_cells) {
         if (!eager) return fail(c, GPDF_E_CAPACITY, "query: cell lists not allocated for the bound");
         // grow the per-cell cluster lists (one reallocation per new maximum)
         const int64_t cap = std::min<int64_t>(c->p.max_queries + 1, nc + nc / 4 + 1024);
         if ((e = ensure_cell_lists(c, cap)) != hipSuccess) return hip_fail(c, e, "query: cell lists");
+        lists = c->d_cell_list;
     }
     if (!knn)
         hipLaunchKernelGGL(k_cell_lists, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_cell_key,
                            c->d_chash, c->chash_mask, c->d_chash_val, c->d_pd, c->d_coff,
-                           c->d_woff, c->d_cell_list);
+                           c->d_woff, lists);
     hipLaunchKernelGGL(k_scatter_order, dim3(blocks_for(m)), dim3(kQT), 0, s, c->d_qslot, c->d_qrank, m, dm,
                        c->d_qhash_cell, c->d_cell_off, c->d_order);
     stage_end(c, GPDF_MS_GROUP);
@@ -1863,7 +1910,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     Outputs O{dist, grad, var, aux, valid, c->d_refine, c->d_stat, c->d_spread};
     if (c->p.precision == GPDF_PREC_FP64) {
         stage_begin(c, GPDF_MS_EVAL);
-        launch_query_k<double>(c, kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O, 0);
+        launch_query_k<double>(c, kern, knn, grid, s, d_q, G, lists, Mo, C, O, 0);
         stage_end(c, GPDF_MS_EVAL);
     } else {
         stage_begin(c, GPDF_MS_EVAL);
@@ -1879,12 +1926,12 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
             Cb.tau_v = INFINITY;
             const __bf16 *Mbf = static_cast<const __bf16 *>(c->d_bfM);
             if (kern == GPDF_KERNEL_MATERN32)
-                launch_bf16_m<GPDF_KERNEL_MATERN32>(grid, lds, s, d_q, G, c->d_cell_list, Mo, Mbf, c->d_bfoff, kts, Cb,
+                launch_bf16_m<GPDF_KERNEL_MATERN32>(grid, lds, s, d_q, G, lists, Mo, Mbf, c->d_bfoff, kts, Cb,
                                                     O);
             else
-                launch_bf16_m<GPDF_KERNEL_SE>(grid, lds, s, d_q, G, c->d_cell_list, Mo, Mbf, c->d_bfoff, kts, Cb, O);
+                launch_bf16_m<GPDF_KERNEL_SE>(grid, lds, s, d_q, G, lists, Mo, Mbf, c->d_bfoff, kts, Cb, O);
         } else {
-            launch_query_k<float>(c, kern, knn, grid, s, d_q, G, c->d_cell_list, Mo, C, O, 0);
+            launch_query_k<float>(c, kern, knn, grid, s, d_q, G, lists, Mo, C, O, 0);
         }
         stage_end(c, GPDF_MS_EVAL);
         // 3. queries whose FP32 estimate is too large: regroup by cell
@@ -1894,7 +1941,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         const unsigned rgrid = blocks_for(m);
         hipLaunchKernelGGL(k_refine_count, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
                            c->d_stat + ST_REFINE, m, c->d_rcnt, c->d_rrank);
-        const int4 *rl = knn ? nullptr : c->d_cell_list;
+        const int4 *rl = knn ? nullptr : lists;
         // the per-cell arrays of the FP32 chunk table are free again: they
         // hold the heavy-cell chunk counts and their offsets
         uint32_t *rheavy = c->d_cell_chunks, *hoff = c->d_chunk_off;
@@ -1911,16 +1958,16 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         Outputs O64 = O;
         O64.refine = nullptr;
         if (knn) {
-            launch_query_k<double>(c, kern, knn, grid, s, d_q, R, c->d_cell_list, Mo, C, O64, 1);
+            launch_query_k<double>(c, kern, knn, grid, s, d_q, R, lists, Mo, C, O64, 1);
         } else {
             // pair-parallel, persistent: three wavefronts per SIMD
             uint32_t *work = c->d_work + kWorkSlot;
             fill_u32(work, 0u, 1, s);
             const unsigned rg = 3072;
             if (kern == GPDF_KERNEL_MATERN32)
-                launch_refine_pairs<GPDF_KERNEL_MATERN32>(rg, s, d_q, R, c->d_cell_list, Mo, C, O64, work);
+                launch_refine_pairs<GPDF_KERNEL_MATERN32>(rg, s, d_q, R, lists, Mo, C, O64, work);
             else
-                launch_refine_pairs<GPDF_KERNEL_SE>(rg, s, d_q, R, c->d_cell_list, Mo, C, O64, work);
+                launch_refine_pairs<GPDF_KERNEL_SE>(rg, s, d_q, R, lists, Mo, C, O64, work);
         }
         stage_end(c, GPDF_MS_REFINE);
     }
