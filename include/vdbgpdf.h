@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPDF_ABI_VERSION 1u
+#define GPDF_ABI_VERSION 2u
 
 typedef struct gpdf_ctx gpdf_ctx;
 
@@ -79,6 +79,16 @@ enum { GPDF_GRAD_WEIGHTED = 0, GPDF_GRAD_PAPER_MEAN = 1 };
  * re-evaluated in FP64 for distance and gradient but not for the variance,
  * which keeps the BF16 error */
 enum { GPDF_PREC_FP32 = 0, GPDF_PREC_BF16 = 1, GPDF_PREC_FP64 = 2 };
+/* fusion rule: inverse-variance weighting of Eq. (7)-(8), or the TSDF-style
+ * accumulated weights of Eq. (9) with the weight 1 - v of each observation
+ * (non-positive weights are skipped) */
+enum { GPDF_FUSE_INVVAR = 0, GPDF_FUSE_TSDF = 1 };
+/* test points of a fused frame: every global voxel within fuse_band of a
+ * training point, or the voxels that the rays from the sensor to the
+ * training voxels cross and that the grid already holds, plus the voxels
+ * along each training voxel's surface normal up to normal_reach
+ * (Sec. IV-B) */
+enum { GPDF_TEST_BAND = 0, GPDF_TEST_RAYCAST = 1 };
 
 typedef struct {
     uint32_t abi_version;      /* must equal GPDF_ABI_VERSION */
@@ -108,6 +118,9 @@ typedef struct {
     int64_t max_factor_elems;  /* capacity: sum over clusters of n(n+1)/2 */
     int64_t max_queries;       /* capacity: queries per call (also test points) */
     int64_t global_capacity;   /* capacity: voxels of the global grid */
+    int32_t fuse_rule;         /* GPDF_FUSE_* */
+    int32_t test_points;       /* GPDF_TEST_* */
+    double normal_reach;       /* GPDF_TEST_RAYCAST: metres along the normal */
 } gpdf_params;
 
 typedef struct {

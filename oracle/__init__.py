@@ -55,14 +55,15 @@ class Params(C.Structure):
         ("l", C.c_double), ("s", C.c_double), ("voxel", C.c_double),
         ("cell", C.c_double), ("lam", C.c_double), ("occ_min", C.c_double),
         ("occ_max", C.c_double), ("fuse_voxel", C.c_double),
-        ("fuse_band", C.c_double),
+        ("fuse_band", C.c_double), ("fuse_rule", C.c_int32),
+        ("tp_mode", C.c_int32), ("normal_reach", C.c_double),
     ]
 
     def __init__(self, **kw):
         d = dict(kernel=0, selection=0, knn_q=8, combine=0, grad_mode=0,
                  pad_=0, l=0.2, s=0.01, voxel=0.0, cell=0.4, lam=100.0,
                  occ_min=1e-15, occ_max=1.0 - 1e-5, fuse_voxel=0.05,
-                 fuse_band=0.2)
+                 fuse_band=0.2, fuse_rule=0, tp_mode=0, normal_reach=0.2)
         d.update(kw)
         super().__init__(**d)
 
@@ -101,7 +102,7 @@ def _bind(L):
     L.orc_map_size.argtypes = [_P]
     L.orc_map_size.restype = _I64
     L.orc_map_export.argtypes = [_P, _P, _P, _P, _P, _P]
-    L.orc_map_merge.argtypes = [_P, _P, _P, _P, _P, _P, _I64, C.c_uint32]
+    L.orc_map_merge.argtypes = [_P, _P, _P, _P, _P, _P, _I64, C.c_uint32, C.c_int]
     L.orc_map_merge.restype = _I64
     L.orc_fuse.argtypes = [_P, _P, _P, C.c_uint32, C.POINTER(_I64), C.c_int]
     L.orc_fuse.restype = _I64
@@ -237,14 +238,14 @@ class Map:
                            C.byref(sk), int(nthreads))
         return int(n), int(sk.value)
 
-    def merge(self, keys_, d, v, ok, frame: int, tie=None):
+    def merge(self, keys_, d, v, ok, frame: int, tie=None, rule: int = 0):
         k = np.ascontiguousarray(keys_, np.uint64)
         d = np.ascontiguousarray(d, np.float64)
         v = np.ascontiguousarray(v, np.float64)
         ok = np.ascontiguousarray(ok, np.uint8)
         t = None if tie is None else np.ascontiguousarray(tie, np.uint8)
         return int(lib().orc_map_merge(self._h, _ptr(k), _ptr(d), _ptr(v),
-                                       _ptr(ok), _ptr(t), k.shape[0], int(frame)))
+                                       _ptr(ok), _ptr(t), k.shape[0], int(frame), int(rule)))
 
     def size(self) -> int:
         return int(lib().orc_map_size(self._h))

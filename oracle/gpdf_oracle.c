@@ -62,6 +62,9 @@ typedef struct {
     double occ_max;      /* upper cap                                        */
     double fuse_voxel;   /* global grid edge                                 */
     double fuse_band;    /* test-point band radius in metres                 */
+    int32_t fuse_rule;   /* 0 inverse-variance Eq. (7)-(8), 1 TSDF-style (9) */
+    int32_t tp_mode;     /* 0 band test points, 1 ray-cast + normals (IV-B)  */
+    double normal_reach; /* metres along the normal (tp_mode 1)              */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -818,11 +821,18 @@ void orc_map_export(const orc_map *g, uint64_t *key, double *D, double *V,
  * Eq. (8)); a present one is updated by Eq. (7)-(8):
  *   D <- (V d + v D) / (V + v),  V <- (1/V + 1/v)^{-1} = V v / (V + v).
  * Observations with a non-finite or non-positive variance are skipped.
+ *
+ * rule 1 is the TSDF-style alternative of Eq. (9): the observation's weight
+ * is w = 1 - v, V accumulates the weights, and
+ *   D <- (w d + V D) / (V + w),  V <- V + w;
+ * an absent voxel takes (d, w).  1 - v can be negative (v is a variance in
+ * m^2); observations with w <= 0 carry no weight and are skipped.
+ *
  * tie (may be NULL) marks observations whose sign was a near-tie; the mark
  * stays on the voxel. */
 int64_t orc_map_merge(orc_map *g, const uint64_t *k, const double *d,
                       const double *v, const uint8_t *ok, const uint8_t *tie,
-                      int64_t n, uint32_t frame)
+                      int64_t n, uint32_t frame, int rule)
 {
     int64_t cap = g->n + n, i = 0, j = 0, w = 0, skipped = 0;
     uint64_t *nk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(cap + 1));
@@ -832,7 +842,8 @@ int64_t orc_map_merge(orc_map *g, const uint64_t *k, const double *d,
     uint8_t *nt = (uint8_t *)malloc((size_t)(cap + 1));
     while (i < g->n || j < n) {
         int use_obs;
-        if (j < n && !(ok[j] && isfinite(v[j]) && v[j] > 0.0 && isfinite(d[j]))) {
+        if (j < n && !(ok[j] && isfinite(v[j]) && isfinite(d[j]) &&
+                       (rule == 1 ? 1.0 - v[j] > 0.0 : v[j] > 0.0))) {
             skipped += ok[j] ? 1 : 0;
             j++;
             continue;
@@ -847,13 +858,19 @@ int64_t orc_map_merge(orc_map *g, const uint64_t *k, const double *d,
         } else if (i < g->n && k[j] == g->key[i]) {
             double Vp = g->V[i], Dp = g->D[i];
             nk[w] = k[j];
-            nD[w] = (Vp * d[j] + v[j] * Dp) / (Vp + v[j]);
-            nV[w] = (Vp * v[j]) / (Vp + v[j]);
+            if (rule == 1) {
+                double wt = 1.0 - v[j];
+                nD[w] = (wt * d[j] + Vp * Dp) / (Vp + wt);
+                nV[w] = Vp + wt;
+            } else {
+                nD[w] = (Vp * d[j] + v[j] * Dp) / (Vp + v[j]);
+                nV[w] = (Vp * v[j]) / (Vp + v[j]);
+            }
             ns[w] = frame;
             nt[w] = (uint8_t)(g->tie[i] | (tie ? tie[j] : 0));
             i++; j++; w++;
         } else {
-            nk[w] = k[j]; nD[w] = d[j]; nV[w] = v[j]; ns[w] = frame;
+            nk[w] = k[j]; nD[w] = d[j]; nV[w] = rule == 1 ? 1.0 - v[j] : v[j]; ns[w] = frame;
             nt[w] = tie ? tie[j] : 0;
             j++; w++;
         }
@@ -880,7 +897,7 @@ int64_t orc_fuse(orc_map *g, const orc_model *m, const float origin[3],
     orc_test_points(m, k, n);
     orc_voxel_centres(k, n, m->p.fuse_voxel, x);
     orc_query(m, x, n, origin, d, gr, v, ok, NULL, tie, nthreads);
-    sk = orc_map_merge(g, k, d, v, ok, tie, n, frame);
+    sk = orc_map_merge(g, k, d, v, ok, tie, n, frame, m->p.fuse_rule);
     if (skipped) *skipped = sk;
     free(k); free(x); free(d); free(gr); free(v); free(ok); free(tie);
     return n;

@@ -15,15 +15,18 @@ __all__ = ["Params", "Stats", "Context", "load_library", "library_path",
            "KERNEL_MATERN32", "KERNEL_SE", "SEL_NEIGHBOR27", "SEL_KNN",
            "COMB_SMOOTHMIN", "COMB_HARDMIN", "GRAD_WEIGHTED", "GRAD_PAPER_MEAN",
            "PREC_FP32", "PREC_BF16", "PREC_FP64", "MLP_NPARAM", "GpdfError",
+           "FUSE_INVVAR", "FUSE_TSDF", "TEST_BAND", "TEST_RAYCAST",
            "STATUS_HASH_FULL", "STATUS_GLOBAL_FULL", "STATUS_NONFINITE", "STATUS_NONPD",
            "STATUS_CAPACITY"]
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 KERNEL_MATERN32, KERNEL_SE = 0, 1
 SEL_NEIGHBOR27, SEL_KNN = 0, 1
 COMB_SMOOTHMIN, COMB_HARDMIN = 0, 1
 GRAD_WEIGHTED, GRAD_PAPER_MEAN = 0, 1
 PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
+FUSE_INVVAR, FUSE_TSDF = 0, 1
+TEST_BAND, TEST_RAYCAST = 0, 1
 MLP_NPARAM = 8897
 STATUS_HASH_FULL, STATUS_GLOBAL_FULL, STATUS_NONFINITE, STATUS_NONPD, STATUS_CAPACITY = 1, 2, 4, 8, 16
 
@@ -63,6 +66,7 @@ class Params(C.Structure):
         ("max_points", C.c_int64), ("max_clusters", C.c_int64),
         ("max_cluster_points", C.c_int64), ("max_factor_elems", C.c_int64),
         ("max_queries", C.c_int64), ("global_capacity", C.c_int64),
+        ("fuse_rule", C.c_int32), ("test_points", C.c_int32), ("normal_reach", C.c_double),
     ]
 
     @classmethod

@@ -99,6 +99,9 @@ extern "C" gpdf_status gpdf_params_default(gpdf_params *p) {
     p->max_factor_elems = int64_t(1) << 24;
     p->max_queries = int64_t(6) << 20;
     p->global_capacity = int64_t(1) << 24;
+    p->fuse_rule = GPDF_FUSE_INVVAR;
+    p->test_points = GPDF_TEST_BAND;
+    p->normal_reach = 0.2;
     return GPDF_OK;
 }
 
@@ -124,7 +127,11 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
         p->max_cluster_points > 1024 || p->max_factor_elems < 1 ||
         p->max_factor_elems > (int64_t(1) << 31) - 1 || p->max_queries < 1 ||
         p->max_queries > (int64_t(1) << 30) || p->global_capacity < 1 ||
-        p->global_capacity > (int64_t(1) << 30))
+        p->global_capacity > (int64_t(1) << 30) ||
+        (p->fuse_rule != GPDF_FUSE_INVVAR && p->fuse_rule != GPDF_FUSE_TSDF) ||
+        (p->test_points != GPDF_TEST_BAND && p->test_points != GPDF_TEST_RAYCAST) ||
+        !(std::isfinite(p->normal_reach) && p->normal_reach >= 0.0) ||
+        (p->test_points == GPDF_TEST_RAYCAST && p->voxel_size <= 0.0))
         return GPDF_E_INVALID_ARG;
     gpdf_ctx *c = new (std::nothrow) gpdf_ctx();
     if (!c) return GPDF_E_OOM;

@@ -105,18 +105,21 @@ __device__ inline bool grid_resolve(const GSlot *__restrict__ g, uint32_t gmask,
 }
 
 // Eq. (7)-(8): D <- (V d + v D) / (V + v), V <- V v / (V + v); an absent voxel
-// takes (d, v) (the V = infinity limit)
+// takes (d, v) (the V = infinity limit).
+// TSDF (Eq. (9)): weight w = 1 - v, D <- (w d + V D) / (V + w), V <- V + w; an
+// absent voxel takes (d, w); w <= 0 carries no weight and is skipped.
 __global__ void k_fuse(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ nptr,
                        const float *__restrict__ d, const float *__restrict__ v,
                        const uint8_t *__restrict__ ok, GSlot *__restrict__ g, uint32_t gmask,
                        uint32_t *__restrict__ gstamp, uint32_t frame_h, const uint32_t *__restrict__ dframe,
-                       unsigned long long *__restrict__ spread) {
+                       unsigned long long *__restrict__ spread, int tsdf) {
     const int64_t n = int64_t(*nptr);
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (int64_t(blockIdx.x) * blockDim.x >= n) return;  // whole block past the end
     const bool in = i < n;
     const float di = in ? d[i] : 0.f, vi = in ? v[i] : 0.f;
-    const bool use = in && ok[i] && isfinite(di) && isfinite(vi) && vi > 0.f;
+    const float wi = 1.f - vi;
+    const bool use = in && ok[i] && isfinite(di) && isfinite(vi) && (tsdf ? wi > 0.f : vi > 0.f);
     spread_count(spread, ST_FUSE_SKIPPED, in && !use);
     bool ins = false;
     int64_t s = -1;
@@ -127,7 +130,12 @@ __global__ void k_fuse(const uint64_t *__restrict__ keys, const uint32_t *__rest
     if (s < 0) return;
     if (ins) {
         g[s].D = di;
-        g[s].V = vi;
+        g[s].V = tsdf ? wi : vi;
+    } else if (tsdf) {
+        const float Vp = g[s].V, Dp = g[s].D;
+        const float den = Vp + wi;
+        g[s].D = (wi * di + Vp * Dp) / den;
+        g[s].V = den;
     } else {
         const float Vp = g[s].V, Dp = g[s].D;
         const float den = Vp + vi;
@@ -329,7 +337,7 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin, int64_
     stage_begin(c, GPDF_MS_FUSE);
     hipLaunchKernelGGL(k_fuse, dim3(blocks_for(nt)), dim3(kT), 0, s, c->d_tkeys, cnt + CNT_TEST, c->d_tmp_dist,
                        c->d_tmp_var, c->d_tmp_valid, c->d_gslot, c->gmask, c->d_gstamp, c->frame,
-                       eager ? nullptr : cnt + CNT_FRAME, c->d_spread);
+                       eager ? nullptr : cnt + CNT_FRAME, c->d_spread, c->p.fuse_rule == GPDF_FUSE_TSDF ? 1 : 0);
     fold_stats(c->d_spread, c->d_stat, s);
     stage_end(c, GPDF_MS_FUSE);
     if (eager) c->frame++;

@@ -34,7 +34,8 @@ def oracle_params(p: P.Params) -> O.Params:
                     combine=p.combine, grad_mode=p.grad_mode, l=p.length_scale,
                     s=p.noise_sigma, voxel=p.voxel_size, cell=p.cluster_size,
                     lam=p.smooth_min_lambda, occ_min=p.occ_min, occ_max=p.occ_max,
-                    fuse_voxel=p.fuse_voxel_size, fuse_band=p.fuse_band)
+                    fuse_voxel=p.fuse_voxel_size, fuse_band=p.fuse_band,
+                    fuse_rule=p.fuse_rule, tp_mode=p.test_points, normal_reach=p.normal_reach)
 
 
 def gpu_query(ctx, q, origin=None):

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_default_layout_and_values():
     p = P.Params.default()
-    assert p.abi_version == 1
+    assert p.abi_version == 2
     assert p.kernel == P.KERNEL_MATERN32
     assert p.length_scale == 0.2 and p.noise_sigma == 0.01
     assert p.cluster_size == 0.4 and p.voxel_size == 0.0
@@ -47,7 +47,8 @@ def test_params_default_layout_and_values():
     assert p.max_cluster_points == 1024
     # the last field lands where the C struct puts it
     assert p.global_capacity == 1 << 24
-    assert ctypes.sizeof(P.Params) == 160
+    assert p.fuse_rule == P.FUSE_INVVAR and p.test_points == P.TEST_BAND and p.normal_reach == 0.2
+    assert ctypes.sizeof(P.Params) == 176
 
 
 def test_create_rejects_bad_parameters_without_touching_the_gpu():
@@ -55,7 +56,9 @@ def test_create_rejects_bad_parameters_without_touching_the_gpu():
     h = ctypes.c_void_p()
     bad = [dict(abi_version=7), dict(length_scale=0.0), dict(length_scale=float("nan")),
            dict(occ_max=1.0), dict(knn_q=0, selection=P.SEL_KNN), dict(kernel=9),
-           dict(max_cluster_points=2048), dict(precision=5)]
+           dict(max_cluster_points=2048), dict(precision=5), dict(fuse_rule=2),
+           dict(test_points=2), dict(test_points=P.TEST_RAYCAST, voxel_size=0.0),
+           dict(normal_reach=-1.0)]
     for kw in bad:
         p = P.Params.default(**kw)
         assert lib.gpdf_create(ctypes.byref(p), None, ctypes.byref(h)) == 1, kw

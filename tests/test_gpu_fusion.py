@@ -76,10 +76,13 @@ def check_global(ctx, omap, q, dev, label, min_valid=0.0):
     return v.mean()
 
 
-def test_fusion_three_frames_parity(dev):
+@pytest.mark.parametrize("rule", ["invvar", "tsdf"])
+def test_fusion_three_frames_parity(dev, rule):
+    """Three frames fused by Eq. (7)-(8) or by the TSDF-style weights of
+    Eq. (9) (V then accumulates weights 1 - v)."""
     path, frames = _frames(4, 3)
-    ctx, omap = _fuse_both(dev, frames, path)
-    _, o = check_grid(ctx, omap, "three frames")
+    ctx, omap = _fuse_both(dev, frames, path, fuse_rule=P.FUSE_TSDF if rule == "tsdf" else P.FUSE_INVVAR)
+    _, o = check_grid(ctx, omap, f"three frames {rule}")
     # the global query: trilinear interpolation of the fused field
     rng = np.random.default_rng(0)
     q = _keys_to_centres(o["key"][rng.choice(len(o["key"]), 20000)], 0.05, rng)

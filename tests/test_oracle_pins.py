@@ -608,6 +608,32 @@ def test_fusion_invariants_and_order_independence():
     assert sk == 2 and g.size() == 1
 
 
+def test_tsdf_fusion_hand_computed():
+    # Eq. (9): weight w = 1 - v; D <- (w d + V D) / (V + w), V <- V + w
+    g = O.Map()
+    k = np.array([4, 8, 12], np.uint64)
+    g.merge(k, [1.0, 2.0, 5.0], [0.5, 0.75, 1.5], [1, 1, 1], frame=0, rule=1)
+    e = g.export()
+    # the third observation has 1 - v < 0: no weight, skipped
+    assert e["key"].tolist() == [4, 8]
+    assert e["D"].tolist() == [1.0, 2.0] and e["V"].tolist() == [0.5, 0.25]
+    g.merge(k[:2], [3.0, 6.0], [0.5, 0.25], [1, 1], frame=1, rule=1)
+    e = g.export()
+    # voxel 4: weights 0.5 and 0.5 -> mean 2.0, weight 1.0
+    assert e["D"][0] == 2.0 and e["V"][0] == 1.0
+    # voxel 8: weights 0.25 (D = 2) and 0.75 (d = 6): (0.75*6 + 0.25*2) / 1 = 5
+    assert abs(e["D"][1] - 5.0) < 1e-15 and e["V"][1] == 1.0 and e["stamp"].tolist() == [1, 1]
+    # with equal per-frame variances the rule is the plain running mean,
+    # whatever the frame order
+    rng = np.random.default_rng(21)
+    ds = rng.normal(size=7)
+    g2 = O.Map()
+    for f, dv in enumerate(ds):
+        g2.merge(k[:1], [dv], [0.3], [1], frame=f, rule=1)
+    e2 = g2.export()
+    assert abs(e2["D"][0] - ds.mean()) < 1e-14 and abs(e2["V"][0] - 7 * 0.7) < 1e-14
+
+
 def test_global_query_reproduces_affine_field():
     h = 0.05
     c = np.stack(np.meshgrid(np.arange(-5, 6), np.arange(-4, 5), np.arange(-3, 4),
