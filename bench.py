@@ -36,7 +36,7 @@ The ``extensions`` object reports, on the same GPU:
               gain, and its fused inference rate.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-extensions]
+                       [--no-extensions] [--legs precision,batched,sequence,correction]
 """
 from __future__ import annotations
 
@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extensions", action="store_true")
+    ap.add_argument("--legs", default="precision,batched,sequence,correction",
+                    help="extension legs to run (comma-separated subset)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -252,7 +254,8 @@ def main():
     gpu_out = {k: v.cpu().numpy() for k, v in out.items()}
     others = {}
     ext = {}
-    if not args.no_extensions:
+    legs = set() if args.no_extensions else set(args.legs.split(","))
+    if "precision" in legs:
         ext["precision"], others = precision_leg(P, torch, dev, x, qd, timer)
     if not args.no_cpu_baseline:
         res["cpu_baseline"], res["parity"], ref = run_cpu_baseline(
@@ -260,10 +263,13 @@ def main():
         for name, g in others.items():
             ext["precision"][name].update(dist_errors(g, ref))
     ctx.close()
-    if not args.no_extensions:
+    if "batched" in legs:
         ext["batched"] = batched_leg(P, torch, dev)
+    if "sequence" in legs:
         ext["sequence"] = sequence_leg(P, torch, dev)
+    if "correction" in legs:
         ext["correction"] = correction_leg(P, torch, dev)
+    if legs:
         res["extensions"] = ext
     print(json.dumps(res))
 

@@ -217,9 +217,10 @@ enum DevCount : int {
     CNT_VALID,    // finite points
     CNT_PTS,      // training points (unique voxels or valid points)
     CNT_CL,       // clusters
-    CNT_TINY,     // size buckets: n <= 8, n <= 64, larger
+    CNT_TINY,     // size buckets: n <= 8, n <= 64, n <= 256, larger
     CNT_WAVE,
     CNT_BIG,
+    CNT_HUGE,
     CNT_WTOT,     // factor elements
     CNT_ATOT,     // FP64 workspace elements
     CNT_MAXN,     // largest cluster
@@ -290,7 +291,7 @@ enum Stat : int {
 constexpr int kXcds = 8;
 constexpr int kCtrStride = 32;                     // u32 per counter line
 constexpr int kWorkSlot = kXcds * kCtrStride;
-constexpr int kWorkSlots = 3;
+constexpr int kWorkSlots = 4;
 
 constexpr int kSpread = 64;
 constexpr int kSpreadStride = 16 * ((ST_COUNT + 15) / 16);

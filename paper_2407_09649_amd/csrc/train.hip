@@ -362,6 +362,402 @@ __global__ __launch_bounds__(T) void k_train_block(
 }
 
 // ---------------------------------------------------------------------------
+// Blocked FP64 training on 16 x 16 tiles with FP64 MFMA (65 to 256 points)
+//
+// A = K + s^2 I is padded to T = ceil(n / 16) tiles per edge with an identity
+// block (so the padded factor is block diagonal with I and changes nothing),
+// and its lower tiles are kept in LDS (n <= 192) or in the FP64 workspace.
+// Right-looking Cholesky by tile columns p = 0 .. T - 1:
+//   one wavefront factors the diagonal tile, L_pp = chol(A_pp), and inverts
+//   it, V_p = L_pp^{-1} (16 steps in registers, row r in lane r), which
+//   replaces A_pp (L_pp is not read again);
+//   L_ip = A_ip V_p^T                for the tiles below (i > p);
+//   A_ij -= L_ip L_jp^T              for the trailing tiles (p < j <= i),
+// then W = L^{-1} in place by tile columns j = T - 1 .. 0 (the blocked
+// triangular inverse): M_kj = L_kj V_j, W_ij = -sum_{k=j+1..i} W_ik M_kj,
+// with W_jj = V_j already in place.  Every tile product is four
+// v_mfma_f64_16x16x4f64.  Finally
+// alpha = W^T (W 1) and W in the query layout.  A pivot at or below
+// 1e-10 (1 + s^2) marks the cluster non positive definite.
+// Lane layout of v_mfma_f64_16x16x4f64 (lane l, r = l % 16, g = l / 16):
+//   A[m][k] lane m + 16 k; B[k][n] lane n + 16 k; D[m][n] lane n + 16 (m % 4),
+//   element m / 4 (checked on the device).
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kTb = 16;                                  // tile edge
+constexpr int kTileElems = kTb * kTb;                    // 2 KB of FP64
+constexpr int kMfmaMaxN = 256;                           // largest cluster of this trainer
+constexpr int kMfmaLdsT = 12;                            // tiles per edge held in LDS (n <= 192)
+constexpr int kMfmaLdsTiles = kMfmaLdsT * (kMfmaLdsT + 1) / 2;
+constexpr int kMfmaT = 512;                              // workgroup
+__host__ __device__ inline int mfma_tiles(int n) { return (n + kTb - 1) / kTb; }
+// FP64 workspace of a cluster: its lower tiles
+__host__ __device__ inline int64_t mfma_ws(int n) {
+    const int64_t T = mfma_tiles(n);
+    return T * (T + 1) / 2 * kTileElems;
+}
+// element (r, c) of a tile: rows of 16, the column XOR-swizzled by the row,
+// so that 16 lanes reading one column, or one row, meet 16 distinct bank
+// pairs of the LDS
+__device__ __forceinline__ int tel(int r, int c) { return r * kTb + (c ^ r); }
+__device__ __forceinline__ int tlow(int ti, int tj) { return (ti * (ti + 1) / 2 + tj) * kTileElems; }
+
+__device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// acc += s X Y^T (X, Y tiles)
+__device__ __forceinline__ f64x4 tile_xyt(const double *X, const double *Y, f64x4 acc, double sgn, int lane) {
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int k0 = 0; k0 < kTb; k0 += 4) acc = mfma64(sgn * X[tel(r, k0 + g)], Y[tel(r, k0 + g)], acc);
+    return acc;
+}
+// acc += X Y
+__device__ __forceinline__ f64x4 tile_xy(const double *X, const double *Y, f64x4 acc, int lane) {
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int k0 = 0; k0 < kTb; k0 += 4) acc = mfma64(X[tel(r, k0 + g)], Y[tel(k0 + g, r)], acc);
+    return acc;
+}
+// the accumulator of a lane: rows g, g + 4, g + 8, g + 12 (g = lane / 16) of
+// column lane % 16
+__device__ __forceinline__ f64x4 tile_get(const double *X, int lane) {
+    const int g = lane >> 4, c = lane & 15;
+    return f64x4{X[tel(g, c)], X[tel(g + 4, c)], X[tel(g + 8, c)], X[tel(g + 12, c)]};
+}
+__device__ __forceinline__ void tile_put(double *X, f64x4 v, int lane) {
+    const int g = lane >> 4, c = lane & 15;
+    X[tel(g, c)] = v[0];
+    X[tel(g + 4, c)] = v[1];
+    X[tel(g + 8, c)] = v[2];
+    X[tel(g + 12, c)] = v[3];
+}
+__device__ __forceinline__ double bcast(double v, int lane) {
+    return __builtin_bit_cast(double, (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(__builtin_bit_cast(uint64_t, v) >> 32), lane))) << 32) |
+                                          uint64_t(uint32_t(__builtin_amdgcn_readlane(int(__builtin_bit_cast(uint64_t, v)), lane))));
+}
+
+// Cholesky and inverse of the diagonal tile D (one wavefront).  Lane l holds
+// column c = l % 16 of rows g, g + 4, g + 8, g + 12 (g = l / 16) of A (then
+// L) and of R (then V = L^{-1}).  Step k: the pivot by readlane; column k of
+// L and row k of V go through LDS (colb, rowb), written and read by the same
+// wavefront in program order; then
+//   A(r, c) -= L(r, k) L(c, k)  (k < c <= r),   R(r, c) -= L(r, k) V(k, c)  (c <= k < r).
+// Writes V over D (zero above the diagonal): L_pp itself is not read again;
+// false if a pivot is not above thr.
+__device__ bool diag_factor(double *D, double *colb, double *rowb, double thr, int lane) {
+    const int g = lane >> 4, c = lane & 15;
+    double a[4], w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = g + 4 * e;
+        a[e] = D[tel(r, c)];
+        w[e] = r == c ? 1.0 : 0.0;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < kTb; ++k) {
+        const double piv = bcast(a[k >> 2], k + 16 * (k & 3));   // A(k, k)
+        ok = ok && piv > thr;
+        // 1 / sqrt(pivot): the hardware estimate and two Newton steps
+        // y <- y (3 - x y^2) / 2, each doubling the correct bits; l = x y
+        const double x = ok ? piv : 1.0;
+        double inv = __builtin_amdgcn_rsq(x);
+        inv = inv * fma(-0.5 * x * inv, inv, 1.5);
+        inv = inv * fma(-0.5 * x * inv, inv, 1.5);
+        const double lkk = x * inv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = g + 4 * e;
+            if (c == k) {
+                a[e] = r > k ? a[e] * inv : (r == k ? lkk : a[e]);
+                if (r >= k) colb[r] = a[e];          // L(r, k)
+            }
+            if (r == k) {
+                if (c <= k) w[e] *= inv;             // V(k, c); zero right of k
+                rowb[c] = w[e];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double lck = colb[c], vkc = rowb[c];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = g + 4 * e;
+            if (r > k) {
+                const double lrk = colb[r];
+                if (c > k && c <= r) a[e] -= lrk * lck;
+                if (c <= k) w[e] -= lrk * vkc;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = g + 4 * e;
+        D[tel(r, c)] = c <= r ? w[e] : 0.0;
+    }
+    return ok;
+}
+
+// two independent tile products with all operand loads issued first:
+// acc1 += s X1 Y1^T and acc2 += s X2 Y2^T
+__device__ __forceinline__ void tile_xyt2(const double *X1, const double *Y1, f64x4 &acc1, const double *X2,
+                                          const double *Y2, f64x4 &acc2, double sgn, int lane) {
+    const int r = lane & 15, g = lane >> 4;
+    double a1[4], b1[4], a2[4], b2[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        a1[q] = X1[tel(r, 4 * q + g)];
+        b1[q] = Y1[tel(r, 4 * q + g)];
+        a2[q] = X2[tel(r, 4 * q + g)];
+        b2[q] = Y2[tel(r, 4 * q + g)];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        acc1 = mfma64(sgn * a1[q], b1[q], acc1);
+        acc2 = mfma64(sgn * a2[q], b2[q], acc2);
+    }
+}
+// acc1 += X1 Y1 and acc2 += X2 Y2, loads first
+__device__ __forceinline__ void tile_xy2(const double *X1, const double *Y1, f64x4 &acc1, const double *X2,
+                                         const double *Y2, f64x4 &acc2, int lane) {
+    const int r = lane & 15, g = lane >> 4;
+    double a1[4], b1[4], a2[4], b2[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        a1[q] = X1[tel(r, 4 * q + g)];
+        b1[q] = Y1[tel(4 * q + g, r)];
+        a2[q] = X2[tel(r, 4 * q + g)];
+        b2[q] = Y2[tel(4 * q + g, r)];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        acc1 = mfma64(a1[q], b1[q], acc1);
+        acc2 = mfma64(a2[q], b2[q], acc2);
+    }
+}
+
+// the body, inlined once with the tiles in LDS and once in the workspace
+__device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *__restrict__ ybuf, double *dbuf,
+                                                int *flag,
+                                                int c, int base, int n, float4 *__restrict__ pts,
+                                                const int64_t *__restrict__ woff, double *__restrict__ W64all,
+                                                float *__restrict__ W32all, double *__restrict__ alpha64,
+                                                uint8_t *__restrict__ pd, int kernel, double l, double s2,
+                                                unsigned long long *__restrict__ stat) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int kW = kMfmaT / 64;
+    const int T = mfma_tiles(n);
+    // A = K + s^2 I, padded with the identity; a tile per wavefront, lane l
+    // on column l % 16 of rows l / 16 + 4 e, the five point loads together
+    const int ntl = T * (T + 1) / 2;
+    for (int t = wv; t < ntl; t += kW) {
+        int ti = int((sqrtf(8.f * float(t) + 1.f) - 1.f) * 0.5f);
+        if ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        if (ti * (ti + 1) / 2 > t) --ti;
+        const int tj = t - ti * (ti + 1) / 2;
+        const int g = lane >> 4, cc = lane & 15;
+        const int j = tj * kTb + cc;
+        const float4 pj = pts[base + min(j, n - 1)];
+        float4 pi[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) pi[e] = pts[base + min(ti * kTb + g + 4 * e, n - 1)];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int rr = g + 4 * e, i = ti * kTb + rr;
+            double v;
+            if (i < n && j < n) {
+                const double dx = double(pi[e].x) - double(pj.x), dy = double(pi[e].y) - double(pj.y),
+                             dz = double(pi[e].z) - double(pj.z);
+                v = kernel64(kernel, sqrt(dx * dx + dy * dy + dz * dz), l);
+                if (i == j) v += s2;
+            } else {
+                v = i == j ? 1.0 : 0.0;
+            }
+            A[tlow(ti, tj) + tel(rr, cc)] = v;
+        }
+    }
+    if (tid == 0) *flag = 1;
+    __syncthreads();
+    const double thr = 1e-10 * (1.0 + s2);
+    // the diagonal tile of the next column is factored by wavefront 0 inside
+    // the trailing update of the current one (its own update comes first)
+    if (wv == 0 && !diag_factor(A, dbuf, dbuf + kTb, thr, lane) && lane == 0) *flag = 0;
+    __syncthreads();
+    for (int p = 0; p < T; ++p) {
+        if (!*flag) break;
+        // L_ip = A_ip V_p^T
+        const double *Vp = A + tlow(p, p);
+        for (int i = p + 1 + wv; i < T; i += kW) {
+            double *X = A + tlow(i, p);
+            const f64x4 acc = tile_xyt(X, Vp, f64x4{0.0, 0.0, 0.0, 0.0}, 1.0, lane);
+            tile_put(X, acc, lane);
+        }
+        __syncthreads();
+        // A_ij -= L_ip L_jp^T, two tiles at a time (the second repeats the
+        // first when the count is odd and is then not stored)
+        const int m = T - 1 - p, nt = m * (m + 1) / 2;
+        auto trail_tile = [&](int t, int &i, int &j) {
+            int a = int((sqrtf(8.f * float(t) + 1.f) - 1.f) * 0.5f);
+            if ((a + 1) * (a + 2) / 2 <= t) ++a;
+            if (a * (a + 1) / 2 > t) --a;
+            i = p + 1 + a;
+            j = p + 1 + (t - a * (a + 1) / 2);
+        };
+        for (int t = wv; t < nt; t += 2 * kW) {
+            const bool two = t + kW < nt;
+            int i1, j1, i2, j2;
+            trail_tile(t, i1, j1);
+            trail_tile(two ? t + kW : t, i2, j2);
+            double *Y1 = A + tlow(i1, j1), *Y2 = A + tlow(i2, j2);
+            f64x4 acc1 = tile_get(Y1, lane), acc2 = tile_get(Y2, lane);
+            tile_xyt2(A + tlow(i1, p), A + tlow(j1, p), acc1, A + tlow(i2, p), A + tlow(j2, p), acc2, -1.0, lane);
+            tile_put(Y1, acc1, lane);
+            if (two) tile_put(Y2, acc2, lane);
+            if (t == 0 && !diag_factor(Y1, dbuf, dbuf + kTb, thr, lane) && lane == 0) *flag = 0;
+        }
+        __syncthreads();
+    }
+    if (!*flag) {
+        for (int i = tid; i < n; i += kMfmaT) {
+            alpha64[base + i] = 0.0;
+            pts[base + i].w = 0.0f;
+        }
+        if (tid == 0) {
+            pd[c] = 0;
+            atomicAdd(&stat[ST_NONPD], 1ull);
+        }
+        return;
+    }
+    // W = L^{-1} by tile columns, right to left
+    for (int j = T - 1; j >= 0; --j) {
+        const double *Vj = A + tlow(j, j);
+        // M_kj = L_kj V_j
+        for (int k = j + 1 + wv; k < T; k += kW) {
+            double *X = A + tlow(k, j);
+            const f64x4 acc = tile_xy(X, Vj, f64x4{0.0, 0.0, 0.0, 0.0}, lane);
+            tile_put(X, acc, lane);
+        }
+        __syncthreads();
+        // W_ij = -sum_k W_ik M_kj (i > j), kept in registers until every
+        // product of the column has read its M tiles
+        constexpr int kMaxOut = (kMfmaMaxN / kTb + kW - 1) / kW;
+        f64x4 out[kMaxOut];
+#pragma unroll
+        for (int o = 0; o < kMaxOut; ++o) {
+            const int i = j + 1 + wv + o * kW;
+            out[o] = f64x4{0.0, 0.0, 0.0, 0.0};
+            if (i < T) {
+                // two chains (k even and odd offsets) with their loads together
+                f64x4 odd = f64x4{0.0, 0.0, 0.0, 0.0};
+                int k = j + 1;
+                for (; k + 1 <= i; k += 2)
+                    tile_xy2(A + tlow(i, k), A + tlow(k, j), out[o], A + tlow(i, k + 1), A + tlow(k + 1, j), odd,
+                             lane);
+                if (k <= i) out[o] = tile_xy(A + tlow(i, k), A + tlow(k, j), out[o], lane);
+                out[o] += odd;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < kMaxOut; ++o) {
+            const int i = j + 1 + wv + o * kW;
+            if (i < T) tile_put(A + tlow(i, j), -out[o], lane);
+        }
+        __syncthreads();
+    }
+    // y = W 1, alpha = W^T y
+    for (int i = tid; i < n; i += kMfmaT) {
+        const int ti = i / kTb, rr = i - ti * kTb;
+        double s0 = 0.0;
+        for (int tj = 0; tj <= ti; ++tj) {
+            const double *X = A + tlow(ti, tj);
+#pragma unroll
+            for (int cc = 0; cc < kTb; ++cc) s0 += X[tel(rr, cc)];
+        }
+        ybuf[i] = s0;
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += kMfmaT) {
+        const int tj = j / kTb, cc = j - tj * kTb;
+        // rows at or above j in the diagonal tile and the padded rows
+        // contribute zeros (W is lower triangular, its padding block I
+        // meets no real column)
+        double a = 0.0;
+        for (int ti = tj; ti < T; ++ti) {
+            const double *X = A + tlow(ti, tj);
+            double v[kTb];
+#pragma unroll
+            for (int rr = 0; rr < kTb; ++rr) v[rr] = X[tel(rr, cc)];
+#pragma unroll
+            for (int rr = 0; rr < kTb; ++rr) {
+                const int i = ti * kTb + rr;
+                if (i >= j && i < n) a += v[rr] * ybuf[i];
+            }
+        }
+        alpha64[base + j] = a;
+        pts[base + j].w = float(a);
+    }
+    // W in the query layout: 32-row panels, column-major inside, zero above
+    // the diagonal
+    float *W32 = W32all + woff[c];
+    double *W64 = W64all + woff[c];
+    const int nb = (n + kPanel - 1) / kPanel;
+    for (int rp = 0; rp < nb; ++rp) {
+        const int64_t po = w32_panel_offset(n, rp);
+        const int ncol = min((rp + 1) * kPanel, n);
+        for (int idx = tid; idx < ncol * kPanel; idx += kMfmaT) {
+            const int jj = idx / kPanel, rr = idx - jj * kPanel;
+            const int i = rp * kPanel + rr;
+            double v = 0.0;
+            if (i < n && jj <= i) {
+                const int ti = i / kTb, tj = jj / kTb;
+                v = A[tlow(ti, tj) + tel(i - ti * kTb, jj - tj * kTb)];
+            }
+            W32[po + idx] = float(v);
+            W64[po + idx] = v;
+        }
+    }
+    if (tid == 0) pd[c] = 1;
+}
+
+// persistent: each workgroup takes the next cluster of the bucket from the
+// counter *work (zero at launch) until none is left
+__global__ __launch_bounds__(kMfmaT) void k_train_mfma(
+    const int32_t *__restrict__ list, const uint32_t *__restrict__ dcnt, uint32_t *__restrict__ work,
+    float4 *__restrict__ pts, const int32_t *__restrict__ coff, const int64_t *__restrict__ aoff,
+    const int64_t *__restrict__ woff, double *__restrict__ Aall, double *__restrict__ W64all,
+    float *__restrict__ W32all, double *__restrict__ alpha64, uint8_t *__restrict__ pd, int kernel, double l,
+    double s2, unsigned long long *__restrict__ stat) {
+    __shared__ double sA[kMfmaLdsTiles * kTileElems];
+    __shared__ double ybuf[kMfmaMaxN];
+    __shared__ double dbuf[2 * kTb];
+    __shared__ int flag;
+    __shared__ uint32_t item;
+    const uint32_t cnt = *dcnt;
+    while (true) {
+        __syncthreads();  // the previous cluster is done with the LDS and item
+        if (threadIdx.x == 0) item = atomicAdd(work, 1u);
+        __syncthreads();
+        const uint32_t b = item;
+        if (b >= cnt) break;
+        const int c = list[b];
+        const int base = coff[c];
+        const int n = coff[c + 1] - base;
+        if (mfma_tiles(n) <= kMfmaLdsT)
+            train_mfma_body(sA, ybuf, dbuf, &flag, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel, l,
+                            s2, stat);
+        else
+            train_mfma_body(Aall + aoff[c], ybuf, dbuf, &flag, c, base, n, pts, woff, W64all, W32all, alpha64,
+                            pd, kernel, l, s2, stat);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // size buckets: n <= 8 one lane per cluster (registers), n <= 64 one
 // wavefront per cluster (LDS), larger one workgroup per cluster (above)
 // ---------------------------------------------------------------------------
@@ -615,13 +1011,17 @@ __global__ void k_cluster_sizes(const int32_t *__restrict__ coff, int64_t nbound
     const int n = coff[c + 1] - coff[c];
     const bool ok = n <= max_cp && n <= kMaxClusterN;
     wsz[c] = ok ? uint32_t(w32_size(n)) : 0u;
-    asz[c] = (ok && n > kBlockLdsN) ? uint32_t(n * (n + 1) / 2) : 0u;
+    // FP64 workspace: tiles of the MFMA trainer above its LDS limit, the
+    // packed triangle of the workgroup trainer above 256 points
+    asz[c] = !ok ? 0u
+             : n > kMfmaMaxN ? uint32_t(n * (n + 1) / 2)
+             : (n > kWaveN && mfma_tiles(n) > kMfmaLdsT) ? uint32_t(mfma_ws(n)) : 0u;
     atomicMax(maxn, uint32_t(n));
 }
 
 // offsets and size buckets: n <= 8 to list[0..], n <= 64 to list[C..],
-// larger to list[2C..]; clusters that exceed a capacity are not trained
-// (pd = 0) and counted
+// n <= 256 to list[2C..], larger to list[3C..]; clusters that exceed a
+// capacity are not trained (pd = 0) and counted
 __global__ void k_cluster_plan(const int32_t *__restrict__ coff, int64_t nbound, const uint32_t *__restrict__ dcl,
                                const uint32_t *__restrict__ wsz, const uint32_t *__restrict__ asz,
                                const uint32_t *__restrict__ wo, const uint32_t *__restrict__ ao, int64_t cap_w,
@@ -645,13 +1045,16 @@ __global__ void k_cluster_plan(const int32_t *__restrict__ coff, int64_t nbound,
     }
     const bool tiny = in && ok && n <= kTinyN;
     const bool wave = in && ok && n > kTinyN && n <= kWaveN;
-    const bool big = in && ok && n > kWaveN;
+    const bool big = in && ok && n > kWaveN && n <= kMfmaMaxN;
+    const bool huge = in && ok && n > kMfmaMaxN;
     const uint32_t rt = wave_count32(&cnt[CNT_TINY], tiny);
     const uint32_t rw = wave_count32(&cnt[CNT_WAVE], wave);
     const uint32_t rb = wave_count32(&cnt[CNT_BIG], big);
+    const uint32_t rh = wave_count32(&cnt[CNT_HUGE], huge);
     if (tiny) list[rt] = int32_t(c);
     if (wave) list[C + rw] = int32_t(c);
     if (big) list[2 * C + rb] = int32_t(c);
+    if (huge) list[3 * C + rh] = int32_t(c);
 }
 
 __global__ void k_copy_count(uint32_t *__restrict__ cnt, int dst, int src) {
@@ -746,10 +1149,14 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
     if ((e = hipEventRecord(c->fork_ev, s)) != hipSuccess || (e = hipStreamWaitEvent(sb, c->fork_ev, 0)) != hipSuccess)
         return hip_fail(c, e, "train: fork");
     fill_u32(c->d_work + 2 * kWorkSlot, 0u, 1, sb);
+    fill_u32(c->d_work + 3 * kWorkSlot, 0u, 1, sb);
+    hipLaunchKernelGGL(k_train_mfma, dim3(unsigned(std::min<int64_t>(C, 256))), dim3(kMfmaT), 0, sb,
+                       c->d_blist + 2 * C, cnt + CNT_BIG, c->d_work + 3 * kWorkSlot, c->d_pts, c->d_coff, c->d_aoff,
+                       c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l, s2, c->d_stat);
     {
         const unsigned gb = unsigned(std::min<int64_t>(C, 256));
 #define GPDF_TRAIN_BLOCK(T)                                                                                    \
-    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, sb, c->d_blist + 2 * C, cnt + CNT_BIG, c->d_work + 2 * kWorkSlot, \
+    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, sb, c->d_blist + 3 * C, cnt + CNT_HUGE, c->d_work + 2 * kWorkSlot, \
                        c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64,     \
                        c->d_pd, c->p.kernel, l, s2, c->d_stat)
         if (c->tune.train_threads == 512) GPDF_TRAIN_BLOCK(512);
