@@ -108,6 +108,8 @@ def _bind(L):
     L.orc_fuse.restype = _I64
     L.orc_query_global.argtypes = [_P, _D, _P, _I64, _P, _P, _P, _P]
     L.orc_nearest_distance.argtypes = [_P, _I64, _P, _I64, _P, C.c_int]
+    L.orc_zero_crossings.argtypes = [_P, _D, _P, _I64]
+    L.orc_zero_crossings.restype = _I64
     L.orc_max_threads.restype = C.c_int
     return L
 
@@ -259,6 +261,14 @@ class Map:
         t = np.empty(n, np.uint8)
         lib().orc_map_export(self._h, _ptr(k), _ptr(D), _ptr(V), _ptr(s), _ptr(t))
         return dict(key=k, D=D, V=V, stamp=s, sign_tie=t.astype(bool))
+
+    def zero_crossings(self, h):
+        """Surface points on the grid edges where D changes sign (linear
+        interpolation along the edge), ascending voxel key then axis."""
+        n = int(lib().orc_zero_crossings(self._h, float(h), None, 0))
+        out = np.empty((n, 3), np.float32)
+        lib().orc_zero_crossings(self._h, float(h), _ptr(out), n)
+        return out
 
     def query(self, h, q):
         x = _f32(q).reshape(-1, 3)

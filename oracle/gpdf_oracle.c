@@ -968,6 +968,46 @@ void orc_query_global(const orc_map *g, double h, const float *q, int64_t nq,
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* zero crossings of the fused grid (Sec. IV-D): the surface points that the  */
+/* marching cubes (Lorensen and Cline) place on the grid edges whose two      */
+/* voxel centres carry distances of opposite sign, where the linear           */
+/* interpolant of D along the edge is zero.  They train the global GPs        */
+/* (G-GPDF, one GP per leaf of 8^3 voxels).                                   */
+/* ------------------------------------------------------------------------ */
+/* Edges from voxel a to its neighbour b = a + e_axis (axis x, y, z); a sign
+ * change means (D_a < 0) != (D_b < 0).  The point lies at t = D_a / (D_a - D_b)
+ * of the edge: coordinate (c_a + 1/2 + t) h on the edge's axis, (c + 1/2) h on
+ * the others, each formed in FP64 and rounded once to FP32.  Order: ascending
+ * key of a, then axis.  Returns the count; writes at most cap points. */
+int64_t orc_zero_crossings(const orc_map *g, double h, float *out, int64_t cap)
+{
+    int64_t n = 0;
+    for (int64_t i = 0; i < g->n; ++i) {
+        int64_t c[3];
+        orc_unpack(g->key[i], c);
+        for (int a = 0; a < 3; ++a) {
+            int64_t nb[3] = {c[0], c[1], c[2]}, j;
+            double Da = g->D[i], Db, t;
+            nb[a] += 1;
+            if (nb[a] >= ORC_KEY_BIAS) continue;
+            j = orc_map_find(g, orc_pack(nb[0], nb[1], nb[2]));
+            if (j < 0) continue;
+            Db = g->D[j];
+            if ((Da < 0.0) == (Db < 0.0)) continue;
+            t = Da / (Da - Db);
+            if (out && n < cap)
+                for (int b = 0; b < 3; ++b) {
+                    double u = (double)c[b] + 0.5;
+                    if (b == a) u = u + t;
+                    out[3 * n + b] = (float)(u * h);
+                }
+            n++;
+        }
+    }
+    return n;
+}
+
 /* brute-force distance from each query to the nearest of n points (FP64) */
 void orc_nearest_distance(const float *pts, int64_t n, const float *q,
                           int64_t nq, double *out, int nthreads)

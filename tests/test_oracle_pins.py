@@ -658,6 +658,65 @@ def test_global_query_reproduces_affine_field():
     assert not far["valid"][0]
 
 
+def _grid_map(c, D):
+    b = 1 << 20
+    keys = ((c[:, 0] + b).astype(np.uint64) << np.uint64(42)) | \
+           ((c[:, 1] + b).astype(np.uint64) << np.uint64(21)) | (c[:, 2] + b).astype(np.uint64)
+    order = np.argsort(keys)
+    g = O.Map()
+    g.merge(keys[order], D[order], np.ones(len(D)), np.ones(len(D)), 0)
+    return g
+
+
+def test_zero_crossings_of_an_affine_field_lie_on_its_plane():
+    # linear interpolation is exact for an affine D: every crossing lies on
+    # the plane D = 0 (to FP32 rounding of the point), and there is exactly
+    # one per grid edge whose end values differ in sign
+    h = 0.05
+    c = np.stack(np.meshgrid(np.arange(-8, 9), np.arange(-7, 8), np.arange(-6, 7), indexing="ij"), -1).reshape(-1, 3)
+    nrm = np.array([0.36, -0.48, 0.8])
+    ctr = (c + 0.5) * h
+    D = ctr @ nrm - 0.013
+    g = _grid_map(c, D)
+    p = g.zero_crossings(h)
+    assert len(p) > 100
+    assert np.abs(p.astype(np.float64) @ nrm - 0.013).max() < 4e-7
+    # brute force over the edges, with the stored D of both ends
+    Dof = {tuple(ci): di for ci, di in zip(c.tolist(), D.tolist())}
+    want = 0
+    for ci, di in Dof.items():
+        for a in range(3):
+            nb = list(ci); nb[a] += 1
+            dj = Dof.get(tuple(nb))
+            if dj is not None and (di < 0) != (dj < 0):
+                want += 1
+    assert len(p) == want
+    # ascending voxel key, then axis: the same set in any merge order
+    g2 = _grid_map(c[::-1], D[::-1])
+    assert np.array_equal(g2.zero_crossings(h), p)
+
+
+def test_zero_crossings_of_a_sphere():
+    # D = |x| - R sampled at voxel centres: the crossings lie within the
+    # linear-interpolation error of the sphere, h^2 / (8 R) (second derivative
+    # of |x| along an edge is at most 1 / R near the surface, times h^2 / 8)
+    h, R = 0.05, 0.6
+    k = np.arange(-16, 16)
+    c = np.stack(np.meshgrid(k, k, k, indexing="ij"), -1).reshape(-1, 3)
+    ctr = (c + 0.5) * h
+    D = np.linalg.norm(ctr, axis=1) - R
+    keep = np.abs(D) < 2.5 * h
+    g = _grid_map(c[keep], D[keep])
+    p = g.zero_crossings(h).astype(np.float64)
+    r = np.linalg.norm(p, axis=1)
+    assert len(p) > 1000
+    assert np.abs(r - R).max() <= h * h / (8 * (R - h)) + 1e-6
+    # each crossing sits on a grid edge: two coordinates are voxel centres
+    frac = p / h - 0.5
+    on_lattice = np.abs(frac - np.round(frac)) < 1e-4
+    assert (on_lattice.sum(1) >= 2).all()
+
+
 def test_test_points_brute_force():
     pts = np.array([[0.01, 0.02, 0.03], [0.33, -0.12, 0.07], [0.36, -0.1, 0.05]],
                    np.float32)
