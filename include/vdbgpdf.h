@@ -290,6 +290,24 @@ gpdf_status gpdf_export_global(gpdf_ctx *ctx, uint64_t *h_key, float *h_D,
 gpdf_status gpdf_export_test_points(gpdf_ctx *ctx, uint64_t *h_key,
                                     int64_t cap, int64_t *count);
 
+/* Zero crossings of the global grid: the surface points from which the
+ * global GP distance field (G-GPDF, Sec. IV-D) is trained.  On every edge
+ * between two neighbouring voxels of the grid whose distances D have opposite
+ * signs (one negative, the other not), the point where the linear
+ * interpolant of D along the edge is zero -- the vertices that marching cubes
+ * places (Lorensen and Cline 1987).  The coordinate along the edge is
+ * (c + 1/2 + t) h with t = D_a / (D_a - D_b) computed in FP64, the others
+ * (c + 1/2) h; rounded once to FP32.  Points are listed by ascending key of
+ * the edge's lower voxel, then by axis x, y, z.
+ * *count receives the number of points; d_out (device, [cap][3]) is written
+ * only when cap >= *count (call with d_out NULL and cap 0 to size it).
+ * Synchronises the stream twice; allocates its work buffers on first use
+ * (and when a larger grid needs more).  A G-GPDF is a second context with
+ * voxel_size 0, cluster_size 8 fuse_voxel_size (a leaf of the grid) and
+ * GPDF_SEL_KNN (the Q nearest nodes), trained on these points.
+ * Errors: GPDF_E_INVALID_ARG (null count, cap > 0 with null d_out). */
+gpdf_status gpdf_zero_crossings(gpdf_ctx *ctx, float *d_out, int64_t cap, int64_t *count);
+
 /* Write / read the global grid: a header (magic, version, voxel size, count,
  * frame counter) and the key-sorted (key, D, V, stamp) records. */
 gpdf_status gpdf_save_global(gpdf_ctx *ctx, const char *path);

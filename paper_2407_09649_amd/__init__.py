@@ -42,6 +42,7 @@ EXPORTS = [
     "gpdf_set_tuning", "gpdf_get_tuning", "gpdf_autotune", "gpdf_fuse_frame_graph",
     "gpdf_mlp_get_weights", "gpdf_mlp_set_norm", "gpdf_mlp_get_norm", "gpdf_mlp_features",
     "gpdf_mlp_forward", "gpdf_mlp_grad", "gpdf_mlp_train", "gpdf_query_distance_noalloc",
+    "gpdf_zero_crossings",
 ]
 
 
@@ -133,6 +134,7 @@ def _bind(L):
         "gpdf_load_global": [P, C.c_char_p],
         "gpdf_nearest_distance": [P, P, I64, P, I64, P],
         "gpdf_fuse_frame_graph": [P, P, I64, P],
+        "gpdf_zero_crossings": [P, P, I64, P],
         "gpdf_set_tuning": [P, C.c_int32, C.c_int32],
         "gpdf_get_tuning": [P, P, P],
         "gpdf_autotune": [P, P, I64, P, I64, P, P],
@@ -342,6 +344,17 @@ class Context:
         _check(self.lib.gpdf_export_test_points(self._h, k.ctypes.data_as(C.c_void_p), cnt.value,
                                                 C.byref(cnt)), self._h)
         return k
+
+    def zero_crossings(self):
+        """The surface points of the fused grid (gpdf_zero_crossings) as a
+        device tensor [n, 3]."""
+        torch = self._torch
+        cnt = C.c_int64(0)
+        _check(self.lib.gpdf_zero_crossings(self._h, None, 0, C.byref(cnt)), self._h)
+        out = torch.empty((cnt.value, 3), dtype=torch.float32, device=self.device)
+        if cnt.value:
+            _check(self.lib.gpdf_zero_crossings(self._h, _dptr(out), cnt.value, C.byref(cnt)), self._h)
+        return out
 
     def save_global(self, path):
         _check(self.lib.gpdf_save_global(self._h, os.fsencode(path)), self._h)

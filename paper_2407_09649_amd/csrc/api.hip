@@ -55,6 +55,10 @@ void release(gpdf_ctx *c) {
                     c->d_mlp_norm, c->d_mlp_loss, c->d_mlp_mom, c->d_stat, c->d_spread, c->d_blist, c->d_tile_cnt, c->d_tile_off, c->d_bfM, c->d_bfoff, c->d_work, c->d_cnt, c->d_wsz, c->d_asz, c->d_wo32, c->d_ao32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    void *zptrs[] = {c->d_zkey, c->d_zkey2, c->d_zslot, c->d_zslot2, c->d_zcnt, c->d_zoff,
+                     c->d_zhist, c->d_zpart, c->d_ztile, c->d_ztoff};
+    for (void *p : zptrs)
+        if (p) (void)hipFree(p);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
     if (c->h_read) (void)hipHostFree(c->h_read);
     for (hipEvent_t &e : c->ev)

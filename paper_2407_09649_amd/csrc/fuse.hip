@@ -344,6 +344,190 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin, int64_
     return (e = hipGetLastError()) == hipSuccess ? GPDF_OK : hip_fail(c, e, "fuse launch");
 }
 
+// ---------------------------------------------------------------------------
+// zero crossings of the fused grid, the surface points of the G-GPDF
+// (Sec. IV-D): the vertices marching cubes places on the grid edges whose two
+// voxel centres carry distances of opposite sign, at the zero of the linear
+// interpolant along the edge.  Listed in ascending key of the edge's lower
+// voxel, then axis (x, y, z).
+// ---------------------------------------------------------------------------
+namespace {
+
+// sign-changing edges from voxel e to its +x, +y, +z neighbours (bits 0..2)
+__device__ inline uint32_t zc_edges(const GSlot *__restrict__ g, uint32_t gmask, const GSlot e, float *Dn) {
+    if (e.key == kNoKey) return 0u;
+    int64_t c[3];
+    unpack_key(e.key, c);
+    uint32_t m = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int64_t nb[3] = {c[0], c[1], c[2]};
+        nb[a] += 1;
+        if (nb[a] >= kBias) continue;
+        const uint64_t k = pack_key(nb[0], nb[1], nb[2]);
+        const uint64_t s0 = grid_start(k, gmask);
+        float Db = 0.f;
+        if (grid_resolve(g, gmask, k, s0, g[s0], &Db) && ((e.D < 0.f) != (Db < 0.f))) {
+            m |= 1u << a;
+            if (Dn) Dn[a] = Db;
+        }
+    }
+    return m;
+}
+
+// voxels with at least one crossing edge, per tile of kCompactTile slots
+__global__ __launch_bounds__(256) void k_zc_count(const GSlot *__restrict__ g, uint32_t gmask, int64_t cap,
+                                                  uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t wsum[4];
+    const int64_t t0 = int64_t(blockIdx.x) * kCompactTile;
+    uint32_t n = 0;
+    for (int r = 0; r < kCompactItems; ++r) {
+        const int64_t s = t0 + r * 256 + threadIdx.x;
+        const uint32_t m = s < cap ? zc_edges(g, gmask, g[s], nullptr) : 0u;
+        n += uint32_t(__popcll(__ballot(m != 0u)));
+    }
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// (key, slot) of those voxels in slot order at the tile offsets
+__global__ __launch_bounds__(256) void k_zc_emit(const GSlot *__restrict__ g, uint32_t gmask, int64_t cap,
+                                                 const uint32_t *__restrict__ tile_off, uint64_t *__restrict__ ekey,
+                                                 uint32_t *__restrict__ eslot) {
+    __shared__ uint32_t wsum[4];
+    const int w = threadIdx.x >> 6;
+    const int64_t t0 = int64_t(blockIdx.x) * kCompactTile;
+    uint32_t base = tile_off[blockIdx.x];
+    for (int r = 0; r < kCompactItems; ++r) {
+        const int64_t s = t0 + r * 256 + threadIdx.x;
+        const GSlot e = s < cap ? g[s] : GSlot{(unsigned long long)kNoKey, 0.f, 0.f};
+        const uint32_t m = zc_edges(g, gmask, e, nullptr);
+        const uint64_t b = __ballot(m != 0u);
+        if ((threadIdx.x & 63) == 0) wsum[w] = uint32_t(__popcll(b));
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int i = 0; i < 4; ++i) {
+            before += i < w ? wsum[i] : 0u;
+            tot += wsum[i];
+        }
+        if (m) {
+            const uint32_t id = base + before + uint32_t(__popcll(b & lanes_below()));
+            ekey[id] = e.key;
+            eslot[id] = uint32_t(s);
+        }
+        __syncthreads();
+        base += tot;
+    }
+}
+
+// crossings per sorted voxel
+__global__ void k_zc_points_count(const uint32_t *__restrict__ eslot, int64_t ne, const GSlot *__restrict__ g,
+                                  uint32_t gmask, uint32_t *__restrict__ cnt) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    cnt[i] = uint32_t(__popc(zc_edges(g, gmask, g[eslot[i]], nullptr)));
+}
+
+// the points: on the edge's axis (c + 1/2 + t) h with t = D_a / (D_a - D_b),
+// (c + 1/2) h on the others, in FP64 (no contraction) rounded once to FP32
+__global__ void k_zc_points(const uint32_t *__restrict__ eslot, int64_t ne, const GSlot *__restrict__ g,
+                            uint32_t gmask, const uint32_t *__restrict__ off, double h, float *__restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    const GSlot e = g[eslot[i]];
+    float Dn[3] = {0.f, 0.f, 0.f};
+    const uint32_t m = zc_edges(g, gmask, e, Dn);
+    int64_t c[3];
+    unpack_key(e.key, c);
+    uint32_t o = off[i];
+    for (int a = 0; a < 3; ++a) {
+        if (!((m >> a) & 1u)) continue;
+        const double Da = double(e.D), Db = double(Dn[a]);
+        const double t = __ddiv_rn(Da, __dsub_rn(Da, Db));
+        for (int b = 0; b < 3; ++b) {
+            double u = __dadd_rn(double(c[b]), 0.5);
+            if (b == a) u = __dadd_rn(u, t);
+            out[3 * int64_t(o) + b] = float(__dmul_rn(u, h));
+        }
+        ++o;
+    }
+}
+
+hipError_t zc_reserve(gpdf_ctx *c, int64_t ne, int64_t ntiles) {
+    hipError_t e;
+    if (ntiles + 1 > c->ztiles) {
+        if (c->d_ztile) (void)hipFree(c->d_ztile);
+        if (c->d_ztoff) (void)hipFree(c->d_ztoff);
+        c->d_ztile = c->d_ztoff = nullptr;
+        c->ztiles = 0;
+        if ((e = hipMalloc((void **)&c->d_ztile, sizeof(uint32_t) * size_t(ntiles + 1))) != hipSuccess ||
+            (e = hipMalloc((void **)&c->d_ztoff, sizeof(uint32_t) * size_t(ntiles + 1))) != hipSuccess)
+            return e;
+        c->ztiles = ntiles + 1;
+    }
+    if (ne + 1 <= c->zcap) return hipSuccess;
+    void *old[] = {c->d_zkey, c->d_zkey2, c->d_zslot, c->d_zslot2, c->d_zcnt, c->d_zoff, c->d_zhist, c->d_zpart};
+    for (void *p : old)
+        if (p) (void)hipFree(p);
+    c->d_zkey = c->d_zkey2 = nullptr;
+    c->d_zslot = c->d_zslot2 = c->d_zcnt = c->d_zoff = c->d_zhist = c->d_zpart = nullptr;
+    c->zcap = 0;
+    const int64_t cap = ne + ne / 4 + 1024;
+    const int64_t nh = 256 * ((cap + kRsTileKeys - 1) / kRsTileKeys) + 1;
+    const int64_t np = std::max<int64_t>(nh, cap) / 4096 + 64;
+    if ((e = hipMalloc((void **)&c->d_zkey, sizeof(uint64_t) * size_t(cap))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_zkey2, sizeof(uint64_t) * size_t(cap))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_zslot, sizeof(uint32_t) * size_t(cap))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_zslot2, sizeof(uint32_t) * size_t(cap))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_zcnt, sizeof(uint32_t) * size_t(cap))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_zoff, sizeof(uint32_t) * size_t(cap))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_zhist, sizeof(uint32_t) * size_t(nh))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_zpart, sizeof(uint32_t) * size_t(np))) != hipSuccess)
+        return e;
+    c->zcap = cap;
+    return hipSuccess;
+}
+
+}  // namespace
+
+gpdf_status zero_crossings(gpdf_ctx *c, float *d_out, int64_t cap, int64_t *count) {
+    hipStream_t s = c->stream;
+    hipError_t e;
+    const int64_t slots = int64_t(c->gmask) + 1;
+    const int64_t ntiles = compact_tiles(slots);
+    if ((e = zc_reserve(c, 0, ntiles)) != hipSuccess) return hip_fail(c, e, "zero crossings: alloc");
+    hipLaunchKernelGGL(k_zc_count, dim3(unsigned(ntiles)), dim3(256), 0, s, c->d_gslot, c->gmask, slots, c->d_ztile);
+    exclusive_scan_u32(c->d_ztile, c->d_ztoff, ntiles, c->d_part, s);
+    ReadList R;
+    R.u32(c->d_ztoff + ntiles);
+    if ((e = read_back(c, R, s)) != hipSuccess) return hip_fail(c, e, "zero crossings: count");
+    const int64_t ne = int64_t(c->h_read[0]);
+    if (ne == 0) {
+        *count = 0;
+        return GPDF_OK;
+    }
+    if ((e = zc_reserve(c, ne, ntiles)) != hipSuccess) return hip_fail(c, e, "zero crossings: alloc");
+    hipLaunchKernelGGL(k_zc_emit, dim3(unsigned(ntiles)), dim3(256), 0, s, c->d_gslot, c->gmask, slots, c->d_ztoff,
+                       c->d_zkey, c->d_zslot);
+    // ascending voxel key (the radix sort is stable, keys are unique)
+    uint64_t *k = c->d_zkey, *ka = c->d_zkey2;
+    uint32_t *v = c->d_zslot, *va = c->d_zslot2;
+    radix_sort_pairs(k, ka, v, va, ne, ~uint64_t(0), c->d_zhist, c->d_zpart, s);
+    const unsigned gb = unsigned((ne + 255) / 256);
+    hipLaunchKernelGGL(k_zc_points_count, dim3(gb), dim3(256), 0, s, v, ne, c->d_gslot, c->gmask, c->d_zcnt);
+    exclusive_scan_u32(c->d_zcnt, c->d_zoff, ne, c->d_zpart, s);
+    R = ReadList();
+    R.u32(c->d_zoff + ne);
+    if ((e = read_back(c, R, s)) != hipSuccess) return hip_fail(c, e, "zero crossings: points");
+    const int64_t np = int64_t(c->h_read[0]);
+    *count = np;
+    if (d_out && cap >= np)
+        hipLaunchKernelGGL(k_zc_points, dim3(gb), dim3(256), 0, s, v, ne, c->d_gslot, c->gmask, c->d_zoff,
+                           c->p.fuse_voxel_size, d_out);
+    return (e = hipGetLastError()) == hipSuccess ? GPDF_OK : hip_fail(c, e, "zero crossings: launch");
+}
+
 gpdf_status query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *dist, float *grad,
                          uint8_t *valid) {
     if (m < 0) return fail(c, GPDF_E_INVALID_ARG, "query_global: m < 0");
@@ -415,6 +599,17 @@ extern "C" gpdf_status gpdf_export_global(gpdf_ctx *c, uint64_t *h_key, float *h
         if (h_stamp) h_stamp[i] = r[i].st;
     }
     return GPDF_OK;
+}
+
+extern "C" gpdf_status gpdf_zero_crossings(gpdf_ctx *c, float *d_out, int64_t cap, int64_t *count) {
+    if (!c || !count) return GPDF_E_INVALID_ARG;
+    if (cap < 0 || (cap > 0 && !d_out)) return fail(c, GPDF_E_INVALID_ARG, "zero crossings: bad output buffer");
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
+    try {
+        return zero_crossings(c, d_out, cap, count);
+    } catch (...) {
+        return fail(c, GPDF_E_OOM, "zero crossings: host allocation failed");
+    }
 }
 
 extern "C" gpdf_status gpdf_export_test_points(gpdf_ctx *c, uint64_t *h_key, int64_t cap,

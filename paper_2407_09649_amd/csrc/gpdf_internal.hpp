@@ -450,6 +450,11 @@ struct gpdf_ctx {
     std::vector<int4> h_offs;                      // band offsets (host)
     int4 *d_offs = nullptr;
     int64_t offs_cap = 0;
+    // zero crossings of the grid (G-GPDF input), grown on demand
+    uint64_t *d_zkey = nullptr, *d_zkey2 = nullptr;
+    uint32_t *d_zslot = nullptr, *d_zslot2 = nullptr, *d_zcnt = nullptr, *d_zoff = nullptr;
+    uint32_t *d_zhist = nullptr, *d_zpart = nullptr, *d_ztile = nullptr, *d_ztoff = nullptr;
+    int64_t zcap = 0, ztiles = 0;
     int64_t last_test = 0;
 
     // ---- MLP ----------------------------------------------------------------
@@ -578,6 +583,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
                   float *grad, float *var, uint8_t *valid, float *aux, int32_t correct,
                   const uint32_t *dm = nullptr, const float *d_origin = nullptr, bool noalloc = false);
 gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin = nullptr, int64_t npts_bound = -1);
+gpdf_status zero_crossings(gpdf_ctx *c, float *d_out, int64_t cap, int64_t *count);
 gpdf_status ensure_offsets(gpdf_ctx *c);
 gpdf_status query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *dist, float *grad,
                          uint8_t *valid);
