@@ -121,6 +121,13 @@ typedef struct {
     int32_t fuse_rule;         /* GPDF_FUSE_* */
     int32_t test_points;       /* GPDF_TEST_* */
     double normal_reach;       /* GPDF_TEST_RAYCAST: metres along the normal */
+    int32_t lazy_train;        /* 1: gpdf_train_local_gps builds the clusters
+                                  but factors none; each query call trains
+                                  the clusters its queries select that are
+                                  not trained yet (the lazily trained nodes
+                                  of the G-GPDF, Sec. IV-D).  Not with
+                                  gpdf_fuse_frame_graph. */
+    int32_t pad1;
 } gpdf_params;
 
 typedef struct {
@@ -147,6 +154,8 @@ typedef struct {
     float ms[8];               /* with timing = 1: GPU time of the last run of
                                   each stage (GPDF_MS_*), milliseconds;
                                   -1 when the stage has not run */
+    int64_t trained_clusters;  /* clusters factored since the last training
+                                  (all of them unless lazy_train) */
 } gpdf_stats;
 
 enum {

@@ -68,6 +68,7 @@ class Params(C.Structure):
         ("max_cluster_points", C.c_int64), ("max_factor_elems", C.c_int64),
         ("max_queries", C.c_int64), ("global_capacity", C.c_int64),
         ("fuse_rule", C.c_int32), ("test_points", C.c_int32), ("normal_reach", C.c_double),
+        ("lazy_train", C.c_int32), ("pad1", C.c_int32),
     ]
 
     @classmethod
@@ -87,7 +88,8 @@ class Stats(C.Structure):
         "valid_queries", "refined_queries", "test_points", "fused",
         "fuse_skipped", "global_voxels", "gated", "eval_pairs", "eval_points",
         "eval_tri", "refine_dist", "refine_grad", "refine_var")] + [
-        ("status_bits", C.c_uint32), ("pad0", C.c_uint32), ("ms", C.c_float * 8)]
+        ("status_bits", C.c_uint32), ("pad0", C.c_uint32), ("ms", C.c_float * 8),
+        ("trained_clusters", C.c_int64)]
 
     STAGES = ("train", "group", "eval", "refine", "testpts", "fuse", "global", "mlp")
 

@@ -56,7 +56,7 @@ void release(gpdf_ctx *c) {
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     void *zptrs[] = {c->d_zkey, c->d_zkey2, c->d_zslot, c->d_zslot2, c->d_zcnt, c->d_zoff,
-                     c->d_zhist, c->d_zpart, c->d_ztile, c->d_ztoff};
+                     c->d_zhist, c->d_zpart, c->d_ztile, c->d_ztoff, c->d_need, c->d_trained};
     for (void *p : zptrs)
         if (p) (void)hipFree(p);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
@@ -106,6 +106,8 @@ extern "C" gpdf_status gpdf_params_default(gpdf_params *p) {
     p->fuse_rule = GPDF_FUSE_INVVAR;
     p->test_points = GPDF_TEST_BAND;
     p->normal_reach = 0.2;
+    p->lazy_train = 0;
+    p->pad1 = 0;
     return GPDF_OK;
 }
 
@@ -135,7 +137,8 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
         (p->fuse_rule != GPDF_FUSE_INVVAR && p->fuse_rule != GPDF_FUSE_TSDF) ||
         (p->test_points != GPDF_TEST_BAND && p->test_points != GPDF_TEST_RAYCAST) ||
         !(std::isfinite(p->normal_reach) && p->normal_reach >= 0.0) ||
-        (p->test_points == GPDF_TEST_RAYCAST && p->voxel_size <= 0.0))
+        (p->test_points == GPDF_TEST_RAYCAST && p->voxel_size <= 0.0) ||
+        (p->lazy_train != 0 && p->lazy_train != 1))
         return GPDF_E_INVALID_ARG;
     gpdf_ctx *c = new (std::nothrow) gpdf_ctx();
     if (!c) return GPDF_E_OOM;
@@ -164,6 +167,7 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
               dalloc(c->d_ao32, C + 1, e) &&
               dalloc(c->d_pts, P + kPtsPad, e) && dalloc(c->d_alpha64, P, e) && dalloc(c->d_ckey, C + 1, e) &&
               dalloc(c->d_coff, C + 1, e) && dalloc(c->d_pd, C + 1, e) && dalloc(c->d_woff, C, e) && dalloc(c->d_blist, 4 * C, e) &&
+              dalloc(c->d_need, C + 8, e) && dalloc(c->d_trained, C + 8, e) &&
               dalloc(c->d_aoff, C, e) && dalloc(c->d_W32, c->cap_w + kW32Pad, e) &&
               dalloc(c->d_W64, c->cap_w, e) &&
               dalloc(c->d_A, c->cap_a, e) &&
@@ -217,6 +221,7 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
     fill_u32(reinterpret_cast<uint32_t *>(c->d_W32), 0u, c->cap_w + kW32Pad, c->stream);
     grid_clear(c, c->stream);
     fill_u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1, c->stream);
+    fill_u32(reinterpret_cast<uint32_t *>(c->d_need), 0u, (C + 4) / 4, c->stream);
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) {
         release(c);
         delete c;
@@ -349,7 +354,7 @@ extern "C" gpdf_status gpdf_fuse_frame_graph(gpdf_ctx *c, const float *d_xyz, in
         return fail(c, GPDF_E_INVALID_ARG, "fuse_frame_graph: origin required");
     if (n < 0 || n > c->p.max_points) return fail(c, GPDF_E_CAPACITY, "fuse_frame_graph: n exceeds max_points");
     if (n > 0 && !d_xyz) return fail(c, GPDF_E_INVALID_ARG, "fuse_frame_graph: null points");
-    if (c->p.selection != GPDF_SEL_NEIGHBOR27 || c->p.precision == GPDF_PREC_BF16)
+    if (c->p.selection != GPDF_SEL_NEIGHBOR27 || c->p.precision == GPDF_PREC_BF16 || c->p.lazy_train)
         return fail(c, GPDF_E_INVALID_ARG, "fuse_frame_graph: needs NEIGHBOR27 selection in FP32 or FP64");
     try {
         if (!c->gexec) {
@@ -427,6 +432,7 @@ extern "C" gpdf_status gpdf_get_stats(gpdf_ctx *c, gpdf_stats *out) {
     out->refine_dist = int64_t(h[ST_REF_D]);
     out->refine_grad = int64_t(h[ST_REF_G]);
     out->refine_var = int64_t(h[ST_REF_V]);
+    out->trained_clusters = c->model.ntrained;
     uint32_t bits = 0;
     if (h[ST_HASH_FULL]) bits |= GPDF_STATUS_HASH_FULL;
     if (h[ST_GLOBAL_FULL]) bits |= GPDF_STATUS_GLOBAL_FULL;

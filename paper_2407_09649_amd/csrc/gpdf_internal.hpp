@@ -350,6 +350,8 @@ struct Model {
     bool trained = false;
     bool bf16_ready = false;   // BF16 copies of [W; alpha] built for this model
     bool host_counts = false;  // counts below were read back (eager calls)
+    bool lazy = false;         // clusters are factored when a query selects them
+    int64_t ntrained = 0;      // clusters factored (host count, eager calls)
 };
 
 }  // namespace gpdf
@@ -411,6 +413,7 @@ struct gpdf_ctx {
     double *d_A = nullptr;                         // FP64 workspace: packed A, L, then L^{-1} (n > 192)
     int64_t cap_w = 0, cap_a = 0;
     int32_t *d_blist = nullptr;
+    uint8_t *d_need = nullptr, *d_trained = nullptr;  // lazy training: selected / factored clusters
     unsigned long long *d_chash = nullptr;         // cluster hash keys
     int32_t *d_chash_val = nullptr;
     uint32_t chash_mask = 0;
@@ -584,6 +587,9 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
                   const uint32_t *dm = nullptr, const float *d_origin = nullptr, bool noalloc = false);
 gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin = nullptr, int64_t npts_bound = -1);
 gpdf_status zero_crossings(gpdf_ctx *c, float *d_out, int64_t cap, int64_t *count);
+// lazy training: factor the clusters marked in d_need that are not trained
+// yet (one round; *ntrained receives their number)
+gpdf_status lazy_train_round(gpdf_ctx *c, int64_t *ntrained);
 gpdf_status ensure_offsets(gpdf_ctx *c);
 gpdf_status query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *dist, float *grad,
                          uint8_t *valid);

@@ -964,6 +964,9 @@ struct ModelView {
     const uint8_t *pd;
     int64_t ncl;
     double edge;
+    const unsigned long long *chash;   // cluster hash (key -> slot)
+    const int32_t *chash_val;          // slot -> cluster
+    uint32_t cmask;
 };
 
 // NEIGHBOR27: one wavefront per (cell, 64-query chunk).  The cell's list
@@ -1497,6 +1500,113 @@ __device__ inline int wave_min_i32(int v) {
     return v;
 }
 
+// the Q nearest usable clusters of a query by FP64 distance from the query to
+// the cell centre, ties to the smaller key (= smaller index): bd/bi hold the
+// best Q as (distance^2, index) in ascending order (index 0x7fffffff for an
+// empty place)
+__device__ inline void knn_insert(double d2, int ci, int Qn, double *bd, int *bi, double &worst) {
+    if (d2 > worst) return;   // an equal distance may still enter by its smaller index
+    double cd = d2;
+#pragma unroll
+    for (int j = 0; j < kMaxKnn; ++j) {
+        // keep (distance, index) order; an equal distance stays behind the
+        // smaller index
+        if (j < Qn && (cd < bd[j] || (cd == bd[j] && ci < bi[j]))) {
+            const double td = bd[j];
+            const int ti = bi[j];
+            bd[j] = cd;
+            bi[j] = ci;
+            cd = td;
+            ci = ti;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxKnn; ++j)
+        if (j == Qn - 1) worst = bd[j];
+}
+
+// Shells of cells at Chebyshev distance r = 0, 1, 2, ... around the query's
+// cell, looked up in the cluster hash.  A cell of shell r + 1 has its centre
+// at least (r + 1/2) edge from the query along one axis, so the search ends
+// once Q clusters are held and the Q-th is nearer than that (with a margin
+// for the FP64 rounding of the squared distances).  Beyond kKnnShells shells
+// (fewer than Q clusters nearby) every cluster is scanned.  The result is the
+// brute-force selection.
+constexpr int kKnnShells = 8;
+__device__ inline void knn_select(const QueryPoint &Q, const ModelView &Mo, const QueryConsts &C, int Qn, double *bd,
+                                  int *bi) {
+#pragma unroll
+    for (int j = 0; j < kMaxKnn; ++j) { bd[j] = INFINITY; bi[j] = 0x7fffffff; }
+    double worst = INFINITY;
+    int64_t cq[3];
+    const float xq[3] = {Q.fx, Q.fy, Q.fz};
+    bool done = false;
+    if (query_cell(xq, C.hv > 0.0 ? 1 : 0, C.hv, C.hc, cq)) {
+        auto in_range = [](int64_t v) { return v >= -kBias && v < kBias; };
+        for (int r = 0; r <= kKnnShells && !done; ++r) {
+            for (int dx = -r; dx <= r; ++dx)
+                for (int dy = -r; dy <= r; ++dy)
+                    for (int dz = -r; dz <= r; ++dz) {
+                        if (max(abs(dx), max(abs(dy), abs(dz))) != r) continue;
+                        const int64_t nx = cq[0] + dx, ny = cq[1] + dy, nz = cq[2] + dz;
+                        if (!(in_range(nx) && in_range(ny) && in_range(nz))) continue;
+                        const int64_t sl = hash_find(Mo.chash, Mo.cmask, pack_key(nx, ny, nz));
+                        if (sl < 0) continue;
+                        const int c = Mo.chash_val[sl];
+                        if (!Mo.pd[c] || Mo.coff[c + 1] == Mo.coff[c]) continue;
+                        knn_insert(centre_d2(Q, Mo.ckey[c], Mo.edge), c, Qn, bd, bi, worst);
+                    }
+            const double b = (double(r) + 0.5) * Mo.edge;
+            done = worst < b * b * (1.0 - 1e-12);
+        }
+    }
+    if (!done) {
+        // a non-finite query keeps no cluster (as the brute-force scan, whose
+        // distances are then NaN); otherwise scan every cluster
+#pragma unroll
+        for (int j = 0; j < kMaxKnn; ++j) { bd[j] = INFINITY; bi[j] = 0x7fffffff; }
+        worst = INFINITY;
+        for (int64_t c = 0; c < Mo.ncl; ++c) {
+            if (!Mo.pd[c] || Mo.coff[c + 1] == Mo.coff[c]) continue;
+            knn_insert(centre_d2(Q, Mo.ckey[c], Mo.edge), int(c), Qn, bd, bi, worst);
+        }
+    }
+}
+
+// lazy training: mark the clusters that the queries select and that are not
+// trained yet (the Q nearest of each query)
+__global__ void k_lazy_mark_knn(const float *__restrict__ q, int64_t m, ModelView Mo, QueryConsts C,
+                                const uint8_t *__restrict__ trained, uint8_t *__restrict__ need) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const QueryPoint Q{q[3 * j], q[3 * j + 1], q[3 * j + 2]};
+    double bd[kMaxKnn];
+    int bi[kMaxKnn];
+    knn_select(Q, Mo, C, C.knn_q, bd, bi);
+#pragma unroll
+    for (int k = 0; k < kMaxKnn; ++k)
+        if (k < C.knn_q && bi[k] != 0x7fffffff && !trained[bi[k]]) need[bi[k]] = 1;
+}
+
+// ... and the clusters of the 27 cells around each query cell
+__global__ void k_lazy_mark_cells(int64_t ncb, const uint32_t *__restrict__ dnc,
+                                  const uint64_t *__restrict__ cell_key, ModelView Mo,
+                                  const uint8_t *__restrict__ trained, uint8_t *__restrict__ need) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= dev_count(ncb, dnc)) return;
+    int64_t cc[3];
+    unpack_key(cell_key[c], cc);
+    auto in_range = [](int64_t v) { return v >= -kBias && v < kBias; };
+    for (int t = 0; t < 27; ++t) {
+        const int64_t nx = cc[0] + t / 9 - 1, ny = cc[1] + (t / 3) % 3 - 1, nz = cc[2] + t % 3 - 1;
+        if (!(in_range(nx) && in_range(ny) && in_range(nz))) continue;
+        const int64_t sl = hash_find(Mo.chash, Mo.cmask, pack_key(nx, ny, nz));
+        if (sl < 0) continue;
+        const int id = Mo.chash_val[sl];
+        if (Mo.pd[id] && Mo.coff[id + 1] > Mo.coff[id] && !trained[id]) need[id] = 1;
+    }
+}
+
 // KNN: each lane picks its Q nearest clusters by cell-centre distance (ties
 // to the smaller key); the wavefront walks the union of the lanes' lists in
 // ascending cluster order and each lane evaluates exactly its own clusters
@@ -1517,28 +1627,7 @@ __global__ __launch_bounds__(kEvalT) void k_query_knn(const float *__restrict__ 
     const int Qn = C.knn_q;
     double bd[kMaxKnn];
     int bi[kMaxKnn];
-#pragma unroll
-    for (int j = 0; j < kMaxKnn; ++j) { bd[j] = INFINITY; bi[j] = 0x7fffffff; }
-    double worst = INFINITY;
-    for (int64_t c = 0; c < Mo.ncl; ++c) {
-        if (!Mo.pd[c] || Mo.coff[c + 1] == Mo.coff[c]) continue;
-        const double d2 = centre_d2(Q, Mo.ckey[c], Mo.edge);
-        if (!(d2 < worst)) continue;
-        // insert keeping (distance, index) order; an equal distance stays
-        // behind the earlier (smaller-key) cluster
-        double cd = d2;
-        int ci = int(c);
-#pragma unroll
-        for (int j = 0; j < kMaxKnn; ++j) {
-            if (j < Qn && cd < bd[j]) {
-                const double td = bd[j]; const int ti = bi[j];
-                bd[j] = cd; bi[j] = ci; cd = td; ci = ti;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < kMaxKnn; ++j)
-            if (j == Qn - 1) worst = bd[j];
-    }
+    knn_select(Q, Mo, C, Qn, bd, bi);
     // ascending cluster index (= ascending key)
 #pragma unroll
     for (int a = 1; a < kMaxKnn; ++a)
@@ -1850,7 +1939,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     const double edge = vox ? 8.0 * c->p.voxel_size : c->p.cluster_size;
     const int kern = c->p.kernel;
     const ModelView Mo{c->d_pts, c->d_alpha64, c->d_coff, c->d_woff, c->d_W32, c->d_W64,
-                       c->d_ckey, c->d_pd, M.nclusters, edge};
+                       c->d_ckey, c->d_pd, M.nclusters, edge, c->d_chash, c->d_chash_val, c->chash_mask};
     // 1. group by cell
     stage_begin(c, GPDF_MS_GROUP);
     // at most m distinct cells (far fewer in practice): a table of 1.25m to
@@ -1884,6 +1973,24 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     exclusive_scan_u32(c->d_cell_chunks, c->d_chunk_off, nc, c->d_part, s, dnc, cnt + CNT_CHUNKS);
     hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_cell_chunks,
                        c->d_chunk_off, nullptr, c->d_chunk);
+    // lazy training: factor the clusters these queries select, until a
+    // round trains none (a cluster found not positive definite leaves the
+    // selection, which may then take another)
+    if (M.lazy) {
+        if (!eager) return fail(c, GPDF_E_INVALID_ARG, "query with device counts on a lazily trained model");
+        for (int round = 0; round < 8; ++round) {
+            if (knn)
+                hipLaunchKernelGGL(k_lazy_mark_knn, dim3(blocks_for(m)), dim3(kQT), 0, s, d_q, m, Mo, C,
+                                   c->d_trained, c->d_need);
+            else
+                hipLaunchKernelGGL(k_lazy_mark_cells, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_cell_key,
+                                   Mo, c->d_trained, c->d_need);
+            int64_t k = 0;
+            const gpdf_status st = lazy_train_round(c, &k);
+            if (st != GPDF_OK) return st;
+            if (k == 0) break;
+        }
+    }
     int4 *lists = noalloc ? c->scratch_lists : c->d_cell_list;
     if (!knn && noalloc && nc > kNoAllocCells)
         return fail(c, GPDF_E_CAPACITY,

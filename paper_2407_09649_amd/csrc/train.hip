@@ -1027,7 +1027,8 @@ __global__ void k_cluster_plan(const int32_t *__restrict__ coff, int64_t nbound,
                                const uint32_t *__restrict__ wo, const uint32_t *__restrict__ ao, int64_t cap_w,
                                int64_t cap_a, int max_cp, int64_t *__restrict__ woff, int64_t *__restrict__ aoff,
                                int32_t *__restrict__ list, int64_t C, uint32_t *__restrict__ cnt,
-                               uint8_t *__restrict__ pd, unsigned long long *__restrict__ stat) {
+                               uint8_t *__restrict__ pd, unsigned long long *__restrict__ stat,
+                               uint8_t *__restrict__ trained, int lazy) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const bool in = c < dev_count(nbound, dcl);
     int n = 0;
@@ -1042,11 +1043,45 @@ __global__ void k_cluster_plan(const int32_t *__restrict__ coff, int64_t nbound,
             pd[c] = 0;
             atomicAdd(&stat[ST_CAPACITY], 1ull);
         }
+        // lazy: selectable until a query's selection trains it
+        if (lazy) {
+            trained[c] = 0;
+            if (ok) pd[c] = 1;
+        }
     }
+    if (lazy) return;
     const bool tiny = in && ok && n <= kTinyN;
     const bool wave = in && ok && n > kTinyN && n <= kWaveN;
     const bool big = in && ok && n > kWaveN && n <= kMfmaMaxN;
     const bool huge = in && ok && n > kMfmaMaxN;
+    const uint32_t rt = wave_count32(&cnt[CNT_TINY], tiny);
+    const uint32_t rw = wave_count32(&cnt[CNT_WAVE], wave);
+    const uint32_t rb = wave_count32(&cnt[CNT_BIG], big);
+    const uint32_t rh = wave_count32(&cnt[CNT_HUGE], huge);
+    if (tiny) list[rt] = int32_t(c);
+    if (wave) list[C + rw] = int32_t(c);
+    if (big) list[2 * C + rb] = int32_t(c);
+    if (huge) list[3 * C + rh] = int32_t(c);
+}
+
+// lazy training: the marked clusters that are not trained yet into the size
+// buckets (as k_cluster_plan), marked trained
+__global__ void k_lazy_plan(const int32_t *__restrict__ coff, int64_t ncl, uint8_t *__restrict__ need,
+                            uint8_t *__restrict__ trained, const uint8_t *__restrict__ pd,
+                            int32_t *__restrict__ list, int64_t C, uint32_t *__restrict__ cnt) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool take = false;
+    int n = 0;
+    if (c < ncl && need[c]) {
+        need[c] = 0;
+        take = !trained[c] && pd[c];
+        if (take) trained[c] = 1;
+        n = coff[c + 1] - coff[c];
+    }
+    const bool tiny = take && n <= kTinyN;
+    const bool wave = take && n > kTinyN && n <= kWaveN;
+    const bool big = take && n > kWaveN && n <= kMfmaMaxN;
+    const bool huge = take && n > kMfmaMaxN;
     const uint32_t rt = wave_count32(&cnt[CNT_TINY], tiny);
     const uint32_t rw = wave_count32(&cnt[CNT_WAVE], wave);
     const uint32_t rb = wave_count32(&cnt[CNT_BIG], big);
@@ -1076,6 +1111,43 @@ __global__ void k_chash_insert(const uint64_t *__restrict__ ckey, int64_t nbound
 }
 
 }  // namespace
+
+// The trainers of the four size buckets (lists and counts from the plan):
+// the two small-cluster trainers on s, the large-cluster ones on sb (forked
+// from s; join_ev marks their end)
+hipError_t launch_trainers(gpdf_ctx *c, int64_t C, hipStream_t s, hipStream_t sb) {
+    hipError_t e;
+    uint32_t *cnt = c->d_cnt;
+    const double l = c->p.length_scale, s2 = c->p.noise_sigma * c->p.noise_sigma;
+    if (sb != s) {
+        if ((e = hipEventRecord(c->fork_ev, s)) != hipSuccess || (e = hipStreamWaitEvent(sb, c->fork_ev, 0)) != hipSuccess)
+            return e;
+    }
+    fill_u32(c->d_work + 2 * kWorkSlot, 0u, 1, sb);
+    fill_u32(c->d_work + 3 * kWorkSlot, 0u, 1, sb);
+    hipLaunchKernelGGL(k_train_mfma, dim3(unsigned(std::min<int64_t>(C, 256))), dim3(kMfmaT), 0, sb,
+                       c->d_blist + 2 * C, cnt + CNT_BIG, c->d_work + 3 * kWorkSlot, c->d_pts, c->d_coff, c->d_aoff,
+                       c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l, s2, c->d_stat);
+    {
+        const unsigned gb = unsigned(std::min<int64_t>(C, 256));
+#define GPDF_TRAIN_BLOCK(T)                                                                                    \
+    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, sb, c->d_blist + 3 * C, cnt + CNT_HUGE, c->d_work + 2 * kWorkSlot, \
+                       c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64,     \
+                       c->d_pd, c->p.kernel, l, s2, c->d_stat)
+        if (c->tune.train_threads == 512) GPDF_TRAIN_BLOCK(512);
+        else if (c->tune.train_threads == 256) GPDF_TRAIN_BLOCK(256);
+        else GPDF_TRAIN_BLOCK(1024);
+#undef GPDF_TRAIN_BLOCK
+    }
+    if (sb != s && (e = hipEventRecord(c->join_ev, sb)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_train_tiny, dim3(blocks_for(C, 64)), dim3(64), 0, s, c->d_blist, cnt + CNT_TINY,
+                       c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l,
+                       s2, c->d_stat);
+    hipLaunchKernelGGL(k_train_wave, dim3(unsigned(std::min<int64_t>(C, 2048))), dim3(64), 0, s, c->d_blist + C,
+                       cnt + CNT_WAVE, c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
+                       c->p.kernel, l, s2, c->d_stat);
+    return hipGetLastError();
+}
 
 // Training of one frame.  Every count stays on the device (DevCount):
 // grids are sized by the number of input points n and the capacities.  With
@@ -1140,42 +1212,21 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
     exclusive_scan_u32(c->d_asz, c->d_ao32, C, c->d_part, s, cnt + CNT_CL, cnt + CNT_ATOT);
     hipLaunchKernelGGL(k_cluster_plan, dim3(blocks_for(C)), dim3(kT), 0, s, c->d_coff, C, cnt + CNT_CL, c->d_wsz,
                        c->d_asz, c->d_wo32, c->d_ao32, c->cap_w, c->cap_a, int(c->p.max_cluster_points),
-                       c->d_woff, c->d_aoff, c->d_blist, C, cnt, c->d_pd, c->d_stat);
-    // 5. FP64 training, one persistent launch per size bucket.  The
-    //    large-cluster trainer (few workgroups, each for long) runs on a
-    //    second stream beside the other two; the buckets are disjoint.
-    const double l = c->p.length_scale, s2 = c->p.noise_sigma * c->p.noise_sigma;
-    hipStream_t sb = c->side;
-    if ((e = hipEventRecord(c->fork_ev, s)) != hipSuccess || (e = hipStreamWaitEvent(sb, c->fork_ev, 0)) != hipSuccess)
-        return hip_fail(c, e, "train: fork");
-    fill_u32(c->d_work + 2 * kWorkSlot, 0u, 1, sb);
-    fill_u32(c->d_work + 3 * kWorkSlot, 0u, 1, sb);
-    hipLaunchKernelGGL(k_train_mfma, dim3(unsigned(std::min<int64_t>(C, 256))), dim3(kMfmaT), 0, sb,
-                       c->d_blist + 2 * C, cnt + CNT_BIG, c->d_work + 3 * kWorkSlot, c->d_pts, c->d_coff, c->d_aoff,
-                       c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l, s2, c->d_stat);
-    {
-        const unsigned gb = unsigned(std::min<int64_t>(C, 256));
-#define GPDF_TRAIN_BLOCK(T)                                                                                    \
-    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, sb, c->d_blist + 3 * C, cnt + CNT_HUGE, c->d_work + 2 * kWorkSlot, \
-                       c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64,     \
-                       c->d_pd, c->p.kernel, l, s2, c->d_stat)
-        if (c->tune.train_threads == 512) GPDF_TRAIN_BLOCK(512);
-        else if (c->tune.train_threads == 256) GPDF_TRAIN_BLOCK(256);
-        else GPDF_TRAIN_BLOCK(1024);
-#undef GPDF_TRAIN_BLOCK
+                       c->d_woff, c->d_aoff, c->d_blist, C, cnt, c->d_pd, c->d_stat, c->d_trained,
+                       c->p.lazy_train);
+    hipError_t e2 = hipGetLastError();
+    if (e2 != hipSuccess) return hip_fail(c, e2, "train: launch");
+    if (!c->p.lazy_train) {
+        // 5. FP64 training, one persistent launch per size bucket.  The
+        //    large-cluster trainers (few workgroups, each for long) run on a
+        //    second stream beside the other two; the buckets are disjoint.
+        //    eager: the join is left to the first operation that needs the
+        //    model (the test voxels of a fusion, which need only the points,
+        //    run beside the trainer); a captured frame joins here
+        if ((e = launch_trainers(c, C, s, c->side)) != hipSuccess) return hip_fail(c, e, "train: trainers");
+        if (eager) c->join_pending = true;
+        else if ((e = hipStreamWaitEvent(s, c->join_ev, 0)) != hipSuccess) return hip_fail(c, e, "train: join");
     }
-    if ((e = hipEventRecord(c->join_ev, sb)) != hipSuccess) return hip_fail(c, e, "train: join");
-    hipLaunchKernelGGL(k_train_tiny, dim3(blocks_for(C, 64)), dim3(64), 0, s, c->d_blist, cnt + CNT_TINY,
-                       c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l,
-                       s2, c->d_stat);
-    hipLaunchKernelGGL(k_train_wave, dim3(unsigned(std::min<int64_t>(C, 2048))), dim3(64), 0, s, c->d_blist + C,
-                       cnt + CNT_WAVE, c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd,
-                       c->p.kernel, l, s2, c->d_stat);
-    // eager: the join is left to the first operation that needs the model
-    // (the test voxels of a fusion, which need only the points, run beside
-    // the trainer); a captured frame joins here
-    if (eager) c->join_pending = true;
-    else if ((e = hipStreamWaitEvent(s, c->join_ev, 0)) != hipSuccess) return hip_fail(c, e, "train: join");
     // 6. cluster hash
     HashView hv{c->d_chash, c->chash_mask};
     hipLaunchKernelGGL(k_chash_insert, dim3(blocks_for(C)), dim3(kT), 0, s, c->d_ckey, C, cnt + CNT_CL, hv,
@@ -1192,15 +1243,44 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
     for (int k = 0; k < kCnt; ++k) hc[k] = uint32_t(c->h_read[k]);
     const unsigned long long capx = c->h_read[kCnt];
     M.host_counts = true;
+    M.lazy = c->p.lazy_train != 0;
     M.skipped = n - int64_t(hc[CNT_VALID]);
     M.npoints = hc[CNT_PTS];
     M.nclusters = hc[CNT_CL];
+    M.ntrained = M.lazy ? 0 : M.nclusters;
     M.max_n = hc[CNT_MAXN];
     if (capx) {
         M.trained = false;
         return fail(c, GPDF_E_CAPACITY,
                     "train: capacity exceeded (max_clusters, max_cluster_points or max_factor_elems)");
     }
+    return GPDF_OK;
+}
+
+}  // namespace gpdf
+
+namespace gpdf {
+
+gpdf_status lazy_train_round(gpdf_ctx *c, int64_t *ntrained) {
+    hipStream_t s = c->stream;
+    const Model &M = c->model;
+    uint32_t *cnt = c->d_cnt;
+    const int64_t C = std::max<int64_t>(M.nclusters, 1);
+    hipError_t e;
+    FillList F;
+    F.u32(cnt + CNT_TINY, 0u, CNT_HUGE - CNT_TINY + 1);
+    if ((e = fill_multi(F, s)) != hipSuccess) return hip_fail(c, e, "lazy: clear");
+    hipLaunchKernelGGL(k_lazy_plan, dim3(blocks_for(M.nclusters)), dim3(kT), 0, s, c->d_coff, M.nclusters, c->d_need,
+                       c->d_trained, c->d_pd, c->d_blist, C, cnt);
+    ReadList R;
+    for (int k = CNT_TINY; k <= CNT_HUGE; ++k) R.u32(cnt + k);
+    if ((e = read_back(c, R, s)) != hipSuccess) return hip_fail(c, e, "lazy: counts");
+    int64_t tot = 0;
+    for (int k = 0; k <= CNT_HUGE - CNT_TINY; ++k) tot += int64_t(c->h_read[k]);
+    *ntrained = tot;
+    c->model.ntrained += tot;
+    if (tot == 0) return GPDF_OK;
+    if ((e = launch_trainers(c, C, s, s)) != hipSuccess) return hip_fail(c, e, "lazy: trainers");
     return GPDF_OK;
 }
 
