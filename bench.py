@@ -428,8 +428,62 @@ def sequence_oracle_check(P, torch, dev, frames, path, prm, k_frames=5):
                      "validity_equal": bool((gq["valid"].astype(bool) == v).all()),
                      "max_dist_err_m": float(np.abs(gq["dist"][ok] - rq["dist"][ok]).max()) if ok.any() else 0.0,
                      "max_grad_err": float(np.abs(gq["grad"][ok] - rq["grad"][ok]).max()) if ok.any() else 0.0}
+    out["ggpdf"] = ggpdf_check(P, torch, dev, c, omap, qo)
     c.close()
     return out
+
+
+def ggpdf_check(P, torch, dev, c, omap, qo, n_sample=2000):
+    """The global GP distance field (G-GPDF, Sec. IV-D) of the fused grid: its
+    zero crossings, one lazily trained GP per leaf of the grid (0.4 m), the
+    Q = 8 nearest leaves per query combined by the smooth minimum; timed on
+    the GPU for the observed-voxel queries, and checked against the FP64
+    oracle (crossings of the same grid, every leaf trained) on a sample."""
+    import oracle as O
+    rep = {}
+    timer = Timer(torch, c.stream)
+    zc = {}
+    rep["zero_crossings_ms"] = timer.median(lambda: zc.update(p=c.zero_crossings()), reps=3)
+    pts = zc["p"]
+    rep["zero_crossings"] = int(pts.shape[0])
+    prm = dict(cluster_size=0.4, selection=P.SEL_KNN, knn_q=8, max_cluster_points=1024,
+               max_points=max(1 << 20, int(pts.shape[0]) + 1), max_clusters=1 << 20,
+               max_factor_elems=1 << 29, max_queries=len(qo), lazy_train=1, timing=1)
+    g = P.Context(P.Params.default(**prm), device=dev)
+    qd = torch.from_numpy(qo).to(dev)
+    t0 = time.perf_counter()
+    g.train(pts)
+    r = g.query(qd)               # trains the leaves these queries select
+    torch.cuda.synchronize()
+    rep["first_query_with_lazy_training_ms"] = 1e3 * (time.perf_counter() - t0)
+    st = g.stats()
+    rep["leaves"], rep["trained_leaves"] = st["clusters"], st["trained_clusters"]
+    out = {}
+    q_ms = Timer(torch, g.stream).median(lambda: out.update(g.query(qd)), reps=5)
+    rep["queries"] = int(len(qo))
+    rep["query_ms"] = q_ms
+    rep["query_rate"] = len(qo) / (q_ms / 1e3)
+    # oracle: the crossings of the oracle's own fused grid (FP64 fusion), so
+    # the comparison also covers the fusion; every leaf trained
+    op = O.Params(cell=0.4, selection=1, knn_q=8)
+    zo = omap.zero_crossings(0.05)
+    rep["oracle_zero_crossings"] = int(len(zo))
+    # the GPU field on the oracle's crossings, against the oracle field
+    g2 = P.Context(P.Params.default(**{**prm, "max_points": max(1 << 20, len(zo) + 1)}), device=dev)
+    g2.train(torch.from_numpy(zo).to(dev))
+    idx = np.random.default_rng(8).choice(len(qo), n_sample, replace=False)
+    gs = {k: v.cpu().numpy() for k, v in g2.query(torch.from_numpy(qo[idx]).to(dev)).items()}
+    t1 = time.perf_counter()
+    ref = O.Model(op, zo).query(qo[idx])
+    rep["oracle_sample_s"] = time.perf_counter() - t1
+    v = ref["valid"]
+    rep["sample"] = n_sample
+    rep["validity_equal"] = bool((gs["valid"].astype(bool) == v).all())
+    rep["max_dist_err_m"] = float(np.abs(gs["dist"][v] - ref["dist"][v]).max())
+    rep["max_grad_err"] = float(np.abs(gs["grad"][v] - ref["grad"][v]).max())
+    g.close()
+    g2.close()
+    return rep
 
 
 def correction_leg(P, torch, dev, n_train_scenes=40, n_eval_scenes=32, per_scene=250_000):
