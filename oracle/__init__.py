@@ -88,6 +88,14 @@ def _bind(L):
     L.orc_cholesky.argtypes = [_P, _I64]
     L.orc_cholesky.restype = C.c_int
     L.orc_train.argtypes = [C.POINTER(Params), _P, _I64, C.c_int]
+    L.orc_train_prop.argtypes = [C.POINTER(Params), _P, _P, _I64, C.c_int]
+    L.orc_train_prop.restype = _P
+    L.orc_model_props.argtypes = [_P, _P, _P]
+    L.orc_query_prop.argtypes = [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int]
+    L.orc_map_merge_prop.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _I64, C.c_uint32, C.c_int]
+    L.orc_map_merge_prop.restype = _I64
+    L.orc_map_export_prop.argtypes = [_P, _P, _P]
+    L.orc_query_global_prop.argtypes = [_P, _D, _P, _I64, _P, _P]
     L.orc_train.restype = _P
     L.orc_free.argtypes = [_P]
     L.orc_model_sizes.argtypes = [_P, _P]
@@ -155,11 +163,19 @@ def cholesky(A):
 class Model:
     """The local GPs of one point cloud (one per leaf cluster)."""
 
-    def __init__(self, params: Params, xyz, nthreads: int = 0):
+    def __init__(self, params: Params, xyz, nthreads: int = 0, prop=None):
+        """prop: optional surface property per input point (Eq. (6))."""
         self.params = params.copy()
         x = _f32(xyz).reshape(-1, 3)
-        self._h = lib().orc_train(C.byref(self.params), _ptr(x), x.shape[0],
-                                  int(nthreads))
+        self.has_props = prop is not None
+        if prop is None:
+            self._h = lib().orc_train(C.byref(self.params), _ptr(x), x.shape[0],
+                                      int(nthreads))
+        else:
+            c = _f32(prop).reshape(-1)
+            assert c.shape[0] == x.shape[0]
+            self._h = lib().orc_train_prop(C.byref(self.params), _ptr(x), _ptr(c),
+                                           x.shape[0], int(nthreads))
         s = np.zeros(4, np.int64)
         lib().orc_model_sizes(self._h, _ptr(s))
         self.nclusters, self.npoints, self.nonpd, self.skipped = map(int, s)
@@ -181,6 +197,14 @@ class Model:
                                _ptr(al), _ptr(pd))
         return dict(ckey=ck, off=off, points=pts, alpha=al, pd=pd.astype(bool))
 
+    def props(self):
+        """Property c and beta = (K + s^2 I)^{-1} c of every training point."""
+        c = np.empty(self.npoints)
+        b = np.empty(self.npoints)
+        if not lib().orc_model_props(self._h, _ptr(c), _ptr(b)):
+            raise ValueError("model trained without properties")
+        return dict(prop=c, beta=b)
+
     def factor(self, c: int):
         e = self.export()
         n = int(e["off"][c + 1] - e["off"][c])
@@ -199,10 +223,13 @@ class Model:
                    valid=np.empty(m, np.uint8), aux=np.empty((m, 3)),
                    sign_tie=np.zeros(m, np.uint8))
         o = None if origin is None else _f32(origin).reshape(3)
-        lib().orc_query(self._h, _ptr(x), m, _ptr(o), _ptr(out["dist"]),
-                        _ptr(out["grad"]), _ptr(out["var"]),
-                        _ptr(out["valid"]), _ptr(out["aux"]), _ptr(out["sign_tie"]),
-                        int(nthreads))
+        if self.has_props:
+            out["prop"] = np.empty(m)
+            out["prop_var"] = np.empty(m)
+        lib().orc_query_prop(self._h, _ptr(x), m, _ptr(o), _ptr(out["dist"]),
+                             _ptr(out["grad"]), _ptr(out["var"]),
+                             _ptr(out["valid"]), _ptr(out["aux"]), _ptr(out["sign_tie"]),
+                             _ptr(out.get("prop")), _ptr(out.get("prop_var")), int(nthreads))
         out["valid"] = out["valid"].astype(bool)
         out["sign_tie"] = out["sign_tie"].astype(bool)
         return out
@@ -240,14 +267,16 @@ class Map:
                            C.byref(sk), int(nthreads))
         return int(n), int(sk.value)
 
-    def merge(self, keys_, d, v, ok, frame: int, tie=None, rule: int = 0):
+    def merge(self, keys_, d, v, ok, frame: int, tie=None, rule: int = 0, prop=None, prop_var=None):
         k = np.ascontiguousarray(keys_, np.uint64)
         d = np.ascontiguousarray(d, np.float64)
         v = np.ascontiguousarray(v, np.float64)
         ok = np.ascontiguousarray(ok, np.uint8)
         t = None if tie is None else np.ascontiguousarray(tie, np.uint8)
-        return int(lib().orc_map_merge(self._h, _ptr(k), _ptr(d), _ptr(v),
-                                       _ptr(ok), _ptr(t), k.shape[0], int(frame), int(rule)))
+        c = None if prop is None else np.ascontiguousarray(prop, np.float64)
+        cv = None if prop is None else np.ascontiguousarray(prop_var, np.float64)
+        return int(lib().orc_map_merge_prop(self._h, _ptr(k), _ptr(d), _ptr(v), _ptr(ok), _ptr(t),
+                                            _ptr(c), _ptr(cv), k.shape[0], int(frame), int(rule)))
 
     def size(self) -> int:
         return int(lib().orc_map_size(self._h))
@@ -260,7 +289,11 @@ class Map:
         s = np.empty(n, np.uint32)
         t = np.empty(n, np.uint8)
         lib().orc_map_export(self._h, _ptr(k), _ptr(D), _ptr(V), _ptr(s), _ptr(t))
-        return dict(key=k, D=D, V=V, stamp=s, sign_tie=t.astype(bool))
+        out = dict(key=k, D=D, V=V, stamp=s, sign_tie=t.astype(bool))
+        Cp, W = np.empty(n), np.empty(n)
+        if lib().orc_map_export_prop(self._h, _ptr(Cp), _ptr(W)):
+            out["C"], out["W"] = Cp, W
+        return out
 
     def zero_crossings(self, h):
         """Surface points on the grid edges where D changes sign (linear
@@ -280,6 +313,16 @@ class Map:
         lib().orc_query_global(self._h, float(h), _ptr(x), m, _ptr(d), _ptr(g),
                                _ptr(ok), _ptr(t))
         return dict(dist=d, grad=g, valid=ok.astype(bool), sign_tie=t.astype(bool))
+
+    def query_prop(self, h, q):
+        """Trilinear interpolation of the fused property; valid where the
+        eight voxels around q exist and hold a property."""
+        x = _f32(q).reshape(-1, 3)
+        m = x.shape[0]
+        c = np.empty(m)
+        ok = np.empty(m, np.uint8)
+        lib().orc_query_global_prop(self._h, float(h), _ptr(x), m, _ptr(c), _ptr(ok))
+        return dict(prop=c, valid=ok.astype(bool))
 
 
 def nearest_distance(points, q, nthreads: int = 0):

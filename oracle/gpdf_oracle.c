@@ -263,6 +263,8 @@ typedef struct {
     int64_t *loff;    /* [nclusters] offset of the cluster's n*n factor */
     double *L;        /* dense row-major Cholesky factors */
     uint8_t *pd;      /* [nclusters] */
+    double *cprop;    /* [npoints] surface property of each training point, or NULL */
+    double *beta;     /* [npoints] (K + s^2 I)^{-1} c (Eq. (6)), or NULL */
 } orc_model;
 
 typedef struct { uint64_t key; uint64_t sub; int64_t src; } orc_item;
@@ -272,6 +274,7 @@ static int orc_item_cmp(const void *a, const void *b)
     const orc_item *x = (const orc_item *)a, *y = (const orc_item *)b;
     if (x->key != y->key) return x->key < y->key ? -1 : 1;
     if (x->sub != y->sub) return x->sub < y->sub ? -1 : 1;
+    if (x->src != y->src) return x->src < y->src ? -1 : 1;
     return 0;
 }
 
@@ -285,7 +288,7 @@ void orc_free(orc_model *m)
 {
     if (!m) return;
     free(m->ckey); free(m->off); free(m->pts); free(m->alpha);
-    free(m->loff); free(m->L); free(m->pd); free(m);
+    free(m->loff); free(m->L); free(m->pd); free(m->cprop); free(m->beta); free(m);
 }
 
 /* cell coordinates of a point for cluster selection, consistent with the
@@ -304,8 +307,14 @@ static int orc_cell_of(const orc_params *p, const float *x, int64_t c[3])
     return 1;
 }
 
-orc_model *orc_train(const orc_params *prm, const float *xyz, int64_t n,
-                     int nthreads)
+/* prop (may be NULL): a surface property per input point (intensity,
+ * colour channel).  The property of a training point is that of its raw
+ * points: in voxel mode their mean, summed in FP64 in input order; in raw
+ * mode the point's own.  The property GP of each cluster shares the kernel
+ * matrix and noise of the distance GP, so beta = (K + s^2 I)^{-1} c is a
+ * second right-hand side on the same factor (Eq. (6)). */
+orc_model *orc_train_prop(const orc_params *prm, const float *xyz, const float *prop,
+                          int64_t n, int nthreads)
 {
     orc_model *m = (orc_model *)calloc(1, sizeof(orc_model));
     orc_item *it = (orc_item *)malloc(sizeof(orc_item) * (size_t)(n > 0 ? n : 1));
@@ -332,13 +341,26 @@ orc_model *orc_train(const orc_params *prm, const float *xyz, int64_t n,
         it[cnt].src = i;
         cnt++;
     }
-    /* 2. order by (cluster key, member key); voxel mode drops duplicates */
+    /* 2. order by (cluster key, member key, input index); voxel mode drops
+     * duplicates, keeping the mean property of each voxel's raw points */
     qsort(it, (size_t)cnt, sizeof(orc_item), orc_item_cmp);
+    if (prop) m->cprop = (double *)malloc(sizeof(double) * (size_t)(cnt > 0 ? cnt : 1));
     if (prm->voxel > 0.0 && cnt > 0) {
-        int64_t w = 1;
-        for (int64_t i = 1; i < cnt; ++i)
-            if (it[i].sub != it[w - 1].sub) it[w++] = it[i];
+        int64_t w = 0;
+        for (int64_t i = 0; i < cnt;) {
+            int64_t e = i + 1;
+            double sum = prop ? (double)prop[it[i].src] : 0.0;
+            while (e < cnt && it[e].sub == it[i].sub) {
+                if (prop) sum += (double)prop[it[e].src];
+                e++;
+            }
+            if (prop) m->cprop[w] = sum / (double)(e - i);
+            it[w++] = it[i];
+            i = e;
+        }
         cnt = w;
+    } else if (prop) {
+        for (int64_t i = 0; i < cnt; ++i) m->cprop[i] = (double)prop[it[i].src];
     }
     m->npoints = cnt;
     m->pts = (float *)malloc(sizeof(float) * 3 * (size_t)(cnt > 0 ? cnt : 1));
@@ -381,6 +403,7 @@ orc_model *orc_train(const orc_params *prm, const float *xyz, int64_t n,
         m->L = (double *)malloc(sizeof(double) * (size_t)(tot > 0 ? tot : 1));
     }
     m->alpha = (double *)malloc(sizeof(double) * (size_t)(cnt > 0 ? cnt : 1));
+    if (prop) m->beta = (double *)malloc(sizeof(double) * (size_t)(cnt > 0 ? cnt : 1));
     m->pd = (uint8_t *)malloc((size_t)(m->nclusters + 1));
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -406,10 +429,33 @@ orc_model *orc_train(const orc_params *prm, const float *xyz, int64_t n,
         } else {
             for (int64_t i = 0; i < nc; ++i) m->alpha[o + i] = 0.0;
         }
+        if (m->beta) {
+            /* Eq. (6): the property right-hand side on the same factor */
+            for (int64_t i = 0; i < nc; ++i) m->beta[o + i] = m->pd[c] ? m->cprop[o + i] : 0.0;
+            if (m->pd[c]) {
+                orc_forward(A, nc, m->beta + o);
+                orc_backward(A, nc, m->beta + o);
+            }
+        }
     }
     m->nonpd = 0;
     for (int64_t c = 0; c < m->nclusters; ++c) m->nonpd += !m->pd[c];
     return m;
+}
+
+orc_model *orc_train(const orc_params *prm, const float *xyz, int64_t n,
+                     int nthreads)
+{
+    return orc_train_prop(prm, xyz, NULL, n, nthreads);
+}
+
+/* training-point properties and beta of a model trained with properties */
+int orc_model_props(const orc_model *m, double *cprop, double *beta)
+{
+    if (!m->beta) return 0;
+    memcpy(cprop, m->cprop, sizeof(double) * (size_t)m->npoints);
+    memcpy(beta, m->beta, sizeof(double) * (size_t)m->npoints);
+    return 1;
 }
 
 void orc_model_sizes(const orc_model *m, int64_t out[4])
@@ -512,7 +558,7 @@ static int orc_select(const orc_model *m, const float *x, int64_t *sel)
 /* ------------------------------------------------------------------------ */
 /* one (query, cluster) pair: Eq. (1), (2), (5), then (3), (4)               */
 /* ------------------------------------------------------------------------ */
-typedef struct { double o, u, d, g[3], v; } orc_pair;
+typedef struct { double o, u, d, g[3], v, c; } orc_pair;
 
 static void orc_eval_pair(const orc_model *m, int64_t c, const double x[3],
                           double *kbuf, orc_pair *r)
@@ -521,13 +567,14 @@ static void orc_eval_pair(const orc_model *m, int64_t c, const double x[3],
     int64_t o = m->off[c], nc = m->off[c + 1] - o;
     const float *P = m->pts + 3 * o;
     const double *L = m->L + m->loff[c];
-    double occ = 0.0, go[3] = {0.0, 0.0, 0.0}, ss = 0.0;
+    double occ = 0.0, go[3] = {0.0, 0.0, 0.0}, ss = 0.0, cp = 0.0;
     for (int64_t i = 0; i < nc; ++i) {
         double dx[3], rr;
         for (int a = 0; a < 3; ++a) dx[a] = x[a] - (double)P[3 * i + a];
         rr = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
         kbuf[i] = orc_kernel(p, rr);
         occ += m->alpha[o + i] * kbuf[i];                 /* Eq. (1) */
+        if (m->beta) cp += m->beta[o + i] * kbuf[i];      /* Eq. (6) */
         {
             double gc = m->alpha[o + i] * orc_kernel_grad_coef(p, rr);
             for (int a = 0; a < 3; ++a) go[a] += gc * dx[a];  /* Eq. (5) */
@@ -541,6 +588,7 @@ static void orc_eval_pair(const orc_model *m, int64_t c, const double x[3],
     if (r->u < 0.0) r->u = 0.0;
     if (r->u > 1.0) r->u = 1.0;
     r->o = occ;
+    r->c = cp;
     {
         /* footnote 1: the occupancy is capped before reverting */
         double oc = occ, d, lam;
@@ -630,9 +678,17 @@ static int orc_sign(const orc_model *m, const int64_t *sel, int ns, const float 
 /* ------------------------------------------------------------------------ */
 /* query: selection, per-pair inference, Eq. (10), sign                      */
 /* ------------------------------------------------------------------------ */
-void orc_query(const orc_model *m, const float *q, int64_t nq,
-               const float *origin, double *dist, double *grad, double *var,
-               uint8_t *valid, double *aux, uint8_t *tie, int nthreads)
+/* prop, prop_var (may be NULL; need a model trained with properties): the
+ * surface property (Eq. (6)) and its variance.  The property GP has the
+ * distance GP's kernel and noise, so its posterior variance is the latent
+ * variance u of Eq. (2).  Both are combined over the selected clusters like
+ * the distance variance: with the smooth-minimum weights of the distances,
+ * or from the closest node alone.  An invalid query gives prop 0 and
+ * prop_var infinity. */
+void orc_query_prop(const orc_model *m, const float *q, int64_t nq,
+                    const float *origin, double *dist, double *grad, double *var,
+                    uint8_t *valid, double *aux, uint8_t *tie, double *prop,
+                    double *prop_var, int nthreads)
 {
     const orc_params *p = &m->p;
     int64_t maxn = 1;
@@ -657,6 +713,8 @@ void orc_query(const orc_model *m, const float *q, int64_t nq,
             if (tie) tie[j] = 0;
             if (ns == 0) {
                 dist[j] = INFINITY; var[j] = INFINITY; valid[j] = 0;
+                if (prop) prop[j] = 0.0;
+                if (prop_var) prop_var[j] = INFINITY;
                 for (int a = 0; a < 3; ++a) grad[3 * j + a] = 0.0;
                 if (aux) { aux[3 * j] = 0.0; aux[3 * j + 1] = 0.0; aux[3 * j + 2] = 0.0; }
                 continue;
@@ -672,19 +730,21 @@ void orc_query(const orc_model *m, const float *q, int64_t nq,
                  * exp(-lambda (d_q - d_min)).  Subtracting d_min leaves the
                  * ratio unchanged. */
                 int amin = 0;
-                double dmin, W = 0.0, D = 0.0, V = 0.0, G[3] = {0, 0, 0};
+                double dmin, W = 0.0, D = 0.0, V = 0.0, G[3] = {0, 0, 0}, Cp = 0.0, Cw = 0.0;
                 for (int s = 1; s < ns; ++s) if (pr[s].d < pr[amin].d) amin = s;
                 dmin = pr[amin].d;
                 if (p->combine == 1) {
                     D = pr[amin].d; V = pr[amin].v;
+                    Cp = pr[amin].c; Cw = pr[amin].u;
                     for (int a = 0; a < 3; ++a) G[a] = pr[amin].g[a];
                 } else {
                     for (int s = 0; s < ns; ++s) {
                         double w = exp(-p->lambda * (pr[s].d - dmin));
                         W += w; D += w * pr[s].d; V += w * pr[s].v;
+                        Cp += w * pr[s].c; Cw += w * pr[s].u;
                         for (int a = 0; a < 3; ++a) G[a] += w * pr[s].g[a];
                     }
-                    D /= W; V /= W;
+                    D /= W; V /= W; Cp /= W; Cw /= W;
                     if (p->grad_mode == 1) {
                         /* "directly average" the Q gradients */
                         for (int a = 0; a < 3; ++a) {
@@ -705,6 +765,8 @@ void orc_query(const orc_model *m, const float *q, int64_t nq,
                     if (tie) tie[j] = t;
                 }
                 dist[j] = D; var[j] = V; valid[j] = 1;
+                if (prop) prop[j] = Cp;
+                if (prop_var) prop_var[j] = Cw;
                 for (int a = 0; a < 3; ++a) grad[3 * j + a] = G[a];
                 if (aux) {
                     aux[3 * j] = pr[amin].o;
@@ -716,6 +778,13 @@ void orc_query(const orc_model *m, const float *q, int64_t nq,
         free(kbuf);
         free(pr);
     }
+}
+
+void orc_query(const orc_model *m, const float *q, int64_t nq,
+               const float *origin, double *dist, double *grad, double *var,
+               uint8_t *valid, double *aux, uint8_t *tie, int nthreads)
+{
+    orc_query_prop(m, q, nq, origin, dist, grad, var, valid, aux, tie, NULL, NULL, nthreads);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -794,6 +863,9 @@ typedef struct {
     double *D, *V;
     uint32_t *stamp;
     uint8_t *tie;     /* some fused observation had a sign near-tie */
+    double *C, *W;    /* fused surface property and its variance (or weight);
+                         NaN where no property has been fused; NULL until a
+                         frame with properties is merged */
 } orc_map;
 
 orc_map *orc_map_new(void) { return (orc_map *)calloc(1, sizeof(orc_map)); }
@@ -801,7 +873,8 @@ orc_map *orc_map_new(void) { return (orc_map *)calloc(1, sizeof(orc_map)); }
 void orc_map_free(orc_map *g)
 {
     if (!g) return;
-    free(g->key); free(g->D); free(g->V); free(g->stamp); free(g->tie); free(g);
+    free(g->key); free(g->D); free(g->V); free(g->stamp); free(g->tie);
+    free(g->C); free(g->W); free(g);
 }
 
 int64_t orc_map_size(const orc_map *g) { return g->n; }
@@ -830,11 +903,25 @@ void orc_map_export(const orc_map *g, uint64_t *key, double *D, double *V,
  *
  * tie (may be NULL) marks observations whose sign was a near-tie; the mark
  * stays on the voxel. */
-int64_t orc_map_merge(orc_map *g, const uint64_t *k, const double *d,
-                      const double *v, const uint8_t *ok, const uint8_t *tie,
-                      int64_t n, uint32_t frame, int rule)
+/* Surface properties (c, cv may be NULL): Sec. IV-C fuses them with the
+ * same expressions, using their own variance cv in place of v.  A property
+ * observation rides on its voxel's distance observation (a voxel skipped
+ * for the distance skips its property too); one whose variance (rule 0) or
+ * weight 1 - cv (rule 1) is not positive and finite leaves the voxel's
+ * property unchanged.  A voxel with no property yet (NaN) takes the
+ * observation: (c, cv), or (c, 1 - cv) under rule 1. */
+int64_t orc_map_merge_prop(orc_map *g, const uint64_t *k, const double *d,
+                           const double *v, const uint8_t *ok, const uint8_t *tie,
+                           const double *c, const double *cv,
+                           int64_t n, uint32_t frame, int rule)
 {
     int64_t cap = g->n + n, i = 0, j = 0, w = 0, skipped = 0;
+    const int props = c != NULL || g->C != NULL;
+    double *nC = NULL, *nW = NULL;
+    if (props) {
+        nC = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
+        nW = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
+    }
     uint64_t *nk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(cap + 1));
     double *nD = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
     double *nV = (double *)malloc(sizeof(double) * (size_t)(cap + 1));
@@ -854,10 +941,31 @@ int64_t orc_map_merge(orc_map *g, const uint64_t *k, const double *d,
         if (!use_obs) {
             nk[w] = g->key[i]; nD[w] = g->D[i]; nV[w] = g->V[i]; ns[w] = g->stamp[i];
             nt[w] = g->tie[i];
+            if (props) {
+                nC[w] = g->C ? g->C[i] : NAN;
+                nW[w] = g->C ? g->W[i] : NAN;
+            }
             i++; w++;
         } else if (i < g->n && k[j] == g->key[i]) {
             double Vp = g->V[i], Dp = g->D[i];
             nk[w] = k[j];
+            if (props) {
+                double Cp = g->C ? g->C[i] : NAN, Wp = g->C ? g->W[i] : NAN;
+                nC[w] = Cp; nW[w] = Wp;
+                if (c && isfinite(c[j]) && isfinite(cv[j]) &&
+                    (rule == 1 ? 1.0 - cv[j] > 0.0 : cv[j] > 0.0)) {
+                    double wt = rule == 1 ? 1.0 - cv[j] : cv[j];
+                    if (isnan(Cp)) {
+                        nC[w] = c[j]; nW[w] = wt;
+                    } else if (rule == 1) {
+                        nC[w] = (wt * c[j] + Wp * Cp) / (Wp + wt);
+                        nW[w] = Wp + wt;
+                    } else {
+                        nC[w] = (Wp * c[j] + wt * Cp) / (Wp + wt);
+                        nW[w] = (Wp * wt) / (Wp + wt);
+                    }
+                }
+            }
             if (rule == 1) {
                 double wt = 1.0 - v[j];
                 nD[w] = (wt * d[j] + Vp * Dp) / (Vp + wt);
@@ -872,12 +980,37 @@ int64_t orc_map_merge(orc_map *g, const uint64_t *k, const double *d,
         } else {
             nk[w] = k[j]; nD[w] = d[j]; nV[w] = rule == 1 ? 1.0 - v[j] : v[j]; ns[w] = frame;
             nt[w] = tie ? tie[j] : 0;
+            if (props) {
+                nC[w] = NAN; nW[w] = NAN;
+                if (c && isfinite(c[j]) && isfinite(cv[j]) &&
+                    (rule == 1 ? 1.0 - cv[j] > 0.0 : cv[j] > 0.0)) {
+                    nC[w] = c[j]; nW[w] = rule == 1 ? 1.0 - cv[j] : cv[j];
+                }
+            }
             j++; w++;
         }
     }
     free(g->key); free(g->D); free(g->V); free(g->stamp); free(g->tie);
+    free(g->C); free(g->W);
     g->key = nk; g->D = nD; g->V = nV; g->stamp = ns; g->tie = nt; g->n = w;
+    g->C = nC; g->W = nW;
     return skipped;
+}
+
+int64_t orc_map_merge(orc_map *g, const uint64_t *k, const double *d,
+                      const double *v, const uint8_t *ok, const uint8_t *tie,
+                      int64_t n, uint32_t frame, int rule)
+{
+    return orc_map_merge_prop(g, k, d, v, ok, tie, NULL, NULL, n, frame, rule);
+}
+
+/* fused properties in key order (NaN where none); 0 if the map has none */
+int orc_map_export_prop(const orc_map *g, double *C, double *W)
+{
+    if (!g->C) return 0;
+    memcpy(C, g->C, sizeof(double) * (size_t)g->n);
+    memcpy(W, g->W, sizeof(double) * (size_t)g->n);
+    return 1;
 }
 
 /* One frame of fusion against an already trained model: test points, signed
@@ -896,8 +1029,16 @@ int64_t orc_fuse(orc_map *g, const orc_model *m, const float origin[3],
     int64_t sk;
     orc_test_points(m, k, n);
     orc_voxel_centres(k, n, m->p.fuse_voxel, x);
-    orc_query(m, x, n, origin, d, gr, v, ok, NULL, tie, nthreads);
-    sk = orc_map_merge(g, k, d, v, ok, tie, n, frame, m->p.fuse_rule);
+    {
+        double *c = NULL, *cv = NULL;
+        if (m->beta) {
+            c = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+            cv = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+        }
+        orc_query_prop(m, x, n, origin, d, gr, v, ok, NULL, tie, c, cv, nthreads);
+        sk = orc_map_merge_prop(g, k, d, v, ok, tie, c, cv, n, frame, m->p.fuse_rule);
+        free(c); free(cv);
+    }
     if (skipped) *skipped = sk;
     free(k); free(x); free(d); free(gr); free(v); free(ok); free(tie);
     return n;
@@ -964,6 +1105,44 @@ void orc_query_global(const orc_map *g, double h, const float *q, int64_t nq,
             }
             dist[j] = D; valid[j] = 1;
             for (int a = 0; a < 3; ++a) grad[3 * j + a] = G[a] / h;
+        }
+    }
+}
+
+/* Fused surface property at q: the same trilinear interpolation, of C;
+ * valid only when all eight voxels exist and hold a property.  Invalid
+ * queries give 0. */
+void orc_query_global_prop(const orc_map *g, double h, const float *q, int64_t nq,
+                           double *prop, uint8_t *valid)
+{
+    for (int64_t j = 0; j < nq; ++j) {
+        double u[3], f[3], Cc[8];
+        int64_t i0[3];
+        int okq = g->C != NULL;
+        for (int a = 0; a < 3 && okq; ++a) {
+            if (!isfinite(q[3 * j + a])) { okq = 0; break; }
+            u[a] = (double)q[3 * j + a] / h - 0.5;
+            i0[a] = (int64_t)floor(u[a]);
+            f[a] = u[a] - (double)i0[a];
+            if (i0[a] < -ORC_KEY_BIAS || i0[a] + 1 >= ORC_KEY_BIAS) okq = 0;
+        }
+        for (int b = 0; b < 8 && okq; ++b) {
+            int64_t k = orc_map_find(g, orc_pack(i0[0] + ((b >> 2) & 1),
+                                                 i0[1] + ((b >> 1) & 1),
+                                                 i0[2] + (b & 1)));
+            if (k < 0 || isnan(g->C[k])) okq = 0;
+            else Cc[b] = g->C[k];
+        }
+        if (!okq) { prop[j] = 0.0; valid[j] = 0; continue; }
+        {
+            double C = 0.0;
+            for (int b = 0; b < 8; ++b) {
+                double w0 = ((b >> 2) & 1) ? f[0] : 1.0 - f[0];
+                double w1 = ((b >> 1) & 1) ? f[1] : 1.0 - f[1];
+                double w2 = (b & 1) ? f[2] : 1.0 - f[2];
+                C += w0 * w1 * w2 * Cc[b];
+            }
+            prop[j] = C; valid[j] = 1;
         }
     }
 }

@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "SphereScene", "sphere_scene", "lidar_scene", "LidarScene", "lidar_frame",
     "lidar_band_queries", "planar_patches", "PatchScene", "sensor_path",
-    "sphere_eval_queries", "shuffle_rows", "jitter_points",
+    "sphere_eval_queries", "shuffle_rows", "jitter_points", "surface_intensity",
 ]
 
 
@@ -254,3 +254,15 @@ def jitter_points(points: np.ndarray, n: int, sigma: float, seed: int) -> np.nda
 def shuffle_rows(a: np.ndarray, seed: int) -> np.ndarray:
     """A seeded row permutation (used to check order independence)."""
     return a[np.random.default_rng(seed).permutation(a.shape[0])]
+
+
+# --------------------------------------------------------------------------
+# A surface property per point (LiDAR intensity, a colour channel).
+# --------------------------------------------------------------------------
+def surface_intensity(points: np.ndarray, seed: int, sigma: float = 0.01) -> np.ndarray:
+    """A smooth texture over space plus N(0, sigma) noise per point:
+    0.5 + 0.3 sin(1.3 x) cos(0.9 y) + 0.1 tanh(z), as float32 [n]."""
+    rng = np.random.default_rng(seed)
+    x = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    v = 0.5 + 0.3 * np.sin(1.3 * x[:, 0]) * np.cos(0.9 * x[:, 1]) + 0.1 * np.tanh(x[:, 2])
+    return (v + rng.normal(0.0, sigma, size=x.shape[0])).astype(np.float32)
