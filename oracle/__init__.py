@@ -91,7 +91,7 @@ def _bind(L):
     L.orc_train_prop.argtypes = [C.POINTER(Params), _P, _P, _I64, C.c_int]
     L.orc_train_prop.restype = _P
     L.orc_model_props.argtypes = [_P, _P, _P]
-    L.orc_query_prop.argtypes = [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int]
+    L.orc_query_prop.argtypes = [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int]
     L.orc_map_merge_prop.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _I64, C.c_uint32, C.c_int]
     L.orc_map_merge_prop.restype = _I64
     L.orc_map_export_prop.argtypes = [_P, _P, _P]
@@ -120,6 +120,12 @@ def _bind(L):
     L.orc_zero_crossings.restype = _I64
     L.orc_max_threads.restype = C.c_int
     return L
+
+
+class _Alt(C.Structure):
+    """Mirror of ``orc_alt``: the second-closest node's results."""
+    _fields_ = [("tie", C.c_void_p), ("dist", C.c_void_p), ("grad", C.c_void_p),
+                ("var", C.c_void_p), ("prop", C.c_void_p), ("prop_var", C.c_void_p)]
 
 
 def _ptr(a):
@@ -216,7 +222,10 @@ class Model:
         """Distance, gradient, variance, validity and aux (occupancy and
         latent variance of the closest node, points used) per query.  With an
         origin the result is signed and ``sign_tie`` marks the queries whose
-        sign an FP32 evaluation could decide the other way."""
+        sign an FP32 evaluation could decide the other way.  ``node_tie``
+        marks the queries whose second-closest node lies within 2e-4 m of the
+        closest, and ``alt`` holds their results with that node taken as the
+        closest (the other valid answer of the closest-node rule)."""
         x = _f32(q).reshape(-1, 3)
         m = x.shape[0]
         out = dict(dist=np.empty(m), grad=np.empty((m, 3)), var=np.empty(m),
@@ -226,10 +235,16 @@ class Model:
         if self.has_props:
             out["prop"] = np.empty(m)
             out["prop_var"] = np.empty(m)
+        alt = dict(tie=np.zeros(m, np.uint8), dist=np.zeros(m), grad=np.zeros((m, 3)), var=np.zeros(m),
+                   prop=np.zeros(m), prop_var=np.zeros(m))
+        ab = _Alt(*[_ptr(alt[k]) for k in ("tie", "dist", "grad", "var", "prop", "prop_var")])
         lib().orc_query_prop(self._h, _ptr(x), m, _ptr(o), _ptr(out["dist"]),
                              _ptr(out["grad"]), _ptr(out["var"]),
                              _ptr(out["valid"]), _ptr(out["aux"]), _ptr(out["sign_tie"]),
-                             _ptr(out.get("prop")), _ptr(out.get("prop_var")), int(nthreads))
+                             _ptr(out.get("prop")), _ptr(out.get("prop_var")), C.byref(ab), int(nthreads))
+        alt["tie"] = alt["tie"].astype(bool)
+        out["node_tie"] = alt["tie"]
+        out["alt"] = alt
         out["valid"] = out["valid"].astype(bool)
         out["sign_tie"] = out["sign_tie"].astype(bool)
         return out

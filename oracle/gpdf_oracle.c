@@ -678,6 +678,19 @@ static int orc_sign(const orc_model *m, const int64_t *sel, int ns, const float 
 /* ------------------------------------------------------------------------ */
 /* query: selection, per-pair inference, Eq. (10), sign                      */
 /* ------------------------------------------------------------------------ */
+/* The closest node (the pair of smallest distance) is an argmin that an FP32
+ * evaluation can take differently when two pairs lie close.  alt (may be
+ * NULL) reports, per query, whether the second-closest pair lies within
+ * ORC_NODE_TIE of the closest (alt->tie), and the results the query would
+ * have with that pair as the closest node (distance and gradient with the
+ * query's sign, variance, property and its variance) -- the other valid
+ * answer of the closest-node rule there. */
+#define ORC_NODE_TIE 2e-4
+typedef struct {
+    uint8_t *tie;
+    double *dist, *grad, *var, *prop, *prop_var;
+} orc_alt;
+
 /* prop, prop_var (may be NULL; need a model trained with properties): the
  * surface property (Eq. (6)) and its variance.  The property GP has the
  * distance GP's kernel and noise, so its posterior variance is the latent
@@ -688,7 +701,7 @@ static int orc_sign(const orc_model *m, const int64_t *sel, int ns, const float 
 void orc_query_prop(const orc_model *m, const float *q, int64_t nq,
                     const float *origin, double *dist, double *grad, double *var,
                     uint8_t *valid, double *aux, uint8_t *tie, double *prop,
-                    double *prop_var, int nthreads)
+                    double *prop_var, const orc_alt *alt, int nthreads)
 {
     const orc_params *p = &m->p;
     int64_t maxn = 1;
@@ -711,6 +724,7 @@ void orc_query_prop(const orc_model *m, const float *q, int64_t nq,
             int ns = orc_select(m, xf, sel);
             int64_t ntot = 0;
             if (tie) tie[j] = 0;
+            if (alt) alt->tie[j] = 0;
             if (ns == 0) {
                 dist[j] = INFINITY; var[j] = INFINITY; valid[j] = 0;
                 if (prop) prop[j] = 0.0;
@@ -756,13 +770,28 @@ void orc_query_prop(const orc_model *m, const float *q, int64_t nq,
                         for (int a = 0; a < 3; ++a) G[a] /= W;
                     }
                 }
-                if (origin) {
-                    uint8_t t = 0;
-                    if (orc_sign(m, sel, ns, xf, origin, &t) < 0) {
-                        D = -D;
-                        for (int a = 0; a < 3; ++a) G[a] = -G[a];
+                {
+                    double sg = 1.0;
+                    int a2 = -1;
+                    if (origin) {
+                        uint8_t t = 0;
+                        if (orc_sign(m, sel, ns, xf, origin, &t) < 0) {
+                            sg = -1.0;
+                            D = -D;
+                            for (int a = 0; a < 3; ++a) G[a] = -G[a];
+                        }
+                        if (tie) tie[j] = t;
                     }
-                    if (tie) tie[j] = t;
+                    for (int s = 0; s < ns; ++s)
+                        if (s != amin && (a2 < 0 || pr[s].d < pr[a2].d)) a2 = s;
+                    if (alt && a2 >= 0 && pr[a2].d - pr[amin].d <= ORC_NODE_TIE) {
+                        alt->tie[j] = 1;
+                        alt->dist[j] = sg * pr[a2].d;
+                        alt->var[j] = pr[a2].v;
+                        for (int a = 0; a < 3; ++a) alt->grad[3 * j + a] = sg * pr[a2].g[a];
+                        alt->prop[j] = pr[a2].c;
+                        alt->prop_var[j] = pr[a2].u;
+                    }
                 }
                 dist[j] = D; var[j] = V; valid[j] = 1;
                 if (prop) prop[j] = Cp;
@@ -784,7 +813,7 @@ void orc_query(const orc_model *m, const float *q, int64_t nq,
                const float *origin, double *dist, double *grad, double *var,
                uint8_t *valid, double *aux, uint8_t *tie, int nthreads)
 {
-    orc_query_prop(m, q, nq, origin, dist, grad, var, valid, aux, tie, NULL, NULL, nthreads);
+    orc_query_prop(m, q, nq, origin, dist, grad, var, valid, aux, tie, NULL, NULL, NULL, nthreads);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1035,7 +1064,7 @@ int64_t orc_fuse(orc_map *g, const orc_model *m, const float origin[3],
             c = (double *)malloc(sizeof(double) * (size_t)(n + 1));
             cv = (double *)malloc(sizeof(double) * (size_t)(n + 1));
         }
-        orc_query_prop(m, x, n, origin, d, gr, v, ok, NULL, tie, c, cv, nthreads);
+        orc_query_prop(m, x, n, origin, d, gr, v, ok, NULL, tie, c, cv, NULL, nthreads);
         sk = orc_map_merge_prop(g, k, d, v, ok, tie, c, cv, n, frame, m->p.fuse_rule);
         free(c); free(cv);
     }

@@ -779,3 +779,35 @@ def test_lower_cap_saturates_distance_and_zeroes_gradient():
     assert (r["grad"][:2] == 0.0).all()
     # inside the cap range the gradient is the unit direction (single point)
     assert abs(np.linalg.norm(r["grad"][2]) - 1.0) < 1e-3
+
+
+def test_closest_node_near_tie_reports_the_second_node():
+    # Two clusters mirrored across the cell boundary x = 0.4: queries on that
+    # plane see both at nearly the same distance (FP32 mirror images differ by
+    # rounding).  The oracle flags them as node near-ties and reports, as the
+    # alternative answer of the closest-node rule, the second cluster's own
+    # results (checked against each cluster trained on its own).
+    rng = np.random.default_rng(21)
+    a = rng.uniform([0.25, 0.02, 0.02], [0.38, 0.38, 0.38], size=(12, 3))
+    b = a.copy()
+    b[:, 0] = 0.8 - a[:, 0]
+    pts = np.concatenate([a, b]).astype(np.float32)
+    q = np.stack([np.full(40, 0.4), rng.uniform(0.05, 0.35, 40), rng.uniform(0.05, 0.35, 40)], 1).astype(np.float32)
+    prm = O.Params(cell=0.4, combine=1)
+    r = O.Model(prm, pts).query(q)
+    ra = O.Model(prm, pts[:12]).query(q)
+    rb = O.Model(prm, pts[12:]).query(q)
+    assert r["valid"].all() and r["node_tie"].all()
+    assert (np.abs(ra["dist"] - rb["dist"]) < 1e-5).all()
+    first_a = ra["dist"] <= rb["dist"]     # the closest is A where d_A <= d_B (A has the smaller key)
+    best = np.where(first_a[:, None], np.stack([ra["dist"], ra["var"]], 1), np.stack([rb["dist"], rb["var"]], 1))
+    other = np.where(first_a[:, None], np.stack([rb["dist"], rb["var"]], 1), np.stack([ra["dist"], ra["var"]], 1))
+    assert np.array_equal(np.stack([r["dist"], r["var"]], 1), best)
+    assert np.array_equal(np.stack([r["alt"]["dist"], r["alt"]["var"]], 1), other)
+    g_other = np.where(first_a[:, None], rb["grad"], ra["grad"])
+    assert np.array_equal(r["alt"]["grad"], g_other)
+    # the mirrored gradients differ in x: the two answers are genuinely different
+    assert (np.abs(ra["grad"][:, 0] - rb["grad"][:, 0]) > 0.1).any()
+    # far apart clusters: no near-tie
+    far = O.Model(prm, np.concatenate([a, a + np.float32(2.0)]).astype(np.float32)).query(q)
+    assert not far["node_tie"].any()
