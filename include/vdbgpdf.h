@@ -127,7 +127,12 @@ typedef struct {
                                   not trained yet (the lazily trained nodes
                                   of the G-GPDF, Sec. IV-D).  Not with
                                   gpdf_fuse_frame_graph. */
-    int32_t pad1;
+    int32_t properties;        /* 1: the context also carries one surface
+                                  property per point (intensity, a colour
+                                  channel; Eq. (6), Sec. IV-C): its GP, its
+                                  fusion and its global query (the *_prop
+                                  calls).  Needs FP32 or FP64 precision,
+                                  NEIGHBOR27 selection and lazy_train = 0. */
 } gpdf_params;
 
 typedef struct {
@@ -200,6 +205,18 @@ void gpdf_destroy(gpdf_ctx *ctx);
  * beyond the arenas), GPDF_E_INVALID_ARG. */
 gpdf_status gpdf_train_local_gps(gpdf_ctx *ctx, const float *d_xyz, int64_t n);
 
+/* gpdf_train_local_gps with a surface property per point, d_prop [n]
+ * (device; Eq. (6)).  The property of a training point is that of its raw
+ * points: in voxel mode their mean (summed in FP64 in input order), in raw
+ * mode the point's own.  The property GP of a cluster has the distance GP's
+ * kernel and noise s, so beta = (K + s^2 I)^{-1} c is solved on the same
+ * factor: beta = W^T (W c).  Properties are expected of order one (an
+ * intensity or colour channel in [0, 1]); the FP32 query refines them in
+ * FP64 beyond an estimated error of 2e-5 in their own units.
+ * Errors: GPDF_E_INVALID_ARG (properties = 0 in the parameters, or null
+ * pointers), and those of gpdf_train_local_gps. */
+gpdf_status gpdf_train_local_gps_prop(gpdf_ctx *ctx, const float *d_xyz, const float *d_prop, int64_t n);
+
 /* Distance field at d_q [m][3] from the current local GPs: per selected
  * cluster the latent occupancy (Eq. (1)), its variance (Eq. (2), posterior
  * minus sign), reverting (Eq. (3)), distance variance (Eq. (4)) and gradient
@@ -219,6 +236,19 @@ gpdf_status gpdf_query_distance(gpdf_ctx *ctx, const float *d_q, int64_t m,
                                 const float *h_origin, float *d_dist,
                                 float *d_grad, float *d_var, uint8_t *d_valid,
                                 float *d_aux, int32_t correct);
+
+/* gpdf_query_distance plus the surface property (Eq. (6)): per selected
+ * cluster c_q = k . beta and its variance, the latent variance u of
+ * Eq. (2) (the property GP's posterior variance); both combined over the
+ * clusters like the distance variance (smooth-minimum weights of the
+ * distances, or the closest node).  d_prop [m] and d_prop_var [m] (device;
+ * either may be NULL, not both); invalid queries get 0 and infinity.
+ * Errors: as gpdf_query_distance; GPDF_E_INVALID_ARG when the current
+ * model was trained without a property. */
+gpdf_status gpdf_query_distance_prop(gpdf_ctx *ctx, const float *d_q, int64_t m,
+                                     const float *h_origin, float *d_dist, float *d_grad,
+                                     float *d_var, uint8_t *d_valid, float *d_aux,
+                                     float *d_prop, float *d_prop_var);
 
 /* gpdf_query_distance for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
@@ -252,6 +282,18 @@ gpdf_status gpdf_query_distance_noalloc(gpdf_ctx *ctx, const float *d_q, int64_t
 gpdf_status gpdf_fuse_frame(gpdf_ctx *ctx, const float *d_xyz, int64_t n,
                             const float *h_origin);
 
+/* gpdf_fuse_frame with a surface property per point, d_prop [n] (device):
+ * trains with it (gpdf_train_local_gps_prop) and fuses the property of each
+ * test voxel beside its distance, with the same expressions and the
+ * property's variance w in place of v (Eq. (7)-(8); with GPDF_FUSE_TSDF the
+ * weight 1 - w): C <- (W c + w C) / (W + w), W <- W w / (W + w).  A voxel
+ * with no property yet takes (c, w); an observation whose variance (weight)
+ * is not positive and finite leaves the voxel's property unchanged.  Voxels
+ * fused by calls without a property hold none (NaN).
+ * Errors: as gpdf_fuse_frame and gpdf_train_local_gps_prop. */
+gpdf_status gpdf_fuse_frame_prop(gpdf_ctx *ctx, const float *d_xyz, const float *d_prop, int64_t n,
+                                 const float *h_origin);
+
 /* gpdf_fuse_frame as one replay of a captured HIP graph (batching
  * extension).  The first call records training, test voxels, their query and
  * the fusion with every count kept on the device and every grid sized by the
@@ -263,7 +305,8 @@ gpdf_status gpdf_fuse_frame(gpdf_ctx *ctx, const float *d_xyz, int64_t n,
  * max_queries cells (448 B each).  A capacity exceeded inside the graph
  * (max_clusters, max_cluster_points, max_factor_elems, max_queries) is not
  * returned: the affected clusters are left out and GPDF_STATUS_CAPACITY is
- * set in gpdf_stats.status_bits.
+ * set in gpdf_stats.status_bits.  The graph fuses no surface property (voxels
+ * it creates hold none).
  * Errors: GPDF_E_INVALID_ARG, GPDF_E_CAPACITY (n > max_points). */
 gpdf_status gpdf_fuse_frame_graph(gpdf_ctx *ctx, const float *d_xyz, int64_t n,
                                   const float *h_origin);
@@ -274,6 +317,13 @@ gpdf_status gpdf_fuse_frame_graph(gpdf_ctx *ctx, const float *d_xyz, int64_t n,
  * Outputs: d_dist [m], d_grad [m][3] (may be NULL), d_valid [m]. */
 gpdf_status gpdf_query_global(gpdf_ctx *ctx, const float *d_q, int64_t m,
                               float *d_dist, float *d_grad, uint8_t *d_valid);
+
+/* The fused surface property at d_q [m][3]: trilinear interpolation of C
+ * over the eight voxel centres around each point; valid only where all
+ * eight exist and hold a property.  Outputs (device): d_prop [m] (0 where
+ * invalid), d_valid [m].  Errors: GPDF_E_INVALID_ARG (properties = 0). */
+gpdf_status gpdf_query_global_prop(gpdf_ctx *ctx, const float *d_q, int64_t m, float *d_prop,
+                                   uint8_t *d_valid);
 
 /* Counters of the last calls (synchronises the stream). */
 gpdf_status gpdf_get_stats(gpdf_ctx *ctx, gpdf_stats *out);
@@ -294,6 +344,12 @@ gpdf_status gpdf_export_model(gpdf_ctx *ctx, uint64_t *h_ckey, int64_t *h_off,
 gpdf_status gpdf_export_global(gpdf_ctx *ctx, uint64_t *h_key, float *h_D,
                                float *h_V, uint32_t *h_stamp, int64_t cap,
                                int64_t *count);
+
+/* The fused property of every voxel of the global grid, in the order of
+ * gpdf_export_global (host arrays; C and W are NaN where none was fused).
+ * Errors: GPDF_E_INVALID_ARG (properties = 0). */
+gpdf_status gpdf_export_global_prop(gpdf_ctx *ctx, uint64_t *h_key, float *h_C, float *h_W,
+                                    int64_t cap, int64_t *count);
 
 /* Copy the sorted unique test-voxel keys of the last fused frame. */
 gpdf_status gpdf_export_test_points(gpdf_ctx *ctx, uint64_t *h_key,
@@ -318,7 +374,9 @@ gpdf_status gpdf_export_test_points(gpdf_ctx *ctx, uint64_t *h_key,
 gpdf_status gpdf_zero_crossings(gpdf_ctx *ctx, float *d_out, int64_t cap, int64_t *count);
 
 /* Write / read the global grid: a header (magic, version, voxel size, count,
- * frame counter) and the key-sorted (key, D, V, stamp) records. */
+ * frame counter) and the key-sorted (key, D, V, stamp) records; version 2
+ * (written with properties = 1) appends (C, W) to each record and loads only
+ * into a context with properties = 1. */
 gpdf_status gpdf_save_global(gpdf_ctx *ctx, const char *path);
 gpdf_status gpdf_load_global(gpdf_ctx *ctx, const char *path);
 

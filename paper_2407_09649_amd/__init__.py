@@ -42,7 +42,8 @@ EXPORTS = [
     "gpdf_set_tuning", "gpdf_get_tuning", "gpdf_autotune", "gpdf_fuse_frame_graph",
     "gpdf_mlp_get_weights", "gpdf_mlp_set_norm", "gpdf_mlp_get_norm", "gpdf_mlp_features",
     "gpdf_mlp_forward", "gpdf_mlp_grad", "gpdf_mlp_train", "gpdf_query_distance_noalloc",
-    "gpdf_zero_crossings",
+    "gpdf_zero_crossings", "gpdf_train_local_gps_prop", "gpdf_query_distance_prop",
+    "gpdf_fuse_frame_prop", "gpdf_query_global_prop", "gpdf_export_global_prop",
 ]
 
 
@@ -68,7 +69,7 @@ class Params(C.Structure):
         ("max_cluster_points", C.c_int64), ("max_factor_elems", C.c_int64),
         ("max_queries", C.c_int64), ("global_capacity", C.c_int64),
         ("fuse_rule", C.c_int32), ("test_points", C.c_int32), ("normal_reach", C.c_double),
-        ("lazy_train", C.c_int32), ("pad1", C.c_int32),
+        ("lazy_train", C.c_int32), ("properties", C.c_int32),
     ]
 
     @classmethod
@@ -127,6 +128,11 @@ def _bind(L):
         "gpdf_query_distance": [P, P, I64, P, P, P, P, P, P, C.c_int32],
         "gpdf_query_distance_noalloc": [P, P, I64, P, P, P, P, P, P, C.c_int32],
         "gpdf_fuse_frame": [P, P, I64, P],
+        "gpdf_train_local_gps_prop": [P, P, P, I64],
+        "gpdf_query_distance_prop": [P, P, I64, P, P, P, P, P, P, P, P],
+        "gpdf_fuse_frame_prop": [P, P, P, I64, P],
+        "gpdf_query_global_prop": [P, P, I64, P, P],
+        "gpdf_export_global_prop": [P, P, P, P, I64, P],
         "gpdf_query_global": [P, P, I64, P, P, P],
         "gpdf_get_stats": [P, P],
         "gpdf_export_model": [P, P, P, P, P, P],
@@ -236,6 +242,34 @@ class Context:
         _check(self.lib.gpdf_train_local_gps(self._h, _dptr(xyz, torch.float32, 3) if n else None, n),
                self._h)
 
+    def train_prop(self, xyz, prop):
+        """gpdf_train_local_gps_prop: training with a surface property per point."""
+        torch = self._torch
+        n = xyz.shape[0]
+        _check(self.lib.gpdf_train_local_gps_prop(self._h, _dptr(xyz, torch.float32, 3) if n else None,
+                                                  _dptr(prop, torch.float32) if n else None, n), self._h)
+
+    def query_prop(self, q, origin=None, grad=True, var=True, aux=True):
+        """gpdf_query_distance_prop: query() plus prop and prop_var."""
+        torch = self._torch
+        m = q.shape[0]
+        dev = self.device
+        r = {"dist": torch.empty(m, dtype=torch.float32, device=dev),
+             "valid": torch.empty(m, dtype=torch.uint8, device=dev),
+             "prop": torch.empty(m, dtype=torch.float32, device=dev),
+             "prop_var": torch.empty(m, dtype=torch.float32, device=dev)}
+        if grad:
+            r["grad"] = torch.empty((m, 3), dtype=torch.float32, device=dev)
+        if var:
+            r["var"] = torch.empty(m, dtype=torch.float32, device=dev)
+        if aux:
+            r["aux"] = torch.empty((m, 3), dtype=torch.float32, device=dev)
+        _check(self.lib.gpdf_query_distance_prop(
+            self._h, _dptr(q, torch.float32, 3) if m else None, m, _host3(origin), _dptr(r["dist"]),
+            _dptr(r.get("grad")), _dptr(r.get("var")), _dptr(r["valid"]), _dptr(r.get("aux")),
+            _dptr(r["prop"]), _dptr(r["prop_var"])), self._h)
+        return r
+
     def query(self, q, origin=None, grad=True, var=True, aux=True, correct=False, out=None):
         torch = self._torch
         m = q.shape[0]
@@ -276,6 +310,35 @@ class Context:
         _check(self.lib.gpdf_fuse_frame(
             self._h, _dptr(xyz, torch.float32, 3) if xyz is not None and n else None, n,
             _host3(origin)), self._h)
+
+    def fuse_prop(self, xyz, prop, origin):
+        """gpdf_fuse_frame_prop: train with a property per point and fuse it."""
+        torch = self._torch
+        n = xyz.shape[0]
+        _check(self.lib.gpdf_fuse_frame_prop(self._h, _dptr(xyz, torch.float32, 3),
+                                             _dptr(prop, torch.float32) if n else None, n,
+                                             _host3(origin)), self._h)
+
+    def query_global_prop(self, q):
+        torch = self._torch
+        m = q.shape[0]
+        prop = torch.empty(m, dtype=torch.float32, device=self.device)
+        valid = torch.empty(m, dtype=torch.uint8, device=self.device)
+        _check(self.lib.gpdf_query_global_prop(self._h, _dptr(q, torch.float32, 3) if m else None, m,
+                                               _dptr(prop), _dptr(valid)), self._h)
+        return {"prop": prop, "valid": valid}
+
+    def export_global_prop(self):
+        import numpy as np
+        cnt = C.c_int64(0)
+        _check(self.lib.gpdf_export_global_prop(self._h, None, None, None, 0, C.byref(cnt)), self._h)
+        n = cnt.value
+        k = np.empty(n, np.uint64)
+        Cp = np.empty(n, np.float32)
+        W = np.empty(n, np.float32)
+        P = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check(self.lib.gpdf_export_global_prop(self._h, P(k), P(Cp), P(W), n, C.byref(cnt)), self._h)
+        return dict(key=k, C=Cp, W=W)
 
     def fuse_graph(self, xyz, origin):
         """fuse() as one replay of a captured HIP graph (captured on the first

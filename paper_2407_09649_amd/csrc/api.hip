@@ -56,7 +56,8 @@ void release(gpdf_ctx *c) {
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     void *zptrs[] = {c->d_zkey, c->d_zkey2, c->d_zslot, c->d_zslot2, c->d_zcnt, c->d_zoff,
-                     c->d_zhist, c->d_zpart, c->d_ztile, c->d_ztoff, c->d_need, c->d_trained};
+                     c->d_zhist, c->d_zpart, c->d_ztile, c->d_ztoff, c->d_need, c->d_trained,
+                     c->d_cprop, c->d_beta64, c->d_beta32, c->d_gprop, c->d_tprop, c->d_tpropv};
     for (void *p : zptrs)
         if (p) (void)hipFree(p);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
@@ -107,7 +108,7 @@ extern "C" gpdf_status gpdf_params_default(gpdf_params *p) {
     p->test_points = GPDF_TEST_BAND;
     p->normal_reach = 0.2;
     p->lazy_train = 0;
-    p->pad1 = 0;
+    p->properties = 0;
     return GPDF_OK;
 }
 
@@ -138,7 +139,9 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
         (p->test_points != GPDF_TEST_BAND && p->test_points != GPDF_TEST_RAYCAST) ||
         !(std::isfinite(p->normal_reach) && p->normal_reach >= 0.0) ||
         (p->test_points == GPDF_TEST_RAYCAST && p->voxel_size <= 0.0) ||
-        (p->lazy_train != 0 && p->lazy_train != 1))
+        (p->lazy_train != 0 && p->lazy_train != 1) || (p->properties != 0 && p->properties != 1) ||
+        (p->properties && (p->precision == GPDF_PREC_BF16 || p->selection != GPDF_SEL_NEIGHBOR27 ||
+                           p->lazy_train)))
         return GPDF_E_INVALID_ARG;
     gpdf_ctx *c = new (std::nothrow) gpdf_ctx();
     if (!c) return GPDF_E_OOM;
@@ -189,6 +192,9 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
               dalloc(c->d_tpts, 3 * M, e) && dalloc(c->d_gslot, int64_t(c->gmask) + 1, e) &&
               dalloc(c->d_gstamp, int64_t(c->gmask) + 1, e) && dalloc(c->d_offs, c->offs_cap, e) &&
               dalloc(c->d_stat, ST_COUNT, e) && dalloc(c->d_spread, int64_t(kSpread) * kSpreadStride, e);
+    if (ok && p->properties)
+        ok = dalloc(c->d_cprop, P, e) && dalloc(c->d_beta64, P, e) && dalloc(c->d_beta32, P + kPtsPad, e) &&
+             dalloc(c->d_gprop, int64_t(c->gmask) + 1, e) && dalloc(c->d_tprop, M, e) && dalloc(c->d_tpropv, M, e);
     if (ok) {
         ok = (e = hipHostMalloc((void **)&c->h_stat, sizeof(unsigned long long) * ST_COUNT, 0)) == hipSuccess &&
              (e = hipHostMalloc((void **)&c->h_read, sizeof(unsigned long long) * ReadList::kMax, 0)) == hipSuccess;
@@ -219,6 +225,7 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
     // finite contents everywhere, pads included (masked FP32 rows read them)
     fill_u32(reinterpret_cast<uint32_t *>(c->d_pts), 0u, 4 * (P + kPtsPad), c->stream);
     fill_u32(reinterpret_cast<uint32_t *>(c->d_W32), 0u, c->cap_w + kW32Pad, c->stream);
+    if (c->d_beta32) fill_u32(reinterpret_cast<uint32_t *>(c->d_beta32), 0u, P + kPtsPad, c->stream);
     grid_clear(c, c->stream);
     fill_u64(c->d_chash, (unsigned long long)kNoKey, int64_t(c->chash_mask) + 1, c->stream);
     fill_u32(reinterpret_cast<uint32_t *>(c->d_need), 0u, (C + 4) / 4, c->stream);
@@ -248,6 +255,53 @@ extern "C" gpdf_status gpdf_train_local_gps(gpdf_ctx *c, const float *d_xyz, int
         return s;
     } catch (...) {
         return fail(c, GPDF_E_OOM, "train: host allocation failed");
+    }
+}
+
+extern "C" gpdf_status gpdf_train_local_gps_prop(gpdf_ctx *c, const float *d_xyz, const float *d_prop,
+                                                 int64_t n) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!d_xyz || !d_prop))) return fail(c, GPDF_E_INVALID_ARG, "train_prop: bad arguments");
+    try {
+        stage_begin(c, GPDF_MS_TRAIN);
+        gpdf_status s = train(c, d_xyz, n, nullptr, d_prop);
+        stage_end(c, GPDF_MS_TRAIN);
+        return s;
+    } catch (...) {
+        return fail(c, GPDF_E_OOM, "train_prop: host allocation failed");
+    }
+}
+
+extern "C" gpdf_status gpdf_query_distance_prop(gpdf_ctx *c, const float *d_q, int64_t m,
+                                                const float *h_origin, float *d_dist, float *d_grad,
+                                                float *d_var, uint8_t *d_valid, float *d_aux, float *d_prop,
+                                                float *d_prop_var) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    if (m > 0 && !d_prop && !d_prop_var) return fail(c, GPDF_E_INVALID_ARG, "query_prop: no property output");
+    try {
+        return query(c, d_q, m, h_origin, d_dist, d_grad, d_var, d_valid, d_aux, 0, nullptr, nullptr, false, d_prop,
+                     d_prop_var);
+    } catch (...) {
+        return fail(c, GPDF_E_OOM, "query_prop: host allocation failed");
+    }
+}
+
+extern "C" gpdf_status gpdf_fuse_frame_prop(gpdf_ctx *c, const float *d_xyz, const float *d_prop, int64_t n,
+                                            const float *h_origin) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    if (!d_xyz || (n > 0 && !d_prop)) return fail(c, GPDF_E_INVALID_ARG, "fuse_prop: bad arguments");
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
+    if (!h_origin || !(std::isfinite(h_origin[0]) && std::isfinite(h_origin[1]) &&
+                       std::isfinite(h_origin[2])))
+        return fail(c, GPDF_E_INVALID_ARG, "fuse_prop: origin required");
+    try {
+        stage_begin(c, GPDF_MS_TRAIN);
+        gpdf_status s = train(c, d_xyz, n, nullptr, d_prop);
+        stage_end(c, GPDF_MS_TRAIN);
+        if (s != GPDF_OK) return s;
+        return fuse(c, h_origin);
+    } catch (...) {
+        return fail(c, GPDF_E_OOM, "fuse_prop: host allocation failed");
     }
 }
 

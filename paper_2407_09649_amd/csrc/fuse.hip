@@ -104,15 +104,36 @@ __device__ inline bool grid_resolve(const GSlot *__restrict__ g, uint32_t gmask,
     return false;
 }
 
+// the slot of a voxel, or -1 when the grid does not hold it
+__device__ inline int64_t grid_find(const GSlot *__restrict__ g, uint32_t gmask, uint64_t key) {
+    uint64_t s = grid_start(key, gmask);
+    const uint32_t ngroups = (gmask >> 3) + 1;
+    for (uint32_t p = 0; p < ngroups; ++p) {
+        const uint64_t k = g[s].key;
+        if (k == key) return int64_t(s);
+        if (k == kNoKey) return -1;
+        s = (s + 8) & gmask;
+    }
+    return -1;
+}
+
 // Eq. (7)-(8): D <- (V d + v D) / (V + v), V <- V v / (V + v); an absent voxel
 // takes (d, v) (the V = infinity limit).
 // TSDF (Eq. (9)): weight w = 1 - v, D <- (w d + V D) / (V + w), V <- V + w; an
 // absent voxel takes (d, w); w <= 0 carries no weight and is skipped.
+//
+// Surface property (gprop != NULL; Sec. IV-C): the same expressions with the
+// property's variance w in place of v (TSDF: weight 1 - w).  It rides on the
+// voxel's distance observation; an observation whose variance (weight) is not
+// positive and finite, or a frame without a property (cp == NULL), leaves the
+// voxel's property as it is, and a new voxel then holds none (NaN).  A voxel
+// with no property takes the observation as is.
 __global__ void k_fuse(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ nptr,
                        const float *__restrict__ d, const float *__restrict__ v,
                        const uint8_t *__restrict__ ok, GSlot *__restrict__ g, uint32_t gmask,
                        uint32_t *__restrict__ gstamp, uint32_t frame_h, const uint32_t *__restrict__ dframe,
-                       unsigned long long *__restrict__ spread, int tsdf) {
+                       unsigned long long *__restrict__ spread, int tsdf, const float *__restrict__ cp,
+                       const float *__restrict__ cpv, float2 *__restrict__ gprop) {
     const int64_t n = int64_t(*nptr);
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (int64_t(blockIdx.x) * blockDim.x >= n) return;  // whole block past the end
@@ -143,6 +164,72 @@ __global__ void k_fuse(const uint64_t *__restrict__ keys, const uint32_t *__rest
         g[s].V = (Vp * vi) / den;
     }
     gstamp[s] = dframe ? *dframe : frame_h;
+    if (gprop) {
+        const float ci = cp ? cp[i] : 0.f, wi2 = cp ? cpv[i] : 0.f;
+        const float wt = tsdf ? 1.f - wi2 : wi2;
+        const bool pok = cp && isfinite(ci) && isfinite(wi2) && wt > 0.f;
+        if (ins || pok) {
+            float2 P = ins ? make_float2(NAN, NAN) : gprop[s];
+            if (pok) {
+                if (isnan(P.x)) {
+                    P = make_float2(ci, wt);
+                } else if (tsdf) {
+                    const float den = P.y + wt;
+                    P = make_float2((wt * ci + P.y * P.x) / den, den);
+                } else {
+                    const float den = P.y + wt;
+                    P = make_float2((P.y * ci + wt * P.x) / den, (P.y * wt) / den);
+                }
+            }
+            gprop[s] = P;
+        }
+    }
+}
+
+// trilinear interpolation of the fused property C over the eight voxel
+// centres around x; valid where all eight exist and hold a property
+__global__ void k_global_query_prop(const float *__restrict__ q, int64_t m, double h,
+                                    const GSlot *__restrict__ g, const float2 *__restrict__ gprop,
+                                    uint32_t gmask, float *__restrict__ prop, uint8_t *__restrict__ valid) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double f[3];
+    int64_t i0[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        const float x = q[3 * j + a];
+        if (!isfinite(x)) { ok = false; break; }
+        const double u = double(x) / h - 0.5;
+        const double fl = floor(u);
+        if (fl < -double(kBias) || fl + 1.0 >= double(kBias)) { ok = false; break; }
+        i0[a] = int64_t(fl);
+        f[a] = u - fl;
+    }
+    double Cc[8];
+    if (ok) {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t key = pack_key(i0[0] + ((b >> 2) & 1), i0[1] + ((b >> 1) & 1), i0[2] + (b & 1));
+            const int64_t sl = grid_find(g, gmask, key);
+            const float cb = sl >= 0 ? gprop[sl].x : NAN;
+            ok = ok && !isnan(cb);
+            Cc[b] = double(cb);
+        }
+    }
+    if (!ok) {
+        prop[j] = 0.f;
+        valid[j] = 0;
+        return;
+    }
+    double C = 0.0;
+    for (int b = 0; b < 8; ++b) {
+        const int bx = (b >> 2) & 1, by = (b >> 1) & 1, bz = b & 1;
+        const double wx = bx ? f[0] : 1.0 - f[0], wy = by ? f[1] : 1.0 - f[1],
+                     wz = bz ? f[2] : 1.0 - f[2];
+        C += wx * wy * wz * Cc[b];
+    }
+    prop[j] = float(C);
+    valid[j] = 1;
 }
 
 // trilinear interpolation of D over the eight voxel centres around x
@@ -212,7 +299,8 @@ __global__ void k_global_query(const float *__restrict__ q, int64_t m, double h,
 __global__ void k_global_load(const uint64_t *__restrict__ k, const float *__restrict__ D,
                               const float *__restrict__ V, const uint32_t *__restrict__ st, int64_t n,
                               GSlot *__restrict__ g, uint32_t gmask, uint32_t *__restrict__ gs,
-                              unsigned long long *__restrict__ stat) {
+                              unsigned long long *__restrict__ stat, const float2 *__restrict__ cw,
+                              float2 *__restrict__ gprop) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     bool ins = false;
     int64_t s = -1;
@@ -223,12 +311,15 @@ __global__ void k_global_load(const uint64_t *__restrict__ k, const float *__res
     g[s].D = D[i];
     g[s].V = V[i];
     gs[s] = st[i];
+    if (gprop) gprop[s] = cw ? cw[i] : make_float2(NAN, NAN);
 }
 
-__global__ void k_grid_clear(GSlot *__restrict__ g, int64_t n) {
+__global__ void k_grid_clear(GSlot *__restrict__ g, int64_t n, float2 *__restrict__ gprop) {
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
         g[i] = GSlot{(unsigned long long)kNoKey, 0.f, 0.f};
+        if (gprop) gprop[i] = make_float2(NAN, NAN);
+    }
 }
 
 // brute-force nearest distance, FP32 differences, exact minimum
@@ -331,13 +422,17 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin, int64_
         nt = int64_t(t);
         c->last_test = nt;
     }
+    // a model trained with a property fuses it too (Sec. IV-C)
+    const bool props = M.props && c->d_gprop;
     st = query(c, c->d_tpts, nt, origin, c->d_tmp_dist, nullptr, c->d_tmp_var, c->d_tmp_valid, nullptr, 0,
-               eager ? nullptr : cnt + CNT_TEST, d_origin);
+               eager ? nullptr : cnt + CNT_TEST, d_origin, false, props ? c->d_tprop : nullptr,
+               props ? c->d_tpropv : nullptr);
     if (st != GPDF_OK) return st;
     stage_begin(c, GPDF_MS_FUSE);
     hipLaunchKernelGGL(k_fuse, dim3(blocks_for(nt)), dim3(kT), 0, s, c->d_tkeys, cnt + CNT_TEST, c->d_tmp_dist,
                        c->d_tmp_var, c->d_tmp_valid, c->d_gslot, c->gmask, c->d_gstamp, c->frame,
-                       eager ? nullptr : cnt + CNT_FRAME, c->d_spread, c->p.fuse_rule == GPDF_FUSE_TSDF ? 1 : 0);
+                       eager ? nullptr : cnt + CNT_FRAME, c->d_spread, c->p.fuse_rule == GPDF_FUSE_TSDF ? 1 : 0,
+                       props ? c->d_tprop : nullptr, props ? c->d_tpropv : nullptr, c->d_gprop);
     fold_stats(c->d_spread, c->d_stat, s);
     stage_end(c, GPDF_MS_FUSE);
     if (eager) c->frame++;
@@ -539,10 +634,21 @@ gpdf_status query_global(gpdf_ctx *c, const float *d_q, int64_t m, float *dist, 
     return e == hipSuccess ? GPDF_OK : hip_fail(c, e, "query_global launch");
 }
 
+gpdf_status query_global_prop(gpdf_ctx *c, const float *d_q, int64_t m, float *prop, uint8_t *valid) {
+    if (!c->d_gprop) return fail(c, GPDF_E_INVALID_ARG, "query_global_prop: properties are off in the parameters");
+    if (m < 0) return fail(c, GPDF_E_INVALID_ARG, "query_global_prop: m < 0");
+    if (m == 0) return GPDF_OK;
+    if (!d_q || !prop || !valid) return fail(c, GPDF_E_INVALID_ARG, "query_global_prop: null buffer");
+    hipLaunchKernelGGL(k_global_query_prop, dim3(blocks_for(m)), dim3(kT), 0, c->stream, d_q, m,
+                       c->p.fuse_voxel_size, c->d_gslot, c->d_gprop, c->gmask, prop, valid);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GPDF_OK : hip_fail(c, e, "query_global_prop launch");
+}
+
 void grid_clear(gpdf_ctx *c, hipStream_t s) {
     const int64_t n = int64_t(c->gmask) + 1;
     hipLaunchKernelGGL(k_grid_clear, dim3(unsigned(std::min<int64_t>((n + kT - 1) / kT, 65536))), dim3(kT), 0, s,
-                       c->d_gslot, n);
+                       c->d_gslot, n, c->d_gprop);
 }
 
 gpdf_status nearest_distance(gpdf_ctx *c, const float *pts, int64_t n, const float *q, int64_t m,
@@ -564,20 +670,25 @@ struct Rec {
     uint64_t k;
     float D, V;
     uint32_t st;
+    float C, W;   // fused property (NaN: none, or properties off)
 };
 
 gpdf_status read_global(gpdf_ctx *c, std::vector<Rec> &out) {
     const int64_t cap = int64_t(c->gmask) + 1;
     std::vector<GSlot> g(cap);
     std::vector<uint32_t> st(cap);
+    std::vector<float2> cw(c->d_gprop ? cap : 0);
     hipError_t e;
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess ||
         (e = hipMemcpy(g.data(), c->d_gslot, sizeof(GSlot) * cap, hipMemcpyDeviceToHost)) != hipSuccess ||
-        (e = hipMemcpy(st.data(), c->d_gstamp, 4 * cap, hipMemcpyDeviceToHost)) != hipSuccess)
+        (e = hipMemcpy(st.data(), c->d_gstamp, 4 * cap, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (c->d_gprop &&
+         (e = hipMemcpy(cw.data(), c->d_gprop, sizeof(float2) * cap, hipMemcpyDeviceToHost)) != hipSuccess))
         return hip_fail(c, e, "read global grid");
     out.clear();
     for (int64_t i = 0; i < cap; ++i)
-        if (g[i].key != kNoKey) out.push_back(Rec{g[i].key, g[i].D, g[i].V, st[i]});
+        if (g[i].key != kNoKey)
+            out.push_back(Rec{g[i].key, g[i].D, g[i].V, st[i], c->d_gprop ? cw[i].x : NAN, c->d_gprop ? cw[i].y : NAN});
     std::sort(out.begin(), out.end(), [](const Rec &a, const Rec &b) { return a.k < b.k; });
     return GPDF_OK;
 }
@@ -599,6 +710,31 @@ extern "C" gpdf_status gpdf_export_global(gpdf_ctx *c, uint64_t *h_key, float *h
         if (h_stamp) h_stamp[i] = r[i].st;
     }
     return GPDF_OK;
+}
+
+extern "C" gpdf_status gpdf_export_global_prop(gpdf_ctx *c, uint64_t *h_key, float *h_C, float *h_W,
+                                               int64_t cap, int64_t *count) {
+    if (!c || !count) return GPDF_E_INVALID_ARG;
+    if (!c->d_gprop) return fail(c, GPDF_E_INVALID_ARG, "export_global_prop: properties are off in the parameters");
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
+    std::vector<Rec> r;
+    gpdf_status s = read_global(c, r);
+    if (s != GPDF_OK) return s;
+    *count = int64_t(r.size());
+    if (int64_t(r.size()) > cap) return GPDF_OK;
+    for (size_t i = 0; i < r.size(); ++i) {
+        if (h_key) h_key[i] = r[i].k;
+        if (h_C) h_C[i] = r[i].C;
+        if (h_W) h_W[i] = r[i].W;
+    }
+    return GPDF_OK;
+}
+
+extern "C" gpdf_status gpdf_query_global_prop(gpdf_ctx *c, const float *d_q, int64_t m, float *d_prop,
+                                              uint8_t *d_valid) {
+    if (!c) return GPDF_E_INVALID_ARG;
+    if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "join");
+    return query_global_prop(c, d_q, m, d_prop, d_valid);
 }
 
 extern "C" gpdf_status gpdf_zero_crossings(gpdf_ctx *c, float *d_out, int64_t cap, int64_t *count) {
@@ -647,11 +783,14 @@ extern "C" gpdf_status gpdf_save_global(gpdf_ctx *c, const char *path) {
     if (s != GPDF_OK) return s;
     FILE *f = std::fopen(path, "wb");
     if (!f) return fail(c, GPDF_E_INVALID_ARG, "save_global: cannot open file");
-    FileHeader h{kMagic, 1u, c->frame, c->p.fuse_voxel_size, int64_t(r.size())};
+    // version 1: (key, D, V, stamp); version 2 adds the property (C, W)
+    const uint32_t ver = c->d_gprop ? 2u : 1u;
+    FileHeader h{kMagic, ver, c->frame, c->p.fuse_voxel_size, int64_t(r.size())};
     bool ok = std::fwrite(&h, sizeof h, 1, f) == 1;
     for (size_t i = 0; ok && i < r.size(); ++i) {
         ok = std::fwrite(&r[i].k, 8, 1, f) == 1 && std::fwrite(&r[i].D, 4, 1, f) == 1 &&
              std::fwrite(&r[i].V, 4, 1, f) == 1 && std::fwrite(&r[i].st, 4, 1, f) == 1;
+        if (ok && ver == 2u) ok = std::fwrite(&r[i].C, 4, 1, f) == 1 && std::fwrite(&r[i].W, 4, 1, f) == 1;
     }
     ok = (std::fclose(f) == 0) && ok;
     return ok ? GPDF_OK : fail(c, GPDF_E_INVALID_ARG, "save_global: write failed");
@@ -663,10 +802,14 @@ extern "C" gpdf_status gpdf_load_global(gpdf_ctx *c, const char *path) {
     FILE *f = std::fopen(path, "rb");
     if (!f) return fail(c, GPDF_E_INVALID_ARG, "load_global: cannot open file");
     FileHeader h{};
-    if (std::fread(&h, sizeof h, 1, f) != 1 || h.magic != kMagic || h.version != 1u || h.count < 0 ||
-        h.voxel != c->p.fuse_voxel_size) {
+    if (std::fread(&h, sizeof h, 1, f) != 1 || h.magic != kMagic || (h.version != 1u && h.version != 2u) ||
+        h.count < 0 || h.voxel != c->p.fuse_voxel_size) {
         std::fclose(f);
         return fail(c, GPDF_E_INVALID_ARG, "load_global: bad header or voxel size");
+    }
+    if (h.version == 2u && !c->d_gprop) {
+        std::fclose(f);
+        return fail(c, GPDF_E_INVALID_ARG, "load_global: the file holds properties and properties are off");
     }
     if (h.count > c->p.global_capacity) {
         std::fclose(f);
@@ -675,10 +818,13 @@ extern "C" gpdf_status gpdf_load_global(gpdf_ctx *c, const char *path) {
     std::vector<uint64_t> k(h.count);
     std::vector<float> D(h.count), V(h.count);
     std::vector<uint32_t> st(h.count);
+    std::vector<float2> cw(h.version == 2u ? h.count : 0);
     bool ok = true;
-    for (int64_t i = 0; ok && i < h.count; ++i)
+    for (int64_t i = 0; ok && i < h.count; ++i) {
         ok = std::fread(&k[i], 8, 1, f) == 1 && std::fread(&D[i], 4, 1, f) == 1 &&
              std::fread(&V[i], 4, 1, f) == 1 && std::fread(&st[i], 4, 1, f) == 1;
+        if (ok && h.version == 2u) ok = std::fread(&cw[i].x, 4, 1, f) == 1 && std::fread(&cw[i].y, 4, 1, f) == 1;
+    }
     std::fclose(f);
     if (!ok) return fail(c, GPDF_E_INVALID_ARG, "load_global: truncated file");
     hipStream_t s = c->stream;
@@ -691,18 +837,23 @@ extern "C" gpdf_status gpdf_load_global(gpdf_ctx *c, const char *path) {
     uint64_t *dk = nullptr;
     float *dD = nullptr, *dV = nullptr;
     uint32_t *ds = nullptr;
+    float2 *dcw = nullptr;
     if ((e = hipMallocAsync((void **)&dk, 8 * h.count, s)) != hipSuccess ||
         (e = hipMallocAsync((void **)&dD, 4 * h.count, s)) != hipSuccess ||
         (e = hipMallocAsync((void **)&dV, 4 * h.count, s)) != hipSuccess ||
-        (e = hipMallocAsync((void **)&ds, 4 * h.count, s)) != hipSuccess)
+        (e = hipMallocAsync((void **)&ds, 4 * h.count, s)) != hipSuccess ||
+        (!cw.empty() && (e = hipMallocAsync((void **)&dcw, sizeof(float2) * h.count, s)) != hipSuccess))
         return hip_fail(c, e, "load_global: allocate staging");
     if ((e = hipMemcpyAsync(dk, k.data(), 8 * h.count, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(dD, D.data(), 4 * h.count, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(dV, V.data(), 4 * h.count, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(ds, st.data(), 4 * h.count, hipMemcpyHostToDevice, s)) != hipSuccess)
+        (e = hipMemcpyAsync(ds, st.data(), 4 * h.count, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (dcw && (e = hipMemcpyAsync(dcw, cw.data(), sizeof(float2) * h.count, hipMemcpyHostToDevice, s)) !=
+                    hipSuccess))
         return hip_fail(c, e, "load_global: upload");
     hipLaunchKernelGGL(k_global_load, dim3(unsigned((h.count + kT - 1) / kT)), dim3(kT), 0, s, dk, dD,
-                       dV, ds, h.count, c->d_gslot, c->gmask, c->d_gstamp, c->d_stat);
+                       dV, ds, h.count, c->d_gslot, c->gmask, c->d_gstamp, c->d_stat, dcw, c->d_gprop);
+    if (dcw) hipFreeAsync(dcw, s);
     hipFreeAsync(dk, s);
     hipFreeAsync(dD, s);
     hipFreeAsync(dV, s);

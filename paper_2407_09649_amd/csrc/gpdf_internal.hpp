@@ -333,6 +333,7 @@ struct QueryConsts {
     float lam;              // smooth-minimum lambda
     float omin, omax;
     float tau_d, tau_g, tau_v;  // FP32 error-estimate thresholds for FP64 refinement
+    float tau_c;                // the same for the surface property (absolute)
     float err_c;            // error-bound constant on sum |alpha k|
     int kernel, combine, grad_mode, knn_q;
     int signed_, has_origin_pad;
@@ -351,6 +352,7 @@ struct Model {
     bool bf16_ready = false;   // BF16 copies of [W; alpha] built for this model
     bool host_counts = false;  // counts below were read back (eager calls)
     bool lazy = false;         // clusters are factored when a query selects them
+    bool props = false;        // trained with a surface property (beta valid)
     int64_t ntrained = 0;      // clusters factored (host count, eager calls)
 };
 
@@ -398,6 +400,9 @@ struct gpdf_ctx {
     uint32_t *d_wo32 = nullptr, *d_ao32 = nullptr; // their exclusive scans
     float4 *d_pts = nullptr;                       // training points (x, y, z, alpha32)
     double *d_alpha64 = nullptr;                   // alpha in FP64
+    double *d_cprop = nullptr;                     // property of each training point (FP64), properties = 1
+    double *d_beta64 = nullptr;                    // (K + s^2 I)^{-1} c per point (Eq. (6))
+    float *d_beta32 = nullptr;                     // its FP32 copy, with a zero tail pad of 64
     uint64_t *d_ckey = nullptr;                    // cluster keys [max_clusters]
     int32_t *d_coff = nullptr;                     // CSR offsets  [max_clusters + 1]
     uint8_t *d_pd = nullptr;                       // positive definite
@@ -448,6 +453,9 @@ struct gpdf_ctx {
     float *d_tpts = nullptr;                       // test points [3]
     gpdf::GSlot *d_gslot = nullptr;                // global grid slots (key, D, V)
     uint32_t *d_gstamp = nullptr;
+    float2 *d_gprop = nullptr;                     // per slot: fused property C and its variance or weight W
+                                                   // (NaN: none fused yet), properties = 1
+    float *d_tprop = nullptr, *d_tpropv = nullptr; // property query of the test voxels
     uint32_t gmask = 0;
     uint32_t frame = 0;
     std::vector<int4> h_offs;                      // band offsets (host)
@@ -578,14 +586,18 @@ hipError_t read_back(gpdf_ctx *c, const ReadList &L, hipStream_t s);
 void grid_clear(gpdf_ctx *c, hipStream_t s);
 
 // stages (train.hip, query.hip, fuse.hip, mlp.hip)
-gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn = nullptr);
+// d_prop (may be NULL): a surface property per input point (Eq. (6))
+gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn = nullptr,
+                  const float *d_prop = nullptr);
 // With dm (a device count of queries, at most m) and optionally d_origin, the
 // call reads nothing back and can be captured in a graph.
 gpdf_status scratch_setup(gpdf_ctx *c);
 gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin, float *dist,
                   float *grad, float *var, uint8_t *valid, float *aux, int32_t correct,
-                  const uint32_t *dm = nullptr, const float *d_origin = nullptr, bool noalloc = false);
+                  const uint32_t *dm = nullptr, const float *d_origin = nullptr, bool noalloc = false,
+                  float *prop = nullptr, float *prop_var = nullptr);
 gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin = nullptr, int64_t npts_bound = -1);
+gpdf_status query_global_prop(gpdf_ctx *c, const float *d_q, int64_t m, float *prop, uint8_t *valid);
 gpdf_status zero_crossings(gpdf_ctx *c, float *d_out, int64_t cap, int64_t *count);
 // lazy training: factor the clusters marked in d_need that are not trained
 // yet (one round; *ntrained receives their number)

@@ -63,8 +63,12 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgc
 // bit kNoGrad, that the call asked for no gradient: the FP32 instances then
 // leave out the gradient sums, its reverting and its error estimate.
 constexpr int kNoGrad = 8;
+// the bit kProp: the model carries a surface property and the call asks for
+// it (Eq. (6)): one more product k . beta per point and its combination
+constexpr int kProp = 16;
 constexpr int kern_kind(int k) { return k & 7; }
 constexpr bool kern_grad(int k) { return (k & kNoGrad) == 0; }
+constexpr bool kern_prop(int k) { return (k & kProp) != 0; }
 
 // Data that no kernel of a launch writes (model arrays, cell lists, chunk
 // table, counts) is read through the constant address space.  That tells
@@ -144,12 +148,14 @@ __device__ inline bool query_cell(const float *x, int voxel_mode, double hv, dou
 }
 
 __device__ inline void write_invalid(uint32_t qi, float *dist, float *grad, float *var,
-                                     uint8_t *valid, float *aux) {
+                                     uint8_t *valid, float *aux, float *prop, float *prop_var) {
     dist[qi] = INFINITY;
     valid[qi] = 0;
     if (grad) { grad[3 * qi] = 0.f; grad[3 * qi + 1] = 0.f; grad[3 * qi + 2] = 0.f; }
     if (var) var[qi] = INFINITY;
     if (aux) { aux[3 * qi] = 0.f; aux[3 * qi + 1] = 0.f; aux[3 * qi + 2] = 0.f; }
+    if (prop) prop[qi] = 0.f;
+    if (prop_var) prop_var[qi] = INFINITY;
 }
 
 // ---------------------------------------------------------------------------
@@ -158,7 +164,8 @@ __device__ inline void write_invalid(uint32_t qi, float *dist, float *grad, floa
 __global__ void k_qcells(const float *__restrict__ q, int64_t mb, const uint32_t *__restrict__ dm, int voxel_mode,
                          double hv, double hc, HashView qh, uint32_t *__restrict__ cnt, int32_t *__restrict__ qslot,
                          uint32_t *__restrict__ qrank, float *dist, float *grad, float *var,
-                         uint8_t *valid, float *aux, unsigned long long *__restrict__ stat) {
+                         uint8_t *valid, float *aux, float *prop, float *prop_var,
+                         unsigned long long *__restrict__ stat) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t m = dev_count(mb, dm);
     if (int64_t(blockIdx.x) * blockDim.x >= m) return;  // whole block past the end
@@ -195,7 +202,7 @@ __global__ void k_qcells(const float *__restrict__ q, int64_t mb, const uint32_t
     if (!in) return;
     if (s < 0) {
         qslot[i] = -1;
-        write_invalid(uint32_t(i), dist, grad, var, valid, aux);
+        write_invalid(uint32_t(i), dist, grad, var, valid, aux, prop, prop_var);
         return;
     }
     qslot[i] = int32_t(s);
@@ -300,9 +307,9 @@ __global__ void k_scatter_order(const int32_t *__restrict__ qslot, const uint32_
 }
 
 __global__ void k_all_invalid(int64_t m, float *dist, float *grad, float *var, uint8_t *valid,
-                              float *aux) {
+                              float *aux, float *prop, float *prop_var) {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < m) write_invalid(uint32_t(i), dist, grad, var, valid, aux);
+    if (i < m) write_invalid(uint32_t(i), dist, grad, var, valid, aux, prop, prop_var);
 }
 
 // refine records (cell, query) -> counting sort by cell
@@ -368,6 +375,8 @@ struct PairRaw {
     T o, gx, gy, gz;
     T ss;
     float S;   // sum of squared term scales (FP32 error estimate)
+    T c;       // property k . beta (Eq. (6))
+    float Sc;  // its sum of squared term scales
 };
 
 template <typename T>
@@ -378,6 +387,8 @@ struct Acc {
     float A1, A2, B1, C1;                  // error-estimate sums (smooth-min scaled, FP32 only)
     float Ggx, Ggy, Ggz, G2;               // sum w e_d g and w e_d |g|^2
     float hed, heg, hev, sum_eg;           // closest node estimates, plain sum of e_g
+    T swc, swu, hc;                        // property and latent variance: weighted sums, closest node
+    float Cc1, Mc1, Mc2, hec;              // property error sums: w e_c, w e_d c, w e_d c^2; closest node
     int nq, ntot;
     float best;                            // nearest training point (FP32 decision)
     int bidx;
@@ -392,6 +403,8 @@ __device__ inline void acc_init(Acc<T> &A) {
     A.A1 = A.A2 = A.B1 = A.C1 = 0.f;
     A.Ggx = A.Ggy = A.Ggz = A.G2 = 0.f;
     A.hed = A.heg = A.hev = A.sum_eg = 0.f;
+    A.swc = A.swu = A.hc = T(0);
+    A.Cc1 = A.Mc1 = A.Mc2 = A.hec = 0.f;
     A.nq = 0; A.ntot = 0;
     A.best = INFINITY; A.bidx = -1;
 }
@@ -409,7 +422,7 @@ struct QueryPoint {
 template <typename T, int KERN>
 __device__ __forceinline__ T point_eval(const float4 p, T alpha, const QueryPoint &Q, int gidx,
                                         const QueryConsts &C, PairRaw<T> &r, Acc<T> &A,
-                                        bool live = true) {
+                                        bool live = true, T beta = T(0)) {
     // nearest training point, decided in FP32 in a fixed order
     {
         const float ex = Q.fx - p.x, ey = Q.fy - p.y, ez = Q.fz - p.z;
@@ -447,7 +460,23 @@ __device__ __forceinline__ T point_eval(const float4 p, T alpha, const QueryPoin
         const float akt = fabsf(alpha) * fmaf(k, t, k);
         r.S = fmaf(akt, akt, r.S);
     }
+    if constexpr (kern_prop(KERN)) {
+        // the property GP shares the kernel values (Eq. (6))
+        const T bl = live ? beta : T(0);
+        r.c = fma(bl, k, r.c);
+        if constexpr (std::is_same<T, float>::value) {
+            const float bkt = fabsf(bl) * fmaf(k, t, k);
+            r.Sc = fmaf(bkt, bkt, r.Sc);
+        }
+    }
     return k;
+}
+
+// beta of point i of a cluster (FP64 array), 0 when the launch has no property
+template <typename T, int KERN>
+__device__ __forceinline__ T beta_of(const double *__restrict__ b64, int i) {
+    if constexpr (kern_prop(KERN)) return T(b64[i]);
+    else return T(0);
 }
 
 template <typename T>
@@ -490,16 +519,18 @@ __device__ __forceinline__ T row_dot(PW Wi, const T *kr, std::integer_sequence<i
 
 template <typename T, int KERN, int NMAX, int I>
 __device__ __forceinline__ void small_rows(const float4 *__restrict__ P, const double *__restrict__ a64,
+                                           const double *__restrict__ b64,
                                            const T *__restrict__ W, int n, int pbase,
                                            const QueryPoint &Q, const QueryConsts &C, PairRaw<T> &r,
                                            Acc<T> &A, T *kr) {
     if constexpr (I < NMAX) {
         if (I >= n) return;
         const float4 p = ro(P)[I];
-        kr[I] = point_eval<T, KERN>(p, alpha_of<T>(p, a64, I), Q, pbase + I, C, r, A);
+        kr[I] = point_eval<T, KERN>(p, alpha_of<T>(p, a64, I), Q, pbase + I, C, r, A, true,
+                                    beta_of<T, KERN>(b64, I));
         const T t = row_dot<T>(ro(W + (I * (I + 1)) / 2), kr, std::make_integer_sequence<int, I + 1>{});
         r.ss = fma(t, t, r.ss);
-        small_rows<T, KERN, NMAX, I + 1>(P, a64, W, n, pbase, Q, C, r, A, kr);
+        small_rows<T, KERN, NMAX, I + 1>(P, a64, b64, W, n, pbase, Q, C, r, A, kr);
     }
 }
 
@@ -513,26 +544,27 @@ __device__ __forceinline__ void small_rows(const float4 *__restrict__ P, const d
 constexpr int f32_group(int i) { return i < 8 ? 4 : 2; }   // rows per batch
 
 template <int KERN, int I, int WO>
-__device__ __forceinline__ void group_row_f32(const float4 pp, const float *w, int n, int pbase,
+__device__ __forceinline__ void group_row_f32(const float4 pp, float bb, const float *w, int n, int pbase,
                                               const QueryPoint &Q, const QueryConsts &C,
                                               PairRaw<float> &r, Acc<float> &A, float *kr) {
     const bool live = I < n;
-    kr[I] = point_eval<float, KERN>(pp, pp.w, Q, pbase + I, C, r, A, live);
+    kr[I] = point_eval<float, KERN>(pp, pp.w, Q, pbase + I, C, r, A, live, bb);
     const float t = row_dot<float>(w + WO, kr, std::make_integer_sequence<int, I + 1>{});
     r.ss = live ? fmaf(t, t, r.ss) : r.ss;
 }
 
 template <int KERN, int I0, int... R>
-__device__ __forceinline__ void group_rows_f32(const float4 *p, const float *w, int n, int pbase,
+__device__ __forceinline__ void group_rows_f32(const float4 *p, const float *b, const float *w, int n, int pbase,
                                                const QueryPoint &Q, const QueryConsts &C,
                                                PairRaw<float> &r, Acc<float> &A, float *kr,
                                                std::integer_sequence<int, R...>) {
     // row I0 + R starts at R I0 + R (R + 1) / 2 inside the batch
-    (group_row_f32<KERN, I0 + R, R * I0 + R * (R + 1) / 2>(p[R], w, n, pbase, Q, C, r, A, kr), ...);
+    (group_row_f32<KERN, I0 + R, R * I0 + R * (R + 1) / 2>(p[R], b[R], w, n, pbase, Q, C, r, A, kr), ...);
 }
 
 template <int KERN, int NMAX, int I0>
-__device__ __forceinline__ void small_groups_f32(const float4 *__restrict__ P, const float *__restrict__ W,
+__device__ __forceinline__ void small_groups_f32(const float4 *__restrict__ P, const float *__restrict__ B,
+                                                 const float *__restrict__ W,
                                                  int n, int pbase, const QueryPoint &Q,
                                                  const QueryConsts &C, PairRaw<float> &r,
                                                  Acc<float> &A, float *kr) {
@@ -542,26 +574,32 @@ __device__ __forceinline__ void small_groups_f32(const float4 *__restrict__ P, c
         constexpr int WB = I0 * (I0 + 1) / 2;        // first element of row I0
         constexpr int WL = G * I0 + G * (G + 1) / 2;  // elements of rows I0 .. I0 + G - 1
         float4 p[G];
+        float b[G];
         float w[WL];
 #pragma unroll
         for (int i = 0; i < G; ++i) p[i] = ro(P)[I0 + i];
 #pragma unroll
+        for (int i = 0; i < G; ++i) b[i] = kern_prop(KERN) ? ro(B)[I0 + i] : 0.f;
+#pragma unroll
         for (int i = 0; i < WL; ++i) w[i] = ro(W)[WB + i];
-        group_rows_f32<KERN, I0>(p, w, n, pbase, Q, C, r, A, kr, std::make_integer_sequence<int, G>{});
-        small_groups_f32<KERN, NMAX, I0 + G>(P, W, n, pbase, Q, C, r, A, kr);
+        group_rows_f32<KERN, I0>(p, b, w, n, pbase, Q, C, r, A, kr, std::make_integer_sequence<int, G>{});
+        small_groups_f32<KERN, NMAX, I0 + G>(P, B, W, n, pbase, Q, C, r, A, kr);
     }
 }
 
+// B: beta in FP32 (the FP32 path), b64: in FP64; read only when KERN
+// carries kProp
 template <typename T, int KERN, int NMAX>
 __device__ __forceinline__ void eval_small(const float4 *__restrict__ P, const double *__restrict__ a64,
+                                           const float *__restrict__ B, const double *__restrict__ b64,
                                            const T *__restrict__ W, int n, int pbase,
                                            const QueryPoint &Q, const QueryConsts &C, PairRaw<T> &r,
                                            Acc<T> &A) {
     T kr[NMAX];
     if constexpr (std::is_same<T, float>::value)
-        small_groups_f32<KERN, NMAX, 0>(P, W, n, pbase, Q, C, r, A, kr);
+        small_groups_f32<KERN, NMAX, 0>(P, B, W, n, pbase, Q, C, r, A, kr);
     else
-        small_rows<T, KERN, NMAX, 0>(P, a64, W, n, pbase, Q, C, r, A, kr);
+        small_rows<T, KERN, NMAX, 0>(P, a64, b64, W, n, pbase, Q, C, r, A, kr);
 }
 
 // t[R0 + R] += col[R0 + R] k_j for R = 0 .. kPanel - 1 - R0
@@ -574,41 +612,45 @@ __device__ __forceinline__ void panel_update(T *t, PC col, T kj, std::integer_se
 // triangle), so the update starts at row J; its points are summed here
 template <typename T, int KERN, int J>
 __device__ __forceinline__ void diag_cols(const float4 *__restrict__ P, const double *__restrict__ a64,
+                                          const double *__restrict__ b64,
                                           const T *__restrict__ D, int nrem, int pbase,
                                           const QueryPoint &Q, const QueryConsts &C, PairRaw<T> &r,
                                           Acc<T> &A, T *t) {
     if constexpr (J < kPanel) {
         if (J >= nrem) return;
         const float4 p = ro(P)[J];
-        const T kj = point_eval<T, KERN>(p, alpha_of<T>(p, a64, J), Q, pbase + J, C, r, A);
+        const T kj = point_eval<T, KERN>(p, alpha_of<T>(p, a64, J), Q, pbase + J, C, r, A, true,
+                                         beta_of<T, KERN>(b64, J));
         panel_update<T, J>(t, ro(D + J * kPanel), kj, std::make_integer_sequence<int, kPanel - J>{});
-        diag_cols<T, KERN, J + 1>(P, a64, D, nrem, pbase, Q, C, r, A, t);
+        diag_cols<T, KERN, J + 1>(P, a64, b64, D, nrem, pbase, Q, C, r, A, t);
     }
 }
 
 // FP32 diagonal block, two columns per batch of scalar loads; the second
 // column of the last pair may lie past the cluster and is then masked
 template <int KERN, int J>
-__device__ __forceinline__ void diag_pairs_f32(const float4 *__restrict__ P, const float *__restrict__ D,
+__device__ __forceinline__ void diag_pairs_f32(const float4 *__restrict__ P, const float *__restrict__ B,
+                                               const float *__restrict__ D,
                                                int nrem, int pbase, const QueryPoint &Q,
                                                const QueryConsts &C, PairRaw<float> &r, Acc<float> &A,
                                                float *t) {
     if constexpr (J < kPanel) {
         if (J >= nrem) return;
         const float4 p0 = ro(P)[J], p1 = ro(P)[J + 1];
+        const float b0 = kern_prop(KERN) ? ro(B)[J] : 0.f, b1 = kern_prop(KERN) ? ro(B)[J + 1] : 0.f;
         float a[kPanel - J], b[kPanel - J - 1];
 #pragma unroll
         for (int i = 0; i < kPanel - J; ++i) a[i] = ro(D)[J * kPanel + J + i];
 #pragma unroll
         for (int i = 0; i < kPanel - J - 1; ++i) b[i] = ro(D)[(J + 1) * kPanel + J + 1 + i];
-        const float k0 = point_eval<float, KERN>(p0, p0.w, Q, pbase + J, C, r, A);
+        const float k0 = point_eval<float, KERN>(p0, p0.w, Q, pbase + J, C, r, A, true, b0);
 #pragma unroll
         for (int i = 0; i < kPanel - J; ++i) t[J + i] = fmaf(a[i], k0, t[J + i]);
         const bool live = J + 1 < nrem;
-        const float k1 = point_eval<float, KERN>(p1, p1.w, Q, pbase + J + 1, C, r, A, live);
+        const float k1 = point_eval<float, KERN>(p1, p1.w, Q, pbase + J + 1, C, r, A, live, b1);
 #pragma unroll
         for (int i = 0; i < kPanel - J - 1; ++i) t[J + 1 + i] = live ? fmaf(b[i], k1, t[J + 1 + i]) : t[J + 1 + i];
-        diag_pairs_f32<KERN, J + 2>(P, D, nrem, pbase, Q, C, r, A, t);
+        diag_pairs_f32<KERN, J + 2>(P, B, D, nrem, pbase, Q, C, r, A, t);
     }
 }
 
@@ -618,6 +660,7 @@ __device__ __forceinline__ void diag_pairs_f32(const float4 *__restrict__ P, con
 // recomputed; the diagonal block sums its own points.
 template <typename T, int KERN>
 __device__ __forceinline__ void eval_panels(const float4 *__restrict__ P, const double *__restrict__ a64,
+                                            const float *__restrict__ B, const double *__restrict__ b64,
                                             const T *__restrict__ W, int n, int pbase,
                                             const QueryPoint &Q, const QueryConsts &C, PairRaw<T> &r,
                                             Acc<T> &A) {
@@ -638,13 +681,13 @@ __device__ __forceinline__ void eval_panels(const float4 *__restrict__ P, const 
                 panel_update<float, 0>(t, a, k0, std::make_integer_sequence<int, kPanel>{});
                 panel_update<float, 0>(t, b, k1, std::make_integer_sequence<int, kPanel>{});
             }
-            diag_pairs_f32<KERN, 0>(P + c0, Pn + c0 * kPanel, n - c0, pbase + c0, Q, C, r, A, t);
+            diag_pairs_f32<KERN, 0>(P + c0, B + c0, Pn + c0 * kPanel, n - c0, pbase + c0, Q, C, r, A, t);
         } else {
             for (int j = 0; j < c0; ++j) {
                 const T kj = point_k<T, KERN>(ro(P)[j], Q, C);
                 panel_update<T, 0>(t, ro(Pn + j * kPanel), kj, std::make_integer_sequence<int, kPanel>{});
             }
-            diag_cols<T, KERN, 0>(P + c0, a64 + c0, Pn + c0 * kPanel, n - c0, pbase + c0, Q, C, r, A, t);
+            diag_cols<T, KERN, 0>(P + c0, a64 + c0, b64 + c0, Pn + c0 * kPanel, n - c0, pbase + c0, Q, C, r, A, t);
         }
 #pragma unroll
         for (int q = 0; q < kPanel; ++q) r.ss = fma(t[q], t[q], r.ss);
@@ -695,6 +738,8 @@ template <typename T>
 struct PairOut {
     T d, v, gx, gy, gz, o, u;
     float ed, eg, ev, gn;
+    T c;        // property (Eq. (6))
+    float ec;   // its FP32 error estimate
 };
 
 template <typename T, int KERN>
@@ -765,12 +810,14 @@ __device__ __forceinline__ PairOut<T> pair_out(const PairRaw<T> &r, int n, const
             eg += float(gsc) * go;
         }
     }
-    return PairOut<T>{d, v, gx, gy, gz, o, u, ed, eg, ev, gn};
+    float ec = 0.f;
+    if constexpr (f32 && kern_prop(KERN)) ec = C.err_c * kEps * fsqrt(r.Sc) + 2.f * kEps * fabsf(r.c);
+    return PairOut<T>{d, v, gx, gy, gz, o, u, ed, eg, ev, gn, kern_prop(KERN) ? r.c : T(0), ec};
 }
 
 // accumulation of one pair into the combination of its query (closest node,
 // online smooth minimum, plain gradient sum, counts)
-template <typename T, bool GRAD = true>
+template <typename T, bool GRAD = true, bool PROP = false>
 __device__ __forceinline__ void pair_accumulate(const PairOut<T> &P, int n, const QueryConsts &C, Acc<T> &A) {
     constexpr bool f32 = std::is_same<T, float>::value;
     const T d = P.d, v = P.v, gx = P.gx, gy = P.gy, gz = P.gz, o = P.o, u = P.u;
@@ -780,6 +827,7 @@ __device__ __forceinline__ void pair_accumulate(const PairOut<T> &P, int n, cons
         A.hd = d; A.hv = v; A.ho = o; A.hu = u;
         A.hed = ed; A.hev = ev;
         if constexpr (GRAD) { A.hgx = gx; A.hgy = gy; A.hgz = gz; A.heg = eg; }
+        if constexpr (PROP) { A.hc = P.c; A.hec = P.ec; }
     }
     // smooth minimum, online: rescale the sums when the minimum moves
     const T delta = d - A.m;
@@ -803,10 +851,20 @@ __device__ __forceinline__ void pair_accumulate(const PairOut<T> &P, int n, cons
             A.G2 = fmaf(so, A.G2, wed * gn * gn);
             A.sum_eg += eg;
         }
+        if constexpr (PROP) {
+            const float wed = w * ed, cf = float(P.c);
+            A.Cc1 = fmaf(so, A.Cc1, w * P.ec);
+            A.Mc1 = fmaf(so, A.Mc1, wed * cf);
+            A.Mc2 = fmaf(so, A.Mc2, wed * cf * cf);
+        }
     }
     A.sw = fma(so, A.sw, w);
     A.swd = fma(so, A.swd, w * d);
     A.swv = fma(so, A.swv, w * v);
+    if constexpr (PROP) {
+        A.swc = fma(so, A.swc, w * P.c);
+        A.swu = fma(so, A.swu, w * u);
+    }
     if constexpr (GRAD) {
         A.sgx = fma(so, A.sgx, w * gx);
         A.sgy = fma(so, A.sgy, w * gy);
@@ -820,7 +878,7 @@ __device__ __forceinline__ void pair_accumulate(const PairOut<T> &P, int n, cons
 
 template <typename T, int KERN>
 __device__ __forceinline__ void finish_pair(const PairRaw<T> &r, int n, const QueryConsts &C, Acc<T> &A) {
-    pair_accumulate<T, kern_grad(KERN)>(pair_out<T, KERN>(r, n, C), n, C, A);
+    pair_accumulate<T, kern_grad(KERN), kern_prop(KERN)>(pair_out<T, KERN>(r, n, C), n, C, A);
 }
 
 struct Outputs {
@@ -829,26 +887,31 @@ struct Outputs {
     uint2 *refine;              // FP32 pass: (cell, query) records to redo in FP64
     unsigned long long *stat;   // the refine record counter (its value is used)
     unsigned long long *spread; // every other per-wavefront count (spread_add)
+    float *prop, *prop_var;     // surface property and its variance (kProp launches)
 };
 
 // final combination, sign, error test and stores for one lane
-template <typename T, int MODE>
+template <typename T, int MODE, bool PROP = false>
 __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell, bool active,
                                     const QueryPoint &Q, const float4 *__restrict__ pts,
                                     const QueryConsts &C, const Outputs &O) {
     constexpr bool f32 = std::is_same<T, float>::value;
     bool bad = false, bd = false, bg = false, bv = false;
-    if (active && A.nq == 0) write_invalid(qi, O.dist, O.grad, O.var, O.valid, O.aux);
+    if (active && A.nq == 0)
+        write_invalid(qi, O.dist, O.grad, O.var, O.valid, O.aux, PROP ? O.prop : nullptr,
+                      PROP ? O.prop_var : nullptr);
     if (active && A.nq > 0) {
-        T D, V, Gx, Gy, Gz;
-        float Ed = 0.f, Eg = 0.f, Ev = 0.f;
+        T D, V, Gx, Gy, Gz, Cp = T(0), Wp = T(0);
+        float Ed = 0.f, Eg = 0.f, Ev = 0.f, Ec = 0.f;
         if constexpr (MODE == kModeHard) {
             D = A.hd; V = A.hv; Gx = A.hgx; Gy = A.hgy; Gz = A.hgz;
             Ed = A.hed; Eg = A.heg; Ev = A.hev;
+            if constexpr (PROP) { Cp = A.hc; Wp = A.hu; Ec = A.hec; }
         } else {
             const T iw = T(1) / A.sw;
             D = A.swd * iw;
             V = A.swv * iw;
+            if constexpr (PROP) { Cp = A.swc * iw; Wp = A.swu * iw; }
             if constexpr (MODE == kModeMean) {
                 const T iq = T(1) / T(A.nq);
                 Gx = A.pgx * iq; Gy = A.pgy * iq; Gz = A.pgz * iq;
@@ -865,6 +928,13 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
                 Eg = (A.B1 + lam * sqrtf(fmaxf(A.A1 * Q2, 0.f))) * iw;
                 if constexpr (MODE == kModeMean) Eg = A.sum_eg / float(A.nq) + Eg;
                 Ev = A.C1 / A.swv;
+                if constexpr (PROP) {
+                    // as the gradient: the pair errors plus the weight errors,
+                    // lambda sum (w/W) e_d |c_q - C| by Cauchy-Schwarz
+                    const float Cf = float(Cp);
+                    const float Q2c = A.Mc2 - 2.f * Cf * A.Mc1 + Cf * Cf * A.A1;
+                    Ec = (A.Cc1 + lam * sqrtf(fmaxf(A.A1 * Q2c, 0.f))) * iw;
+                }
             }
         }
         if (C.signed_ && A.bidx >= 0) {
@@ -882,12 +952,19 @@ __device__ inline void finish_query(const Acc<T> &A, uint32_t qi, uint32_t cell,
         if (O.grad) { O.grad[3 * qi] = float(Gx); O.grad[3 * qi + 1] = float(Gy); O.grad[3 * qi + 2] = float(Gz); }
         if (O.var) O.var[qi] = float(V);
         if (O.aux) { O.aux[3 * qi] = float(A.ho); O.aux[3 * qi + 1] = float(A.hu); O.aux[3 * qi + 2] = float(A.ntot); }
+        if constexpr (PROP) {
+            if (O.prop) O.prop[qi] = float(Cp);
+            if (O.prop_var) O.prop_var[qi] = float(Wp);
+        }
         if constexpr (f32) {
-            // an output the caller did not ask for is not refined for
+            // an output the caller did not ask for is not refined for; the
+            // property variance is the latent variance, whose error the
+            // relative variance estimate covers
             bd = !(Ed <= C.tau_d);
             bg = O.grad && !(Eg <= C.tau_g);
-            bv = O.var && !(Ev <= C.tau_v);
+            bv = (O.var || (PROP && O.prop_var)) && !(Ev <= C.tau_v);
             bad = bd || bg || bv;
+            if constexpr (PROP) bad = bad || (O.prop && !(Ec <= C.tau_c));
         }
     }
     // one atomic per wavefront for the valid count and the refine records
@@ -931,17 +1008,21 @@ __device__ __forceinline__ const T *factor_base(const float *W32, const double *
 template <typename T, int KERN>
 __device__ __forceinline__ void eval_cluster(int base, int n, int64_t woff, const float4 *__restrict__ pts,
                                              const double *__restrict__ alpha64,
+                                             const float *__restrict__ beta32,
+                                             const double *__restrict__ beta64,
                                              const float *__restrict__ W32,
                                              const double *__restrict__ W64, const QueryPoint &Q,
                                              const QueryConsts &C, Acc<T> &A) {
     const float4 *P = pts + base;
     const double *a64 = alpha64 + base;
+    const float *B = beta32 + base;
+    const double *b64 = beta64 + base;
     const T *W = factor_base<T>(W32, W64, woff);
-    PairRaw<T> r{T(0), T(0), T(0), T(0), T(0), 0.f};
-    if (n <= 8) eval_small<T, KERN, 8>(P, a64, W, n, base, Q, C, r, A);
-    else if (n <= 16) eval_small<T, KERN, 16>(P, a64, W, n, base, Q, C, r, A);
-    else if (n <= kPanel) eval_small<T, KERN, kPanel>(P, a64, W, n, base, Q, C, r, A);
-    else eval_panels<T, KERN>(P, a64, W, n, base, Q, C, r, A);
+    PairRaw<T> r{T(0), T(0), T(0), T(0), T(0), 0.f, T(0), 0.f};
+    if (n <= 8) eval_small<T, KERN, 8>(P, a64, B, b64, W, n, base, Q, C, r, A);
+    else if (n <= 16) eval_small<T, KERN, 16>(P, a64, B, b64, W, n, base, Q, C, r, A);
+    else if (n <= kPanel) eval_small<T, KERN, kPanel>(P, a64, B, b64, W, n, base, Q, C, r, A);
+    else eval_panels<T, KERN>(P, a64, B, b64, W, n, base, Q, C, r, A);
     finish_pair<T, KERN>(r, n, C, A);
 }
 
@@ -956,6 +1037,8 @@ struct Grouping {
 struct ModelView {
     const float4 *pts;
     const double *alpha64;
+    const float *beta32;     // property right-hand side (Eq. (6)), read only by kProp launches;
+    const double *beta64;    // never null (without a property they alias unread arrays)
     const int32_t *coff;
     const int64_t *woff;
     const float *W32;
@@ -995,11 +1078,11 @@ __device__ __forceinline__ void cells_chunk(uint32_t wave, const float *__restri
         if (s + 1 < nsel) nxt = L[2 + s];
         const int base = int(uniform(uint32_t(d.y))), n = int(uniform(uint32_t(d.z)));
         const int64_t woff = int64_t(uniform(uint32_t(d.w)));
-        eval_cluster<T, KERN>(base, n, woff, Mo.pts, Mo.alpha64, Mo.W32, Mo.W64, Q, C, A);
+        eval_cluster<T, KERN>(base, n, woff, Mo.pts, Mo.alpha64, Mo.beta32, Mo.beta64, Mo.W32, Mo.W64, Q, C, A);
         sum_n += uint32_t(n);
         sum_tri += uint32_t(n * (n + 1) / 2);
     }
-    finish_query<T, MODE>(A, qi, cell, active, Q, Mo.pts, C, O);
+    finish_query<T, MODE, kern_prop(KERN)>(A, qi, cell, active, Q, Mo.pts, C, O);
     // algorithmic work of this wavefront (active lanes), one atomic each
     if (std::is_same<T, float>::value && lane == 0 && nsel > 0) {
         spread_add(O.spread, ST_PAIRS, (unsigned long long)nsel * cnt);
@@ -1103,8 +1186,8 @@ __device__ void coop_batch(const float *__restrict__ q, const Grouping &G, uint3
                            int n, int64_t woff, const ModelView &Mo, const QueryConsts &C, double *kb,
                            PairSlot *slot, int sidx, int nsel, uint32_t a0) {
     const int lane = int(threadIdx.x & 63);
-    // kernel values and the Eq. (1)/(5) sums of each query, the sums to LDS
-    __shared__ double sums[4][4];
+    // kernel values and the Eq. (1)/(5)/(6) sums of each query, the sums to LDS
+    __shared__ double sums[4][5];
     __shared__ float sbest[4];
     __shared__ int sbidx[4];
 #pragma unroll
@@ -1115,7 +1198,7 @@ __device__ void coop_batch(const float *__restrict__ q, const Grouping &G, uint3
         }
         const uint32_t qj = G.order[first + uint32_t(a)];
         const float fx = q[3 * qj], fy = q[3 * qj + 1], fz = q[3 * qj + 2];
-        double o = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        double o = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, cp = 0.0;
         float best = INFINITY;
         int bidx = 0x7fffffff;
         for (int j = lane; j < n; j += 64) {
@@ -1136,6 +1219,7 @@ __device__ void coop_batch(const float *__restrict__ q, const Grouping &G, uint3
                 e = k;
             }
             o = fma(al, k, o);
+            if constexpr (kern_prop(KERN)) cp = fma(Mo.beta64[base + j], k, cp);
             const double cg = al * e;
             gx = fma(cg, dx, gx);
             gy = fma(cg, dy, gy);
@@ -1143,13 +1227,14 @@ __device__ void coop_batch(const float *__restrict__ q, const Grouping &G, uint3
             kb[j * NB + a] = k;
         }
         o = wave_sum(o); gx = wave_sum(gx); gy = wave_sum(gy); gz = wave_sum(gz);
+        if constexpr (kern_prop(KERN)) cp = wave_sum(cp);
         for (int s = 1; s < 64; s <<= 1) {
             const float b2 = __shfl_xor(best, s, 64);
             const int i2 = __shfl_xor(bidx, s, 64);
             if (b2 < best || (b2 == best && i2 < bidx)) { best = b2; bidx = i2; }
         }
         if (lane == 0) {
-            sums[a][0] = o; sums[a][1] = gx; sums[a][2] = gy; sums[a][3] = gz;
+            sums[a][0] = o; sums[a][1] = gx; sums[a][2] = gy; sums[a][3] = gz; sums[a][4] = cp;
             sbest[a] = best; sbidx[a] = bidx;
         }
     }
@@ -1200,7 +1285,8 @@ __device__ void coop_batch(const float *__restrict__ q, const Grouping &G, uint3
         if (lane == a) mss = t;
     }
     if (lane < rem && lane < NB) {
-        const PairRaw<double> rr{sums[lane][0], sums[lane][1], sums[lane][2], sums[lane][3], mss, 0.f};
+        const PairRaw<double> rr{sums[lane][0], sums[lane][1], sums[lane][2], sums[lane][3], mss, 0.f,
+                                 sums[lane][4], 0.f};
         slot[(a0 + uint32_t(lane)) * nsel + sidx] =
             PairSlot{pair_out<double, KERN>(rr, n, C), sbest[lane], sbidx[lane], n};
     }
@@ -1238,11 +1324,13 @@ __global__ __launch_bounds__(kEvalT, 3) void k_refine_pairs(const float *__restr
             if (n <= kPanel) {
                 const float4 *P = Mo.pts + base;
                 const double *a64 = Mo.alpha64 + base;
+                const float *B = Mo.beta32 + base;
+                const double *b64 = Mo.beta64 + base;
                 const double *W = Mo.W64 + d.w;
-                PairRaw<double> r{0.0, 0.0, 0.0, 0.0, 0.0, 0.f};
-                if (n <= 8) eval_small<double, KERN, 8>(P, a64, W, n, base, Q, C, r, A);
-                else if (n <= 16) eval_small<double, KERN, 16>(P, a64, W, n, base, Q, C, r, A);
-                else eval_small<double, KERN, kPanel>(P, a64, W, n, base, Q, C, r, A);
+                PairRaw<double> r{0.0, 0.0, 0.0, 0.0, 0.0, 0.f, 0.0, 0.f};
+                if (n <= 8) eval_small<double, KERN, 8>(P, a64, B, b64, W, n, base, Q, C, r, A);
+                else if (n <= 16) eval_small<double, KERN, 16>(P, a64, B, b64, W, n, base, Q, C, r, A);
+                else eval_small<double, KERN, kPanel>(P, a64, B, b64, W, n, base, Q, C, r, A);
                 slot[lane] = PairSlot{pair_out<double, KERN>(r, n, C), A.best, A.bidx, n};
             }
         }
@@ -1270,12 +1358,12 @@ __global__ __launch_bounds__(kEvalT, 3) void k_refine_pairs(const float *__restr
         if (leader) {
             for (int k = 0; k < nsel; ++k) {
                 const PairSlot &ps = slot[lane + k];
-                pair_accumulate<double>(ps.p, ps.n, C, B);
+                pair_accumulate<double, true, kern_prop(KERN)>(ps.p, ps.n, C, B);
                 if (ps.best < B.best) { B.best = ps.best; B.bidx = ps.bidx; }
             }
         }
         __syncthreads();  // the slots are rewritten by the next chunk
-        finish_query<double, MODE>(B, qi, cell, leader, Q, Mo.pts, C, O);
+        finish_query<double, MODE, kern_prop(KERN)>(B, qi, cell, leader, Q, Mo.pts, C, O);
     }
 }
 
@@ -1465,8 +1553,8 @@ __global__ __launch_bounds__(kEvalT) void k_query_cells_bf16(const float *__rest
         if (n <= kBfMaxN)
             eval_cluster_bf16<KERN>(base, n, bfoff[cid], Mo.pts, Mbf, Kt, kts, Q, C, A);
         else
-            eval_cluster<float, KERN>(base, n, int64_t(uniform(uint32_t(d.w))), Mo.pts, Mo.alpha64, Mo.W32,
-                                      Mo.W64, Q, C, A);
+            eval_cluster<float, KERN>(base, n, int64_t(uniform(uint32_t(d.w))), Mo.pts, Mo.alpha64, Mo.beta32,
+                                      Mo.beta64, Mo.W32, Mo.W64, Q, C, A);
         sum_n += uint32_t(n);
         sum_tri += uint32_t(n * (n + 1) / 2);
     }
@@ -1647,10 +1735,10 @@ __global__ __launch_bounds__(kEvalT) void k_query_knn(const float *__restrict__ 
             ++ptr;
             const int base = int(uniform(uint32_t(Mo.coff[c])));
             const int n = int(uniform(uint32_t(Mo.coff[c + 1]))) - base;
-            eval_cluster<T, KERN>(base, n, Mo.woff[c], Mo.pts, Mo.alpha64, Mo.W32, Mo.W64, Q, C, A);
+            eval_cluster<T, KERN>(base, n, Mo.woff[c], Mo.pts, Mo.alpha64, Mo.beta32, Mo.beta64, Mo.W32, Mo.W64, Q, C, A);
         }
     }
-    finish_query<T, MODE>(A, qi, cell, active, Q, Mo.pts, C, O);
+    finish_query<T, MODE, kern_prop(KERN)>(A, qi, cell, active, Q, Mo.pts, C, O);
 }
 
 // grid: one workgroup per chunk (an upper bound); with work != NULL the
@@ -1659,14 +1747,20 @@ template <typename T, int KERN, int MODE>
 void launch_query(bool knn, unsigned grid, hipStream_t s, const float *q, const Grouping &G,
                   const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O,
                   uint32_t *work) {
-    if (knn)
+    // property launches: NEIGHBOR27, one workgroup per chunk (the caller
+    // rejects the other combinations)
+    if constexpr (kern_prop(KERN)) {
+        hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, false>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
+                           Mo, C, O, nullptr);
+    } else if (knn) {
         hipLaunchKernelGGL((k_query_knn<T, KERN, MODE>), dim3(grid), dim3(kEvalT), 0, s, q, G, Mo, C, O);
-    else if (work)
+    } else if (work) {
         hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, true>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
                            Mo, C, O, work);
-    else
+    } else {
         hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, false>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
                            Mo, C, O, work);
+    }
 }
 
 template <typename T, int KERN>
@@ -1696,10 +1790,33 @@ void launch_bf16_m(unsigned grid, size_t lds, hipStream_t s, const float *q, con
                            Mo, Mbf, bfoff, kts, C, O);
 }
 
+template <typename T, int PF>
+void launch_query_kf(int kernel, bool knn, unsigned grid, hipStream_t s, const float *q, const Grouping &G,
+                     const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O,
+                     uint32_t *work) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (!O.grad) {
+            if (kernel == GPDF_KERNEL_MATERN32)
+                launch_query_m<T, GPDF_KERNEL_MATERN32 | kNoGrad | PF>(knn, grid, s, q, G, lists, Mo, C, O, work);
+            else
+                launch_query_m<T, GPDF_KERNEL_SE | kNoGrad | PF>(knn, grid, s, q, G, lists, Mo, C, O, work);
+            return;
+        }
+    }
+    if (kernel == GPDF_KERNEL_MATERN32)
+        launch_query_m<T, GPDF_KERNEL_MATERN32 | PF>(knn, grid, s, q, G, lists, Mo, C, O, work);
+    else
+        launch_query_m<T, GPDF_KERNEL_SE | PF>(knn, grid, s, q, G, lists, Mo, C, O, work);
+}
+
 template <typename T>
 void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_t s, const float *q,
                     const Grouping &G, const int4 *lists, const ModelView &Mo,
                     const QueryConsts &C, const Outputs &O, int slot) {
+    if (O.prop || O.prop_var) {
+        launch_query_kf<T, kProp>(kernel, knn, grid, s, q, G, lists, Mo, C, O, nullptr);
+        return;
+    }
     uint32_t *work = nullptr;
     // persistent when tuned so, and always in a captured graph (its grid
     // bound would otherwise be one workgroup per possible chunk); the FP32
@@ -1711,19 +1828,7 @@ void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_
         fill_u32(work, 0u, kWorkSlot, s);
         grid = std::min<unsigned>(grid, 1024u * unsigned(per));
     }
-    if constexpr (std::is_same<T, float>::value) {
-        if (!O.grad) {
-            if (kernel == GPDF_KERNEL_MATERN32)
-                launch_query_m<T, GPDF_KERNEL_MATERN32 | kNoGrad>(knn, grid, s, q, G, lists, Mo, C, O, work);
-            else
-                launch_query_m<T, GPDF_KERNEL_SE | kNoGrad>(knn, grid, s, q, G, lists, Mo, C, O, work);
-            return;
-        }
-    }
-    if (kernel == GPDF_KERNEL_MATERN32)
-        launch_query_m<T, GPDF_KERNEL_MATERN32>(knn, grid, s, q, G, lists, Mo, C, O, work);
-    else
-        launch_query_m<T, GPDF_KERNEL_SE>(knn, grid, s, q, G, lists, Mo, C, O, work);
+    launch_query_kf<T, 0>(kernel, knn, grid, s, q, G, lists, Mo, C, O, work);
 }
 
 }  // namespace
@@ -1780,6 +1885,9 @@ QueryConsts make_consts(const gpdf_params &p, const float *origin, const float *
     C.tau_d = 2e-5f;
     C.tau_g = 2e-4f;
     C.tau_v = 1e-3f;
+    // surface property: 2e-5 in the property's own units (intensities and
+    // colour channels in [0, 1]), 5x inside a 1e-4 tolerance, as the distance
+    C.tau_c = 2e-5f;
     C.err_c = 2.f;
     C.kernel = p.kernel;
     C.combine = p.combine;
@@ -1889,7 +1997,7 @@ gpdf_status build_bf16(gpdf_ctx *c) {
 
 gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin, float *dist,
                   float *grad, float *var, uint8_t *valid, float *aux, int32_t correct, const uint32_t *dm,
-                  const float *d_origin, bool noalloc) {
+                  const float *d_origin, bool noalloc, float *prop, float *prop_var) {
     if (noalloc) {
         // nothing below may allocate: the BF16 copy of the factors is built
         // (and its buffer sized) on the first BF16 query of a training
@@ -1906,6 +2014,13 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     if (m > 0 && (!dist || !valid || !d_q)) return fail(c, GPDF_E_INVALID_ARG, "query: null buffer");
     if (origin && !(std::isfinite(origin[0]) && std::isfinite(origin[1]) && std::isfinite(origin[2])))
         return fail(c, GPDF_E_INVALID_ARG, "query: non-finite origin");
+    const bool want_prop = prop || prop_var;
+    if (want_prop) {
+        if (!M.props) return fail(c, GPDF_E_INVALID_ARG, "query: the model was trained without a property");
+        if (c->p.precision == GPDF_PREC_BF16 || c->p.selection != GPDF_SEL_NEIGHBOR27 || noalloc || correct)
+            return fail(c, GPDF_E_INVALID_ARG,
+                        "query: the property needs FP32 or FP64 precision, NEIGHBOR27 selection, no correction");
+    }
     c->last_queries = m;
     uint32_t *cnt = c->d_cnt;
     // per-call counters
@@ -1926,7 +2041,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         // nothing to select: every query is invalid
         (void)fill_multi(F, s);
         hipLaunchKernelGGL(k_all_invalid, dim3(blocks_for(m)), dim3(kQT), 0, s, m, dist, grad, var,
-                           valid, aux);
+                           valid, aux, prop, prop_var);
         return (e = hipGetLastError()) == hipSuccess ? GPDF_OK : hip_fail(c, e, "query launch");
     }
     const QueryConsts C = make_consts(c->p, origin, d_origin);
@@ -1938,7 +2053,10 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     }
     const double edge = vox ? 8.0 * c->p.voxel_size : c->p.cluster_size;
     const int kern = c->p.kernel;
-    const ModelView Mo{c->d_pts, c->d_alpha64, c->d_coff, c->d_woff, c->d_W32, c->d_W64,
+    // without a property the beta pointers alias arrays that no launch reads
+    const float *b32 = c->d_beta32 ? c->d_beta32 : c->d_W32;
+    const double *b64 = c->d_beta64 ? c->d_beta64 : c->d_alpha64;
+    const ModelView Mo{c->d_pts, c->d_alpha64, b32, b64, c->d_coff, c->d_woff, c->d_W32, c->d_W64,
                        c->d_ckey, c->d_pd, M.nclusters, edge, c->d_chash, c->d_chash_val, c->chash_mask};
     // 1. group by cell
     stage_begin(c, GPDF_MS_GROUP);
@@ -1952,7 +2070,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     HashView qh{c->d_qhash, qmask};
     hipLaunchKernelGGL(k_qcells, dim3(blocks_for(m)), dim3(kQT), 0, s, d_q, m, dm, vox ? 1 : 0,
                        c->p.voxel_size, c->p.cluster_size, qh, c->d_qhash_cnt, c->d_qslot, c->d_qrank,
-                       dist, grad, var, valid, aux, c->d_stat);
+                       dist, grad, var, valid, aux, prop, prop_var, c->d_stat);
     count_occupied(c->d_qhash, qcap, c->d_tile_cnt, c->d_tile_off, c->d_part, s);
     const int64_t ntiles = compact_tiles(qcap);
     hipLaunchKernelGGL(k_cells_compact, dim3(unsigned(ntiles)), dim3(256), 0, s, c->d_qhash,
@@ -2014,7 +2132,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     const int64_t max_chunks = nc + (m + 63) / 64;
     const unsigned grid = blocks_for(max_chunks * 64, kEvalT);
     const Grouping G{c->d_chunk, cnt + CNT_CHUNKS, c->d_cell_cnt, c->d_cell_off, c->d_order};
-    Outputs O{dist, grad, var, aux, valid, c->d_refine, c->d_stat, c->d_spread};
+    Outputs O{dist, grad, var, aux, valid, c->d_refine, c->d_stat, c->d_spread, prop, prop_var};
     if (c->p.precision == GPDF_PREC_FP64) {
         stage_begin(c, GPDF_MS_EVAL);
         launch_query_k<double>(c, kern, knn, grid, s, d_q, G, lists, Mo, C, O, 0);
@@ -2071,10 +2189,16 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
             uint32_t *work = c->d_work + kWorkSlot;
             fill_u32(work, 0u, 1, s);
             const unsigned rg = 3072;
-            if (kern == GPDF_KERNEL_MATERN32)
+            if (want_prop) {
+                if (kern == GPDF_KERNEL_MATERN32)
+                    launch_refine_pairs<GPDF_KERNEL_MATERN32 | kProp>(rg, s, d_q, R, lists, Mo, C, O64, work);
+                else
+                    launch_refine_pairs<GPDF_KERNEL_SE | kProp>(rg, s, d_q, R, lists, Mo, C, O64, work);
+            } else if (kern == GPDF_KERNEL_MATERN32) {
                 launch_refine_pairs<GPDF_KERNEL_MATERN32>(rg, s, d_q, R, lists, Mo, C, O64, work);
-            else
+            } else {
                 launch_refine_pairs<GPDF_KERNEL_SE>(rg, s, d_q, R, lists, Mo, C, O64, work);
+            }
         }
         stage_end(c, GPDF_MS_REFINE);
     }

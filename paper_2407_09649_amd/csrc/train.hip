@@ -100,6 +100,73 @@ __global__ void k_compact_unique(const uint64_t *__restrict__ key, int64_t n,
         if (flag[i]) out[pos[i]] = key[i];
 }
 
+// Surface property of each training point (Eq. (6)).  Voxel mode: the mean
+// of the properties of the voxel's raw points, summed in FP64 in input order
+// (the sort is stable, so a voxel's run holds its points by ascending input
+// index); flag marks the first entry of each voxel run and pos is its voxel
+// index.  Raw mode (flag == NULL): the point's own property.
+__global__ void k_point_prop(const uint64_t *__restrict__ key, const uint32_t *__restrict__ val, int64_t n,
+                             const uint32_t *__restrict__ dn, const uint32_t *__restrict__ flag,
+                             const uint32_t *__restrict__ pos, const float *__restrict__ prop,
+                             double *__restrict__ cprop) {
+    const int64_t na = dev_count(n, dn);
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < na;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        if (!flag) {
+            cprop[i] = double(prop[val[i]]);
+            continue;
+        }
+        if (!flag[i]) continue;
+        const uint64_t k = key[i];
+        double sum = double(prop[val[i]]);
+        int64_t e = i + 1;
+        while (e < na && key[e] == k) {
+            sum += double(prop[val[e]]);
+            ++e;
+        }
+        cprop[pos[i]] = sum / double(e - i);
+    }
+}
+
+// beta = W^T (W c) = (K + s^2 I)^{-1} c per cluster (Eq. (6)): the property
+// right-hand side on the trained factor W = L^{-1}, read in the query layout
+// (packed rows for n <= 32, 32-row column-major panels above).  One
+// workgroup per cluster; a cluster that is not positive definite gets 0.
+__device__ __forceinline__ int64_t w_at(int n, int i, int j) {
+    if (n <= kPanel) return int64_t(i) * (i + 1) / 2 + j;
+    const int r = i / kPanel;
+    return w32_panel_offset(n, r) + int64_t(j) * kPanel + (i - r * kPanel);
+}
+
+__global__ __launch_bounds__(256) void k_beta(const int32_t *__restrict__ coff, int64_t Cb,
+                                              const uint32_t *__restrict__ dncl, const int64_t *__restrict__ woff,
+                                              const double *__restrict__ W64, const uint8_t *__restrict__ pd,
+                                              const double *__restrict__ cprop, double *__restrict__ beta64,
+                                              float *__restrict__ beta32) {
+    __shared__ double y[1024];   // the largest cluster (max_cluster_points <= 1024)
+    const int64_t C = dev_count(Cb, dncl);
+    for (int64_t c = blockIdx.x; c < C; c += gridDim.x) {
+        const int base = coff[c], n = coff[c + 1] - base;
+        const bool ok = pd[c] != 0;
+        const double *W = W64 + woff[c];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            double t = 0.0;
+            if (ok)
+                for (int j = 0; j <= i; ++j) t = fma(W[w_at(n, i, j)], cprop[base + j], t);
+            y[i] = t;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            double t = 0.0;
+            if (ok)
+                for (int i = j; i < n; ++i) t = fma(W[w_at(n, i, j)], y[i], t);
+            beta64[base + j] = t;
+            beta32[base + j] = float(t);
+        }
+        __syncthreads();
+    }
+}
+
 // clusters: offsets, keys and training points.  voxel_mode: keys are the
 // unique composite keys; raw mode: keys are cell keys, vals input indices.
 __global__ void k_clusters(const uint64_t *__restrict__ key, const uint32_t *__restrict__ val,
@@ -1154,7 +1221,7 @@ hipError_t launch_trainers(gpdf_ctx *c, int64_t C, hipStream_t s, hipStream_t sb
 // dn (a device count of input points, at most n) nothing is read back, so the
 // sequence can be captured in a graph; otherwise the counts and the
 // capacity counter are read back once at the end.
-gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn) {
+gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn, const float *d_prop) {
     if (hipError_t je = join_train(c); je != hipSuccess) return hip_fail(c, je, "train: join");
     hipStream_t s = c->stream;
     Model &M = c->model;
@@ -1163,6 +1230,10 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
         return fail(c, GPDF_E_CAPACITY, "train: n exceeds max_points");
     M = Model();
     M.trained = true;
+    if (d_prop && !c->d_cprop) return fail(c, GPDF_E_INVALID_ARG, "train: properties are off in the parameters");
+    if (d_prop && (c->p.lazy_train || !eager))
+        return fail(c, GPDF_E_INVALID_ARG, "train: a property needs eager, non-lazy training");
+    M.props = d_prop != nullptr;
     uint32_t *cnt = c->d_cnt;
     FillList F;
     F.u32(cnt + CNT_VALID, 0u, CNT_MAXN - CNT_VALID + 1);
@@ -1195,10 +1266,16 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
         hipLaunchKernelGGL(k_run_flags, dim3(g), dim3(kT), 0, s, k, n, cnt + CNT_VALID, 0, c->d_flag);
         exclusive_scan_u32(c->d_flag, c->d_scan, n, c->d_part, s, nullptr, cnt + CNT_PTS);
         hipLaunchKernelGGL(k_compact_unique, dim3(g), dim3(kT), 0, s, k, n, c->d_flag, c->d_scan, ka);
+        if (d_prop)
+            hipLaunchKernelGGL(k_point_prop, dim3(g), dim3(kT), 0, s, k, v, n, cnt + CNT_VALID, c->d_flag,
+                               c->d_scan, d_prop, c->d_cprop);
         keys = ka;
         hipLaunchKernelGGL(k_run_flags, dim3(g), dim3(kT), 0, s, keys, n, cnt + CNT_PTS, 9, c->d_flag);
     } else {
         hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, s, cnt, int(CNT_PTS), int(CNT_VALID));
+        if (d_prop)
+            hipLaunchKernelGGL(k_point_prop, dim3(g), dim3(kT), 0, s, keys, v, n, cnt + CNT_VALID, nullptr,
+                               nullptr, d_prop, c->d_cprop);
         hipLaunchKernelGGL(k_run_flags, dim3(g), dim3(kT), 0, s, keys, n, cnt + CNT_VALID, 0, c->d_flag);
     }
     exclusive_scan_u32(c->d_flag, c->d_scan, n, c->d_part, s);
@@ -1224,8 +1301,12 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
         //    model (the test voxels of a fusion, which need only the points,
         //    run beside the trainer); a captured frame joins here
         if ((e = launch_trainers(c, C, s, c->side)) != hipSuccess) return hip_fail(c, e, "train: trainers");
-        if (eager) c->join_pending = true;
+        if (eager && !d_prop) c->join_pending = true;
         else if ((e = hipStreamWaitEvent(s, c->join_ev, 0)) != hipSuccess) return hip_fail(c, e, "train: join");
+        // the property right-hand side on every factor (Eq. (6))
+        if (d_prop)
+            hipLaunchKernelGGL(k_beta, dim3(unsigned(std::min<int64_t>(C, 4096))), dim3(256), 0, s, c->d_coff, C,
+                               cnt + CNT_CL, c->d_woff, c->d_W64, c->d_pd, c->d_cprop, c->d_beta64, c->d_beta32);
     }
     // 6. cluster hash
     HashView hv{c->d_chash, c->chash_mask};

@@ -48,7 +48,7 @@ def test_params_default_layout_and_values():
     # the last field lands where the C struct puts it
     assert p.global_capacity == 1 << 24
     assert p.fuse_rule == P.FUSE_INVVAR and p.test_points == P.TEST_BAND and p.normal_reach == 0.2
-    assert p.lazy_train == 0
+    assert p.lazy_train == 0 and p.properties == 0
     assert ctypes.sizeof(P.Params) == 184
 
 
@@ -59,7 +59,9 @@ def test_create_rejects_bad_parameters_without_touching_the_gpu():
            dict(occ_max=1.0), dict(knn_q=0, selection=P.SEL_KNN), dict(kernel=9),
            dict(max_cluster_points=2048), dict(precision=5), dict(fuse_rule=2),
            dict(test_points=2), dict(test_points=P.TEST_RAYCAST, voxel_size=0.0),
-           dict(normal_reach=-1.0), dict(lazy_train=2)]
+           dict(normal_reach=-1.0), dict(lazy_train=2), dict(properties=2),
+           dict(properties=1, precision=P.PREC_BF16), dict(properties=1, selection=P.SEL_KNN),
+           dict(properties=1, lazy_train=1)]
     for kw in bad:
         p = P.Params.default(**kw)
         assert lib.gpdf_create(ctypes.byref(p), None, ctypes.byref(h)) == 1, kw

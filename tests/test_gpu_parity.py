@@ -61,7 +61,23 @@ def test_sphere_modes_parity(dev, mode):
         _train(ctx, sc.points)
         g = gpu_query(ctx, sc.queries)
         om = O.Model(oracle_params(ctx.params), sc.points)
-    compare(g, om.query(sc.queries), label=mode)
+    compare(g, om.query(sc.queries), label=mode, closest_node=(mode == "hardmin"))
+
+
+def test_lidar_closest_node_parity(dev):
+    """The closest-node rule on a signed LiDAR scan: where two leaves give
+    nearly the same distance the FP32 argmin may take the other one, and the
+    result must then be that node's (the oracle's second answer)."""
+    pts = _lidar(7, beams=16, az=256)
+    q = S.lidar_band_queries(pts, radius_cells=4)
+    origin = np.array([0.0, 0.0, 1.5], np.float32)
+    with _ctx(dev, voxel_size=0.1, combine=P.COMB_HARDMIN) as ctx:
+        _train(ctx, pts)
+        g = gpu_query(ctx, q, origin=origin)
+        om = O.Model(oracle_params(ctx.params), pts)
+    o = om.query(q, origin=origin)
+    r = compare(g, o, label="lidar hardmin", closest_node=True)
+    assert r["node_alt"] <= 0.01 * r["n"]
 
 
 def test_knn_far_field_parity(dev):
