@@ -33,10 +33,13 @@ The ``extensions`` object reports, on the same GPU:
               (grid, and global queries at observed voxels and uniform points);
   correction  the learned correction trained on the GPU on pairs the method
               generates (GP output vs brute-force nearest point), its held-out
-              gain, and its fused inference rate.
+              gain, and its fused inference rate;
+  properties  the frame with a surface property per return (Eq. (6)):
+              training, the band query with the property, one fused frame,
+              and 20,000 sampled queries against the oracle.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-extensions] [--legs precision,batched,sequence,correction]
+                       [--no-extensions] [--legs precision,properties,batched,sequence,correction]
 """
 from __future__ import annotations
 
@@ -141,7 +144,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extensions", action="store_true")
-    ap.add_argument("--legs", default="precision,batched,sequence,correction",
+    ap.add_argument("--legs", default="precision,properties,batched,sequence,correction",
                     help="extension legs to run (comma-separated subset)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -257,6 +260,8 @@ def main():
     legs = set() if args.no_extensions else set(args.legs.split(","))
     if "precision" in legs:
         ext["precision"], others = precision_leg(P, torch, dev, x, qd, timer)
+    if "properties" in legs:
+        ext["properties"] = properties_leg(P, torch, dev, pts, q, x, qd, q_ms)
     if not args.no_cpu_baseline:
         res["cpu_baseline"], res["parity"], ref = run_cpu_baseline(
             pts, q, qg, gpu_out, {k: v.cpu().numpy() for k, v in glob.items()}, st["test_points"])
@@ -303,6 +308,40 @@ def precision_leg(P, torch, dev, x, qd, timer):
         outs[name] = {k: v.cpu().numpy() for k, v in o.items()}
         c.close()
     return rep, outs
+
+
+def properties_leg(P, torch, dev, pts, q, x, qd, q_plain_ms, n_sample=20000):
+    """The same frame with one surface property per return (a smooth
+    intensity texture plus N(0, 0.01) noise, Eq. (6)): training with it, the
+    band query with property and property variance, one fused frame with
+    the property (Sec. IV-C), and a sample of the band queries against the
+    FP64 oracle."""
+    import oracle as O
+    from paper_2407_09649_amd import scenes as S
+    prop = S.surface_intensity(pts, 11)
+    cp = torch.from_numpy(prop).to(dev)
+    c = P.Context(P.Params.default(voxel_size=0.1, properties=1), device=dev)
+    tm = Timer(torch, c.stream)
+    rep = {"train_ms": tm.median(lambda: c.train_prop(x, cp), reps=5)}
+    out = {}
+    rep["query_ms"] = tm.median(lambda: out.update(c.query_prop(qd, origin=ORIGIN, aux=False)), reps=10)
+    rep["query_rate"] = q.shape[0] / (rep["query_ms"] / 1e3)
+    rep["query_ms_without_property"] = q_plain_ms
+    rep["fuse_frame_ms"] = tm.median(lambda: c.fuse_prop(x, cp, ORIGIN), reps=5)
+    st = c.stats()
+    rep["refined_queries"] = st["refined_queries"]
+    idx = np.random.default_rng(12).choice(q.shape[0], n_sample, replace=False)
+    g = {k: v.cpu().numpy()[idx] for k, v in out.items()}
+    c.close()
+    t0 = time.perf_counter()
+    ref = O.Model(O.Params(voxel=0.1), pts, prop=prop).query(q[idx], origin=np.asarray(ORIGIN, np.float32))
+    rep["oracle_sample_s"] = time.perf_counter() - t0
+    v = ref["valid"]
+    rep.update(dist_errors(g, ref))
+    rep["sample"] = n_sample
+    rep["max_prop_err"] = float(np.abs(g["prop"][v] - ref["prop"][v]).max())
+    rep["max_prop_var_rel_err"] = float(np.abs(g["prop_var"][v] / ref["prop_var"][v] - 1).max())
+    return rep
 
 
 def batched_leg(P, torch, dev):
