@@ -103,6 +103,8 @@ def _bind(L):
     L.orc_model_factor.argtypes = [_P, _I64, _P]
     L.orc_query.argtypes = [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, C.c_int]
     L.orc_test_points.argtypes = [_P, _P, _I64]
+    L.orc_test_points_ray.argtypes = [_P, _P, _P, _P, _I64]
+    L.orc_test_points_ray.restype = _I64
     L.orc_test_points.restype = _I64
     L.orc_voxel_centres.argtypes = [_P, _I64, _D, _P]
     L.orc_map_new.restype = _P
@@ -253,6 +255,16 @@ class Model:
         n = int(lib().orc_test_points(self._h, None, 0))
         k = np.empty(n, np.uint64)
         lib().orc_test_points(self._h, _ptr(k), n)
+        return k
+
+    def test_points_ray(self, gmap, origin):
+        """Ray-cast test voxels (Sec. IV-B) against the map ``gmap`` (None:
+        an empty map): sorted unique keys."""
+        o = _f32(origin).reshape(3)
+        g = None if gmap is None else gmap._h
+        n = int(lib().orc_test_points_ray(self._h, g, _ptr(o), None, 0))
+        k = np.empty(n, np.uint64)
+        lib().orc_test_points_ray(self._h, g, _ptr(o), _ptr(k), n)
         return k
 
 

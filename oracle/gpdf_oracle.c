@@ -1042,12 +1042,18 @@ int orc_map_export_prop(const orc_map *g, double *C, double *W)
     return 1;
 }
 
-/* One frame of fusion against an already trained model: test points, signed
- * query, merge.  Returns the number of test points. */
+int64_t orc_test_points_ray(const orc_model *m, const orc_map *g, const float origin[3],
+                            uint64_t *out, int64_t cap);
+
+/* One frame of fusion against an already trained model: test points (the
+ * band, or the ray-cast and normal voxels of Sec. IV-B against the map as it
+ * is before this frame), signed query, merge.  Returns the number of test
+ * points. */
 int64_t orc_fuse(orc_map *g, const orc_model *m, const float origin[3],
                  uint32_t frame, int64_t *skipped, int nthreads)
 {
-    int64_t n = orc_test_points(m, NULL, 0);
+    const int ray = m->p.tp_mode == 1;
+    int64_t n = ray ? orc_test_points_ray(m, g, origin, NULL, 0) : orc_test_points(m, NULL, 0);
     uint64_t *k = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n + 1));
     float *x = (float *)malloc(sizeof(float) * 3 * (size_t)(n + 1));
     double *d = (double *)malloc(sizeof(double) * (size_t)(n + 1));
@@ -1056,7 +1062,8 @@ int64_t orc_fuse(orc_map *g, const orc_model *m, const float origin[3],
     uint8_t *ok = (uint8_t *)malloc((size_t)(n + 1));
     uint8_t *tie = (uint8_t *)malloc((size_t)(n + 1));
     int64_t sk;
-    orc_test_points(m, k, n);
+    if (ray) orc_test_points_ray(m, g, origin, k, n);
+    else orc_test_points(m, k, n);
     orc_voxel_centres(k, n, m->p.fuse_voxel, x);
     {
         double *c = NULL, *cv = NULL;
@@ -1082,6 +1089,176 @@ static int64_t orc_map_find(const orc_map *g, uint64_t key)
         if (g->key[mid] < key) lo = mid + 1; else hi = mid - 1;
     }
     return -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ray-cast test points (Sec. IV-B): for every training voxel, the global    */
+/* voxels on the ray from the sensor that the map already holds (previously  */
+/* observed surface), the voxel of the measurement itself, and the voxels    */
+/* along its surface normal up to normal_reach.                             */
+/* ------------------------------------------------------------------------ */
+/* The ray is walked in global-voxel units from the centre of the origin's
+ * voxel O to the centre of the training point's voxel E, visiting every
+ * voxel the segment passes through (a face-connected walk, the traversal of
+ * Amanatides and Woo) in exact integer arithmetic: with A = |E - O| per
+ * axis, the n-th boundary crossing on axis a lies at parameter
+ * (2n + 1) / (2 A_a), so the next axis is the one with the smallest
+ * (2 n_a + 1) / A_a, compared by cross-multiplication; equal parameters
+ * (the segment through an edge or corner) step the lower axis first. */
+static int orc_key_ok(const int64_t v[3])
+{
+    for (int a = 0; a < 3; ++a)
+        if (v[a] < -ORC_KEY_BIAS || v[a] >= ORC_KEY_BIAS) return 0;
+    return 1;
+}
+
+static int64_t orc_gcd(int64_t a, int64_t b)
+{
+    if (a < 0) a = -a;
+    if (b < 0) b = -b;
+    while (b) { int64_t t = a % b; a = b; b = t; }
+    return a;
+}
+
+/* candidate normal directions: the integer vectors with components in
+ * [-2, 2], primitive (gcd 1) and canonical (first non-zero component
+ * positive), in ascending lexicographic order of (x, y, z): 49 of them */
+static int orc_normal_dirs(int64_t d[64][3])
+{
+    int n = 0;
+    for (int64_t x = -2; x <= 2; ++x)
+        for (int64_t y = -2; y <= 2; ++y)
+            for (int64_t z = -2; z <= 2; ++z) {
+                int64_t f = x != 0 ? x : (y != 0 ? y : z);
+                if (f <= 0) continue;
+                if (orc_gcd(orc_gcd(x, y), z) != 1) continue;
+                d[n][0] = x; d[n][1] = y; d[n][2] = z; n++;
+            }
+    return n;
+}
+
+static int64_t orc_find_sorted(const uint64_t *a, int64_t n, uint64_t key)
+{
+    int64_t lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] == key) return mid;
+        if (a[mid] < key) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+/* The surface normal of a training voxel is the direction of least spread
+ * of the training voxels in the 5 x 5 x 5 block around it: among the
+ * candidate directions d the one minimising d^T M d / |d|^2, with
+ * M = N S2 - s1 s1^T (N^2 times the covariance of the integer offsets o:
+ * N their count, s1 = sum o, S2 = sum o o^T), compared exactly in integers;
+ * ties go to the first candidate.  Fewer than 3 neighbours: no normal. */
+int64_t orc_test_points_ray(const orc_model *m, const orc_map *g, const float origin[3],
+                            uint64_t *out, int64_t cap)
+{
+    const orc_params *p = &m->p;
+    const int64_t R = (int64_t)floor(p->normal_reach / p->fuse_voxel + 1e-9);
+    int64_t dirs[64][3];
+    const int nd = orc_normal_dirs(dirs);
+    int64_t O[3], n = 0, alloc = 1024;
+    uint64_t *vk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(m->npoints + 1));
+    uint64_t *all = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)alloc);
+    int okO = orc_floor_coord(origin[0], p->fuse_voxel, &O[0]) &&
+              orc_floor_coord(origin[1], p->fuse_voxel, &O[1]) &&
+              orc_floor_coord(origin[2], p->fuse_voxel, &O[2]);
+#define ORC_PUSH(key) do { if (n == alloc) { alloc *= 2; all = (uint64_t *)realloc(all, sizeof(uint64_t) * (size_t)alloc); } all[n++] = (key); } while (0)
+    /* the training voxels (voxel mode: one training point per voxel) */
+    for (int64_t i = 0; i < m->npoints; ++i) {
+        int64_t c[3] = {0, 0, 0};
+        orc_floor_coord(m->pts[3 * i], p->voxel, &c[0]);
+        orc_floor_coord(m->pts[3 * i + 1], p->voxel, &c[1]);
+        orc_floor_coord(m->pts[3 * i + 2], p->voxel, &c[2]);
+        vk[i] = orc_pack(c[0], c[1], c[2]);
+    }
+    qsort(vk, (size_t)m->npoints, sizeof(uint64_t), orc_u64_cmp);
+    for (int64_t i = 0; i < m->npoints && okO; ++i) {
+        int64_t E[3], cv[3];
+        const float *x = m->pts + 3 * i;
+        if (!(orc_floor_coord(x[0], p->fuse_voxel, &E[0]) && orc_floor_coord(x[1], p->fuse_voxel, &E[1]) &&
+              orc_floor_coord(x[2], p->fuse_voxel, &E[2]) && orc_floor_coord(x[0], p->voxel, &cv[0]) &&
+              orc_floor_coord(x[1], p->voxel, &cv[1]) && orc_floor_coord(x[2], p->voxel, &cv[2]))) continue;
+        /* the ray O -> E: previously observed voxels */
+        {
+            int64_t A[3], st[3], cnt[3] = {0, 0, 0}, cur[3] = {O[0], O[1], O[2]}, total = 0;
+            for (int a = 0; a < 3; ++a) {
+                int64_t dd = E[a] - O[a];
+                A[a] = dd < 0 ? -dd : dd;
+                st[a] = dd < 0 ? -1 : 1;
+                total += A[a];
+            }
+            for (int64_t k = 0; k <= total; ++k) {
+                if (k > 0) {
+                    int best = -1;
+                    for (int a = 0; a < 3; ++a) {
+                        if (cnt[a] >= A[a]) continue;
+                        if (best < 0 || (2 * cnt[a] + 1) * A[best] < (2 * cnt[best] + 1) * A[a]) best = a;
+                    }
+                    cur[best] += st[best];
+                    cnt[best]++;
+                }
+                if (k < total && g && orc_map_find(g, orc_pack(cur[0], cur[1], cur[2])) >= 0)
+                    ORC_PUSH(orc_pack(cur[0], cur[1], cur[2]));
+            }
+        }
+        /* the measured voxel */
+        ORC_PUSH(orc_pack(E[0], E[1], E[2]));
+        /* the normal: least spread of the training voxels within +-2 */
+        {
+            int64_t N = 0, s1[3] = {0, 0, 0}, S2[3][3] = {{0}};
+            for (int64_t a = -2; a <= 2; ++a)
+                for (int64_t b = -2; b <= 2; ++b)
+                    for (int64_t c = -2; c <= 2; ++c) {
+                        int64_t v[3] = {cv[0] + a, cv[1] + b, cv[2] + c}, o[3] = {a, b, c};
+                        if (!orc_key_ok(v) || orc_find_sorted(vk, m->npoints, orc_pack(v[0], v[1], v[2])) < 0)
+                            continue;
+                        N++;
+                        for (int r = 0; r < 3; ++r) {
+                            s1[r] += o[r];
+                            for (int q = 0; q < 3; ++q) S2[r][q] += o[r] * o[q];
+                        }
+                    }
+            if (N >= 3) {
+                int64_t M[3][3], bn = 0, bd = 1;
+                int best = -1;
+                for (int r = 0; r < 3; ++r)
+                    for (int q = 0; q < 3; ++q) M[r][q] = N * S2[r][q] - s1[r] * s1[q];
+                for (int t = 0; t < nd; ++t) {
+                    int64_t num = 0, den = 0;
+                    for (int r = 0; r < 3; ++r) {
+                        den += dirs[t][r] * dirs[t][r];
+                        for (int q = 0; q < 3; ++q) num += dirs[t][r] * M[r][q] * dirs[t][q];
+                    }
+                    if (best < 0 || num * bd < bn * den) { best = t; bn = num; bd = den; }
+                }
+                for (int64_t k = -R; k <= R; ++k) {
+                    int64_t v[3];
+                    if (k == 0 || k * k * bd > R * R) continue;
+                    for (int a = 0; a < 3; ++a) v[a] = E[a] + k * dirs[best][a];
+                    if (orc_key_ok(v)) ORC_PUSH(orc_pack(v[0], v[1], v[2]));
+                }
+            }
+        }
+    }
+#undef ORC_PUSH
+    qsort(all, (size_t)n, sizeof(uint64_t), orc_u64_cmp);
+    {
+        int64_t w = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (i == 0 || all[i] != all[i - 1]) {
+                if (out && w < cap) out[w] = all[i];
+                w++;
+            }
+        n = w;
+    }
+    free(all);
+    free(vk);
+    return n;
 }
 
 /* Global query on the fused grid: trilinear interpolation of D over the
