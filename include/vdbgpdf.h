@@ -273,8 +273,13 @@ gpdf_status gpdf_query_distance_noalloc(gpdf_ctx *ctx, const float *d_q, int64_t
 
 /* One frame of fusion (Sec. IV-B, IV-C): train on d_xyz [n][3] (or, with
  * d_xyz == NULL, reuse the current local GPs), generate the test voxels of
- * the global grid within fuse_band of the training points, query them signed
- * from h_origin, and fuse each valid result into the grid:
+ * the global grid (GPDF_TEST_BAND: those within fuse_band of the training
+ * points; GPDF_TEST_RAYCAST: for every training voxel the voxels on the ray
+ * from h_origin that the grid already holds, the measured voxel, and the
+ * voxels along its surface normal within normal_reach -- an exact integer
+ * walk between voxel centres, and the least-spread integer direction of the
+ * training voxels within +-2 voxels), query them signed from h_origin, and
+ * fuse each valid result into the grid:
  * D <- (V d + v D) / (V + v), V <- V v / (V + v) (Eq. (7)-(8)); absent voxels
  * take (d, v).  Updated voxels are stamped with the frame counter.
  * Errors: GPDF_E_CAPACITY (test points > max_queries, grid full),

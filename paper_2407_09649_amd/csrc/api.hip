@@ -57,7 +57,7 @@ void release(gpdf_ctx *c) {
         if (p) (void)hipFree(p);
     void *zptrs[] = {c->d_zkey, c->d_zkey2, c->d_zslot, c->d_zslot2, c->d_zcnt, c->d_zoff,
                      c->d_zhist, c->d_zpart, c->d_ztile, c->d_ztoff, c->d_need, c->d_trained,
-                     c->d_cprop, c->d_beta64, c->d_beta32, c->d_gprop, c->d_tprop, c->d_tpropv};
+                     c->d_cprop, c->d_beta64, c->d_beta32, c->d_gprop, c->d_tprop, c->d_tpropv, c->d_vhash};
     for (void *p : zptrs)
         if (p) (void)hipFree(p);
     if (c->h_stat) (void)hipHostFree(c->h_stat);
@@ -192,6 +192,10 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
               dalloc(c->d_tpts, 3 * M, e) && dalloc(c->d_gslot, int64_t(c->gmask) + 1, e) &&
               dalloc(c->d_gstamp, int64_t(c->gmask) + 1, e) && dalloc(c->d_offs, c->offs_cap, e) &&
               dalloc(c->d_stat, ST_COUNT, e) && dalloc(c->d_spread, int64_t(kSpread) * kSpreadStride, e);
+    if (ok && p->test_points == GPDF_TEST_RAYCAST) {
+        c->vhash_mask = pow2_mask(2 * P);
+        ok = dalloc(c->d_vhash, int64_t(c->vhash_mask) + 1, e);
+    }
     if (ok && p->properties)
         ok = dalloc(c->d_cprop, P, e) && dalloc(c->d_beta64, P, e) && dalloc(c->d_beta32, P + kPtsPad, e) &&
              dalloc(c->d_gprop, int64_t(c->gmask) + 1, e) && dalloc(c->d_tprop, M, e) && dalloc(c->d_tpropv, M, e);

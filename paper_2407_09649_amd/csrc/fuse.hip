@@ -117,6 +117,139 @@ __device__ inline int64_t grid_find(const GSlot *__restrict__ g, uint32_t gmask,
     return -1;
 }
 
+// ---------------------------------------------------------------------------
+// ray-cast test points (Sec. IV-B): for every training voxel, the global
+// voxels on the ray from the sensor that the grid already holds (previously
+// observed surface), the measured voxel itself, and the voxels along its
+// surface normal up to the normal reach R (in global voxels).
+// ---------------------------------------------------------------------------
+// the training voxels (keys at the training voxel size), for the normals
+__global__ void k_vox_insert(const float4 *__restrict__ pts, int64_t nb, const uint32_t *__restrict__ dn, double hv,
+                             HashView vh, unsigned long long *__restrict__ stat) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= dev_count(nb, dn)) return;
+    const float4 p = pts[i];
+    int64_t c[3];
+    if (!(cell_coord(p.x, hv, c[0]) && cell_coord(p.y, hv, c[1]) && cell_coord(p.z, hv, c[2]))) return;
+    bool ins;
+    if (hash_insert(vh, pack_key(c[0], c[1], c[2]), &ins) < 0) atomicAdd(&stat[ST_HASH_FULL], 1ull);
+}
+
+__device__ inline void test_add(HashView set, const int64_t v[3], unsigned long long *stat) {
+    if (v[0] < -kBias || v[0] >= kBias || v[1] < -kBias || v[1] >= kBias || v[2] < -kBias || v[2] >= kBias) return;
+    bool ins;
+    if (brick_insert(set, pack_key(v[0], v[1], v[2]), &ins) < 0) atomicAdd(&stat[ST_HASH_FULL], 1ull);
+}
+
+__device__ inline int64_t igcd(int64_t a, int64_t b) {
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// One lane per training voxel.  The ray: an exact integer walk between the
+// centres of the origin's voxel O and the measured voxel E that visits every
+// voxel the segment passes through; with A = |E - O| per axis the n-th
+// boundary crossing on axis a lies at parameter (2n + 1) / (2 A_a), so each
+// step takes the axis of the smallest (2 n_a + 1) / A_a (cross-multiplied
+// in integers), the lower axis at equal parameters.  The normal: among the
+// integer directions d with components in [-2, 2] (primitive, first non-zero
+// component positive, in lexicographic order), the first minimising
+// d^T M d / |d|^2 with M = N S2 - s1 s1^T over the training voxels within
+// +-2 voxels (N, s1 = sum of offsets, S2 = sum of their outer products),
+// compared exactly; no normal with fewer than 3 of them.
+__global__ __launch_bounds__(256) void k_ray_tests(const float4 *__restrict__ pts, int64_t nb,
+                                                   const uint32_t *__restrict__ dn, double hv, double hf, float ox,
+                                                   float oy, float oz, const float *__restrict__ d_origin, int R,
+                                                   HashView vh, const GSlot *__restrict__ g, uint32_t gmask,
+                                                   HashView set, unsigned long long *__restrict__ stat) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= dev_count(nb, dn)) return;
+    if (d_origin) { ox = d_origin[0]; oy = d_origin[1]; oz = d_origin[2]; }
+    int64_t O[3], E[3], cv[3];
+    if (!(cell_coord(ox, hf, O[0]) && cell_coord(oy, hf, O[1]) && cell_coord(oz, hf, O[2]))) return;
+    const float4 p = pts[i];
+    if (!(cell_coord(p.x, hf, E[0]) && cell_coord(p.y, hf, E[1]) && cell_coord(p.z, hf, E[2]) &&
+          cell_coord(p.x, hv, cv[0]) && cell_coord(p.y, hv, cv[1]) && cell_coord(p.z, hv, cv[2])))
+        return;
+    // the ray O -> E: voxels the grid holds before this frame
+    {
+        int64_t A[3], st[3], n[3] = {0, 0, 0}, cur[3] = {O[0], O[1], O[2]}, total = 0;
+        for (int a = 0; a < 3; ++a) {
+            const int64_t d = E[a] - O[a];
+            A[a] = d < 0 ? -d : d;
+            st[a] = d < 0 ? -1 : 1;
+            total += A[a];
+        }
+        for (int64_t k = 0; k < total; ++k) {
+            if (k > 0) {
+                int b = -1;
+                for (int a = 0; a < 3; ++a) {
+                    if (n[a] >= A[a]) continue;
+                    if (b < 0 || (2 * n[a] + 1) * A[b] < (2 * n[b] + 1) * A[a]) b = a;
+                }
+                cur[b] += st[b];
+                ++n[b];
+            }
+            if (grid_find(g, gmask, pack_key(cur[0], cur[1], cur[2])) >= 0) test_add(set, cur, stat);
+        }
+    }
+    // the measured voxel
+    test_add(set, E, stat);
+    // the normal
+    int64_t N = 0, s1[3] = {0, 0, 0}, S2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int a = -2; a <= 2; ++a)
+        for (int b = -2; b <= 2; ++b)
+            for (int c = -2; c <= 2; ++c) {
+                const int64_t v[3] = {cv[0] + a, cv[1] + b, cv[2] + c};
+                if (v[0] < -kBias || v[0] >= kBias || v[1] < -kBias || v[1] >= kBias || v[2] < -kBias ||
+                    v[2] >= kBias)
+                    continue;
+                if (hash_find(vh.keys, vh.mask, pack_key(v[0], v[1], v[2])) < 0) continue;
+                const int64_t o[3] = {a, b, c};
+                ++N;
+                for (int r = 0; r < 3; ++r) {
+                    s1[r] += o[r];
+                    for (int q = 0; q < 3; ++q) S2[r][q] += o[r] * o[q];
+                }
+            }
+    if (N < 3) return;
+    int64_t M[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) M[r][q] = N * S2[r][q] - s1[r] * s1[q];
+    int64_t bn = 0, bd = 1, bdir[3] = {0, 0, 0};
+    bool have = false;
+    for (int x = -2; x <= 2; ++x)
+        for (int y = -2; y <= 2; ++y)
+            for (int z = -2; z <= 2; ++z) {
+                const int f = x != 0 ? x : (y != 0 ? y : z);
+                if (f <= 0 || igcd(igcd(x, y), z) != 1) continue;
+                const int64_t d[3] = {x, y, z};
+                int64_t num = 0, den = 0;
+                for (int r = 0; r < 3; ++r) {
+                    den += d[r] * d[r];
+                    for (int q = 0; q < 3; ++q) num += d[r] * M[r][q] * d[q];
+                }
+                if (!have || num * bd < bn * den) {
+                    have = true;
+                    bn = num;
+                    bd = den;
+                    bdir[0] = x; bdir[1] = y; bdir[2] = z;
+                }
+            }
+    for (int64_t k = -R; k <= R; ++k) {
+        if (k == 0 || k * k * bd > int64_t(R) * R) continue;
+        const int64_t v[3] = {E[0] + k * bdir[0], E[1] + k * bdir[1], E[2] + k * bdir[2]};
+        test_add(set, v, stat);
+    }
+}
+
+
 // Eq. (7)-(8): D <- (V d + v D) / (V + v), V <- V v / (V + v); an absent voxel
 // takes (d, v) (the V = infinity limit).
 // TSDF (Eq. (9)): weight w = 1 - v, D <- (w d + V D) / (V + w), V <- V + w; an
@@ -391,21 +524,37 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin, int64_
         c->frame++;
         return GPDF_OK;
     }
-    gpdf_status st = ensure_offsets(c);
+    const bool ray = c->p.test_points == GPDF_TEST_RAYCAST;
+    gpdf_status st = ray ? GPDF_OK : ensure_offsets(c);
     if (st != GPDF_OK) {
         (void)fill_multi(F, s);
         return st;
     }
     const double hf = c->p.fuse_voxel_size;
-    const int noffs = int(c->h_offs.size());
     const int64_t tcap = int64_t(c->tset_mask) + 1;
     stage_begin(c, GPDF_MS_TESTPTS);
     F.u64(c->d_tset, (unsigned long long)kNoKey, tcap);
+    if (ray) F.u64(c->d_vhash, (unsigned long long)kNoKey, int64_t(c->vhash_mask) + 1);
     if ((e = fill_multi(F, s)) != hipSuccess) return hip_fail(c, e, "fuse: clear");
     HashView set{c->d_tset, c->tset_mask};
-    const int64_t work = npts * int64_t(noffs);
-    hipLaunchKernelGGL(k_test_insert, dim3(blocks_for(work)), dim3(kT), 0, s, c->d_pts, npts,
-                       eager ? nullptr : cnt + CNT_PTS, hf, c->d_offs, noffs, set, c->d_stat);
+    const uint32_t *dpts = eager ? nullptr : cnt + CNT_PTS;
+    if (ray) {
+        // Sec. IV-B: rays from the sensor to the training voxels against the
+        // grid as it is before this frame, the measured voxels and their
+        // normals
+        const HashView vh{c->d_vhash, c->vhash_mask};
+        const int R = int(std::floor(c->p.normal_reach / hf + 1e-9));
+        hipLaunchKernelGGL(k_vox_insert, dim3(blocks_for(npts)), dim3(kT), 0, s, c->d_pts, npts, dpts,
+                           c->p.voxel_size, vh, c->d_stat);
+        hipLaunchKernelGGL(k_ray_tests, dim3(blocks_for(npts)), dim3(kT), 0, s, c->d_pts, npts, dpts,
+                           c->p.voxel_size, hf, origin ? origin[0] : 0.f, origin ? origin[1] : 0.f,
+                           origin ? origin[2] : 0.f, d_origin, R, vh, c->d_gslot, c->gmask, set, c->d_stat);
+    } else {
+        const int noffs = int(c->h_offs.size());
+        const int64_t work = npts * int64_t(noffs);
+        hipLaunchKernelGGL(k_test_insert, dim3(blocks_for(work)), dim3(kT), 0, s, c->d_pts, npts, dpts, hf,
+                           c->d_offs, noffs, set, c->d_stat);
+    }
     count_occupied(c->d_tset, tcap, c->d_tile_cnt, c->d_tile_off, c->d_part, s);
     const int64_t ntiles = compact_tiles(tcap);
     hipLaunchKernelGGL(k_test_compact, dim3(unsigned(ntiles)), dim3(256), 0, s, c->d_tset, tcap,

@@ -449,6 +449,8 @@ struct gpdf_ctx {
     // ---- fusion / global grid ---------------------------------------------
     unsigned long long *d_tset = nullptr;          // test-voxel set keys
     uint32_t tset_mask = 0;
+    unsigned long long *d_vhash = nullptr;         // ray-cast test points: training voxel keys
+    uint32_t vhash_mask = 0;
     uint64_t *d_tkeys = nullptr;                   // compacted test keys
     float *d_tpts = nullptr;                       // test points [3]
     gpdf::GSlot *d_gslot = nullptr;                // global grid slots (key, D, V)

@@ -160,3 +160,51 @@ def test_fuse_before_training_fails(dev):
         with pytest.raises(P.GpdfError) as ei:
             ctx.fuse(None, np.zeros(3, np.float32))
         assert ei.value.status == 5
+
+
+def test_raycast_test_points_and_fusion_parity(dev):
+    """Ray-cast test voxels (Sec. IV-B) over four frames of the moving
+    sensor: every frame's test-voxel set equals the oracle's bit for bit
+    (rays against the grid before the frame, measured voxels, normals), and
+    the fused grid and global queries match within the tolerances."""
+    path, frames = _frames(8, 4)
+    p = small_params(voxel_size=0.1, test_points=P.TEST_RAYCAST, normal_reach=0.2)
+    ctx = P.Context(p, device=dev)
+    omap = O.Map()
+    for i, (pts, o) in enumerate(zip(frames, path)):
+        o32 = np.asarray(o, np.float32)
+        om = O.Model(oracle_params(p), pts)
+        expect = om.test_points_ray(omap, o32)
+        ctx.fuse(torch.from_numpy(pts).to(dev), o32)
+        got = ctx.export_test_points()
+        assert np.array_equal(got, expect), f"frame {i}: {len(got)} vs {len(expect)} test voxels"
+        n, _ = omap.fuse(om, o32, i)
+        assert n == len(expect)
+        print(f"frame {i}: {n} ray-cast test voxels", flush=True)
+    torch.cuda.synchronize()
+    _, o = check_grid(ctx, omap, "ray-cast four frames")
+    rng = np.random.default_rng(2)
+    q = _keys_to_centres(o["key"][rng.choice(len(o["key"]), 20000)], 0.05, rng)
+    # the ray-cast grid is a thin shell along the normals: few points have
+    # all eight neighbouring voxels (validity itself is compared exactly)
+    assert check_global(ctx, omap, q, dev, "ray-cast observed voxels") > 0
+    ctx.close()
+
+
+def test_raycast_graph_equals_eager(dev):
+    """The captured frame with ray-cast test voxels (origin read on the
+    device) gives bitwise the grid of the eager calls."""
+    path, frames = _frames(9, 4)
+    p = small_params(voxel_size=0.1, test_points=P.TEST_RAYCAST, max_points=1 << 14,
+                     max_queries=1 << 19, global_capacity=1 << 21)
+    a = P.Context(p, device=dev)
+    b = P.Context(p, device=dev)
+    for pts, o in zip(frames, path):
+        x = torch.from_numpy(pts).to(dev)
+        a.fuse(x, np.asarray(o, np.float32))
+        b.fuse_graph(x, np.asarray(o, np.float32))
+    ga, gb = a.export_global(), b.export_global()
+    for k in ("key", "stamp", "D", "V"):
+        assert np.array_equal(ga[k], gb[k]), k
+    a.close()
+    b.close()
