@@ -426,6 +426,54 @@ def sequence_leg(P, torch, dev, n_frames=100):
     rep["graph_equals_eager"] = all(np.array_equal(grids["eager"][k], grids["graph"][k])
                                     for k in ("key", "D", "V", "stamp"))
     rep["oracle_check"] = sequence_oracle_check(P, torch, dev, frames, path, prm)
+    rep["raycast"] = raycast_check(P, torch, dev, frames, path, prm)
+    return rep
+
+
+def raycast_check(P, torch, dev, frames, path, prm, n_frames=20, k_oracle=2):
+    """The paper's test points (Sec. IV-B: rays against the grid, measured
+    voxels, normals) on the first frames of the sequence, beside the band:
+    test voxels and time per frame, and the first frames' test-voxel sets
+    and grid against the oracle."""
+    import oracle as O
+    rep = {"frames": n_frames}
+    for mode, tp in (("band", P.TEST_BAND), ("raycast", P.TEST_RAYCAST)):
+        c = P.Context(P.Params.default(timing=1, test_points=tp, **prm), device=dev)
+        c.fuse(frames[0], path[0].astype(np.float32))
+        torch.cuda.synchronize()
+        tests, tp_ms = 0, 0.0
+        t = time.perf_counter()
+        for i in range(1, n_frames):
+            c.fuse(frames[i], path[i].astype(np.float32))
+            st = c.stats()
+            tests += st["test_points"]
+            tp_ms += st["ms"]["testpts"]
+        dt = time.perf_counter() - t
+        rep[mode] = {"ms_per_frame": 1e3 * dt / (n_frames - 1), "test_voxels_per_frame": tests / (n_frames - 1),
+                     "test_voxel_generation_ms": tp_ms / (n_frames - 1), "global_voxels": c.stats()["global_voxels"]}
+        c.close()
+    # the first frames against the oracle (host cores)
+    c = P.Context(P.Params.default(test_points=P.TEST_RAYCAST, **prm), device=dev)
+    omap = O.Map()
+    op = O.Params(voxel=0.1, tp_mode=1, normal_reach=0.2)
+    same = True
+    t0 = time.perf_counter()
+    for i in range(k_oracle):
+        o = path[i].astype(np.float32)
+        om = O.Model(op, frames[i].cpu().numpy())
+        expect = om.test_points_ray(omap, o)
+        c.fuse(frames[i], o)
+        same = same and bool(np.array_equal(c.export_test_points(), expect))
+        omap.fuse(om, o, i)
+    g, r = c.export_global(), omap.export()
+    t = r["sign_tie"]
+    rep["oracle"] = {"frames": k_oracle, "test_voxel_sets_equal": same, "oracle_s": time.perf_counter() - t0,
+                     "keys_and_stamps_equal": bool(np.array_equal(g["key"], r["key"]) and
+                                                   np.array_equal(g["stamp"], r["stamp"]))}
+    if rep["oracle"]["keys_and_stamps_equal"]:
+        rep["oracle"]["max_D_err_m"] = float(np.abs(g["D"][~t] - r["D"][~t]).max())
+        rep["oracle"]["max_V_rel_err"] = float(np.abs(g["V"] / r["V"] - 1).max())
+    c.close()
     return rep
 
 

@@ -152,72 +152,151 @@ __device__ inline int64_t igcd(int64_t a, int64_t b) {
     return a;
 }
 
-// One lane per training voxel.  The ray: an exact integer walk between the
+// The ray of every training voxel: an exact integer walk between the
 // centres of the origin's voxel O and the measured voxel E that visits every
-// voxel the segment passes through; with A = |E - O| per axis the n-th
-// boundary crossing on axis a lies at parameter (2n + 1) / (2 A_a), so each
-// step takes the axis of the smallest (2 n_a + 1) / A_a (cross-multiplied
-// in integers), the lower axis at equal parameters.  The normal: among the
-// integer directions d with components in [-2, 2] (primitive, first non-zero
-// component positive, in lexicographic order), the first minimising
-// d^T M d / |d|^2 with M = N S2 - s1 s1^T over the training voxels within
-// +-2 voxels (N, s1 = sum of offsets, S2 = sum of their outer products),
-// compared exactly; no normal with fewer than 3 of them.
-__global__ __launch_bounds__(256) void k_ray_tests(const float4 *__restrict__ pts, int64_t nb,
-                                                   const uint32_t *__restrict__ dn, double hv, double hf, float ox,
-                                                   float oy, float oz, const float *__restrict__ d_origin, int R,
-                                                   HashView vh, const GSlot *__restrict__ g, uint32_t gmask,
-                                                   HashView set, unsigned long long *__restrict__ stat) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// voxel the segment passes through.  With A = |E - O| per axis the n-th
+// boundary crossing on axis a lies at parameter (2n + 1) / (2 A_a); each
+// step takes the axis of the smallest such parameter (cross-multiplied in
+// integers), the lower axis at equal parameters.  The voxels the grid holds
+// before this frame are test voxels (E itself is added by k_normal_tests).
+// kRaySeg lanes share a ray: lane j walks the crossings with parameter in
+// [j / kRaySeg, (j + 1) / kRaySeg), starting from the counts of the crossings
+// before it (n with (2n + 1) kRaySeg < 2 j A_a), so the crossings of one
+// parameter stay in one piece and the pieces visit exactly the voxels of the
+// whole walk; piece 0 also probes O.
+constexpr int kRaySeg = 16;
+
+__device__ inline int64_t crossings_before(int64_t jj, int64_t A) {
+    const int64_t num = 2 * jj * A - kRaySeg, den = 2 * kRaySeg;
+    const int64_t c = num <= 0 ? 0 : (num + den - 1) / den;
+    return c < A ? c : A;
+}
+
+__global__ __launch_bounds__(256) void k_ray_walk(const float4 *__restrict__ pts, int64_t nb,
+                                                  const uint32_t *__restrict__ dn, double hf, float ox, float oy,
+                                                  float oz, const float *__restrict__ d_origin,
+                                                  const GSlot *__restrict__ g, uint32_t gmask, HashView set,
+                                                  unsigned long long *__restrict__ stat) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t i = t / kRaySeg;
+    const int j = int(t - i * kRaySeg);
     if (i >= dev_count(nb, dn)) return;
     if (d_origin) { ox = d_origin[0]; oy = d_origin[1]; oz = d_origin[2]; }
-    int64_t O[3], E[3], cv[3];
+    int64_t O[3], E[3];
     if (!(cell_coord(ox, hf, O[0]) && cell_coord(oy, hf, O[1]) && cell_coord(oz, hf, O[2]))) return;
+    const float4 p = pts[i];
+    if (!(cell_coord(p.x, hf, E[0]) && cell_coord(p.y, hf, E[1]) && cell_coord(p.z, hf, E[2]))) return;
+    int64_t A[3], st[3], n[3], cur[3], total = 0, k = 0, steps = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t d = E[a] - O[a];
+        A[a] = d < 0 ? -d : d;
+        st[a] = d < 0 ? -1 : 1;
+        total += A[a];
+        n[a] = crossings_before(j, A[a]);
+        steps += crossings_before(j + 1, A[a]) - n[a];
+        k += n[a];
+        cur[a] = O[a] + st[a] * n[a];
+    }
+    if (total == 0) return;
+    if (j == 0 && grid_find(g, gmask, pack_key(O[0], O[1], O[2])) >= 0) test_add(set, O, stat);
+    // kRayBatch steps at a time: the walk does not depend on the probes, so
+    // the first slot of every step's voxel is loaded together
+    constexpr int kRayBatch = 8;
+    for (int64_t s0i = 0; s0i < steps; s0i += kRayBatch) {
+        uint64_t key[kRayBatch], sl[kRayBatch];
+        GSlot e[kRayBatch];
+        bool use[kRayBatch];
+#pragma unroll
+        for (int b = 0; b < kRayBatch; ++b) {
+            use[b] = false;
+            if (s0i + b < steps) {
+                int ax = -1;
+                for (int a = 0; a < 3; ++a) {
+                    if (n[a] >= A[a]) continue;
+                    if (ax < 0 || (2 * n[a] + 1) * A[ax] < (2 * n[ax] + 1) * A[a]) ax = a;
+                }
+                cur[ax] += st[ax];
+                ++n[ax];
+                ++k;
+                use[b] = k < total;   // the last position is E
+            }
+            key[b] = pack_key(cur[0], cur[1], cur[2]);
+            sl[b] = grid_start(key[b], gmask);
+        }
+#pragma unroll
+        for (int b = 0; b < kRayBatch; ++b)
+            if (use[b]) e[b] = g[sl[b]];
+#pragma unroll
+        for (int b = 0; b < kRayBatch; ++b) {
+            float D;
+            if (use[b] && grid_resolve(g, gmask, key[b], sl[b], e[b], &D)) {
+                int64_t v[3];
+                unpack_key(key[b], v);
+                test_add(set, v, stat);
+            }
+        }
+    }
+}
+
+// One lane per training voxel: the measured voxel E and the voxels along its
+// normal.  The normal: among the integer directions d with components in
+// [-2, 2] (primitive, first non-zero component positive, in lexicographic
+// order), the first minimising d^T M d / |d|^2 with M = N S2 - s1 s1^T over
+// the training voxels within +-2 voxels (N, s1 = sum of offsets, S2 = sum of
+// their outer products), compared exactly; no normal with fewer than 3.
+__global__ __launch_bounds__(256) void k_normal_tests(const float4 *__restrict__ pts, int64_t nb,
+                                                      const uint32_t *__restrict__ dn, double hv, double hf, int R,
+                                                      HashView vh, HashView set,
+                                                      unsigned long long *__restrict__ stat) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= dev_count(nb, dn)) return;
+    int64_t E[3], cv[3];
     const float4 p = pts[i];
     if (!(cell_coord(p.x, hf, E[0]) && cell_coord(p.y, hf, E[1]) && cell_coord(p.z, hf, E[2]) &&
           cell_coord(p.x, hv, cv[0]) && cell_coord(p.y, hv, cv[1]) && cell_coord(p.z, hv, cv[2])))
         return;
-    // the ray O -> E: voxels the grid holds before this frame
-    {
-        int64_t A[3], st[3], n[3] = {0, 0, 0}, cur[3] = {O[0], O[1], O[2]}, total = 0;
-        for (int a = 0; a < 3; ++a) {
-            const int64_t d = E[a] - O[a];
-            A[a] = d < 0 ? -d : d;
-            st[a] = d < 0 ? -1 : 1;
-            total += A[a];
-        }
-        for (int64_t k = 0; k < total; ++k) {
-            if (k > 0) {
-                int b = -1;
-                for (int a = 0; a < 3; ++a) {
-                    if (n[a] >= A[a]) continue;
-                    if (b < 0 || (2 * n[a] + 1) * A[b] < (2 * n[b] + 1) * A[a]) b = a;
-                }
-                cur[b] += st[b];
-                ++n[b];
-            }
-            if (grid_find(g, gmask, pack_key(cur[0], cur[1], cur[2])) >= 0) test_add(set, cur, stat);
-        }
-    }
     // the measured voxel
     test_add(set, E, stat);
     // the normal
+    // the 5 x 5 x 5 block, a 5 x 5 slice at a time: the first slots of its
+    // 25 lookups are loaded together
     int64_t N = 0, s1[3] = {0, 0, 0}, S2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int a = -2; a <= 2; ++a)
-        for (int b = -2; b <= 2; ++b)
-            for (int c = -2; c <= 2; ++c) {
-                const int64_t v[3] = {cv[0] + a, cv[1] + b, cv[2] + c};
-                if (v[0] < -kBias || v[0] >= kBias || v[1] < -kBias || v[1] >= kBias || v[2] < -kBias ||
-                    v[2] >= kBias)
-                    continue;
-                if (hash_find(vh.keys, vh.mask, pack_key(v[0], v[1], v[2])) < 0) continue;
-                const int64_t o[3] = {a, b, c};
-                ++N;
-                for (int r = 0; r < 3; ++r) {
-                    s1[r] += o[r];
-                    for (int q = 0; q < 3; ++q) S2[r][q] += o[r] * o[q];
-                }
+    for (int a = -2; a <= 2; ++a) {
+        uint64_t key[25], sl[25];
+        unsigned long long f[25];
+        bool in[25];
+#pragma unroll
+        for (int j = 0; j < 25; ++j) {
+            const int64_t v[3] = {cv[0] + a, cv[1] + j / 5 - 2, cv[2] + j % 5 - 2};
+            in[j] = !(v[0] < -kBias || v[0] >= kBias || v[1] < -kBias || v[1] >= kBias || v[2] < -kBias ||
+                      v[2] >= kBias);
+            key[j] = in[j] ? pack_key(v[0], v[1], v[2]) : 0ull;
+            sl[j] = mix64(key[j]) & vh.mask;
+        }
+#pragma unroll
+        for (int j = 0; j < 25; ++j) f[j] = in[j] ? vh.keys[sl[j]] : (unsigned long long)kNoKey;
+#pragma unroll
+        for (int j = 0; j < 25; ++j) {
+            if (!in[j]) continue;
+            // linear probing from the slot already read
+            bool found = false;
+            uint64_t sj = sl[j];
+            unsigned long long kj = f[j];
+            for (uint32_t p = 0; p <= vh.mask; ++p) {
+                if (kj == key[j]) { found = true; break; }
+                if (kj == kNoKey) break;
+                sj = (sj + 1) & vh.mask;
+                kj = vh.keys[sj];
             }
+            if (!found) continue;
+            const int64_t o[3] = {a, j / 5 - 2, j % 5 - 2};
+            ++N;
+            for (int r = 0; r < 3; ++r) {
+                s1[r] += o[r];
+                for (int q = 0; q < 3; ++q) S2[r][q] += o[r] * o[q];
+            }
+        }
+    }
     if (N < 3) return;
     int64_t M[3][3];
     for (int r = 0; r < 3; ++r)
@@ -546,9 +625,11 @@ gpdf_status fuse(gpdf_ctx *c, const float *origin, const float *d_origin, int64_
         const int R = int(std::floor(c->p.normal_reach / hf + 1e-9));
         hipLaunchKernelGGL(k_vox_insert, dim3(blocks_for(npts)), dim3(kT), 0, s, c->d_pts, npts, dpts,
                            c->p.voxel_size, vh, c->d_stat);
-        hipLaunchKernelGGL(k_ray_tests, dim3(blocks_for(npts)), dim3(kT), 0, s, c->d_pts, npts, dpts,
-                           c->p.voxel_size, hf, origin ? origin[0] : 0.f, origin ? origin[1] : 0.f,
-                           origin ? origin[2] : 0.f, d_origin, R, vh, c->d_gslot, c->gmask, set, c->d_stat);
+        hipLaunchKernelGGL(k_ray_walk, dim3(blocks_for(npts * kRaySeg)), dim3(kT), 0, s, c->d_pts, npts, dpts, hf,
+                           origin ? origin[0] : 0.f, origin ? origin[1] : 0.f, origin ? origin[2] : 0.f, d_origin,
+                           c->d_gslot, c->gmask, set, c->d_stat);
+        hipLaunchKernelGGL(k_normal_tests, dim3(blocks_for(npts)), dim3(kT), 0, s, c->d_pts, npts, dpts,
+                           c->p.voxel_size, hf, R, vh, set, c->d_stat);
     } else {
         const int noffs = int(c->h_offs.size());
         const int64_t work = npts * int64_t(noffs);
@@ -1002,11 +1083,11 @@ extern "C" gpdf_status gpdf_load_global(gpdf_ctx *c, const char *path) {
         return hip_fail(c, e, "load_global: upload");
     hipLaunchKernelGGL(k_global_load, dim3(unsigned((h.count + kT - 1) / kT)), dim3(kT), 0, s, dk, dD,
                        dV, ds, h.count, c->d_gslot, c->gmask, c->d_gstamp, c->d_stat, dcw, c->d_gprop);
-    if (dcw) hipFreeAsync(dcw, s);
-    hipFreeAsync(dk, s);
-    hipFreeAsync(dD, s);
-    hipFreeAsync(dV, s);
-    hipFreeAsync(ds, s);
+    if (dcw) (void)hipFreeAsync(dcw, s);
+    (void)hipFreeAsync(dk, s);
+    (void)hipFreeAsync(dD, s);
+    (void)hipFreeAsync(dV, s);
+    (void)hipFreeAsync(ds, s);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "load_global");
     return GPDF_OK;
 }
