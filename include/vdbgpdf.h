@@ -74,11 +74,14 @@ enum { GPDF_COMB_SMOOTHMIN = 0, GPDF_COMB_HARDMIN = 1 };
  * gradients ("directly average", Sec. IV-D) */
 enum { GPDF_GRAD_WEIGHTED = 0, GPDF_GRAD_PAPER_MEAN = 1 };
 /* query arithmetic: FP32 with an FP64 re-evaluation of the queries whose FP32
- * error bound exceeds the tolerance; everything in FP64; or the FP32 path with
+ * error bound exceeds the tolerance; everything in FP64; the FP32 path with
  * the variance product W k on BF16 MFMA (FP32 accumulation), whose queries are
  * re-evaluated in FP64 for distance and gradient but not for the variance,
- * which keeps the BF16 error */
-enum { GPDF_PREC_FP32 = 0, GPDF_PREC_BF16 = 1, GPDF_PREC_FP64 = 2 };
+ * which keeps the BF16 error; or the FP32 path with W k on FP32 MFMA
+ * (v_mfma_f32_16x16x4_f32, clusters up to 248 points), every output keeping
+ * the FP32 path's tolerances.  The two MFMA modes need NEIGHBOR27 selection
+ * and are not captured in the frame graph. */
+enum { GPDF_PREC_FP32 = 0, GPDF_PREC_BF16 = 1, GPDF_PREC_FP64 = 2, GPDF_PREC_FP32_MFMA = 3 };
 /* fusion rule: inverse-variance weighting of Eq. (7)-(8), or the TSDF-style
  * accumulated weights of Eq. (9) with the weight 1 - v of each observation
  * (non-positive weights are skipped) */

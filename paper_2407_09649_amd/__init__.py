@@ -14,7 +14,7 @@ import os
 __all__ = ["Params", "Stats", "Context", "load_library", "library_path",
            "KERNEL_MATERN32", "KERNEL_SE", "SEL_NEIGHBOR27", "SEL_KNN",
            "COMB_SMOOTHMIN", "COMB_HARDMIN", "GRAD_WEIGHTED", "GRAD_PAPER_MEAN",
-           "PREC_FP32", "PREC_BF16", "PREC_FP64", "MLP_NPARAM", "GpdfError",
+           "PREC_FP32", "PREC_BF16", "PREC_FP64", "PREC_FP32_MFMA", "MLP_NPARAM", "GpdfError",
            "FUSE_INVVAR", "FUSE_TSDF", "TEST_BAND", "TEST_RAYCAST",
            "STATUS_HASH_FULL", "STATUS_GLOBAL_FULL", "STATUS_NONFINITE", "STATUS_NONPD",
            "STATUS_CAPACITY"]
@@ -24,7 +24,7 @@ KERNEL_MATERN32, KERNEL_SE = 0, 1
 SEL_NEIGHBOR27, SEL_KNN = 0, 1
 COMB_SMOOTHMIN, COMB_HARDMIN = 0, 1
 GRAD_WEIGHTED, GRAD_PAPER_MEAN = 0, 1
-PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_FP64, PREC_FP32_MFMA = 0, 1, 2, 3
 FUSE_INVVAR, FUSE_TSDF = 0, 1
 TEST_BAND, TEST_RAYCAST = 0, 1
 MLP_NPARAM = 8897

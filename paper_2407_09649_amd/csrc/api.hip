@@ -127,8 +127,8 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
         (p->selection == GPDF_SEL_KNN && (p->knn_q < 1 || p->knn_q > 16)) ||
         (p->combine != GPDF_COMB_SMOOTHMIN && p->combine != GPDF_COMB_HARDMIN) ||
         (p->grad_mode != GPDF_GRAD_WEIGHTED && p->grad_mode != GPDF_GRAD_PAPER_MEAN) ||
-        (p->precision < GPDF_PREC_FP32 || p->precision > GPDF_PREC_FP64) ||
-        (p->precision == GPDF_PREC_BF16 && p->selection == GPDF_SEL_KNN) ||
+        (p->precision < GPDF_PREC_FP32 || p->precision > GPDF_PREC_FP32_MFMA) ||
+        ((p->precision == GPDF_PREC_BF16 || p->precision == GPDF_PREC_FP32_MFMA) && p->selection == GPDF_SEL_KNN) ||
         (p->timing != 0 && p->timing != 1) || p->max_points < 1 ||
         p->max_points > (int64_t(1) << 30) || p->max_clusters < 1 || p->max_cluster_points < 1 ||
         p->max_cluster_points > 1024 || p->max_factor_elems < 1 ||
@@ -140,7 +140,8 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
         !(std::isfinite(p->normal_reach) && p->normal_reach >= 0.0) ||
         (p->test_points == GPDF_TEST_RAYCAST && p->voxel_size <= 0.0) ||
         (p->lazy_train != 0 && p->lazy_train != 1) || (p->properties != 0 && p->properties != 1) ||
-        (p->properties && (p->precision == GPDF_PREC_BF16 || p->selection != GPDF_SEL_NEIGHBOR27 ||
+        (p->properties && (p->precision == GPDF_PREC_BF16 || p->precision == GPDF_PREC_FP32_MFMA ||
+                           p->selection != GPDF_SEL_NEIGHBOR27 ||
                            p->lazy_train)))
         return GPDF_E_INVALID_ARG;
     gpdf_ctx *c = new (std::nothrow) gpdf_ctx();
@@ -412,7 +413,8 @@ extern "C" gpdf_status gpdf_fuse_frame_graph(gpdf_ctx *c, const float *d_xyz, in
         return fail(c, GPDF_E_INVALID_ARG, "fuse_frame_graph: origin required");
     if (n < 0 || n > c->p.max_points) return fail(c, GPDF_E_CAPACITY, "fuse_frame_graph: n exceeds max_points");
     if (n > 0 && !d_xyz) return fail(c, GPDF_E_INVALID_ARG, "fuse_frame_graph: null points");
-    if (c->p.selection != GPDF_SEL_NEIGHBOR27 || c->p.precision == GPDF_PREC_BF16 || c->p.lazy_train)
+    if (c->p.selection != GPDF_SEL_NEIGHBOR27 || c->p.precision == GPDF_PREC_BF16 ||
+        c->p.precision == GPDF_PREC_FP32_MFMA || c->p.lazy_train)
         return fail(c, GPDF_E_INVALID_ARG, "fuse_frame_graph: needs NEIGHBOR27 selection in FP32 or FP64");
     try {
         if (!c->gexec) {

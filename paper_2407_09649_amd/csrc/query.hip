@@ -1524,6 +1524,126 @@ __device__ void eval_cluster_bf16(int base, int n, int64_t bfo, const float4 *__
     finish_pair<float, KERN>(r, n, C, A);
 }
 
+// ---------------------------------------------------------------------------
+// FP32 on MFMA: the variance product W k of a 64-query chunk and one cluster
+// as C = W K^T with v_mfma_f32_16x16x4_f32, FP32 operands and accumulation.
+// Everything else is the FP32 path (kernel values, sums, reverting, error
+// estimate and the FP64 re-evaluation of every output).
+// Lane layout (lane l, lr = l % 16, lg = l / 16): A[m][k] lane m + 16 k,
+// B[k][n] lane n + 16 k, D[m][n] lane n + 16 (m / 4), element m % 4
+// (checked on the device).  W is read from the FP32 factor in the query
+// layout; the kernel values sit in LDS, one row of kts floats per query (kts
+// odd, so that the 16 rows one MFMA operand reads lie in distinct banks).
+// Clusters above kF32mMaxN points use the VALU path.
+// ---------------------------------------------------------------------------
+constexpr int kF32mMaxN = 248;
+
+template <int KERN>
+__device__ void eval_cluster_f32m(int base, int n, int64_t woff, const float4 *__restrict__ pts,
+                                  const float *__restrict__ W32, float *Kt, int kts, const QueryPoint &Q,
+                                  const QueryConsts &C, Acc<float> &A) {
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    PairRaw<float> r{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int cols = (n + 3) & ~3;
+    const float4 *P = pts + base;
+    float *kr = Kt + lane * kts;
+    for (int j = 0; j < cols; ++j) {
+        float k = 0.f;
+        if (j < n) {
+            const float4 p = P[j];
+            k = point_eval<float, KERN>(p, p.w, Q, base + j, C, r, A);
+        }
+        kr[j] = k;
+    }
+    __syncthreads();
+    const float *W = W32 + woff;
+    float ssp[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int p0 = 0; p0 < n; p0 += 64) {
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // columns this row panel needs: up to its last row
+        const int kend = min(cols, (p0 + 64 + 3) & ~3);
+        for (int k0 = 0; k0 < kend; k0 += 4) {
+            float b[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) b[nt] = Kt[(16 * nt + lr) * kts + k0 + lg];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int row0 = p0 + 16 * mt;
+                if (row0 >= n) break;
+                // blocks above the diagonal of W are zero
+                if (k0 > row0 + 15) continue;
+                const int i = row0 + lr, j = k0 + lg;
+                const float a = (i < n && j <= i) ? W[w_index(n, i, j)] : 0.f;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nt], acc[mt][nt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int i = p0 + 16 * mt + 4 * lg + e;
+                    const float v = acc[mt][nt][e];
+                    if (i < n) ssp[nt] = fmaf(v, v, ssp[nt]);
+                }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        ssp[nt] += __shfl_xor(ssp[nt], 16, 64);
+        ssp[nt] += __shfl_xor(ssp[nt], 32, 64);
+    }
+    // query of this lane: column lr of tile lg
+    r.ss = pick4(ssp, lg);
+    __syncthreads();  // K is rewritten by the next cluster
+    finish_pair<float, KERN>(r, n, C, A);
+}
+
+template <int KERN, int MODE>
+__global__ __launch_bounds__(kEvalT) void k_query_cells_f32m(const float *__restrict__ q, Grouping G,
+                                                             const int4 *__restrict__ lists, ModelView Mo, int kts,
+                                                             QueryConsts C, Outputs O) {
+    extern __shared__ float Kf[];
+    const uint32_t nch = *ro(G.nchunks);
+    const uint32_t wave = xcd_item(nch);
+    const int lane = threadIdx.x & 63;
+    if (wave >= nch) return;
+    const uint2 ch = ro(G.chunk)[wave];
+    const uint32_t cell = uniform(ch.x), start = uniform(ch.y);
+    const uint32_t cnt = uniform(min(ro(G.cell_cnt)[cell] - start, 64u));
+    const bool active = uint32_t(lane) < cnt;
+    const uint32_t qi = G.order[ro(G.cell_off)[cell] + start + (active ? lane : 0)];
+    const QueryPoint Q{q[3 * qi], q[3 * qi + 1], q[3 * qi + 2]};
+    const RoPtr<int4> L = ro(lists + size_t(cell) * kListStride);
+    const int nsel = int(uniform(uint32_t(L[0].x)));
+    Acc<float> A;
+    acc_init(A);
+    uint32_t sum_n = 0, sum_tri = 0;
+    for (int s = 0; s < nsel; ++s) {
+        const int4 d = L[1 + s];
+        const int base = int(uniform(uint32_t(d.y))), n = int(uniform(uint32_t(d.z)));
+        const int64_t woff = int64_t(uniform(uint32_t(d.w)));
+        if (n <= kF32mMaxN)
+            eval_cluster_f32m<KERN>(base, n, woff, Mo.pts, Mo.W32, Kf, kts, Q, C, A);
+        else
+            eval_cluster<float, KERN>(base, n, woff, Mo.pts, Mo.alpha64, Mo.beta32, Mo.beta64, Mo.W32, Mo.W64, Q, C, A);
+        sum_n += uint32_t(n);
+        sum_tri += uint32_t(n * (n + 1) / 2);
+    }
+    finish_query<float, MODE>(A, qi, cell, active, Q, Mo.pts, C, O);
+    if (lane == 0 && nsel > 0) {
+        spread_add(O.spread, ST_PAIRS, (unsigned long long)nsel * cnt);
+        spread_add(O.spread, ST_POINTS, (unsigned long long)sum_n * cnt);
+        spread_add(O.spread, ST_TRI, (unsigned long long)sum_tri * cnt);
+    }
+}
+
 template <int KERN, int MODE>
 __global__ __launch_bounds__(kEvalT) void k_query_cells_bf16(const float *__restrict__ q, Grouping G,
                                                              const int4 *__restrict__ lists, ModelView Mo,
@@ -1809,6 +1929,20 @@ void launch_query_kf(int kernel, bool knn, unsigned grid, hipStream_t s, const f
         launch_query_m<T, GPDF_KERNEL_SE | PF>(knn, grid, s, q, G, lists, Mo, C, O, work);
 }
 
+template <int KERN>
+void launch_f32m_m(unsigned grid, size_t lds, hipStream_t s, const float *q, const Grouping &G, const int4 *lists,
+                   const ModelView &Mo, int kts, const QueryConsts &C, const Outputs &O) {
+    if (C.combine == GPDF_COMB_HARDMIN)
+        hipLaunchKernelGGL((k_query_cells_f32m<KERN, kModeHard>), dim3(grid), dim3(kEvalT), lds, s, q, G, lists, Mo,
+                           kts, C, O);
+    else if (C.grad_mode == GPDF_GRAD_PAPER_MEAN)
+        hipLaunchKernelGGL((k_query_cells_f32m<KERN, kModeMean>), dim3(grid), dim3(kEvalT), lds, s, q, G, lists, Mo,
+                           kts, C, O);
+    else
+        hipLaunchKernelGGL((k_query_cells_f32m<KERN, kModeSmooth>), dim3(grid), dim3(kEvalT), lds, s, q, G, lists,
+                           Mo, kts, C, O);
+}
+
 template <typename T>
 void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_t s, const float *q,
                     const Grouping &G, const int4 *lists, const ModelView &Mo,
@@ -2017,7 +2151,8 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     const bool want_prop = prop || prop_var;
     if (want_prop) {
         if (!M.props) return fail(c, GPDF_E_INVALID_ARG, "query: the model was trained without a property");
-        if (c->p.precision == GPDF_PREC_BF16 || c->p.selection != GPDF_SEL_NEIGHBOR27 || noalloc || correct)
+        if (c->p.precision == GPDF_PREC_BF16 || c->p.precision == GPDF_PREC_FP32_MFMA ||
+            c->p.selection != GPDF_SEL_NEIGHBOR27 || noalloc || correct)
             return fail(c, GPDF_E_INVALID_ARG,
                         "query: the property needs FP32 or FP64 precision, NEIGHBOR27 selection, no correction");
     }
@@ -2047,7 +2182,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     const QueryConsts C = make_consts(c->p, origin, d_origin);
     const bool vox = c->p.voxel_size > 0.0;
     const bool knn = C.knn_q > 0;
-    if (!eager && (knn || c->p.precision == GPDF_PREC_BF16 || correct)) {
+    if (!eager && (knn || c->p.precision == GPDF_PREC_BF16 || c->p.precision == GPDF_PREC_FP32_MFMA || correct)) {
         (void)fill_multi(F, s);
         return fail(c, GPDF_E_INVALID_ARG, "query with device counts: NEIGHBOR27, FP32/FP64, no correction");
     }
@@ -2155,6 +2290,16 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
                                                     O);
             else
                 launch_bf16_m<GPDF_KERNEL_SE>(grid, lds, s, d_q, G, lists, Mo, Mbf, c->d_bfoff, kts, Cb, O);
+        } else if (c->p.precision == GPDF_PREC_FP32_MFMA) {
+            // the variance product on FP32 MFMA; every output keeps the FP32
+            // path's error estimate and FP64 re-evaluation.  The LDS row of a
+            // query holds the largest cluster's kernel values (odd stride).
+            const int kts = ((int(std::min<int64_t>(std::max<int64_t>(M.max_n, 1), kF32mMaxN)) + 3) & ~3) + 1;
+            const size_t lds = size_t(64) * kts * sizeof(float);
+            if (kern == GPDF_KERNEL_MATERN32)
+                launch_f32m_m<GPDF_KERNEL_MATERN32>(grid, lds, s, d_q, G, lists, Mo, kts, C, O);
+            else
+                launch_f32m_m<GPDF_KERNEL_SE>(grid, lds, s, d_q, G, lists, Mo, kts, C, O);
         } else {
             launch_query_k<float>(c, kern, knn, grid, s, d_q, G, lists, Mo, C, O, 0);
         }

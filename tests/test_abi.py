@@ -61,7 +61,9 @@ def test_create_rejects_bad_parameters_without_touching_the_gpu():
            dict(test_points=2), dict(test_points=P.TEST_RAYCAST, voxel_size=0.0),
            dict(normal_reach=-1.0), dict(lazy_train=2), dict(properties=2),
            dict(properties=1, precision=P.PREC_BF16), dict(properties=1, selection=P.SEL_KNN),
-           dict(properties=1, lazy_train=1)]
+           dict(properties=1, lazy_train=1), dict(precision=4),
+           dict(precision=P.PREC_FP32_MFMA, selection=P.SEL_KNN),
+           dict(properties=1, precision=P.PREC_FP32_MFMA)]
     for kw in bad:
         p = P.Params.default(**kw)
         assert lib.gpdf_create(ctypes.byref(p), None, ctypes.byref(h)) == 1, kw

@@ -102,3 +102,36 @@ def test_bf16_uneven_patches(dev):
     q = ps.queries
     g32, g16, ref = _run(dev, ps.points, q, cluster_size=0.8, max_factor_elems=1 << 24)
     _check(g32, g16, ref, "patches")
+
+
+@pytest.mark.parametrize("scene", ["sphere", "lidar", "patches"])
+def test_fp32_mfma_parity(dev, scene):
+    """FP32 MFMA mode (the variance product on v_mfma_f32_16x16x4_f32): every
+    output within the FP32 path's tolerances against the oracle, with the
+    same FP64 re-evaluation; the patches reach 256 points, so clusters above
+    the MFMA path's 248 take the VALU path in the same launch."""
+    from parity import compare
+    import torch
+    origin = None
+    if scene == "sphere":
+        sc = S.sphere_scene(4)
+        pts, q, kw = sc.points, sc.queries, {}
+    elif scene == "lidar":
+        sc = S.lidar_scene(3)
+        origin = np.array([0.0, 0.0, 1.5], np.float32)
+        pts = S.lidar_frame(sc, origin, np.random.default_rng(3), n_beams=16, n_azimuth=256)
+        q = S.lidar_band_queries(pts, radius_cells=3)
+        kw = dict(voxel_size=0.1)
+    else:
+        ps = S.planar_patches(seed=3, n_patches=256)
+        pts, q, kw = ps.points, ps.queries, dict(cluster_size=0.8)
+    p = small_params(precision=P.PREC_FP32_MFMA, **kw)
+    ctx = P.Context(p, device=dev)
+    ctx.train(torch.from_numpy(pts).to(dev))
+    g = gpu_query(ctx, q, origin)
+    st = ctx.stats()
+    ctx.close()
+    ref = O.Model(oracle_params(p), pts).query(q, origin=origin)
+    r = compare(g, ref, label=f"fp32 mfma {scene}")
+    print(scene, "refined", st["refined_queries"], "of", st["valid_queries"], flush=True)
+    assert r["n"] > 1000
