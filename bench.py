@@ -295,10 +295,10 @@ def dist_errors(g, ref):
 
 
 def precision_leg(P, torch, dev, x, qd, timer):
-    """The band query of the same frame with BF16 MFMA products and in FP64."""
+    """The band query of the same frame with BF16 and FP32 MFMA products and in FP64."""
     m = qd.shape[0]
     rep, outs = {}, {}
-    for name, prec in (("bf16", P.PREC_BF16), ("fp64", P.PREC_FP64)):
+    for name, prec in (("bf16", P.PREC_BF16), ("fp32_mfma", P.PREC_FP32_MFMA), ("fp64", P.PREC_FP64)):
         c = P.Context(P.Params.default(voxel_size=0.1, precision=prec), device=dev)
         c.train(x)
         o = dict(dist=torch.empty(m, device=dev), grad=torch.empty((m, 3), device=dev),
@@ -346,7 +346,7 @@ def properties_leg(P, torch, dev, pts, q, x, qd, q_plain_ms, n_sample=20000):
 
 def batched_leg(P, torch, dev):
     """8,192 local GPs of U{8..256} points on planar patches, 64 queries each:
-    autotuned launch shapes, then FP32 and BF16 queries; the error against the
+    autotuned launch shapes, then FP32, BF16 and FP32-MFMA queries; the error against the
     oracle is taken on a sample of 256 patches (each query's 27 neighbour
     cells hold only its own patch, so a model of the sampled patches gives
     the oracle value of their queries)."""
@@ -364,7 +364,7 @@ def batched_leg(P, torch, dev):
     sp = np.concatenate([ps.points[starts[i]:starts[i + 1]] for i in sample])
     qi = np.concatenate([np.arange(64 * i, 64 * i + 64) for i in sample])
     ref = O.Model(O.Params(cell=0.8), sp).query(ps.queries[qi])
-    for name, prec in (("fp32", P.PREC_FP32), ("bf16", P.PREC_BF16)):
+    for name, prec in (("fp32", P.PREC_FP32), ("bf16", P.PREC_BF16), ("fp32_mfma", P.PREC_FP32_MFMA)):
         c = P.Context(P.Params.default(precision=prec, timing=1, **base), device=dev)
         tune = c.autotune(x, q)
         t = Timer(torch, c.stream)
