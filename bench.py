@@ -23,14 +23,19 @@ cores and checks every GPU output of the last step against it.
 
 The ``extensions`` object reports, on the same GPU:
   precision   the band query of the same frame with the variance product on
-              BF16 MFMA and in FP64, rate and errors against the oracle;
+              BF16 MFMA, on FP32 MFMA, and in FP64, rate and errors against
+              the oracle;
   batched     8,192 local GPs of 8-256 points on planar patches with 524,288
-              queries: autotuned launch shapes, FP64 training, FP32 and BF16
-              queries, error against the oracle on a sample of the patches;
+              queries: autotuned launch shapes, FP64 training, FP32, BF16 and
+              FP32-MFMA queries, error against the oracle on a sample of the
+              patches;
   sequence    100 frames of a moving sensor fused eagerly and through the
               per-frame HIP graph (bitwise compared), then 4M global queries;
               the first 5 frames fused again and compared with the oracle
-              (grid, and global queries at observed voxels and uniform points);
+              (grid, and global queries at observed voxels and uniform
+              points), the G-GPDF on their zero crossings, and 20 frames with
+              the paper's ray-cast test points beside the band (test voxels,
+              time, the first frames against the oracle);
   correction  the learned correction trained on the GPU on pairs the method
               generates (GP output vs brute-force nearest point), its held-out
               gain, and its fused inference rate;
