@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPDF_ABI_VERSION 2u
+#define GPDF_ABI_VERSION 3u
 
 typedef struct gpdf_ctx gpdf_ctx;
 
@@ -395,23 +395,41 @@ gpdf_status gpdf_nearest_distance(gpdf_ctx *ctx, const float *d_pts, int64_t n,
                                   const float *d_q, int64_t m, float *d_out);
 
 /* ---- batching: launch shapes picked by measurement (an extension) --------
- * train_threads: workgroup of the trainer of clusters above 64 points (256,
- * 512 or 1024).  eval_persistent: 0 launches one wavefront per 64-query
+ * train_threads: workgroup of the trainer of the clusters above 256 points
+ * (256, 512 or 1024).  eval_persistent: 0 launches one wavefront per 64-query
  * chunk; 1, 2 or 4 keep that many persistent wavefronts per SIMD taking
- * chunks from a counter (NEIGHBOR27 selection; KNN ignores it).
- * gpdf_autotune trains on d_xyz [n][3] with each train_threads candidate and
- * queries d_q [m][3] (signed from h_origin, or unsigned with NULL) with each
- * eval_persistent candidate, three timed runs after a warm-up each, keeps the
- * fastest of both and leaves the context trained on d_xyz.  h_ms (float[7] or
- * NULL) receives the median times in ms: train 256/512/1024, query 0/1/2/4.
- * Errors: GPDF_E_INVALID_ARG (empty input, unknown shape), GPDF_E_CAPACITY. */
+ * chunks from a counter (NEIGHBOR27 selection; KNN ignores it).  mfma_min_n:
+ * the size bucket boundary of the FP32 evaluation -- the clusters of
+ * mfma_min_n (17, 33, 65 or 129) to 248 points take the variance product on
+ * FP32 MFMA (as GPDF_PREC_FP32_MFMA), the others the VALU path; 0 keeps the
+ * VALU path for every cluster (eager NEIGHBOR27 queries without a property;
+ * with a non-zero boundary eval_persistent does not apply).
+ * gpdf_autotune trains on d_xyz [n][3], then times the train_threads
+ * candidates and, on queries d_q [m][3] (signed from h_origin, or unsigned
+ * with NULL), the eval_persistent candidates and the mfma_min_n boundaries,
+ * three timed runs after a warm-up each; it keeps the fastest and leaves the
+ * context trained on d_xyz.  h_ms (float[11] or NULL) receives the median
+ * times in ms: train 256/512/1024, query 0/1/2/4, MFMA from 17/33/65/129
+ * points (-1 where not run).  The result is cached, process-wide, under the
+ * shape of the workload (precision, selection, kernel, clustering mode, the
+ * cluster-size histogram over 1-8, 9-16, ..., 129-256, >256 and the query
+ * count, counts rounded to powers of two): a later call with a cached shape
+ * takes the cached shapes without timing and sets *h_cached (may be NULL)
+ * to 1.  gpdf_tuning_cache_save / _load write and read the cache as text
+ * (a header line, then `shape|train_threads eval_persistent mfma_min_n`
+ * lines); _clear empties it.
+ * Errors: GPDF_E_INVALID_ARG (empty input, unknown shape, unreadable or
+ * malformed cache file), GPDF_E_CAPACITY. */
 gpdf_status gpdf_set_tuning(gpdf_ctx *ctx, int32_t train_threads,
-                            int32_t eval_persistent);
+                            int32_t eval_persistent, int32_t mfma_min_n);
 gpdf_status gpdf_get_tuning(const gpdf_ctx *ctx, int32_t *train_threads,
-                            int32_t *eval_persistent);
+                            int32_t *eval_persistent, int32_t *mfma_min_n);
 gpdf_status gpdf_autotune(gpdf_ctx *ctx, const float *d_xyz, int64_t n,
                           const float *d_q, int64_t m, const float *h_origin,
-                          float *h_ms);
+                          float *h_ms, int32_t *h_cached);
+gpdf_status gpdf_tuning_cache_save(const char *path);
+gpdf_status gpdf_tuning_cache_load(const char *path);
+gpdf_status gpdf_tuning_cache_clear(void);
 
 /* ---- learned correction (an extension; not in the paper) ----------------
  * A 7-64-64-64-1 GELU network maps standardised features

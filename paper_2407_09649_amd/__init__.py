@@ -19,7 +19,7 @@ __all__ = ["Params", "Stats", "Context", "load_library", "library_path",
            "STATUS_HASH_FULL", "STATUS_GLOBAL_FULL", "STATUS_NONFINITE", "STATUS_NONPD",
            "STATUS_CAPACITY"]
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 KERNEL_MATERN32, KERNEL_SE = 0, 1
 SEL_NEIGHBOR27, SEL_KNN = 0, 1
 COMB_SMOOTHMIN, COMB_HARDMIN = 0, 1
@@ -44,6 +44,7 @@ EXPORTS = [
     "gpdf_mlp_forward", "gpdf_mlp_grad", "gpdf_mlp_train", "gpdf_query_distance_noalloc",
     "gpdf_zero_crossings", "gpdf_train_local_gps_prop", "gpdf_query_distance_prop",
     "gpdf_fuse_frame_prop", "gpdf_query_global_prop", "gpdf_export_global_prop",
+    "gpdf_tuning_cache_save", "gpdf_tuning_cache_load", "gpdf_tuning_cache_clear",
 ]
 
 
@@ -143,9 +144,12 @@ def _bind(L):
         "gpdf_nearest_distance": [P, P, I64, P, I64, P],
         "gpdf_fuse_frame_graph": [P, P, I64, P],
         "gpdf_zero_crossings": [P, P, I64, P],
-        "gpdf_set_tuning": [P, C.c_int32, C.c_int32],
-        "gpdf_get_tuning": [P, P, P],
-        "gpdf_autotune": [P, P, I64, P, I64, P, P],
+        "gpdf_set_tuning": [P, C.c_int32, C.c_int32, C.c_int32],
+        "gpdf_get_tuning": [P, P, P, P],
+        "gpdf_autotune": [P, P, I64, P, I64, P, P, P],
+        "gpdf_tuning_cache_save": [C.c_char_p],
+        "gpdf_tuning_cache_load": [C.c_char_p],
+        "gpdf_tuning_cache_clear": [],
         "gpdf_mlp_init": [P, U64],
         "gpdf_mlp_set_weights": [P, P, I64],
         "gpdf_mlp_get_weights": [P, P, I64],
@@ -428,27 +432,33 @@ class Context:
         _check(self.lib.gpdf_load_global(self._h, os.fsencode(path)), self._h)
 
     # -- batching: tuned launch shapes ----------------------------------------
-    def set_tuning(self, train_threads=256, eval_persistent=0):
-        _check(self.lib.gpdf_set_tuning(self._h, int(train_threads), int(eval_persistent)), self._h)
+    def set_tuning(self, train_threads=256, eval_persistent=0, mfma_min_n=0):
+        _check(self.lib.gpdf_set_tuning(self._h, int(train_threads), int(eval_persistent), int(mfma_min_n)),
+               self._h)
 
     def get_tuning(self):
-        t, p = C.c_int32(0), C.c_int32(0)
-        _check(self.lib.gpdf_get_tuning(self._h, C.byref(t), C.byref(p)), self._h)
-        return {"train_threads": t.value, "eval_persistent": p.value}
+        t, p, mm = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        _check(self.lib.gpdf_get_tuning(self._h, C.byref(t), C.byref(p), C.byref(mm)), self._h)
+        return {"train_threads": t.value, "eval_persistent": p.value, "mfma_min_n": mm.value}
 
     def autotune(self, xyz, q, origin=None):
-        """Times the launch-shape candidates on this workload, keeps the
-        fastest and leaves the context trained on xyz.  Returns the median
-        times (ms) of every candidate."""
+        """Times the launch-shape candidates on this workload (or takes them
+        from the process-wide cache when its shape was tuned before), keeps
+        the fastest and leaves the context trained on xyz.  Returns the
+        median times (ms) of every candidate (-1: not run) and ``cached``."""
         import numpy as np
         torch = self._torch
-        ms = np.zeros(7, np.float32)
+        ms = np.zeros(11, np.float32)
+        cached = C.c_int32(0)
         _check(self.lib.gpdf_autotune(self._h, _dptr(xyz, torch.float32, 3), xyz.shape[0],
                                       _dptr(q, torch.float32, 3), q.shape[0], _host3(origin),
-                                      ms.ctypes.data_as(C.c_void_p)), self._h)
+                                      ms.ctypes.data_as(C.c_void_p), C.byref(cached)), self._h)
         names = ["train_256", "train_512", "train_1024", "eval_grid", "eval_persist1",
-                 "eval_persist2", "eval_persist4"]
-        return dict(zip(names, ms.tolist()))
+                 "eval_persist2", "eval_persist4", "eval_mfma_from17", "eval_mfma_from33",
+                 "eval_mfma_from65", "eval_mfma_from129"]
+        out = dict(zip(names, ms.tolist()))
+        out["cached"] = bool(cached.value)
+        return out
 
     # -- learned correction ---------------------------------------------------
     def mlp_init(self, seed=0):
@@ -512,3 +522,17 @@ class Context:
                                        _dptr(target, torch.float32), feat.shape[0], int(epochs),
                                        int(batch), float(lr), int(seed), C.byref(loss)), self._h)
         return loss.value
+
+
+def tuning_cache_save(path):
+    """Write the process-wide tuning cache (gpdf_tuning_cache_save)."""
+    _check(load_library().gpdf_tuning_cache_save(str(path).encode()), None)
+
+
+def tuning_cache_load(path):
+    """Add the entries of a tuning cache file (gpdf_tuning_cache_load)."""
+    _check(load_library().gpdf_tuning_cache_load(str(path).encode()), None)
+
+
+def tuning_cache_clear():
+    _check(load_library().gpdf_tuning_cache_clear(), None)

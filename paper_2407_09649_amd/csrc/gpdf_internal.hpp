@@ -362,6 +362,8 @@ struct Model {
 struct gpdf_tune {
     int train_threads = 1024;  // workgroup of the large-cluster trainer: 256, 512 or 1024
     int eval_persistent = 0;   // evaluation: 0 = one workgroup per chunk, else persistent waves per SIMD
+    int mfma_min_n = 0;        // FP32 evaluation: clusters of at least this size (to 248) take the
+                               // variance product on FP32 MFMA; 0 = VALU only
     int tuned = 0;
 };
 

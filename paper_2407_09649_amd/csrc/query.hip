@@ -1605,10 +1605,12 @@ __device__ void eval_cluster_f32m(int base, int n, int64_t woff, const float4 *_
     finish_pair<float, KERN>(r, n, C, A);
 }
 
+// min_n: clusters of min_n to kF32mMaxN points take the MFMA product, the
+// others the VALU path (the size bucket boundary the autotuner picks)
 template <int KERN, int MODE>
 __global__ __launch_bounds__(kEvalT) void k_query_cells_f32m(const float *__restrict__ q, Grouping G,
                                                              const int4 *__restrict__ lists, ModelView Mo, int kts,
-                                                             QueryConsts C, Outputs O) {
+                                                             int min_n, QueryConsts C, Outputs O) {
     extern __shared__ float Kf[];
     const uint32_t nch = *ro(G.nchunks);
     const uint32_t wave = xcd_item(nch);
@@ -1629,7 +1631,7 @@ __global__ __launch_bounds__(kEvalT) void k_query_cells_f32m(const float *__rest
         const int4 d = L[1 + s];
         const int base = int(uniform(uint32_t(d.y))), n = int(uniform(uint32_t(d.z)));
         const int64_t woff = int64_t(uniform(uint32_t(d.w)));
-        if (n <= kF32mMaxN)
+        if (n >= min_n && n <= kF32mMaxN)
             eval_cluster_f32m<KERN>(base, n, woff, Mo.pts, Mo.W32, Kf, kts, Q, C, A);
         else
             eval_cluster<float, KERN>(base, n, woff, Mo.pts, Mo.alpha64, Mo.beta32, Mo.beta64, Mo.W32, Mo.W64, Q, C, A);
@@ -1931,16 +1933,16 @@ void launch_query_kf(int kernel, bool knn, unsigned grid, hipStream_t s, const f
 
 template <int KERN>
 void launch_f32m_m(unsigned grid, size_t lds, hipStream_t s, const float *q, const Grouping &G, const int4 *lists,
-                   const ModelView &Mo, int kts, const QueryConsts &C, const Outputs &O) {
+                   const ModelView &Mo, int kts, int min_n, const QueryConsts &C, const Outputs &O) {
     if (C.combine == GPDF_COMB_HARDMIN)
         hipLaunchKernelGGL((k_query_cells_f32m<KERN, kModeHard>), dim3(grid), dim3(kEvalT), lds, s, q, G, lists, Mo,
-                           kts, C, O);
+                           kts, min_n, C, O);
     else if (C.grad_mode == GPDF_GRAD_PAPER_MEAN)
         hipLaunchKernelGGL((k_query_cells_f32m<KERN, kModeMean>), dim3(grid), dim3(kEvalT), lds, s, q, G, lists, Mo,
-                           kts, C, O);
+                           kts, min_n, C, O);
     else
         hipLaunchKernelGGL((k_query_cells_f32m<KERN, kModeSmooth>), dim3(grid), dim3(kEvalT), lds, s, q, G, lists,
-                           Mo, kts, C, O);
+                           Mo, kts, min_n, C, O);
 }
 
 template <typename T>
@@ -2290,16 +2292,21 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
                                                     O);
             else
                 launch_bf16_m<GPDF_KERNEL_SE>(grid, lds, s, d_q, G, lists, Mo, Mbf, c->d_bfoff, kts, Cb, O);
-        } else if (c->p.precision == GPDF_PREC_FP32_MFMA) {
-            // the variance product on FP32 MFMA; every output keeps the FP32
-            // path's error estimate and FP64 re-evaluation.  The LDS row of a
-            // query holds the largest cluster's kernel values (odd stride).
+        } else if (c->p.precision == GPDF_PREC_FP32_MFMA ||
+                   (c->tune.mfma_min_n > 0 && eager && !knn && !want_prop)) {
+            // the variance product on FP32 MFMA for the clusters of
+            // mfma_min_n to 248 points (FP32_MFMA precision: every cluster up
+            // to 248 unless tuned otherwise), the VALU path for the others;
+            // every output keeps the FP32 error estimate and FP64
+            // re-evaluation.  The LDS row of a query holds the largest
+            // cluster's kernel values (odd stride).
+            const int min_n = c->tune.mfma_min_n > 0 ? c->tune.mfma_min_n : 1;
             const int kts = ((int(std::min<int64_t>(std::max<int64_t>(M.max_n, 1), kF32mMaxN)) + 3) & ~3) + 1;
             const size_t lds = size_t(64) * kts * sizeof(float);
             if (kern == GPDF_KERNEL_MATERN32)
-                launch_f32m_m<GPDF_KERNEL_MATERN32>(grid, lds, s, d_q, G, lists, Mo, kts, C, O);
+                launch_f32m_m<GPDF_KERNEL_MATERN32>(grid, lds, s, d_q, G, lists, Mo, kts, min_n, C, O);
             else
-                launch_f32m_m<GPDF_KERNEL_SE>(grid, lds, s, d_q, G, lists, Mo, kts, C, O);
+                launch_f32m_m<GPDF_KERNEL_SE>(grid, lds, s, d_q, G, lists, Mo, kts, min_n, C, O);
         } else {
             launch_query_k<float>(c, kern, knn, grid, s, d_q, G, lists, Mo, C, O, 0);
         }
