@@ -16,8 +16,11 @@ the whole step; the fusion test points are extra work inside the step.
 The roofline object describes the dominant kernel, the FP32 evaluation
 kernel of the band query, timed with HIP events on the context stream;
 roofline_test_voxels the other evaluation launch of the step (the fusion's
-test voxels, no gradient).  query_only_shuffled times the band query with
-its queries in a random order.  cpu_baseline also reports one host thread.
+test voxels, no gradient).  frac_of_measured prices the same work at the
+FMA and exp2 rates the probe kernels sustain on this device (measured_peaks:
+HBM copy, FP32 VALU, exp2, BF16 / FP32 / FP64 MFMA).  query_only_shuffled
+times the band query with its queries in a random order.  cpu_baseline also
+reports one host thread.
 The cpu_baseline leg runs the same step with the FP64 oracle on the host
 cores and checks every GPU output of the last step against it.
 
@@ -237,6 +240,17 @@ def main():
                    "flops_only_tflops": f2 / tv_s / 1e12, "kernel": "k_query_cells<float, Matern-3/2, no gradient>",
                    "flops_per_launch": f2, "transcendentals_per_launch": t2, "pairs": st_tv["eval_pairs"],
                    "queries": st_tv["queries"], "avg_launch_ms": tv_s * 1e3}
+    # what this device sustains (probe kernels): the same work at the
+    # measured FMA and exp2 rates
+    peaks = ctx.measure_peaks()
+    meas_fma = peaks["fp32_valu_tflops"] * 1e12 / 2
+    meas_trans = peaks["exp2_gops"] * 1e9
+
+    def frac_measured(fl, tr, sec):
+        return ((fl / 2) / meas_fma + tr / meas_trans) / sec
+
+    roofline["frac_of_measured"] = frac_measured(flops, trans, eval_s)
+    roofline_tv["frac_of_measured"] = frac_measured(f2, t2, tv_s)
     res = {
         "metric": METRIC, "value": value, "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -257,6 +271,7 @@ def main():
         "fp64_share_of_band_query": stages["refine"] / max(stages["group"] + stages["eval"] + stages["refine"], 1e-9),
         "roofline": roofline,
         "roofline_test_voxels": roofline_tv,
+        "measured_peaks": peaks,
         "input_generation_s": gen_s,
     }
     gpu_out = {k: v.cpu().numpy() for k, v in out.items()}

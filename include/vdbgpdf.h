@@ -431,6 +431,19 @@ gpdf_status gpdf_tuning_cache_save(const char *path);
 gpdf_status gpdf_tuning_cache_load(const char *path);
 gpdf_status gpdf_tuning_cache_clear(void);
 
+/* ---- measured peaks (measurement support; not in the paper) -------------
+ * gpdf_measure_peaks runs small probe kernels on the context's device and
+ * writes what this device sustains into h_out[0..8]: a 1 GiB device copy in
+ * GB/s (bytes read plus written), FP32 FMA chains in TFLOP/s (an FMA counts
+ * two) in the VOP2 register form (v_fmac_f32), exp2 in Gop/s, BF16 16x16x32,
+ * FP32 16x16x4 and FP64 16x16x4 MFMA in TFLOP/s, the copy size in GiB, and
+ * FP32 FMA in the VOP3 form (v_fma_f32) and the VOP2 literal form
+ * (v_fmamk_f32).  Each probe is timed with HIP events on
+ * the context's stream after one warm-up launch.  It allocates 2 GiB of
+ * device memory for the duration of the call, and frees it before it returns.
+ * Errors: GPDF_E_INVALID_ARG (n_out < 9 or a NULL pointer), GPDF_E_HIP. */
+gpdf_status gpdf_measure_peaks(gpdf_ctx *ctx, double *h_out, int32_t n_out);
+
 /* ---- learned correction (an extension; not in the paper) ----------------
  * A 7-64-64-64-1 GELU network maps standardised features
  * [d, log v, o, grad d (3), log(1 + n_local)] to a residual r.  Parameters

@@ -45,6 +45,7 @@ EXPORTS = [
     "gpdf_zero_crossings", "gpdf_train_local_gps_prop", "gpdf_query_distance_prop",
     "gpdf_fuse_frame_prop", "gpdf_query_global_prop", "gpdf_export_global_prop",
     "gpdf_tuning_cache_save", "gpdf_tuning_cache_load", "gpdf_tuning_cache_clear",
+    "gpdf_measure_peaks",
 ]
 
 
@@ -150,6 +151,7 @@ def _bind(L):
         "gpdf_tuning_cache_save": [C.c_char_p],
         "gpdf_tuning_cache_load": [C.c_char_p],
         "gpdf_tuning_cache_clear": [],
+        "gpdf_measure_peaks": [P, P, C.c_int32],
         "gpdf_mlp_init": [P, U64],
         "gpdf_mlp_set_weights": [P, P, I64],
         "gpdf_mlp_get_weights": [P, P, I64],
@@ -459,6 +461,18 @@ class Context:
         out = dict(zip(names, ms.tolist()))
         out["cached"] = bool(cached.value)
         return out
+
+    def measure_peaks(self):
+        """What this device sustains, from probe kernels: HBM copy GB/s, FP32
+        FMA TFLOP/s (VOP2 register form; the VOP3 and literal forms beside
+        it), exp2 Gop/s, BF16 / FP32 / FP64 MFMA TFLOP/s."""
+        import numpy as np
+        out = np.zeros(9, np.float64)
+        _check(self.lib.gpdf_measure_peaks(self._h, out.ctypes.data_as(C.c_void_p), 9), self._h)
+        names = ["hbm_copy_gbs", "fp32_valu_tflops", "exp2_gops", "mfma_bf16_tflops",
+                 "mfma_f32_tflops", "mfma_f64_tflops", "copy_gib", "fp32_fma_vop3_tflops",
+                 "fp32_fma_literal_tflops"]
+        return dict(zip(names, out.tolist()))
 
     # -- learned correction ---------------------------------------------------
     def mlp_init(self, seed=0):

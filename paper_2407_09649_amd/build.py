@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvdbgpdf.so")
-SOURCES = ["api.hip", "sort.hip", "train.hip", "query.hip", "fuse.hip", "mlp.hip", "tune.hip"]
+SOURCES = ["api.hip", "sort.hip", "train.hip", "query.hip", "fuse.hip", "mlp.hip", "tune.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -20,6 +20,11 @@ CFLAGS = [
     "-Wno-unused-function", "-Wno-unused-parameter",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: with the AGPR form the compiler
+    # copies loop-carried accumulators between the two register classes on
+    # every iteration and spills the MFMA query kernels; kernels without MFMA
+    # compile to the same code either way
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
@@ -33,10 +38,14 @@ def _compile(src: str, extra) -> str:
     return obj
 
 
-def build(extra=(), jobs: int = 6) -> str:
+def build(extra=(), jobs: int = 6, only=None) -> str:
+    """Compile every source (or only those named in ``only``, keeping the
+    other objects) and link the library."""
     os.makedirs(OUT, exist_ok=True)
+    todo = SOURCES if only is None else [s for s in SOURCES if s in only]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, list(extra)), SOURCES))
+        list(ex.map(lambda s: _compile(s, list(extra)), todo))
+    objs = [os.path.join(OUT, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
