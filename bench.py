@@ -268,6 +268,8 @@ def main():
         "query_only_shuffled_ms": q_ms_shuffled,
         "query_only_shuffled_rate": m / (q_ms_shuffled / 1e3),
         "refined_fraction": st["refined_queries"] / max(st["valid_queries"], 1),
+        "refine_pairs": {"small_clusters": st["refine_pairs_small"], "large_clusters": st["refine_pairs_large"],
+                         "large_cluster_items": st["refine_items_large"]},
         "fp64_share_of_band_query": stages["refine"] / max(stages["group"] + stages["eval"] + stages["refine"], 1e-9),
         "roofline": roofline,
         "roofline_test_voxels": roofline_tv,

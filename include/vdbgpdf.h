@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPDF_ABI_VERSION 3u
+#define GPDF_ABI_VERSION 4u
 
 typedef struct gpdf_ctx gpdf_ctx;
 
@@ -164,6 +164,15 @@ typedef struct {
                                   -1 when the stage has not run */
     int64_t trained_clusters;  /* clusters factored since the last training
                                   (all of them unless lazy_train) */
+    int64_t refine_pairs_small;/* last query, FP64 re-evaluation: (refined
+                                  query, cluster) pairs of clusters of at most
+                                  32 points, */
+    int64_t refine_pairs_large;/*   of 33 to 256 points, */
+    int64_t refine_items_large;/*   and the work items of the latter (up to
+                                  16 queries of one cluster each); all 0
+                                  when the pass did not run (KNN selection,
+                                  a cluster above 256 points, or more pairs
+                                  than its buffers hold) */
 } gpdf_stats;
 
 enum {

@@ -19,7 +19,7 @@ __all__ = ["Params", "Stats", "Context", "load_library", "library_path",
            "STATUS_HASH_FULL", "STATUS_GLOBAL_FULL", "STATUS_NONFINITE", "STATUS_NONPD",
            "STATUS_CAPACITY"]
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 KERNEL_MATERN32, KERNEL_SE = 0, 1
 SEL_NEIGHBOR27, SEL_KNN = 0, 1
 COMB_SMOOTHMIN, COMB_HARDMIN = 0, 1
@@ -92,7 +92,8 @@ class Stats(C.Structure):
         "fuse_skipped", "global_voxels", "gated", "eval_pairs", "eval_points",
         "eval_tri", "refine_dist", "refine_grad", "refine_var")] + [
         ("status_bits", C.c_uint32), ("pad0", C.c_uint32), ("ms", C.c_float * 8),
-        ("trained_clusters", C.c_int64)]
+        ("trained_clusters", C.c_int64), ("refine_pairs_small", C.c_int64),
+        ("refine_pairs_large", C.c_int64), ("refine_items_large", C.c_int64)]
 
     STAGES = ("train", "group", "eval", "refine", "testpts", "fuse", "global", "mlp")
 

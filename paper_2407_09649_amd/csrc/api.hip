@@ -48,7 +48,8 @@ void release(gpdf_ctx *c) {
                     c->d_qrank, c->d_order, c->d_cell_key, c->d_cell_cnt, c->d_cell_off,
                     c->d_cell_chunks, c->d_chunk_off, c->d_cell_list, c->d_chunk, c->d_refine,
                     c->d_rcnt, c->d_roff, c->d_rchunks, c->d_rchunk_off, c->d_rorder, c->d_rrank,
-                    c->d_rchunk,
+                    c->d_rchunk, c->d_bbase, c->d_bcnt, c->d_boff, c->d_bcs, c->d_boffs, c->d_bcb,
+                    c->d_boffb, c->d_bnit, c->d_bioff, c->d_bitem, c->d_bnits, c->d_bioffs, c->d_bitems, c->d_bq, c->d_bdst, c->d_rcell, c->d_bres,
                     c->d_tmp_dist, c->d_tmp_var, c->d_tmp_grad, c->d_tmp_valid, c->d_tset,
                     c->d_tkeys, c->d_tpts, c->d_gslot, c->d_gstamp, c->d_offs,
                     c->d_mlp_w, c->d_mlp_m, c->d_mlp_v, c->d_mlp_g, c->d_mlp_rec, c->d_mlp_pack,
@@ -193,6 +194,22 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
               dalloc(c->d_tpts, 3 * M, e) && dalloc(c->d_gslot, int64_t(c->gmask) + 1, e) &&
               dalloc(c->d_gstamp, int64_t(c->gmask) + 1, e) && dalloc(c->d_offs, c->offs_cap, e) &&
               dalloc(c->d_stat, ST_COUNT, e) && dalloc(c->d_spread, int64_t(kSpread) * kSpreadStride, e);
+    if (ok) {
+        // cluster-major re-evaluation: frames beyond these bounds fall back
+        // to the chunk pass on the device
+        c->cap_bchunks = std::min<int64_t>(std::max<int64_t>(M / 16, int64_t(1) << 14), int64_t(1) << 18);
+        c->cap_bpairs = std::min<int64_t>(std::max<int64_t>(M, int64_t(1) << 16), int64_t(1) << 22);
+        // results are laid out per cell-list slot: 27 slots per refined query
+        c->cap_bref = c->cap_bpairs / (kCellListStride - 1);
+        ok = dalloc(c->d_bbase, c->cap_bchunks * (kCellListStride - 1), e) && dalloc(c->d_bcnt, C + 1, e) &&
+             dalloc(c->d_boff, C + 1, e) && dalloc(c->d_bcs, C + 1, e) && dalloc(c->d_boffs, C + 1, e) &&
+             dalloc(c->d_bcb, C + 1, e) && dalloc(c->d_boffb, C + 1, e) && dalloc(c->d_bnit, C + 1, e) &&
+             dalloc(c->d_bioff, C + 1, e) && dalloc(c->d_bitem, c->cap_bpairs, e) &&
+             dalloc(c->d_bnits, C + 1, e) && dalloc(c->d_bioffs, C + 1, e) && dalloc(c->d_bitems, c->cap_bpairs, e) &&
+             dalloc(c->d_bq, c->cap_bpairs, e) &&
+             dalloc(c->d_bdst, c->cap_bpairs, e) && dalloc(c->d_rcell, M, e) &&
+             (e = hipMalloc(&c->d_bres, size_t(80) * c->cap_bpairs)) == hipSuccess;
+    }
     if (ok && p->test_points == GPDF_TEST_RAYCAST) {
         c->vhash_mask = pow2_mask(2 * P);
         ok = dalloc(c->d_vhash, int64_t(c->vhash_mask) + 1, e);
@@ -493,6 +510,16 @@ extern "C" gpdf_status gpdf_get_stats(gpdf_ctx *c, gpdf_stats *out) {
     out->refine_grad = int64_t(h[ST_REF_G]);
     out->refine_var = int64_t(h[ST_REF_V]);
     out->trained_clusters = c->model.ntrained;
+    {
+        uint32_t dc[kCnt];
+        if ((e = hipMemcpy(dc, c->d_cnt, sizeof dc, hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(c, e, "get_stats");
+        if (dc[CNT_NREF_FAST] > 0) {
+            out->refine_pairs_small = dc[CNT_BPAIRS_S];
+            out->refine_pairs_large = dc[CNT_BPAIRS_B];
+            out->refine_items_large = dc[CNT_BITEMS];
+        }
+    }
     uint32_t bits = 0;
     if (h[ST_HASH_FULL]) bits |= GPDF_STATUS_HASH_FULL;
     if (h[ST_GLOBAL_FULL]) bits |= GPDF_STATUS_GLOBAL_FULL;

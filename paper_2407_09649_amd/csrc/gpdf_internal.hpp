@@ -230,7 +230,13 @@ enum DevCount : int {
     CNT_TEST,     // test voxels (clamped to max_queries)
     CNT_FRAME,    // frame stamp (graph input)
     CNT_M,        // query count read by the kernels (graph)
-    CNT_RHEAVY,   // re-evaluation chunks of cells with a cluster above one panel
+    CNT_BPAIRS_S, // cluster-major re-evaluation: (refined query, cluster) pairs, clusters of <= one panel
+    CNT_BPAIRS_B, // the same, larger clusters
+    CNT_BITEMS,   // work items of the larger clusters
+    CNT_BITEMS_S, // work items of the clusters of <= one panel
+    CNT_BIGOK,    // 1 when the pairs fit the buffers
+    CNT_NREF_FAST,// refined queries for the combination of the pass's pairs (0: the pass did not take all)
+    CNT_RCH_SLOW, // re-evaluation chunks for the FP64 query kernel (0 when the pass took all)
     kCnt
 };
 
@@ -445,6 +451,21 @@ struct gpdf_ctx {
     uint32_t *d_rchunks = nullptr, *d_rchunk_off = nullptr;
     uint32_t *d_rorder = nullptr, *d_rrank = nullptr;
     uint2 *d_rchunk = nullptr;
+    // cluster-major re-evaluation: per cell (at its first chunk index) and
+    // descriptor the cell's first slot in the cluster's run; per cluster the
+    // pair count, run offset, the counts and offsets split by size class, and
+    // the item counts and offsets of the larger clusters; the items, each
+    // pair's query and result slot, and the reverted pairs (struct BigOut, 80 bytes)
+    int64_t cap_bchunks = 0, cap_bpairs = 0;
+    uint32_t *d_bbase = nullptr, *d_bcnt = nullptr, *d_boff = nullptr;
+    uint32_t *d_bcs = nullptr, *d_boffs = nullptr, *d_bcb = nullptr, *d_boffb = nullptr;
+    uint32_t *d_bnit = nullptr, *d_bioff = nullptr, *d_bnits = nullptr, *d_bioffs = nullptr;
+    uint2 *d_bitem = nullptr, *d_bitems = nullptr;
+    uint32_t *d_bq = nullptr;                     // per pair: query,
+    uint32_t *d_bdst = nullptr;                   //   result slot s * cap_bref + (refine position)
+    int64_t cap_bref = 0;                         // refined queries the result layout holds
+    uint32_t *d_rcell = nullptr;                  // cell of each refined query (refine order)
+    void *d_bres = nullptr;
     float *d_tmp_dist = nullptr, *d_tmp_var = nullptr, *d_tmp_grad = nullptr;
     uint8_t *d_tmp_valid = nullptr;
 

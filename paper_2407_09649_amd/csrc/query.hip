@@ -39,8 +39,6 @@ constexpr int kQT = 256;            // threads per workgroup of the helper kerne
 constexpr int kEvalT = 64;
 constexpr int kWaves = kEvalT / 64;
 constexpr int kListStride = kCellListStride;
-// queries per chunk of the pair-parallel FP64 pass: one lane per pair
-__device__ __forceinline__ int refine_qpw(int nsel) { return nsel > 0 ? max(1, 64 / nsel) : 64; }
 // combination variants, fixed per launch: smooth minimum with the weighted
 // gradient, smooth minimum with the plain gradient mean, closest node
 constexpr int kModeSmooth = 0, kModeMean = 1, kModeHard = 2;
@@ -287,13 +285,11 @@ __global__ void k_cell_lists(int64_t ncb, const uint32_t *__restrict__ dnc, cons
 
 // chunk table: (cell, first query) for every 64-query chunk of every cell
 __global__ void k_chunk_table(int64_t ncb, const uint32_t *__restrict__ dnc, const uint32_t *__restrict__ cell_chunks,
-                              const uint32_t *__restrict__ chunk_off, const int4 *__restrict__ lists,
-                              uint2 *__restrict__ chunk) {
+                              const uint32_t *__restrict__ chunk_off, uint2 *__restrict__ chunk) {
     int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= dev_count(ncb, dnc)) return;
     const uint32_t o = chunk_off[c];
-    const uint32_t per = lists ? uint32_t(refine_qpw(lists[c * kListStride].x)) : 64u;
-    for (uint32_t j = 0; j < cell_chunks[c]; ++j) chunk[o + j] = make_uint2(uint32_t(c), j * per);
+    for (uint32_t j = 0; j < cell_chunks[c]; ++j) chunk[o + j] = make_uint2(uint32_t(c), j * 64u);
 }
 
 __global__ void k_scatter_order(const int32_t *__restrict__ qslot, const uint32_t *__restrict__ qrank,
@@ -322,49 +318,24 @@ __global__ void k_refine_count(const uint2 *__restrict__ rec, const unsigned lon
     if (i < n) rrank[i] = r;
 }
 
-// chunks of the re-evaluation: 64 queries per chunk, or with the cell lists
-// (pair-parallel pass) floor(64 / nsel)
-// re-evaluation chunks per cell; rheavy repeats the count for cells whose
-// list holds a cluster above one panel (their chunks cost far more) and is
-// zero elsewhere
+// re-evaluation chunks per cell, 64 refined queries each
 __global__ void k_refine_chunks(int64_t ncb, const uint32_t *__restrict__ dnc, const uint32_t *__restrict__ rcnt,
-                                const int4 *__restrict__ lists, uint32_t *__restrict__ rchunks,
-                                uint32_t *__restrict__ rheavy) {
+                                uint32_t *__restrict__ rchunks) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= dev_count(ncb, dnc)) return;
-    const uint32_t per = lists ? uint32_t(refine_qpw(lists[c * kListStride].x)) : 64u;
-    const uint32_t k = (rcnt[c] + per - 1) / per;
-    bool heavy = false;
-    if (lists && k > 0) {
-        const int4 *L = lists + c * kListStride;
-        for (int s = 0; s < L[0].x; ++s) heavy = heavy || L[1 + s].z > kPanel;
-    }
-    rchunks[c] = k;
-    rheavy[c] = heavy ? k : 0u;
-}
-
-// chunk table of the re-evaluation, the chunks of heavy cells first (so that
-// the persistent pass starts its longest chunks early), then the others in
-// cell order: roff counts the chunks of all cells before c, hoff those of
-// the heavy cells, *nheavy all heavy chunks
-__global__ void k_refine_table(int64_t ncb, const uint32_t *__restrict__ dnc, const uint32_t *__restrict__ rchunks,
-                               const uint32_t *__restrict__ roff, const uint32_t *__restrict__ rheavy,
-                               const uint32_t *__restrict__ hoff, const uint32_t *__restrict__ nheavy,
-                               const int4 *__restrict__ lists, uint2 *__restrict__ chunk) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= dev_count(ncb, dnc)) return;
-    const uint32_t per = lists ? uint32_t(refine_qpw(lists[c * kListStride].x)) : 64u;
-    const uint32_t o = rheavy[c] ? hoff[c] : *nheavy + (roff[c] - hoff[c]);
-    for (uint32_t j = 0; j < rchunks[c]; ++j) chunk[o + j] = make_uint2(uint32_t(c), j * per);
+    rchunks[c] = (rcnt[c] + 63) / 64;
 }
 
 __global__ void k_refine_scatter(const uint2 *__restrict__ rec, const unsigned long long *__restrict__ nrec,
                                  int64_t cap, const uint32_t *__restrict__ rrank,
-                                 const uint32_t *__restrict__ roff, uint32_t *__restrict__ rorder) {
+                                 const uint32_t *__restrict__ roff, uint32_t *__restrict__ rorder,
+                                 uint32_t *__restrict__ rcell) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t n = min(int64_t(*nrec), cap);
     if (i >= n) return;
-    rorder[roff[rec[i].x] + rrank[i]] = rec[i].y;
+    const uint32_t p = roff[rec[i].x] + rrank[i];
+    rorder[p] = rec[i].y;
+    rcell[p] = rec[i].x;
 }
 
 // ---------------------------------------------------------------------------
@@ -1139,244 +1110,461 @@ __global__ __launch_bounds__(kEvalT, (eval_min_waves<T, PERSIST>())) void k_quer
 }
 
 // ---------------------------------------------------------------------------
-// FP64 re-evaluation, one (query, cluster) pair per lane.  A chunk holds
-// floor(64 / nsel) queries of one cell (nsel: its selected clusters); lane
-// l evaluates query l / nsel against cluster l % nsel, stores the pair in
-// LDS, and one lane per query replays the accumulation over its pairs in
-// ascending cluster order: the same arithmetic, in the same order, as the
-// one-query-per-lane FP64 kernel, with the latency of one pair instead of
-// nsel.  Persistent: wavefronts take chunks from the counter *work.
+// Cluster-major FP64 re-evaluation.  The refined queries are a small, sparse
+// share of a call (under 1 % of a LiDAR band), spread over thousands of
+// cells; grouped per cell or per cluster they fill few lanes of a wavefront.
+// So the pairs (refined query, cluster of at most kBigMaxN points) of all
+// cells are counting-sorted by cluster, the clusters of at most one panel
+// first, and evaluated densely:
+//   n <= 32   one lane per pair, 64 consecutive pairs of the sorted list per
+//             wavefront (neighbouring lanes mostly share a cluster, so their
+//             loads coalesce): the FP64 small-cluster evaluation of the query
+//             kernel;
+//   n > 32    items of up to 16 queries of one cluster, a workgroup of four
+//             wavefronts: kernel values into LDS, then the product W K on
+//             FP64 MFMA (v_mfma_f64_16x16x4f64), the 16-row tiles of W shared
+//             out over the wavefronts, each factor element read once per item.
+// The pairs are reverted where they are evaluated (Eq. (3)-(5), one lane per
+// pair) and go to a buffer with their nearest point; a combination pass with
+// one lane per refined query combines them in list order.  Counts and offsets stay on the
+// device; when a call's pairs exceed the buffers, or a cluster exceeds
+// kBigMaxN points, a device flag hands every refined query to the FP64 query
+// kernel instead.
+//
+// Indexing: a cell reserves one run of slots per selected cluster,
+// cbase[cell, s], in the cluster's run; refined query p of the cell (its
+// rank) sits at off[cluster] + cbase + p of the sorted pair list.  cbase
+// lives at the cell's first re-evaluation chunk index (rchunk_off).  The
+// reverted pair of the refined query at refine position r and descriptor s
+// of its cell's list is stored at s * cap_ref + r, so that the combination
+// reads consecutive records in consecutive lanes.
 // ---------------------------------------------------------------------------
+constexpr int kBigB = 16;                 // queries per item, clusters above one panel
+constexpr int kBigMaxN = 256;             // larger clusters: the FP64 query kernel
+constexpr int kBigStride = kListStride - 1;
+constexpr int kBigT = 256;                // threads per large-cluster item
 
-struct PairSlot {
-    PairOut<double> p;
+// a reverted pair (the FP64 PairOut without the FP32 error estimates), its
+// nearest training point and the cluster size
+struct BigOut {
+    double d, v, gx, gy, gz, o, u, c;
     float best;
-    int bidx, n;
+    int bidx;
+    int n, pad;
+};
+static_assert(sizeof(BigOut) == 80, "BigOut layout");
+
+template <int KERN>
+__device__ __forceinline__ BigOut big_out(const PairRaw<double> &r, int n, const QueryConsts &C, float best, int bidx) {
+    const PairOut<double> p = pair_out<double, KERN>(r, n, C);
+    return BigOut{p.d, p.v, p.gx, p.gy, p.gz, p.o, p.u, p.c, best, bidx, n, 0};
+}
+
+struct BigView {
+    const BigOut *res;      // [descriptor s][refine position]
+    int64_t cap_ref;        // refine positions per descriptor
 };
 
-// Clusters above one panel are evaluated in FP64 for a batch of NB queries
-// of the chunk at a time.  First, for each query of the batch, the lanes take
-// the points j = lane + 64 m for the kernel values and the sums of Eq. (1)
-// and (5); the kernel values go to LDS as kb[j][NB].  Then the lanes take the
-// rows of the factor, 64 consecutive rows per pass (two 32-row panels, whose
-// rows are consecutive in a column), so that each element of the FP64 factor
-// read from memory is applied to every query of the batch.  A panel is stored
-// up to its last column with zeros above the diagonal and below row n, so a
-// lane runs its panel's full width.  The nearest training point is the
-// minimum of (distance, index), the same decision as the scan in index order.
-constexpr int kCoopMaxN = 1024;   // the largest cluster the library accepts
+__device__ __forceinline__ bool cm_cluster(int n) { return n <= kBigMaxN; }
 
-template <typename V>
-__device__ __forceinline__ V wave_sum(V v) {
-    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// pairs per cluster; each cell with refined queries reserves a run per
+// selected cluster
+__global__ void k_cm_count(int64_t ncb, const uint32_t *__restrict__ dnc, const uint32_t *__restrict__ rcnt,
+                           const uint32_t *__restrict__ rchunk_off, const uint32_t *__restrict__ nchunks,
+                           int64_t cap_ch, const int4 *__restrict__ lists, uint32_t *__restrict__ bcnt,
+                           uint32_t *__restrict__ cbase) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (int64_t(*nchunks) > cap_ch || c >= dev_count(ncb, dnc)) return;
+    const uint32_t k = rcnt[c];
+    if (k == 0) return;
+    const int4 *L = lists + size_t(c) * kListStride;
+    uint32_t *cb = cbase + size_t(rchunk_off[c]) * kBigStride;
+    const int nsel = L[0].x;
+    for (int s = 0; s < nsel; ++s) {
+        const int4 d = L[1 + s];
+        if (cm_cluster(d.z)) cb[s] = atomicAdd(&bcnt[d.x], k);
+    }
 }
 
-// Batch size for `rem` queries left on a cluster of n points: a power of two
-// up to 4 whose kernel values fit the LDS buffer.
-__device__ __forceinline__ int coop_nb(int rem, int n) {
-    const int fit = kCoopMaxN / n;
-    int nb = 1;
-    while (nb < rem && 2 * nb <= fit && nb < 4) nb <<= 1;
-    return nb;
+// the counts by size class, and the items of the larger clusters
+__global__ void k_cm_split(int64_t ncb, const uint32_t *__restrict__ dncl, const int32_t *__restrict__ coff,
+                           const uint32_t *__restrict__ bcnt, uint32_t *__restrict__ bcs,
+                           uint32_t *__restrict__ bcb, uint32_t *__restrict__ nits, uint32_t *__restrict__ nit) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= dev_count(ncb, dncl)) return;
+    const int n = coff[c + 1] - coff[c];
+    const uint32_t k = bcnt[c];
+    const bool big = n > kPanel && n <= kBigMaxN;
+    bcs[c] = n <= kPanel ? k : 0u;
+    bcb[c] = big ? k : 0u;
+    nits[c] = n <= kPanel ? (k + 63) / 64 : 0u;
+    nit[c] = big ? (k + kBigB - 1) / kBigB : 0u;
 }
 
-template <int KERN, int NB>
-__device__ void coop_batch(const float *__restrict__ q, const Grouping &G, uint32_t first, int rem, int base,
-                           int n, int64_t woff, const ModelView &Mo, const QueryConsts &C, double *kb,
-                           PairSlot *slot, int sidx, int nsel, uint32_t a0) {
+// ok: the pairs fit the buffers; fast: ok and no cluster above kBigMaxN
+// points (every pair in the buffer): the refined queries go to the
+// combination, else the chunks go to the FP64 query kernel
+__global__ void k_cm_check(const uint32_t *__restrict__ nchunks, int64_t cap_ch, const uint32_t *__restrict__ nps,
+                           const uint32_t *__restrict__ npb, int64_t cap_pairs, const uint32_t *__restrict__ maxn,
+                           const unsigned long long *__restrict__ nrec, int64_t cap_rec, int64_t cap_ref,
+                           uint32_t *__restrict__ ok, uint32_t *__restrict__ nref_fast,
+                           uint32_t *__restrict__ nch_slow) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int64_t nr = min(int64_t(*nrec), cap_rec);
+        const bool fit = int64_t(*nchunks) <= cap_ch && int64_t(*nps) + int64_t(*npb) <= cap_pairs && nr <= cap_ref;
+        const bool all = fit && *maxn <= uint32_t(kBigMaxN);
+        *ok = fit ? 1u : 0u;
+        *nref_fast = all ? uint32_t(nr) : 0u;
+        *nch_slow = all ? 0u : *nchunks;
+    }
+}
+
+// run offsets: the clusters of at most one panel first, then the others
+__global__ void k_cm_off(int64_t ncb, const uint32_t *__restrict__ dncl, const int32_t *__restrict__ coff,
+                         const uint32_t *__restrict__ boffs, const uint32_t *__restrict__ boffb,
+                         const uint32_t *__restrict__ nps, uint32_t *__restrict__ boff) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= dev_count(ncb, dncl)) return;
+    const int n = coff[c + 1] - coff[c];
+    boff[c] = n <= kPanel ? boffs[c] : *nps + boffb[c];
+}
+
+__global__ void k_cm_items(int64_t ncb, const uint32_t *__restrict__ dncl, const uint32_t *__restrict__ nits,
+                           const uint32_t *__restrict__ ioffs, const uint32_t *__restrict__ nit,
+                           const uint32_t *__restrict__ ioff, const uint32_t *__restrict__ ok,
+                           uint2 *__restrict__ items_s, uint2 *__restrict__ item) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (*ok == 0 || c >= dev_count(ncb, dncl)) return;
+    for (uint32_t i = 0; i < nits[c]; ++i) items_s[ioffs[c] + i] = make_uint2(uint32_t(c), i * 64u);
+    for (uint32_t i = 0; i < nit[c]; ++i) item[ioff[c] + i] = make_uint2(uint32_t(c), i * kBigB);
+}
+
+// the query and result slot of every pair: one thread per refine record
+__global__ void k_cm_fill(const uint2 *__restrict__ rec, const unsigned long long *__restrict__ nrec, int64_t cap,
+                          const uint32_t *__restrict__ rrank, const uint32_t *__restrict__ roff,
+                          const uint32_t *__restrict__ rchunk_off, const int4 *__restrict__ lists,
+                          const uint32_t *__restrict__ cbase, const uint32_t *__restrict__ boff,
+                          const uint32_t *__restrict__ ok, int64_t cap_ref, uint32_t *__restrict__ bq,
+                          uint32_t *__restrict__ bdst) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nr = min(int64_t(*nrec), cap);
+    if (*ok == 0 || i >= nr) return;
+    const uint2 r = rec[i];
+    const uint32_t p = rrank[i];
+    const uint32_t rp = roff[r.x] + p;   // position in the refine order
+    const int4 *L = lists + size_t(r.x) * kListStride;
+    const uint32_t *cb = cbase + size_t(rchunk_off[r.x]) * kBigStride;
+    const int nsel = L[0].x;
+    for (int s = 0; s < nsel; ++s) {
+        const int4 d = L[1 + s];
+        if (!cm_cluster(d.z)) continue;
+        const uint32_t pos = boff[d.x] + cb[s] + p;
+        bq[pos] = r.y;
+        bdst[pos] = uint32_t(int64_t(s) * cap_ref + rp);
+    }
+}
+
+// the FP64 small-cluster rows of the query kernel, on the cluster's data
+// staged in LDS (the same arithmetic in the same order)
+template <int KERN, int NMAX, int I>
+__device__ __forceinline__ void cm_rows(const float4 *P, const double *a64, const double *b64, const double *W,
+                                        int n, int pbase, const QueryPoint &Q, const QueryConsts &C,
+                                        PairRaw<double> &r, Acc<double> &A, double *kr) {
+    if constexpr (I < NMAX) {
+        if (I >= n) return;
+        const float4 p = P[I];
+        kr[I] = point_eval<double, KERN>(p, a64[I], Q, pbase + I, C, r, A, true, beta_of<double, KERN>(b64, I));
+        const double t = row_dot<double>(W + (I * (I + 1)) / 2, kr, std::make_integer_sequence<int, I + 1>{});
+        r.ss = fma(t, t, r.ss);
+        cm_rows<KERN, NMAX, I + 1>(P, a64, b64, W, n, pbase, Q, C, r, A, kr);
+    }
+}
+
+constexpr int kSmallB = 64;   // queries per item, clusters of at most one panel
+constexpr int kSmallW = kPanel * (kPanel + 1) / 2;
+
+// clusters of at most one panel: one wavefront per item (up to 64 queries of
+// one cluster), one query per lane.  The cluster's packed factor, points,
+// alpha and beta are staged in LDS by the whole wavefront, every load issued
+// before the first store, so that the item waits for memory once.
+template <int KERN>
+__global__ __launch_bounds__(64, 3) void k_cm_small(const float *__restrict__ q, const uint2 *__restrict__ items,
+                                                    const uint32_t *__restrict__ nitems,
+                                                    const uint32_t *__restrict__ bcnt,
+                                                    const uint32_t *__restrict__ boff,
+                                                    const uint32_t *__restrict__ bq,
+                                                    const uint32_t *__restrict__ bdst, ModelView Mo, QueryConsts C,
+                                                    const uint32_t *__restrict__ ok, BigOut *__restrict__ res) {
+    __shared__ double sW[kSmallW + 64];
+    __shared__ float4 sP[kPanel];
+    __shared__ double sA[kPanel], sB[kPanel];
+    if (uniform(*ro(ok)) == 0) return;
+    const uint32_t ni = *ro(nitems);
     const int lane = int(threadIdx.x & 63);
-    // kernel values and the Eq. (1)/(5)/(6) sums of each query, the sums to LDS
-    __shared__ double sums[4][5];
-    __shared__ float sbest[4];
-    __shared__ int sbidx[4];
+    for (uint32_t w = blockIdx.x; w < ni; w += gridDim.x) {
+        const uint2 it = ro(items)[w];
+        const uint32_t cl = uniform(it.x), first = uniform(it.y);
+        const int cnt = int(uniform(min(ro(bcnt)[cl] - first, uint32_t(kSmallB))));
+        const uint32_t pos0 = uniform(ro(boff)[cl] + first);
+        const int base = int(uniform(uint32_t(Mo.coff[cl])));
+        const int n = int(uniform(uint32_t(Mo.coff[cl + 1]))) - base;
+        const int nw = n * (n + 1) / 2;
+        const double *W = Mo.W64 + int64_t(uniform(uint32_t(Mo.woff[cl])));
+        const bool act = lane < cnt;
+        const uint32_t pos = pos0 + uint32_t(act ? lane : 0);
+        const uint32_t qi = bq[pos];
+        // staging: all loads first
+        double wv[(kSmallW + 63) / 64];
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
-        if (a >= rem) {
-            for (int j = lane; j < n; j += 64) kb[j * NB + a] = 0.0;
-            continue;
+        for (int u = 0; u < (kSmallW + 63) / 64; ++u) {
+            const int i = lane + 64 * u;
+            wv[u] = i < nw ? W[i] : 0.0;
         }
-        const uint32_t qj = G.order[first + uint32_t(a)];
-        const float fx = q[3 * qj], fy = q[3 * qj + 1], fz = q[3 * qj + 2];
+        float4 pv = make_float4(0.f, 0.f, 0.f, 0.f);
+        double av = 0.0, bv = 0.0;
+        if (lane < n) {
+            pv = Mo.pts[base + lane];
+            av = Mo.alpha64[base + lane];
+            if constexpr (kern_prop(KERN)) bv = Mo.beta64[base + lane];
+        }
+        const QueryPoint Q{q[3 * qi], q[3 * qi + 1], q[3 * qi + 2]};
+#pragma unroll
+        for (int u = 0; u < (kSmallW + 63) / 64; ++u) sW[lane + 64 * u] = wv[u];
+        if (lane < kPanel) {
+            sP[lane] = pv;
+            sA[lane] = av;
+            sB[lane] = bv;
+        }
+        __syncthreads();  // the cluster's data in LDS
+        PairRaw<double> r{0.0, 0.0, 0.0, 0.0, 0.0, 0.f, 0.0, 0.f};
+        Acc<double> A;
+        acc_init(A);
+        double kr[kPanel];
+        if (n <= 8) cm_rows<KERN, 8, 0>(sP, sA, sB, sW, n, base, Q, C, r, A, kr);
+        else if (n <= 16) cm_rows<KERN, 16, 0>(sP, sA, sB, sW, n, base, Q, C, r, A, kr);
+        else cm_rows<KERN, kPanel, 0>(sP, sA, sB, sW, n, base, Q, C, r, A, kr);
+        const BigOut b = big_out<KERN>(r, n, C, A.best, A.bidx);
+        if (act) res[bdst[pos]] = b;
+        __syncthreads();  // the LDS is rewritten by the next item
+    }
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// W(i, j) of a cluster above one panel (32-row panels, column-major inside;
+// panel r starts at 512 r (r + 1): every panel before the last is full);
+// 0 above the diagonal and outside the cluster
+__device__ __forceinline__ double w64_panel_at(const double *__restrict__ W, int n, int i, int j) {
+    if (i >= n || j > i) return 0.0;
+    const int r = i >> 5;
+    return W[int64_t(512) * r * (r + 1) + int64_t(j) * kPanel + (i - (r << 5))];
+}
+
+// clusters of 33 to kBigMaxN points: one workgroup of four wavefronts per
+// item.  Kernel values: thread t takes query t % 16 and the points
+// j = t / 16 + 16 m; the partial sums of a query are added over the four
+// lane groups of a wavefront by shuffles and over the wavefronts in LDS, in a
+// fixed order.  Product: wavefront v takes the 16-row tiles v, v + 4, ...;
+// per tile the k-steps of four columns accumulate on MFMA (A = W tile from
+// memory, B = kernel values from LDS) in four independent accumulators,
+// whose sum is squared into the lane's query (column) sum.
+// MFMA lane layout (lane l, lr = l % 16, lg = l / 16): A[m][k] lane m + 16 k,
+// B[k][n] lane n + 16 k, D[m][n] lane n + 16 (m / 4), element m % 4.
+template <int KERN>
+__global__ __launch_bounds__(kBigT) void k_cm_big(const float *__restrict__ q, const uint2 *__restrict__ items,
+                                                  const uint32_t *__restrict__ nitems,
+                                                  const uint32_t *__restrict__ bcnt,
+                                                  const uint32_t *__restrict__ boff, const uint32_t *__restrict__ bq,
+                                                  const uint32_t *__restrict__ bdst, ModelView Mo, QueryConsts C,
+                                                  const uint32_t *__restrict__ ok, BigOut *__restrict__ res) {
+    extern __shared__ double kb[];   // [rows rounded up to 4][kBigB]
+    __shared__ float4 sP[kBigMaxN];
+    __shared__ double sA[kBigMaxN], sB[kBigMaxN];
+    __shared__ double part[4][kBigB][6];
+    __shared__ float pbest[4][kBigB];
+    __shared__ int pidx[4][kBigB];
+    __shared__ double pss[4][kBigB];
+    if (uniform(*ro(ok)) == 0) return;
+    const uint32_t ni = *ro(nitems);
+    const int t = int(threadIdx.x), lane = t & 63, wv = t >> 6;
+    for (uint32_t w = blockIdx.x; w < ni; w += gridDim.x) {
+    const uint2 it = ro(items)[w];
+    const uint32_t cl = uniform(it.x), first = uniform(it.y);
+    const int cnt = int(uniform(min(ro(bcnt)[cl] - first, uint32_t(kBigB))));
+    const uint32_t pos0 = uniform(ro(boff)[cl] + first);
+    const int base = int(uniform(uint32_t(Mo.coff[cl])));
+    const int n = int(uniform(uint32_t(Mo.coff[cl + 1]))) - base;
+    const int rows = (n + 3) & ~3;
+    const double *W = Mo.W64 + int64_t(uniform(uint32_t(Mo.woff[cl])));
+    // the cluster's points, alpha and beta staged in LDS (one round of loads)
+    if (t < n) {
+        sP[t] = Mo.pts[base + t];
+        sA[t] = Mo.alpha64[base + t];
+        if constexpr (kern_prop(KERN)) sB[t] = Mo.beta64[base + t];
+    }
+    __syncthreads();
+    // kernel values and sums
+    {
+        const int a = t & 15, ph = t >> 4;
+        const bool act = a < cnt;
+        const uint32_t qi = ro(bq)[pos0 + uint32_t(act ? a : 0)];
+        const float fx = q[3 * qi], fy = q[3 * qi + 1], fz = q[3 * qi + 2];
         double o = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, cp = 0.0;
         float best = INFINITY;
         int bidx = 0x7fffffff;
-        for (int j = lane; j < n; j += 64) {
-            const float4 p = Mo.pts[base + j];
-            const double al = Mo.alpha64[base + j];
-            const float ex = fx - p.x, ey = fy - p.y, ez = fz - p.z;
-            const float r2f = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
-            if (r2f < best) { best = r2f; bidx = base + j; }
-            const double dx = double(fx) - double(p.x), dy = double(fy) - double(p.y), dz = double(fz) - double(p.z);
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            double k, e;
-            if (kern_kind(KERN) == GPDF_KERNEL_MATERN32) {
-                const double t = ::sqrt(r2) * C.ad;
-                e = ::exp(-t);
-                k = fma(t, e, e);
-            } else {
-                k = ::exp(-(r2 * C.ad));
-                e = k;
+        for (int j = ph; j < rows; j += 16) {
+            double k = 0.0;
+            if (j < n) {
+                const float4 p = sP[j];
+                const double al = sA[j];
+                const float ex = fx - p.x, ey = fy - p.y, ez = fz - p.z;
+                const float r2f = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+                if (r2f < best) { best = r2f; bidx = base + j; }
+                const double dx = double(fx) - double(p.x), dy = double(fy) - double(p.y),
+                             dz = double(fz) - double(p.z);
+                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                double e;
+                if (kern_kind(KERN) == GPDF_KERNEL_MATERN32) {
+                    const double tt = ::sqrt(r2) * C.ad;
+                    e = ::exp(-tt);
+                    k = fma(tt, e, e);
+                } else {
+                    k = ::exp(-(r2 * C.ad));
+                    e = k;
+                }
+                o = fma(al, k, o);
+                if constexpr (kern_prop(KERN)) cp = fma(sB[j], k, cp);
+                const double cg = al * e;
+                gx = fma(cg, dx, gx);
+                gy = fma(cg, dy, gy);
+                gz = fma(cg, dz, gz);
             }
-            o = fma(al, k, o);
-            if constexpr (kern_prop(KERN)) cp = fma(Mo.beta64[base + j], k, cp);
-            const double cg = al * e;
-            gx = fma(cg, dx, gx);
-            gy = fma(cg, dy, gy);
-            gz = fma(cg, dz, gz);
-            kb[j * NB + a] = k;
+            kb[j * kBigB + a] = act ? k : 0.0;
         }
-        o = wave_sum(o); gx = wave_sum(gx); gy = wave_sum(gy); gz = wave_sum(gz);
-        if constexpr (kern_prop(KERN)) cp = wave_sum(cp);
-        for (int s = 1; s < 64; s <<= 1) {
-            const float b2 = __shfl_xor(best, s, 64);
-            const int i2 = __shfl_xor(bidx, s, 64);
+#pragma unroll
+        for (int m = 16; m <= 32; m <<= 1) {
+            o += __shfl_xor(o, m, 64);
+            gx += __shfl_xor(gx, m, 64);
+            gy += __shfl_xor(gy, m, 64);
+            gz += __shfl_xor(gz, m, 64);
+            if constexpr (kern_prop(KERN)) cp += __shfl_xor(cp, m, 64);
+            const float b2 = __shfl_xor(best, m, 64);
+            const int i2 = __shfl_xor(bidx, m, 64);
             if (b2 < best || (b2 == best && i2 < bidx)) { best = b2; bidx = i2; }
         }
-        if (lane == 0) {
-            sums[a][0] = o; sums[a][1] = gx; sums[a][2] = gy; sums[a][3] = gz; sums[a][4] = cp;
-            sbest[a] = best; sbidx[a] = bidx;
+        if (lane < kBigB) {
+            part[wv][lane][0] = o; part[wv][lane][1] = gx; part[wv][lane][2] = gy;
+            part[wv][lane][3] = gz; part[wv][lane][4] = cp;
+            pbest[wv][lane] = best;
+            pidx[wv][lane] = bidx;
         }
     }
-    __syncthreads();  // kernel values visible to the wave
-    // ||W k||^2 for every query of the batch
-    constexpr int P = 4 / NB;  // partial sums per query
-    static_assert(NB == 1 || NB == 2 || NB == 4, "batch of 1, 2 or 4 queries");
-    double ss[NB];
+    __syncthreads();  // kernel values and partial sums visible
+    // product W K on MFMA
+    const int lr = lane & 15, lg = lane >> 4;
+    const int ntile = (n + 15) >> 4;
+    double ssq = 0.0;
+    for (int tile = wv; tile < ntile; tile += 4) {
+        const int i = 16 * tile + lr;
+        const int ksteps = (min(16 * tile + 16, n) + 3) >> 2;   // columns up to the tile's last row
+        f64x4 acc[4];
 #pragma unroll
-    for (int a = 0; a < NB; ++a) ss[a] = 0.0;
-    for (int r0 = 0; r0 * kPanel < n; r0 += 2) {
-        const int r = r0 + (lane >> 5);
-        if (r * kPanel >= n) continue;
-        const int ncol = min((r + 1) * kPanel, n);
-        const double *Wp = Mo.W64 + woff + w32_panel_offset(n, r) + (lane & 31);
-        double v[NB][P];
+        for (int u = 0; u < 4; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+        // 16 k-steps of factor loads in flight at a time
+        for (int s0 = 0; s0 < ksteps; s0 += 16) {
+            double av[16];
 #pragma unroll
-        for (int a = 0; a < NB; ++a)
+            for (int u = 0; u < 16; ++u) {
+                const int j = 4 * (s0 + u) + lg;
+                av[u] = s0 + u < ksteps ? w64_panel_at(W, n, i, j) : 0.0;
+            }
 #pragma unroll
-            for (int u = 0; u < P; ++u) v[a][u] = 0.0;
-        int j = 0;
-        for (; j + 8 <= ncol; j += 8) {
-            double w[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) w[u] = Wp[int64_t(j + u) * kPanel];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int a = 0; a < NB; ++a) v[a][u % P] = fma(w[u], kb[(j + u) * NB + a], v[a][u % P]);
+            for (int u = 0; u < 16; ++u) {
+                const int j = min(4 * (s0 + u) + lg, rows - 1);
+                acc[u & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], kb[j * kBigB + lr], acc[u & 3], 0, 0, 0);
+            }
         }
-        for (; j < ncol; ++j) {
-            const double w = Wp[int64_t(j) * kPanel];
-#pragma unroll
-            for (int a = 0; a < NB; ++a) v[a][0] = fma(w, kb[j * NB + a], v[a][0]);
-        }
-#pragma unroll
-        for (int a = 0; a < NB; ++a) {
-            double t = v[a][0];
-#pragma unroll
-            for (int u = 1; u < P; ++u) t += v[a][u];
-            ss[a] = fma(t, t, ss[a]);
-        }
+        const f64x4 d = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        ssq = fma(d[0], d[0], ssq);
+        ssq = fma(d[1], d[1], ssq);
+        ssq = fma(d[2], d[2], ssq);
+        ssq = fma(d[3], d[3], ssq);
     }
-    double mss = 0.0;
+    ssq += __shfl_xor(ssq, 16, 64);
+    ssq += __shfl_xor(ssq, 32, 64);
+    if (lane < kBigB) pss[wv][lane] = ssq;
+    __syncthreads();
+    if (t < cnt) {
+        double sm[5];
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
-        const double t = wave_sum(ss[a]);
-        if (lane == a) mss = t;
+        for (int k = 0; k < 5; ++k) sm[k] = ((part[0][t][k] + part[1][t][k]) + part[2][t][k]) + part[3][t][k];
+        float best = pbest[0][t];
+        int bidx = pidx[0][t];
+#pragma unroll
+        for (int v = 1; v < 4; ++v)
+            if (pbest[v][t] < best || (pbest[v][t] == best && pidx[v][t] < bidx)) { best = pbest[v][t]; bidx = pidx[v][t]; }
+        const double ss = ((pss[0][t] + pss[1][t]) + pss[2][t]) + pss[3][t];
+        const PairRaw<double> r{sm[0], sm[1], sm[2], sm[3], ss, 0.f, sm[4], 0.f};
+        res[bdst[pos0 + uint32_t(t)]] = big_out<KERN>(r, n, C, best, bidx);
     }
-    if (lane < rem && lane < NB) {
-        const PairRaw<double> rr{sums[lane][0], sums[lane][1], sums[lane][2], sums[lane][3], mss, 0.f,
-                                 sums[lane][4], 0.f};
-        slot[(a0 + uint32_t(lane)) * nsel + sidx] =
-            PairSlot{pair_out<double, KERN>(rr, n, C), sbest[lane], sbidx[lane], n};
+    __syncthreads();  // kb and the partial sums are rewritten by the next item
     }
-    __syncthreads();  // kb and the sums are rewritten by the next batch
 }
 
+// The combination of the re-evaluated queries: one lane per refined query,
+// 64 consecutive queries of the refine order (grouped by cell) per
+// wavefront; each lane takes its cell's selected clusters in list order as
+// the query kernel does and combines every reverted pair from the
+// cluster-major buffer.  The next pair is loaded while the current one is
+// combined.  Grid-stride over the windows.
 template <int KERN, int MODE>
-__global__ __launch_bounds__(kEvalT, 3) void k_refine_pairs(const float *__restrict__ q, Grouping G,
-                                                        const int4 *__restrict__ lists, ModelView Mo, QueryConsts C,
-                                                        Outputs O, uint32_t *work) {
-    __shared__ PairSlot slot[64];
-    __shared__ double kbuf[kCoopMaxN];
+__global__ __launch_bounds__(kEvalT) void k_cm_combine(const float *__restrict__ q,
+                                                       const uint32_t *__restrict__ nref,
+                                                       const uint32_t *__restrict__ rorder,
+                                                       const uint32_t *__restrict__ rcell,
+                                                       const int4 *__restrict__ lists, ModelView Mo, QueryConsts C,
+                                                       Outputs O, BigView BV) {
     const int lane = threadIdx.x & 63;
-    const uint32_t nch = *ro(G.nchunks);
-    while (true) {
-        uint32_t w = 0;
-        if (lane == 0) w = atomicAdd(work, 1u);
-        w = uniform(uint32_t(__shfl(int(w), 0, 64)));
-        if (w >= nch) break;
-        const uint2 ch = ro(G.chunk)[w];
-        const uint32_t cell = uniform(ch.x), start = uniform(ch.y);
-        const RoPtr<int4> L = ro(lists + size_t(cell) * kListStride);
-        const int nsel = int(uniform(uint32_t(L[0].x)));
-        const int qpw = refine_qpw(nsel);
-        const uint32_t cnt = uniform(min(ro(G.cell_cnt)[cell] - start, uint32_t(qpw)));
-        const int qa = nsel > 0 ? lane / nsel : 0, sl = nsel > 0 ? lane - qa * nsel : 0;
-        const bool pair_on = nsel > 0 && uint32_t(qa) < cnt;
-        const uint32_t qi = G.order[ro(G.cell_off)[cell] + start + (pair_on ? qa : 0)];
+    const uint32_t nr = *ro(nref), nwin = (nr + 63) / 64;
+    for (uint32_t w = blockIdx.x; w < nwin; w += gridDim.x) {
+        const uint32_t p = 64 * w + uint32_t(lane);
+        const bool active = p < nr;
+        const uint32_t pp = active ? p : 64 * w;
+        const uint32_t qi = rorder[pp], cell = rcell[pp];
         const QueryPoint Q{q[3 * qi], q[3 * qi + 1], q[3 * qi + 2]};
+        const int nsel = lists[size_t(cell) * kListStride].x;
+        const BigOut *R = BV.res + pp;
         Acc<double> A;
         acc_init(A);
-        if (pair_on) {
-            const int4 d = L[1 + sl];
-            const int base = d.y, n = d.z;
-            if (n <= kPanel) {
-                const float4 *P = Mo.pts + base;
-                const double *a64 = Mo.alpha64 + base;
-                const float *B = Mo.beta32 + base;
-                const double *b64 = Mo.beta64 + base;
-                const double *W = Mo.W64 + d.w;
-                PairRaw<double> r{0.0, 0.0, 0.0, 0.0, 0.0, 0.f, 0.0, 0.f};
-                if (n <= 8) eval_small<double, KERN, 8>(P, a64, B, b64, W, n, base, Q, C, r, A);
-                else if (n <= 16) eval_small<double, KERN, 16>(P, a64, B, b64, W, n, base, Q, C, r, A);
-                else eval_small<double, KERN, kPanel>(P, a64, B, b64, W, n, base, Q, C, r, A);
-                slot[lane] = PairSlot{pair_out<double, KERN>(r, n, C), A.best, A.bidx, n};
-            }
-        }
-        // clusters above one panel: the chunk's queries in batches
-        const uint32_t first = ro(G.cell_off)[cell] + start;
+        // two pairs in flight ahead of the one combined
+        BigOut b0{}, b1{};
+        if (nsel > 0) b0 = R[0];
+        if (nsel > 1) b1 = R[BV.cap_ref];
         for (int s = 0; s < nsel; ++s) {
-            const int4 d = L[1 + s];
-            const int n = int(uniform(uint32_t(d.z)));
-            if (n <= kPanel) continue;
-            const int base = int(uniform(uint32_t(d.y)));
-            const int64_t woff = int64_t(uniform(uint32_t(d.w)));
-            for (uint32_t a0 = 0; a0 < cnt;) {
-                const int rem = int(cnt - a0), nb = coop_nb(rem, n);
-                if (nb == 4) coop_batch<KERN, 4>(q, G, first + a0, rem, base, n, woff, Mo, C, kbuf, slot, s, nsel, a0);
-                else if (nb == 2) coop_batch<KERN, 2>(q, G, first + a0, rem, base, n, woff, Mo, C, kbuf, slot, s, nsel, a0);
-                else coop_batch<KERN, 1>(q, G, first + a0, rem, base, n, woff, Mo, C, kbuf, slot, s, nsel, a0);
-                a0 += uint32_t(nb);
-            }
+            const BigOut b = b0;
+            b0 = b1;
+            if (s + 2 < nsel) b1 = R[int64_t(s + 2) * BV.cap_ref];
+            const PairOut<double> po{b.d, b.v, b.gx, b.gy, b.gz, b.o, b.u, 0.f, 0.f, 0.f, 0.f, b.c, 0.f};
+            pair_accumulate<double, kern_grad(KERN), kern_prop(KERN)>(po, b.n, C, A);
+            if (b.best < A.best) { A.best = b.best; A.bidx = b.bidx; }
         }
-        __syncthreads();
-        // the first lane of each query accumulates its pairs in cluster order
-        const bool leader = pair_on && sl == 0;
-        Acc<double> B;
-        acc_init(B);
-        if (leader) {
-            for (int k = 0; k < nsel; ++k) {
-                const PairSlot &ps = slot[lane + k];
-                pair_accumulate<double, true, kern_prop(KERN)>(ps.p, ps.n, C, B);
-                if (ps.best < B.best) { B.best = ps.best; B.bidx = ps.bidx; }
-            }
-        }
-        __syncthreads();  // the slots are rewritten by the next chunk
-        finish_query<double, MODE, kern_prop(KERN)>(B, qi, cell, leader, Q, Mo.pts, C, O);
+        finish_query<double, MODE, kern_prop(KERN)>(A, qi, cell, active, Q, Mo.pts, C, O);
     }
 }
 
 template <int KERN>
-void launch_refine_pairs(unsigned grid, hipStream_t s, const float *q, const Grouping &G, const int4 *lists,
-                         const ModelView &Mo, const QueryConsts &C, const Outputs &O, uint32_t *work) {
+void launch_cm_combine(unsigned grid, hipStream_t s, const float *q, const uint32_t *nref, const uint32_t *rorder,
+                       const uint32_t *rcell, const int4 *lists, const ModelView &Mo, const QueryConsts &C,
+                       const Outputs &O, const BigView &BV) {
     if (C.combine == GPDF_COMB_HARDMIN)
-        hipLaunchKernelGGL((k_refine_pairs<KERN, kModeHard>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists, Mo, C, O, work);
+        hipLaunchKernelGGL((k_cm_combine<KERN, kModeHard>), dim3(grid), dim3(kEvalT), 0, s, q, nref, rorder, rcell,
+                           lists, Mo, C, O, BV);
     else if (C.grad_mode == GPDF_GRAD_PAPER_MEAN)
-        hipLaunchKernelGGL((k_refine_pairs<KERN, kModeMean>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists, Mo, C, O, work);
+        hipLaunchKernelGGL((k_cm_combine<KERN, kModeMean>), dim3(grid), dim3(kEvalT), 0, s, q, nref, rorder, rcell,
+                           lists, Mo, C, O, BV);
     else
-        hipLaunchKernelGGL((k_refine_pairs<KERN, kModeSmooth>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists, Mo, C, O,
-                           work);
+        hipLaunchKernelGGL((k_cm_combine<KERN, kModeSmooth>), dim3(grid), dim3(kEvalT), 0, s, q, nref, rorder,
+                           rcell, lists, Mo, C, O, BV);
 }
 
 // ---------------------------------------------------------------------------
@@ -1869,11 +2057,15 @@ template <typename T, int KERN, int MODE>
 void launch_query(bool knn, unsigned grid, hipStream_t s, const float *q, const Grouping &G,
                   const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O,
                   uint32_t *work) {
-    // property launches: NEIGHBOR27, one workgroup per chunk (the caller
-    // rejects the other combinations)
+    // property launches: NEIGHBOR27 (the caller rejects the other
+    // combinations), one workgroup per chunk, or persistent given a counter
     if constexpr (kern_prop(KERN)) {
-        hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, false>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
-                           Mo, C, O, nullptr);
+        if (work)
+            hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, true>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
+                               Mo, C, O, work);
+        else
+            hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, false>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
+                               Mo, C, O, nullptr);
     } else if (knn) {
         hipLaunchKernelGGL((k_query_knn<T, KERN, MODE>), dim3(grid), dim3(kEvalT), 0, s, q, G, Mo, C, O);
     } else if (work) {
@@ -2131,6 +2323,61 @@ gpdf_status build_bf16(gpdf_ctx *c) {
     return GPDF_OK;
 }
 
+// The cluster-major FP64 pass over the refine records and chunk table just
+// built: pair counts per cluster, run offsets (clusters of at most one panel
+// first), the items of both size classes, each pair's query and result slot,
+// then the two evaluation kernels.  Returns the view the combination reads.
+static BigView refine_cm(gpdf_ctx *c, const Model &M, hipStream_t s, const float *d_q, const int4 *lists,
+                         const ModelView &Mo, const QueryConsts &C, int64_t nc, const uint32_t *dnc, int64_t m,
+                         bool want_prop) {
+    uint32_t *cnt = c->d_cnt;
+    // cluster bound (the device count dncl is the exact one)
+    const int64_t ncl = std::max<int64_t>(M.host_counts ? M.nclusters : c->p.max_clusters, 1);
+    const uint32_t *dncl = cnt + CNT_CL;
+    const unsigned long long *nrec = c->d_stat + ST_REFINE;
+    fill_u32(c->d_bcnt, 0u, ncl, s);
+    hipLaunchKernelGGL(k_cm_count, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rcnt, c->d_rchunk_off,
+                       cnt + CNT_RCHUNKS, c->cap_bchunks, lists, c->d_bcnt, c->d_bbase);
+    hipLaunchKernelGGL(k_cm_split, dim3(blocks_for(ncl)), dim3(kQT), 0, s, ncl, dncl, c->d_coff, c->d_bcnt,
+                       c->d_bcs, c->d_bcb, c->d_bnits, c->d_bnit);
+    exclusive_scan_u32(c->d_bnits, c->d_bioffs, ncl, c->d_part, s, dncl, cnt + CNT_BITEMS_S);
+    exclusive_scan_u32(c->d_bcs, c->d_boffs, ncl, c->d_part, s, dncl, cnt + CNT_BPAIRS_S);
+    exclusive_scan_u32(c->d_bcb, c->d_boffb, ncl, c->d_part, s, dncl, cnt + CNT_BPAIRS_B);
+    exclusive_scan_u32(c->d_bnit, c->d_bioff, ncl, c->d_part, s, dncl, cnt + CNT_BITEMS);
+    hipLaunchKernelGGL(k_cm_check, dim3(1), dim3(64), 0, s, cnt + CNT_RCHUNKS, c->cap_bchunks, cnt + CNT_BPAIRS_S,
+                       cnt + CNT_BPAIRS_B, c->cap_bpairs, cnt + CNT_MAXN, nrec, m, c->cap_bref, cnt + CNT_BIGOK,
+                       cnt + CNT_NREF_FAST, cnt + CNT_RCH_SLOW);
+    hipLaunchKernelGGL(k_cm_off, dim3(blocks_for(ncl)), dim3(kQT), 0, s, ncl, dncl, c->d_coff, c->d_boffs,
+                       c->d_boffb, cnt + CNT_BPAIRS_S, c->d_boff);
+    hipLaunchKernelGGL(k_cm_items, dim3(blocks_for(ncl)), dim3(kQT), 0, s, ncl, dncl, c->d_bnits, c->d_bioffs,
+                       c->d_bnit, c->d_bioff, cnt + CNT_BIGOK, c->d_bitems, c->d_bitem);
+    hipLaunchKernelGGL(k_cm_fill, dim3(blocks_for(m)), dim3(kQT), 0, s, c->d_refine, nrec, m, c->d_rrank, c->d_roff,
+                       c->d_rchunk_off, lists, c->d_bbase, c->d_boff, cnt + CNT_BIGOK, c->cap_bref, c->d_bq,
+                       c->d_bdst);
+    // kernel values of the largest cluster the large-cluster pass takes
+    const int64_t nmax = M.host_counts ? std::min<int64_t>(std::max<int64_t>(M.max_n, 4), kBigMaxN) : kBigMaxN;
+    const size_t lds = size_t((nmax + 3) & ~int64_t(3)) * kBigB * sizeof(double);
+    BigOut *res = static_cast<BigOut *>(c->d_bres);
+    const int kern = c->p.kernel;
+#define GPDF_CM(K)                                                                                              \
+    do {                                                                                                        \
+        hipLaunchKernelGGL((k_cm_small<K>), dim3(3072), dim3(64), 0, s, d_q, c->d_bitems, cnt + CNT_BITEMS_S,    \
+                           c->d_bcnt, c->d_boff, c->d_bq, c->d_bdst, Mo, C, cnt + CNT_BIGOK, res);              \
+        hipLaunchKernelGGL((k_cm_big<K>), dim3(768), dim3(kBigT), lds, s, d_q, c->d_bitem, cnt + CNT_BITEMS,     \
+                           c->d_bcnt, c->d_boff, c->d_bq, c->d_bdst, Mo, C, cnt + CNT_BIGOK, res);              \
+    } while (0)
+    if (want_prop) {
+        if (kern == GPDF_KERNEL_MATERN32) GPDF_CM(GPDF_KERNEL_MATERN32 | kProp);
+        else GPDF_CM(GPDF_KERNEL_SE | kProp);
+    } else if (kern == GPDF_KERNEL_MATERN32) {
+        GPDF_CM(GPDF_KERNEL_MATERN32);
+    } else {
+        GPDF_CM(GPDF_KERNEL_SE);
+    }
+#undef GPDF_CM
+    return BigView{res, c->cap_bref};
+}
+
 gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin, float *dist,
                   float *grad, float *var, uint8_t *valid, float *aux, int32_t correct, const uint32_t *dm,
                   const float *d_origin, bool noalloc, float *prop, float *prop_var) {
@@ -2227,7 +2474,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
     exclusive_scan_u32(c->d_cell_cnt, c->d_cell_off, nc, c->d_part, s, dnc);
     exclusive_scan_u32(c->d_cell_chunks, c->d_chunk_off, nc, c->d_part, s, dnc, cnt + CNT_CHUNKS);
     hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_cell_chunks,
-                       c->d_chunk_off, nullptr, c->d_chunk);
+                       c->d_chunk_off, c->d_chunk);
     // lazy training: factor the clusters these queries select, until a
     // round trains none (a cluster found not positive definite leaves the
     // selection, which may then take another)
@@ -2318,39 +2565,45 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         const unsigned rgrid = blocks_for(m);
         hipLaunchKernelGGL(k_refine_count, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
                            c->d_stat + ST_REFINE, m, c->d_rcnt, c->d_rrank);
-        const int4 *rl = knn ? nullptr : lists;
-        // the per-cell arrays of the FP32 chunk table are free again: they
-        // hold the heavy-cell chunk counts and their offsets
-        uint32_t *rheavy = c->d_cell_chunks, *hoff = c->d_chunk_off;
-        hipLaunchKernelGGL(k_refine_chunks, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rcnt, rl,
-                           c->d_rchunks, rheavy);
+        hipLaunchKernelGGL(k_refine_chunks, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rcnt,
+                           c->d_rchunks);
         exclusive_scan_u32(c->d_rcnt, c->d_roff, nc, c->d_part, s, dnc);
         exclusive_scan_u32(c->d_rchunks, c->d_rchunk_off, nc, c->d_part, s, dnc, cnt + CNT_RCHUNKS);
-        exclusive_scan_u32(rheavy, hoff, nc, c->d_part, s, dnc, cnt + CNT_RHEAVY);
-        hipLaunchKernelGGL(k_refine_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rchunks,
-                           c->d_rchunk_off, rheavy, hoff, cnt + CNT_RHEAVY, rl, c->d_rchunk);
+        hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rchunks,
+                           c->d_rchunk_off, c->d_rchunk);
         hipLaunchKernelGGL(k_refine_scatter, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
-                           c->d_stat + ST_REFINE, m, c->d_rrank, c->d_roff, c->d_rorder);
+                           c->d_stat + ST_REFINE, m, c->d_rrank, c->d_roff, c->d_rorder, c->d_rcell);
         const Grouping R{c->d_rchunk, cnt + CNT_RCHUNKS, c->d_rcnt, c->d_roff, c->d_rorder};
         Outputs O64 = O;
         O64.refine = nullptr;
         if (knn) {
             launch_query_k<double>(c, kern, knn, grid, s, d_q, R, lists, Mo, C, O64, 1);
         } else {
-            // pair-parallel, persistent: three wavefronts per SIMD
-            uint32_t *work = c->d_work + kWorkSlot;
-            fill_u32(work, 0u, 1, s);
-            const unsigned rg = 3072;
+            // cluster-major evaluation of the pairs, then their combination
+            // (persistent); the FP64 query kernel (persistent) takes the
+            // chunks instead when the pass could not take every pair
+            const BigView BV = refine_cm(c, M, s, d_q, lists, Mo, C, nc, dnc, m, want_prop);
+            // grid-stride launches: the items are of even size, and one
+            // shared work counter would serialise on its atomics
+            const unsigned rg = unsigned(std::min<int64_t>(2048, (m + 63) / 64));
+            const Grouping Rs{c->d_rchunk, cnt + CNT_RCH_SLOW, c->d_rcnt, c->d_roff, c->d_rorder};
+            const uint32_t *nrf = cnt + CNT_NREF_FAST;
+#define GPDF_CMB(K) \
+    launch_cm_combine<K>(rg, s, d_q, nrf, c->d_rorder, c->d_rcell, lists, Mo, C, O64, BV)
             if (want_prop) {
-                if (kern == GPDF_KERNEL_MATERN32)
-                    launch_refine_pairs<GPDF_KERNEL_MATERN32 | kProp>(rg, s, d_q, R, lists, Mo, C, O64, work);
-                else
-                    launch_refine_pairs<GPDF_KERNEL_SE | kProp>(rg, s, d_q, R, lists, Mo, C, O64, work);
+                if (kern == GPDF_KERNEL_MATERN32) GPDF_CMB(GPDF_KERNEL_MATERN32 | kProp);
+                else GPDF_CMB(GPDF_KERNEL_SE | kProp);
             } else if (kern == GPDF_KERNEL_MATERN32) {
-                launch_refine_pairs<GPDF_KERNEL_MATERN32>(rg, s, d_q, R, lists, Mo, C, O64, work);
+                GPDF_CMB(GPDF_KERNEL_MATERN32);
             } else {
-                launch_refine_pairs<GPDF_KERNEL_SE>(rg, s, d_q, R, lists, Mo, C, O64, work);
+                GPDF_CMB(GPDF_KERNEL_SE);
             }
+#undef GPDF_CMB
+            // the evaluation's slot: its launch has finished
+            uint32_t *work2 = c->d_work;
+            fill_u32(work2, 0u, kWorkSlot, s);
+            if (want_prop) launch_query_kf<double, kProp>(kern, false, 1024, s, d_q, Rs, lists, Mo, C, O64, work2);
+            else launch_query_kf<double, 0>(kern, false, 1024, s, d_q, Rs, lists, Mo, C, O64, work2);
         }
         stage_end(c, GPDF_MS_REFINE);
     }

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_default_layout_and_values():
     p = P.Params.default()
-    assert p.abi_version == 3
+    assert p.abi_version == 4
     assert p.kernel == P.KERNEL_MATERN32
     assert p.length_scale == 0.2 and p.noise_sigma == 0.01
     assert p.cluster_size == 0.4 and p.voxel_size == 0.0
