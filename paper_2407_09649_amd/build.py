@@ -47,7 +47,8 @@ def build(extra=(), jobs: int = 6, only=None) -> str:
         list(ex.map(lambda s: _compile(s, list(extra)), todo))
     objs = [os.path.join(OUT, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    # every symbol resolved at link time (a missing definition fails the build, not the first load)
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,-z,defs", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

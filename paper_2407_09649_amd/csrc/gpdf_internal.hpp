@@ -554,6 +554,24 @@ gpdf_status hip_fail(gpdf_ctx *c, hipError_t e, const char *what);
 // ceil(n / 4096) + 1 entries.
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
                         hipStream_t s, const uint32_t *dn = nullptr, uint32_t *total_out = nullptr);
+// up to four exclusive scans of the same length n (and device count dn),
+// each as exclusive_scan_u32: one launch when n is small, else one after
+// the other (the partials are then shared in stream order)
+struct ScanList {
+    static constexpr int kMax = 4;
+    const uint32_t *in[kMax] = {};
+    uint32_t *out[kMax] = {};
+    uint32_t *total[kMax] = {};
+    int count = 0;
+    void add(const uint32_t *i, uint32_t *o, uint32_t *t) {
+        in[count] = i;
+        out[count] = o;
+        total[count] = t;
+        ++count;
+    }
+};
+void exclusive_scan_u32_multi(const ScanList &L, int64_t n, uint32_t *partials, hipStream_t s,
+                              const uint32_t *dn = nullptr);
 void radix_sort_pairs(uint64_t *&keys, uint64_t *&keys_alt, uint32_t *&vals, uint32_t *&vals_alt,
                       int64_t n, uint64_t varying_bits, uint32_t *hist, uint32_t *partials,
                       hipStream_t s);

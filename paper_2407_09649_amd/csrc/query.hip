@@ -309,13 +309,16 @@ __global__ void k_all_invalid(int64_t m, float *dist, float *grad, float *var, u
 }
 
 // refine records (cell, query) -> counting sort by cell
+// (grid-stride: the records are a small share of the queries that bound the
+// grid)
 __global__ void k_refine_count(const uint2 *__restrict__ rec, const unsigned long long *__restrict__ nrec,
                                int64_t cap, uint32_t *__restrict__ rcnt, uint32_t *__restrict__ rrank) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t n = min(int64_t(*nrec), cap);
-    if (int64_t(blockIdx.x) * blockDim.x >= n) return;
-    const uint32_t r = wave_rank(rcnt, i < n ? int64_t(rec[i].x) : int64_t(-1));
-    if (i < n) rrank[i] = r;
+    for (int64_t b = int64_t(blockIdx.x) * blockDim.x; b < n; b += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = b + threadIdx.x;
+        const uint32_t r = wave_rank(rcnt, i < n ? int64_t(rec[i].x) : int64_t(-1));
+        if (i < n) rrank[i] = r;
+    }
 }
 
 // re-evaluation chunks per cell, 64 refined queries each
@@ -330,12 +333,12 @@ __global__ void k_refine_scatter(const uint2 *__restrict__ rec, const unsigned l
                                  int64_t cap, const uint32_t *__restrict__ rrank,
                                  const uint32_t *__restrict__ roff, uint32_t *__restrict__ rorder,
                                  uint32_t *__restrict__ rcell) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t n = min(int64_t(*nrec), cap);
-    if (i >= n) return;
-    const uint32_t p = roff[rec[i].x] + rrank[i];
-    rorder[p] = rec[i].y;
-    rcell[p] = rec[i].x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const uint32_t p = roff[rec[i].x] + rrank[i];
+        rorder[p] = rec[i].y;
+        rcell[p] = rec[i].x;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1168,21 +1171,23 @@ struct BigView {
 __device__ __forceinline__ bool cm_cluster(int n) { return n <= kBigMaxN; }
 
 // pairs per cluster; each cell with refined queries reserves a run per
-// selected cluster
-__global__ void k_cm_count(int64_t ncb, const uint32_t *__restrict__ dnc, const uint32_t *__restrict__ rcnt,
-                           const uint32_t *__restrict__ rchunk_off, const uint32_t *__restrict__ nchunks,
-                           int64_t cap_ch, const int4 *__restrict__ lists, uint32_t *__restrict__ bcnt,
-                           uint32_t *__restrict__ cbase) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (int64_t(*nchunks) > cap_ch || c >= dev_count(ncb, dnc)) return;
-    const uint32_t k = rcnt[c];
-    if (k == 0) return;
-    const int4 *L = lists + size_t(c) * kListStride;
-    uint32_t *cb = cbase + size_t(rchunk_off[c]) * kBigStride;
-    const int nsel = L[0].x;
-    for (int s = 0; s < nsel; ++s) {
+// selected cluster.  One thread per (first re-evaluation chunk of a cell,
+// list slot); the chunk table is in cell order, so the cell's first chunk
+// index is w.
+__global__ void k_cm_count(const uint2 *__restrict__ chunk, const uint32_t *__restrict__ nchunks, int64_t cap_ch,
+                           const uint32_t *__restrict__ rcnt, const int4 *__restrict__ lists,
+                           uint32_t *__restrict__ bcnt, uint32_t *__restrict__ cbase) {
+    const uint32_t nch = *nchunks;
+    if (int64_t(nch) > cap_ch) return;
+    const uint32_t total = nch * uint32_t(kBigStride);
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+        const uint32_t w = idx / kBigStride, s = idx - w * kBigStride;
+        const uint2 ch = chunk[w];
+        if (ch.y != 0) continue;
+        const int4 *L = lists + size_t(ch.x) * kListStride;
+        if (int(s) >= L[0].x) continue;
         const int4 d = L[1 + s];
-        if (cm_cluster(d.z)) cb[s] = atomicAdd(&bcnt[d.x], k);
+        if (cm_cluster(d.z)) cbase[size_t(w) * kBigStride + s] = atomicAdd(&bcnt[d.x], rcnt[ch.x]);
     }
 }
 
@@ -1201,66 +1206,67 @@ __global__ void k_cm_split(int64_t ncb, const uint32_t *__restrict__ dncl, const
     nit[c] = big ? (k + kBigB - 1) / kBigB : 0u;
 }
 
-// ok: the pairs fit the buffers; fast: ok and no cluster above kBigMaxN
-// points (every pair in the buffer): the refined queries go to the
-// combination, else the chunks go to the FP64 query kernel
-__global__ void k_cm_check(const uint32_t *__restrict__ nchunks, int64_t cap_ch, const uint32_t *__restrict__ nps,
-                           const uint32_t *__restrict__ npb, int64_t cap_pairs, const uint32_t *__restrict__ maxn,
-                           const unsigned long long *__restrict__ nrec, int64_t cap_rec, int64_t cap_ref,
-                           uint32_t *__restrict__ ok, uint32_t *__restrict__ nref_fast,
-                           uint32_t *__restrict__ nch_slow) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const int64_t nr = min(int64_t(*nrec), cap_rec);
-        const bool fit = int64_t(*nchunks) <= cap_ch && int64_t(*nps) + int64_t(*npb) <= cap_pairs && nr <= cap_ref;
-        const bool all = fit && *maxn <= uint32_t(kBigMaxN);
+// per cluster, once the counts are scanned: the run offsets (the clusters of
+// at most one panel first, then the others) and the items of both size
+// classes, when the pairs fit the buffers.  The first thread also records
+// the decision: ok (the pairs fit), and the refined queries for the
+// combination when every selected cluster has at most kBigMaxN points, else
+// the chunks for the FP64 query kernel.
+struct CmTotals {
+    const uint32_t *nchunks, *nps, *npb, *maxn;
+    const unsigned long long *nrec;
+    int64_t cap_ch, cap_pairs, cap_rec, cap_ref;
+};
+
+__device__ __forceinline__ bool cm_fit(const CmTotals &T, int64_t nr) {
+    return int64_t(*T.nchunks) <= T.cap_ch && int64_t(*T.nps) + int64_t(*T.npb) <= T.cap_pairs && nr <= T.cap_ref;
+}
+
+__global__ void k_cm_finish(int64_t ncb, const uint32_t *__restrict__ dncl, const int32_t *__restrict__ coff,
+                            CmTotals T, const uint32_t *__restrict__ boffs, const uint32_t *__restrict__ boffb,
+                            const uint32_t *__restrict__ nits, const uint32_t *__restrict__ ioffs,
+                            const uint32_t *__restrict__ nit, const uint32_t *__restrict__ ioff,
+                            uint32_t *__restrict__ boff, uint2 *__restrict__ items_s, uint2 *__restrict__ item,
+                            uint32_t *__restrict__ ok, uint32_t *__restrict__ nref_fast,
+                            uint32_t *__restrict__ nch_slow) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nr = min(int64_t(*T.nrec), T.cap_rec);
+    const bool fit = cm_fit(T, nr);
+    if (c == 0) {
+        const bool all = fit && *T.maxn <= uint32_t(kBigMaxN);
         *ok = fit ? 1u : 0u;
         *nref_fast = all ? uint32_t(nr) : 0u;
-        *nch_slow = all ? 0u : *nchunks;
+        *nch_slow = all ? 0u : *T.nchunks;
     }
-}
-
-// run offsets: the clusters of at most one panel first, then the others
-__global__ void k_cm_off(int64_t ncb, const uint32_t *__restrict__ dncl, const int32_t *__restrict__ coff,
-                         const uint32_t *__restrict__ boffs, const uint32_t *__restrict__ boffb,
-                         const uint32_t *__restrict__ nps, uint32_t *__restrict__ boff) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= dev_count(ncb, dncl)) return;
+    if (!fit || c >= dev_count(ncb, dncl)) return;
     const int n = coff[c + 1] - coff[c];
-    boff[c] = n <= kPanel ? boffs[c] : *nps + boffb[c];
-}
-
-__global__ void k_cm_items(int64_t ncb, const uint32_t *__restrict__ dncl, const uint32_t *__restrict__ nits,
-                           const uint32_t *__restrict__ ioffs, const uint32_t *__restrict__ nit,
-                           const uint32_t *__restrict__ ioff, const uint32_t *__restrict__ ok,
-                           uint2 *__restrict__ items_s, uint2 *__restrict__ item) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (*ok == 0 || c >= dev_count(ncb, dncl)) return;
+    boff[c] = n <= kPanel ? boffs[c] : *T.nps + boffb[c];
     for (uint32_t i = 0; i < nits[c]; ++i) items_s[ioffs[c] + i] = make_uint2(uint32_t(c), i * 64u);
     for (uint32_t i = 0; i < nit[c]; ++i) item[ioff[c] + i] = make_uint2(uint32_t(c), i * kBigB);
 }
 
-// the query and result slot of every pair: one thread per refine record
+// the query and result slot of every pair: one thread per (refine record,
+// list slot)
 __global__ void k_cm_fill(const uint2 *__restrict__ rec, const unsigned long long *__restrict__ nrec, int64_t cap,
                           const uint32_t *__restrict__ rrank, const uint32_t *__restrict__ roff,
                           const uint32_t *__restrict__ rchunk_off, const int4 *__restrict__ lists,
                           const uint32_t *__restrict__ cbase, const uint32_t *__restrict__ boff,
                           const uint32_t *__restrict__ ok, int64_t cap_ref, uint32_t *__restrict__ bq,
                           uint32_t *__restrict__ bdst) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t nr = min(int64_t(*nrec), cap);
-    if (*ok == 0 || i >= nr) return;
-    const uint2 r = rec[i];
-    const uint32_t p = rrank[i];
-    const uint32_t rp = roff[r.x] + p;   // position in the refine order
-    const int4 *L = lists + size_t(r.x) * kListStride;
-    const uint32_t *cb = cbase + size_t(rchunk_off[r.x]) * kBigStride;
-    const int nsel = L[0].x;
-    for (int s = 0; s < nsel; ++s) {
+    if (*ok == 0) return;
+    const uint32_t nr = uint32_t(min(int64_t(*nrec), cap));
+    const uint32_t total = nr * uint32_t(kBigStride);
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+        const uint32_t i = idx / kBigStride, s = idx - i * kBigStride;
+        const uint2 r = rec[i];
+        const int4 *L = lists + size_t(r.x) * kListStride;
+        if (int(s) >= L[0].x) continue;
         const int4 d = L[1 + s];
         if (!cm_cluster(d.z)) continue;
-        const uint32_t pos = boff[d.x] + cb[s] + p;
+        const uint32_t p = rrank[i];
+        const uint32_t pos = boff[d.x] + cbase[size_t(rchunk_off[r.x]) * kBigStride + s] + p;
         bq[pos] = r.y;
-        bdst[pos] = uint32_t(int64_t(s) * cap_ref + rp);
+        bdst[pos] = uint32_t(int64_t(s) * cap_ref + roff[r.x] + p);
     }
 }
 
@@ -1367,11 +1373,12 @@ __device__ __forceinline__ double w64_panel_at(const double *__restrict__ W, int
 // fixed order.  Product: wavefront v takes the 16-row tiles v, v + 4, ...;
 // per tile the k-steps of four columns accumulate on MFMA (A = W tile from
 // memory, B = kernel values from LDS) in four independent accumulators,
-// whose sum is squared into the lane's query (column) sum.
+// whose sum is squared into the lane's query (column) sum; the factor loads
+// of 16 k-steps are in flight at a time.
 // MFMA lane layout (lane l, lr = l % 16, lg = l / 16): A[m][k] lane m + 16 k,
 // B[k][n] lane n + 16 k, D[m][n] lane n + 16 (m / 4), element m % 4.
 template <int KERN>
-__global__ __launch_bounds__(kBigT) void k_cm_big(const float *__restrict__ q, const uint2 *__restrict__ items,
+__global__ __launch_bounds__(kBigT, 4) void k_cm_big(const float *__restrict__ q, const uint2 *__restrict__ items,
                                                   const uint32_t *__restrict__ nitems,
                                                   const uint32_t *__restrict__ bcnt,
                                                   const uint32_t *__restrict__ boff, const uint32_t *__restrict__ bq,
@@ -1504,10 +1511,26 @@ __global__ __launch_bounds__(kBigT) void k_cm_big(const float *__restrict__ q, c
         for (int v = 1; v < 4; ++v)
             if (pbest[v][t] < best || (pbest[v][t] == best && pidx[v][t] < bidx)) { best = pbest[v][t]; bidx = pidx[v][t]; }
         const double ss = ((pss[0][t] + pss[1][t]) + pss[2][t]) + pss[3][t];
-        const PairRaw<double> r{sm[0], sm[1], sm[2], sm[3], ss, 0.f, sm[4], 0.f};
-        res[bdst[pos0 + uint32_t(t)]] = big_out<KERN>(r, n, C, best, bidx);
+        // the raw sums; k_cm_revert reverts them (o, grad o, |W k|^2 in u, c)
+        res[bdst[pos0 + uint32_t(t)]] = BigOut{0.0, 0.0, sm[1], sm[2], sm[3], sm[0], ss, sm[4], best, bidx, n, 0};
     }
     __syncthreads();  // kb and the partial sums are rewritten by the next item
+    }
+}
+
+// the pairs of the larger clusters: the raw sums the item kernel stored (o,
+// grad o, |W k|^2 in u, c) reverted in place, one lane per pair
+template <int KERN>
+__global__ __launch_bounds__(64) void k_cm_revert(const uint32_t *__restrict__ nps, const uint32_t *__restrict__ npb,
+                                                  const uint32_t *__restrict__ bdst, QueryConsts C,
+                                                  const uint32_t *__restrict__ ok, BigOut *__restrict__ res) {
+    if (uniform(*ro(ok)) == 0) return;
+    const uint32_t s0 = *ro(nps), nb = *ro(npb);
+    for (uint32_t i = blockIdx.x * 64u + threadIdx.x; i < nb; i += gridDim.x * 64u) {
+        BigOut *b = res + bdst[s0 + i];
+        const BigOut raw = *b;
+        const PairRaw<double> r{raw.o, raw.gx, raw.gy, raw.gz, raw.u, 0.f, raw.c, 0.f};
+        *b = big_out<KERN>(r, raw.n, C, raw.best, raw.bidx);
     }
 }
 
@@ -2323,37 +2346,39 @@ gpdf_status build_bf16(gpdf_ctx *c) {
     return GPDF_OK;
 }
 
+// the cluster bound of the cluster-major pass (the device count is the exact one)
+static int64_t cm_cluster_bound(const gpdf_ctx *c, const Model &M) {
+    return std::max<int64_t>(M.host_counts ? M.nclusters : c->p.max_clusters, 1);
+}
+
 // The cluster-major FP64 pass over the refine records and chunk table just
 // built: pair counts per cluster, run offsets (clusters of at most one panel
-// first), the items of both size classes, each pair's query and result slot,
-// then the two evaluation kernels.  Returns the view the combination reads.
+// first), the items of both size classes, each pair's query and result
+// slot, then the evaluation kernels.  bcnt is cleared by the caller.
 static BigView refine_cm(gpdf_ctx *c, const Model &M, hipStream_t s, const float *d_q, const int4 *lists,
-                         const ModelView &Mo, const QueryConsts &C, int64_t nc, const uint32_t *dnc, int64_t m,
-                         bool want_prop) {
+                         const ModelView &Mo, const QueryConsts &C, int64_t m, bool want_prop) {
     uint32_t *cnt = c->d_cnt;
-    // cluster bound (the device count dncl is the exact one)
-    const int64_t ncl = std::max<int64_t>(M.host_counts ? M.nclusters : c->p.max_clusters, 1);
+    const int64_t ncl = cm_cluster_bound(c, M);
     const uint32_t *dncl = cnt + CNT_CL;
     const unsigned long long *nrec = c->d_stat + ST_REFINE;
-    fill_u32(c->d_bcnt, 0u, ncl, s);
-    hipLaunchKernelGGL(k_cm_count, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rcnt, c->d_rchunk_off,
-                       cnt + CNT_RCHUNKS, c->cap_bchunks, lists, c->d_bcnt, c->d_bbase);
+    hipLaunchKernelGGL(k_cm_count, dim3(1024), dim3(kQT), 0, s, c->d_rchunk, cnt + CNT_RCHUNKS, c->cap_bchunks,
+                       c->d_rcnt, lists, c->d_bcnt, c->d_bbase);
     hipLaunchKernelGGL(k_cm_split, dim3(blocks_for(ncl)), dim3(kQT), 0, s, ncl, dncl, c->d_coff, c->d_bcnt,
                        c->d_bcs, c->d_bcb, c->d_bnits, c->d_bnit);
-    exclusive_scan_u32(c->d_bnits, c->d_bioffs, ncl, c->d_part, s, dncl, cnt + CNT_BITEMS_S);
-    exclusive_scan_u32(c->d_bcs, c->d_boffs, ncl, c->d_part, s, dncl, cnt + CNT_BPAIRS_S);
-    exclusive_scan_u32(c->d_bcb, c->d_boffb, ncl, c->d_part, s, dncl, cnt + CNT_BPAIRS_B);
-    exclusive_scan_u32(c->d_bnit, c->d_bioff, ncl, c->d_part, s, dncl, cnt + CNT_BITEMS);
-    hipLaunchKernelGGL(k_cm_check, dim3(1), dim3(64), 0, s, cnt + CNT_RCHUNKS, c->cap_bchunks, cnt + CNT_BPAIRS_S,
-                       cnt + CNT_BPAIRS_B, c->cap_bpairs, cnt + CNT_MAXN, nrec, m, c->cap_bref, cnt + CNT_BIGOK,
-                       cnt + CNT_NREF_FAST, cnt + CNT_RCH_SLOW);
-    hipLaunchKernelGGL(k_cm_off, dim3(blocks_for(ncl)), dim3(kQT), 0, s, ncl, dncl, c->d_coff, c->d_boffs,
-                       c->d_boffb, cnt + CNT_BPAIRS_S, c->d_boff);
-    hipLaunchKernelGGL(k_cm_items, dim3(blocks_for(ncl)), dim3(kQT), 0, s, ncl, dncl, c->d_bnits, c->d_bioffs,
-                       c->d_bnit, c->d_bioff, cnt + CNT_BIGOK, c->d_bitems, c->d_bitem);
-    hipLaunchKernelGGL(k_cm_fill, dim3(blocks_for(m)), dim3(kQT), 0, s, c->d_refine, nrec, m, c->d_rrank, c->d_roff,
-                       c->d_rchunk_off, lists, c->d_bbase, c->d_boff, cnt + CNT_BIGOK, c->cap_bref, c->d_bq,
-                       c->d_bdst);
+    ScanList SL;
+    SL.add(c->d_bcs, c->d_boffs, cnt + CNT_BPAIRS_S);
+    SL.add(c->d_bcb, c->d_boffb, cnt + CNT_BPAIRS_B);
+    SL.add(c->d_bnits, c->d_bioffs, cnt + CNT_BITEMS_S);
+    SL.add(c->d_bnit, c->d_bioff, cnt + CNT_BITEMS);
+    exclusive_scan_u32_multi(SL, ncl, c->d_part, s, dncl);
+    const CmTotals T{cnt + CNT_RCHUNKS, cnt + CNT_BPAIRS_S, cnt + CNT_BPAIRS_B, cnt + CNT_MAXN, nrec,
+                     c->cap_bchunks, c->cap_bpairs, m, c->cap_bref};
+    hipLaunchKernelGGL(k_cm_finish, dim3(blocks_for(ncl)), dim3(kQT), 0, s, ncl, dncl, c->d_coff, T, c->d_boffs,
+                       c->d_boffb, c->d_bnits, c->d_bioffs, c->d_bnit, c->d_bioff, c->d_boff, c->d_bitems,
+                       c->d_bitem, cnt + CNT_BIGOK, cnt + CNT_NREF_FAST, cnt + CNT_RCH_SLOW);
+    hipLaunchKernelGGL(k_cm_fill, dim3(1024), dim3(kQT), 0, s, c->d_refine,
+                       nrec, m, c->d_rrank, c->d_roff, c->d_rchunk_off, lists, c->d_bbase, c->d_boff,
+                       cnt + CNT_BIGOK, c->cap_bref, c->d_bq, c->d_bdst);
     // kernel values of the largest cluster the large-cluster pass takes
     const int64_t nmax = M.host_counts ? std::min<int64_t>(std::max<int64_t>(M.max_n, 4), kBigMaxN) : kBigMaxN;
     const size_t lds = size_t((nmax + 3) & ~int64_t(3)) * kBigB * sizeof(double);
@@ -2363,8 +2388,10 @@ static BigView refine_cm(gpdf_ctx *c, const Model &M, hipStream_t s, const float
     do {                                                                                                        \
         hipLaunchKernelGGL((k_cm_small<K>), dim3(3072), dim3(64), 0, s, d_q, c->d_bitems, cnt + CNT_BITEMS_S,    \
                            c->d_bcnt, c->d_boff, c->d_bq, c->d_bdst, Mo, C, cnt + CNT_BIGOK, res);              \
-        hipLaunchKernelGGL((k_cm_big<K>), dim3(768), dim3(kBigT), lds, s, d_q, c->d_bitem, cnt + CNT_BITEMS,     \
+        hipLaunchKernelGGL((k_cm_big<K>), dim3(1024), dim3(kBigT), lds, s, d_q, c->d_bitem, cnt + CNT_BITEMS,    \
                            c->d_bcnt, c->d_boff, c->d_bq, c->d_bdst, Mo, C, cnt + CNT_BIGOK, res);              \
+        hipLaunchKernelGGL((k_cm_revert<K>), dim3(2048), dim3(64), 0, s, cnt + CNT_BPAIRS_S, cnt + CNT_BPAIRS_B, \
+                           c->d_bdst, C, cnt + CNT_BIGOK, res);                                                 \
     } while (0)
     if (want_prop) {
         if (kern == GPDF_KERNEL_MATERN32) GPDF_CM(GPDF_KERNEL_MATERN32 | kProp);
@@ -2561,14 +2588,26 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         // 3. queries whose FP32 estimate is too large: regroup by cell
         //    (counting sort of the records) and redo them in FP64
         stage_begin(c, GPDF_MS_REFINE);
-        fill_u32(c->d_rcnt, 0u, nc, s);
-        const unsigned rgrid = blocks_for(m);
+        // records (grid-stride over a bounded grid: they are a small share
+        // of the queries)
+        const unsigned rgrid = std::min<unsigned>(blocks_for(m), 1024u);
+        {
+            FillList F2;
+            F2.u32(c->d_rcnt, 0u, nc);
+            if (!knn) {
+                F2.u32(c->d_bcnt, 0u, cm_cluster_bound(c, M));
+                F2.u32(c->d_work, 0u, kWorkSlot);
+            }
+            if ((e = fill_multi(F2, s)) != hipSuccess) return hip_fail(c, e, "query: refine clear");
+        }
         hipLaunchKernelGGL(k_refine_count, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
                            c->d_stat + ST_REFINE, m, c->d_rcnt, c->d_rrank);
         hipLaunchKernelGGL(k_refine_chunks, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rcnt,
                            c->d_rchunks);
-        exclusive_scan_u32(c->d_rcnt, c->d_roff, nc, c->d_part, s, dnc);
-        exclusive_scan_u32(c->d_rchunks, c->d_rchunk_off, nc, c->d_part, s, dnc, cnt + CNT_RCHUNKS);
+        ScanList RL;
+        RL.add(c->d_rcnt, c->d_roff, nullptr);
+        RL.add(c->d_rchunks, c->d_rchunk_off, cnt + CNT_RCHUNKS);
+        exclusive_scan_u32_multi(RL, nc, c->d_part, s, dnc);
         hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rchunks,
                            c->d_rchunk_off, c->d_rchunk);
         hipLaunchKernelGGL(k_refine_scatter, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,
@@ -2579,10 +2618,11 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         if (knn) {
             launch_query_k<double>(c, kern, knn, grid, s, d_q, R, lists, Mo, C, O64, 1);
         } else {
-            // cluster-major evaluation of the pairs, then their combination
-            // (persistent); the FP64 query kernel (persistent) takes the
-            // chunks instead when the pass could not take every pair
-            const BigView BV = refine_cm(c, M, s, d_q, lists, Mo, C, nc, dnc, m, want_prop);
+            // cluster-major evaluation of the pairs, then their combination;
+            // the FP64 query kernel (persistent, on the evaluation's counter
+            // slot, cleared above) takes the chunks instead when the pass
+            // could not take every pair
+            const BigView BV = refine_cm(c, M, s, d_q, lists, Mo, C, m, want_prop);
             // grid-stride launches: the items are of even size, and one
             // shared work counter would serialise on its atomics
             const unsigned rg = unsigned(std::min<int64_t>(2048, (m + 63) / 64));
@@ -2599,11 +2639,8 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
                 GPDF_CMB(GPDF_KERNEL_SE);
             }
 #undef GPDF_CMB
-            // the evaluation's slot: its launch has finished
-            uint32_t *work2 = c->d_work;
-            fill_u32(work2, 0u, kWorkSlot, s);
-            if (want_prop) launch_query_kf<double, kProp>(kern, false, 1024, s, d_q, Rs, lists, Mo, C, O64, work2);
-            else launch_query_kf<double, 0>(kern, false, 1024, s, d_q, Rs, lists, Mo, C, O64, work2);
+            if (want_prop) launch_query_kf<double, kProp>(kern, false, 1024, s, d_q, Rs, lists, Mo, C, O64, c->d_work);
+            else launch_query_kf<double, 0>(kern, false, 1024, s, d_q, Rs, lists, Mo, C, O64, c->d_work);
         }
         stage_end(c, GPDF_MS_REFINE);
     }

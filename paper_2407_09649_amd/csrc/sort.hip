@@ -128,13 +128,10 @@ constexpr int64_t kScan1Max = 4 * kScan1Tile;
 
 __device__ __forceinline__ int scan1_pad(int j) { return j + j / kScan1Items; }
 
-__global__ __launch_bounds__(kScan1Threads) void k_scan_single(const uint32_t *__restrict__ in,
-                                                               uint32_t *__restrict__ out, int64_t nb_,
-                                                               const uint32_t *__restrict__ dn,
-                                                               uint32_t *__restrict__ total_out) {
+__device__ __forceinline__ void scan_single(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                            int64_t n, uint32_t *__restrict__ total_out) {
     __shared__ uint32_t lds[kScan1Threads / 64];
     __shared__ uint32_t buf[kScan1Tile + kScan1Tile / kScan1Items];
-    const int64_t n = scan_count(nb_, dn);
     const int t = int(threadIdx.x);
     uint32_t carry = 0;
     // the next tile's loads are issued before the current tile is scanned
@@ -181,6 +178,20 @@ __global__ __launch_bounds__(kScan1Threads) void k_scan_single(const uint32_t *_
         out[n] = carry;
         if (total_out) *total_out = carry;
     }
+}
+
+__global__ __launch_bounds__(kScan1Threads) void k_scan_single(const uint32_t *__restrict__ in,
+                                                               uint32_t *__restrict__ out, int64_t nb_,
+                                                               const uint32_t *__restrict__ dn,
+                                                               uint32_t *__restrict__ total_out) {
+    scan_single(in, out, scan_count(nb_, dn), total_out);
+}
+
+// several independent scans of one length, one block each
+__global__ __launch_bounds__(kScan1Threads) void k_scan_multi(ScanList L, int64_t nb_,
+                                                              const uint32_t *__restrict__ dn) {
+    const int k = int(blockIdx.x);
+    scan_single(L.in[k], L.out[k], scan_count(nb_, dn), L.total[k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -311,6 +322,15 @@ void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s, partials, nb);
     hipLaunchKernelGGL(k_scan_down, dim3(unsigned(nb)), dim3(kScanThreads), 0, s, in, out, n, dn,
                        partials, total_out);
+}
+
+void exclusive_scan_u32_multi(const ScanList &L, int64_t n, uint32_t *partials, hipStream_t s,
+                              const uint32_t *dn) {
+    if (n <= kScan1Max) {
+        hipLaunchKernelGGL(k_scan_multi, dim3(unsigned(L.count)), dim3(kScan1Threads), 0, s, L, n, dn);
+        return;
+    }
+    for (int k = 0; k < L.count; ++k) exclusive_scan_u32(L.in[k], L.out[k], n, partials, s, dn, L.total[k]);
 }
 
 // Stable sort by key over the 8-bit digits that contain varying bits; the
