@@ -601,13 +601,15 @@ __device__ __forceinline__ void diag_cols(const float4 *__restrict__ P, const do
 }
 
 // FP32 diagonal block, two columns per batch of scalar loads; the second
-// column of the last pair may lie past the cluster and is then masked
+// column of the last pair may lie past the cluster and is then masked.  The
+// kernel values go to the lane's column of kc (stride 64), which the next
+// panel reads instead of recomputing them.
 template <int KERN, int J>
 __device__ __forceinline__ void diag_pairs_f32(const float4 *__restrict__ P, const float *__restrict__ B,
                                                const float *__restrict__ D,
                                                int nrem, int pbase, const QueryPoint &Q,
                                                const QueryConsts &C, PairRaw<float> &r, Acc<float> &A,
-                                               float *t) {
+                                               float *t, float *kc) {
     if constexpr (J < kPanel) {
         if (J >= nrem) return;
         const float4 p0 = ro(P)[J], p1 = ro(P)[J + 1];
@@ -624,14 +626,18 @@ __device__ __forceinline__ void diag_pairs_f32(const float4 *__restrict__ P, con
         const float k1 = point_eval<float, KERN>(p1, p1.w, Q, pbase + J + 1, C, r, A, live, b1);
 #pragma unroll
         for (int i = 0; i < kPanel - J - 1; ++i) t[J + 1 + i] = live ? fmaf(b[i], k1, t[J + 1 + i]) : t[J + 1 + i];
-        diag_pairs_f32<KERN, J + 2>(P, B, D, nrem, pbase, Q, C, r, A, t);
+        kc[J * 64] = k0;
+        kc[(J + 1) * 64] = k1;
+        diag_pairs_f32<KERN, J + 2>(P, B, D, nrem, pbase, Q, C, r, A, t, kc);
     }
 }
 
 // n > 32: W in 32-row panels (column-major inside).  Panel r needs k_j for
 // every column j < 32 (r + 1): the columns left of its diagonal block belong
 // to points summed in earlier panels and only their kernel values are
-// recomputed; the diagonal block sums its own points.
+// needed; the diagonal block sums its own points.  In FP32 the kernel values
+// of the previous panel's diagonal block come from an LDS cache (8 KB per
+// wavefront), the earlier ones are recomputed; in FP64 all are recomputed.
 template <typename T, int KERN>
 __device__ __forceinline__ void eval_panels(const float4 *__restrict__ P, const double *__restrict__ a64,
                                             const float *__restrict__ B, const double *__restrict__ b64,
@@ -639,23 +645,38 @@ __device__ __forceinline__ void eval_panels(const float4 *__restrict__ P, const 
                                             const QueryPoint &Q, const QueryConsts &C, PairRaw<T> &r,
                                             Acc<T> &A) {
     const T *Pn = W;
+    // FP32: the kernel values of the previous panel's diagonal block, one
+    // column of 32 per lane (column-major over the lanes, conflict-free)
+    [[maybe_unused]] float *kc = nullptr;
+    if constexpr (std::is_same<T, float>::value) {
+        __shared__ float kcache[kPanel * 64];
+        kc = kcache + (threadIdx.x & 63);
+    }
     for (int c0 = 0; c0 < n; c0 += kPanel) {
         T t[kPanel];
 #pragma unroll
         for (int q = 0; q < kPanel; ++q) t[q] = T(0);
         if constexpr (std::is_same<T, float>::value) {
-            // c0 is a multiple of the panel height: columns go in pairs
+            // c0 is a multiple of the panel height: columns go in pairs; the
+            // last panel's columns come from the cache, the earlier ones are
+            // recomputed
             for (int j = 0; j < c0; j += 2) {
                 const float4 p0 = ro(P)[j], p1 = ro(P)[j + 1];
                 float a[kPanel], b[kPanel];
 #pragma unroll
                 for (int i = 0; i < kPanel; ++i) { a[i] = ro(Pn)[j * kPanel + i]; b[i] = ro(Pn)[(j + 1) * kPanel + i]; }
-                const float k0 = point_k<float, KERN>(p0, Q, C);
-                const float k1 = point_k<float, KERN>(p1, Q, C);
+                float k0, k1;
+                if (j >= c0 - kPanel) {
+                    k0 = kc[(j - (c0 - kPanel)) * 64];
+                    k1 = kc[(j + 1 - (c0 - kPanel)) * 64];
+                } else {
+                    k0 = point_k<float, KERN>(p0, Q, C);
+                    k1 = point_k<float, KERN>(p1, Q, C);
+                }
                 panel_update<float, 0>(t, a, k0, std::make_integer_sequence<int, kPanel>{});
                 panel_update<float, 0>(t, b, k1, std::make_integer_sequence<int, kPanel>{});
             }
-            diag_pairs_f32<KERN, 0>(P + c0, B + c0, Pn + c0 * kPanel, n - c0, pbase + c0, Q, C, r, A, t);
+            diag_pairs_f32<KERN, 0>(P + c0, B + c0, Pn + c0 * kPanel, n - c0, pbase + c0, Q, C, r, A, t, kc);
         } else {
             for (int j = 0; j < c0; ++j) {
                 const T kj = point_k<T, KERN>(ro(P)[j], Q, C);
