@@ -626,8 +626,10 @@ __device__ __forceinline__ void diag_pairs_f32(const float4 *__restrict__ P, con
         const float k1 = point_eval<float, KERN>(p1, p1.w, Q, pbase + J + 1, C, r, A, live, b1);
 #pragma unroll
         for (int i = 0; i < kPanel - J - 1; ++i) t[J + 1 + i] = live ? fmaf(b[i], k1, t[J + 1 + i]) : t[J + 1 + i];
-        kc[J * 64] = k0;
-        kc[(J + 1) * 64] = k1;
+        if (kc) {
+            kc[J * 64] = k0;
+            kc[(J + 1) * 64] = k1;
+        }
         diag_pairs_f32<KERN, J + 2>(P, B, D, nrem, pbase, Q, C, r, A, t, kc);
     }
 }
@@ -635,23 +637,17 @@ __device__ __forceinline__ void diag_pairs_f32(const float4 *__restrict__ P, con
 // n > 32: W in 32-row panels (column-major inside).  Panel r needs k_j for
 // every column j < 32 (r + 1): the columns left of its diagonal block belong
 // to points summed in earlier panels and only their kernel values are
-// needed; the diagonal block sums its own points.  In FP32 the kernel values
-// of the previous panel's diagonal block come from an LDS cache (8 KB per
-// wavefront), the earlier ones are recomputed; in FP64 all are recomputed.
+// needed; the diagonal block sums its own points.  Given kc (the FP32 query
+// kernel: the lane's column of an 8 KB LDS array per wavefront), the kernel
+// values of the previous panel's diagonal block are kept there and the
+// earlier ones recomputed; otherwise all are recomputed.
 template <typename T, int KERN>
 __device__ __forceinline__ void eval_panels(const float4 *__restrict__ P, const double *__restrict__ a64,
                                             const float *__restrict__ B, const double *__restrict__ b64,
                                             const T *__restrict__ W, int n, int pbase,
                                             const QueryPoint &Q, const QueryConsts &C, PairRaw<T> &r,
-                                            Acc<T> &A) {
+                                            Acc<T> &A, float *kc) {
     const T *Pn = W;
-    // FP32: the kernel values of the previous panel's diagonal block, one
-    // column of 32 per lane (column-major over the lanes, conflict-free)
-    [[maybe_unused]] float *kc = nullptr;
-    if constexpr (std::is_same<T, float>::value) {
-        __shared__ float kcache[kPanel * 64];
-        kc = kcache + (threadIdx.x & 63);
-    }
     for (int c0 = 0; c0 < n; c0 += kPanel) {
         T t[kPanel];
 #pragma unroll
@@ -666,7 +662,7 @@ __device__ __forceinline__ void eval_panels(const float4 *__restrict__ P, const 
 #pragma unroll
                 for (int i = 0; i < kPanel; ++i) { a[i] = ro(Pn)[j * kPanel + i]; b[i] = ro(Pn)[(j + 1) * kPanel + i]; }
                 float k0, k1;
-                if (j >= c0 - kPanel) {
+                if (kc && j >= c0 - kPanel) {
                     k0 = kc[(j - (c0 - kPanel)) * 64];
                     k1 = kc[(j + 1 - (c0 - kPanel)) * 64];
                 } else {
@@ -1007,7 +1003,7 @@ __device__ __forceinline__ void eval_cluster(int base, int n, int64_t woff, cons
                                              const double *__restrict__ beta64,
                                              const float *__restrict__ W32,
                                              const double *__restrict__ W64, const QueryPoint &Q,
-                                             const QueryConsts &C, Acc<T> &A) {
+                                             const QueryConsts &C, Acc<T> &A, float *kc = nullptr) {
     const float4 *P = pts + base;
     const double *a64 = alpha64 + base;
     const float *B = beta32 + base;
@@ -1017,7 +1013,7 @@ __device__ __forceinline__ void eval_cluster(int base, int n, int64_t woff, cons
     if (n <= 8) eval_small<T, KERN, 8>(P, a64, B, b64, W, n, base, Q, C, r, A);
     else if (n <= 16) eval_small<T, KERN, 16>(P, a64, B, b64, W, n, base, Q, C, r, A);
     else if (n <= kPanel) eval_small<T, KERN, kPanel>(P, a64, B, b64, W, n, base, Q, C, r, A);
-    else eval_panels<T, KERN>(P, a64, B, b64, W, n, base, Q, C, r, A);
+    else eval_panels<T, KERN>(P, a64, B, b64, W, n, base, Q, C, r, A, kc);
     finish_pair<T, KERN>(r, n, C, A);
 }
 
@@ -1066,6 +1062,13 @@ __device__ __forceinline__ void cells_chunk(uint32_t wave, const float *__restri
     const int nsel = int(uniform(uint32_t(L[0].x)));
     Acc<T> A;
     acc_init(A);
+    // FP32: the kernel values of the previous panel (clusters above one
+    // panel), one column of 32 per lane, column-major over the lanes
+    [[maybe_unused]] float *kc = nullptr;
+    if constexpr (std::is_same<T, float>::value) {
+        __shared__ float kcache[kPanel * 64];
+        kc = kcache + lane;
+    }
     uint32_t sum_n = 0, sum_tri = 0;
     int4 nxt = L[1];
     for (int s = 0; s < nsel; ++s) {
@@ -1073,7 +1076,8 @@ __device__ __forceinline__ void cells_chunk(uint32_t wave, const float *__restri
         if (s + 1 < nsel) nxt = L[2 + s];
         const int base = int(uniform(uint32_t(d.y))), n = int(uniform(uint32_t(d.z)));
         const int64_t woff = int64_t(uniform(uint32_t(d.w)));
-        eval_cluster<T, KERN>(base, n, woff, Mo.pts, Mo.alpha64, Mo.beta32, Mo.beta64, Mo.W32, Mo.W64, Q, C, A);
+        eval_cluster<T, KERN>(base, n, woff, Mo.pts, Mo.alpha64, Mo.beta32, Mo.beta64, Mo.W32, Mo.W64, Q, C, A,
+                              kc);
         sum_n += uint32_t(n);
         sum_tri += uint32_t(n * (n + 1) / 2);
     }
