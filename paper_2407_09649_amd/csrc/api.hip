@@ -171,7 +171,7 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
               dalloc(c->d_wsz, C + 1, e) && dalloc(c->d_asz, C + 1, e) && dalloc(c->d_wo32, C + 1, e) &&
               dalloc(c->d_ao32, C + 1, e) &&
               dalloc(c->d_pts, P + kPtsPad, e) && dalloc(c->d_alpha64, P, e) && dalloc(c->d_ckey, C + 1, e) &&
-              dalloc(c->d_coff, C + 1, e) && dalloc(c->d_pd, C + 1, e) && dalloc(c->d_woff, C, e) && dalloc(c->d_blist, 4 * C, e) &&
+              dalloc(c->d_coff, C + 1, e) && dalloc(c->d_pd, C + 1, e) && dalloc(c->d_woff, C, e) && dalloc(c->d_blist, int64_t(kBuckets) * C, e) &&
               dalloc(c->d_need, C + 8, e) && dalloc(c->d_trained, C + 8, e) &&
               dalloc(c->d_aoff, C, e) && dalloc(c->d_W32, c->cap_w + kW32Pad, e) &&
               dalloc(c->d_W64, c->cap_w, e) &&

@@ -217,9 +217,12 @@ enum DevCount : int {
     CNT_VALID,    // finite points
     CNT_PTS,      // training points (unique voxels or valid points)
     CNT_CL,       // clusters
-    CNT_TINY,     // size buckets: n <= 8, n <= 64, n <= 256, larger
-    CNT_WAVE,
-    CNT_BIG,
+    CNT_TINY,     // size buckets: n <= 8, n <= 64, then by 16-row tiles T:
+    CNT_WAVE,     // T <= 6, T <= 8, T <= 12, T <= 16 (n <= 256), larger
+    CNT_BIG6,
+    CNT_BIG8,
+    CNT_BIG12,
+    CNT_BIG16,
     CNT_HUGE,
     CNT_WTOT,     // factor elements
     CNT_ATOT,     // FP64 workspace elements
@@ -298,6 +301,7 @@ constexpr int kXcds = 8;
 constexpr int kCtrStride = 32;                     // u32 per counter line
 constexpr int kWorkSlot = kXcds * kCtrStride;
 constexpr int kWorkSlots = 4;
+constexpr int kBuckets = CNT_HUGE - CNT_TINY + 1;  // training size buckets (lists of C clusters each)
 
 constexpr int kSpread = 64;
 constexpr int kSpreadStride = 16 * ((ST_COUNT + 15) / 16);

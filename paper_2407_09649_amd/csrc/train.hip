@@ -454,9 +454,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kTb = 16;                                  // tile edge
 constexpr int kTileElems = kTb * kTb;                    // 2 KB of FP64
 constexpr int kMfmaMaxN = 256;                           // largest cluster of this trainer
-constexpr int kMfmaLdsT = 12;                            // tiles per edge held in LDS (n <= 192)
-constexpr int kMfmaLdsTiles = kMfmaLdsT * (kMfmaLdsT + 1) / 2;
-constexpr int kMfmaT = 512;                              // workgroup
+constexpr int kMfmaLdsT = 12;                            // tiles per edge held in LDS at most (n <= 192)
 __host__ __device__ inline int mfma_tiles(int n) { return (n + kTb - 1) / kTb; }
 // FP64 workspace of a cluster: its lower tiles
 __host__ __device__ inline int64_t mfma_ws(int n) {
@@ -504,68 +502,54 @@ __device__ __forceinline__ double bcast(double v, int lane) {
                                           uint64_t(uint32_t(__builtin_amdgcn_readlane(int(__builtin_bit_cast(uint64_t, v)), lane))));
 }
 
-// Cholesky and inverse of the diagonal tile D (one wavefront).  Lane l holds
-// column c = l % 16 of rows g, g + 4, g + 8, g + 12 (g = l / 16) of A (then
-// L) and of R (then V = L^{-1}).  Step k: the pivot by readlane; column k of
-// L and row k of V go through LDS (colb, rowb), written and read by the same
-// wavefront in program order; then
-//   A(r, c) -= L(r, k) L(c, k)  (k < c <= r),   R(r, c) -= L(r, k) V(k, c)  (c <= k < r).
-// Writes V over D (zero above the diagonal): L_pp itself is not read again;
+// Cholesky and inverse of the diagonal tile D (one wavefront).  Lane c
+// (c = lane % 16; the four groups of 16 lanes repeat the same work) holds
+// column c of A in registers, which is also row c as A is symmetric, and
+// column c of R = I, which becomes V = L^{-1}.  Step k broadcasts the
+// pivot A(k, k) and the column A(r, k), r > k, from lane k by readlane; with
+// L(k, k) = sqrt(A(k, k)) and L(r, k) = A(r, k) / L(k, k):
+//   V(k, c) = R(k, c) / L(k, k),
+//   A(r, c) -= A(r, k) A(k, c) / A(k, k),   R(r, c) -= L(r, k) V(k, c)   (r > k).
+// No LDS and no branch: the columns c <= k of A are finished and take
+// updates nobody reads, and R(k, c) = 0 for c > k keeps V(k, c) = 0 there.
+// Writes V over D (zero above the diagonal): L_pp itself is not needed;
 // false if a pivot is not above thr.
-__device__ bool diag_factor(double *D, double *colb, double *rowb, double thr, int lane) {
-    const int g = lane >> 4, c = lane & 15;
-    double a[4], w[4];
+__device__ __forceinline__ bool diag_factor(double *D, double thr, int lane) {
+    const int c = lane & 15;
+    double a[kTb], w[kTb];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int r = g + 4 * e;
-        a[e] = D[tel(r, c)];
-        w[e] = r == c ? 1.0 : 0.0;
+    for (int r = 0; r < kTb; ++r) {
+        a[r] = D[tel(r, c)];
+        w[r] = r == c ? 1.0 : 0.0;
     }
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < kTb; ++k) {
-        const double piv = bcast(a[k >> 2], k + 16 * (k & 3));   // A(k, k)
+        const double piv = bcast(a[k], k);
         ok = ok && piv > thr;
         // 1 / sqrt(pivot): the hardware estimate and two Newton steps
-        // y <- y (3 - x y^2) / 2, each doubling the correct bits; l = x y
+        // y <- y (3 - x y^2) / 2, each doubling the correct bits
         const double x = ok ? piv : 1.0;
         double inv = __builtin_amdgcn_rsq(x);
         inv = inv * fma(-0.5 * x * inv, inv, 1.5);
         inv = inv * fma(-0.5 * x * inv, inv, 1.5);
-        const double lkk = x * inv;
+        const double t = a[k] * (inv * inv);   // A(k, c) / A(k, k)
+        const double v = w[k] * inv;           // V(k, c)
+        w[k] = v;
+        const double vi = v * inv;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int r = g + 4 * e;
-            if (c == k) {
-                a[e] = r > k ? a[e] * inv : (r == k ? lkk : a[e]);
-                if (r >= k) colb[r] = a[e];          // L(r, k)
-            }
-            if (r == k) {
-                if (c <= k) w[e] *= inv;             // V(k, c); zero right of k
-                rowb[c] = w[e];
-            }
+        for (int r = k + 1; r < kTb; ++r) {
+            const double ark = bcast(a[r], k);  // read before this step's update of a[r]
+            w[r] = fma(-ark, vi, w[r]);
+            a[r] = fma(-ark, t, a[r]);
+            // the update of R stays here: nothing else depends on it before
+            // the store, and sunk there it would hold every broadcast value
+            asm volatile("" : "+v"(w[r]));
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const double lck = colb[c], vkc = rowb[c];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int r = g + 4 * e;
-            if (r > k) {
-                const double lrk = colb[r];
-                if (c > k && c <= r) a[e] -= lrk * lck;
-                if (c <= k) w[e] -= lrk * vkc;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    if (lane < kTb) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int r = g + 4 * e;
-        D[tel(r, c)] = c <= r ? w[e] : 0.0;
+        for (int r = 0; r < kTb; ++r) D[tel(r, c)] = c <= r ? w[r] : 0.0;
     }
     return ok;
 }
@@ -608,16 +592,22 @@ __device__ __forceinline__ void tile_xy2(const double *X1, const double *Y1, f64
     }
 }
 
-// the body, inlined once with the tiles in LDS and once in the workspace
-__device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *__restrict__ ybuf, double *dbuf,
+// the body of one cluster (NT threads), the tiles in LDS or in the workspace
+template <int NT>
+__device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *__restrict__ ybuf,
                                                 int *flag,
                                                 int c, int base, int n, float4 *__restrict__ pts,
                                                 const int64_t *__restrict__ woff, double *__restrict__ W64all,
                                                 float *__restrict__ W32all, double *__restrict__ alpha64,
                                                 uint8_t *__restrict__ pd, int kernel, double l, double s2,
                                                 unsigned long long *__restrict__ stat) {
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    constexpr int kW = kMfmaT / 64;
+    // the thread index passes through an empty asm once per cluster: every
+    // address derived from it is then formed inside the cluster's work, not
+    // hoisted out of the persistent loop and held in registers throughout
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int kW = NT / 64;
     const int T = mfma_tiles(n);
     // A = K + s^2 I, padded with the identity; a tile per wavefront, lane l
     // on column l % 16 of rows l / 16 + 4 e, the five point loads together
@@ -653,7 +643,7 @@ __device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *
     const double thr = 1e-10 * (1.0 + s2);
     // the diagonal tile of the next column is factored by wavefront 0 inside
     // the trailing update of the current one (its own update comes first)
-    if (wv == 0 && !diag_factor(A, dbuf, dbuf + kTb, thr, lane) && lane == 0) *flag = 0;
+    if (wv == 0 && !diag_factor(A, thr, lane) && lane == 0) *flag = 0;
     __syncthreads();
     for (int p = 0; p < T; ++p) {
         if (!*flag) break;
@@ -685,12 +675,12 @@ __device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *
             tile_xyt2(A + tlow(i1, p), A + tlow(j1, p), acc1, A + tlow(i2, p), A + tlow(j2, p), acc2, -1.0, lane);
             tile_put(Y1, acc1, lane);
             if (two) tile_put(Y2, acc2, lane);
-            if (t == 0 && !diag_factor(Y1, dbuf, dbuf + kTb, thr, lane) && lane == 0) *flag = 0;
+            if (t == 0 && !diag_factor(Y1, thr, lane) && lane == 0) *flag = 0;
         }
         __syncthreads();
     }
     if (!*flag) {
-        for (int i = tid; i < n; i += kMfmaT) {
+        for (int i = tid; i < n; i += NT) {
             alpha64[base + i] = 0.0;
             pts[base + i].w = 0.0f;
         }
@@ -738,7 +728,7 @@ __device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *
         __syncthreads();
     }
     // y = W 1, alpha = W^T y
-    for (int i = tid; i < n; i += kMfmaT) {
+    for (int i = tid; i < n; i += NT) {
         const int ti = i / kTb, rr = i - ti * kTb;
         double s0 = 0.0;
         for (int tj = 0; tj <= ti; ++tj) {
@@ -749,7 +739,7 @@ __device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *
         ybuf[i] = s0;
     }
     __syncthreads();
-    for (int j = tid; j < n; j += kMfmaT) {
+    for (int j = tid; j < n; j += NT) {
         const int tj = j / kTb, cc = j - tj * kTb;
         // rows at or above j in the diagonal tile and the padded rows
         // contribute zeros (W is lower triangular, its padding block I
@@ -777,7 +767,7 @@ __device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *
     for (int rp = 0; rp < nb; ++rp) {
         const int64_t po = w32_panel_offset(n, rp);
         const int ncol = min((rp + 1) * kPanel, n);
-        for (int idx = tid; idx < ncol * kPanel; idx += kMfmaT) {
+        for (int idx = tid; idx < ncol * kPanel; idx += NT) {
             const int jj = idx / kPanel, rr = idx - jj * kPanel;
             const int i = rp * kPanel + rr;
             double v = 0.0;
@@ -792,17 +782,22 @@ __device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *
     if (tid == 0) pd[c] = 1;
 }
 
-// persistent: each workgroup takes the next cluster of the bucket from the
-// counter *work (zero at launch) until none is left
-__global__ __launch_bounds__(kMfmaT) void k_train_mfma(
+// persistent: each workgroup takes the next cluster of its bucket from the
+// counter *work (zero at launch) until none is left.  LT > 0: the bucket's
+// clusters have at most LT tile rows and keep their tiles in LDS, sized for
+// LT, so that two or three small GPs share a CU; LT = 0: the tiles are in the
+// FP64 workspace and the LDS holds only y.  WPE, the wavefronts per SIMD
+// that the registers must allow, is the GPs per CU times NT / 256
+template <int LT, int NT, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_train_mfma(
     const int32_t *__restrict__ list, const uint32_t *__restrict__ dcnt, uint32_t *__restrict__ work,
     float4 *__restrict__ pts, const int32_t *__restrict__ coff, const int64_t *__restrict__ aoff,
     const int64_t *__restrict__ woff, double *__restrict__ Aall, double *__restrict__ W64all,
     float *__restrict__ W32all, double *__restrict__ alpha64, uint8_t *__restrict__ pd, int kernel, double l,
     double s2, unsigned long long *__restrict__ stat) {
-    __shared__ double sA[kMfmaLdsTiles * kTileElems];
-    __shared__ double ybuf[kMfmaMaxN];
-    __shared__ double dbuf[2 * kTb];
+    static_assert(LT <= kMfmaLdsT, "LDS tiles beyond the bucket bound");
+    __shared__ double sA[LT > 0 ? LT * (LT + 1) / 2 * kTileElems : 1];
+    __shared__ double ybuf[LT > 0 ? LT * kTb : kMfmaMaxN];
     __shared__ int flag;
     __shared__ uint32_t item;
     const uint32_t cnt = *dcnt;
@@ -815,12 +810,14 @@ __global__ __launch_bounds__(kMfmaT) void k_train_mfma(
         const int c = list[b];
         const int base = coff[c];
         const int n = coff[c + 1] - base;
-        if (mfma_tiles(n) <= kMfmaLdsT)
-            train_mfma_body(sA, ybuf, dbuf, &flag, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel, l,
-                            s2, stat);
-        else
-            train_mfma_body(Aall + aoff[c], ybuf, dbuf, &flag, c, base, n, pts, woff, W64all, W32all, alpha64,
-                            pd, kernel, l, s2, stat);
+        if constexpr (LT > 0) {
+            if (mfma_tiles(n) > LT) continue;  // not of this bucket (the plan never puts it here)
+            train_mfma_body<NT>(sA, ybuf, &flag, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel,
+                                l, s2, stat);
+        } else {
+            train_mfma_body<NT>(Aall + aoff[c], ybuf, &flag, c, base, n, pts, woff, W64all, W32all, alpha64,
+                                pd, kernel, l, s2, stat);
+        }
     }
 }
 
@@ -830,6 +827,27 @@ __global__ __launch_bounds__(kMfmaT) void k_train_mfma(
 // ---------------------------------------------------------------------------
 constexpr int kTinyN = 8;
 constexpr int kWaveN = 64;
+// the bucket of a cluster of n points, 0 .. kBuckets - 1: one lane (n <= 8),
+// one wavefront (n <= 64), the blocked trainer by tile rows T (T <= 6, 8, 12
+// with the tiles in LDS; T <= 16 in the workspace), one workgroup (larger)
+__device__ inline int size_bucket(int n) {
+    if (n <= kTinyN) return 0;
+    if (n <= kWaveN) return 1;
+    if (n > kMfmaMaxN) return 6;
+    const int T = mfma_tiles(n);
+    return T <= 6 ? 2 : T <= 8 ? 3 : T <= kMfmaLdsT ? 4 : 5;
+}
+static_assert(kBuckets == 7 && CNT_BIG6 - CNT_TINY == 2 && CNT_BIG16 - CNT_TINY == 5, "size buckets");
+// appends cluster c to list b (lists of C entries, counts from CNT_TINY);
+// b < 0 appends nothing (every lane of the wavefront calls it)
+__device__ inline void bucket_append(int b, int64_t c, int32_t *__restrict__ list, int64_t C,
+                                     uint32_t *__restrict__ cnt) {
+#pragma unroll
+    for (int k = 0; k < kBuckets; ++k) {
+        const uint32_t r = wave_count32(&cnt[CNT_TINY + k], b == k);
+        if (b == k) list[k * C + r] = int32_t(c);
+    }
+}
 
 // store W (FP32 and FP64, packed rows), alpha and the positive-definite flag
 __device__ inline void put_w(float *W32, double *W64, int64_t off, int idx, double w) {
@@ -1117,18 +1135,7 @@ __global__ void k_cluster_plan(const int32_t *__restrict__ coff, int64_t nbound,
         }
     }
     if (lazy) return;
-    const bool tiny = in && ok && n <= kTinyN;
-    const bool wave = in && ok && n > kTinyN && n <= kWaveN;
-    const bool big = in && ok && n > kWaveN && n <= kMfmaMaxN;
-    const bool huge = in && ok && n > kMfmaMaxN;
-    const uint32_t rt = wave_count32(&cnt[CNT_TINY], tiny);
-    const uint32_t rw = wave_count32(&cnt[CNT_WAVE], wave);
-    const uint32_t rb = wave_count32(&cnt[CNT_BIG], big);
-    const uint32_t rh = wave_count32(&cnt[CNT_HUGE], huge);
-    if (tiny) list[rt] = int32_t(c);
-    if (wave) list[C + rw] = int32_t(c);
-    if (big) list[2 * C + rb] = int32_t(c);
-    if (huge) list[3 * C + rh] = int32_t(c);
+    bucket_append(in && ok ? size_bucket(n) : -1, c, list, C, cnt);
 }
 
 // lazy training: the marked clusters that are not trained yet into the size
@@ -1145,18 +1152,7 @@ __global__ void k_lazy_plan(const int32_t *__restrict__ coff, int64_t ncl, uint8
         if (take) trained[c] = 1;
         n = coff[c + 1] - coff[c];
     }
-    const bool tiny = take && n <= kTinyN;
-    const bool wave = take && n > kTinyN && n <= kWaveN;
-    const bool big = take && n > kWaveN && n <= kMfmaMaxN;
-    const bool huge = take && n > kMfmaMaxN;
-    const uint32_t rt = wave_count32(&cnt[CNT_TINY], tiny);
-    const uint32_t rw = wave_count32(&cnt[CNT_WAVE], wave);
-    const uint32_t rb = wave_count32(&cnt[CNT_BIG], big);
-    const uint32_t rh = wave_count32(&cnt[CNT_HUGE], huge);
-    if (tiny) list[rt] = int32_t(c);
-    if (wave) list[C + rw] = int32_t(c);
-    if (big) list[2 * C + rb] = int32_t(c);
-    if (huge) list[3 * C + rh] = int32_t(c);
+    bucket_append(take ? size_bucket(n) : -1, c, list, C, cnt);
 }
 
 __global__ void k_copy_count(uint32_t *__restrict__ cnt, int dst, int src) {
@@ -1190,15 +1186,32 @@ hipError_t launch_trainers(gpdf_ctx *c, int64_t C, hipStream_t s, hipStream_t sb
         if ((e = hipEventRecord(c->fork_ev, s)) != hipSuccess || (e = hipStreamWaitEvent(sb, c->fork_ev, 0)) != hipSuccess)
             return e;
     }
-    fill_u32(c->d_work + 2 * kWorkSlot, 0u, 1, sb);
-    fill_u32(c->d_work + 3 * kWorkSlot, 0u, 1, sb);
-    hipLaunchKernelGGL(k_train_mfma, dim3(unsigned(std::min<int64_t>(C, 256))), dim3(kMfmaT), 0, sb,
-                       c->d_blist + 2 * C, cnt + CNT_BIG, c->d_work + 3 * kWorkSlot, c->d_pts, c->d_coff, c->d_aoff,
-                       c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l, s2, c->d_stat);
+    // work counters: the workgroup trainer in slot 2, the four blocked
+    // trainers on their own lines of slot 3
+    fill_u32(c->d_work + 2 * kWorkSlot, 0u, 2 * kWorkSlot, sb);
+    {
+        // grids: a CU holds three GPs of <= 6 tile rows, two of <= 8, one of
+        // <= 12 (their LDS) and two with the tiles in the workspace (their
+        // registers); the smaller GPs take four wavefronts each, the others
+        // eight; a bucket never takes more workgroups than clusters
+        uint32_t *w3 = c->d_work + 3 * kWorkSlot;
+        const unsigned g1 = unsigned(std::min<int64_t>(C, 256)), g2 = unsigned(std::min<int64_t>(C, 512)),
+                       g3 = unsigned(std::min<int64_t>(C, 768));
+#define GPDF_TRAIN_MFMA(LT, NT, WPE, G, B, K)                                                                   \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_train_mfma<LT, NT, WPE>), dim3(G), dim3(NT), 0, sb, c->d_blist + (B - CNT_TINY) * C, \
+                       cnt + B, w3 + K * kCtrStride, c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64,   \
+                       c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l, s2, c->d_stat)
+        // largest first, so that the long GPs start early
+        GPDF_TRAIN_MFMA(0, 256, 2, g2, CNT_BIG16, 3);
+        GPDF_TRAIN_MFMA(12, 512, 2, g1, CNT_BIG12, 2);
+        GPDF_TRAIN_MFMA(8, 256, 2, g2, CNT_BIG8, 1);
+        GPDF_TRAIN_MFMA(6, 256, 3, g3, CNT_BIG6, 0);
+#undef GPDF_TRAIN_MFMA
+    }
     {
         const unsigned gb = unsigned(std::min<int64_t>(C, 256));
 #define GPDF_TRAIN_BLOCK(T)                                                                                    \
-    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, sb, c->d_blist + 3 * C, cnt + CNT_HUGE, c->d_work + 2 * kWorkSlot, \
+    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, sb, c->d_blist + (CNT_HUGE - CNT_TINY) * C, cnt + CNT_HUGE, c->d_work + 2 * kWorkSlot, \
                        c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64,     \
                        c->d_pd, c->p.kernel, l, s2, c->d_stat)
         if (c->tune.train_threads == 512) GPDF_TRAIN_BLOCK(512);
