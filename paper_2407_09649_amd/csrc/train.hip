@@ -595,7 +595,7 @@ __device__ __forceinline__ void tile_xy2(const double *X1, const double *Y1, f64
 // the body of one cluster (NT threads), the tiles in LDS or in the workspace
 template <int NT>
 __device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *__restrict__ ybuf,
-                                                int *flag,
+                                                int *flag, int *next,
                                                 int c, int base, int n, float4 *__restrict__ pts,
                                                 const int64_t *__restrict__ woff, double *__restrict__ W64all,
                                                 float *__restrict__ W32all, double *__restrict__ alpha64,
@@ -654,9 +654,13 @@ __device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *
             const f64x4 acc = tile_xyt(X, Vp, f64x4{0.0, 0.0, 0.0, 0.0}, 1.0, lane);
             tile_put(X, acc, lane);
         }
+        if (tid == 0) *next = 1;
         __syncthreads();
-        // A_ij -= L_ip L_jp^T, two tiles at a time (the second repeats the
-        // first when the count is odd and is then not stored)
+        // A_ij -= L_ip L_jp^T.  Trailing tile 0, the next diagonal tile, is
+        // updated and factored by wavefront 0 first (look-ahead); the others
+        // go in pairs (the second repeats the first when none is left and is
+        // then not stored) to whichever wavefront takes the next pair from
+        // the LDS counter, so wavefront 0 joins once it has factored
         const int m = T - 1 - p, nt = m * (m + 1) / 2;
         auto trail_tile = [&](int t, int &i, int &j) {
             int a = int((sqrtf(8.f * float(t) + 1.f) - 1.f) * 0.5f);
@@ -665,17 +669,26 @@ __device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *
             i = p + 1 + a;
             j = p + 1 + (t - a * (a + 1) / 2);
         };
-        for (int t = wv; t < nt; t += 2 * kW) {
-            const bool two = t + kW < nt;
+        if (wv == 0 && nt > 0) {
+            double *Y = A + tlow(p + 1, p + 1);
+            const f64x4 acc = tile_xyt(A + tlow(p + 1, p), A + tlow(p + 1, p), tile_get(Y, lane), -1.0, lane);
+            tile_put(Y, acc, lane);
+            if (!diag_factor(Y, thr, lane) && lane == 0) *flag = 0;
+        }
+        while (true) {
+            int t0 = 0;
+            if (lane == 0) t0 = atomicAdd(next, 2);
+            const int t = __builtin_amdgcn_readfirstlane(t0);
+            if (t >= nt) break;
+            const bool two = t + 1 < nt;
             int i1, j1, i2, j2;
             trail_tile(t, i1, j1);
-            trail_tile(two ? t + kW : t, i2, j2);
+            trail_tile(two ? t + 1 : t, i2, j2);
             double *Y1 = A + tlow(i1, j1), *Y2 = A + tlow(i2, j2);
             f64x4 acc1 = tile_get(Y1, lane), acc2 = tile_get(Y2, lane);
             tile_xyt2(A + tlow(i1, p), A + tlow(j1, p), acc1, A + tlow(i2, p), A + tlow(j2, p), acc2, -1.0, lane);
             tile_put(Y1, acc1, lane);
             if (two) tile_put(Y2, acc2, lane);
-            if (t == 0 && !diag_factor(Y1, thr, lane) && lane == 0) *flag = 0;
         }
         __syncthreads();
     }
@@ -798,7 +811,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     static_assert(LT <= kMfmaLdsT, "LDS tiles beyond the bucket bound");
     __shared__ double sA[LT > 0 ? LT * (LT + 1) / 2 * kTileElems : 1];
     __shared__ double ybuf[LT > 0 ? LT * kTb : kMfmaMaxN];
-    __shared__ int flag;
+    __shared__ int flag, next;
     __shared__ uint32_t item;
     const uint32_t cnt = *dcnt;
     while (true) {
@@ -812,10 +825,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         const int n = coff[c + 1] - base;
         if constexpr (LT > 0) {
             if (mfma_tiles(n) > LT) continue;  // not of this bucket (the plan never puts it here)
-            train_mfma_body<NT>(sA, ybuf, &flag, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel,
+            train_mfma_body<NT>(sA, ybuf, &flag, &next, c, base, n, pts, woff, W64all, W32all, alpha64, pd, kernel,
                                 l, s2, stat);
         } else {
-            train_mfma_body<NT>(Aall + aoff[c], ybuf, &flag, c, base, n, pts, woff, W64all, W32all, alpha64,
+            train_mfma_body<NT>(Aall + aoff[c], ybuf, &flag, &next, c, base, n, pts, woff, W64all, W32all, alpha64,
                                 pd, kernel, l, s2, stat);
         }
     }
