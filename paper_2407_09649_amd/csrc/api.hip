@@ -28,14 +28,17 @@ namespace {
 
 void release(gpdf_ctx *c) {
     if (c->side) (void)hipStreamSynchronize(c->side);  // a trainer may still run there
+    if (c->side2) (void)hipStreamSynchronize(c->side2);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->gstream) (void)hipStreamDestroy(c->gstream);
     if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->side2) (void)hipStreamDestroy(c->side2);
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     if (c->join_ev) (void)hipEventDestroy(c->join_ev);
-    c->side = nullptr;
-    c->fork_ev = c->join_ev = nullptr;
+    if (c->join2_ev) (void)hipEventDestroy(c->join2_ev);
+    c->side = c->side2 = nullptr;
+    c->fork_ev = c->join_ev = c->join2_ev = nullptr;
     if (c->d_gin) (void)hipFree(c->d_gin);
     if (c->d_gorigin) (void)hipFree(c->d_gorigin);
     c->gexec = nullptr;
@@ -228,8 +231,10 @@ extern "C" gpdf_status gpdf_create(const gpdf_params *p, void *hip_stream, gpdf_
     if (ok) {
         // default priority, like the caller's stream
         ok = (e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) == hipSuccess &&
+             (e = hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking)) == hipSuccess &&
              (e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) == hipSuccess &&
-             (e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming)) == hipSuccess;
+             (e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming)) == hipSuccess &&
+             (e = hipEventCreateWithFlags(&c->join2_ev, hipEventDisableTiming)) == hipSuccess;
     }
     if (!ok) {
         release(c);

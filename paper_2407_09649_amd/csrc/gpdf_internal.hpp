@@ -384,8 +384,9 @@ struct gpdf_ctx {
     bool offs_ready = false;       // band offsets of the test voxels uploaded
     // per-frame graph (fuse_frame with every count on the device)
     hipStream_t gstream = nullptr; // capture stream
-    hipStream_t side = nullptr;    // second stream: the large-cluster trainer beside the others
-    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    hipStream_t side = nullptr;    // second stream: the large-cluster trainers beside the others
+    hipStream_t side2 = nullptr;   // third stream: the blocked trainers with their tiles in LDS
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr, join2_ev = nullptr;
     // an eager training leaves the large-cluster trainer running on `side`;
     // the first later operation that needs the model (or its buffers) makes
     // the caller's stream wait for join_ev (join_train)

@@ -1195,13 +1195,20 @@ hipError_t launch_trainers(gpdf_ctx *c, int64_t C, hipStream_t s, hipStream_t sb
     hipError_t e;
     uint32_t *cnt = c->d_cnt;
     const double l = c->p.length_scale, s2 = c->p.noise_sigma * c->p.noise_sigma;
+    // work counters: the workgroup trainer in slot 2, the four blocked
+    // trainers on their own lines of slot 3, cleared before the fork
+    fill_u32(c->d_work + 2 * kWorkSlot, 0u, 2 * kWorkSlot, s);
+    // the blocked trainer with its tiles in the workspace on sb, those with
+    // their tiles in LDS and the workgroup trainer on sb2 beside it, so that
+    // each fills the CUs that the end of the other leaves idle (an LDS
+    // trainer's workgroup cannot share a CU with one of 9-12 tile rows, so
+    // the smaller buckets follow that one); sb2 joins sb
+    hipStream_t sb2 = sb == s ? s : c->side2;
     if (sb != s) {
-        if ((e = hipEventRecord(c->fork_ev, s)) != hipSuccess || (e = hipStreamWaitEvent(sb, c->fork_ev, 0)) != hipSuccess)
+        if ((e = hipEventRecord(c->fork_ev, s)) != hipSuccess || (e = hipStreamWaitEvent(sb, c->fork_ev, 0)) != hipSuccess ||
+            (e = hipStreamWaitEvent(sb2, c->fork_ev, 0)) != hipSuccess)
             return e;
     }
-    // work counters: the workgroup trainer in slot 2, the four blocked
-    // trainers on their own lines of slot 3
-    fill_u32(c->d_work + 2 * kWorkSlot, 0u, 2 * kWorkSlot, sb);
     {
         // grids: a CU holds three GPs of <= 6 tile rows, two of <= 8, one of
         // <= 12 (their LDS) and two with the tiles in the workspace (their
@@ -1210,21 +1217,21 @@ hipError_t launch_trainers(gpdf_ctx *c, int64_t C, hipStream_t s, hipStream_t sb
         uint32_t *w3 = c->d_work + 3 * kWorkSlot;
         const unsigned g1 = unsigned(std::min<int64_t>(C, 256)), g2 = unsigned(std::min<int64_t>(C, 512)),
                        g3 = unsigned(std::min<int64_t>(C, 768));
-#define GPDF_TRAIN_MFMA(LT, NT, WPE, G, B, K)                                                                   \
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_train_mfma<LT, NT, WPE>), dim3(G), dim3(NT), 0, sb, c->d_blist + (B - CNT_TINY) * C, \
+#define GPDF_TRAIN_MFMA(LT, NT, WPE, G, B, K, ST)                                                               \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_train_mfma<LT, NT, WPE>), dim3(G), dim3(NT), 0, ST, c->d_blist + (B - CNT_TINY) * C, \
                        cnt + B, w3 + K * kCtrStride, c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64,   \
                        c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l, s2, c->d_stat)
-        // largest first, so that the long GPs start early
-        GPDF_TRAIN_MFMA(0, 256, 2, g2, CNT_BIG16, 3);
-        GPDF_TRAIN_MFMA(12, 512, 2, g1, CNT_BIG12, 2);
-        GPDF_TRAIN_MFMA(8, 256, 2, g2, CNT_BIG8, 1);
-        GPDF_TRAIN_MFMA(6, 256, 3, g3, CNT_BIG6, 0);
+        // largest first on each stream, so that the long GPs start early
+        GPDF_TRAIN_MFMA(0, 256, 2, g2, CNT_BIG16, 3, sb);
+        GPDF_TRAIN_MFMA(12, 512, 2, g1, CNT_BIG12, 2, sb2);
+        GPDF_TRAIN_MFMA(8, 256, 2, g2, CNT_BIG8, 1, sb2);
+        GPDF_TRAIN_MFMA(6, 256, 3, g3, CNT_BIG6, 0, sb2);
 #undef GPDF_TRAIN_MFMA
     }
     {
         const unsigned gb = unsigned(std::min<int64_t>(C, 256));
 #define GPDF_TRAIN_BLOCK(T)                                                                                    \
-    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, sb, c->d_blist + (CNT_HUGE - CNT_TINY) * C, cnt + CNT_HUGE, c->d_work + 2 * kWorkSlot, \
+    hipLaunchKernelGGL(k_train_block<T>, dim3(gb), dim3(T), 0, sb2, c->d_blist + (CNT_HUGE - CNT_TINY) * C, cnt + CNT_HUGE, c->d_work + 2 * kWorkSlot, \
                        c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64, c->d_W32, c->d_alpha64,     \
                        c->d_pd, c->p.kernel, l, s2, c->d_stat)
         if (c->tune.train_threads == 512) GPDF_TRAIN_BLOCK(512);
@@ -1232,7 +1239,9 @@ hipError_t launch_trainers(gpdf_ctx *c, int64_t C, hipStream_t s, hipStream_t sb
         else GPDF_TRAIN_BLOCK(1024);
 #undef GPDF_TRAIN_BLOCK
     }
-    if (sb != s && (e = hipEventRecord(c->join_ev, sb)) != hipSuccess) return e;
+    if (sb != s && ((e = hipEventRecord(c->join2_ev, sb2)) != hipSuccess || (e = hipStreamWaitEvent(sb, c->join2_ev, 0)) != hipSuccess ||
+                    (e = hipEventRecord(c->join_ev, sb)) != hipSuccess))
+        return e;
     hipLaunchKernelGGL(k_train_tiny, dim3(blocks_for(C, 64)), dim3(64), 0, s, c->d_blist, cnt + CNT_TINY,
                        c->d_pts, c->d_coff, c->d_woff, c->d_W64, c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l,
                        s2, c->d_stat);
