@@ -41,6 +41,11 @@ void release(gpdf_ctx *c) {
     c->fork_ev = c->join_ev = c->join2_ev = nullptr;
     if (c->d_gin) (void)hipFree(c->d_gin);
     if (c->d_gorigin) (void)hipFree(c->d_gorigin);
+    if (c->d_gfirst) (void)hipFree(c->d_gfirst);
+    if (c->h_gchunks) (void)hipHostFree(c->h_gchunks);
+    c->d_gfirst = c->h_gchunks = c->d_gchunks = nullptr;
+    c->geval_node = nullptr;
+    c->geval_ok = false;
     c->gexec = nullptr;
     c->graph = nullptr;
     c->gstream = nullptr;
@@ -392,10 +397,25 @@ __global__ void k_set_frame(uint32_t *cnt, uint32_t n, uint32_t frame, float ox,
 gpdf_status capture_frame_graph(gpdf_ctx *c) {
     hipError_t e;
     const int64_t P = c->p.max_points;
+    // buffers of an earlier capture that failed
+    if (c->d_gin) (void)hipFree(c->d_gin);
+    if (c->d_gorigin) (void)hipFree(c->d_gorigin);
+    if (c->d_gfirst) (void)hipFree(c->d_gfirst);
+    if (c->h_gchunks) (void)hipHostFree(c->h_gchunks);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    c->d_gin = c->d_gorigin = nullptr;
+    c->d_gfirst = c->h_gchunks = c->d_gchunks = nullptr;
+    c->gstream = nullptr;
     if ((e = hipMalloc((void **)&c->d_gin, sizeof(float) * 3 * size_t(P))) != hipSuccess ||
         (e = hipMalloc((void **)&c->d_gorigin, sizeof(float) * 4)) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_gfirst, 256)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&c->h_gchunks, 256, hipHostMallocMapped)) != hipSuccess ||
+        (e = hipHostGetDevicePointer((void **)&c->d_gchunks, c->h_gchunks, 0)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(c, e, "graph: allocate");
+    *c->h_gchunks = 0;
+    c->geval_node = nullptr;
+    c->geval_ok = false;
     gpdf_status st = ensure_offsets(c);
     if (st != GPDF_OK) return st;
     if ((e = ensure_cell_lists(c, c->p.max_queries + 1)) != hipSuccess) return hip_fail(c, e, "graph: cell lists");
@@ -408,6 +428,8 @@ gpdf_status capture_frame_graph(gpdf_ctx *c) {
     } else {
         st = train(c, c->d_gin, P, c->d_cnt + CNT_IN);
         if (st == GPDF_OK) st = fuse(c, nullptr, c->d_gorigin, P);
+        // every stream forked in the capture joins it before it ends
+        if (hipError_t je = join_train(c); je != hipSuccess && st == GPDF_OK) st = hip_fail(c, je, "graph: join");
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(c->gstream, &g);
         if (st == GPDF_OK && e != hipSuccess) st = hip_fail(c, e, "graph: end capture");
@@ -416,9 +438,18 @@ gpdf_status capture_frame_graph(gpdf_ctx *c) {
             if ((e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0)) != hipSuccess) {
                 c->gexec = nullptr;
                 st = hip_fail(c, e, "graph: instantiate");
+            } else if (c->geval_node) {
+                // without the node's parameters every replay keeps the
+                // captured grid (the persistent instance takes the rest)
+                c->geval_ok = hipGraphKernelNodeGetParams(c->geval_node, &c->geval_params) == hipSuccess;
+                c->geval_cur = c->geval_grid0;
             }
         } else if (g) {
             (void)hipGraphDestroy(g);
+        }
+        if (st != GPDF_OK) {
+            c->geval_node = nullptr;
+            c->geval_ok = false;
         }
     }
     c->capturing = false;
@@ -454,6 +485,19 @@ extern "C" gpdf_status gpdf_fuse_frame_graph(gpdf_ctx *c, const float *d_xyz, in
         if (n > 0 && (e = hipMemcpyAsync(c->d_gin, d_xyz, sizeof(float) * 3 * size_t(n), hipMemcpyDeviceToDevice,
                                          s)) != hipSuccess)
             return hip_fail(c, e, "fuse_frame_graph: copy points");
+        // the evaluation node's grid: the chunk count of the last replay that
+        // has finished, with an eighth and 64 chunks to spare (a replay still
+        // running gives an older count; either way only the speed changes)
+        if (c->geval_ok) {
+            const uint32_t last = *static_cast<volatile uint32_t *>(c->h_gchunks);
+            const unsigned want = std::min<unsigned>(c->geval_gridmax, ((last + last / 8 + 64) + 7u) & ~7u);
+            if (last > 0 && want != c->geval_cur) {
+                hipKernelNodeParams kp = c->geval_params;
+                kp.gridDim = dim3(want);
+                if ((e = hipGraphExecKernelNodeSetParams(c->gexec, c->geval_node, &kp)) == hipSuccess) c->geval_cur = want;
+                else c->geval_ok = false;  // keep the grid it has
+            }
+        }
         hipLaunchKernelGGL(k_set_frame, dim3(1), dim3(64), 0, s, c->d_cnt, uint32_t(n), uint32_t(c->frame),
                            h_origin[0], h_origin[1], h_origin[2], c->d_gorigin);
         if ((e = hipGetLastError()) != hipSuccess || (e = hipGraphLaunch(c->gexec, s)) != hipSuccess)

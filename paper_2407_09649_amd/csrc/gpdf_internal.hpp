@@ -302,6 +302,7 @@ constexpr int kCtrStride = 32;                     // u32 per counter line
 constexpr int kWorkSlot = kXcds * kCtrStride;
 constexpr int kWorkSlots = 4;
 constexpr int kBuckets = CNT_HUGE - CNT_TINY + 1;  // training size buckets (lists of C clusters each)
+constexpr unsigned kGraphEvalGrid0 = 1024;  // captured grid of the graph's evaluation node, before any replay
 
 constexpr int kSpread = 64;
 constexpr int kSpreadStride = 16 * ((ST_COUNT + 15) / 16);
@@ -384,6 +385,17 @@ struct gpdf_ctx {
     bool offs_ready = false;       // band offsets of the test voxels uploaded
     // per-frame graph (fuse_frame with every count on the device)
     hipStream_t gstream = nullptr; // capture stream
+    // the captured frame's FP32 evaluation: its one-workgroup-per-chunk node,
+    // whose grid is set before each replay (captured, largest, current), the
+    // chunks that node took (device word, written by it, read by the
+    // persistent instance after it), the chunk count of the last replay
+    // (pinned host word and its device address)
+    hipGraphNode_t geval_node = nullptr;
+    hipKernelNodeParams geval_params{};
+    bool geval_ok = false;
+    unsigned geval_grid0 = 0, geval_gridmax = 0, geval_cur = 0;
+    uint32_t *d_gfirst = nullptr;
+    uint32_t *h_gchunks = nullptr, *d_gchunks = nullptr;
     hipStream_t side = nullptr;    // second stream: the large-cluster trainers beside the others
     hipStream_t side2 = nullptr;   // third stream: the blocked trainers with their tiles in LDS
     hipEvent_t fork_ev = nullptr, join_ev = nullptr, join2_ev = nullptr;
@@ -556,9 +568,12 @@ gpdf_status hip_fail(gpdf_ctx *c, hipError_t e, const char *what);
 // out[i] = sum_{j < i} in[j] for i <= n (out has n + 1 entries).  With dn,
 // the count is min(n, *dn) read on the device (n is then a bound that sizes
 // the grid); total_out, when given, receives the total.  partials needs
-// ceil(n / 4096) + 1 entries.
+// ceil(n / 4096) + 1 entries.  by_count (with dn): one block whatever n, its
+// work following *dn, for a count known to be small beside a loose bound n
+// (a captured graph, which cannot read the count back to size the scan).
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
-                        hipStream_t s, const uint32_t *dn = nullptr, uint32_t *total_out = nullptr);
+                        hipStream_t s, const uint32_t *dn = nullptr, uint32_t *total_out = nullptr,
+                        bool by_count = false);
 // up to four exclusive scans of the same length n (and device count dn),
 // each as exclusive_scan_u32: one launch when n is small, else one after
 // the other (the partials are then shared in stream order)
@@ -576,7 +591,7 @@ struct ScanList {
     }
 };
 void exclusive_scan_u32_multi(const ScanList &L, int64_t n, uint32_t *partials, hipStream_t s,
-                              const uint32_t *dn = nullptr);
+                              const uint32_t *dn = nullptr, bool by_count = false);
 void radix_sort_pairs(uint64_t *&keys, uint64_t *&keys_alt, uint32_t *&vals, uint32_t *&vals_alt,
                       int64_t n, uint64_t varying_bits, uint32_t *hist, uint32_t *partials,
                       hipStream_t s);

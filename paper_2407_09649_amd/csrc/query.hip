@@ -1023,6 +1023,9 @@ struct Grouping {
     const uint32_t *cell_cnt;  // queries per cell
     const uint32_t *cell_off;  // first query of each cell in order[]
     const uint32_t *order;     // query indices grouped by cell
+    const uint32_t *first = nullptr;  // persistent instance: the first chunk it takes (null: 0)
+    uint32_t *covered = nullptr;      // one-chunk instance: where block 0 writes min(grid, chunks)
+    uint32_t *publish = nullptr;      // persistent instance: where block 0 writes the chunk count
 };
 
 struct ModelView {
@@ -1106,6 +1109,8 @@ __global__ __launch_bounds__(kEvalT, (eval_min_waves<T, PERSIST>())) void k_quer
                                                      QueryConsts C, Outputs O, uint32_t *work) {
     const uint32_t nch = *ro(G.nchunks);
     if constexpr (!PERSIST) {
+        // the chunks this launch takes are 0 .. min(grid, chunks) - 1
+        if (G.covered && blockIdx.x == 0 && threadIdx.x == 0) *G.covered = min(gridDim.x, nch);
         const uint32_t wave = xcd_item(nch);
         if (wave < nch) cells_chunk<T, KERN, MODE>(wave, q, G, lists, Mo, C, O);
     } else {
@@ -1116,12 +1121,15 @@ __global__ __launch_bounds__(kEvalT, (eval_min_waves<T, PERSIST>())) void k_quer
         // neighbouring chunks share an L2 and the load still balances.  The
         // next index is requested before the current chunk is evaluated, so
         // the round trip of the counter overlaps the work.
+        // Chunks below *G.first (when given) are another launch's.
+        if (G.publish && blockIdx.x == 0 && threadIdx.x == 0) *G.publish = nch;
         const bool lead = (threadIdx.x & 63) == 0;
-        const uint32_t per = (nch + kXcds - 1) / kXcds;
+        const uint32_t f = G.first ? min(uniform(*ro(G.first)), nch) : 0u;
+        const uint32_t per = (nch - f + kXcds - 1) / kXcds;
         const uint32_t x0 = blockIdx.x % kXcds;
         for (uint32_t r = 0; r < uint32_t(kXcds); ++r) {
             const uint32_t x = (x0 + r) % kXcds;
-            const uint32_t lo = x * per, hi = min(nch, lo + per);
+            const uint32_t lo = f + x * per, hi = min(nch, lo + per);
             if (lo >= hi) continue;
             uint32_t *ctr = work + x * kCtrStride;
             uint32_t i = 0;
@@ -2194,9 +2202,39 @@ void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_
         return;
     }
     uint32_t *work = nullptr;
-    // persistent when tuned so, and always in a captured graph (its grid
-    // bound would otherwise be one workgroup per possible chunk); the FP32
-    // instance holds four wavefronts per SIMD
+    // In a captured graph the FP32 evaluation is one workgroup per chunk
+    // over the first g chunks, g set before each replay from the chunk count
+    // of the last one (the node's grid; the graph runs no count back to the
+    // host), then the persistent instance over the chunks from g on (none
+    // unless the count grew), which also writes the count to pinned host
+    // memory.  The first launch writes how many chunks it took and the
+    // second starts there, so the split holds whatever grid a replay runs
+    // with.  The persistent instance alone costs more: the loop around the
+    // chunk keeps the launch's arguments in scalar registers and spills them.
+    if (std::is_same<T, float>::value && c->capturing && c->d_gfirst && !knn && c->tune.eval_persistent == 0 &&
+        !c->geval_node) {
+        work = c->d_work + int64_t(slot) * kWorkSlot;
+        fill_u32(work, 0u, kWorkSlot, s);
+        const unsigned g0 = std::min<unsigned>(grid, kGraphEvalGrid0);
+        Grouping G1 = G;
+        G1.covered = c->d_gfirst;
+        launch_query_kf<T, 0>(kernel, knn, g0, s, q, G1, lists, Mo, C, O, nullptr);
+        hipStreamCaptureStatus cs;
+        const hipGraphNode_t *deps = nullptr;
+        size_t nd = 0;
+        if (hipStreamGetCaptureInfo_v2(s, &cs, nullptr, nullptr, &deps, &nd) == hipSuccess && nd == 1) {
+            c->geval_node = deps[0];
+            c->geval_grid0 = g0;
+            c->geval_gridmax = grid;
+        }
+        Grouping Gp = G;
+        Gp.first = c->d_gfirst;
+        Gp.publish = c->d_gchunks;
+        launch_query_kf<T, 0>(kernel, knn, std::min<unsigned>(grid, 1024u), s, q, Gp, lists, Mo, C, O, work);
+        return;
+    }
+    // persistent when tuned so, and always in a captured graph otherwise;
+    // the FP32 instance holds four wavefronts per SIMD
     const int per = c->tune.eval_persistent > 0 ? c->tune.eval_persistent : (c->capturing ? 4 : 0);
     if (per > 0 && !knn) {
         // 256 CUs x 4 SIMDs x the wavefronts per SIMD
@@ -2395,7 +2433,7 @@ static BigView refine_cm(gpdf_ctx *c, const Model &M, hipStream_t s, const float
     SL.add(c->d_bcb, c->d_boffb, cnt + CNT_BPAIRS_B);
     SL.add(c->d_bnits, c->d_bioffs, cnt + CNT_BITEMS_S);
     SL.add(c->d_bnit, c->d_bioff, cnt + CNT_BITEMS);
-    exclusive_scan_u32_multi(SL, ncl, c->d_part, s, dncl);
+    exclusive_scan_u32_multi(SL, ncl, c->d_part, s, dncl, c->capturing);
     const CmTotals T{cnt + CNT_RCHUNKS, cnt + CNT_BPAIRS_S, cnt + CNT_BPAIRS_B, cnt + CNT_MAXN, nrec,
                      c->cap_bchunks, c->cap_bpairs, m, c->cap_bref};
     hipLaunchKernelGGL(k_cm_finish, dim3(blocks_for(ncl)), dim3(kQT), 0, s, ncl, dncl, c->d_coff, T, c->d_boffs,
@@ -2523,8 +2561,10 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         nc = int64_t(ncells);
     }
     const uint32_t *dnc = cnt + CNT_CELLS;
-    exclusive_scan_u32(c->d_cell_cnt, c->d_cell_off, nc, c->d_part, s, dnc);
-    exclusive_scan_u32(c->d_cell_chunks, c->d_chunk_off, nc, c->d_part, s, dnc, cnt + CNT_CHUNKS);
+    ScanList CL;
+    CL.add(c->d_cell_cnt, c->d_cell_off, nullptr);
+    CL.add(c->d_cell_chunks, c->d_chunk_off, cnt + CNT_CHUNKS);
+    exclusive_scan_u32_multi(CL, nc, c->d_part, s, dnc, c->capturing);
     hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_cell_chunks,
                        c->d_chunk_off, c->d_chunk);
     // lazy training: factor the clusters these queries select, until a
@@ -2632,7 +2672,7 @@ gpdf_status query(gpdf_ctx *c, const float *d_q, int64_t m, const float *origin,
         ScanList RL;
         RL.add(c->d_rcnt, c->d_roff, nullptr);
         RL.add(c->d_rchunks, c->d_rchunk_off, cnt + CNT_RCHUNKS);
-        exclusive_scan_u32_multi(RL, nc, c->d_part, s, dnc);
+        exclusive_scan_u32_multi(RL, nc, c->d_part, s, dnc, c->capturing);
         hipLaunchKernelGGL(k_chunk_table, dim3(blocks_for(nc)), dim3(kQT), 0, s, nc, dnc, c->d_rchunks,
                            c->d_rchunk_off, c->d_rchunk);
         hipLaunchKernelGGL(k_refine_scatter, dim3(rgrid), dim3(kQT), 0, s, c->d_refine,

@@ -311,8 +311,8 @@ inline unsigned grid_for(int64_t n, int threads) {
 }  // namespace
 
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
-                        hipStream_t s, const uint32_t *dn, uint32_t *total_out) {
-    if (n <= kScan1Max) {
+                        hipStream_t s, const uint32_t *dn, uint32_t *total_out, bool by_count) {
+    if (n <= kScan1Max || (by_count && dn)) {
         hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScan1Threads), 0, s, in, out, n, dn, total_out);
         return;
     }
@@ -325,8 +325,8 @@ void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *
 }
 
 void exclusive_scan_u32_multi(const ScanList &L, int64_t n, uint32_t *partials, hipStream_t s,
-                              const uint32_t *dn) {
-    if (n <= kScan1Max) {
+                              const uint32_t *dn, bool by_count) {
+    if (n <= kScan1Max || (by_count && dn)) {
         hipLaunchKernelGGL(k_scan_multi, dim3(unsigned(L.count)), dim3(kScan1Threads), 0, s, L, n, dn);
         return;
     }

@@ -1334,7 +1334,8 @@ gpdf_status train(gpdf_ctx *c, const float *d_xyz, int64_t n, const uint32_t *dn
         //    second stream beside the other two; the buckets are disjoint.
         //    eager: the join is left to the first operation that needs the
         //    model (the test voxels of a fusion, which need only the points,
-        //    run beside the trainer); a captured frame joins here
+        //    run beside the trainer); a captured frame joins here (left to
+        //    the query, its replays measured slower)
         if ((e = launch_trainers(c, C, s, c->side)) != hipSuccess) return hip_fail(c, e, "train: trainers");
         if (eager && !d_prop) c->join_pending = true;
         else if ((e = hipStreamWaitEvent(s, c->join_ev, 0)) != hipSuccess) return hip_fail(c, e, "train: join");

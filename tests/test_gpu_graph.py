@@ -55,6 +55,35 @@ def test_graph_replays_equal_eager_frames(dev):
     graph.close()
 
 
+def test_graph_replays_with_growing_frames_equal_eager(dev):
+    # the graph's evaluation runs one workgroup per chunk over a grid sized
+    # from the previous replay's chunk count, the rest persistent: a frame
+    # with a quarter of the points, then full frames (about four times the
+    # chunks), puts most of a replay's chunks beyond that grid
+    path, frames = _frames(7, 4)
+    frames[0] = frames[0][::4].copy()
+    p = _params()
+    eager = P.Context(p, device=dev)
+    graph = P.Context(p, device=dev)
+    tp = []
+    for i, (pts, o) in enumerate(zip(frames, path)):
+        x = torch.from_numpy(pts).to(dev)
+        o32 = np.asarray(o, np.float32)
+        eager.fuse(x, o32)
+        graph.fuse_graph(x, o32)
+        torch.cuda.synchronize()
+        a, b = eager.export_global(), graph.export_global()
+        for k in ("key", "D", "V", "stamp"):
+            assert np.array_equal(a[k], b[k]), (i, k)
+        sa, sb = eager.stats(), graph.stats()
+        assert sa["test_points"] == sb["test_points"], (i, sa["test_points"], sb["test_points"])
+        tp.append(sb["test_points"])
+    print("test voxels per frame", tp, flush=True)
+    assert tp[1] > 2 * tp[0]
+    eager.close()
+    graph.close()
+
+
 def test_graph_reports_capacity_overflow(dev):
     path, frames = _frames(6, 2)
     ctx = P.Context(_params(max_clusters=32), device=dev)
