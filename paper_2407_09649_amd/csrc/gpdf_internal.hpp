@@ -218,11 +218,14 @@ enum DevCount : int {
     CNT_PTS,      // training points (unique voxels or valid points)
     CNT_CL,       // clusters
     CNT_TINY,     // size buckets: n <= 8, n <= 64, then by 16-row tiles T:
-    CNT_WAVE,     // T <= 6, T <= 8, T <= 12, T <= 16 (n <= 256), larger
-    CNT_BIG6,
-    CNT_BIG8,
+    CNT_WAVE,     // T <= 6, T <= 8, T <= 12, then T = 16, 15, 14, 13 (tiles
+    CNT_BIG6,     // in the workspace, one trainer launch over the four lists,
+    CNT_BIG8,     // longest first), larger than 256 points
     CNT_BIG12,
-    CNT_BIG16,
+    CNT_T16,
+    CNT_T15,
+    CNT_T14,
+    CNT_T13,
     CNT_HUGE,
     CNT_WTOT,     // factor elements
     CNT_ATOT,     // FP64 workspace elements

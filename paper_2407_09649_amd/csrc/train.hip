@@ -801,9 +801,9 @@ __device__ __forceinline__ void train_mfma_body(double *__restrict__ A, double *
 // LT, so that two or three small GPs share a CU; LT = 0: the tiles are in the
 // FP64 workspace and the LDS holds only y.  WPE, the wavefronts per SIMD
 // that the registers must allow, is the GPs per CU times NT / 256
-template <int LT, int NT, int WPE>
+template <int LT, int NT, int WPE, int NL>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_train_mfma(
-    const int32_t *__restrict__ list, const uint32_t *__restrict__ dcnt, uint32_t *__restrict__ work,
+    const int32_t *__restrict__ list, const uint32_t *__restrict__ dcnt, int64_t lstride, uint32_t *__restrict__ work,
     float4 *__restrict__ pts, const int32_t *__restrict__ coff, const int64_t *__restrict__ aoff,
     const int64_t *__restrict__ woff, double *__restrict__ Aall, double *__restrict__ W64all,
     float *__restrict__ W32all, double *__restrict__ alpha64, uint8_t *__restrict__ pd, int kernel, double l,
@@ -813,14 +813,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     __shared__ double ybuf[LT > 0 ? LT * kTb : kMfmaMaxN];
     __shared__ int flag, next;
     __shared__ uint32_t item;
-    const uint32_t cnt = *dcnt;
+    // NL lists (lstride apart) with their counts at dcnt[0 .. NL - 1], taken
+    // one after the other
+    uint32_t lcnt[NL], cnt = 0;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        lcnt[k] = dcnt[k];
+        cnt += lcnt[k];
+    }
     while (true) {
         __syncthreads();  // the previous cluster is done with the LDS and item
         if (threadIdx.x == 0) item = atomicAdd(work, 1u);
         __syncthreads();
-        const uint32_t b = item;
+        uint32_t b = item;
         if (b >= cnt) break;
-        const int c = list[b];
+        int64_t lo = 0;
+#pragma unroll
+        for (int k = 0; k + 1 < NL; ++k) {
+            if (lo == int64_t(k) * lstride && b >= lcnt[k]) {
+                b -= lcnt[k];
+                lo += lstride;
+            }
+        }
+        const int c = list[lo + b];
         const int base = coff[c];
         const int n = coff[c + 1] - base;
         if constexpr (LT > 0) {
@@ -842,15 +857,18 @@ constexpr int kTinyN = 8;
 constexpr int kWaveN = 64;
 // the bucket of a cluster of n points, 0 .. kBuckets - 1: one lane (n <= 8),
 // one wavefront (n <= 64), the blocked trainer by tile rows T (T <= 6, 8, 12
-// with the tiles in LDS; T <= 16 in the workspace), one workgroup (larger)
+// with the tiles in LDS; T = 16, 15, 14, 13 in the workspace, one list each
+// so that its trainer takes the longest GPs first), one workgroup (larger)
 __device__ inline int size_bucket(int n) {
     if (n <= kTinyN) return 0;
     if (n <= kWaveN) return 1;
-    if (n > kMfmaMaxN) return 6;
+    if (n > kMfmaMaxN) return CNT_HUGE - CNT_TINY;
     const int T = mfma_tiles(n);
-    return T <= 6 ? 2 : T <= 8 ? 3 : T <= kMfmaLdsT ? 4 : 5;
+    return T <= 6 ? 2 : T <= 8 ? 3 : T <= kMfmaLdsT ? 4 : 5 + (16 - T);
 }
-static_assert(kBuckets == 7 && CNT_BIG6 - CNT_TINY == 2 && CNT_BIG16 - CNT_TINY == 5, "size buckets");
+static_assert(kBuckets == 10 && CNT_BIG6 - CNT_TINY == 2 && CNT_T16 - CNT_TINY == 5 && CNT_T13 - CNT_TINY == 8 &&
+                  kMfmaMaxN == 16 * kTb,
+              "size buckets");
 // appends cluster c to list b (lists of C entries, counts from CNT_TINY);
 // b < 0 appends nothing (every lane of the wavefront calls it)
 __device__ inline void bucket_append(int b, int64_t c, int32_t *__restrict__ list, int64_t C,
@@ -1217,15 +1235,15 @@ hipError_t launch_trainers(gpdf_ctx *c, int64_t C, hipStream_t s, hipStream_t sb
         uint32_t *w3 = c->d_work + 3 * kWorkSlot;
         const unsigned g1 = unsigned(std::min<int64_t>(C, 256)), g2 = unsigned(std::min<int64_t>(C, 512)),
                        g3 = unsigned(std::min<int64_t>(C, 768));
-#define GPDF_TRAIN_MFMA(LT, NT, WPE, G, B, K, ST)                                                               \
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_train_mfma<LT, NT, WPE>), dim3(G), dim3(NT), 0, ST, c->d_blist + (B - CNT_TINY) * C, \
-                       cnt + B, w3 + K * kCtrStride, c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64,   \
+#define GPDF_TRAIN_MFMA(LT, NT, WPE, NL, G, B, K, ST)                                                           \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_train_mfma<LT, NT, WPE, NL>), dim3(G), dim3(NT), 0, ST, c->d_blist + (B - CNT_TINY) * C, \
+                       cnt + B, C, w3 + K * kCtrStride, c->d_pts, c->d_coff, c->d_aoff, c->d_woff, c->d_A, c->d_W64,   \
                        c->d_W32, c->d_alpha64, c->d_pd, c->p.kernel, l, s2, c->d_stat)
         // largest first on each stream, so that the long GPs start early
-        GPDF_TRAIN_MFMA(0, 256, 2, g2, CNT_BIG16, 3, sb);
-        GPDF_TRAIN_MFMA(12, 512, 2, g1, CNT_BIG12, 2, sb2);
-        GPDF_TRAIN_MFMA(8, 256, 2, g2, CNT_BIG8, 1, sb2);
-        GPDF_TRAIN_MFMA(6, 256, 3, g3, CNT_BIG6, 0, sb2);
+        GPDF_TRAIN_MFMA(0, 256, 2, 4, g2, CNT_T16, 3, sb);
+        GPDF_TRAIN_MFMA(12, 512, 2, 1, g1, CNT_BIG12, 2, sb2);
+        GPDF_TRAIN_MFMA(8, 256, 2, 1, g2, CNT_BIG8, 1, sb2);
+        GPDF_TRAIN_MFMA(6, 256, 3, 1, g3, CNT_BIG6, 0, sb2);
 #undef GPDF_TRAIN_MFMA
     }
     {
