@@ -485,13 +485,16 @@ extern "C" gpdf_status gpdf_fuse_frame_graph(gpdf_ctx *c, const float *d_xyz, in
         if (n > 0 && (e = hipMemcpyAsync(c->d_gin, d_xyz, sizeof(float) * 3 * size_t(n), hipMemcpyDeviceToDevice,
                                          s)) != hipSuccess)
             return hip_fail(c, e, "fuse_frame_graph: copy points");
-        // the evaluation node's grid: the chunk count of the last replay that
-        // has finished, with an eighth and 64 chunks to spare (a replay still
-        // running gives an older count; either way only the speed changes)
+        // the evaluation node's grid: from the chunk count of the last replay
+        // that has finished (a replay still running gives an older count;
+        // either way only the speed changes), reset to that count with a
+        // quarter and 64 chunks to spare when the count outgrew the grid or
+        // the grid is over twice the count, and left alone otherwise (setting
+        // it while replays are queued can wait for them)
         if (c->geval_ok) {
             const uint32_t last = *static_cast<volatile uint32_t *>(c->h_gchunks);
-            const unsigned want = std::min<unsigned>(c->geval_gridmax, ((last + last / 8 + 64) + 7u) & ~7u);
-            if (last > 0 && want != c->geval_cur) {
+            const unsigned want = std::min<unsigned>(c->geval_gridmax, ((last + last / 4 + 64) + 7u) & ~7u);
+            if (last > 0 && (last > c->geval_cur || uint64_t(last) * 2 < c->geval_cur) && want != c->geval_cur) {
                 hipKernelNodeParams kp = c->geval_params;
                 kp.gridDim = dim3(want);
                 if ((e = hipGraphExecKernelNodeSetParams(c->gexec, c->geval_node, &kp)) == hipSuccess) c->geval_cur = want;

@@ -1023,9 +1023,6 @@ struct Grouping {
     const uint32_t *cell_cnt;  // queries per cell
     const uint32_t *cell_off;  // first query of each cell in order[]
     const uint32_t *order;     // query indices grouped by cell
-    const uint32_t *first = nullptr;  // persistent instance: the first chunk it takes (null: 0)
-    uint32_t *covered = nullptr;      // one-chunk instance: where block 0 writes min(grid, chunks)
-    uint32_t *publish = nullptr;      // persistent instance: where block 0 writes the chunk count
 };
 
 struct ModelView {
@@ -1103,14 +1100,25 @@ __device__ __forceinline__ void cells_chunk(uint32_t wave, const float *__restri
 template <typename T, bool PERSIST>
 constexpr int eval_min_waves() { return PERSIST && std::is_same<T, float>::value ? 4 : 1; }
 
-template <typename T, int KERN, int MODE, bool PERSIST>
+// REC (one-chunk instance of a captured frame): block 0 writes the number of
+// chunks the launch takes, min(grid, chunks), to *work and the chunk count to
+// *aux (pinned host memory).  The persistent instance takes the chunks from
+// *aux on when aux is given (from 0 otherwise).  aux is the last argument, so
+// that the instances without it lay out the others as before.
+template <typename T, int KERN, int MODE, bool PERSIST, bool REC = false>
 __global__ __launch_bounds__(kEvalT, (eval_min_waves<T, PERSIST>())) void k_query_cells(const float *__restrict__ q, Grouping G,
                                                      const int4 *__restrict__ lists, ModelView Mo,
-                                                     QueryConsts C, Outputs O, uint32_t *work) {
+                                                     QueryConsts C, Outputs O, uint32_t *work,
+                                                     uint32_t *aux) {
     const uint32_t nch = *ro(G.nchunks);
     if constexpr (!PERSIST) {
         // the chunks this launch takes are 0 .. min(grid, chunks) - 1
-        if (G.covered && blockIdx.x == 0 && threadIdx.x == 0) *G.covered = min(gridDim.x, nch);
+        if constexpr (REC) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                *work = min(gridDim.x, nch);
+                *aux = nch;
+            }
+        }
         const uint32_t wave = xcd_item(nch);
         if (wave < nch) cells_chunk<T, KERN, MODE>(wave, q, G, lists, Mo, C, O);
     } else {
@@ -1121,10 +1129,9 @@ __global__ __launch_bounds__(kEvalT, (eval_min_waves<T, PERSIST>())) void k_quer
         // neighbouring chunks share an L2 and the load still balances.  The
         // next index is requested before the current chunk is evaluated, so
         // the round trip of the counter overlaps the work.
-        // Chunks below *G.first (when given) are another launch's.
-        if (G.publish && blockIdx.x == 0 && threadIdx.x == 0) *G.publish = nch;
+        // Chunks below *aux (when given) are another launch's.
         const bool lead = (threadIdx.x & 63) == 0;
-        const uint32_t f = G.first ? min(uniform(*ro(G.first)), nch) : 0u;
+        const uint32_t f = aux ? min(uniform(*ro(aux)), nch) : 0u;
         const uint32_t per = (nch - f + kXcds - 1) / kXcds;
         const uint32_t x0 = blockIdx.x % kXcds;
         for (uint32_t r = 0; r < uint32_t(kXcds); ++r) {
@@ -2112,37 +2119,46 @@ __global__ __launch_bounds__(kEvalT) void k_query_knn(const float *__restrict__ 
 template <typename T, int KERN, int MODE>
 void launch_query(bool knn, unsigned grid, hipStream_t s, const float *q, const Grouping &G,
                   const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O,
-                  uint32_t *work) {
+                  uint32_t *work, uint32_t *covered = nullptr, uint32_t *aux = nullptr) {
     // property launches: NEIGHBOR27 (the caller rejects the other
     // combinations), one workgroup per chunk, or persistent given a counter
     if constexpr (kern_prop(KERN)) {
         if (work)
             hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, true>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
-                               Mo, C, O, work);
+                               Mo, C, O, work, nullptr);
         else
             hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, false>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
-                               Mo, C, O, nullptr);
+                               Mo, C, O, nullptr, nullptr);
     } else if (knn) {
         hipLaunchKernelGGL((k_query_knn<T, KERN, MODE>), dim3(grid), dim3(kEvalT), 0, s, q, G, Mo, C, O);
     } else if (work) {
         hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, true>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
-                           Mo, C, O, work);
+                           Mo, C, O, work, aux);
     } else {
+        // covered: the one-chunk instance that records its share (a captured
+        // frame's FP32 evaluation without gradient, the only one it has)
+        if constexpr (std::is_same<T, float>::value && !kern_grad(KERN)) {
+            if (covered) {
+                hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, false, true>), dim3(grid), dim3(kEvalT), 0, s, q, G,
+                                   lists, Mo, C, O, covered, aux);
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_query_cells<T, KERN, MODE, false>), dim3(grid), dim3(kEvalT), 0, s, q, G, lists,
-                           Mo, C, O, work);
+                           Mo, C, O, work, nullptr);
     }
 }
 
 template <typename T, int KERN>
 void launch_query_m(bool knn, unsigned grid, hipStream_t s, const float *q, const Grouping &G,
                     const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O,
-                    uint32_t *work) {
+                    uint32_t *work, uint32_t *covered = nullptr, uint32_t *aux = nullptr) {
     if (C.combine == GPDF_COMB_HARDMIN)
-        launch_query<T, KERN, kModeHard>(knn, grid, s, q, G, lists, Mo, C, O, work);
+        launch_query<T, KERN, kModeHard>(knn, grid, s, q, G, lists, Mo, C, O, work, covered, aux);
     else if (C.grad_mode == GPDF_GRAD_PAPER_MEAN)
-        launch_query<T, KERN, kModeMean>(knn, grid, s, q, G, lists, Mo, C, O, work);
+        launch_query<T, KERN, kModeMean>(knn, grid, s, q, G, lists, Mo, C, O, work, covered, aux);
     else
-        launch_query<T, KERN, kModeSmooth>(knn, grid, s, q, G, lists, Mo, C, O, work);
+        launch_query<T, KERN, kModeSmooth>(knn, grid, s, q, G, lists, Mo, C, O, work, covered, aux);
 }
 
 template <int KERN>
@@ -2163,13 +2179,15 @@ void launch_bf16_m(unsigned grid, size_t lds, hipStream_t s, const float *q, con
 template <typename T, int PF>
 void launch_query_kf(int kernel, bool knn, unsigned grid, hipStream_t s, const float *q, const Grouping &G,
                      const int4 *lists, const ModelView &Mo, const QueryConsts &C, const Outputs &O,
-                     uint32_t *work) {
+                     uint32_t *work, uint32_t *covered = nullptr, uint32_t *aux = nullptr) {
     if constexpr (std::is_same<T, float>::value) {
         if (!O.grad) {
             if (kernel == GPDF_KERNEL_MATERN32)
-                launch_query_m<T, GPDF_KERNEL_MATERN32 | kNoGrad | PF>(knn, grid, s, q, G, lists, Mo, C, O, work);
+                launch_query_m<T, GPDF_KERNEL_MATERN32 | kNoGrad | PF>(knn, grid, s, q, G, lists, Mo, C, O, work,
+                                                                       covered, aux);
             else
-                launch_query_m<T, GPDF_KERNEL_SE | kNoGrad | PF>(knn, grid, s, q, G, lists, Mo, C, O, work);
+                launch_query_m<T, GPDF_KERNEL_SE | kNoGrad | PF>(knn, grid, s, q, G, lists, Mo, C, O, work, covered,
+                                                                 aux);
             return;
         }
     }
@@ -2206,19 +2224,16 @@ void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_
     // over the first g chunks, g set before each replay from the chunk count
     // of the last one (the node's grid; the graph runs no count back to the
     // host), then the persistent instance over the chunks from g on (none
-    // unless the count grew), which also writes the count to pinned host
-    // memory.  The first launch writes how many chunks it took and the
-    // second starts there, so the split holds whatever grid a replay runs
-    // with.  The persistent instance alone costs more: the loop around the
+    // unless the count grew).  The first launch writes how many chunks it
+    // took, where the second starts, so the split holds whatever grid a
+    // replay runs with, and the chunk count to pinned host memory.  The persistent instance alone costs more: the loop around the
     // chunk keeps the launch's arguments in scalar registers and spills them.
-    if (std::is_same<T, float>::value && c->capturing && c->d_gfirst && !knn && c->tune.eval_persistent == 0 &&
-        !c->geval_node) {
+    if (std::is_same<T, float>::value && c->capturing && c->d_gfirst && !knn && !O.grad &&
+        c->tune.eval_persistent == 0 && !c->geval_node) {
         work = c->d_work + int64_t(slot) * kWorkSlot;
         fill_u32(work, 0u, kWorkSlot, s);
         const unsigned g0 = std::min<unsigned>(grid, kGraphEvalGrid0);
-        Grouping G1 = G;
-        G1.covered = c->d_gfirst;
-        launch_query_kf<T, 0>(kernel, knn, g0, s, q, G1, lists, Mo, C, O, nullptr);
+        launch_query_kf<T, 0>(kernel, knn, g0, s, q, G, lists, Mo, C, O, nullptr, c->d_gfirst, c->d_gchunks);
         hipStreamCaptureStatus cs;
         const hipGraphNode_t *deps = nullptr;
         size_t nd = 0;
@@ -2227,10 +2242,8 @@ void launch_query_k(gpdf_ctx *c, int kernel, bool knn, unsigned grid, hipStream_
             c->geval_grid0 = g0;
             c->geval_gridmax = grid;
         }
-        Grouping Gp = G;
-        Gp.first = c->d_gfirst;
-        Gp.publish = c->d_gchunks;
-        launch_query_kf<T, 0>(kernel, knn, std::min<unsigned>(grid, 1024u), s, q, Gp, lists, Mo, C, O, work);
+        launch_query_kf<T, 0>(kernel, knn, std::min<unsigned>(grid, 1024u), s, q, G, lists, Mo, C, O, work, nullptr,
+                              c->d_gfirst);
         return;
     }
     // persistent when tuned so, and always in a captured graph otherwise;
