@@ -84,6 +84,28 @@ def test_graph_replays_with_growing_frames_equal_eager(dev):
     graph.close()
 
 
+@pytest.mark.parametrize("kw", [dict(precision=P.PREC_FP64), dict(kernel=P.KERNEL_SE, length_scale=0.15)],
+                         ids=["fp64", "se-kernel"])
+def test_graph_other_precision_and_kernel_equal_eager(dev, kw):
+    # the FP64 evaluation takes the persistent instance in a captured frame;
+    # the squared-exponential kernel has its own recording instance
+    path, frames = _frames(8, 3)
+    p = _params(**kw)
+    eager = P.Context(p, device=dev)
+    graph = P.Context(p, device=dev)
+    for i, (pts, o) in enumerate(zip(frames, path)):
+        x = torch.from_numpy(pts).to(dev)
+        o32 = np.asarray(o, np.float32)
+        eager.fuse(x, o32)
+        graph.fuse_graph(x, o32)
+        torch.cuda.synchronize()
+        a, b = eager.export_global(), graph.export_global()
+        for k in ("key", "D", "V", "stamp"):
+            assert np.array_equal(a[k], b[k]), (i, k)
+    eager.close()
+    graph.close()
+
+
 def test_graph_reports_capacity_overflow(dev):
     path, frames = _frames(6, 2)
     ctx = P.Context(_params(max_clusters=32), device=dev)
