@@ -436,7 +436,7 @@ __global__ __launch_bounds__(T) void k_train_block(
 // and its lower tiles are kept in LDS (n <= 192) or in the FP64 workspace.
 // Right-looking Cholesky by tile columns p = 0 .. T - 1:
 //   one wavefront factors the diagonal tile, L_pp = chol(A_pp), and inverts
-//   it, V_p = L_pp^{-1} (16 steps in registers, row r in lane r), which
+//   it, V_p = L_pp^{-1} (16 steps in registers, column c in lane c), which
 //   replaces A_pp (L_pp is not read again);
 //   L_ip = A_ip V_p^T                for the tiles below (i > p);
 //   A_ij -= L_ip L_jp^T              for the trailing tiles (p < j <= i),
