@@ -1096,9 +1096,13 @@ __device__ __forceinline__ void cells_chunk(uint32_t wave, const float *__restri
 // the register allocation of a single chunk body.
 // the persistent FP32 instance is held to the occupancy of the one-chunk
 // instance (four wavefronts per SIMD); left alone, the compiler keeps far more
-// live across the chunk loop
-template <typename T, bool PERSIST>
-constexpr int eval_min_waves() { return PERSIST && std::is_same<T, float>::value ? 4 : 1; }
+// live across the chunk loop.  The FP32 one-chunk instances without gradient
+// (the fusion's test voxels) are held to five, measured faster there (the
+// ones with gradient measured slower at five)
+template <typename T, int KERN, bool PERSIST>
+constexpr int eval_min_waves() {
+    return !std::is_same<T, float>::value ? 1 : PERSIST ? 4 : (KERN & kNoGrad) ? 5 : 1;
+}
 
 // REC (one-chunk instance of a captured frame): block 0 writes the number of
 // chunks the launch takes, min(grid, chunks), to *work and the chunk count to
@@ -1106,7 +1110,7 @@ constexpr int eval_min_waves() { return PERSIST && std::is_same<T, float>::value
 // *aux on when aux is given (from 0 otherwise).  aux is the last argument, so
 // that the instances without it lay out the others as before.
 template <typename T, int KERN, int MODE, bool PERSIST, bool REC = false>
-__global__ __launch_bounds__(kEvalT, (eval_min_waves<T, PERSIST>())) void k_query_cells(const float *__restrict__ q, Grouping G,
+__global__ __launch_bounds__(kEvalT, (eval_min_waves<T, KERN, PERSIST>())) void k_query_cells(const float *__restrict__ q, Grouping G,
                                                      const int4 *__restrict__ lists, ModelView Mo,
                                                      QueryConsts C, Outputs O, uint32_t *work,
                                                      uint32_t *aux) {
