@@ -59,9 +59,11 @@ def test_graph_replays_with_growing_frames_equal_eager(dev):
     # the graph's evaluation runs one workgroup per chunk over a grid sized
     # from the previous replay's chunk count, the rest persistent: a frame
     # with a quarter of the points, then full frames (about four times the
-    # chunks), puts most of a replay's chunks beyond that grid
-    path, frames = _frames(7, 4)
+    # chunks), puts most of a replay's chunks beyond that grid; a last
+    # quarter frame runs on a grid over twice its count, which is then reset
+    path, frames = _frames(7, 5)
     frames[0] = frames[0][::4].copy()
+    frames[4] = frames[4][::4].copy()
     p = _params()
     eager = P.Context(p, device=dev)
     graph = P.Context(p, device=dev)
@@ -79,7 +81,7 @@ def test_graph_replays_with_growing_frames_equal_eager(dev):
         assert sa["test_points"] == sb["test_points"], (i, sa["test_points"], sb["test_points"])
         tp.append(sb["test_points"])
     print("test voxels per frame", tp, flush=True)
-    assert tp[1] > 2 * tp[0]
+    assert tp[1] > 2 * tp[0] and tp[3] > 2 * tp[4]
     eager.close()
     graph.close()
 
